@@ -1,0 +1,332 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a hand-stepped
+run of Algorithm 2, an exact dense solve (the method is exact when nothing is
+truncated), LAPACK's geqp3 through SciPy (the routine the paper used), the
+Schur-complement identity of the stability theorem (Sec. 3.2), a brute-force
+symbolic elimination, closed-form special cases and invariants.
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse.linalg as spla
+
+import gridgen
+from oracle import spand_oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _code(s):
+    if s == "-":
+        return 0
+    l, k = s.split(".")
+    return int(O.pack(int(l), int(k)))
+
+
+@pytest.mark.parametrize("fname,shape,levels", [("nd_7x7_L3.txt", (7, 7), 3), ("nd_6x4_L2.txt", (6, 4), 2)])
+def test_alg2_hand_stepped(fname, shape, levels):
+    """Algorithm 2 (Sec. 2.3) on small grids against hand-stepped runs."""
+    rows = [ln.split(":")[1].split() for ln in open(os.path.join(GOLDEN, fname))
+            if ln.startswith("y")]
+    p = gridgen.laplacian(shape)
+    S, L, R = O.nd_order(p.n, p.rowptr, p.colind, p.coords, levels)
+    assert len(rows) == shape[1]
+    for y, row in enumerate(rows):
+        assert len(row) == shape[0]
+        for x, ent in enumerate(row):
+            s, l, r = ent.split("/")
+            v = x + shape[0] * y
+            assert (S[v], L[v], R[v]) == (_code(s), _code(l), _code(r)), (x, y)
+
+
+@pytest.mark.parametrize("shape,levels", [((7, 7), 3), ((16, 16), 5), ((9, 7, 6), 4), ((8, 8, 8), 5)])
+def test_alg2_invariants(shape, levels):
+    """ND invariants: an edge never joins two different separators unless one is an
+    ancestor of the other in the ND tree; leaves number 2^(L-1); pointers of a
+    separator vertex point below its own level."""
+    p = gridgen.laplacian(shape)
+    S, L, R = O.nd_order(p.n, p.rowptr, p.colind, p.coords, levels)
+    rows = np.repeat(np.arange(p.n), np.diff(p.rowptr))
+    a, b = S[rows], S[p.colind]
+    la, lb = O.lev_of(a), O.lev_of(b)
+    # ancestor test: truncating the deeper id to the shallower level gives the shallower id
+    deep = np.where(la >= lb, a, b)
+    shallow = np.where(la >= lb, b, a)
+    anc = O.truncate(deep, np.minimum(la, lb)) == shallow
+    assert np.all(anc)
+    leaves = np.unique(S[O.lev_of(S) == levels])
+    assert len(leaves) == 2 ** (levels - 1)
+    sep = O.lev_of(S) < levels
+    assert np.all(O.lev_of(L[sep]) > O.lev_of(S[sep]))
+    assert np.all(O.lev_of(R[sep]) > O.lev_of(S[sep]))
+    assert np.all(L[~sep] == 0) and np.all(R[~sep] == 0)
+
+
+@pytest.mark.parametrize("shape,levels", [((7, 7), 3), ((12, 10), 4), ((6, 5, 7), 4), ((8, 8, 8), 4)])
+def test_each_separator_is_one_cluster(shape, levels):
+    """At the step that eliminates level l, every separator (l, k) is exactly one cluster."""
+    p = gridgen.laplacian(shape)
+    an = O.Analysis(p.n, p.rowptr, p.colind, p.coords, levels)
+    for st in an.steps:
+        ids = st.keys[: st.n_elim, 0]
+        assert len(np.unique(ids)) == st.n_elim
+        assert np.all(O.lev_of(ids) == st.level)
+
+
+def _brute_force_pattern(p, an):
+    """Vertex-level symbolic elimination: eliminating a vertex joins all its
+    remaining neighbours.  Returns, per step, the set of cluster pairs joined by a
+    (filled) edge among the clusters present before that step's elimination."""
+    n = p.n
+    adj = [set() for _ in range(n)]
+    for v in range(n):
+        for u in p.colind[p.rowptr[v]:p.rowptr[v + 1]]:
+            if u != v:
+                adj[v].add(int(u))
+    # vertex -> cluster id per step
+    owner = []
+    step_of_vertex = np.empty(n, dtype=np.int64)
+    cl = np.empty(n, dtype=np.int64)
+    for c, ch in enumerate(an.steps[0].children):
+        cl[ch] = c
+    for t, st in enumerate(an.steps):
+        if t > 0:
+            prev = an.steps[t - 1]
+            cl = np.where(cl >= 0, prev.parent[np.maximum(cl, 0)], -1)
+            cl[(cl < 0)] = -1
+        owner.append(cl.copy())
+        step_of_vertex[(cl >= 0) & (cl < st.n_elim)] = t
+    alive = np.ones(n, dtype=bool)
+    pats = []
+    for t, st in enumerate(an.steps):
+        cl = owner[t]
+        pat = set()
+        for v in np.nonzero(alive)[0]:
+            pat.add((cl[v], cl[v]))
+            for u in adj[v]:
+                a, b = cl[v], cl[u]
+                pat.add((max(a, b), min(a, b)))
+        pats.append(pat)
+        for v in np.nonzero(alive & (step_of_vertex == t))[0]:
+            nb = [u for u in adj[v] if alive[u] and u != v]
+            for u in nb:
+                adj[u].discard(int(v))
+                for w in nb:
+                    if w != u:
+                        adj[u].add(int(w))
+            alive[v] = False
+    return pats
+
+
+@pytest.mark.parametrize("shape,levels", [((7, 7), 3), ((16, 16), 4), ((6, 5, 7), 4), ((8, 8, 8), 4)])
+def test_fill_pattern_brute_force(shape, levels):
+    """Block pattern of every step against a vertex-level symbolic elimination
+    (ND creates fill only among neighbours of an eliminated cluster, Sec. 2.1/2.4)."""
+    p = gridgen.laplacian(shape)
+    an = O.Analysis(p.n, p.rowptr, p.colind, p.coords, levels)
+    pats = _brute_force_pattern(p, an)
+    for st, pat in zip(an.steps, pats):
+        assert set(map(tuple, st.blocks)) == pat
+
+
+@pytest.mark.parametrize("shape,levels", [((7, 7), 3), ((16, 16), 5), ((6, 5, 7), 4), ((8, 8, 8), 5)])
+@pytest.mark.parametrize("tol,skip", [(0.0, 0), (0.3, 99)])
+def test_exact_when_nothing_truncated(shape, levels, tol, skip):
+    """With eps = 0 (full rank kept) or sparsification skipped ("Direct", Sec. 4),
+    M M^T = A^-1: the preconditioned solve equals a dense Cholesky solve."""
+    p = gridgen.laplacian(shape)
+    A = p.scipy().toarray()
+    b = np.random.default_rng(7).standard_normal((p.n, 3))
+    x_ref = sla.cho_solve(sla.cho_factor(A), b)
+    an = O.Analysis(p.n, p.rowptr, p.colind, p.coords, levels, skip)
+    fac = O.factor(an, p.values, tol)
+    z = O.apply(fac, b)
+    assert np.abs(z - x_ref).max() <= 1e-12 * np.abs(x_ref).max()
+    _, it, rr = O.pcg(p.scipy(), b, lambda r: O.apply(fac, r))
+    assert np.all(it == 1) and np.all(rr < 1e-13)
+
+
+def test_exact_variable_coefficients():
+    """Exactness also holds for the high-contrast variable-coefficient operator."""
+    p = gridgen.variable_coefficient((6, 7, 5), np.random.default_rng(3), -3, 3)
+    A = p.scipy().toarray()
+    b = np.random.default_rng(1).standard_normal((p.n, 2))
+    x_ref = sla.cho_solve(sla.cho_factor(A), b)
+    an = O.Analysis(p.n, p.rowptr, p.colind, p.coords, 4)
+    fac = O.factor(an, p.values, 0.0)
+    z = O.apply(fac, b)
+    assert np.abs(z - x_ref).max() <= 1e-10 * np.abs(x_ref).max()
+
+
+def test_full_preconditioner_dense_identity():
+    """F A F^T = I exactly at eps = 0, where z = F^T F r is the apply (Sec. 2.8)."""
+    p = gridgen.laplacian((9, 8))
+    A = p.scipy().toarray()
+    an = O.Analysis(p.n, p.rowptr, p.colind, p.coords, 4)
+    fac = O.factor(an, p.values, 0.0)
+    Minv = O.apply(fac, np.eye(p.n))          # = F^T F
+    assert np.abs(Minv @ A - np.eye(p.n)).max() < 1e-12
+
+
+@pytest.mark.parametrize("eps", [1e-12, 1e-2, 0.5, 0.9, 1.0, 2.0])
+def test_never_breaks_down(eps):
+    """OrthS never breaks down for any eps >= 0 (Corollary, Sec. 3.2), including on
+    a high-contrast operator; M M^T stays SPD."""
+    p = gridgen.variable_coefficient((9, 8, 7), np.random.default_rng(11), -3, 3)
+    an = O.Analysis(p.n, p.rowptr, p.colind, p.coords, 5)
+    fac = O.factor(an, p.values, eps)
+    P = O.apply(fac, np.eye(p.n))
+    assert np.allclose(P, P.T, atol=1e-10 * np.abs(P).max())
+    assert np.linalg.eigvalsh(0.5 * (P + P.T)).min() > 0
+
+
+def test_accuracy_improves_as_eps_decreases():
+    """||I - F A F^T|| shrinks with eps (qualitative claim of Sec. 4)."""
+    p = gridgen.laplacian((8, 8, 8))
+    A = p.scipy().toarray()
+    an = O.Analysis(p.n, p.rowptr, p.colind, p.coords, 5)
+    errs = []
+    for eps in [0.5, 1e-1, 1e-2, 1e-4, 1e-8]:
+        fac = O.factor(an, p.values, eps)
+        P = O.apply(fac, np.eye(p.n))
+        w = np.linalg.eigvals(P @ A).real
+        errs.append(w.max() / w.min())
+    assert all(a >= b * 0.999 for a, b in zip(errs, errs[1:])), errs
+    assert errs[-1] < 1 + 1e-6
+
+
+def test_cg_iterations_fall_with_eps():
+    p = gridgen.laplacian((12, 12, 12))
+    b = gridgen.rhs(np.random.default_rng(5), p.n, 1)
+    an = O.Analysis(p.n, p.rowptr, p.colind, p.coords, 6)
+    its = []
+    for eps in [1e-1, 1e-2, 1e-4]:
+        fac = O.factor(an, p.values, eps)
+        _, it, rr = O.pcg(p.scipy(), b, lambda r: O.apply(fac, r))
+        assert rr[0] <= 1e-12
+        its.append(int(it[0]))
+    assert its[0] > its[1] > its[2], its
+
+
+# ---------------------------------------------------------------- CPQR pins
+@pytest.mark.parametrize("m,n,seed", [(20, 35, 0), (35, 20, 1), (49, 120, 2), (7, 7, 3)])
+def test_cpqr_matches_geqp3(m, n, seed):
+    """Pivots and |R_ii| agree with LAPACK geqp3 (the routine of Sec. 4 intro) on
+    random matrices, whose column norms have no ties."""
+    A = np.random.default_rng(seed).standard_normal((m, n))
+    r, V, tau, W, perm = O.cpqr(A, 0.0)
+    Q, R, P = sla.qr(A, pivoting=True, mode="economic")
+    k = min(m, n)
+    assert r == k
+    assert np.array_equal(perm[:k], P[:k])
+    Rd = np.abs(np.diag(W[:, perm]))
+    assert np.allclose(Rd, np.abs(np.diag(R)), rtol=1e-12)
+    # W = Q^T A restricted to the kept rows; Q orthogonal
+    Qf = O.apply_q(V, tau, np.eye(m))
+    assert np.abs(Qf.T @ Qf - np.eye(m)).max() < 1e-13
+    assert np.abs((Qf.T @ A)[:r] - W).max() < 1e-12 * np.abs(A).max()
+    if m > k:
+        assert np.abs((Qf.T @ A)[r:]).max() < 1e-12 * np.abs(A).max()
+
+
+@pytest.mark.parametrize("eps", [1e-8, 1e-6, 1e-3])
+def test_cpqr_rank_of_noisy_low_rank(eps):
+    rng = np.random.default_rng(4)
+    k = 9
+    A = rng.standard_normal((40, k)) @ rng.standard_normal((k, 90)) + 1e-10 * rng.standard_normal((40, 90))
+    r, *_ = O.cpqr(A, eps)
+    assert r == k
+
+
+def test_cpqr_special_cases():
+    assert O.cpqr(np.zeros((5, 8)), 1e-2)[0] == 0          # R_00 = 0
+    A = np.random.default_rng(0).standard_normal((6, 9))
+    assert O.cpqr(A, 0.0)[0] == 6                           # eps = 0 keeps min(m, n)
+    assert O.cpqr(A, 1.5)[0] == 0                           # eps > 1 keeps nothing
+    assert O.cpqr(A, 1.0)[0] >= 1                           # |R_00| >= 1 * |R_00|
+
+
+def test_cpqr_tie_goes_to_first_column():
+    A = np.eye(4)[:, [0, 1, 2, 3]] * 2.0
+    r, V, tau, W, perm = O.cpqr(A, 0.0)
+    assert list(perm) == [0, 1, 2, 3]
+
+
+def test_sparsification_schur_identity():
+    """Theorem of Sec. 3.2: with A_pp = I and A_pn = Q [W_cn; W_fn], the n-n Schur
+    complement after dropping f is S_B = S_A + W_fn^T W_fn, and B_p is SPD."""
+    rng = np.random.default_rng(2)
+    np_, nn = 12, 30
+    X = rng.standard_normal((np_ + nn, np_ + nn))
+    A = X @ X.T + (np_ + nn) * np.eye(np_ + nn)
+    Lp = np.linalg.cholesky(A[:np_, :np_])
+    Apn = sla.solve_triangular(Lp, A[:np_, np_:], lower=True)   # scaled so A_pp = I
+    Ann = A[np_:, np_:]
+    for eps in [0.5, 0.1, 1e-2]:
+        r, V, tau, W, perm = O.cpqr(Apn, eps)
+        Qf = O.apply_q(V, tau, np.eye(np_))
+        full = Qf.T @ Apn
+        Wc, Wf = full[:r], full[r:]
+        assert np.abs(Wc - W).max() < 1e-12
+        S_A = Ann - Apn.T @ Apn
+        S_B = Ann - Wc.T @ Wc
+        assert np.abs(S_B - (S_A + Wf.T @ Wf)).max() < 1e-10
+        B = np.block([[np.eye(r), Wc], [Wc.T, Ann]])
+        assert np.linalg.eigvalsh(B).min() > 0
+        # dropped part bounded by the truncation rule
+        if r < np_:
+            assert np.linalg.norm(Wf, 2) <= np.sqrt(nn) * eps * np.linalg.norm(Apn[:, perm[0]])
+
+
+# ---------------------------------------------------------------- misc pins
+def test_scale_invariance():
+    """A -> 7.3 A leaves ranks and iteration counts unchanged (ratio rule + Cholesky scaling)."""
+    p = gridgen.laplacian((10, 9, 8))
+    b = gridgen.rhs(np.random.default_rng(9), p.n, 1)
+    an = O.Analysis(p.n, p.rowptr, p.colind, p.coords, 5)
+    f1 = O.factor(an, p.values, 1e-2)
+    f2 = O.factor(an, 7.3 * p.values, 1e-2)
+    assert f1.stats["ranks"] == f2.stats["ranks"]
+    A = p.scipy()
+    _, i1, _ = O.pcg(A, b, lambda r: O.apply(f1, r))
+    _, i2, _ = O.pcg(7.3 * A, b, lambda r: O.apply(f2, r))
+    assert np.array_equal(i1, i2)
+
+
+def test_not_spd_detected():
+    p = gridgen.laplacian((8, 8))
+    vals = p.values.copy()
+    d = np.nonzero(p.colind == 0)[0][0]     # row 0 diagonal
+    vals[d] = -4.0
+    an = O.Analysis(p.n, p.rowptr, p.colind, p.coords, 3)
+    with pytest.raises(O.NotSPD) as e:
+        O.factor(an, vals, 1e-2)
+    assert e.value.step == 1
+
+
+def test_pcg_zero_rhs_and_solution():
+    p, b, L = gridgen.config_problem("c1")
+    an = O.Analysis(p.n, p.rowptr, p.colind, p.coords, L)
+    fac = O.factor(an, p.values, 1e-2)
+    A = p.scipy()
+    x, it, rr = O.pcg(A, np.zeros((p.n, 1)), lambda r: O.apply(fac, r))
+    assert it[0] == 0 and np.all(x == 0)
+    x, it, rr = O.pcg(A, b, lambda r: O.apply(fac, r))
+    xs = spla.spsolve(A.tocsc(), b[:, 0])
+    assert rr[0] <= 1e-12
+    assert np.abs(x[:, 0] - xs).max() <= 1e-10 * np.abs(xs).max()
+
+
+def test_generator_operator():
+    """The generator builds the stated stencil: SPD, symmetric, row sums 0 inside."""
+    p = gridgen.laplacian((5, 4, 3))
+    A = p.scipy().toarray()
+    assert np.array_equal(A, A.T)
+    v = 1 + 5 * (1 + 4 * 1)   # interior vertex (1,1,1)
+    assert A[v, v] == 6 and A[v].sum() == 0
+    q = gridgen.variable_coefficient((4, 3, 5), np.random.default_rng(0), -3, 3)
+    B = q.scipy().toarray()
+    assert np.allclose(B, B.T) and np.linalg.eigvalsh(B).min() > 0
