@@ -1,0 +1,153 @@
+/* spand.h -- C ABI of the MI355X sparsified nested dissection library (libspand.so).
+ *
+ * Solves A x = b for a sparse symmetric positive-definite A (Cambier et al.,
+ * "An algebraic sparsified nested dissection algorithm using low-rank
+ * approximations", Sec. 1, eq. (1)) with CG preconditioned by the approximate
+ * factorization M of Algorithm 3 (OrthS: block Cholesky elimination, block
+ * diagonal scaling, orthogonal sparsification, merge), M^T A M ~ I (Sec. 2.8).
+ *
+ * Conventions
+ *  - Every call returns spand_status; SPAND_OK == 0.  No call aborts or prints.
+ *    The text of the last error of a handle is available from spand_error_string.
+ *  - The caller owns every array it passes; the library keeps no caller pointer
+ *    after a call returns.  The handle owns copies of what it needs and all
+ *    device memory it allocates; spand_destroy releases them.
+ *  - "host" arrays are ordinary CPU memory.  "device" arrays are HIP device
+ *    memory on the current device (e.g. a torch tensor's data_ptr()).
+ *  - Matrices are given as the FULL symmetric CSR pattern (both triangles and
+ *    the diagonal), rows 0..n-1, column indices sorted within a row.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ *  - State machine: analyze -> factor* -> solve*.  factor may be repeated with
+ *    new values (same pattern) or new tol/skip/prec; solve before any
+ *    successful factor returns SPAND_E_STATE.
+ */
+#ifndef SPAND_H
+#define SPAND_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spand_ctx* spand_t;
+
+typedef enum {
+  SPAND_OK = 0,
+  SPAND_E_INVALID = 1, /* bad argument, non-symmetric pattern, non-finite value */
+  SPAND_E_NOT_SPD = 2, /* a Cholesky pivot failed; site in spand_stats.fail_* */
+  SPAND_E_NOCONV = 3,  /* PCG hit maxit; x, iters, relres are still written */
+  SPAND_E_NOMEM = 4,   /* device or host allocation failed */
+  SPAND_E_HIP = 5,     /* a HIP runtime call failed (text in spand_error_string) */
+  SPAND_E_STATE = 6    /* call out of order (e.g. solve before factor) */
+} spand_status;
+
+/* Arithmetic of the dense Schur-complement products (TRSM-by-inverse and SYRK of
+ * the elimination, Sec. 2.4).  Trailing storage, Cholesky pivots, CPQR, the apply
+ * and PCG are FP64 in every mode. */
+typedef enum { SPAND_FP64 = 0, SPAND_FP32 = 1, SPAND_BF16X3 = 2 } spand_prec;
+
+/* Per-run statistics (the paper's metrics of Sec. 4: t_P, t_F, t_S, n_CG,
+ * size_Top, mem_F). Times in seconds measured with host clocks around the calls,
+ * after device synchronisation. */
+typedef struct {
+  double t_analyze;      /* t_P: ordering, clustering and symbolic pattern */
+  double t_factor;       /* t_F: numerical factorization (excludes analyze) */
+  double t_solve;        /* t_S: total PCG time of the last solve */
+  int64_t n;             /* matrix dimension */
+  int32_t levels;        /* ND tree depth (root = level 1, leaves = level L) */
+  int32_t n_steps;       /* = levels */
+  int32_t last_iters;    /* max PCG iteration count over the RHS of the last solve */
+  int32_t s_top;         /* size of the top separator right before its elimination */
+  int64_t m_F;           /* stored factor entries (L_s, G_ns, L_p, Householder) */
+  double schur_flops;    /* algorithmic flops of the elimination TRSM + SYRK */
+  double schur_seconds;  /* summed device time of those kernels (HIP events) */
+  int32_t fail_step;     /* on SPAND_E_NOT_SPD: elimination step (1-based) */
+  int32_t fail_cluster;  /* ... cluster id within that step */
+  int32_t fail_phase;    /* ... 0 = elimination, 1 = scaling */
+  int32_t reserved;
+} spand_stats;
+
+/* Ordering, clustering and symbolic factorization (Algorithm 2 with a geometric
+ * vertex separator, Sec. 2.3; cluster hierarchy, Sec. 2.7; fill pattern, Sec. 2.4).
+ *   n        matrix dimension (>= 1)
+ *   rowptr   host, n+1 entries, rowptr[0] = 0
+ *   colind   host, rowptr[n] entries, sorted per row, pattern symmetric, diagonal present
+ *   dim      2 or 3; coords host, n*dim doubles, row-major (x, y[, z]) per vertex
+ *   levels   ND tree depth L >= 1 (2^(L-1) leaves)
+ *   out      receives the new handle (NULL on failure)
+ * Host-only: touches no GPU.  Errors: SPAND_E_INVALID, SPAND_E_NOMEM. */
+spand_status spand_analyze(int64_t n, const int64_t* rowptr, const int32_t* colind,
+                           int32_t dim, const double* coords, int32_t levels, spand_t* out);
+
+/* Numerical factorization, Algorithm 3 (OrthS), on the GPU.
+ *   values   device, rowptr[n] doubles in the CSR order given to analyze
+ *   tol      sparsification tolerance eps >= 0: keep the leading CPQR steps with
+ *            |R_jj| >= eps |R_00| (Sec. 4 intro); eps = 0 keeps full rank
+ *   skip     number of initial elimination steps without scaling/sparsification
+ *            (skip >= levels gives the exact ND Cholesky, "Direct" in Sec. 4)
+ *   prec     arithmetic of the Schur products (spand_prec)
+ * Synchronises the handle's stream.  Errors: SPAND_E_INVALID (negative tol,
+ * non-finite values), SPAND_E_NOT_SPD (site in stats), SPAND_E_NOMEM, SPAND_E_HIP. */
+spand_status spand_factor(spand_t h, const double* values, double tol, int32_t skip, spand_prec prec);
+
+/* PCG with the preconditioner M M^T, x0 = 0, FP64 (Sec. 4: stop at ||Ax-b||/||b|| <= rtol).
+ *   nrhs     number of right-hand sides (>= 1)
+ *   b        device, n x nrhs column-major
+ *   x        device, n x nrhs column-major, output
+ *   rtol     relative residual target on the recursive residual (e.g. 1e-12)
+ *   maxit    iteration cap (>= 1)
+ *   iters    host, nrhs ints: iterations taken per RHS (0 for b = 0)
+ *   relres   host, nrhs doubles: true relative residual ||b - A x|| / ||b|| at exit
+ * Errors: SPAND_E_STATE (no factor), SPAND_E_INVALID (non-finite b),
+ * SPAND_E_NOCONV (some RHS hit maxit; outputs still written), SPAND_E_HIP. */
+spand_status spand_solve(spand_t h, int32_t nrhs, const double* b, double* x, double rtol,
+                         int32_t maxit, int32_t* iters, double* relres);
+
+/* Preconditioner apply z = M M^T r (Sec. 2.8) for nrhs columns; r, z device n x nrhs
+ * column-major (may not alias).  Errors: SPAND_E_STATE, SPAND_E_HIP. */
+spand_status spand_apply(spand_t h, int32_t nrhs, const double* r, double* z);
+
+/* Use this HIP stream (hipStream_t passed as void*) for all later device work of
+ * the handle; NULL selects the default stream. */
+spand_status spand_set_stream(spand_t h, void* hip_stream);
+
+/* Copy the statistics of the last analyze/factor/solve into *s. */
+spand_status spand_get_stats(spand_t h, spand_stats* s);
+
+/* Per-vertex separator ids of Algorithm 2: S, L, R as level * 2^32 + index
+ * ("none" = 0); host arrays of n entries each. */
+spand_status spand_get_ordering(spand_t h, int64_t* S, int64_t* L, int64_t* R);
+
+/* Symbolic structure of elimination step `step` (1-based; level = levels - step + 1).
+ * counts (host, 6 entries) receives: number of clusters nc, number eliminated ne,
+ * number of blocks before elimination nb, number of blocks among remaining clusters
+ * after fill na, ND level, total neighbour entries of the eliminated clusters. */
+spand_status spand_step_counts(spand_t h, int32_t step, int64_t* counts);
+
+/* Arrays of step `step`, sized by spand_step_counts (any pointer may be NULL):
+ *   keys    nc*3 int64: S, L, R of each cluster in cluster order (pointers truncated)
+ *   parent  nc int32: cluster id at the next step (-1 if eliminated or last step)
+ *   colour  nc int32: sparsification colour (-1 for eliminated clusters)
+ *   before  nb*2 int32: block pairs (i, j), i >= j, sorted, before elimination
+ *   after   na*2 int32: block pairs among remaining clusters after fill */
+spand_status spand_step_structure(spand_t h, int32_t step, int64_t* keys, int32_t* parent,
+                                  int32_t* colour, int32_t* before, int32_t* after);
+
+/* After a factor: sizes (nc int32) of every cluster of step `step` before its
+ * elimination and ranks (nc int32) kept after sparsification (= size when not
+ * sparsified, -1 for eliminated clusters). */
+spand_status spand_step_ranks(spand_t h, int32_t step, int32_t* sizes, int32_t* ranks);
+
+/* Text of the last error on h (or of the last failed analyze when h is NULL).
+ * Valid until the next call on h. */
+const char* spand_error_string(spand_t h);
+
+/* Release the handle and all its memory.  NULL-safe. */
+void spand_destroy(spand_t h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPAND_H */

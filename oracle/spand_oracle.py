@@ -465,7 +465,9 @@ def factor(an: Analysis, values, tol):
             order = sorted(rem, key=lambda p: (st.colour[p], p))
             for p in order:
                 nb = st.nbrs[p]
-                if not nb or sizes[p] == 0:
+                # no coupled dofs (no neighbour, or all neighbours reduced to
+                # zero size): p is left as it is, with A_pp = I after scaling
+                if sizes[p] == 0 or sum(sizes[q] for q in nb) == 0:
                     sf.ranks[p] = sizes[p]
                     continue
                 Apn = np.hstack([_get(blocks, p, q) for q in nb])

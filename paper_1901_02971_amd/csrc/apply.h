@@ -1,0 +1,77 @@
+// Descriptors and launchers of the preconditioner apply and PCG vector kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace spand {
+
+struct ElimAp {
+  const double* Linv;  // ns x ns, ld ns (inverse of the pivot block's Cholesky factor)
+  const double* G;     // nN x ns, ld nN (A_{N_s s} L_s^{-T})
+  int32_t ns, nN;
+  int64_t slot_s;      // offset of s's slots in the step slot array
+  int64_t slot_N;      // offset of s's neighbour slots in the step neighbour-slot array
+  int64_t tmp;         // offset of s's rows in the apply scratch
+};
+struct TargetAp {
+  int32_t nn, cbeg, cend, pad;
+  int64_t slot_n;
+};
+struct TargetContrib {
+  const double* G;  // rows of n inside G_s, ld ldG
+  int32_t ldG, ns;
+  int64_t tmp_s;    // where L_s^{-1} x_s lives in the apply scratch
+};
+struct ScaleAp {
+  const double* Linv;  // np x np
+  int32_t np, pad;
+  int64_t slot_p;
+  int64_t tmp;
+};
+struct HouseAp {
+  const double* V;    // np x r reflectors, ld np
+  const double* tau;  // r
+  int32_t np, r;
+  int64_t slot_p;
+};
+
+// Device-side view of one step for the apply.
+struct StepDev {
+  const ElimAp* elim;
+  const TargetAp* target;
+  const TargetContrib* contrib;
+  const ScaleAp* scale;
+  const HouseAp* house;
+  const int32_t* slot;
+  const int32_t* nslot;
+  int64_t nslot_len;
+  int32_t n_elim, n_target, n_scale, n_house;
+};
+
+struct ApplyArgs {
+  double* x;        // n x nrhs vector being transformed, ld ldx
+  int64_t ldx;
+  int32_t nrhs, pad;
+  double* tmp;      // scratch, ld ldt
+  int64_t ldt;
+  double* gbuf;     // gathered neighbour values, ld ldg
+  int64_t ldg;
+  const int32_t* slot;   // step slot array
+};
+
+void apply_step_forward(const StepDev& s, const ApplyArgs& a, hipStream_t st);
+void apply_step_backward(const StepDev& s, const ApplyArgs& a, hipStream_t st);
+
+void launch_spmv(const int64_t* rowptr, const int32_t* colind, const double* val, int64_t n, int nrhs,
+                 const double* x, double* y, hipStream_t s);
+void launch_dot(const double* a, const double* b, int64_t n, int nrhs, double* partial, int nblk, double* out,
+                hipStream_t s);
+void launch_update_xr(int64_t n, int nrhs, const double* rz, const double* pq, const int32_t* active,
+                      const double* p, const double* q, double* x, double* r, hipStream_t s);
+void launch_update_p(int64_t n, int nrhs, const double* rz_new, const double* rz, const int32_t* active,
+                     const double* z, double* p, hipStream_t s);
+void launch_residual(int64_t len, const double* b, double* y, hipStream_t s);
+
+}  // namespace spand

@@ -1,0 +1,80 @@
+// Handle state of libspand: symbolic analysis, device factor storage and the
+// per-step descriptors of the preconditioner apply.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "apply.h"
+#include "kernels.h"
+#include "spand_internal.h"
+
+namespace spand {
+
+// Owning device allocation.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+struct StepNum {
+  std::vector<int32_t> size;    // cluster sizes before elimination
+  std::vector<int32_t> rank;    // kept size after sparsification (-1: eliminated)
+  std::vector<int64_t> slot_ptr;
+  std::vector<int32_t> slot;    // current dofs of every cluster (vertex ids)
+  DevBuf elim, scale, house;    // factor pieces
+  DevBuf d_slot, d_nslot;       // slot arrays on the device
+  // apply descriptors
+  DevBuf d_elim, d_target, d_contrib, d_scale, d_house;
+  int32_t n_elim_ap = 0, n_target = 0, n_scale = 0, n_house = 0;
+  int64_t nslot_len = 0;
+  int64_t tmp_elim = 0, tmp_scale = 0;  // doubles per RHS of temp needed
+  std::vector<ElimAp> h_elim;
+  std::vector<TargetAp> h_target;
+  std::vector<TargetContrib> h_contrib;
+  std::vector<ScaleAp> h_scale;
+  std::vector<HouseAp> h_house;
+};
+
+}  // namespace spand
+
+struct spand_ctx {
+  spand::Analysis an;
+  std::string err;
+  hipStream_t stream = nullptr;
+  spand_stats stats{};
+  bool factored = false;
+  int device = -1;
+  std::vector<spand::StepNum> num;
+  spand::DevBuf d_rowptr, d_colind, d_values;  // CSR of A for the SpMV
+  int64_t max_tmp = 0;                          // doubles per RHS for apply scratch
+  int64_t max_gather = 0;                       // doubles per RHS for gathered neighbours
+  // PCG / apply scratch, grown on demand
+  spand::DevBuf work;
+  size_t work_bytes = 0;
+};
+
+namespace spand {
+spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int32_t skip, spand_prec prec);
+spand_status apply_precond(spand_ctx* h, int32_t nrhs, const double* r, double* z, double* tmp);
+spand_status pcg_solve(spand_ctx* h, int32_t nrhs, const double* b, double* x, double rtol, int32_t maxit,
+                       int32_t* iters, double* relres);
+spand_status set_err(spand_ctx* h, spand_status st, const std::string& msg);
+}  // namespace spand

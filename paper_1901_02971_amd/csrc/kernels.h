@@ -1,0 +1,94 @@
+// Device-side descriptor types and kernel launchers of libspand (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace spand {
+
+// Batched Cholesky + triangular inverse of one diagonal block.
+struct CholDesc {
+  double* A;     // n x n, column-major, ld lda; lower triangle overwritten by L
+  double* Linv;  // n x n output, ld n: L^{-1} (zeros above the diagonal)
+  int32_t n, lda;
+  int32_t id;    // cluster id reported on failure
+  int32_t pad;
+};
+
+// One product C = alpha * op(A) op(B) + beta * C on column-major operands.
+enum : int32_t {
+  G_TA = 1,      // op(A) = A^T
+  G_TB = 2,      // op(B) = B^T
+  G_TRIA = 4,    // op(A)(m,k) = 0 for k > m (lower-triangular op(A))
+  G_TRIB = 8,    // op(B)(k,n) = 0 for k > n
+  G_LOWERC = 16  // only tiles with tile row >= tile column are produced (host side)
+};
+struct GemmDesc {
+  const double* A;
+  const double* B;
+  double* C;
+  int32_t M, N, K;
+  int32_t lda, ldb, ldc;
+  int32_t flags;
+  int32_t pad;
+  double alpha, beta;
+};
+struct TileRef {
+  int32_t desc, tm, tn, pad;
+};
+
+// Target block of the Schur complement reduction.
+struct ReduceDesc {
+  double* T;          // target block, ld ldT
+  int32_t ldT, rows, cols, diag;  // diag: target is a diagonal (square) block
+  int32_t c_begin, c_end;         // contributions [c_begin, c_end) in ascending s
+};
+struct ContribDesc {
+  const double* C;  // contribution block start inside C_s, ld ldC
+  int32_t ldC, pad;
+};
+
+// Strided copy (optionally transposed) used by merge and assembly.
+struct CopyDesc {
+  const double* src;
+  double* dst;
+  int32_t lds, ldd, rows, cols, trans, pad;
+};
+
+// Sparsification of one interface p (Sec. 2.6.1).
+// The width of A_pn is known only on the device: a neighbour q sparsified in an
+// earlier colour class has shrunk to its rank, read from cursize[q].
+struct SparsDesc {
+  double* ws;      // m x ncols workspace, row-major (row i = dofs of p); sized for the
+                   // pre-sparsification width
+  double* nrm;     // ncols scratch
+  int32_t* perm;   // ncols scratch
+  double* V;       // m x min(m, ncols_max) reflectors, column-major, ld m
+  double* tau;     // min(m, ncols_max)
+  double* diag;    // diagonal block of p (ld ldd), set to I_r on exit
+  int32_t m, ldd, seg_begin, seg_end, id, pad;
+};
+struct SegDesc {
+  double* blk;  // block holding A_pq: trans=0 -> A_pq[r][c] = blk[r + c*ld]; trans=1 -> blk[c + r*ld]
+  int32_t ld, trans, q;
+  int32_t ncol, col_off;  // filled in by the kernel from cursize[q]
+  int32_t pad;
+};
+
+void launch_scatter_values(const double* vals, const int64_t* dst, int64_t nnz, double* arena, int32_t* flag,
+                           hipStream_t s);
+void launch_chol_inv(const CholDesc* d, int32_t count, int32_t* fail, hipStream_t s);
+void launch_gemm(const GemmDesc* d, const TileRef* tiles, int64_t ntiles, int prec, hipStream_t s);
+void launch_reduce(const ReduceDesc* d, int32_t count, const ContribDesc* c, hipStream_t s);
+void launch_copy(const CopyDesc* d, int64_t count, hipStream_t s);
+void launch_set_identity(double* const* diag, const int32_t* n, const int32_t* ld, int32_t count, hipStream_t s);
+// cursize: current size of every cluster of the step; the kernel sets
+// cursize[p] = kept rank when it finishes p and nref[p] = number of reflectors
+// stored (0 when no coupled dofs were left and p was not sparsified).
+void launch_sparsify(const SparsDesc* d, int32_t count, SegDesc* seg, double eps, int32_t* cursize, int32_t* nref,
+                     hipStream_t s);
+
+constexpr int GEMM_TILE = 64;
+
+}  // namespace spand

@@ -1,0 +1,452 @@
+// Dense batched kernels of the factorization (gfx950, wave64).
+//
+//  * k_chol_inv   Cholesky of a pivot block (Sec. 2.4) or interface block (Sec. 2.5)
+//                 and the inverse of its factor, one workgroup per block.
+//  * k_gemm       batched variable-size GEMM over a flat list of 64x64 output tiles;
+//                 carries the TRSM-by-inverse and the SYRK of the Schur update
+//                 (Sec. 2.4) and the two-sided scaling of Sec. 2.5.
+//  * k_reduce     deterministic Schur-complement accumulation: every target block
+//                 subtracts its contributions in ascending eliminated-cluster order.
+//  * k_copy       strided (optionally transposed) block copies for the merge (Sec. 2.7).
+//  * k_sparsify   truncated column-pivoted QR of A_pn with write-back of W_cn
+//                 (Sec. 2.6.1), one workgroup per interface.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels.h"
+
+namespace spand {
+
+#define WG 256
+
+// ---------------------------------------------------------------- reductions
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline int wave_min_i(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+// Block-wide reductions (blockDim.x == WG); `red` is WG/64 doubles of LDS.
+__device__ inline double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int q = 0; q < WG / 64; ++q) s += red[q];
+  return s;
+}
+__device__ inline double block_max(double v, double* red) {
+  v = wave_max(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double s = red[0];
+  for (int q = 1; q < WG / 64; ++q) s = fmax(s, red[q]);
+  return s;
+}
+__device__ inline int block_min_i(int v, int* red) {
+  v = wave_min_i(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  int s = red[0];
+  for (int q = 1; q < WG / 64; ++q) s = min(s, red[q]);
+  return s;
+}
+
+// ---------------------------------------------------------------- CSR scatter
+__global__ void k_scatter_values(const double* __restrict__ vals, const int64_t* __restrict__ dst, int64_t nnz,
+                                 double* __restrict__ arena, int32_t* flag) {
+  int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  double v = vals[e];
+  if (!isfinite(v)) atomicOr(flag, 1);
+  int64_t d = dst[e];
+  if (d >= 0) arena[d] = v;
+}
+
+void launch_scatter_values(const double* vals, const int64_t* dst, int64_t nnz, double* arena, int32_t* flag,
+                           hipStream_t s) {
+  if (nnz == 0) return;
+  hipLaunchKernelGGL(k_scatter_values, dim3((nnz + 255) / 256), dim3(256), 0, s, vals, dst, nnz, arena, flag);
+}
+
+// ---------------------------------------------------------------- Cholesky + inverse
+// Right-looking Cholesky in place (lower triangle), then the inverse of L by rows:
+// X[i][c] = (delta_ic - sum_{c<=k<i} L[i][k] X[k][c]) / L[i][i].  A non-positive or
+// non-finite pivot records the block id in *fail (smallest id wins) and the
+// factorization continues on a unit pivot so that every wave finishes normally.
+__global__ void __launch_bounds__(WG) k_chol_inv(const CholDesc* __restrict__ descs, int32_t* fail) {
+  const CholDesc d = descs[blockIdx.x];
+  const int n = d.n, lda = d.lda;
+  double* A = d.A;
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    double piv = A[k + (int64_t)k * lda];
+    if (!(piv > 0.0) || !isfinite(piv)) {
+      if (threadIdx.x == 0) bad = 1;
+      piv = 1.0;
+    }
+    const double r = sqrt(piv);
+    const double rinv = 1.0 / r;
+    __syncthreads();
+    if (threadIdx.x == 0) A[k + (int64_t)k * lda] = r;
+    for (int i = k + 1 + threadIdx.x; i < n; i += WG) A[i + (int64_t)k * lda] *= rinv;
+    __syncthreads();
+    // trailing update of the lower triangle, flattened: entry q of the packed
+    // lower triangle of size m = n-k-1 (row-major) -> (i', j')
+    const int m = n - k - 1;
+    const int64_t cnt = (int64_t)m * (m + 1) / 2;
+    const double* colk = A + (int64_t)k * lda;
+    for (int64_t q = threadIdx.x; q < cnt; q += WG) {
+      int ip = (int)((sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
+      while ((int64_t)ip * (ip + 1) / 2 > q) --ip;
+      while ((int64_t)(ip + 1) * (ip + 2) / 2 <= q) ++ip;
+      const int jp = (int)(q - (int64_t)ip * (ip + 1) / 2);
+      const int i = k + 1 + ip, j = k + 1 + jp;
+      A[i + (int64_t)j * lda] -= colk[i] * colk[j];
+    }
+    __syncthreads();
+  }
+  if (bad && threadIdx.x == 0) atomicMin(fail, d.id);
+  // inverse, row by row
+  double* X = d.Linv;
+  const int ldx = n;
+  for (int i = 0; i < n; ++i) {
+    const double lii = A[i + (int64_t)i * lda];
+    for (int c = threadIdx.x; c < n; c += WG) {
+      double acc = (c == i) ? 1.0 : 0.0;
+      if (c < i) {
+        for (int k0 = c; k0 < i; ++k0) acc -= A[i + (int64_t)k0 * lda] * X[k0 + (int64_t)c * ldx];
+      }
+      X[i + (int64_t)c * ldx] = (c <= i) ? acc / lii : 0.0;
+    }
+    __syncthreads();
+  }
+}
+
+void launch_chol_inv(const CholDesc* d, int32_t count, int32_t* fail, hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_chol_inv, dim3(count), dim3(WG), 0, s, d, fail);
+}
+
+// ---------------------------------------------------------------- batched GEMM
+// 64x64 output tile per workgroup, 256 threads as 16x16, 4x4 outputs each
+// (rows ty + 16*a, columns tx + 16*b), K staged through LDS 16 at a time.
+// prec 0: FP64 multiply-add; prec 1: operands rounded to FP32, FP32 products and
+// FP32 accumulation (the result is stored to the FP64 target).
+template <typename T>
+__global__ void __launch_bounds__(WG) k_gemm(const GemmDesc* __restrict__ descs, const TileRef* __restrict__ tiles) {
+  constexpr int BM = 64, BN = 64, BK = 16;
+  __shared__ T As[BK][BM + 1];
+  __shared__ T Bs[BK][BN + 1];
+  const TileRef tr = tiles[blockIdx.x];
+  const GemmDesc d = descs[tr.desc];
+  const int m0 = tr.tm * BM, n0 = tr.tn * BN;
+  const bool ta = d.flags & G_TA, tb = d.flags & G_TB;
+  int kmax = d.K;
+  if (d.flags & G_TRIA) kmax = min(kmax, m0 + BM);
+  if (d.flags & G_TRIB) kmax = min(kmax, n0 + BN);
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  T acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
+  for (int k0 = 0; k0 < kmax; k0 += BK) {
+    // load op(A)[m0:m0+64, k0:k0+16] and op(B)[k0:k0+16, n0:n0+64]
+#pragma unroll
+    for (int q = 0; q < (BM * BK) / WG; ++q) {
+      const int e = threadIdx.x + q * WG;
+      int mm, kk;
+      if (!ta) { mm = e & 63; kk = e >> 6; } else { kk = e & 15; mm = e >> 4; }
+      const int gm = m0 + mm, gk = k0 + kk;
+      double v = 0.0;
+      if (gm < d.M && gk < kmax && !((d.flags & G_TRIA) && gk > gm))
+        v = ta ? d.A[gk + (int64_t)gm * d.lda] : d.A[gm + (int64_t)gk * d.lda];
+      As[kk][mm] = T(v);
+    }
+#pragma unroll
+    for (int q = 0; q < (BN * BK) / WG; ++q) {
+      const int e = threadIdx.x + q * WG;
+      int nn, kk;
+      if (!tb) { kk = e & 15; nn = e >> 4; } else { nn = e & 63; kk = e >> 6; }
+      const int gn = n0 + nn, gk = k0 + kk;
+      double v = 0.0;
+      if (gn < d.N && gk < kmax && !((d.flags & G_TRIB) && gk > gn))
+        v = tb ? d.B[gn + (int64_t)gk * d.ldb] : d.B[gk + (int64_t)gn * d.ldb];
+      Bs[kk][nn] = T(v);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; ++kk) {
+      T a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[q] = As[kk][ty + 16 * q];
+        b[q] = Bs[kk][tx + 16 * q];
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = fma(a[p], b[q], acc[p][q]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const int gm = m0 + ty + 16 * p;
+    if (gm >= d.M) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int gn = n0 + tx + 16 * q;
+      if (gn >= d.N) continue;
+      double* c = d.C + gm + (int64_t)gn * d.ldc;
+      double v = d.alpha * (double)acc[p][q];
+      if (d.beta != 0.0) v += d.beta * (*c);
+      *c = v;
+    }
+  }
+}
+
+void launch_gemm(const GemmDesc* d, const TileRef* tiles, int64_t ntiles, int prec, hipStream_t s) {
+  if (ntiles == 0) return;
+  if (prec == 0)
+    hipLaunchKernelGGL(k_gemm<double>, dim3(ntiles), dim3(WG), 0, s, d, tiles);
+  else
+    hipLaunchKernelGGL(k_gemm<float>, dim3(ntiles), dim3(WG), 0, s, d, tiles);
+}
+
+// ---------------------------------------------------------------- Schur reduce
+__global__ void __launch_bounds__(WG) k_reduce(const ReduceDesc* __restrict__ descs,
+                                               const ContribDesc* __restrict__ cs) {
+  const ReduceDesc d = descs[blockIdx.x];
+  const int64_t cnt = (int64_t)d.rows * d.cols;
+  for (int64_t e = threadIdx.x; e < cnt; e += WG) {
+    const int r = (int)(e % d.rows), c = (int)(e / d.rows);
+    const bool mirror = d.diag && r < c;
+    double sum = 0.0;
+    for (int q = d.c_begin; q < d.c_end; ++q) {
+      const ContribDesc cd = cs[q];
+      sum += mirror ? cd.C[c + (int64_t)r * cd.ldC] : cd.C[r + (int64_t)c * cd.ldC];
+    }
+    d.T[r + (int64_t)c * d.ldT] -= sum;
+  }
+}
+
+void launch_reduce(const ReduceDesc* d, int32_t count, const ContribDesc* c, hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_reduce, dim3(count), dim3(WG), 0, s, d, c);
+}
+
+// ---------------------------------------------------------------- copies
+__global__ void __launch_bounds__(WG) k_copy(const CopyDesc* __restrict__ descs) {
+  const CopyDesc d = descs[blockIdx.x];
+  const int64_t cnt = (int64_t)d.rows * d.cols;
+  for (int64_t e = threadIdx.x; e < cnt; e += WG) {
+    const int r = (int)(e % d.rows), c = (int)(e / d.rows);
+    d.dst[r + (int64_t)c * d.ldd] = d.trans ? d.src[c + (int64_t)r * d.lds] : d.src[r + (int64_t)c * d.lds];
+  }
+}
+
+void launch_copy(const CopyDesc* d, int64_t count, hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_copy, dim3(count), dim3(WG), 0, s, d);
+}
+
+__global__ void k_set_identity(double* const* diag, const int32_t* n, const int32_t* ld) {
+  double* D = diag[blockIdx.x];
+  const int m = n[blockIdx.x], l = ld[blockIdx.x];
+  for (int64_t e = threadIdx.x; e < (int64_t)m * m; e += blockDim.x) {
+    const int r = (int)(e % m), c = (int)(e / m);
+    D[r + (int64_t)c * l] = (r == c) ? 1.0 : 0.0;
+  }
+}
+
+void launch_set_identity(double* const* diag, const int32_t* n, const int32_t* ld, int32_t count, hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_set_identity, dim3(count), dim3(WG), 0, s, diag, n, ld);
+}
+
+// ---------------------------------------------------------------- sparsification
+// One workgroup per interface p.  Gathers A_pn (m x ncols, row-major in ws), runs
+// Householder QR with column pivoting (norms of the trailing columns recomputed
+// from the updated entries after every step; pivot = first column within a
+// relative 1e-10 of the largest norm; stop at the first step with
+// |R_jj| < eps |R_00|), stores the reflectors, writes W_cn = R[:r,:] P^T back into
+// the blocks of p and sets the diagonal block of p to I_r.
+#define TIE_RTOL 1e-10
+
+__global__ void __launch_bounds__(WG) k_sparsify(const SparsDesc* __restrict__ descs, SegDesc* __restrict__ segs,
+                                                 double eps, int32_t* cursize, int32_t* nref) {
+  const SparsDesc d = descs[blockIdx.x];
+  const int m = d.m;
+  double* ws = d.ws;
+  __shared__ double red[WG / 64];
+  __shared__ int redi[WG / 64];
+  __shared__ double sh_beta, sh_tau, sh_scale;
+  __shared__ int sh_nc;
+  // column layout of A_pn from the neighbours' current sizes
+  if (threadIdx.x == 0) {
+    int off = 0;
+    for (int s = d.seg_begin; s < d.seg_end; ++s) {
+      const int w = cursize[segs[s].q];
+      segs[s].ncol = w;
+      segs[s].col_off = off;
+      off += w;
+    }
+    sh_nc = off;
+  }
+  __syncthreads();
+  const int nc = sh_nc;
+  if (nc == 0) {  // no coupled dofs left: p keeps its size, no reflectors
+    if (threadIdx.x == 0) nref[d.id] = 0;
+    return;
+  }
+  // gather A_pn
+  for (int s = d.seg_begin; s < d.seg_end; ++s) {
+    const SegDesc g = segs[s];
+    const int64_t cnt = (int64_t)m * g.ncol;
+    for (int64_t e = threadIdx.x; e < cnt; e += WG) {
+      int r, c;
+      if (g.trans) { c = (int)(e % g.ncol); r = (int)(e / g.ncol); } else { r = (int)(e % m); c = (int)(e / m); }
+      const double v = g.trans ? g.blk[c + (int64_t)r * g.ld] : g.blk[r + (int64_t)c * g.ld];
+      ws[(int64_t)r * nc + g.col_off + c] = v;
+    }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < nc; c += WG) {
+    double s = 0.0;
+    for (int i = 0; i < m; ++i) {
+      const double v = ws[(int64_t)i * nc + c];
+      s += v * v;
+    }
+    d.nrm[c] = s;
+    d.perm[c] = c;
+  }
+  __syncthreads();
+  const int kmax = min(m, nc);
+  int r = kmax;
+  double r00 = 0.0;
+  for (int j = 0; j < kmax; ++j) {
+    // pivot: first column whose norm is within TIE_RTOL of the largest
+    double lmax = 0.0;
+    for (int c = j + threadIdx.x; c < nc; c += WG) lmax = fmax(lmax, sqrt(d.nrm[c]));
+    const double cmax = block_max(lmax, red);
+    int lidx = 0x7fffffff;
+    for (int c = j + threadIdx.x; c < nc; c += WG)
+      if (sqrt(d.nrm[c]) >= cmax * (1.0 - TIE_RTOL)) { lidx = c; break; }
+    const int piv = block_min_i(lidx, redi);
+    if (piv >= nc) { r = j; break; }  // only non-finite norms left
+    const double pnorm = sqrt(d.nrm[piv]);
+    if (j == 0) {
+      r00 = pnorm;
+      if (r00 == 0.0) { r = 0; break; }
+    }
+    if (pnorm < eps * r00) { r = j; break; }
+    __syncthreads();
+    if (piv != j) {
+      for (int i = threadIdx.x; i < m; i += WG) {
+        const double t = ws[(int64_t)i * nc + j];
+        ws[(int64_t)i * nc + j] = ws[(int64_t)i * nc + piv];
+        ws[(int64_t)i * nc + piv] = t;
+      }
+      if (threadIdx.x == 0) {
+        const double t = d.nrm[j]; d.nrm[j] = d.nrm[piv]; d.nrm[piv] = t;
+        const int pi = d.perm[j]; d.perm[j] = d.perm[piv]; d.perm[piv] = pi;
+      }
+    }
+    __syncthreads();
+    // Householder reflector of column j, rows j..m-1 (dlarfg convention)
+    double part = 0.0;
+    for (int i = j + 1 + threadIdx.x; i < m; i += WG) {
+      const double v = ws[(int64_t)i * nc + j];
+      part += v * v;
+    }
+    const double xn2 = block_sum(part, red);
+    if (threadIdx.x == 0) {
+      const double alpha = ws[(int64_t)j * nc + j];
+      if (xn2 == 0.0) {
+        sh_tau = 0.0; sh_beta = alpha; sh_scale = 0.0;
+      } else {
+        const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+        sh_tau = (beta - alpha) / beta;
+        sh_beta = beta;
+        sh_scale = 1.0 / (alpha - beta);
+      }
+    }
+    __syncthreads();
+    const double tau = sh_tau, scale = sh_scale;
+    double* V = d.V + (int64_t)j * m;
+    for (int i = threadIdx.x; i < m; i += WG) {
+      double v;
+      if (i < j) v = 0.0;
+      else if (i == j) v = 1.0;
+      else v = ws[(int64_t)i * nc + j] * scale;
+      V[i] = v;
+    }
+    if (threadIdx.x == 0) d.tau[j] = tau;
+    __syncthreads();
+    if (threadIdx.x == 0) ws[(int64_t)j * nc + j] = sh_beta;
+    for (int i = j + 1 + threadIdx.x; i < m; i += WG) ws[(int64_t)i * nc + j] = 0.0;
+    // apply H = I - tau v v^T to columns j+1.., recomputing trailing norms (rows j+1..)
+    for (int c = j + 1 + threadIdx.x; c < nc; c += WG) {
+      double w = ws[(int64_t)j * nc + c];
+      for (int i = j + 1; i < m; ++i) w += V[i] * ws[(int64_t)i * nc + c];
+      w *= tau;
+      ws[(int64_t)j * nc + c] -= w;
+      double s = 0.0;
+      for (int i = j + 1; i < m; ++i) {
+        const double v = ws[(int64_t)i * nc + c] - w * V[i];
+        ws[(int64_t)i * nc + c] = v;
+        s += v * v;
+      }
+      d.nrm[c] = s;
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  // W[i][perm[jp]] = R[i][jp] for i <= jp, i < r; scatter into the blocks of p
+  for (int jp = threadIdx.x; jp < nc; jp += WG) {
+    const int col = d.perm[jp];
+    int sidx = d.seg_begin;
+    while (sidx + 1 < d.seg_end && segs[sidx + 1].col_off <= col) ++sidx;
+    const SegDesc g = segs[sidx];
+    const int cc = col - g.col_off;
+    for (int i = 0; i < r; ++i) {
+      const double v = (i <= jp) ? ws[(int64_t)i * nc + jp] : 0.0;
+      if (g.trans) g.blk[cc + (int64_t)i * g.ld] = v;
+      else g.blk[i + (int64_t)cc * g.ld] = v;
+    }
+  }
+  // diagonal block of p -> I_r
+  for (int64_t e = threadIdx.x; e < (int64_t)r * r; e += WG) {
+    const int a = (int)(e % r), b = (int)(e / r);
+    d.diag[a + (int64_t)b * d.ldd] = (a == b) ? 1.0 : 0.0;
+  }
+  if (threadIdx.x == 0) {
+    cursize[d.id] = r;
+    nref[d.id] = r;
+  }
+}
+
+void launch_sparsify(const SparsDesc* d, int32_t count, SegDesc* seg, double eps, int32_t* cursize, int32_t* nref,
+                     hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_sparsify, dim3(count), dim3(WG), 0, s, d, seg, eps, cursize, nref);
+}
+
+}  // namespace spand

@@ -1,0 +1,184 @@
+// Preconditioner apply and FP64 PCG driver (Sec. 2.8 and Sec. 4).
+//
+// PCG (Hestenes-Stiefel), x0 = 0, independent per right-hand side:
+//   r = b, z = M M^T r, p = z, rz = r.z
+//   repeat: q = A p; alpha = rz / p.q; x += alpha p; r -= alpha q;
+//           stop a column when ||r|| <= rtol ||b||; z = M M^T r;
+//           beta = r.z / rz; p = z + beta p.
+// Scalars stay on the device; the host reads the residual norms once per
+// iteration to retire converged columns.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "context.h"
+
+namespace spand {
+
+#define HIPCHK(x)                                                                                   \
+  do {                                                                                              \
+    hipError_t e_ = (x);                                                                            \
+    if (e_ != hipSuccess) return set_err(h, SPAND_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+namespace {
+
+StepDev step_dev(const StepNum& s) {
+  StepDev d{};
+  d.elim = s.d_elim.as<ElimAp>();
+  d.target = s.d_target.as<TargetAp>();
+  d.contrib = s.d_contrib.as<TargetContrib>();
+  d.scale = s.d_scale.as<ScaleAp>();
+  d.house = s.d_house.as<HouseAp>();
+  d.slot = s.d_slot.as<int32_t>();
+  d.nslot = s.d_nslot.as<int32_t>();
+  d.nslot_len = s.nslot_len;
+  d.n_elim = s.n_elim_ap;
+  d.n_target = s.n_target;
+  d.n_scale = s.n_scale;
+  d.n_house = s.n_house;
+  return d;
+}
+
+spand_status ensure_work(spand_ctx* h, size_t bytes) {
+  if (h->work.bytes >= bytes) return SPAND_OK;
+  h->work.release();
+  hipError_t e = hipMalloc(&h->work.p, bytes);
+  if (e != hipSuccess) {
+    h->work.p = nullptr;
+    (void)hipGetLastError();
+    return set_err(h, SPAND_E_NOMEM, "device allocation of solve workspace failed");
+  }
+  h->work.bytes = bytes;
+  return SPAND_OK;
+}
+
+}  // namespace
+
+// z = M M^T r; scratch holds (max_tmp + max_gather) * nrhs doubles.
+spand_status apply_precond(spand_ctx* h, int32_t nrhs, const double* r, double* z, double* scratch) {
+  const int64_t n = h->an.n;
+  if (z != r) HIPCHK(hipMemcpyAsync(z, r, size_t(n) * nrhs * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  ApplyArgs a{};
+  a.x = z;
+  a.ldx = n;
+  a.nrhs = nrhs;
+  a.tmp = scratch;
+  a.ldt = std::max<int64_t>(h->max_tmp, 1);
+  a.gbuf = scratch + a.ldt * nrhs;
+  a.ldg = std::max<int64_t>(h->max_gather, 1);
+  for (size_t t = 0; t < h->num.size(); ++t) {
+    const StepDev d = step_dev(h->num[t]);
+    a.slot = d.slot;
+    apply_step_forward(d, a, h->stream);
+  }
+  for (size_t t = h->num.size(); t-- > 0;) {
+    const StepDev d = step_dev(h->num[t]);
+    a.slot = d.slot;
+    apply_step_backward(d, a, h->stream);
+  }
+  HIPCHK(hipGetLastError());
+  return SPAND_OK;
+}
+
+size_t apply_scratch_doubles(const spand_ctx* h, int32_t nrhs) {
+  return size_t(std::max<int64_t>(h->max_tmp, 1) + std::max<int64_t>(h->max_gather, 1)) * size_t(nrhs);
+}
+
+spand_status apply_public(spand_ctx* h, int32_t nrhs, const double* r, double* z) {
+  spand_status st = ensure_work(h, apply_scratch_doubles(h, nrhs) * sizeof(double));
+  if (st != SPAND_OK) return st;
+  st = apply_precond(h, nrhs, r, z, h->work.as<double>());
+  if (st != SPAND_OK) return st;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return SPAND_OK;
+}
+
+spand_status pcg_solve(spand_ctx* h, int32_t nrhs, const double* b, double* x, double rtol, int32_t maxit,
+                       int32_t* iters, double* relres) {
+  const int64_t n = h->an.n;
+  const size_t vec = size_t(n) * nrhs;
+  const int nblk = int(std::min<int64_t>((n + 255) / 256, 1024));
+  // workspace: r, z, p, q, partials, 8 scalar rows, apply scratch
+  const size_t scal = size_t(nrhs);
+  const size_t doubles = 4 * vec + size_t(nblk) * nrhs + 8 * scal + apply_scratch_doubles(h, nrhs) + 16;
+  spand_status st = ensure_work(h, doubles * sizeof(double) + 64 * sizeof(int32_t) + nrhs * sizeof(int32_t));
+  if (st != SPAND_OK) return st;
+  double* w = h->work.as<double>();
+  double* r = w;
+  double* z = r + vec;
+  double* p = z + vec;
+  double* q = p + vec;
+  double* partial = q + vec;
+  double* bb = partial + size_t(nblk) * nrhs;
+  double* rz = bb + scal;
+  double* rz_new = rz + scal;
+  double* pq = rz_new + scal;
+  double* rr = pq + scal;
+  double* scratch = rr + 4 * scal;
+  int32_t* active_d = reinterpret_cast<int32_t*>(scratch + apply_scratch_doubles(h, nrhs) + 16);
+  const hipStream_t s = h->stream;
+
+  std::vector<double> hb(nrhs), hr(nrhs);
+  std::vector<int32_t> act(nrhs, 0);
+  launch_dot(b, b, n, nrhs, partial, nblk, bb, s);
+  HIPCHK(hipMemcpyAsync(hb.data(), bb, scal * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int c = 0; c < nrhs; ++c) {
+    if (!std::isfinite(hb[c])) return set_err(h, SPAND_E_INVALID, "right-hand side contains NaN or Inf");
+    hb[c] = std::sqrt(hb[c]);
+    act[c] = hb[c] > 0.0 ? 1 : 0;
+    iters[c] = 0;
+  }
+  HIPCHK(hipMemsetAsync(x, 0, vec * sizeof(double), s));
+  HIPCHK(hipMemcpyAsync(r, b, vec * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(active_d, act.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  bool any = std::any_of(act.begin(), act.end(), [](int a) { return a != 0; });
+  if (any) {
+    if ((st = apply_precond(h, nrhs, r, z, scratch)) != SPAND_OK) return st;
+    HIPCHK(hipMemcpyAsync(p, z, vec * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_dot(r, z, n, nrhs, partial, nblk, rz, s);
+  }
+  int32_t it = 0;
+  while (any && it < maxit) {
+    launch_spmv(h->d_rowptr.as<int64_t>(), h->d_colind.as<int32_t>(), h->d_values.as<double>(), n, nrhs, p, q, s);
+    launch_dot(p, q, n, nrhs, partial, nblk, pq, s);
+    launch_update_xr(n, nrhs, rz, pq, active_d, p, q, x, r, s);
+    launch_dot(r, r, n, nrhs, partial, nblk, rr, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(hr.data(), rr, scal * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    ++it;
+    for (int c = 0; c < nrhs; ++c) {
+      if (!act[c]) continue;
+      iters[c] = it;
+      if (std::sqrt(hr[c]) <= rtol * hb[c] || !std::isfinite(hr[c])) act[c] = 0;
+    }
+    any = std::any_of(act.begin(), act.end(), [](int a) { return a != 0; });
+    if (!any || it >= maxit) break;
+    HIPCHK(hipMemcpyAsync(active_d, act.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if ((st = apply_precond(h, nrhs, r, z, scratch)) != SPAND_OK) return st;
+    launch_dot(r, z, n, nrhs, partial, nblk, rz_new, s);
+    launch_update_p(n, nrhs, rz_new, rz, active_d, z, p, s);
+    HIPCHK(hipMemcpyAsync(rz, rz_new, scal * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipGetLastError());
+  }
+  // true residual
+  launch_spmv(h->d_rowptr.as<int64_t>(), h->d_colind.as<int32_t>(), h->d_values.as<double>(), n, nrhs, x, q, s);
+  launch_residual(int64_t(vec), b, q, s);
+  launch_dot(q, q, n, nrhs, partial, nblk, rr, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(hr.data(), rr, scal * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  bool noconv = false;
+  for (int c = 0; c < nrhs; ++c) {
+    relres[c] = hb[c] > 0.0 ? std::sqrt(hr[c]) / hb[c] : 0.0;
+    if (act[c]) noconv = true;
+  }
+  h->stats.last_iters = 0;
+  for (int c = 0; c < nrhs; ++c) h->stats.last_iters = std::max(h->stats.last_iters, iters[c]);
+  if (noconv) return set_err(h, SPAND_E_NOCONV, "PCG reached maxit = " + std::to_string(maxit));
+  return SPAND_OK;
+}
+
+}  // namespace spand

@@ -1,0 +1,207 @@
+"""Thin ctypes binding of libspand (names follow include/spand.h).
+
+Argument marshalling only: every step of the factorization, the apply and PCG
+runs inside the HIP library.  Device arrays are torch tensors on a ROCm device
+(``float64``, column-major n x nrhs for vectors, i.e. shape (nrhs, n) contiguous
+or a Fortran-ordered (n, nrhs) view); host arrays are numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+SPAND_FP64, SPAND_FP32, SPAND_BF16X3 = 0, 1, 2
+STATUS = {0: "SPAND_OK", 1: "SPAND_E_INVALID", 2: "SPAND_E_NOT_SPD", 3: "SPAND_E_NOCONV",
+          4: "SPAND_E_NOMEM", 5: "SPAND_E_HIP", 6: "SPAND_E_STATE"}
+
+
+class SpandError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class Stats(C.Structure):
+    _fields_ = [("t_analyze", C.c_double), ("t_factor", C.c_double), ("t_solve", C.c_double),
+                ("n", C.c_int64), ("levels", C.c_int32), ("n_steps", C.c_int32), ("last_iters", C.c_int32),
+                ("s_top", C.c_int32), ("m_F", C.c_int64), ("schur_flops", C.c_double),
+                ("schur_seconds", C.c_double), ("fail_step", C.c_int32), ("fail_cluster", C.c_int32),
+                ("fail_phase", C.c_int32), ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+def library_path() -> str:
+    return os.path.join(HERE, "libspand.so")
+
+
+def load_library():
+    """Load libspand.so; raises if it has not been built (no fallback exists)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1901_02971_amd.build`")
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    i32, i64, f64 = C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "spand_analyze": (i32, [i64, P, P, i32, P, i32, C.POINTER(P)]),
+        "spand_factor": (i32, [P, P, f64, i32, i32]),
+        "spand_solve": (i32, [P, i32, P, P, f64, i32, P, P]),
+        "spand_apply": (i32, [P, i32, P, P]),
+        "spand_set_stream": (i32, [P, P]),
+        "spand_get_stats": (i32, [P, C.POINTER(Stats)]),
+        "spand_get_ordering": (i32, [P, P, P, P]),
+        "spand_step_counts": (i32, [P, i32, P]),
+        "spand_step_structure": (i32, [P, i32, P, P, P, P, P]),
+        "spand_step_ranks": (i32, [P, i32, P, P]),
+        "spand_error_string": (C.c_char_p, [P]),
+        "spand_destroy": (None, [P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def exported_symbols():
+    """Function names declared in include/spand.h."""
+    hdr = os.path.join(os.path.dirname(HERE), "include", "spand.h")
+    src = open(hdr).read()
+    return sorted(set(re.findall(r"\b(spand_[a-z_]+)\s*\(", src)))
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()  # torch tensor
+
+
+def _dev_vec(t, n):
+    """Validate a float64 device tensor holding an n x nrhs column-major block."""
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError("expected a float64 tensor on the GPU")
+    if t.dim() == 1:
+        if t.numel() != n:
+            raise ValueError("length mismatch")
+        return 1
+    if t.dim() == 2 and t.shape[1] == n and t.is_contiguous():
+        return t.shape[0]          # (nrhs, n) row-major = n x nrhs column-major
+    if t.dim() == 2 and t.shape[0] == n and t.t().is_contiguous():
+        return t.shape[1]          # Fortran-ordered (n, nrhs)
+    raise ValueError("expected shape (nrhs, n) contiguous or a column-major (n, nrhs) view")
+
+
+class Solver:
+    """One spaND handle: analyze on construction, then factor / solve / apply."""
+
+    def __init__(self, n, rowptr, colind, coords, levels):
+        lib = load_library()
+        self._lib = lib
+        rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+        colind = np.ascontiguousarray(colind, dtype=np.int32)
+        coords = np.ascontiguousarray(coords, dtype=np.float64)
+        dim = coords.shape[1] if coords.ndim == 2 else 1
+        self.n = int(n)
+        self.levels = int(levels)
+        h = C.c_void_p()
+        st = lib.spand_analyze(self.n, _ptr(rowptr), _ptr(colind), dim, _ptr(coords), self.levels, C.byref(h))
+        if st != 0:
+            raise SpandError(st, lib.spand_error_string(None).decode())
+        self._h = h
+
+    @classmethod
+    def from_problem(cls, problem, levels):
+        return cls(problem.n, problem.rowptr, problem.colind, problem.coords, levels)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.spand_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != 0:
+            raise SpandError(st, self._lib.spand_error_string(self._h).decode())
+
+    def set_stream(self, stream):
+        """Run on a torch.cuda.Stream (or raw hipStream_t int); None = default stream."""
+        raw = None if stream is None else (stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+        self._check(self._lib.spand_set_stream(self._h, raw))
+
+    def factor(self, values, tol, skip=0, prec=SPAND_FP64):
+        import torch
+        if not (isinstance(values, torch.Tensor) and values.is_cuda and values.dtype == torch.float64
+                and values.is_contiguous()):
+            raise TypeError("values must be a contiguous float64 GPU tensor")
+        self._check(self._lib.spand_factor(self._h, _ptr(values), float(tol), int(skip), int(prec)))
+
+    def solve(self, b, x, rtol=1e-12, maxit=500, check=True):
+        nrhs = _dev_vec(b, self.n)
+        if _dev_vec(x, self.n) != nrhs:
+            raise ValueError("b and x differ in nrhs")
+        iters = np.zeros(nrhs, dtype=np.int32)
+        relres = np.zeros(nrhs, dtype=np.float64)
+        st = self._lib.spand_solve(self._h, nrhs, _ptr(b), _ptr(x), float(rtol), int(maxit), _ptr(iters), _ptr(relres))
+        if check and st != 0:
+            self._check(st)
+        return iters, relres, st
+
+    def apply(self, r, z):
+        nrhs = _dev_vec(r, self.n)
+        self._check(self._lib.spand_apply(self._h, nrhs, _ptr(r), _ptr(z)))
+
+    def stats(self):
+        s = Stats()
+        self._check(self._lib.spand_get_stats(self._h, C.byref(s)))
+        return s.as_dict()
+
+    def ordering(self):
+        S = np.zeros(self.n, np.int64)
+        L = np.zeros(self.n, np.int64)
+        R = np.zeros(self.n, np.int64)
+        self._check(self._lib.spand_get_ordering(self._h, _ptr(S), _ptr(L), _ptr(R)))
+        return S, L, R
+
+    def step_counts(self, step):
+        c = np.zeros(6, np.int64)
+        self._check(self._lib.spand_step_counts(self._h, int(step), _ptr(c)))
+        return dict(nc=int(c[0]), ne=int(c[1]), nb=int(c[2]), na=int(c[3]), level=int(c[4]), nenb=int(c[5]))
+
+    def step_structure(self, step):
+        c = self.step_counts(step)
+        keys = np.zeros((c["nc"], 3), np.int64)
+        parent = np.zeros(c["nc"], np.int32)
+        colour = np.zeros(c["nc"], np.int32)
+        before = np.zeros((c["nb"], 2), np.int32)
+        after = np.zeros((c["na"], 2), np.int32)
+        self._check(self._lib.spand_step_structure(self._h, int(step), _ptr(keys), _ptr(parent), _ptr(colour),
+                                                   _ptr(before), _ptr(after)))
+        return dict(keys=keys, parent=parent, colour=colour, before=before, after=after, **c)
+
+    def step_ranks(self, step):
+        c = self.step_counts(step)
+        sizes = np.zeros(c["nc"], np.int32)
+        ranks = np.zeros(c["nc"], np.int32)
+        self._check(self._lib.spand_step_ranks(self._h, int(step), _ptr(sizes), _ptr(ranks)))
+        return sizes, ranks

@@ -1,0 +1,95 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol, and
+its host-only analysis (Algorithm 2 + symbolic factorization) equals the oracle's
+bit for bit.  No compute call touches a GPU here."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import gridgen
+from oracle import spand_oracle as O
+from paper_1901_02971_amd import spand as S
+
+DECLARED = ["spand_analyze", "spand_factor", "spand_solve", "spand_apply", "spand_set_stream", "spand_get_stats",
+            "spand_get_ordering", "spand_step_counts", "spand_step_structure", "spand_step_ranks",
+            "spand_error_string", "spand_destroy"]
+
+
+def test_header_declares_expected_symbols():
+    assert S.exported_symbols() == sorted(DECLARED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(S.library_path())
+    for name in S.exported_symbols():
+        assert hasattr(lib, name), name
+
+
+CASES = [((7, 7), 3), ((6, 4), 2), ((16, 16), 5), ((64, 64), 6), ((9, 7, 6), 4), ((8, 8, 8), 5),
+         ((24, 31, 40), 7), ((32, 32, 32), 9), ((5, 5, 5), 1), ((3, 2), 4)]
+
+
+@pytest.mark.parametrize("shape,levels", CASES)
+def test_analyze_bit_exact_vs_oracle(shape, levels):
+    p = gridgen.laplacian(shape)
+    lib = S.Solver.from_problem(p, levels)
+    an = O.Analysis(p.n, p.rowptr, p.colind, p.coords, levels)
+    Sg, Lg, Rg = lib.ordering()
+    assert np.array_equal(Sg, an.S) and np.array_equal(Lg, an.L) and np.array_equal(Rg, an.R)
+    for t, st in enumerate(an.steps, start=1):
+        g = lib.step_structure(t)
+        assert np.array_equal(g["keys"], st.keys)
+        assert g["ne"] == st.n_elim and g["level"] == st.level
+        assert np.array_equal(g["parent"], st.parent)
+        if st.sparsify:
+            assert np.array_equal(g["colour"], st.colour)
+        assert np.array_equal(g["before"], np.array(st.blocks, dtype=np.int32).reshape(-1, 2))
+        assert np.array_equal(g["after"], np.array(st.after, dtype=np.int32).reshape(-1, 2))
+
+
+def test_analyze_bit_exact_variable_coefficient_config3_shape():
+    """The 64^3 variable-coefficient workload at its real size and depth (10 levels)."""
+    p = gridgen.variable_coefficient((64, 64, 64), np.random.default_rng(3), -3, 3)
+    lib = S.Solver.from_problem(p, 10)
+    an = O.Analysis(p.n, p.rowptr, p.colind, p.coords, 10)
+    Sg, Lg, Rg = lib.ordering()
+    assert np.array_equal(Sg, an.S) and np.array_equal(Lg, an.L) and np.array_equal(Rg, an.R)
+    for t, st in enumerate(an.steps, start=1):
+        g = lib.step_structure(t)
+        assert np.array_equal(g["keys"], st.keys) and np.array_equal(g["parent"], st.parent)
+        assert np.array_equal(g["after"], np.array(st.after, dtype=np.int32).reshape(-1, 2))
+
+
+def _expect(status_name, fn):
+    with pytest.raises(S.SpandError) as e:
+        fn()
+    assert e.value.name == status_name
+
+
+def test_analyze_rejects_bad_input():
+    p = gridgen.laplacian((5, 5))
+    _expect("SPAND_E_INVALID", lambda: S.Solver(p.n, p.rowptr, p.colind, p.coords, 0))
+    bad = p.colind.copy()
+    bad[1] = bad[0]    # not strictly increasing
+    _expect("SPAND_E_INVALID", lambda: S.Solver(p.n, p.rowptr, bad, p.coords, 2))
+    # non-symmetric pattern: drop the (0, 1) entry but keep (1, 0)
+    rp = p.rowptr.copy()
+    keep = np.ones(len(p.colind), bool)
+    keep[1] = False
+    rp[1:] -= 1
+    _expect("SPAND_E_INVALID", lambda: S.Solver(p.n, rp, p.colind[keep], p.coords, 2))
+    c = p.coords.copy()
+    c[3, 0] = np.nan
+    _expect("SPAND_E_INVALID", lambda: S.Solver(p.n, p.rowptr, p.colind, c, 2))
+    _expect("SPAND_E_INVALID", lambda: S.Solver(p.n, p.rowptr, p.colind, np.zeros((p.n, 4)), 2))
+
+
+def test_solve_before_factor_is_state_error():
+    """No GPU work happens: the state check precedes every device call."""
+    p = gridgen.laplacian((5, 5))
+    lib = S.Solver.from_problem(p, 2)
+    lib_c = S.load_library()
+    it = np.zeros(1, np.int32)
+    rr = np.zeros(1)
+    st = lib_c.spand_solve(lib._h, 1, 8, 16, 1e-12, 10, it.ctypes.data, rr.ctypes.data)
+    assert S.STATUS[st] == "SPAND_E_STATE"
