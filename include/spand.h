@@ -66,6 +66,12 @@ typedef struct {
   int32_t fail_cluster;  /* ... cluster id within that step */
   int32_t fail_phase;    /* ... 0 = elimination, 1 = scaling */
   int32_t reserved;
+  /* Per-step profile of the last factor (the paper's time/memory per level,
+   * Sec. 4.4): device seconds (HIP events) of each phase of step t (t = 1..32):
+   * [t-1][0] assembly/merge, [1] elimination, [2] scaling, [3] sparsification;
+   * and the cumulative stored factor entries after step t. */
+  double step_phase_seconds[32][4];
+  int64_t step_m_F[32];
 } spand_stats;
 
 /* Ordering, clustering and symbolic factorization (Algorithm 2 with a geometric

@@ -153,13 +153,20 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
   int32_t* d_fail_scale = dflag.as<int32_t>() + 1;
   int32_t* d_nonfinite = dflag.as<int32_t>() + 2;
 
-  hipEvent_t ev0, ev1;
-  HIPCHK(hipEventCreate(&ev0));
-  HIPCHK(hipEventCreate(&ev1));
+  // ev[0..1]: Schur GEMMs; ph[0..4]: phase boundaries of a step
+  hipEvent_t ev[2], ph[5];
   struct EvGuard {
-    hipEvent_t a, b;
-    ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
-  } evg{ev0, ev1};
+    hipEvent_t* e;
+    int n = 0;
+    ~EvGuard() {
+      for (int q = 0; q < n; ++q) (void)hipEventDestroy(e[q]);
+    }
+  } g1{ev}, g2{ph};
+  for (int q = 0; q < 2; ++q, ++g1.n) HIPCHK(hipEventCreate(&ev[q]));
+  for (int q = 0; q < 5; ++q, ++g2.n) HIPCHK(hipEventCreate(&ph[q]));
+  hipEvent_t ev0 = ev[0], ev1 = ev[1];
+  std::memset(h->stats.step_phase_seconds, 0, sizeof(h->stats.step_phase_seconds));
+  std::memset(h->stats.step_m_F, 0, sizeof(h->stats.step_m_F));
 
   int64_t m_F = 0;
   double schur_flops = 0.0, schur_ms = 0.0;
@@ -205,6 +212,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       for (int32_t s = 0; s < ne; ++s) s_top += sn.size[s];
 
     // ---- arena layout and assembly
+    HIPCHK(hipEventRecord(ph[0], h->stream));
     Layout lay;
     build_layout(sy, sn.size, lay);
     DevBuf arena;
@@ -276,6 +284,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
     }
 
     // ---- elimination (Sec. 2.4)
+    HIPCHK(hipEventRecord(ph[1], h->stream));
     std::vector<int64_t> linv_off(ne), g_off(ne), c_off(ne);
     std::vector<int32_t> nN(ne);
     int64_t elim_total = 0, cbuf_total = 0;
@@ -376,6 +385,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       if ((st = upload(h, dcd, cds2)) != SPAND_OK) return st;
       launch_reduce(drd.as<ReduceDesc>(), int32_t(rds.size()), dcd.as<ContribDesc>(), h->stream);
       HIPCHK(hipGetLastError());
+      HIPCHK(hipEventRecord(ph[2], h->stream));
       HIPCHK(hipStreamSynchronize(h->stream));
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
@@ -398,6 +408,8 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
     for (int32_t c = ne; c < nc; ++c) sn.rank[c] = sn.size[c];
     std::vector<int64_t> sc_off(nc, -1), v_off(nc, -1), tau_off(nc, -1);
     std::vector<int32_t> nref(nc, 0);
+    HIPCHK(hipEventRecord(ph[3], h->stream));
+    HIPCHK(hipEventRecord(ph[4], h->stream));
     if (sparsify && nc > ne) {
       int64_t sc_total = 0;
       for (int32_t p = ne; p < nc; ++p) {
@@ -465,6 +477,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       if ((st = upload(h, d3, dld)) != SPAND_OK) return st;
       launch_set_identity(d1.as<double*>(), d2.as<int32_t>(), d3.as<int32_t>(), int32_t(dptr.size()), h->stream);
       HIPCHK(hipGetLastError());
+      HIPCHK(hipEventRecord(ph[3], h->stream));
       HIPCHK(hipStreamSynchronize(h->stream));
       HIPCHK(hipMemcpy(flags, dflag.p, sizeof(flags), hipMemcpyDeviceToHost));
       if (flags[1] != 0x7fffffff) {
@@ -552,6 +565,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
         keep.push_back(std::move(b));
       }
       std::vector<int32_t> rk(nc, -1);
+      HIPCHK(hipEventRecord(ph[4], h->stream));
       HIPCHK(hipStreamSynchronize(h->stream));
       HIPCHK(hipMemcpy(rk.data(), curb.p, size_t(nc) * sizeof(int32_t), hipMemcpyDeviceToHost));
       HIPCHK(hipMemcpy(nref.data(), nrefb.p, size_t(nc) * sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -563,6 +577,15 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
         }
     }
     HIPCHK(hipStreamSynchronize(h->stream));
+    if (t <= 32) {
+      float ms[4] = {0.f, 0.f, 0.f, 0.f};
+      HIPCHK(hipEventElapsedTime(&ms[0], ph[0], ph[1]));
+      HIPCHK(hipEventElapsedTime(&ms[1], ph[1], ph[2]));
+      HIPCHK(hipEventElapsedTime(&ms[2], ph[2], ph[3]));
+      HIPCHK(hipEventElapsedTime(&ms[3], ph[3], ph[4]));
+      for (int q = 0; q < 4; ++q) h->stats.step_phase_seconds[t - 1][q] = 1e-3 * ms[q];
+      h->stats.step_m_F[t - 1] = m_F;
+    }
 
     // ---- apply descriptors of this step
     {

@@ -33,10 +33,16 @@ class Stats(C.Structure):
                 ("n", C.c_int64), ("levels", C.c_int32), ("n_steps", C.c_int32), ("last_iters", C.c_int32),
                 ("s_top", C.c_int32), ("m_F", C.c_int64), ("schur_flops", C.c_double),
                 ("schur_seconds", C.c_double), ("fail_step", C.c_int32), ("fail_cluster", C.c_int32),
-                ("fail_phase", C.c_int32), ("reserved", C.c_int32)]
+                ("fail_phase", C.c_int32), ("reserved", C.c_int32),
+                ("step_phase_seconds", (C.c_double * 4) * 32), ("step_m_F", C.c_int64 * 32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        d = {k: getattr(self, k) for k, _ in self._fields_
+             if k not in ("reserved", "step_phase_seconds", "step_m_F")}
+        L = max(0, min(32, int(self.n_steps)))
+        d["step_phase_seconds"] = [[self.step_phase_seconds[t][q] for q in range(4)] for t in range(L)]
+        d["step_m_F"] = [int(self.step_m_F[t]) for t in range(L)]
+        return d
 
 
 def library_path() -> str:
