@@ -32,8 +32,8 @@ from dataclasses import dataclass, field
 import numpy as np
 from scipy.linalg import solve_triangular
 
-# Relative window inside which CPQR column norms count as tied; the first such
-# column (smallest current position) is the pivot.
+# Relative window inside which CPQR column norms count as tied; among tied
+# columns the one with the smallest original index is the pivot.
 TIE_RTOL = 1e-10
 
 
@@ -297,7 +297,9 @@ def cpqr(A, eps):
     """Truncated column-pivoted Householder QR of A (m x n) (Sec. 2.6.1, Sec. 4 intro).
 
     At step j the norms of the trailing columns A[j:, j:] are recomputed; the pivot
-    is the first column whose norm is within TIE_RTOL of the largest.  The rank r
+    is, among the columns whose norm is within TIE_RTOL of the largest, the one
+    with the smallest original column index (ties are a reading: the paper's
+    routine, geqp3, does not define them as part of the method).  The rank r
     is the number of leading steps with |R_jj| >= eps |R_00| (r = 0 when R_00 = 0,
     r = min(m, n) when no step fails).  Returns (r, V, tau, W, perm) where V (m x r)
     holds the reflectors (unit first entry, zero above), and W = (Q^T A)[:r, :],
@@ -314,7 +316,8 @@ def cpqr(A, eps):
     for j in range(k):
         norms = np.sqrt(np.sum(A[j:, j:] ** 2, axis=0))
         cmax = norms.max()
-        piv = j + int(np.argmax(norms >= cmax * (1.0 - TIE_RTOL)))
+        cand = np.nonzero(norms >= cmax * (1.0 - TIE_RTOL))[0]
+        piv = j + int(cand[np.argmin(perm[j + cand])])
         if j == 0:
             r00 = norms[piv - j]
             if r00 == 0.0:

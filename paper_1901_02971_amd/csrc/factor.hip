@@ -489,19 +489,39 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       }
       tbuf.release();
 
-      // sparsification, colour by colour
+      // sparsification, colour by colour; A_pn of each interface is cut into
+      // LDS-resident column slabs (one workgroup each)
       std::vector<int64_t> ncols(nc, 0);
       int32_t ncolour = 0;
-      int64_t ws_total = 0, sc2_total = 0, house_total = 0;
-      std::vector<int64_t> ws_off(nc, -1), nrm_off(nc, -1);
+      int64_t house_total = 0, gn_total = 0, pc_total = 0;
+      std::vector<int64_t> gn_off(nc, -1), pc_off(nc, -1);
+      std::vector<int32_t> slabS(nc, 0), slabC(nc, 0), nseg(nc, 0);
+      int32_t nmulti = 0;
       for (int32_t p = ne; p < nc; ++p) {
-        for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e) ncols[p] += sn.size[sy.nb[e]];
+        for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e)
+          if (sn.size[sy.nb[e]] > 0) {
+            ncols[p] += sn.size[sy.nb[e]];
+            nseg[p]++;
+          }
         if (sn.size[p] == 0 || ncols[p] == 0) continue;
         ncolour = std::max(ncolour, sy.colour[p] + 1);
-        ws_off[p] = ws_total;
-        ws_total += int64_t(sn.size[p]) * ncols[p];
-        nrm_off[p] = sc2_total;
-        sc2_total += ncols[p];
+        const int64_t m = sn.size[p];
+        const int64_t budget = int64_t(sparsify_lds_limit()) - 64 - 4 * (nseg[p] + 1) - 8 * m;
+        const int64_t cfit = budget / (8 * (m + 1) + 4);
+        if (cfit < 1)
+          return set_err(h, SPAND_E_INVALID, "interface of " + std::to_string(m) + " dofs exceeds the LDS of one CU");
+        if (ncols[p] <= std::min<int64_t>(cfit, 1024)) {
+          slabS[p] = 1;
+          slabC[p] = int32_t(ncols[p]);
+        } else {
+          slabC[p] = int32_t(std::min<int64_t>(cfit, 256));
+          slabS[p] = int32_t((ncols[p] + slabC[p] - 1) / slabC[p]);
+          gn_off[p] = gn_total;
+          gn_total += ncols[p];
+          pc_off[p] = pc_total;
+          pc_total += m;
+          ++nmulti;
+        }
         const int64_t kmax = std::min<int64_t>(sn.size[p], ncols[p]);
         v_off[p] = house_total;
         house_total += int64_t(sn.size[p]) * kmax;
@@ -509,68 +529,108 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
         house_total += kmax;
       }
       if ((st = dalloc(h, sn.house, size_t(house_total) * sizeof(double))) != SPAND_OK) return st;
-      DevBuf wsb, nrmb, permb, curb, nrefb;
-      if ((st = dalloc(h, wsb, size_t(ws_total) * sizeof(double))) != SPAND_OK) return st;
-      if ((st = dalloc(h, nrmb, size_t(sc2_total) * sizeof(double))) != SPAND_OK) return st;
-      if ((st = dalloc(h, permb, size_t(sc2_total) * sizeof(int32_t))) != SPAND_OK) return st;
+      DevBuf gnb, pcb, cntb, curb, nrefb, errb;
+      if ((st = dalloc(h, gnb, size_t(gn_total) * sizeof(double))) != SPAND_OK) return st;
+      if ((st = dalloc(h, pcb, size_t(pc_total) * sizeof(double))) != SPAND_OK) return st;
+      if ((st = dalloc(h, cntb, size_t(std::max(nmulti, 1)) * sizeof(int32_t))) != SPAND_OK) return st;
+      HIPCHK(hipMemsetAsync(cntb.p, 0, size_t(std::max(nmulti, 1)) * sizeof(int32_t), h->stream));
+      if ((st = dalloc(h, errb, sizeof(int32_t))) != SPAND_OK) return st;
+      HIPCHK(hipMemsetAsync(errb.p, 0, sizeof(int32_t), h->stream));
       // current sizes: interfaces shrink to their rank as their colour class finishes
       if ((st = upload(h, curb, sn.size)) != SPAND_OK) return st;
       if ((st = upload(h, nrefb, std::vector<int32_t>(nc, 0))) != SPAND_OK) return st;
       std::vector<std::vector<int32_t>> by_colour(ncolour);
       for (int32_t p = ne; p < nc; ++p)
-        if (ws_off[p] >= 0) by_colour[sy.colour[p]].push_back(p);
+        if (v_off[p] >= 0) by_colour[sy.colour[p]].push_back(p);
       std::vector<DevBuf> keep;
+      int32_t multi_idx = 0;
       for (int32_t c = 0; c < ncolour; ++c) {
         if (by_colour[c].empty()) continue;
-        std::vector<SparsDesc> sds;
-        std::vector<SegDesc> segs;
-        for (int32_t p : by_colour[c]) {
-          SparsDesc d{};
-          d.ws = wsb.as<double>() + ws_off[p];
-          d.nrm = nrmb.as<double>() + nrm_off[p];
-          d.perm = permb.as<int32_t>() + nrm_off[p];
-          d.V = sn.house.as<double>() + v_off[p];
-          d.tau = sn.house.as<double>() + tau_off[p];
-          d.diag = A + lay.base[p];
-          d.ldd = int32_t(lay.H[p]);
-          d.m = sn.size[p];
-          d.id = p;
-          d.seg_begin = int32_t(segs.size());
-          for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e) {
-            const int32_t q = sy.nb[e];
-            if (sn.size[q] == 0) continue;
-            SegDesc g{};
-            if (q < p) {  // block (p, q) in panel q
-              g.blk = A + lay.base[q] + lay.find(p, q);
-              g.ld = int32_t(lay.H[q]);
-              g.trans = 0;
-            } else {      // block (q, p) in panel p holds A_pq^T
-              g.blk = A + lay.base[p] + lay.find(q, p);
-              g.ld = int32_t(lay.H[p]);
-              g.trans = 1;
+        for (int pass = 0; pass < 2; ++pass) {  // pass 0: single-slab interfaces; pass 1: multi-slab
+          std::vector<int32_t> plist;
+          for (int32_t p : by_colour[c])
+            if ((slabS[p] > 1) == (pass == 1)) plist.push_back(p);
+          size_t pos = 0;
+          while (pos < plist.size()) {
+            std::vector<SparsDesc> sds;
+            std::vector<SegDesc> segs;
+            std::vector<SlabRef> slabs;
+            size_t lds = 0;
+            int cap = 0;
+            if (pass == 1) {
+              size_t lmax = 0;
+              for (int32_t p : plist) lmax = std::max(lmax, sparsify_lds_bytes(sn.size[p], slabC[p], nseg[p]));
+              cap = sparsify_max_coresident(lmax);
+              lds = lmax;
+              if (cap <= 0) return set_err(h, SPAND_E_HIP, "occupancy query for the sparsification kernel failed");
             }
-            g.q = q;
-            segs.push_back(g);
+            while (pos < plist.size()) {
+              const int32_t p = plist[pos];
+              if (pass == 1 && !slabs.empty() && int(slabs.size()) + slabS[p] > cap) break;
+              if (pass == 1 && slabS[p] > cap)
+                return set_err(h, SPAND_E_INVALID, "interface needs more co-resident workgroups than the GPU holds");
+              SparsDesc d{};
+              d.V = sn.house.as<double>() + v_off[p];
+              d.tau = sn.house.as<double>() + tau_off[p];
+              d.diag = A + lay.base[p];
+              d.ldd = int32_t(lay.H[p]);
+              d.m = sn.size[p];
+              d.id = p;
+              d.S = slabS[p];
+              d.C = slabC[p];
+              if (slabS[p] > 1) {
+                d.gnrm = gnb.as<double>() + gn_off[p];
+                d.pivcol = pcb.as<double>() + pc_off[p];
+                d.cnt = cntb.as<int32_t>() + multi_idx++;
+              }
+              d.seg_begin = int32_t(segs.size());
+              for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e) {
+                const int32_t q = sy.nb[e];
+                if (sn.size[q] == 0) continue;
+                SegDesc g{};
+                if (q < p) {  // block (p, q) in panel q
+                  g.blk = A + lay.base[q] + lay.find(p, q);
+                  g.ld = int32_t(lay.H[q]);
+                  g.trans = 0;
+                } else {      // block (q, p) in panel p holds A_pq^T
+                  g.blk = A + lay.base[p] + lay.find(q, p);
+                  g.ld = int32_t(lay.H[p]);
+                  g.trans = 1;
+                }
+                g.q = q;
+                segs.push_back(g);
+              }
+              d.seg_end = int32_t(segs.size());
+              for (int32_t w = 0; w < slabS[p]; ++w) slabs.push_back(SlabRef{int32_t(sds.size()), w});
+              lds = std::max(lds, sparsify_lds_bytes(d.m, d.C, d.seg_end - d.seg_begin));
+              sds.push_back(d);
+              ++pos;
+            }
+            DevBuf a, b, sl;
+            if ((st = upload(h, a, sds)) != SPAND_OK) return st;
+            if ((st = upload(h, b, segs)) != SPAND_OK) return st;
+            if ((st = upload(h, sl, slabs)) != SPAND_OK) return st;
+            hipError_t le = launch_sparsify(a.as<SparsDesc>(), sl.as<SlabRef>(), int32_t(slabs.size()),
+                                            b.as<SegDesc>(), tol, curb.as<int32_t>(), nrefb.as<int32_t>(),
+                                            errb.as<int32_t>(), lds, pass == 1, h->stream);
+            if (le != hipSuccess)
+              return set_err(h, SPAND_E_HIP, std::string("sparsification launch: ") + hipGetErrorString(le));
+            keep.push_back(std::move(a));
+            keep.push_back(std::move(b));
+            keep.push_back(std::move(sl));
           }
-          d.seg_end = int32_t(segs.size());
-          sds.push_back(d);
         }
-        DevBuf a, b;
-        if ((st = upload(h, a, sds)) != SPAND_OK) return st;
-        if ((st = upload(h, b, segs)) != SPAND_OK) return st;
-        launch_sparsify(a.as<SparsDesc>(), int32_t(sds.size()), b.as<SegDesc>(), tol, curb.as<int32_t>(),
-                        nrefb.as<int32_t>(), h->stream);
-        HIPCHK(hipGetLastError());
-        keep.push_back(std::move(a));
-        keep.push_back(std::move(b));
       }
       std::vector<int32_t> rk(nc, -1);
       HIPCHK(hipEventRecord(ph[4], h->stream));
       HIPCHK(hipStreamSynchronize(h->stream));
       HIPCHK(hipMemcpy(rk.data(), curb.p, size_t(nc) * sizeof(int32_t), hipMemcpyDeviceToHost));
       HIPCHK(hipMemcpy(nref.data(), nrefb.p, size_t(nc) * sizeof(int32_t), hipMemcpyDeviceToHost));
+      int32_t serr = 0;
+      HIPCHK(hipMemcpy(&serr, errb.p, sizeof(int32_t), hipMemcpyDeviceToHost));
+      if (serr) return set_err(h, SPAND_E_HIP, "sparsification slab barrier timed out");
       for (int32_t p = ne; p < nc; ++p)
-        if (ws_off[p] >= 0) {
+        if (v_off[p] >= 0) {
           sn.rank[p] = rk[p];
           const int64_t r = nref[p];
           m_F += (2 * int64_t(sn.size[p]) - r + 1) * r / 2 + r;

@@ -56,24 +56,25 @@ struct CopyDesc {
   int32_t lds, ldd, rows, cols, trans, pad;
 };
 
-// Sparsification of one interface p (Sec. 2.6.1).
-// The width of A_pn is known only on the device: a neighbour q sparsified in an
-// earlier colour class has shrunk to its rank, read from cursize[q].
+// Sparsification of one interface p (Sec. 2.6.1).  A_pn is split into S column
+// slabs of width C, each held in the LDS of one workgroup.  The width of A_pn is
+// known only on the device: a neighbour q sparsified in an earlier colour class
+// has shrunk to its rank, read from cursize[q].
 struct SparsDesc {
-  double* ws;      // m x ncols workspace, row-major (row i = dofs of p); sized for the
-                   // pre-sparsification width
-  double* nrm;     // ncols scratch
-  int32_t* perm;   // ncols scratch
   double* V;       // m x min(m, ncols_max) reflectors, column-major, ld m
   double* tau;     // min(m, ncols_max)
   double* diag;    // diagonal block of p (ld ldd), set to I_r on exit
-  int32_t m, ldd, seg_begin, seg_end, id, pad;
+  double* gnrm;    // ncols_max trailing column norms shared by the slabs (S > 1)
+  double* pivcol;  // m entries: the pivot column shared by the slabs (S > 1)
+  int32_t* cnt;    // barrier counter of the slabs (zeroed before the launch)
+  int32_t m, ldd, seg_begin, seg_end, id, S, C, pad;
 };
 struct SegDesc {
   double* blk;  // block holding A_pq: trans=0 -> A_pq[r][c] = blk[r + c*ld]; trans=1 -> blk[c + r*ld]
-  int32_t ld, trans, q;
-  int32_t ncol, col_off;  // filled in by the kernel from cursize[q]
-  int32_t pad;
+  int32_t ld, trans, q, pad;
+};
+struct SlabRef {
+  int32_t desc, w;
 };
 
 void launch_scatter_values(const double* vals, const int64_t* dst, int64_t nnz, double* arena, int32_t* flag,
@@ -85,9 +86,15 @@ void launch_copy(const CopyDesc* d, int64_t count, hipStream_t s);
 void launch_set_identity(double* const* diag, const int32_t* n, const int32_t* ld, int32_t count, hipStream_t s);
 // cursize: current size of every cluster of the step; the kernel sets
 // cursize[p] = kept rank when it finishes p and nref[p] = number of reflectors
-// stored (0 when no coupled dofs were left and p was not sparsified).
-void launch_sparsify(const SparsDesc* d, int32_t count, SegDesc* seg, double eps, int32_t* cursize, int32_t* nref,
-                     hipStream_t s);
+// stored (0 when no coupled dofs were left and p was not sparsified).  err
+// receives bit 2 if a slab barrier timed out.  Launches with more than one slab
+// per interface are cooperative (all workgroups resident).
+size_t sparsify_lds_bytes(int32_t m, int32_t C, int32_t nseg);
+size_t sparsify_lds_limit();
+int sparsify_max_coresident(size_t lds_bytes);
+hipError_t launch_sparsify(const SparsDesc* d, const SlabRef* slabs, int32_t nslab, const SegDesc* seg, double eps,
+                           int32_t* cursize, int32_t* nref, int32_t* err, size_t lds_bytes, bool cooperative,
+                           hipStream_t s);
 
 constexpr int GEMM_TILE = 64;
 

@@ -8,8 +8,6 @@
 //  * k_reduce     deterministic Schur-complement accumulation: every target block
 //                 subtracts its contributions in ascending eliminated-cluster order.
 //  * k_copy       strided (optionally transposed) block copies for the merge (Sec. 2.7).
-//  * k_sparsify   truncated column-pivoted QR of A_pn with write-back of W_cn
-//                 (Sec. 2.6.1), one workgroup per interface.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -279,174 +277,6 @@ __global__ void k_set_identity(double* const* diag, const int32_t* n, const int3
 void launch_set_identity(double* const* diag, const int32_t* n, const int32_t* ld, int32_t count, hipStream_t s) {
   if (count == 0) return;
   hipLaunchKernelGGL(k_set_identity, dim3(count), dim3(WG), 0, s, diag, n, ld);
-}
-
-// ---------------------------------------------------------------- sparsification
-// One workgroup per interface p.  Gathers A_pn (m x ncols, row-major in ws), runs
-// Householder QR with column pivoting (norms of the trailing columns recomputed
-// from the updated entries after every step; pivot = first column within a
-// relative 1e-10 of the largest norm; stop at the first step with
-// |R_jj| < eps |R_00|), stores the reflectors, writes W_cn = R[:r,:] P^T back into
-// the blocks of p and sets the diagonal block of p to I_r.
-#define TIE_RTOL 1e-10
-
-__global__ void __launch_bounds__(WG) k_sparsify(const SparsDesc* __restrict__ descs, SegDesc* __restrict__ segs,
-                                                 double eps, int32_t* cursize, int32_t* nref) {
-  const SparsDesc d = descs[blockIdx.x];
-  const int m = d.m;
-  double* ws = d.ws;
-  __shared__ double red[WG / 64];
-  __shared__ int redi[WG / 64];
-  __shared__ double sh_beta, sh_tau, sh_scale;
-  __shared__ int sh_nc;
-  // column layout of A_pn from the neighbours' current sizes
-  if (threadIdx.x == 0) {
-    int off = 0;
-    for (int s = d.seg_begin; s < d.seg_end; ++s) {
-      const int w = cursize[segs[s].q];
-      segs[s].ncol = w;
-      segs[s].col_off = off;
-      off += w;
-    }
-    sh_nc = off;
-  }
-  __syncthreads();
-  const int nc = sh_nc;
-  if (nc == 0) {  // no coupled dofs left: p keeps its size, no reflectors
-    if (threadIdx.x == 0) nref[d.id] = 0;
-    return;
-  }
-  // gather A_pn
-  for (int s = d.seg_begin; s < d.seg_end; ++s) {
-    const SegDesc g = segs[s];
-    const int64_t cnt = (int64_t)m * g.ncol;
-    for (int64_t e = threadIdx.x; e < cnt; e += WG) {
-      int r, c;
-      if (g.trans) { c = (int)(e % g.ncol); r = (int)(e / g.ncol); } else { r = (int)(e % m); c = (int)(e / m); }
-      const double v = g.trans ? g.blk[c + (int64_t)r * g.ld] : g.blk[r + (int64_t)c * g.ld];
-      ws[(int64_t)r * nc + g.col_off + c] = v;
-    }
-  }
-  __syncthreads();
-  for (int c = threadIdx.x; c < nc; c += WG) {
-    double s = 0.0;
-    for (int i = 0; i < m; ++i) {
-      const double v = ws[(int64_t)i * nc + c];
-      s += v * v;
-    }
-    d.nrm[c] = s;
-    d.perm[c] = c;
-  }
-  __syncthreads();
-  const int kmax = min(m, nc);
-  int r = kmax;
-  double r00 = 0.0;
-  for (int j = 0; j < kmax; ++j) {
-    // pivot: first column whose norm is within TIE_RTOL of the largest
-    double lmax = 0.0;
-    for (int c = j + threadIdx.x; c < nc; c += WG) lmax = fmax(lmax, sqrt(d.nrm[c]));
-    const double cmax = block_max(lmax, red);
-    int lidx = 0x7fffffff;
-    for (int c = j + threadIdx.x; c < nc; c += WG)
-      if (sqrt(d.nrm[c]) >= cmax * (1.0 - TIE_RTOL)) { lidx = c; break; }
-    const int piv = block_min_i(lidx, redi);
-    if (piv >= nc) { r = j; break; }  // only non-finite norms left
-    const double pnorm = sqrt(d.nrm[piv]);
-    if (j == 0) {
-      r00 = pnorm;
-      if (r00 == 0.0) { r = 0; break; }
-    }
-    if (pnorm < eps * r00) { r = j; break; }
-    __syncthreads();
-    if (piv != j) {
-      for (int i = threadIdx.x; i < m; i += WG) {
-        const double t = ws[(int64_t)i * nc + j];
-        ws[(int64_t)i * nc + j] = ws[(int64_t)i * nc + piv];
-        ws[(int64_t)i * nc + piv] = t;
-      }
-      if (threadIdx.x == 0) {
-        const double t = d.nrm[j]; d.nrm[j] = d.nrm[piv]; d.nrm[piv] = t;
-        const int pi = d.perm[j]; d.perm[j] = d.perm[piv]; d.perm[piv] = pi;
-      }
-    }
-    __syncthreads();
-    // Householder reflector of column j, rows j..m-1 (dlarfg convention)
-    double part = 0.0;
-    for (int i = j + 1 + threadIdx.x; i < m; i += WG) {
-      const double v = ws[(int64_t)i * nc + j];
-      part += v * v;
-    }
-    const double xn2 = block_sum(part, red);
-    if (threadIdx.x == 0) {
-      const double alpha = ws[(int64_t)j * nc + j];
-      if (xn2 == 0.0) {
-        sh_tau = 0.0; sh_beta = alpha; sh_scale = 0.0;
-      } else {
-        const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-        sh_tau = (beta - alpha) / beta;
-        sh_beta = beta;
-        sh_scale = 1.0 / (alpha - beta);
-      }
-    }
-    __syncthreads();
-    const double tau = sh_tau, scale = sh_scale;
-    double* V = d.V + (int64_t)j * m;
-    for (int i = threadIdx.x; i < m; i += WG) {
-      double v;
-      if (i < j) v = 0.0;
-      else if (i == j) v = 1.0;
-      else v = ws[(int64_t)i * nc + j] * scale;
-      V[i] = v;
-    }
-    if (threadIdx.x == 0) d.tau[j] = tau;
-    __syncthreads();
-    if (threadIdx.x == 0) ws[(int64_t)j * nc + j] = sh_beta;
-    for (int i = j + 1 + threadIdx.x; i < m; i += WG) ws[(int64_t)i * nc + j] = 0.0;
-    // apply H = I - tau v v^T to columns j+1.., recomputing trailing norms (rows j+1..)
-    for (int c = j + 1 + threadIdx.x; c < nc; c += WG) {
-      double w = ws[(int64_t)j * nc + c];
-      for (int i = j + 1; i < m; ++i) w += V[i] * ws[(int64_t)i * nc + c];
-      w *= tau;
-      ws[(int64_t)j * nc + c] -= w;
-      double s = 0.0;
-      for (int i = j + 1; i < m; ++i) {
-        const double v = ws[(int64_t)i * nc + c] - w * V[i];
-        ws[(int64_t)i * nc + c] = v;
-        s += v * v;
-      }
-      d.nrm[c] = s;
-    }
-    __syncthreads();
-  }
-  __syncthreads();
-  // W[i][perm[jp]] = R[i][jp] for i <= jp, i < r; scatter into the blocks of p
-  for (int jp = threadIdx.x; jp < nc; jp += WG) {
-    const int col = d.perm[jp];
-    int sidx = d.seg_begin;
-    while (sidx + 1 < d.seg_end && segs[sidx + 1].col_off <= col) ++sidx;
-    const SegDesc g = segs[sidx];
-    const int cc = col - g.col_off;
-    for (int i = 0; i < r; ++i) {
-      const double v = (i <= jp) ? ws[(int64_t)i * nc + jp] : 0.0;
-      if (g.trans) g.blk[cc + (int64_t)i * g.ld] = v;
-      else g.blk[i + (int64_t)cc * g.ld] = v;
-    }
-  }
-  // diagonal block of p -> I_r
-  for (int64_t e = threadIdx.x; e < (int64_t)r * r; e += WG) {
-    const int a = (int)(e % r), b = (int)(e / r);
-    d.diag[a + (int64_t)b * d.ldd] = (a == b) ? 1.0 : 0.0;
-  }
-  if (threadIdx.x == 0) {
-    cursize[d.id] = r;
-    nref[d.id] = r;
-  }
-}
-
-void launch_sparsify(const SparsDesc* d, int32_t count, SegDesc* seg, double eps, int32_t* cursize, int32_t* nref,
-                     hipStream_t s) {
-  if (count == 0) return;
-  hipLaunchKernelGGL(k_sparsify, dim3(count), dim3(WG), 0, s, d, seg, eps, cursize, nref);
 }
 
 }  // namespace spand

@@ -249,10 +249,15 @@ def test_cpqr_special_cases():
     assert O.cpqr(A, 1.0)[0] >= 1                           # |R_00| >= 1 * |R_00|
 
 
-def test_cpqr_tie_goes_to_first_column():
-    A = np.eye(4)[:, [0, 1, 2, 3]] * 2.0
+def test_cpqr_tie_goes_to_smallest_original_column():
+    A = np.eye(4) * 2.0
     r, V, tau, W, perm = O.cpqr(A, 0.0)
     assert list(perm) == [0, 1, 2, 3]
+    # column 3 wins step 0; afterwards columns 0, 1, 2 tie and go in index order
+    # (a swap-order rule would take column 3's old position's occupant, 0, last)
+    B = np.diag([1.0, 1.0, 1.0, 2.0])
+    r, V, tau, W, perm = O.cpqr(B, 0.0)
+    assert list(perm) == [3, 0, 1, 2]
 
 
 def test_sparsification_schur_identity():
