@@ -8,9 +8,10 @@
 namespace spand {
 
 struct ElimAp {
-  const double* Linv;  // ns x ns, ld ns (inverse of the pivot block's Cholesky factor)
-  const double* G;     // nN x ns, ld nN (A_{N_s s} L_s^{-T})
-  int32_t ns, nN;
+  const double* L;     // ns x ns lower-triangular factor L_s (top of the panel), ld ld
+  const double* G;     // nN x ns, A_{N_s s} L_s^{-T} (below L_s in the panel), ld ld
+  const double* Dinv;  // inverses of the diagonal blocks of L_s (CHOL_NB^2 doubles each)
+  int32_t ld, ns, nN, pad;
   int64_t slot_s;      // offset of s's slots in the step slot array
   int64_t slot_N;      // offset of s's neighbour slots in the step neighbour-slot array
   int64_t tmp;         // offset of s's rows in the apply scratch
@@ -25,7 +26,8 @@ struct TargetContrib {
   int64_t tmp_s;    // where L_s^{-1} x_s lives in the apply scratch
 };
 struct ScaleAp {
-  const double* Linv;  // np x np
+  const double* L;     // np x np lower-triangular L_p, ld np
+  const double* Dinv;  // inverses of its diagonal blocks
   int32_t np, pad;
   int64_t slot_p;
   int64_t tmp;

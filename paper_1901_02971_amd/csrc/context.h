@@ -39,7 +39,8 @@ struct StepNum {
   std::vector<int32_t> rank;    // kept size after sparsification (-1: eliminated)
   std::vector<int64_t> slot_ptr;
   std::vector<int32_t> slot;    // current dofs of every cluster (vertex ids)
-  DevBuf elim, scale, house;    // factor pieces
+  DevBuf elim, scale, house;    // factor pieces: [L_s; G_s] panels, L_p, reflectors
+  DevBuf edinv, sdinv;          // inverses of the CHOL_NB-wide diagonal blocks of L_s, L_p
   DevBuf d_slot, d_nslot;       // slot arrays on the device
   // apply descriptors
   DevBuf d_elim, d_target, d_contrib, d_scale, d_house;

@@ -1,20 +1,22 @@
 // Numerical factorization driver: Algorithm 3 (OrthS) level by level on the GPU.
 //
-// Storage.  At step t the trailing matrix lives in one device arena as column
-// panels: the panel of cluster j stacks the dense blocks (i, j), i >= j, of the
-// block pattern (diagonal block first, then the others in ascending i), column-
-// major with the panel height as leading dimension.  Eliminated clusters come
-// first in the canonical order, so the panel of an eliminated s is exactly
-// [A_ss; A_{N_s s}].
+// Storage.  The trailing matrix of step t is a set of column panels: the panel of
+// cluster j stacks the dense blocks (i, j), i >= j, of the block pattern (diagonal
+// block first, then ascending i), column-major with the panel height as leading
+// dimension.  Eliminated clusters come first in the canonical order, so the panel
+// of an eliminated s is exactly [A_ss; A_{N_s s}]; those panels live in persistent
+// factor storage (they become [L_s; G_s]), the panels of the remaining clusters in
+// a per-step arena that the next step's merge consumes.
 //
 // Per step (t = 1..L, level l = L - t + 1):
 //   1. assemble: scatter the CSR values (t = 1) or merge the previous arena
 //      (Sec. 2.7: parent blocks are the concatenation of child blocks);
-//   2. eliminate every level-l cluster s (Sec. 2.4): L_s = chol(A_ss) and
-//      L_s^{-1}; G = A_{N_s s} L_s^{-T}; C_s = G G^T; every target block
-//      subtracts its contributions in ascending s (deterministic);
-//   3. if t > skip and l > 1: scale every remaining cluster (Sec. 2.5):
-//      L_p = chol(A_pp); A_ij <- L_i^{-1} A_ij L_j^{-T}; A_pp <- I;
+//   2. eliminate every level-l cluster s (Sec. 2.4): blocked Cholesky of the panel
+//      [A_ss; A_{N_s s}] -> [L_s; G = A_{N_s s} L_s^{-T}]; C_s = G G^T; every target
+//      block subtracts its contributions in ascending s (deterministic);
+//   3. if t > skip and l > 1: scale every remaining cluster (Sec. 2.5): blocked
+//      Cholesky of its panel gives L_p and the right-scaled blocks below it, a
+//      blocked left triangular solve applies L_i^{-1} to every block (i, p), A_pp <- I;
 //   4. then sparsify every remaining cluster, one colour class per launch
 //      (Sec. 2.6.1), and read the kept ranks back to the host;
 //   5. plan the next step's layout from the ranks.
@@ -56,24 +58,28 @@ spand_status upload(spand_ctx* h, DevBuf& b, const std::vector<T>& v) {
   return SPAND_OK;
 }
 
-// Column-panel layout of one step's arena.
+// Column-panel layout of one step.  Panels of eliminated clusters (j < ne) are
+// placed in the persistent elimination buffer, the others in the step arena.
 struct Layout {
+  int32_t ne = 0;
   std::vector<int64_t> pan_ptr;  // nc+1
   std::vector<int32_t> prow;     // row cluster of each panel entry (diagonal first)
   std::vector<int64_t> proff;    // row offset of each entry inside its panel
   std::vector<int64_t> H;        // panel heights
-  std::vector<int64_t> base;     // panel start (elements)
-  int64_t total = 0;
+  std::vector<int64_t> base;     // panel start (elements) inside its buffer
+  int64_t total_elim = 0, total_arena = 0;
   int64_t find(int32_t i, int32_t j) const {
     auto b = prow.begin() + pan_ptr[j], e = prow.begin() + pan_ptr[j + 1];
     auto it = std::lower_bound(b, e, i);
     if (it == e || *it != i) return -1;
     return proff[it - prow.begin()];
   }
+  double* panel(int32_t j, double* E, double* A) const { return (j < ne ? E : A) + base[j]; }
 };
 
 void build_layout(const SymStep& st, const std::vector<int32_t>& size, Layout& L) {
   const int32_t nc = st.nc, ne = st.ne;
+  L.ne = ne;
   L.pan_ptr.assign(nc + 1, 0);
   auto each = [&](auto&& f) {
     for (uint64_t p : st.before)
@@ -89,7 +95,7 @@ void build_layout(const SymStep& st, const std::vector<int32_t>& size, Layout& L
   each([&](uint64_t p) { L.prow[fill[pair_j(p)]++] = pair_i(p); });
   L.H.assign(nc, 0);
   L.base.assign(nc, 0);
-  int64_t tot = 0;
+  int64_t te = 0, ta = 0;
   for (int32_t j = 0; j < nc; ++j) {
     int64_t h = 0;
     for (int64_t e = L.pan_ptr[j]; e < L.pan_ptr[j + 1]; ++e) {
@@ -97,10 +103,12 @@ void build_layout(const SymStep& st, const std::vector<int32_t>& size, Layout& L
       h += size[L.prow[e]];
     }
     L.H[j] = h;
+    int64_t& tot = (j < ne) ? te : ta;
     L.base[j] = tot;
     tot += h * size[j];
   }
-  L.total = tot;
+  L.total_elim = te;
+  L.total_arena = ta;
 }
 
 void add_tiles(std::vector<TileRef>& tiles, int32_t desc, int32_t M, int32_t N, bool lower) {
@@ -112,26 +120,152 @@ void add_tiles(std::vector<TileRef>& tiles, int32_t desc, int32_t M, int32_t N, 
     }
 }
 
-struct GemmBatch {
+// A sequence of batched-GEMM launches whose descriptors and tiles are uploaded once.
+struct GemmSeq {
   std::vector<GemmDesc> d;
   std::vector<TileRef> t;
+  std::vector<int64_t> cut;  // tile range end of every launch
+  std::vector<int> prec;
   DevBuf dd, dt;
   void add(const GemmDesc& g, bool lower) {
     if (g.M <= 0 || g.N <= 0 || g.K <= 0) return;
     d.push_back(g);
     add_tiles(t, int32_t(d.size() - 1), g.M, g.N, lower);
   }
-  spand_status run(spand_ctx* h, int prec) {
-    if (t.empty()) return SPAND_OK;
+  void end_launch(int p) {
+    cut.push_back(int64_t(t.size()));
+    prec.push_back(p);
+  }
+  spand_status upload_all(spand_ctx* h) {
     spand_status st = upload(h, dd, d);
     if (st != SPAND_OK) return st;
-    st = upload(h, dt, t);
-    if (st != SPAND_OK) return st;
-    launch_gemm(dd.as<GemmDesc>(), dt.as<TileRef>(), int64_t(t.size()), prec, h->stream);
-    HIPCHK(hipGetLastError());
-    return SPAND_OK;
+    return upload(h, dt, t);
+  }
+  void launch(spand_ctx* h, size_t q) const {
+    const int64_t b = q ? cut[q - 1] : 0;
+    if (cut[q] > b) launch_gemm(dd.as<GemmDesc>(), dt.as<TileRef>() + b, cut[q] - b, prec[q], h->stream);
   }
 };
+
+// One panel factorized by the blocked Cholesky: diagonal n x n on top, m rows in all.
+struct Front {
+  double* P;
+  double* dinv;  // ceil(n / CHOL_NB) blocks of CHOL_NB^2 doubles
+  int32_t ld, n, m, id;
+};
+
+int64_t dinv_size(int32_t n) { return int64_t((n + CHOL_NB - 1) / CHOL_NB) * CHOL_NB * CHOL_NB; }
+
+// Right-looking blocked Cholesky of every front in lockstep over its diagonal
+// blocks.  Updates inside the n x n pivot block are FP64; `prec_below` selects the
+// arithmetic of the rows below it (the TRSM and Schur-side updates).
+spand_status blocked_cholesky(spand_ctx* h, const std::vector<Front>& F, int32_t* d_fail, int prec_below) {
+  int32_t nmax = 0;
+  for (const Front& f : F) nmax = std::max(nmax, f.n);
+  std::vector<PotrfDesc> pd;
+  std::vector<PanelDesc> td;
+  std::vector<int64_t> pcut, tcut;
+  GemmSeq g;
+  for (int32_t kb = 0; kb < nmax; kb += CHOL_NB) {
+    for (const Front& f : F) {
+      if (f.n <= kb) continue;
+      const int32_t w = std::min(CHOL_NB, f.n - kb);
+      double* Dk = f.dinv + int64_t(kb / CHOL_NB) * CHOL_NB * CHOL_NB;
+      pd.push_back(PotrfDesc{f.P + kb + int64_t(kb) * f.ld, Dk, f.ld, w, f.id, 0});
+      for (int32_t r0 = kb + w; r0 < f.m; r0 += 256)
+        td.push_back(PanelDesc{f.P + int64_t(kb) * f.ld, Dk, f.ld, w, r0, std::min(f.m, r0 + 256)});
+    }
+    pcut.push_back(int64_t(pd.size()));
+    tcut.push_back(int64_t(td.size()));
+    for (const Front& f : F) {  // trailing update inside the pivot block (FP64, lower tiles)
+      if (f.n <= kb) continue;
+      const int32_t w = std::min(CHOL_NB, f.n - kb);
+      GemmDesc q{};
+      q.A = f.P + (kb + w) + int64_t(kb) * f.ld; q.lda = f.ld;
+      q.B = q.A; q.ldb = f.ld;
+      q.C = f.P + (kb + w) + int64_t(kb + w) * f.ld; q.ldc = f.ld;
+      q.M = f.n - kb - w; q.N = f.n - kb - w; q.K = w;
+      q.flags = G_TB | G_LOWERC; q.alpha = -1.0; q.beta = 1.0;
+      g.add(q, true);
+    }
+    g.end_launch(0);
+    for (const Front& f : F) {  // rows below the pivot block
+      if (f.n <= kb) continue;
+      const int32_t w = std::min(CHOL_NB, f.n - kb);
+      GemmDesc q{};
+      q.A = f.P + f.n + int64_t(kb) * f.ld; q.lda = f.ld;
+      q.B = f.P + (kb + w) + int64_t(kb) * f.ld; q.ldb = f.ld;
+      q.C = f.P + f.n + int64_t(kb + w) * f.ld; q.ldc = f.ld;
+      q.M = f.m - f.n; q.N = f.n - kb - w; q.K = w;
+      q.flags = G_TB; q.alpha = -1.0; q.beta = 1.0;
+      g.add(q, false);
+    }
+    g.end_launch(prec_below);
+  }
+  DevBuf dp, dt;
+  spand_status st;
+  if ((st = upload(h, dp, pd)) != SPAND_OK) return st;
+  if ((st = upload(h, dt, td)) != SPAND_OK) return st;
+  if ((st = g.upload_all(h)) != SPAND_OK) return st;
+  for (size_t q = 0; q < pcut.size(); ++q) {
+    const int64_t pb = q ? pcut[q - 1] : 0, tb = q ? tcut[q - 1] : 0;
+    launch_potrf_diag(dp.as<PotrfDesc>() + pb, int32_t(pcut[q] - pb), d_fail, h->stream);
+    launch_panel_trsm(dt.as<PanelDesc>() + tb, int32_t(tcut[q] - tb), h->stream);
+    g.launch(h, 2 * q);
+    g.launch(h, 2 * q + 1);
+  }
+  HIPCHK(hipGetLastError());
+  // descriptors must outlive the launches
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return SPAND_OK;
+}
+
+// X (nrows x ncols, ld ldx) <- L^{-1} X for lower-triangular L (ld ldl) whose diagonal
+// blocks have the inverses `dinv`.
+struct LeftBlock {
+  double* X;
+  const double* L;
+  const double* dinv;
+  int32_t ldx, ldl, nrows, ncols;
+};
+
+spand_status left_trsm(spand_ctx* h, const std::vector<LeftBlock>& B) {
+  int32_t nmax = 0;
+  for (const LeftBlock& b : B) nmax = std::max(nmax, b.nrows);
+  std::vector<LeftDesc> ld;
+  std::vector<int64_t> lcut;
+  GemmSeq g;
+  for (int32_t kb = 0; kb < nmax; kb += CHOL_NB) {
+    for (const LeftBlock& b : B) {
+      if (b.nrows <= kb) continue;
+      const int32_t w = std::min(CHOL_NB, b.nrows - kb);
+      const double* Dk = b.dinv + int64_t(kb / CHOL_NB) * CHOL_NB * CHOL_NB;
+      for (int32_t c0 = 0; c0 < b.ncols; c0 += 256)
+        ld.push_back(LeftDesc{b.X + kb, Dk, b.ldx, w, c0, std::min(b.ncols, c0 + 256)});
+      GemmDesc q{};
+      q.A = b.L + (kb + w) + int64_t(kb) * b.ldl; q.lda = b.ldl;
+      q.B = b.X + kb; q.ldb = b.ldx;
+      q.C = b.X + kb + w; q.ldc = b.ldx;
+      q.M = b.nrows - kb - w; q.N = b.ncols; q.K = w;
+      q.flags = 0; q.alpha = -1.0; q.beta = 1.0;
+      g.add(q, false);
+    }
+    lcut.push_back(int64_t(ld.size()));
+    g.end_launch(0);
+  }
+  DevBuf dl;
+  spand_status st;
+  if ((st = upload(h, dl, ld)) != SPAND_OK) return st;
+  if ((st = g.upload_all(h)) != SPAND_OK) return st;
+  for (size_t q = 0; q < lcut.size(); ++q) {
+    const int64_t b = q ? lcut[q - 1] : 0;
+    launch_left_trsm_diag(dl.as<LeftDesc>() + b, int32_t(lcut[q] - b), h->stream);
+    g.launch(h, q);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return SPAND_OK;
+}
 
 }  // namespace
 
@@ -153,28 +287,25 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
   int32_t* d_fail_scale = dflag.as<int32_t>() + 1;
   int32_t* d_nonfinite = dflag.as<int32_t>() + 2;
 
-  // ev[0..1]: Schur GEMMs; ph[0..4]: phase boundaries of a step
-  hipEvent_t ev[2], ph[5];
+  // ph[0..4]: phase boundaries of a step
+  hipEvent_t ph[5];
   struct EvGuard {
     hipEvent_t* e;
     int n = 0;
     ~EvGuard() {
       for (int q = 0; q < n; ++q) (void)hipEventDestroy(e[q]);
     }
-  } g1{ev}, g2{ph};
-  for (int q = 0; q < 2; ++q, ++g1.n) HIPCHK(hipEventCreate(&ev[q]));
+  } g2{ph};
   for (int q = 0; q < 5; ++q, ++g2.n) HIPCHK(hipEventCreate(&ph[q]));
-  hipEvent_t ev0 = ev[0], ev1 = ev[1];
   std::memset(h->stats.step_phase_seconds, 0, sizeof(h->stats.step_phase_seconds));
   std::memset(h->stats.step_m_F, 0, sizeof(h->stats.step_m_F));
 
   int64_t m_F = 0;
-  double schur_flops = 0.0, schur_ms = 0.0;
+  double elim_flops = 0.0, elim_ms = 0.0;
   int32_t s_top = 0;
 
   DevBuf arena_prev;
   Layout lay_prev;
-  std::vector<int32_t> rank_prev;
 
   for (int32_t t = 1; t <= Lv; ++t) {
     const SymStep& sy = an.steps[t - 1];
@@ -211,18 +342,22 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
     if (sy.level == 1)
       for (int32_t s = 0; s < ne; ++s) s_top += sn.size[s];
 
-    // ---- arena layout and assembly
+    // ---- layout and assembly
     HIPCHK(hipEventRecord(ph[0], h->stream));
     Layout lay;
     build_layout(sy, sn.size, lay);
     DevBuf arena;
-    if ((st = dalloc(h, arena, size_t(lay.total) * sizeof(double))) != SPAND_OK) return st;
+    if ((st = dalloc(h, sn.elim, size_t(lay.total_elim) * sizeof(double))) != SPAND_OK) return st;
+    if ((st = dalloc(h, arena, size_t(lay.total_arena) * sizeof(double))) != SPAND_OK) return st;
+    double* E = sn.elim.as<double>();
     double* A = arena.as<double>();
-    if (lay.total) HIPCHK(hipMemsetAsync(A, 0, size_t(lay.total) * sizeof(double), h->stream));
+    if (lay.total_elim) HIPCHK(hipMemsetAsync(E, 0, size_t(lay.total_elim) * sizeof(double), h->stream));
+    if (lay.total_arena) HIPCHK(hipMemsetAsync(A, 0, size_t(lay.total_arena) * sizeof(double), h->stream));
     DevBuf d_dst, d_copy;
     std::vector<CopyDesc> copies;
     if (t == 1) {
-      // destination of every CSR entry inside the step-1 panels
+      // destination of every CSR entry inside the step-1 panels: >= 0 arena offset,
+      // <= -2 elimination-buffer offset -(d+2), -1 skipped (upper triangle)
       std::vector<int32_t> cl(an.n), pos(an.n);
       for (int32_t c = 0; c < nc; ++c)
         for (int64_t e = sy.child_ptr[c]; e < sy.child_ptr[c + 1]; ++e) {
@@ -235,19 +370,17 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
           const int32_t u = an.colind[e];
           const int32_t i = cl[v], j = cl[u];
           if (i < j) continue;
-          const int64_t ro = lay.find(i, j);
-          dst[e] = lay.base[j] + ro + pos[v] + int64_t(pos[u]) * lay.H[j];
+          const int64_t off = lay.base[j] + lay.find(i, j) + pos[v] + int64_t(pos[u]) * lay.H[j];
+          dst[e] = (j < ne) ? -(off + 2) : off;
         }
       if ((st = upload(h, d_dst, dst)) != SPAND_OK) return st;
-      launch_scatter_values(values, d_dst.as<int64_t>(), int64_t(dst.size()), A, d_nonfinite, h->stream);
+      launch_scatter_values(values, d_dst.as<int64_t>(), int64_t(dst.size()), A, E, d_nonfinite, h->stream);
       HIPCHK(hipGetLastError());
     } else {
-      const SymStep& ps = an.steps[t - 2];
       const StepNum& pv = h->num[t - 2];
       for (uint64_t pr : sy.before) {
         const int32_t I = pair_i(pr), J = pair_j(pr);
-        const int64_t dro = lay.find(I, J);
-        double* dbase = A + lay.base[J] + dro;
+        double* dbase = lay.panel(J, E, A) + lay.find(I, J);
         int64_t ro = 0;
         for (int64_t a = sy.child_ptr[I]; a < sy.child_ptr[I + 1]; ++a) {
           const int32_t i = sy.child[a];
@@ -277,7 +410,6 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
           ro += ri;
         }
       }
-      (void)ps;
       if ((st = upload(h, d_copy, copies)) != SPAND_OK) return st;
       launch_copy(d_copy.as<CopyDesc>(), int64_t(copies.size()), h->stream);
       HIPCHK(hipGetLastError());
@@ -285,62 +417,45 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
 
     // ---- elimination (Sec. 2.4)
     HIPCHK(hipEventRecord(ph[1], h->stream));
-    std::vector<int64_t> linv_off(ne), g_off(ne), c_off(ne);
+    std::vector<int64_t> c_off(ne), ed_off(ne);
     std::vector<int32_t> nN(ne);
-    int64_t elim_total = 0, cbuf_total = 0;
+    int64_t cbuf_total = 0, ed_total = 0;
     for (int32_t s = 0; s < ne; ++s) {
       nN[s] = int32_t(lay.H[s] - sn.size[s]);
-      linv_off[s] = elim_total;
-      elim_total += int64_t(sn.size[s]) * sn.size[s];
-      g_off[s] = elim_total;
-      elim_total += int64_t(nN[s]) * sn.size[s];
       c_off[s] = cbuf_total;
       cbuf_total += int64_t(nN[s]) * nN[s];
+      ed_off[s] = ed_total;
+      ed_total += dinv_size(sn.size[s]);
       const double ns = sn.size[s], nn = nN[s];
-      schur_flops += nn * ns * ns + nn * (nn + 1.0) * ns;
+      elim_flops += ns * ns * ns / 3.0 + nn * ns * ns + nn * (nn + 1.0) * ns;
       m_F += int64_t(sn.size[s]) * (sn.size[s] + 1) / 2 + int64_t(sn.size[s]) * nN[s];
     }
-    if ((st = dalloc(h, sn.elim, size_t(elim_total) * sizeof(double))) != SPAND_OK) return st;
+    if ((st = dalloc(h, sn.edinv, size_t(ed_total) * sizeof(double))) != SPAND_OK) return st;
     DevBuf cbuf;
     if ((st = dalloc(h, cbuf, size_t(cbuf_total) * sizeof(double))) != SPAND_OK) return st;
-    double* E = sn.elim.as<double>();
     {
-      std::vector<CholDesc> cds;
-      for (int32_t s = 0; s < ne; ++s) {
-        if (sn.size[s] == 0) continue;
-        cds.push_back(CholDesc{A + lay.base[s], E + linv_off[s], sn.size[s], int32_t(lay.H[s]), s, 0});
-      }
-      DevBuf dc;
-      if ((st = upload(h, dc, cds)) != SPAND_OK) return st;
-      launch_chol_inv(dc.as<CholDesc>(), int32_t(cds.size()), d_fail_elim, h->stream);
-      HIPCHK(hipGetLastError());
-      GemmBatch trsm, syrk;
+      std::vector<Front> fr;
+      for (int32_t s = 0; s < ne; ++s)
+        if (sn.size[s] > 0)
+          fr.push_back(Front{E + lay.base[s], sn.edinv.as<double>() + ed_off[s], int32_t(lay.H[s]), sn.size[s],
+                             int32_t(lay.H[s]), s});
+      if ((st = blocked_cholesky(h, fr, d_fail_elim, gemm_prec)) != SPAND_OK) return st;
+      GemmSeq syrk;
       for (int32_t s = 0; s < ne; ++s) {
         const int32_t ns = sn.size[s], nn = nN[s];
-        GemmDesc g{};
-        g.A = A + lay.base[s] + ns;  // A_{N_s s}
-        g.lda = int32_t(lay.H[s]);
-        g.B = E + linv_off[s];       // op(B)(k, n) = Linv[n][k]
-        g.ldb = ns;
-        g.C = E + g_off[s];
-        g.ldc = nn;
-        g.M = nn; g.N = ns; g.K = ns;
-        g.flags = G_TB | G_TRIB;
-        g.alpha = 1.0; g.beta = 0.0;
-        trsm.add(g, false);
         GemmDesc y{};
-        y.A = E + g_off[s]; y.lda = nn;
-        y.B = E + g_off[s]; y.ldb = nn;
+        y.A = E + lay.base[s] + ns; y.lda = int32_t(lay.H[s]);
+        y.B = y.A; y.ldb = y.lda;
         y.C = cbuf.as<double>() + c_off[s]; y.ldc = nn;
         y.M = nn; y.N = nn; y.K = ns;
         y.flags = G_TB | G_LOWERC;
         y.alpha = 1.0; y.beta = 0.0;
         syrk.add(y, true);
       }
-      HIPCHK(hipEventRecord(ev0, h->stream));
-      if ((st = trsm.run(h, gemm_prec)) != SPAND_OK) return st;
-      if ((st = syrk.run(h, gemm_prec)) != SPAND_OK) return st;
-      HIPCHK(hipEventRecord(ev1, h->stream));
+      syrk.end_launch(gemm_prec);
+      if ((st = syrk.upload_all(h)) != SPAND_OK) return st;
+      syrk.launch(h, 0);
+      HIPCHK(hipGetLastError());
       // deterministic reduction of C_s into the targets
       struct Item { uint64_t tgt; int32_t s; int64_t coff; };
       std::vector<Item> items;
@@ -352,7 +467,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
           int64_t ob = 0;
           for (int64_t q = b; q <= a; ++q) {
             const int32_t nb = sy.enb[q];
-            if (sn.size[na] > 0 && sn.size[nb] > 0)
+            if (sn.size[na] > 0 && sn.size[nb] > 0 && sn.size[s] > 0)
               items.push_back(Item{pair_pack(na, nb), s, c_off[s] + oa + ob * nN[s]});
             ob += sn.size[nb];
           }
@@ -388,8 +503,8 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       HIPCHK(hipEventRecord(ph[2], h->stream));
       HIPCHK(hipStreamSynchronize(h->stream));
       float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
-      schur_ms += ms;
+      HIPCHK(hipEventElapsedTime(&ms, ph[1], ph[2]));
+      elim_ms += ms;
     }
     int32_t flags[4];
     HIPCHK(hipMemcpy(flags, dflag.p, sizeof(flags), hipMemcpyDeviceToHost));
@@ -406,63 +521,53 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
     // ---- scaling (Sec. 2.5) and sparsification (Sec. 2.6.1)
     sn.rank.assign(nc, -1);
     for (int32_t c = ne; c < nc; ++c) sn.rank[c] = sn.size[c];
-    std::vector<int64_t> sc_off(nc, -1), v_off(nc, -1), tau_off(nc, -1);
+    std::vector<int64_t> sc_off(nc, -1), sd_off(nc, -1), v_off(nc, -1), tau_off(nc, -1);
     std::vector<int32_t> nref(nc, 0);
     HIPCHK(hipEventRecord(ph[3], h->stream));
     HIPCHK(hipEventRecord(ph[4], h->stream));
     if (sparsify && nc > ne) {
-      int64_t sc_total = 0;
+      int64_t sc_total = 0, sd_total = 0;
       for (int32_t p = ne; p < nc; ++p) {
         if (sn.size[p] == 0) continue;
         sc_off[p] = sc_total;
         sc_total += int64_t(sn.size[p]) * sn.size[p];
+        sd_off[p] = sd_total;
+        sd_total += dinv_size(sn.size[p]);
         m_F += int64_t(sn.size[p]) * (sn.size[p] + 1) / 2;
       }
       if ((st = dalloc(h, sn.scale, size_t(sc_total) * sizeof(double))) != SPAND_OK) return st;
+      if ((st = dalloc(h, sn.sdinv, size_t(sd_total) * sizeof(double))) != SPAND_OK) return st;
       double* SC = sn.scale.as<double>();
-      std::vector<CholDesc> cds;
+      double* SD = sn.sdinv.as<double>();
+      std::vector<Front> fr;
       for (int32_t p = ne; p < nc; ++p)
-        if (sn.size[p] > 0) cds.push_back(CholDesc{A + lay.base[p], SC + sc_off[p], sn.size[p], int32_t(lay.H[p]), p, 0});
-      DevBuf dc;
-      if ((st = upload(h, dc, cds)) != SPAND_OK) return st;
-      launch_chol_inv(dc.as<CholDesc>(), int32_t(cds.size()), d_fail_scale, h->stream);
-      HIPCHK(hipGetLastError());
-      // X <- L_i^{-1} X L_j^{-T}: T_j = (panel j below its diagonal) L_j^{-T}, then per block L_i^{-1} T
-      std::vector<int64_t> toff(nc, 0);
-      int64_t ttot = 0;
+        if (sn.size[p] > 0)
+          fr.push_back(Front{A + lay.base[p], SD + sd_off[p], int32_t(lay.H[p]), sn.size[p], int32_t(lay.H[p]), p});
+      if ((st = blocked_cholesky(h, fr, d_fail_scale, 0)) != SPAND_OK) return st;
+      // keep L_p for the apply, then L_i^{-1} from the left on every block (i, p)
+      std::vector<CopyDesc> lcopy;
+      std::vector<LeftBlock> lb;
       for (int32_t p = ne; p < nc; ++p) {
-        toff[p] = ttot;
-        ttot += (lay.H[p] - sn.size[p]) * sn.size[p];
-      }
-      DevBuf tbuf;
-      if ((st = dalloc(h, tbuf, size_t(ttot) * sizeof(double))) != SPAND_OK) return st;
-      GemmBatch right, left;
-      for (int32_t p = ne; p < nc; ++p) {
-        const int32_t np_ = sn.size[p];
-        const int32_t Mp = int32_t(lay.H[p] - np_);
-        if (np_ == 0 || Mp == 0) continue;
-        GemmDesc g{};
-        g.A = A + lay.base[p] + np_; g.lda = int32_t(lay.H[p]);
-        g.B = SC + sc_off[p]; g.ldb = np_;
-        g.C = tbuf.as<double>() + toff[p]; g.ldc = Mp;
-        g.M = Mp; g.N = np_; g.K = np_;
-        g.flags = G_TB | G_TRIB; g.alpha = 1.0; g.beta = 0.0;
-        right.add(g, false);
+        if (sn.size[p] == 0) continue;
+        CopyDesc cd{};
+        cd.src = A + lay.base[p];
+        cd.lds = int32_t(lay.H[p]);
+        cd.dst = SC + sc_off[p];
+        cd.ldd = sn.size[p];
+        cd.rows = cd.cols = sn.size[p];
+        lcopy.push_back(cd);
         for (int64_t e = lay.pan_ptr[p] + 1; e < lay.pan_ptr[p + 1]; ++e) {
           const int32_t i = lay.prow[e];
-          const int32_t ni = sn.size[i];
-          if (ni == 0) continue;
-          GemmDesc q{};
-          q.A = SC + sc_off[i]; q.lda = ni;
-          q.B = tbuf.as<double>() + toff[p] + (lay.proff[e] - np_); q.ldb = Mp;
-          q.C = A + lay.base[p] + lay.proff[e]; q.ldc = int32_t(lay.H[p]);
-          q.M = ni; q.N = np_; q.K = ni;
-          q.flags = G_TRIA; q.alpha = 1.0; q.beta = 0.0;
-          left.add(q, false);
+          if (sn.size[i] == 0) continue;
+          lb.push_back(LeftBlock{A + lay.base[p] + lay.proff[e], A + lay.base[i], SD + sd_off[i], int32_t(lay.H[p]),
+                                 int32_t(lay.H[i]), sn.size[i], sn.size[p]});
         }
       }
-      if ((st = right.run(h, 0)) != SPAND_OK) return st;
-      if ((st = left.run(h, 0)) != SPAND_OK) return st;
+      DevBuf dlc;
+      if ((st = upload(h, dlc, lcopy)) != SPAND_OK) return st;
+      launch_copy(dlc.as<CopyDesc>(), int64_t(lcopy.size()), h->stream);
+      HIPCHK(hipGetLastError());
+      if ((st = left_trsm(h, lb)) != SPAND_OK) return st;
       std::vector<double*> dptr;
       std::vector<int32_t> dn, dld;
       for (int32_t p = ne; p < nc; ++p)
@@ -487,7 +592,6 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
         return set_err(h, SPAND_E_NOT_SPD, "interface block not SPD at step " + std::to_string(t) + ", cluster " +
                                                std::to_string(flags[1]) + " (scaling)");
       }
-      tbuf.release();
 
       // sparsification, colour by colour; A_pn of each interface is cut into
       // LDS-resident column slabs (one workgroup each)
@@ -654,8 +758,10 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       sn.h_elim.clear();
       for (int32_t s = 0; s < ne; ++s) {
         ElimAp e{};
-        e.Linv = E + linv_off[s];
-        e.G = E + g_off[s];
+        e.L = E + lay.base[s];
+        e.G = E + lay.base[s] + sn.size[s];
+        e.Dinv = sn.edinv.as<double>() + ed_off[s];
+        e.ld = int32_t(lay.H[s]);
         e.ns = sn.size[s];
         e.nN = nN[s];
         e.slot_s = sn.slot_ptr[s];
@@ -691,7 +797,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
         ta.cbeg = int32_t(sn.h_contrib.size());
         while (r < tis.size() && tis[r].n == tis[q].n) {
           const int32_t s = tis[r].s;
-          sn.h_contrib.push_back(TargetContrib{E + g_off[s] + tis[r].row, nN[s], sn.size[s], sn.h_elim[s].tmp});
+          sn.h_contrib.push_back(TargetContrib{sn.h_elim[s].G + tis[r].row, sn.h_elim[s].ld, sn.size[s], sn.h_elim[s].tmp});
           ++r;
         }
         ta.cend = int32_t(sn.h_contrib.size());
@@ -704,7 +810,8 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       for (int32_t p = ne; p < nc; ++p) {
         if (sc_off[p] >= 0) {
           ScaleAp a{};
-          a.Linv = sn.scale.as<double>() + sc_off[p];
+          a.L = sn.scale.as<double>() + sc_off[p];
+          a.Dinv = sn.sdinv.as<double>() + sd_off[p];
           a.np = sn.size[p];
           a.slot_p = sn.slot_ptr[p];
           a.tmp = tmp2;
@@ -745,8 +852,8 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
   arena_prev.release();
   h->stats.m_F = m_F;
   h->stats.s_top = s_top;
-  h->stats.schur_flops = schur_flops;
-  h->stats.schur_seconds = schur_ms * 1e-3;
+  h->stats.schur_flops = elim_flops;
+  h->stats.schur_seconds = elim_ms * 1e-3;
   return SPAND_OK;
 }
 

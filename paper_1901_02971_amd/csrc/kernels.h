@@ -7,14 +7,26 @@
 
 namespace spand {
 
-// Batched Cholesky + triangular inverse of one diagonal block.
-struct CholDesc {
-  double* A;     // n x n, column-major, ld lda; lower triangle overwritten by L
-  double* Linv;  // n x n output, ld n: L^{-1} (zeros above the diagonal)
-  int32_t n, lda;
-  int32_t id;    // cluster id reported on failure
-  int32_t pad;
+// Blocked Cholesky (kernels_chol.hip).  Diagonal blocks are CHOL_NB wide.
+constexpr int CHOL_NB = 64;
+struct PotrfDesc {
+  double* P;     // diagonal block start (column-major, ld)
+  double* Dinv;  // w x w output: inverse of the diagonal block's factor, ld w
+  int32_t ld, w, id, pad;
 };
+struct PanelDesc {
+  double* P;           // panel column kb (row 0 of the panel), ld
+  const double* Dinv;  // w x w
+  int32_t ld, w, r0, r1;  // rows [r0, r1) are solved
+};
+struct LeftDesc {
+  double* X;           // row kb of the block, ld ldx
+  const double* Dinv;  // w x w
+  int32_t ldx, w, c0, c1;  // columns [c0, c1) are solved
+};
+void launch_potrf_diag(const PotrfDesc* d, int32_t count, int32_t* fail, hipStream_t s);
+void launch_panel_trsm(const PanelDesc* d, int32_t count, hipStream_t s);
+void launch_left_trsm_diag(const LeftDesc* d, int32_t count, hipStream_t s);
 
 // One product C = alpha * op(A) op(B) + beta * C on column-major operands.
 enum : int32_t {
@@ -77,9 +89,9 @@ struct SlabRef {
   int32_t desc, w;
 };
 
-void launch_scatter_values(const double* vals, const int64_t* dst, int64_t nnz, double* arena, int32_t* flag,
-                           hipStream_t s);
-void launch_chol_inv(const CholDesc* d, int32_t count, int32_t* fail, hipStream_t s);
+// dst >= 0: arena[dst]; dst <= -2: elim[-dst - 2]; dst == -1: skipped.
+void launch_scatter_values(const double* vals, const int64_t* dst, int64_t nnz, double* arena, double* elim,
+                           int32_t* flag, hipStream_t s);
 void launch_gemm(const GemmDesc* d, const TileRef* tiles, int64_t ntiles, int prec, hipStream_t s);
 void launch_reduce(const ReduceDesc* d, int32_t count, const ContribDesc* c, hipStream_t s);
 void launch_copy(const CopyDesc* d, int64_t count, hipStream_t s);

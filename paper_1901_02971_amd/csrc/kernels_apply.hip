@@ -3,7 +3,9 @@
 // addressed through its slot list (vertex ids of the dofs it currently carries).
 //
 // Forward sweep of one step (levels L -> 1):
-//   k_elim_fwd    x_s <- L_s^{-1} x_s            (one workgroup per eliminated s)
+//   k_elim_fwd    x_s <- L_s^{-1} x_s            (one workgroup per eliminated s;
+//                                                  blocked substitution with the
+//                                                  inverses of the diagonal blocks)
 //   k_target_fwd  x_n <- x_n - sum_s G_ns x_s     (one workgroup per receiving n,
 //                                                  contributions in ascending s)
 //   k_scale_fwd   x_p <- L_p^{-1} x_p
@@ -16,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include "apply.h"
+#include "kernels.h"
 
 namespace spand {
 
@@ -27,33 +30,130 @@ __device__ inline double wsum(double v) {
   return v;
 }
 
-// y = Linv x_s (lower-triangular Linv, ld ns) into tmp, then x_s <- y.
-__global__ void __launch_bounds__(AW) k_elim_fwd(const ElimAp* __restrict__ ds, ApplyArgs a) {
-  const ElimAp e = ds[blockIdx.x];
-  const int ns = e.ns;
-  const int32_t* sl = a.slot + e.slot_s;
-  for (int c0 = 0; c0 < a.nrhs; c0 += RB) {
-    const int nr = min(RB, a.nrhs - c0);
-    for (int r = threadIdx.x; r < ns; r += AW) {
-      double acc[RB];
+// Blocked triangular solves on a vector segment v (n rows, nr <= RB columns, ld ldv)
+// held in the apply scratch.  L is lower triangular (ld), its CHOL_NB-wide diagonal
+// blocks have the inverses Dinv (block k at k*CHOL_NB^2, ld = block width).
+struct TrsvShared {
+  double part[AW / 64][CHOL_NB][RB];
+  double tb[CHOL_NB][RB];
+};
+
+// L y = v, in place: y_k = D_k^{-1} (v_k - sum_{l<k} L_kl y_l)
+__device__ void trsv_fwd(const double* __restrict__ L, int ld, const double* __restrict__ Dinv, int n, double* v,
+                         int64_t ldv, int nr, TrsvShared& sh) {
+  const int rr = threadIdx.x & 63, g = threadIdx.x >> 6;
+  for (int kb = 0; kb < n; kb += CHOL_NB) {
+    const int w = min(CHOL_NB, n - kb);
+    double acc[RB];
 #pragma unroll
-      for (int c = 0; c < RB; ++c) acc[c] = 0.0;
-      for (int k = 0; k <= r; ++k) {
-        const double l = e.Linv[r + (int64_t)k * ns];
-        const double* xp = a.x + sl[k] + (int64_t)c0 * a.ldx;
+    for (int c = 0; c < RB; ++c) acc[c] = 0.0;
+    if (rr < w) {
+      const double* Lr = L + kb + rr;
+      for (int k = g; k < kb; k += AW / 64) {
+        const double l = Lr[(int64_t)k * ld];
 #pragma unroll
         for (int c = 0; c < RB; ++c)
-          if (c < nr) acc[c] += l * xp[(int64_t)c * a.ldx];
+          if (c < nr) acc[c] += l * v[k + (int64_t)c * ldv];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < RB; ++c) sh.part[g][rr][c] = acc[c];
+    __syncthreads();
+    if (threadIdx.x < w) {
+      const int i = threadIdx.x;
+#pragma unroll
+      for (int c = 0; c < RB; ++c)
+        if (c < nr)
+          sh.tb[i][c] = v[kb + i + (int64_t)c * ldv] - (sh.part[0][i][c] + sh.part[1][i][c] + sh.part[2][i][c] +
+                                                       sh.part[3][i][c]);
+    }
+    __syncthreads();
+    if (threadIdx.x < w) {
+      const int i = threadIdx.x;
+      const double* Dk = Dinv + (int64_t)(kb / CHOL_NB) * CHOL_NB * CHOL_NB;
+      double y[RB];
+#pragma unroll
+      for (int c = 0; c < RB; ++c) y[c] = 0.0;
+      for (int k = 0; k <= i; ++k) {
+        const double dv = Dk[i + k * w];
+#pragma unroll
+        for (int c = 0; c < RB; ++c) y[c] += dv * sh.tb[k][c];
       }
 #pragma unroll
       for (int c = 0; c < RB; ++c)
-        if (c < nr) a.tmp[e.tmp + r + (int64_t)(c0 + c) * a.ldt] = acc[c];
+        if (c < nr) v[kb + i + (int64_t)c * ldv] = y[c];
     }
+    __threadfence_block();
+    __syncthreads();
   }
+}
+
+// L^T x = v, in place: x_k = D_k^{-T} (v_k - sum_{l>k} L_lk^T x_l)
+__device__ void trsv_bwd(const double* __restrict__ L, int ld, const double* __restrict__ Dinv, int n, double* v,
+                         int64_t ldv, int nr, TrsvShared& sh) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nblk = (n + CHOL_NB - 1) / CHOL_NB;
+  for (int bi = nblk - 1; bi >= 0; --bi) {
+    const int kb = bi * CHOL_NB;
+    const int w = min(CHOL_NB, n - kb);
+    for (int cc = wave; cc < w; cc += AW / 64) {
+      double acc[RB];
+#pragma unroll
+      for (int c = 0; c < RB; ++c) acc[c] = 0.0;
+      const double* Lc = L + (int64_t)(kb + cc) * ld;
+      for (int r = kb + w + lane; r < n; r += 64) {
+        const double l = Lc[r];
+#pragma unroll
+        for (int c = 0; c < RB; ++c)
+          if (c < nr) acc[c] += l * v[r + (int64_t)c * ldv];
+      }
+#pragma unroll
+      for (int c = 0; c < RB; ++c) {
+        const double sum = wsum(acc[c]);
+        if (lane == 0 && c < nr) sh.tb[cc][c] = v[kb + cc + (int64_t)c * ldv] - sum;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < w) {
+      const int i = threadIdx.x;
+      const double* Dk = Dinv + (int64_t)bi * CHOL_NB * CHOL_NB;
+      double x[RB];
+#pragma unroll
+      for (int c = 0; c < RB; ++c) x[c] = 0.0;
+      for (int q = i; q < w; ++q) {
+        const double dv = Dk[q + i * w];
+#pragma unroll
+        for (int c = 0; c < RB; ++c) x[c] += dv * sh.tb[q][c];
+      }
+#pragma unroll
+      for (int c = 0; c < RB; ++c)
+        if (c < nr) v[kb + i + (int64_t)c * ldv] = x[c];
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+}
+
+__device__ inline void gather_seg(const int32_t* sl, int n, const ApplyArgs& a, int64_t off) {
+  for (int c = 0; c < a.nrhs; ++c)
+    for (int r = threadIdx.x; r < n; r += AW) a.tmp[off + r + (int64_t)c * a.ldt] = a.x[sl[r] + (int64_t)c * a.ldx];
   __threadfence_block();
   __syncthreads();
+}
+__device__ inline void scatter_seg(const int32_t* sl, int n, const ApplyArgs& a, int64_t off) {
   for (int c = 0; c < a.nrhs; ++c)
-    for (int r = threadIdx.x; r < ns; r += AW) a.x[sl[r] + (int64_t)c * a.ldx] = a.tmp[e.tmp + r + (int64_t)c * a.ldt];
+    for (int r = threadIdx.x; r < n; r += AW) a.x[sl[r] + (int64_t)c * a.ldx] = a.tmp[off + r + (int64_t)c * a.ldt];
+}
+
+// y_s = L_s^{-1} x_s; y_s stays in the scratch for the target updates and replaces x_s.
+__global__ void __launch_bounds__(AW) k_elim_fwd(const ElimAp* __restrict__ ds, ApplyArgs a) {
+  __shared__ TrsvShared sh;
+  const ElimAp e = ds[blockIdx.x];
+  const int32_t* sl = a.slot + e.slot_s;
+  gather_seg(sl, e.ns, a, e.tmp);
+  for (int c0 = 0; c0 < a.nrhs; c0 += RB)
+    trsv_fwd(e.L, e.ld, e.Dinv, e.ns, a.tmp + e.tmp + (int64_t)c0 * a.ldt, a.ldt, min(RB, a.nrhs - c0), sh);
+  scatter_seg(sl, e.ns, a, e.tmp);
 }
 
 __global__ void __launch_bounds__(AW) k_target_fwd(const TargetAp* __restrict__ ts, const TargetContrib* __restrict__ cs,
@@ -85,63 +185,23 @@ __global__ void __launch_bounds__(AW) k_target_fwd(const TargetAp* __restrict__ 
 }
 
 __global__ void __launch_bounds__(AW) k_scale_fwd(const ScaleAp* __restrict__ ds, ApplyArgs a) {
+  __shared__ TrsvShared sh;
   const ScaleAp e = ds[blockIdx.x];
-  const int np = e.np;
   const int32_t* sl = a.slot + e.slot_p;
-  for (int c0 = 0; c0 < a.nrhs; c0 += RB) {
-    const int nr = min(RB, a.nrhs - c0);
-    for (int r = threadIdx.x; r < np; r += AW) {
-      double acc[RB];
-#pragma unroll
-      for (int c = 0; c < RB; ++c) acc[c] = 0.0;
-      for (int k = 0; k <= r; ++k) {
-        const double l = e.Linv[r + (int64_t)k * np];
-        const double* xp = a.x + sl[k] + (int64_t)c0 * a.ldx;
-#pragma unroll
-        for (int c = 0; c < RB; ++c)
-          if (c < nr) acc[c] += l * xp[(int64_t)c * a.ldx];
-      }
-#pragma unroll
-      for (int c = 0; c < RB; ++c)
-        if (c < nr) a.tmp[e.tmp + r + (int64_t)(c0 + c) * a.ldt] = acc[c];
-    }
-  }
-  __threadfence_block();
-  __syncthreads();
-  for (int c = 0; c < a.nrhs; ++c)
-    for (int r = threadIdx.x; r < np; r += AW) a.x[sl[r] + (int64_t)c * a.ldx] = a.tmp[e.tmp + r + (int64_t)c * a.ldt];
+  gather_seg(sl, e.np, a, e.tmp);
+  for (int c0 = 0; c0 < a.nrhs; c0 += RB)
+    trsv_fwd(e.L, e.np, e.Dinv, e.np, a.tmp + e.tmp + (int64_t)c0 * a.ldt, a.ldt, min(RB, a.nrhs - c0), sh);
+  scatter_seg(sl, e.np, a, e.tmp);
 }
 
-// x_p <- L_p^{-T} x_p: output k = sum_{r >= k} Linv[r][k] x[r]; one wave per output.
 __global__ void __launch_bounds__(AW) k_scale_bwd(const ScaleAp* __restrict__ ds, ApplyArgs a) {
+  __shared__ TrsvShared sh;
   const ScaleAp e = ds[blockIdx.x];
-  const int np = e.np;
   const int32_t* sl = a.slot + e.slot_p;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int c0 = 0; c0 < a.nrhs; c0 += RB) {
-    const int nr = min(RB, a.nrhs - c0);
-    for (int k = wave; k < np; k += AW / 64) {
-      double acc[RB];
-#pragma unroll
-      for (int c = 0; c < RB; ++c) acc[c] = 0.0;
-      for (int r = k + lane; r < np; r += 64) {
-        const double l = e.Linv[r + (int64_t)k * np];
-        const double* xp = a.x + sl[r] + (int64_t)c0 * a.ldx;
-#pragma unroll
-        for (int c = 0; c < RB; ++c)
-          if (c < nr) acc[c] += l * xp[(int64_t)c * a.ldx];
-      }
-#pragma unroll
-      for (int c = 0; c < RB; ++c) {
-        const double v = wsum(acc[c]);
-        if (lane == 0 && c < nr) a.tmp[e.tmp + k + (int64_t)(c0 + c) * a.ldt] = v;
-      }
-    }
-  }
-  __threadfence_block();
-  __syncthreads();
-  for (int c = 0; c < a.nrhs; ++c)
-    for (int r = threadIdx.x; r < np; r += AW) a.x[sl[r] + (int64_t)c * a.ldx] = a.tmp[e.tmp + r + (int64_t)c * a.ldt];
+  gather_seg(sl, e.np, a, e.tmp);
+  for (int c0 = 0; c0 < a.nrhs; c0 += RB)
+    trsv_bwd(e.L, e.np, e.Dinv, e.np, a.tmp + e.tmp + (int64_t)c0 * a.ldt, a.ldt, min(RB, a.nrhs - c0), sh);
+  scatter_seg(sl, e.np, a, e.tmp);
 }
 
 // Householder sweep over the r reflectors of Q_p (V column-major, ld np, unit
@@ -201,8 +261,9 @@ __global__ void k_gather(const int32_t* __restrict__ nslot, int64_t len, ApplyAr
   for (int c = 0; c < a.nrhs; ++c) a.gbuf[q + (int64_t)c * a.ldg] = a.x[s + (int64_t)c * a.ldx];
 }
 
-// t_k = x_s[k] - sum_r G[r][k] xN[r] (wave per k), then x_s[k'] = sum_{k>=k'} Linv[k][k'] t_k.
+// t_k = x_s[k] - sum_r G[r][k] xN[r] (wave per k), then x_s = L_s^{-T} t.
 __global__ void __launch_bounds__(AW) k_elim_bwd(const ElimAp* __restrict__ ds, ApplyArgs a) {
+  __shared__ TrsvShared sh;
   const ElimAp e = ds[blockIdx.x];
   const int ns = e.ns, nN = e.nN;
   const int32_t* sl = a.slot + e.slot_s;
@@ -213,8 +274,9 @@ __global__ void __launch_bounds__(AW) k_elim_bwd(const ElimAp* __restrict__ ds, 
       double acc[RB];
 #pragma unroll
       for (int c = 0; c < RB; ++c) acc[c] = 0.0;
+      const double* Gk = e.G + (int64_t)k * e.ld;
       for (int r = lane; r < nN; r += 64) {
-        const double g = e.G[r + (int64_t)k * nN];
+        const double g = Gk[r];
         const double* xp = a.gbuf + e.slot_N + r + (int64_t)c0 * a.ldg;
 #pragma unroll
         for (int c = 0; c < RB; ++c)
@@ -230,26 +292,9 @@ __global__ void __launch_bounds__(AW) k_elim_bwd(const ElimAp* __restrict__ ds, 
   }
   __threadfence_block();
   __syncthreads();
-  for (int c0 = 0; c0 < a.nrhs; c0 += RB) {
-    const int nr = min(RB, a.nrhs - c0);
-    for (int k = wave; k < ns; k += AW / 64) {
-      double acc[RB];
-#pragma unroll
-      for (int c = 0; c < RB; ++c) acc[c] = 0.0;
-      for (int r = k + lane; r < ns; r += 64) {
-        const double l = e.Linv[r + (int64_t)k * ns];
-        const double* tp = a.tmp + e.tmp + r + (int64_t)c0 * a.ldt;
-#pragma unroll
-        for (int c = 0; c < RB; ++c)
-          if (c < nr) acc[c] += l * tp[(int64_t)c * a.ldt];
-      }
-#pragma unroll
-      for (int c = 0; c < RB; ++c) {
-        const double v = wsum(acc[c]);
-        if (lane == 0 && c < nr) a.x[sl[k] + (int64_t)(c0 + c) * a.ldx] = v;
-      }
-    }
-  }
+  for (int c0 = 0; c0 < a.nrhs; c0 += RB)
+    trsv_bwd(e.L, e.ld, e.Dinv, ns, a.tmp + e.tmp + (int64_t)c0 * a.ldt, a.ldt, min(RB, a.nrhs - c0), sh);
+  scatter_seg(sl, ns, a, e.tmp);
 }
 
 void apply_step_forward(const StepDev& s, const ApplyArgs& a, hipStream_t st) {

@@ -1,0 +1,133 @@
+// Blocked Cholesky building blocks (Sec. 2.4 pivot blocks, Sec. 2.5 interface
+// blocks), run in lockstep over every panel of a level by the host driver:
+//
+//   for kb = 0, NB, 2NB, ...:
+//     k_potrf_diag   factor the w x w diagonal block D = P[kb:kb+w, kb:kb+w] in LDS,
+//                    write L_kk back and D_k^{-1} = L_kk^{-1} to the inverse store;
+//     k_panel_trsm   P[kb+w:, kb:kb+w] <- P[kb+w:, kb:kb+w] L_kk^{-T} (in place, row per thread);
+//     trailing GEMM  P[kb+w:, kb+w:n] -= P[kb+w:, kb:kb+w] P[kb+w:n, kb:kb+w]^T (k_gemm).
+//
+// Applied to the panel [A_ss; A_{N_s s}] this leaves [L_s; A_{N_s s} L_s^{-T}], i.e. the
+// factor and G of the elimination; applied to an interface panel it leaves L_p on
+// top and the right-scaled blocks below.  The left scaling by L_i^{-1} of block
+// (i, p) is the same recurrence from the left:
+//     k_left_trsm_diag  X[kb:kb+w, :] <- L_kk^{-1} X[kb:kb+w, :]
+//     GEMM              X[kb+w:, :] -= L[kb+w:, kb:kb+w] X[kb:kb+w, :]
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels.h"
+
+namespace spand {
+
+#define PW 256
+
+__global__ void __launch_bounds__(PW) k_potrf_diag(const PotrfDesc* __restrict__ descs, int32_t* fail) {
+  const PotrfDesc d = descs[blockIdx.x];
+  const int w = d.w;
+  __shared__ double D[CHOL_NB][CHOL_NB + 1];
+  __shared__ double X[CHOL_NB][CHOL_NB + 1];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  for (int e = tid; e < w * w; e += PW) {
+    const int r = e % w, c = e / w;
+    D[r][c] = (r >= c) ? d.P[r + (int64_t)c * d.ld] : 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < w; ++k) {
+    double piv = D[k][k];
+    if (!(piv > 0.0) || !isfinite(piv)) {
+      piv = 1.0;
+      if (tid == 0) bad = 1;
+    }
+    const double rk = sqrt(piv);
+    __syncthreads();
+    if (tid == 0) D[k][k] = rk;
+    for (int i = k + 1 + tid; i < w; i += PW) D[i][k] /= rk;
+    __syncthreads();
+    const int m = w - k - 1;
+    for (int e = tid; e < m * m; e += PW) {
+      const int i = k + 1 + e % m, j = k + 1 + e / m;
+      if (i >= j) D[i][j] -= D[i][k] * D[j][k];
+    }
+    __syncthreads();
+  }
+  // X = L^{-1}, row by row: X[i][c] = (delta_ic - sum_{c<=q<i} L[i][q] X[q][c]) / L[i][i]
+  for (int i = 0; i < w; ++i) {
+    for (int c = tid; c < w; c += PW) {
+      double acc = (c == i) ? 1.0 : 0.0;
+      for (int q = c; q < i; ++q) acc -= D[i][q] * X[q][c];
+      X[i][c] = (c <= i) ? acc / D[i][i] : 0.0;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < w * w; e += PW) {
+    const int r = e % w, c = e / w;
+    if (r >= c) d.P[r + (int64_t)c * d.ld] = D[r][c];
+    d.Dinv[r + (int64_t)c * w] = X[r][c];
+  }
+  if (bad && tid == 0) atomicMin(fail, d.id);
+}
+
+// rows [r0, r1) of the panel below the diagonal block: x <- x L_kk^{-T}
+__global__ void __launch_bounds__(PW) k_panel_trsm(const PanelDesc* __restrict__ descs) {
+  const PanelDesc d = descs[blockIdx.x];
+  const int w = d.w;
+  __shared__ double Xi[CHOL_NB][CHOL_NB + 1];
+  for (int e = threadIdx.x; e < w * w; e += PW) Xi[e % w][e / w] = d.Dinv[e];
+  __syncthreads();
+  const int r = d.r0 + threadIdx.x;
+  if (r >= d.r1) return;
+  double* row = d.P + r;
+  double x[CHOL_NB];
+#pragma unroll
+  for (int k = 0; k < CHOL_NB; ++k) x[k] = (k < w) ? row[(int64_t)k * d.ld] : 0.0;
+  // out[c] = sum_{k <= c} x[k] Xi[c][k]; fully unrolled so x stays in registers
+#pragma unroll
+  for (int c = 0; c < CHOL_NB; ++c) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k <= c; ++k) s = fma(x[k], Xi[c][k], s);
+    if (c < w) row[(int64_t)c * d.ld] = s;
+  }
+}
+
+// columns [c0, c1) of X (rows kb..kb+w): x <- L_kk^{-1} x
+__global__ void __launch_bounds__(PW) k_left_trsm_diag(const LeftDesc* __restrict__ descs) {
+  const LeftDesc d = descs[blockIdx.x];
+  const int w = d.w;
+  __shared__ double Xi[CHOL_NB][CHOL_NB + 1];
+  for (int e = threadIdx.x; e < w * w; e += PW) Xi[e % w][e / w] = d.Dinv[e];
+  __syncthreads();
+  const int c = d.c0 + threadIdx.x;
+  if (c >= d.c1) return;
+  double* col = d.X + (int64_t)c * d.ldx;
+  double x[CHOL_NB];
+#pragma unroll
+  for (int k = 0; k < CHOL_NB; ++k) x[k] = (k < w) ? col[k] : 0.0;
+  // out[i] = sum_{k <= i} Xi[i][k] x[k]
+#pragma unroll
+  for (int i = 0; i < CHOL_NB; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k <= i; ++k) s = fma(Xi[i][k], x[k], s);
+    if (i < w) col[i] = s;
+  }
+}
+
+void launch_potrf_diag(const PotrfDesc* d, int32_t count, int32_t* fail, hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_potrf_diag, dim3(count), dim3(PW), 0, s, d, fail);
+}
+void launch_panel_trsm(const PanelDesc* d, int32_t count, hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_panel_trsm, dim3(count), dim3(PW), 0, s, d);
+}
+void launch_left_trsm_diag(const LeftDesc* d, int32_t count, hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_left_trsm_diag, dim3(count), dim3(PW), 0, s, d);
+}
+
+}  // namespace spand

@@ -1,10 +1,8 @@
 // Dense batched kernels of the factorization (gfx950, wave64).
 //
-//  * k_chol_inv   Cholesky of a pivot block (Sec. 2.4) or interface block (Sec. 2.5)
-//                 and the inverse of its factor, one workgroup per block.
 //  * k_gemm       batched variable-size GEMM over a flat list of 64x64 output tiles;
-//                 carries the TRSM-by-inverse and the SYRK of the Schur update
-//                 (Sec. 2.4) and the two-sided scaling of Sec. 2.5.
+//                 carries the trailing updates of the blocked Cholesky, the SYRK of
+//                 the Schur update (Sec. 2.4) and the left scaling of Sec. 2.5.
 //  * k_reduce     deterministic Schur-complement accumulation: every target block
 //                 subtracts its contributions in ascending eliminated-cluster order.
 //  * k_copy       strided (optionally transposed) block copies for the merge (Sec. 2.7).
@@ -65,80 +63,20 @@ __device__ inline int block_min_i(int v, int* red) {
 
 // ---------------------------------------------------------------- CSR scatter
 __global__ void k_scatter_values(const double* __restrict__ vals, const int64_t* __restrict__ dst, int64_t nnz,
-                                 double* __restrict__ arena, int32_t* flag) {
+                                 double* __restrict__ arena, double* __restrict__ elim, int32_t* flag) {
   int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= nnz) return;
   double v = vals[e];
   if (!isfinite(v)) atomicOr(flag, 1);
   int64_t d = dst[e];
   if (d >= 0) arena[d] = v;
+  else if (d <= -2) elim[-d - 2] = v;
 }
 
-void launch_scatter_values(const double* vals, const int64_t* dst, int64_t nnz, double* arena, int32_t* flag,
-                           hipStream_t s) {
+void launch_scatter_values(const double* vals, const int64_t* dst, int64_t nnz, double* arena, double* elim,
+                           int32_t* flag, hipStream_t s) {
   if (nnz == 0) return;
-  hipLaunchKernelGGL(k_scatter_values, dim3((nnz + 255) / 256), dim3(256), 0, s, vals, dst, nnz, arena, flag);
-}
-
-// ---------------------------------------------------------------- Cholesky + inverse
-// Right-looking Cholesky in place (lower triangle), then the inverse of L by rows:
-// X[i][c] = (delta_ic - sum_{c<=k<i} L[i][k] X[k][c]) / L[i][i].  A non-positive or
-// non-finite pivot records the block id in *fail (smallest id wins) and the
-// factorization continues on a unit pivot so that every wave finishes normally.
-__global__ void __launch_bounds__(WG) k_chol_inv(const CholDesc* __restrict__ descs, int32_t* fail) {
-  const CholDesc d = descs[blockIdx.x];
-  const int n = d.n, lda = d.lda;
-  double* A = d.A;
-  __shared__ int bad;
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    double piv = A[k + (int64_t)k * lda];
-    if (!(piv > 0.0) || !isfinite(piv)) {
-      if (threadIdx.x == 0) bad = 1;
-      piv = 1.0;
-    }
-    const double r = sqrt(piv);
-    const double rinv = 1.0 / r;
-    __syncthreads();
-    if (threadIdx.x == 0) A[k + (int64_t)k * lda] = r;
-    for (int i = k + 1 + threadIdx.x; i < n; i += WG) A[i + (int64_t)k * lda] *= rinv;
-    __syncthreads();
-    // trailing update of the lower triangle, flattened: entry q of the packed
-    // lower triangle of size m = n-k-1 (row-major) -> (i', j')
-    const int m = n - k - 1;
-    const int64_t cnt = (int64_t)m * (m + 1) / 2;
-    const double* colk = A + (int64_t)k * lda;
-    for (int64_t q = threadIdx.x; q < cnt; q += WG) {
-      int ip = (int)((sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
-      while ((int64_t)ip * (ip + 1) / 2 > q) --ip;
-      while ((int64_t)(ip + 1) * (ip + 2) / 2 <= q) ++ip;
-      const int jp = (int)(q - (int64_t)ip * (ip + 1) / 2);
-      const int i = k + 1 + ip, j = k + 1 + jp;
-      A[i + (int64_t)j * lda] -= colk[i] * colk[j];
-    }
-    __syncthreads();
-  }
-  if (bad && threadIdx.x == 0) atomicMin(fail, d.id);
-  // inverse, row by row
-  double* X = d.Linv;
-  const int ldx = n;
-  for (int i = 0; i < n; ++i) {
-    const double lii = A[i + (int64_t)i * lda];
-    for (int c = threadIdx.x; c < n; c += WG) {
-      double acc = (c == i) ? 1.0 : 0.0;
-      if (c < i) {
-        for (int k0 = c; k0 < i; ++k0) acc -= A[i + (int64_t)k0 * lda] * X[k0 + (int64_t)c * ldx];
-      }
-      X[i + (int64_t)c * ldx] = (c <= i) ? acc / lii : 0.0;
-    }
-    __syncthreads();
-  }
-}
-
-void launch_chol_inv(const CholDesc* d, int32_t count, int32_t* fail, hipStream_t s) {
-  if (count == 0) return;
-  hipLaunchKernelGGL(k_chol_inv, dim3(count), dim3(WG), 0, s, d, fail);
+  hipLaunchKernelGGL(k_scatter_values, dim3((nnz + 255) / 256), dim3(256), 0, s, vals, dst, nnz, arena, elim, flag);
 }
 
 // ---------------------------------------------------------------- batched GEMM
