@@ -33,10 +33,11 @@ struct ScaleAp {
   int64_t tmp;
 };
 struct HouseAp {
-  const double* V;    // np x r reflectors, ld np
-  const double* tau;  // r
+  const double* V;    // np x r reflectors, ld np (unit diagonal, zeros above)
+  const double* T;    // r x r upper-triangular factor of Q = I - V T V^T, ld r
   int32_t np, r;
   int64_t slot_p;
+  int64_t tmp;        // 3*np rows of scratch: x, V^T x, T-product
 };
 
 // Device-side view of one step for the apply.

@@ -521,7 +521,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
     // ---- scaling (Sec. 2.5) and sparsification (Sec. 2.6.1)
     sn.rank.assign(nc, -1);
     for (int32_t c = ne; c < nc; ++c) sn.rank[c] = sn.size[c];
-    std::vector<int64_t> sc_off(nc, -1), sd_off(nc, -1), v_off(nc, -1), tau_off(nc, -1);
+    std::vector<int64_t> sc_off(nc, -1), sd_off(nc, -1), v_off(nc, -1), tau_off(nc, -1), t_off(nc, -1);
     std::vector<int32_t> nref(nc, 0);
     HIPCHK(hipEventRecord(ph[3], h->stream));
     HIPCHK(hipEventRecord(ph[4], h->stream));
@@ -593,13 +593,15 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
                                                std::to_string(flags[1]) + " (scaling)");
       }
 
-      // sparsification, colour by colour; A_pn of each interface is cut into
-      // LDS-resident column slabs (one workgroup each)
+      // sparsification, colour by colour.  Interface classes: 0 = A_pn fits the LDS
+      // of one workgroup; 2 = several LDS slabs with barriers (cooperative launch);
+      // 1 = one workgroup with A_pn in a global workspace, only when not even one
+      // column fits the LDS (streaming from L2 is latency bound otherwise).
       std::vector<int64_t> ncols(nc, 0);
       int32_t ncolour = 0;
-      int64_t house_total = 0, gn_total = 0, pc_total = 0;
-      std::vector<int64_t> gn_off(nc, -1), pc_off(nc, -1);
-      std::vector<int32_t> slabS(nc, 0), slabC(nc, 0), nseg(nc, 0);
+      int64_t house_total = 0, ws_total = 0, xch_total = 0, xc_total = 0;
+      std::vector<int64_t> ws_off(nc, -1), xch_off(nc, -1), xc_off(nc, -1);
+      std::vector<int32_t> slabS(nc, 0), slabC(nc, 0), nseg(nc, 0), klass(nc, -1);
       int32_t nmulti = 0;
       for (int32_t p = ne; p < nc; ++p) {
         for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e)
@@ -612,18 +614,24 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
         const int64_t m = sn.size[p];
         const int64_t budget = int64_t(sparsify_lds_limit()) - 64 - 4 * (nseg[p] + 1) - 8 * m;
         const int64_t cfit = budget / (8 * (m + 1) + 4);
-        if (cfit < 1)
-          return set_err(h, SPAND_E_INVALID, "interface of " + std::to_string(m) + " dofs exceeds the LDS of one CU");
         if (ncols[p] <= std::min<int64_t>(cfit, 1024)) {
+          klass[p] = 0;
           slabS[p] = 1;
           slabC[p] = int32_t(ncols[p]);
+        } else if (cfit < 1) {
+          klass[p] = 1;
+          slabS[p] = 1;
+          slabC[p] = int32_t(ncols[p]);
+          ws_off[p] = ws_total;
+          ws_total += (m + 1) * ncols[p] + (ncols[p] + 1) / 2 + 1;
         } else {
+          klass[p] = 2;
           slabC[p] = int32_t(std::min<int64_t>(cfit, 256));
           slabS[p] = int32_t((ncols[p] + slabC[p] - 1) / slabC[p]);
-          gn_off[p] = gn_total;
-          gn_total += ncols[p];
-          pc_off[p] = pc_total;
-          pc_total += m;
+          xch_off[p] = xch_total;
+          xch_total += int64_t(slabS[p]) * (m + 2);
+          xc_off[p] = xc_total;
+          xc_total += slabS[p];
           ++nmulti;
         }
         const int64_t kmax = std::min<int64_t>(sn.size[p], ncols[p]);
@@ -631,11 +639,14 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
         house_total += int64_t(sn.size[p]) * kmax;
         tau_off[p] = house_total;
         house_total += kmax;
+        t_off[p] = house_total;  // compact WY factor T (r x r, r <= kmax)
+        house_total += kmax * kmax;
       }
       if ((st = dalloc(h, sn.house, size_t(house_total) * sizeof(double))) != SPAND_OK) return st;
-      DevBuf gnb, pcb, cntb, curb, nrefb, errb;
-      if ((st = dalloc(h, gnb, size_t(gn_total) * sizeof(double))) != SPAND_OK) return st;
-      if ((st = dalloc(h, pcb, size_t(pc_total) * sizeof(double))) != SPAND_OK) return st;
+      DevBuf wsb, xchb, xcb, cntb, curb, nrefb, errb;
+      if ((st = dalloc(h, wsb, size_t(ws_total) * sizeof(double))) != SPAND_OK) return st;
+      if ((st = dalloc(h, xchb, size_t(xch_total) * sizeof(double))) != SPAND_OK) return st;
+      if ((st = dalloc(h, xcb, size_t(xc_total) * sizeof(int32_t))) != SPAND_OK) return st;
       if ((st = dalloc(h, cntb, size_t(std::max(nmulti, 1)) * sizeof(int32_t))) != SPAND_OK) return st;
       HIPCHK(hipMemsetAsync(cntb.p, 0, size_t(std::max(nmulti, 1)) * sizeof(int32_t), h->stream));
       if ((st = dalloc(h, errb, sizeof(int32_t))) != SPAND_OK) return st;
@@ -650,10 +661,10 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       int32_t multi_idx = 0;
       for (int32_t c = 0; c < ncolour; ++c) {
         if (by_colour[c].empty()) continue;
-        for (int pass = 0; pass < 2; ++pass) {  // pass 0: single-slab interfaces; pass 1: multi-slab
+        for (int cls = 0; cls < 3; ++cls) {
           std::vector<int32_t> plist;
           for (int32_t p : by_colour[c])
-            if ((slabS[p] > 1) == (pass == 1)) plist.push_back(p);
+            if (klass[p] == cls) plist.push_back(p);
           size_t pos = 0;
           while (pos < plist.size()) {
             std::vector<SparsDesc> sds;
@@ -661,17 +672,17 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
             std::vector<SlabRef> slabs;
             size_t lds = 0;
             int cap = 0;
-            if (pass == 1) {
+            if (cls == 2) {
               size_t lmax = 0;
-              for (int32_t p : plist) lmax = std::max(lmax, sparsify_lds_bytes(sn.size[p], slabC[p], nseg[p]));
+              for (int32_t p : plist) lmax = std::max(lmax, sparsify_lds_bytes(sn.size[p], slabC[p], nseg[p], false));
               cap = sparsify_max_coresident(lmax);
               lds = lmax;
               if (cap <= 0) return set_err(h, SPAND_E_HIP, "occupancy query for the sparsification kernel failed");
             }
             while (pos < plist.size()) {
               const int32_t p = plist[pos];
-              if (pass == 1 && !slabs.empty() && int(slabs.size()) + slabS[p] > cap) break;
-              if (pass == 1 && slabS[p] > cap)
+              if (cls == 2 && !slabs.empty() && int(slabs.size()) + slabS[p] > cap) break;
+              if (cls == 2 && slabS[p] > cap)
                 return set_err(h, SPAND_E_INVALID, "interface needs more co-resident workgroups than the GPU holds");
               SparsDesc d{};
               d.V = sn.house.as<double>() + v_off[p];
@@ -682,9 +693,10 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
               d.id = p;
               d.S = slabS[p];
               d.C = slabC[p];
-              if (slabS[p] > 1) {
-                d.gnrm = gnb.as<double>() + gn_off[p];
-                d.pivcol = pcb.as<double>() + pc_off[p];
+              if (cls == 1) d.ws = wsb.as<double>() + ws_off[p];
+              if (cls == 2) {
+                d.xch = xchb.as<double>() + xch_off[p];
+                d.xcand = xcb.as<int32_t>() + xc_off[p];
                 d.cnt = cntb.as<int32_t>() + multi_idx++;
               }
               d.seg_begin = int32_t(segs.size());
@@ -706,7 +718,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
               }
               d.seg_end = int32_t(segs.size());
               for (int32_t w = 0; w < slabS[p]; ++w) slabs.push_back(SlabRef{int32_t(sds.size()), w});
-              lds = std::max(lds, sparsify_lds_bytes(d.m, d.C, d.seg_end - d.seg_begin));
+              lds = std::max(lds, sparsify_lds_bytes(d.m, d.C, d.seg_end - d.seg_begin, cls == 1));
               sds.push_back(d);
               ++pos;
             }
@@ -716,7 +728,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
             if ((st = upload(h, sl, slabs)) != SPAND_OK) return st;
             hipError_t le = launch_sparsify(a.as<SparsDesc>(), sl.as<SlabRef>(), int32_t(slabs.size()),
                                             b.as<SegDesc>(), tol, curb.as<int32_t>(), nrefb.as<int32_t>(),
-                                            errb.as<int32_t>(), lds, pass == 1, h->stream);
+                                            errb.as<int32_t>(), lds, cls == 2, cls == 1, h->stream);
             if (le != hipSuccess)
               return set_err(h, SPAND_E_HIP, std::string("sparsification launch: ") + hipGetErrorString(le));
             keep.push_back(std::move(a));
@@ -733,12 +745,22 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       int32_t serr = 0;
       HIPCHK(hipMemcpy(&serr, errb.p, sizeof(int32_t), hipMemcpyDeviceToHost));
       if (serr) return set_err(h, SPAND_E_HIP, "sparsification slab barrier timed out");
+      std::vector<TDesc> tds;
       for (int32_t p = ne; p < nc; ++p)
         if (v_off[p] >= 0) {
           sn.rank[p] = rk[p];
           const int64_t r = nref[p];
           m_F += (2 * int64_t(sn.size[p]) - r + 1) * r / 2 + r;
+          if (r > 4096) return set_err(h, SPAND_E_INVALID, "interface rank above 4096 is not supported");
+          if (r > 0)
+            tds.push_back(TDesc{sn.house.as<double>() + v_off[p], sn.house.as<double>() + tau_off[p],
+                                sn.house.as<double>() + t_off[p], sn.size[p], int32_t(r)});
         }
+      DevBuf dtd;
+      if ((st = upload(h, dtd, tds)) != SPAND_OK) return st;
+      launch_build_t(dtd.as<TDesc>(), int32_t(tds.size()), h->stream);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(h->stream));
     }
     HIPCHK(hipStreamSynchronize(h->stream));
     if (t <= 32) {
@@ -806,7 +828,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       }
       sn.h_scale.clear();
       sn.h_house.clear();
-      int64_t tmp2 = 0;
+      int64_t tmp2 = 0, tmp3 = 0;
       for (int32_t p = ne; p < nc; ++p) {
         if (sc_off[p] >= 0) {
           ScaleAp a{};
@@ -821,14 +843,16 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
         if (v_off[p] >= 0 && nref[p] > 0) {
           HouseAp hp{};
           hp.V = sn.house.as<double>() + v_off[p];
-          hp.tau = sn.house.as<double>() + tau_off[p];
+          hp.T = sn.house.as<double>() + t_off[p];
           hp.np = sn.size[p];
           hp.r = nref[p];
           hp.slot_p = sn.slot_ptr[p];
+          hp.tmp = tmp3;
+          tmp3 += 3 * int64_t(sn.size[p]);
           sn.h_house.push_back(hp);
         }
       }
-      sn.tmp_scale = tmp2;
+      sn.tmp_scale = std::max(tmp2, tmp3);
       sn.nslot_len = int64_t(nslot.size());
       h->max_tmp = std::max(h->max_tmp, std::max(sn.tmp_elim, sn.tmp_scale));
       h->max_gather = std::max(h->max_gather, sn.nslot_len);

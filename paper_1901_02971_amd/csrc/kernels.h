@@ -69,15 +69,17 @@ struct CopyDesc {
 };
 
 // Sparsification of one interface p (Sec. 2.6.1).  A_pn is split into S column
-// slabs of width C, each held in the LDS of one workgroup.  The width of A_pn is
+// slabs of width C.  Slabs live in the LDS of one workgroup each, or (S = 1 only,
+// interfaces too large for one LDS) in a global workspace.  The width of A_pn is
 // known only on the device: a neighbour q sparsified in an earlier colour class
 // has shrunk to its rank, read from cursize[q].
 struct SparsDesc {
   double* V;       // m x min(m, ncols_max) reflectors, column-major, ld m
   double* tau;     // min(m, ncols_max)
   double* diag;    // diagonal block of p (ld ldd), set to I_r on exit
-  double* gnrm;    // ncols_max trailing column norms shared by the slabs (S > 1)
-  double* pivcol;  // m entries: the pivot column shared by the slabs (S > 1)
+  double* ws;      // global slab (m x C), column norms (C) and pivot steps (C ints): global mode
+  double* xch;     // slab exchange (S > 1): S maxima, S candidate norms, S*m staged columns
+  int32_t* xcand;  // S candidate column indices (S > 1)
   int32_t* cnt;    // barrier counter of the slabs (zeroed before the launch)
   int32_t m, ldd, seg_begin, seg_end, id, S, C, pad;
 };
@@ -101,12 +103,21 @@ void launch_set_identity(double* const* diag, const int32_t* n, const int32_t* l
 // stored (0 when no coupled dofs were left and p was not sparsified).  err
 // receives bit 2 if a slab barrier timed out.  Launches with more than one slab
 // per interface are cooperative (all workgroups resident).
-size_t sparsify_lds_bytes(int32_t m, int32_t C, int32_t nseg);
+size_t sparsify_lds_bytes(int32_t m, int32_t C, int32_t nseg, bool global_slab);
 size_t sparsify_lds_limit();
 int sparsify_max_coresident(size_t lds_bytes);
 hipError_t launch_sparsify(const SparsDesc* d, const SlabRef* slabs, int32_t nslab, const SegDesc* seg, double eps,
                            int32_t* cursize, int32_t* nref, int32_t* err, size_t lds_bytes, bool cooperative,
-                           hipStream_t s);
+                           bool global_slab, hipStream_t s);
+
+// Compact WY factor T of the reflectors of one interface (r <= 4096).
+struct TDesc {
+  const double* V;    // m x r, ld m
+  const double* tau;  // r
+  double* T;          // r x r output, ld r
+  int32_t m, r;
+};
+void launch_build_t(const TDesc* d, int32_t count, hipStream_t s);
 
 constexpr int GEMM_TILE = 64;
 

@@ -9,9 +9,9 @@
 //   k_target_fwd  x_n <- x_n - sum_s G_ns x_s     (one workgroup per receiving n,
 //                                                  contributions in ascending s)
 //   k_scale_fwd   x_p <- L_p^{-1} x_p
-//   k_house_fwd   x_p <- Q_p^T x_p                (reflectors in increasing order)
+//   k_house<1>    x_p <- Q_p^T x_p                (compact WY form)
 // Backward sweep (levels 1 -> L), the transposes in reverse order:
-//   k_house_bwd   x_p <- Q_p x_p
+//   k_house<-1>   x_p <- Q_p x_p
 //   k_scale_bwd   x_p <- L_p^{-T} x_p
 //   k_gather      neighbour dofs of every s into a contiguous buffer
 //   k_elim_bwd    x_s <- L_s^{-T} (x_s - G_{N_s s}^T x_{N_s})
@@ -30,104 +30,127 @@ __device__ inline double wsum(double v) {
   return v;
 }
 
-// Blocked triangular solves on a vector segment v (n rows, nr <= RB columns, ld ldv)
-// held in the apply scratch.  L is lower triangular (ld), its CHOL_NB-wide diagonal
-// blocks have the inverses Dinv (block k at k*CHOL_NB^2, ld = block width).
-struct TrsvShared {
-  double part[AW / 64][CHOL_NB][RB];
-  double tb[CHOL_NB][RB];
+// ---------------------------------------------------------------- tile GEMVs
+// Both products stage 64x64 tiles of the matrix in LDS with coalesced loads (lanes
+// run down a column) and compute from LDS.  Thread (t & 63, t >> 6) owns row or
+// column t & 63 of the tile and right-hand sides g and g + 4 (g = t >> 6); `acc`
+// accumulates across calls.
+struct TileShared {
+  double A[64][65];
+  double x[64][RB];
+  double out[64][RB];
 };
 
-// L y = v, in place: y_k = D_k^{-1} (v_k - sum_{l<k} L_kl y_l)
-__device__ void trsv_fwd(const double* __restrict__ L, int ld, const double* __restrict__ Dinv, int n, double* v,
-                         int64_t ldv, int nr, TrsvShared& sh) {
+// acc += A[(r0 + rr) + k*ld] x[k], k < ncols (rows beyond nrows read as zero)
+__device__ void tile_gemv_n(const double* __restrict__ A, int ld, int r0, int nrows, int ncols,
+                            const double* __restrict__ x, int64_t ldx, int nr, TileShared& sh, double acc[2]) {
   const int rr = threadIdx.x & 63, g = threadIdx.x >> 6;
-  for (int kb = 0; kb < n; kb += CHOL_NB) {
-    const int w = min(CHOL_NB, n - kb);
-    double acc[RB];
-#pragma unroll
-    for (int c = 0; c < RB; ++c) acc[c] = 0.0;
+  for (int k0 = 0; k0 < ncols; k0 += 64) {
+    const int kw = min(64, ncols - k0);
+    for (int e = threadIdx.x; e < 64 * 64; e += AW) {
+      const int r = e & 63, k = e >> 6;
+      sh.A[r][k] = (r0 + r < nrows && k < kw) ? A[(r0 + r) + (int64_t)(k0 + k) * ld] : 0.0;
+    }
+    for (int e = threadIdx.x; e < 64 * RB; e += AW) {
+      const int k = e & 63, c = e >> 6;
+      sh.x[k][c] = (k < kw && c < nr) ? x[k0 + k + (int64_t)c * ldx] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int k = 0; k < 64; ++k) {
+      const double a = sh.A[rr][k];
+      acc[0] += a * sh.x[k][g];
+      acc[1] += a * sh.x[k][g + 4];
+    }
+    __syncthreads();
+  }
+}
+
+// acc += sum_{r < nrows} A[r + (c0 + cc)*ld] x[r] for columns c0 + cc < ncols
+__device__ void tile_gemv_t(const double* __restrict__ A, int ld, int c0, int ncols, int nrows,
+                            const double* __restrict__ x, int64_t ldx, int nr, TileShared& sh, double acc[2]) {
+  const int cc = threadIdx.x & 63, g = threadIdx.x >> 6;
+  for (int r0 = 0; r0 < nrows; r0 += 64) {
+    const int rw = min(64, nrows - r0);
+    for (int e = threadIdx.x; e < 64 * 64; e += AW) {
+      const int r = e & 63, k = e >> 6;
+      sh.A[r][k] = (r < rw && c0 + k < ncols) ? A[(r0 + r) + (int64_t)(c0 + k) * ld] : 0.0;
+    }
+    for (int e = threadIdx.x; e < 64 * RB; e += AW) {
+      const int r = e & 63, c = e >> 6;
+      sh.x[r][c] = (r < rw && c < nr) ? x[r0 + r + (int64_t)c * ldx] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int r = 0; r < 64; ++r) {
+      const double a = sh.A[r][cc];
+      acc[0] += a * sh.x[r][g];
+      acc[1] += a * sh.x[r][g + 4];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- triangular solves
+// Blocked solves on a vector segment v (n rows, nr <= RB columns, ld ldv) in the
+// apply scratch.  L is lower triangular (ld); its CHOL_NB-wide diagonal blocks have
+// the inverses Dinv (block k at k*CHOL_NB^2, ld = block width).
+static_assert(CHOL_NB == 64, "tile solves assume 64-wide diagonal blocks");
+
+// L y = v in place: y_k = D_k^{-1} (v_k - L[k, :k] y[:k])
+__device__ void trsv_fwd(const double* __restrict__ L, int ld, const double* __restrict__ Dinv, int n, double* v,
+                         int64_t ldv, int nr, TileShared& sh) {
+  const int rr = threadIdx.x & 63, g = threadIdx.x >> 6;
+  for (int kb = 0; kb < n; kb += 64) {
+    const int w = min(64, n - kb);
+    double acc[2] = {0.0, 0.0};
+    tile_gemv_n(L + kb, ld, 0, w, kb, v, ldv, nr, sh, acc);
     if (rr < w) {
-      const double* Lr = L + kb + rr;
-      for (int k = g; k < kb; k += AW / 64) {
-        const double l = Lr[(int64_t)k * ld];
-#pragma unroll
-        for (int c = 0; c < RB; ++c)
-          if (c < nr) acc[c] += l * v[k + (int64_t)c * ldv];
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < RB; ++c) sh.part[g][rr][c] = acc[c];
-    __syncthreads();
-    if (threadIdx.x < w) {
-      const int i = threadIdx.x;
-#pragma unroll
-      for (int c = 0; c < RB; ++c)
-        if (c < nr)
-          sh.tb[i][c] = v[kb + i + (int64_t)c * ldv] - (sh.part[0][i][c] + sh.part[1][i][c] + sh.part[2][i][c] +
-                                                       sh.part[3][i][c]);
+      sh.out[rr][g] = (g < nr ? v[kb + rr + (int64_t)g * ldv] : 0.0) - acc[0];
+      sh.out[rr][g + 4] = (g + 4 < nr ? v[kb + rr + (int64_t)(g + 4) * ldv] : 0.0) - acc[1];
     }
     __syncthreads();
-    if (threadIdx.x < w) {
-      const int i = threadIdx.x;
-      const double* Dk = Dinv + (int64_t)(kb / CHOL_NB) * CHOL_NB * CHOL_NB;
-      double y[RB];
-#pragma unroll
-      for (int c = 0; c < RB; ++c) y[c] = 0.0;
-      for (int k = 0; k <= i; ++k) {
-        const double dv = Dk[i + k * w];
-#pragma unroll
-        for (int c = 0; c < RB; ++c) y[c] += dv * sh.tb[k][c];
+    if (rr < w) {
+      const double* Dk = Dinv + (int64_t)(kb / 64) * 64 * 64;
+      double y0 = 0.0, y1 = 0.0;
+      for (int k = 0; k <= rr; ++k) {
+        const double dv = Dk[rr + k * w];
+        y0 += dv * sh.out[k][g];
+        y1 += dv * sh.out[k][g + 4];
       }
-#pragma unroll
-      for (int c = 0; c < RB; ++c)
-        if (c < nr) v[kb + i + (int64_t)c * ldv] = y[c];
+      if (g < nr) v[kb + rr + (int64_t)g * ldv] = y0;
+      if (g + 4 < nr) v[kb + rr + (int64_t)(g + 4) * ldv] = y1;
     }
     __threadfence_block();
     __syncthreads();
   }
 }
 
-// L^T x = v, in place: x_k = D_k^{-T} (v_k - sum_{l>k} L_lk^T x_l)
+// L^T x = v in place: x_k = D_k^{-T} (v_k - L[k+1:, k]^T x[k+1:])
 __device__ void trsv_bwd(const double* __restrict__ L, int ld, const double* __restrict__ Dinv, int n, double* v,
-                         int64_t ldv, int nr, TrsvShared& sh) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int nblk = (n + CHOL_NB - 1) / CHOL_NB;
+                         int64_t ldv, int nr, TileShared& sh) {
+  const int cc = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int nblk = (n + 63) / 64;
   for (int bi = nblk - 1; bi >= 0; --bi) {
-    const int kb = bi * CHOL_NB;
-    const int w = min(CHOL_NB, n - kb);
-    for (int cc = wave; cc < w; cc += AW / 64) {
-      double acc[RB];
-#pragma unroll
-      for (int c = 0; c < RB; ++c) acc[c] = 0.0;
-      const double* Lc = L + (int64_t)(kb + cc) * ld;
-      for (int r = kb + w + lane; r < n; r += 64) {
-        const double l = Lc[r];
-#pragma unroll
-        for (int c = 0; c < RB; ++c)
-          if (c < nr) acc[c] += l * v[r + (int64_t)c * ldv];
-      }
-#pragma unroll
-      for (int c = 0; c < RB; ++c) {
-        const double sum = wsum(acc[c]);
-        if (lane == 0 && c < nr) sh.tb[cc][c] = v[kb + cc + (int64_t)c * ldv] - sum;
-      }
+    const int kb = bi * 64;
+    const int w = min(64, n - kb);
+    double acc[2] = {0.0, 0.0};
+    tile_gemv_t(L + kb + w, ld, kb, kb + w, n - kb - w, v + kb + w, ldv, nr, sh, acc);
+    if (cc < w) {
+      sh.out[cc][g] = (g < nr ? v[kb + cc + (int64_t)g * ldv] : 0.0) - acc[0];
+      sh.out[cc][g + 4] = (g + 4 < nr ? v[kb + cc + (int64_t)(g + 4) * ldv] : 0.0) - acc[1];
     }
     __syncthreads();
-    if (threadIdx.x < w) {
-      const int i = threadIdx.x;
-      const double* Dk = Dinv + (int64_t)bi * CHOL_NB * CHOL_NB;
-      double x[RB];
-#pragma unroll
-      for (int c = 0; c < RB; ++c) x[c] = 0.0;
-      for (int q = i; q < w; ++q) {
-        const double dv = Dk[q + i * w];
-#pragma unroll
-        for (int c = 0; c < RB; ++c) x[c] += dv * sh.tb[q][c];
+    if (cc < w) {
+      const double* Dk = Dinv + (int64_t)bi * 64 * 64;
+      double x0 = 0.0, x1 = 0.0;
+      for (int q = cc; q < w; ++q) {
+        const double dv = Dk[q + cc * w];
+        x0 += dv * sh.out[q][g];
+        x1 += dv * sh.out[q][g + 4];
       }
-#pragma unroll
-      for (int c = 0; c < RB; ++c)
-        if (c < nr) v[kb + i + (int64_t)c * ldv] = x[c];
+      if (g < nr) v[kb + cc + (int64_t)g * ldv] = x0;
+      if (g + 4 < nr) v[kb + cc + (int64_t)(g + 4) * ldv] = x1;
     }
     __threadfence_block();
     __syncthreads();
@@ -145,9 +168,10 @@ __device__ inline void scatter_seg(const int32_t* sl, int n, const ApplyArgs& a,
     for (int r = threadIdx.x; r < n; r += AW) a.x[sl[r] + (int64_t)c * a.ldx] = a.tmp[off + r + (int64_t)c * a.ldt];
 }
 
+// ---------------------------------------------------------------- sweep kernels
 // y_s = L_s^{-1} x_s; y_s stays in the scratch for the target updates and replaces x_s.
 __global__ void __launch_bounds__(AW) k_elim_fwd(const ElimAp* __restrict__ ds, ApplyArgs a) {
-  __shared__ TrsvShared sh;
+  __shared__ TileShared sh;
   const ElimAp e = ds[blockIdx.x];
   const int32_t* sl = a.slot + e.slot_s;
   gather_seg(sl, e.ns, a, e.tmp);
@@ -156,36 +180,31 @@ __global__ void __launch_bounds__(AW) k_elim_fwd(const ElimAp* __restrict__ ds, 
   scatter_seg(sl, e.ns, a, e.tmp);
 }
 
+// x_n -= sum_s G_ns y_s over the contributions of n in ascending s
 __global__ void __launch_bounds__(AW) k_target_fwd(const TargetAp* __restrict__ ts, const TargetContrib* __restrict__ cs,
                                                    ApplyArgs a) {
+  __shared__ TileShared sh;
   const TargetAp t = ts[blockIdx.x];
   const int32_t* sl = a.slot + t.slot_n;
-  for (int c0 = 0; c0 < a.nrhs; c0 += RB) {
-    const int nr = min(RB, a.nrhs - c0);
-    for (int r = threadIdx.x; r < t.nn; r += AW) {
-      double acc[RB];
-#pragma unroll
-      for (int c = 0; c < RB; ++c) acc[c] = 0.0;
+  const int rr = threadIdx.x & 63, g = threadIdx.x >> 6;
+  for (int r0 = 0; r0 < t.nn; r0 += 64)
+    for (int c0 = 0; c0 < a.nrhs; c0 += RB) {
+      const int nr = min(RB, a.nrhs - c0);
+      double acc[2] = {0.0, 0.0};
       for (int q = t.cbeg; q < t.cend; ++q) {
         const TargetContrib tc = cs[q];
-        const double* y = a.tmp + tc.tmp_s + (int64_t)c0 * a.ldt;
-        for (int k = 0; k < tc.ns; ++k) {
-          const double g = tc.G[r + (int64_t)k * tc.ldG];
-#pragma unroll
-          for (int c = 0; c < RB; ++c)
-            if (c < nr) acc[c] += g * y[k + (int64_t)c * a.ldt];
-        }
+        tile_gemv_n(tc.G, tc.ldG, r0, t.nn, tc.ns, a.tmp + tc.tmp_s + (int64_t)c0 * a.ldt, a.ldt, nr, sh, acc);
       }
-      double* xp = a.x + sl[r] + (int64_t)c0 * a.ldx;
-#pragma unroll
-      for (int c = 0; c < RB; ++c)
-        if (c < nr) xp[(int64_t)c * a.ldx] -= acc[c];
+      if (r0 + rr < t.nn) {
+        double* xp = a.x + sl[r0 + rr] + (int64_t)c0 * a.ldx;
+        if (g < nr) xp[(int64_t)g * a.ldx] -= acc[0];
+        if (g + 4 < nr) xp[(int64_t)(g + 4) * a.ldx] -= acc[1];
+      }
     }
-  }
 }
 
 __global__ void __launch_bounds__(AW) k_scale_fwd(const ScaleAp* __restrict__ ds, ApplyArgs a) {
-  __shared__ TrsvShared sh;
+  __shared__ TileShared sh;
   const ScaleAp e = ds[blockIdx.x];
   const int32_t* sl = a.slot + e.slot_p;
   gather_seg(sl, e.np, a, e.tmp);
@@ -195,7 +214,7 @@ __global__ void __launch_bounds__(AW) k_scale_fwd(const ScaleAp* __restrict__ ds
 }
 
 __global__ void __launch_bounds__(AW) k_scale_bwd(const ScaleAp* __restrict__ ds, ApplyArgs a) {
-  __shared__ TrsvShared sh;
+  __shared__ TileShared sh;
   const ScaleAp e = ds[blockIdx.x];
   const int32_t* sl = a.slot + e.slot_p;
   gather_seg(sl, e.np, a, e.tmp);
@@ -204,54 +223,69 @@ __global__ void __launch_bounds__(AW) k_scale_bwd(const ScaleAp* __restrict__ ds
   scatter_seg(sl, e.np, a, e.tmp);
 }
 
-// Householder sweep over the r reflectors of Q_p (V column-major, ld np, unit
-// diagonal and zeros above); dir = +1 applies Q^T (increasing), -1 applies Q.
+// Q_p in compact WY form, Q = I - V T V^T (T upper triangular r x r):
+// DIR = +1 applies Q^T = I - V T^T V^T, DIR = -1 applies Q.  Scratch of p:
+// [x: np][w: np][u: np] per right-hand side.
 template <int DIR>
 __global__ void __launch_bounds__(AW) k_house(const HouseAp* __restrict__ ds, ApplyArgs a) {
+  __shared__ TileShared sh;
   const HouseAp e = ds[blockIdx.x];
-  const int np = e.np;
+  const int np = e.np, r = e.r;
   const int32_t* sl = a.slot + e.slot_p;
-  __shared__ double red[AW / 64][RB];
-  __shared__ double w[RB];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int cc = threadIdx.x & 63, g = threadIdx.x >> 6;
+  gather_seg(sl, np, a, e.tmp);
+  double* xs = a.tmp + e.tmp;
+  double* ws = xs + np;
+  double* us = ws + np;
   for (int c0 = 0; c0 < a.nrhs; c0 += RB) {
     const int nr = min(RB, a.nrhs - c0);
-    for (int jj = 0; jj < e.r; ++jj) {
-      const int j = DIR > 0 ? jj : e.r - 1 - jj;
-      const double* v = e.V + (int64_t)j * np;
-      double acc[RB];
-#pragma unroll
-      for (int c = 0; c < RB; ++c) acc[c] = 0.0;
-      for (int i = j + threadIdx.x; i < np; i += AW) {
-        const double vi = v[i];
-        const double* xp = a.x + sl[i] + (int64_t)c0 * a.ldx;
-#pragma unroll
-        for (int c = 0; c < RB; ++c)
-          if (c < nr) acc[c] += vi * xp[(int64_t)c * a.ldx];
+    const int64_t co = (int64_t)c0 * a.ldt;
+    for (int j0 = 0; j0 < r; j0 += 64) {  // w = V^T x
+      double acc[2] = {0.0, 0.0};
+      tile_gemv_t(e.V, np, j0, r, np, xs + co, a.ldt, nr, sh, acc);
+      if (j0 + cc < r) {
+        if (g < nr) ws[co + j0 + cc + (int64_t)g * a.ldt] = acc[0];
+        if (g + 4 < nr) ws[co + j0 + cc + (int64_t)(g + 4) * a.ldt] = acc[1];
       }
-#pragma unroll
-      for (int c = 0; c < RB; ++c) {
-        const double s = wsum(acc[c]);
-        if (lane == 0) red[wave][c] = s;
-      }
-      __syncthreads();
-      if (threadIdx.x < RB) {
-        double s = 0.0;
-        for (int q = 0; q < AW / 64; ++q) s += red[q][threadIdx.x];
-        w[threadIdx.x] = e.tau[j] * s;
-      }
-      __syncthreads();
-      for (int i = j + threadIdx.x; i < np; i += AW) {
-        const double vi = v[i];
-        double* xp = a.x + sl[i] + (int64_t)c0 * a.ldx;
-#pragma unroll
-        for (int c = 0; c < RB; ++c)
-          if (c < nr) xp[(int64_t)c * a.ldx] -= w[c] * vi;
-      }
-      __threadfence_block();
-      __syncthreads();
     }
+    __threadfence_block();
+    __syncthreads();
+    for (int j = cc; j < r; j += 64) {  // u = T^T w (DIR > 0) or T w (DIR < 0)
+      double u0 = 0.0, u1 = 0.0;
+      const double* w0 = ws + co + (int64_t)g * a.ldt;        // valid when g < nr
+      const double* w1 = ws + co + (int64_t)(g + 4) * a.ldt;  // valid when g + 4 < nr
+      const bool h0 = g < nr, h1 = g + 4 < nr;
+      if (DIR > 0) {
+        const double* Tj = e.T + (int64_t)j * r;
+        for (int i = 0; i <= j; ++i) {
+          const double tv = Tj[i];
+          if (h0) u0 += tv * w0[i];
+          if (h1) u1 += tv * w1[i];
+        }
+      } else {
+        for (int i = j; i < r; ++i) {
+          const double tv = e.T[j + (int64_t)i * r];
+          if (h0) u0 += tv * w0[i];
+          if (h1) u1 += tv * w1[i];
+        }
+      }
+      if (g < nr) us[co + j + (int64_t)g * a.ldt] = u0;
+      if (g + 4 < nr) us[co + j + (int64_t)(g + 4) * a.ldt] = u1;
+    }
+    __threadfence_block();
+    __syncthreads();
+    for (int r0 = 0; r0 < np; r0 += 64) {  // x -= V u
+      double acc[2] = {0.0, 0.0};
+      tile_gemv_n(e.V, np, r0, np, r, us + co, a.ldt, nr, sh, acc);
+      if (r0 + cc < np) {
+        if (g < nr) xs[co + r0 + cc + (int64_t)g * a.ldt] -= acc[0];
+        if (g + 4 < nr) xs[co + r0 + cc + (int64_t)(g + 4) * a.ldt] -= acc[1];
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
   }
+  scatter_seg(sl, np, a, e.tmp);
 }
 
 __global__ void k_gather(const int32_t* __restrict__ nslot, int64_t len, ApplyArgs a) {
@@ -261,32 +295,24 @@ __global__ void k_gather(const int32_t* __restrict__ nslot, int64_t len, ApplyAr
   for (int c = 0; c < a.nrhs; ++c) a.gbuf[q + (int64_t)c * a.ldg] = a.x[s + (int64_t)c * a.ldx];
 }
 
-// t_k = x_s[k] - sum_r G[r][k] xN[r] (wave per k), then x_s = L_s^{-T} t.
+// t = x_s - G_{N_s s}^T x_{N_s}, then x_s = L_s^{-T} t
 __global__ void __launch_bounds__(AW) k_elim_bwd(const ElimAp* __restrict__ ds, ApplyArgs a) {
-  __shared__ TrsvShared sh;
+  __shared__ TileShared sh;
   const ElimAp e = ds[blockIdx.x];
-  const int ns = e.ns, nN = e.nN;
+  const int ns = e.ns;
   const int32_t* sl = a.slot + e.slot_s;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int cc = threadIdx.x & 63, g = threadIdx.x >> 6;
   for (int c0 = 0; c0 < a.nrhs; c0 += RB) {
     const int nr = min(RB, a.nrhs - c0);
-    for (int k = wave; k < ns; k += AW / 64) {
-      double acc[RB];
-#pragma unroll
-      for (int c = 0; c < RB; ++c) acc[c] = 0.0;
-      const double* Gk = e.G + (int64_t)k * e.ld;
-      for (int r = lane; r < nN; r += 64) {
-        const double g = Gk[r];
-        const double* xp = a.gbuf + e.slot_N + r + (int64_t)c0 * a.ldg;
-#pragma unroll
-        for (int c = 0; c < RB; ++c)
-          if (c < nr) acc[c] += g * xp[(int64_t)c * a.ldg];
-      }
-#pragma unroll
-      for (int c = 0; c < RB; ++c) {
-        const double v = wsum(acc[c]);
-        if (lane == 0 && c < nr)
-          a.tmp[e.tmp + k + (int64_t)(c0 + c) * a.ldt] = a.x[sl[k] + (int64_t)(c0 + c) * a.ldx] - v;
+    for (int k0 = 0; k0 < ns; k0 += 64) {
+      double acc[2] = {0.0, 0.0};
+      tile_gemv_t(e.G, e.ld, k0, ns, e.nN, a.gbuf + e.slot_N + (int64_t)c0 * a.ldg, a.ldg, nr, sh, acc);
+      const int k = k0 + cc;
+      if (k < ns) {
+        if (g < nr)
+          a.tmp[e.tmp + k + (int64_t)(c0 + g) * a.ldt] = a.x[sl[k] + (int64_t)(c0 + g) * a.ldx] - acc[0];
+        if (g + 4 < nr)
+          a.tmp[e.tmp + k + (int64_t)(c0 + g + 4) * a.ldt] = a.x[sl[k] + (int64_t)(c0 + g + 4) * a.ldx] - acc[1];
       }
     }
   }

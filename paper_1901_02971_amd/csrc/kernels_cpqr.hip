@@ -4,16 +4,20 @@
 // Interface p couples its m dofs to ncols neighbour dofs through A_pn (m x ncols).
 // Its columns are cut into S slabs of C columns; workgroup w holds slab w in LDS
 // (row-major, m x C).  Step j of Householder QR with column pivoting:
-//   1. every slab publishes the exact norms of its remaining columns (rows j..m-1,
-//      recomputed from the updated entries, never downdated);
-//   2. after a barrier every workgroup picks the same pivot: among the columns
-//      whose norm is within a relative 1e-10 of the largest, the smallest column
-//      index; stop when |R_jj| < eps |R_00|;
-//   3. the owner of the pivot column publishes it; after a second barrier every
-//      workgroup forms the reflector (LAPACK dlarfg convention, identical
-//      arithmetic everywhere) and applies it to its own remaining columns.
+//   1. every slab finds the largest exact norm of its remaining columns (rows
+//      j..m-1, recomputed from the updated entries, never downdated) and, after a
+//      barrier, the global largest;
+//   2. each slab stages its first column within a relative 1e-10 of that maximum;
+//      after a second barrier every workgroup takes the smallest such column index
+//      as the pivot; stop when |R_jj| < eps |R_00|;
+//   3. every workgroup forms the reflector from the staged pivot column (LAPACK
+//      dlarfg convention, identical arithmetic everywhere) and applies it to its
+//      own remaining columns.
+// Interfaces too large for one LDS but moderate in size use one workgroup with the
+// slab in a global workspace (no barriers).
 // Columns are not swapped: a column pivoted at step j keeps R_0j..R_jj in rows
-// 0..j of its slab.  At the end every slab writes W_cn = R[:r, :] P^T straight
+// 0..j of its slab.  With S > 1 the slabs exchange only their largest norm, their
+// first candidate column and its entries.  At the end every slab writes W_cn = R[:r, :] P^T straight
 // into the blocks of p, and workgroup 0 stores the reflectors, sets A_cc = I and
 // publishes the rank.  With S = 1 the barriers reduce to __syncthreads.
 #include <hip/hip_runtime.h>
@@ -27,6 +31,7 @@ namespace spand {
 #define CW 256
 #define TIE_RTOL 1e-10
 #define SPIN_LIMIT (1L << 22)
+#define T_MAX_R 4096
 
 namespace {
 
@@ -99,24 +104,42 @@ __device__ inline double shared_load(const double* p) {
 
 }  // namespace
 
+template <bool GLOBAL>
 __global__ void __launch_bounds__(CW) k_sparsify(const SparsDesc* __restrict__ descs, const SlabRef* __restrict__ slabs,
                                                  const SegDesc* __restrict__ segs, double eps, int32_t* cursize,
                                                  int32_t* nref, int32_t* err) {
   extern __shared__ double lds[];
   __shared__ double red[CW / 64];
   __shared__ int redi[CW / 64];
-  __shared__ double sh_beta, sh_tau, sh_scale;
+  __shared__ double sh_beta, sh_tau, sh_scale, sh_pn;
+  __shared__ int sh_piv, sh_owner;
   const SlabRef sr = slabs[blockIdx.x];
   const SparsDesc d = descs[sr.desc];
   const int m = d.m, S = d.S, C = d.C, w = sr.w;
   const int nseg = d.seg_end - d.seg_begin;
   const SegDesc* sg = segs + d.seg_begin;
-  double* slab = lds;                       // m x C, row-major
-  double* nrm = slab + (size_t)m * C;       // C
-  double* vbuf = nrm + C;                   // m
-  int* colstep = reinterpret_cast<int*>(vbuf + m);  // C: step at which a column was pivoted
-  int* segoff = colstep + C;                // nseg + 1
+  double* slab;  // m x C, row-major
+  double* nrm;   // C: squared norms of the remaining columns (rows j..m-1)
+  int* colstep;  // C: step at which a column was pivoted (-1 remaining, -2 absent)
+  double* vbuf;  // m
+  int* segoff;   // nseg + 1
+  if (GLOBAL) {
+    slab = d.ws;
+    nrm = d.ws + (size_t)m * C;
+    colstep = reinterpret_cast<int*>(nrm + C);
+    vbuf = lds;
+    segoff = reinterpret_cast<int*>(vbuf + m);
+  } else {
+    slab = lds;
+    nrm = slab + (size_t)m * C;
+    vbuf = nrm + C;
+    colstep = reinterpret_cast<int*>(vbuf + m);
+    segoff = colstep + C;
+  }
   const int tid = threadIdx.x;
+  double* xmax = d.xch;           // S
+  double* xnrm = d.xch + S;       // S
+  double* xcol = d.xch + 2 * S;   // S * m
 
   // column layout of A_pn from the neighbours' current sizes
   if (tid == 0) {
@@ -152,6 +175,7 @@ __global__ void __launch_bounds__(CW) k_sparsify(const SparsDesc* __restrict__ d
       slab[(size_t)r * C + (a + cc - c0)] = v;
     }
   }
+  if (GLOBAL) __threadfence_block();
   __syncthreads();
   for (int lc = tid; lc < C; lc += CW) {
     double s = -1.0;
@@ -164,53 +188,69 @@ __global__ void __launch_bounds__(CW) k_sparsify(const SparsDesc* __restrict__ d
     }
     nrm[lc] = s;
     colstep[lc] = (lc < nloc) ? -1 : -2;
-    if (S > 1 && lc < nloc) d.gnrm[c0 + lc] = s;
   }
+  if (GLOBAL) __threadfence_block();
   const int kmax = min(m, nc);
   int r = kmax;
   double r00 = 0.0;
   int bar = 0;
   for (int j = 0; j < kmax; ++j) {
-    if (S > 1) slab_barrier(d.cnt, ++bar * S, err);
-    else __syncthreads();
-    // ---- pivot
+    __syncthreads();
+    // ---- pivot: largest norm over all slabs, then the smallest column index within
+    //      TIE_RTOL of it
     double lmax = 0.0;
+    for (int lc = tid; lc < nloc; lc += CW)
+      if (colstep[lc] == -1) lmax = fmax(lmax, sqrt(nrm[lc]));
+    double gmax = bmax(lmax, red);
     if (S > 1) {
-      for (int c = tid; c < nc; c += CW) {
-        const double g = shared_load(d.gnrm + c);
-        if (g >= 0.0) lmax = fmax(lmax, sqrt(g));
-      }
-    } else {
-      for (int lc = tid; lc < nloc; lc += CW)
-        if (colstep[lc] == -1) lmax = fmax(lmax, sqrt(nrm[lc]));
+      if (tid == 0) xmax[w] = gmax;
+      slab_barrier(d.cnt, ++bar * S, err);
+      double g = 0.0;
+      for (int q = tid; q < S; q += CW) g = fmax(g, shared_load(xmax + q));
+      gmax = bmax(g, red);
     }
-    const double gmax = bmax(lmax, red);
     const double thr = gmax * (1.0 - TIE_RTOL);
     int lidx = 0x7fffffff;
+    for (int lc = tid; lc < nloc; lc += CW)
+      if (colstep[lc] == -1 && sqrt(nrm[lc]) >= thr) { lidx = c0 + lc; break; }
+    const int cand = bmini(lidx, redi);
     if (S > 1) {
-      for (int c = tid; c < nc; c += CW) {
-        const double g = shared_load(d.gnrm + c);
-        if (g >= 0.0 && sqrt(g) >= thr) { lidx = c; break; }
+      if (cand < nc) {  // stage this slab's candidate column
+        for (int i = j + tid; i < m; i += CW) xcol[(size_t)w * m + i] = slab[(size_t)i * C + (cand - c0)];
+        if (tid == 0) xnrm[w] = nrm[cand - c0];
       }
+      if (tid == 0) d.xcand[w] = cand;
+      slab_barrier(d.cnt, ++bar * S, err);
+      if (tid == 0) {
+        int best = 0x7fffffff, own = -1;
+        for (int q = 0; q < S; ++q) {
+          const int c = __hip_atomic_load(d.xcand + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (c < best) { best = c; own = q; }
+        }
+        sh_piv = best;
+        sh_owner = own;
+        sh_pn = (own >= 0 && best < nc) ? sqrt(shared_load(xnrm + own)) : 0.0;
+      }
+      __syncthreads();
     } else {
-      for (int lc = tid; lc < nloc; lc += CW)
-        if (colstep[lc] == -1 && sqrt(nrm[lc]) >= thr) { lidx = c0 + lc; break; }
+      if (tid == 0) {
+        sh_piv = cand;
+        sh_owner = 0;
+        sh_pn = (cand < nc) ? sqrt(nrm[cand - c0]) : 0.0;
+      }
+      __syncthreads();
     }
-    const int piv = bmini(lidx, redi);
+    const int piv = sh_piv, owner = sh_owner;
     if (piv >= nc) { r = j; break; }  // only non-finite norms left
-    const double pn = (S > 1) ? sqrt(shared_load(d.gnrm + piv)) : sqrt(nrm[piv - c0]);
+    const double pn = sh_pn;
     if (j == 0) {
       r00 = pn;
       if (r00 == 0.0) { r = 0; break; }
     }
     if (pn < eps * r00) { r = j; break; }
-    const int owner = piv / C;
     // ---- pivot column rows j..m-1 into vbuf
     if (S > 1) {
-      if (owner == w)
-        for (int i = j + tid; i < m; i += CW) d.pivcol[i] = slab[(size_t)i * C + (piv - c0)];
-      slab_barrier(d.cnt, ++bar * S, err);
-      for (int i = j + tid; i < m; i += CW) vbuf[i] = shared_load(d.pivcol + i);
+      for (int i = j + tid; i < m; i += CW) vbuf[i] = shared_load(xcol + (size_t)owner * m + i);
     } else {
       for (int i = j + tid; i < m; i += CW) vbuf[i] = slab[(size_t)i * C + (piv - c0)];
     }
@@ -246,9 +286,9 @@ __global__ void __launch_bounds__(CW) k_sparsify(const SparsDesc* __restrict__ d
       if (tid == 0) {
         colstep[lc] = j;
         nrm[lc] = -1.0;
-        if (S > 1) d.gnrm[piv] = -1.0;
       }
     }
+    if (GLOBAL) __threadfence_block();
     __syncthreads();
     // ---- apply H_j to the remaining columns of this slab; recompute their norms
     for (int lc = tid; lc < nloc; lc += CW) {
@@ -264,8 +304,8 @@ __global__ void __launch_bounds__(CW) k_sparsify(const SparsDesc* __restrict__ d
         s += x * x;
       }
       nrm[lc] = s;
-      if (S > 1) d.gnrm[c0 + lc] = s;
     }
+    if (GLOBAL) __threadfence_block();
   }
   __syncthreads();
   // ---- W_cn = R[:r, :] (column order of A_pn) into the blocks of p
@@ -298,21 +338,74 @@ __global__ void __launch_bounds__(CW) k_sparsify(const SparsDesc* __restrict__ d
   }
 }
 
-size_t sparsify_lds_bytes(int32_t m, int32_t C, int32_t nseg) {
+// Compact WY factor of Q = H_0 ... H_{r-1} = I - V T V^T (T upper triangular):
+// T_jj = tau_j, T[:j, j] = -tau_j T[:j, :j] (V[:, :j]^T v_j).  One workgroup per
+// interface; the strict upper part of T first holds V^T V.
+__global__ void __launch_bounds__(CW) k_build_t(const TDesc* __restrict__ descs) {
+  const TDesc d = descs[blockIdx.x];
+  const int m = d.m, r = d.r;
+  __shared__ double y[T_MAX_R];
+  const int64_t npair = (int64_t)r * (r - 1) / 2;
+  for (int64_t q = threadIdx.x; q < npair; q += CW) {  // pair (i, j), i < j, packed by columns
+    int j = (int)((1.0 + sqrt(1.0 + 8.0 * (double)q)) * 0.5);
+    while ((int64_t)j * (j - 1) / 2 > q) --j;
+    while ((int64_t)(j + 1) * j / 2 <= q) ++j;
+    const int i = (int)(q - (int64_t)j * (j - 1) / 2);
+    const double* vi = d.V + (int64_t)i * m;
+    const double* vj = d.V + (int64_t)j * m;
+    double s = vi[j];  // v_j[j] = 1
+    for (int k = j + 1; k < m; ++k) s += vi[k] * vj[k];
+    d.T[i + (int64_t)j * r] = s;
+  }
+  __threadfence_block();
+  __syncthreads();
+  for (int j = 0; j < r; ++j) {
+    const double tj = d.tau[j];
+    // T[i][j] = -tau_j sum_{l=i}^{j-1} T[i][l] Y[l][j]; Y[:j, j] is staged in LDS
+    // before column j is overwritten (r <= T_MAX_R, checked by the host)
+    if (j > 0) {
+      for (int i = threadIdx.x; i < j; i += CW) y[i] = d.T[i + (int64_t)j * r];
+      __syncthreads();
+      for (int i = threadIdx.x; i < j; i += CW) {
+        double s = 0.0;
+        for (int l = i; l < j; ++l) s += d.T[i + (int64_t)l * r] * y[l];
+        d.T[i + (int64_t)j * r] = -tj * s;
+      }
+    }
+    if (threadIdx.x == 0) d.T[j + (int64_t)j * r] = tj;
+    __threadfence_block();
+    __syncthreads();
+  }
+}
+
+void launch_build_t(const TDesc* d, int32_t count, hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_build_t, dim3(count), dim3(CW), 0, s, d);
+}
+
+size_t sparsify_lds_bytes(int32_t m, int32_t C, int32_t nseg, bool global_slab) {
+  if (global_slab) return size_t(m) * sizeof(double) + (size_t(nseg) + 1) * sizeof(int32_t) + 64;
   return (size_t(m) * C + C + m) * sizeof(double) + (size_t(C) + nseg + 1) * sizeof(int32_t) + 64;
 }
 
 size_t sparsify_lds_limit() { return 150 * 1024; }
 
+namespace {
+void set_lds_attr() {
+  static bool done = false;
+  if (done) return;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sparsify<false>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(sparsify_lds_limit()));
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sparsify<true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(sparsify_lds_limit()));
+  done = true;
+}
+}  // namespace
+
 int sparsify_max_coresident(size_t lds_bytes) {
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sparsify),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, int(sparsify_lds_limit()));
-    attr = true;
-  }
+  set_lds_attr();
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sparsify, CW, lds_bytes) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sparsify<false>, CW, lds_bytes) != hipSuccess) return 0;
   int dev = 0, cus = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -321,15 +414,21 @@ int sparsify_max_coresident(size_t lds_bytes) {
 
 hipError_t launch_sparsify(const SparsDesc* d, const SlabRef* slabs, int32_t nslab, const SegDesc* seg, double eps,
                            int32_t* cursize, int32_t* nref, int32_t* err, size_t lds_bytes, bool cooperative,
-                           hipStream_t s) {
+                           bool global_slab, hipStream_t s) {
   if (nslab == 0) return hipSuccess;
-  (void)sparsify_max_coresident(lds_bytes);  // sets the dynamic-LDS attribute once
+  set_lds_attr();
+  if (global_slab) {
+    hipLaunchKernelGGL(k_sparsify<true>, dim3(nslab), dim3(CW), lds_bytes, s, d, slabs, seg, eps, cursize, nref,
+                       err);
+    return hipGetLastError();
+  }
   if (!cooperative) {
-    hipLaunchKernelGGL(k_sparsify, dim3(nslab), dim3(CW), lds_bytes, s, d, slabs, seg, eps, cursize, nref, err);
+    hipLaunchKernelGGL(k_sparsify<false>, dim3(nslab), dim3(CW), lds_bytes, s, d, slabs, seg, eps, cursize, nref,
+                       err);
     return hipGetLastError();
   }
   void* args[] = {(void*)&d, (void*)&slabs, (void*)&seg, (void*)&eps, (void*)&cursize, (void*)&nref, (void*)&err};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_sparsify), dim3(nslab), dim3(CW), args,
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_sparsify<false>), dim3(nslab), dim3(CW), args,
                                     (unsigned int)lds_bytes, s);
 }
 
