@@ -65,6 +65,7 @@ struct spand_ctx {
   int device = -1;
   std::vector<spand::StepNum> num;
   spand::DevBuf d_rowptr, d_colind, d_values;  // CSR of A for the SpMV
+  spand::DevBuf d_dst1;                         // step-1 destination of every CSR entry (pattern-only)
   int64_t max_tmp = 0;                          // doubles per RHS for apply scratch
   int64_t max_gather = 0;                       // doubles per RHS for gathered neighbours
   // PCG / apply scratch, grown on demand

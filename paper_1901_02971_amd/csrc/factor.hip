@@ -353,9 +353,13 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
     double* A = arena.as<double>();
     if (lay.total_elim) HIPCHK(hipMemsetAsync(E, 0, size_t(lay.total_elim) * sizeof(double), h->stream));
     if (lay.total_arena) HIPCHK(hipMemsetAsync(A, 0, size_t(lay.total_arena) * sizeof(double), h->stream));
-    DevBuf d_dst, d_copy;
+    DevBuf d_copy;
     std::vector<CopyDesc> copies;
-    if (t == 1) {
+    if (t == 1 && h->d_dst1.p) {
+      // the step-1 layout depends on the pattern only: reuse the map of an earlier factor
+      launch_scatter_values(values, h->d_dst1.as<int64_t>(), int64_t(an.colind.size()), A, E, d_nonfinite, h->stream);
+      HIPCHK(hipGetLastError());
+    } else if (t == 1) {
       // destination of every CSR entry inside the step-1 panels: >= 0 arena offset,
       // <= -2 elimination-buffer offset -(d+2), -1 skipped (upper triangle)
       std::vector<int32_t> cl(an.n), pos(an.n);
@@ -373,8 +377,8 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
           const int64_t off = lay.base[j] + lay.find(i, j) + pos[v] + int64_t(pos[u]) * lay.H[j];
           dst[e] = (j < ne) ? -(off + 2) : off;
         }
-      if ((st = upload(h, d_dst, dst)) != SPAND_OK) return st;
-      launch_scatter_values(values, d_dst.as<int64_t>(), int64_t(dst.size()), A, E, d_nonfinite, h->stream);
+      if ((st = upload(h, h->d_dst1, dst)) != SPAND_OK) return st;
+      launch_scatter_values(values, h->d_dst1.as<int64_t>(), int64_t(dst.size()), A, E, d_nonfinite, h->stream);
       HIPCHK(hipGetLastError());
     } else {
       const StepNum& pv = h->num[t - 2];
@@ -625,13 +629,14 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
           ws_off[p] = ws_total;
           ws_total += (m + 1) * ncols[p] + (ncols[p] + 1) / 2 + 1;
         } else {
+          // as few slabs as the LDS allows: the slab barrier costs grow with their number
           klass[p] = 2;
-          slabC[p] = int32_t(std::min<int64_t>(cfit, 256));
+          slabC[p] = int32_t(std::min<int64_t>(cfit, 512));
           slabS[p] = int32_t((ncols[p] + slabC[p] - 1) / slabC[p]);
           xch_off[p] = xch_total;
-          xch_total += int64_t(slabS[p]) * (m + 2);
+          xch_total += 3 * int64_t(slabS[p]) * (m + 2);  // three exchange buffers
           xc_off[p] = xc_total;
-          xc_total += slabS[p];
+          xc_total += 3 * slabS[p];
           ++nmulti;
         }
         const int64_t kmax = std::min<int64_t>(sn.size[p], ncols[p]);
@@ -665,6 +670,10 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
           std::vector<int32_t> plist;
           for (int32_t p : by_colour[c])
             if (klass[p] == cls) plist.push_back(p);
+          // similar sizes in one launch: ranks (step counts) then match within a chunk
+          std::stable_sort(plist.begin(), plist.end(), [&](int32_t x, int32_t y) {
+            return int64_t(sn.size[x]) * ncols[x] > int64_t(sn.size[y]) * ncols[y];
+          });
           size_t pos = 0;
           while (pos < plist.size()) {
             std::vector<SparsDesc> sds;

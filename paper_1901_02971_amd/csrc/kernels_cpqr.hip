@@ -47,33 +47,6 @@ __device__ inline int wmini(int v) {
   for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
   return v;
 }
-__device__ inline double bsum(double v, double* red) {
-  v = wsum(v);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int q = 0; q < CW / 64; ++q) s += red[q];
-  return s;
-}
-__device__ inline double bmax(double v, double* red) {
-  v = wmax(v);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double s = red[0];
-  for (int q = 1; q < CW / 64; ++q) s = fmax(s, red[q]);
-  return s;
-}
-__device__ inline int bmini(int v, int* red) {
-  v = wmini(v);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  int s = red[0];
-  for (int q = 1; q < CW / 64; ++q) s = min(s, red[q]);
-  return s;
-}
 
 // Barrier among the S workgroups of one interface: a monotone counter; barrier
 // number b completes when the counter reaches b*S.  Bounded spin: on time-out the
@@ -104,14 +77,51 @@ __device__ inline double shared_load(const double* p) {
 
 }  // namespace
 
+// Block reductions with four rotating LDS slots: one __syncthreads each.  A slot
+// is reused only four reductions later, after at least three intervening barriers.
+struct RedSlots {
+  double d[4][CW / 64];
+  int i[4][CW / 64];
+};
+__device__ inline double rmax(double v, RedSlots& rs, int& k) {
+  v = wmax(v);
+  double* r = rs.d[k & 3];
+  ++k;
+  if ((threadIdx.x & 63) == 0) r[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = r[0];
+  for (int q = 1; q < CW / 64; ++q) s = fmax(s, r[q]);
+  return s;
+}
+__device__ inline double rsum(double v, RedSlots& rs, int& k) {
+  v = wsum(v);
+  double* r = rs.d[k & 3];
+  ++k;
+  if ((threadIdx.x & 63) == 0) r[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int q = 0; q < CW / 64; ++q) s += r[q];
+  return s;
+}
+__device__ inline int rmini(int v, RedSlots& rs, int& k) {
+  v = wmini(v);
+  int* r = rs.i[k & 3];
+  ++k;
+  if ((threadIdx.x & 63) == 0) r[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int s = r[0];
+  for (int q = 1; q < CW / 64; ++q) s = min(s, r[q]);
+  return s;
+}
+
 template <bool GLOBAL>
 __global__ void __launch_bounds__(CW) k_sparsify(const SparsDesc* __restrict__ descs, const SlabRef* __restrict__ slabs,
                                                  const SegDesc* __restrict__ segs, double eps, int32_t* cursize,
                                                  int32_t* nref, int32_t* err) {
   extern __shared__ double lds[];
-  __shared__ double red[CW / 64];
-  __shared__ int redi[CW / 64];
-  __shared__ double sh_beta, sh_tau, sh_scale, sh_pn;
+  __shared__ RedSlots rs;
+  __shared__ double redc[2][CW / 64][64];
+  __shared__ double sh_pn;
   __shared__ int sh_piv, sh_owner;
   const SlabRef sr = slabs[blockIdx.x];
   const SparsDesc d = descs[sr.desc];
@@ -137,9 +147,11 @@ __global__ void __launch_bounds__(CW) k_sparsify(const SparsDesc* __restrict__ d
     segoff = colstep + C;
   }
   const int tid = threadIdx.x;
-  double* xmax = d.xch;           // S
-  double* xnrm = d.xch + S;       // S
-  double* xcol = d.xch + 2 * S;   // S * m
+  int rk = 0;  // reduction slot counter
+  // Slab exchange: three buffers of [S maxima | S candidate norms | S*m staged
+  // columns] and S candidate indices.  Buffer (j & 1) serves step j (a slab can be
+  // one step ahead of another, never two) and buffer 2 the near-tie second round.
+  auto xbuf = [&](int b) { return d.xch + (size_t)b * S * (m + 2); };
 
   // column layout of A_pn from the neighbours' current sizes
   if (tid == 0) {
@@ -190,48 +202,91 @@ __global__ void __launch_bounds__(CW) k_sparsify(const SparsDesc* __restrict__ d
     colstep[lc] = (lc < nloc) ? -1 : -2;
   }
   if (GLOBAL) __threadfence_block();
+  __syncthreads();
   const int kmax = min(m, nc);
   int r = kmax;
   double r00 = 0.0;
   int bar = 0;
   for (int j = 0; j < kmax; ++j) {
-    __syncthreads();
-    // ---- pivot: largest norm over all slabs, then the smallest column index within
-    //      TIE_RTOL of it
+    // ---- pivot.  Rule: among all remaining columns whose norm is within TIE_RTOL of
+    // the largest, the smallest column index.
     double lmax = 0.0;
     for (int lc = tid; lc < nloc; lc += CW)
       if (colstep[lc] == -1) lmax = fmax(lmax, sqrt(nrm[lc]));
-    double gmax = bmax(lmax, red);
-    if (S > 1) {
-      if (tid == 0) xmax[w] = gmax;
-      slab_barrier(d.cnt, ++bar * S, err);
-      double g = 0.0;
-      for (int q = tid; q < S; q += CW) g = fmax(g, shared_load(xmax + q));
-      gmax = bmax(g, red);
-    }
-    const double thr = gmax * (1.0 - TIE_RTOL);
+    lmax = rmax(lmax, rs, rk);
     int lidx = 0x7fffffff;
-    for (int lc = tid; lc < nloc; lc += CW)
-      if (colstep[lc] == -1 && sqrt(nrm[lc]) >= thr) { lidx = c0 + lc; break; }
-    const int cand = bmini(lidx, redi);
+    {
+      const double lthr = lmax * (1.0 - TIE_RTOL);
+      for (int lc = tid; lc < nloc; lc += CW)
+        if (colstep[lc] == -1 && sqrt(nrm[lc]) >= lthr) { lidx = c0 + lc; break; }
+    }
+    int cand = rmini(lidx, rs, rk);
+    int xb = 0;  // exchange buffer holding the pivot column
     if (S > 1) {
-      if (cand < nc) {  // stage this slab's candidate column
+      // publish (slab max, first column within the window of the slab max, its
+      // norm and entries); one barrier
+      xb = j & 1;
+      double* xmax = xbuf(xb);
+      double* xnrm = xmax + S;
+      double* xcol = xmax + 2 * S;
+      int* xcand = d.xcand + (size_t)xb * S;
+      if (cand < nc)
         for (int i = j + tid; i < m; i += CW) xcol[(size_t)w * m + i] = slab[(size_t)i * C + (cand - c0)];
-        if (tid == 0) xnrm[w] = nrm[cand - c0];
+      if (tid == 0) {
+        xmax[w] = lmax;
+        xcand[w] = cand;
+        xnrm[w] = (cand < nc) ? sqrt(nrm[cand - c0]) : 0.0;
       }
-      if (tid == 0) d.xcand[w] = cand;
       slab_barrier(d.cnt, ++bar * S, err);
       if (tid == 0) {
+        double gmax = 0.0;
+        for (int q = 0; q < S; ++q) gmax = fmax(gmax, shared_load(xmax + q));
+        const double thr = gmax * (1.0 - TIE_RTOL);
         int best = 0x7fffffff, own = -1;
+        bool ambiguous = false;
         for (int q = 0; q < S; ++q) {
-          const int c = __hip_atomic_load(d.xcand + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if (c < best) { best = c; own = q; }
+          const int c = __hip_atomic_load(xcand + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (c >= nc) continue;
+          if (shared_load(xnrm + q) >= thr) {
+            if (c < best) { best = c; own = q; }
+          } else if (shared_load(xmax + q) >= thr) {
+            ambiguous = true;  // the slab's first column at the global threshold lies further on
+          }
         }
-        sh_piv = best;
+        sh_piv = ambiguous ? -1 : best;
         sh_owner = own;
-        sh_pn = (own >= 0 && best < nc) ? sqrt(shared_load(xnrm + own)) : 0.0;
+        sh_pn = ambiguous ? gmax : ((own >= 0) ? shared_load(xnrm + own) : 0.0);
       }
       __syncthreads();
+      if (sh_piv == -1) {  // second round with the exact global threshold (near-ties across slabs)
+        const double thr = sh_pn * (1.0 - TIE_RTOL);
+        xb = 2;
+        double* xnrm2 = xbuf(2) + S;
+        double* xcol2 = xbuf(2) + 2 * S;
+        int* xcand2 = d.xcand + 2 * (size_t)S;
+        int l2 = 0x7fffffff;
+        for (int lc = tid; lc < nloc; lc += CW)
+          if (colstep[lc] == -1 && sqrt(nrm[lc]) >= thr) { l2 = c0 + lc; break; }
+        const int c2 = rmini(l2, rs, rk);
+        if (c2 < nc)
+          for (int i = j + tid; i < m; i += CW) xcol2[(size_t)w * m + i] = slab[(size_t)i * C + (c2 - c0)];
+        if (tid == 0) {
+          xcand2[w] = c2;
+          xnrm2[w] = (c2 < nc) ? sqrt(nrm[c2 - c0]) : 0.0;
+        }
+        slab_barrier(d.cnt, ++bar * S, err);
+        if (tid == 0) {
+          int best = 0x7fffffff, own = -1;
+          for (int q = 0; q < S; ++q) {
+            const int c = __hip_atomic_load(xcand2 + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (c < best) { best = c; own = q; }
+          }
+          sh_piv = best;
+          sh_owner = own;
+          sh_pn = (own >= 0 && best < nc) ? shared_load(xnrm2 + own) : 0.0;
+        }
+        __syncthreads();
+      }
     } else {
       if (tid == 0) {
         sh_piv = cand;
@@ -248,41 +303,32 @@ __global__ void __launch_bounds__(CW) k_sparsify(const SparsDesc* __restrict__ d
       if (r00 == 0.0) { r = 0; break; }
     }
     if (pn < eps * r00) { r = j; break; }
-    // ---- pivot column rows j..m-1 into vbuf
+    // ---- pivot column rows j..m-1 into vbuf; reflector (dlarfg convention)
     if (S > 1) {
+      const double* xcol = xbuf(xb) + 2 * S;
       for (int i = j + tid; i < m; i += CW) vbuf[i] = shared_load(xcol + (size_t)owner * m + i);
     } else {
       for (int i = j + tid; i < m; i += CW) vbuf[i] = slab[(size_t)i * C + (piv - c0)];
     }
     __syncthreads();
-    // ---- reflector (dlarfg convention)
     const double alpha = vbuf[j];
     double part = 0.0;
     for (int i = j + 1 + tid; i < m; i += CW) part += vbuf[i] * vbuf[i];
-    const double xn2 = bsum(part, red);
-    if (tid == 0) {
-      if (xn2 == 0.0) {
-        sh_tau = 0.0; sh_beta = alpha; sh_scale = 0.0;
-      } else {
-        const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-        sh_tau = (beta - alpha) / beta;
-        sh_beta = beta;
-        sh_scale = 1.0 / (alpha - beta);
-      }
+    const double xn2 = rsum(part, rs, rk);
+    double tau, scale, beta;
+    if (xn2 == 0.0) {
+      tau = 0.0; beta = alpha; scale = 0.0;
+    } else {
+      beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+      tau = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
     }
-    __syncthreads();
-    const double tau = sh_tau, scale = sh_scale;
+    __syncthreads();  // everyone has read vbuf[j] and the pivot column
     for (int i = j + 1 + tid; i < m; i += CW) vbuf[i] *= scale;
     if (tid == 0) vbuf[j] = 1.0;
-    __syncthreads();
-    if (w == 0) {
-      double* V = d.V + (int64_t)j * m;
-      for (int i = tid; i < m; i += CW) V[i] = (i < j) ? 0.0 : vbuf[i];
-      if (tid == 0) d.tau[j] = tau;
-    }
     if (owner == w) {
       const int lc = piv - c0;
-      for (int i = j + tid; i < m; i += CW) slab[(size_t)i * C + lc] = (i == j) ? sh_beta : 0.0;
+      for (int i = j + tid; i < m; i += CW) slab[(size_t)i * C + lc] = (i == j) ? beta : 0.0;
       if (tid == 0) {
         colstep[lc] = j;
         nrm[lc] = -1.0;
@@ -290,22 +336,68 @@ __global__ void __launch_bounds__(CW) k_sparsify(const SparsDesc* __restrict__ d
     }
     if (GLOBAL) __threadfence_block();
     __syncthreads();
+    if (w == 0) {
+      double* V = d.V + (int64_t)j * m;
+      for (int i = tid; i < m; i += CW) V[i] = (i < j) ? 0.0 : vbuf[i];
+      if (tid == 0) d.tau[j] = tau;
+    }
     // ---- apply H_j to the remaining columns of this slab; recompute their norms
-    for (int lc = tid; lc < nloc; lc += CW) {
-      if (colstep[lc] != -1) continue;
-      double dot = slab[(size_t)j * C + lc];
-      for (int i = j + 1; i < m; ++i) dot += vbuf[i] * slab[(size_t)i * C + lc];
-      const double wv = tau * dot;
-      slab[(size_t)j * C + lc] -= wv;
-      double s = 0.0;
-      for (int i = j + 1; i < m; ++i) {
-        const double x = slab[(size_t)i * C + lc] - wv * vbuf[i];
-        slab[(size_t)i * C + lc] = x;
-        s += x * x;
+    if (m <= 64) {  // short columns: one thread per column
+      for (int lc = tid; lc < nloc; lc += CW) {
+        if (colstep[lc] != -1) continue;
+        double dot = slab[(size_t)j * C + lc];
+        for (int i = j + 1; i < m; ++i) dot += vbuf[i] * slab[(size_t)i * C + lc];
+        const double wv = tau * dot;
+        slab[(size_t)j * C + lc] -= wv;
+        double s = 0.0;
+        for (int i = j + 1; i < m; ++i) {
+          const double x = slab[(size_t)i * C + lc] - wv * vbuf[i];
+          slab[(size_t)i * C + lc] = x;
+          s += x * x;
+        }
+        nrm[lc] = s;
       }
-      nrm[lc] = s;
+    } else {  // tall columns: 64 columns per pass, the 4 waves split the rows
+      const int lane = tid & 63, wv4 = tid >> 6;
+      for (int t0 = 0; t0 < nloc; t0 += 64) {
+        const int lc = t0 + lane;
+        const bool act = lc < nloc && colstep[lc] == -1;
+        double d0 = 0.0, d1 = 0.0;
+        if (act) {
+          int i = j + wv4;
+          for (; i + 4 < m; i += 8) {
+            d0 += vbuf[i] * slab[(size_t)i * C + lc];
+            d1 += vbuf[i + 4] * slab[(size_t)(i + 4) * C + lc];
+          }
+          if (i < m) d0 += vbuf[i] * slab[(size_t)i * C + lc];
+        }
+        redc[0][wv4][lane] = d0 + d1;
+        __syncthreads();
+        const double wvv = tau * (redc[0][0][lane] + redc[0][1][lane] + redc[0][2][lane] + redc[0][3][lane]);
+        double s0 = 0.0, s1 = 0.0;
+        if (act) {
+          int i = j + wv4;
+          for (; i + 4 < m; i += 8) {
+            const double x0 = slab[(size_t)i * C + lc] - wvv * vbuf[i];
+            const double x1 = slab[(size_t)(i + 4) * C + lc] - wvv * vbuf[i + 4];
+            slab[(size_t)i * C + lc] = x0;
+            slab[(size_t)(i + 4) * C + lc] = x1;
+            if (i > j) s0 += x0 * x0;
+            s1 += x1 * x1;
+          }
+          if (i < m) {
+            const double x0 = slab[(size_t)i * C + lc] - wvv * vbuf[i];
+            slab[(size_t)i * C + lc] = x0;
+            if (i > j) s0 += x0 * x0;
+          }
+        }
+        redc[1][wv4][lane] = s0 + s1;
+        __syncthreads();
+        if (act && wv4 == 0) nrm[lc] = redc[1][0][lane] + redc[1][1][lane] + redc[1][2][lane] + redc[1][3][lane];
+      }
     }
     if (GLOBAL) __threadfence_block();
+    __syncthreads();
   }
   __syncthreads();
   // ---- W_cn = R[:r, :] (column order of A_pn) into the blocks of p
