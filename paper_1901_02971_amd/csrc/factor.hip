@@ -272,7 +272,7 @@ spand_status left_trsm(spand_ctx* h, const std::vector<LeftBlock>& B) {
 spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int32_t skip, spand_prec prec) {
   Analysis& an = h->an;
   const int32_t Lv = an.levels;
-  const int gemm_prec = (prec == SPAND_FP64) ? 0 : 1;
+  const int gemm_prec = (prec == SPAND_FP64) ? 0 : (prec == SPAND_FP32 ? 1 : 2);
   h->num.clear();
   h->num.resize(Lv);
   h->max_tmp = 0;

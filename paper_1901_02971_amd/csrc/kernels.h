@@ -94,6 +94,9 @@ struct SlabRef {
 // dst >= 0: arena[dst]; dst <= -2: elim[-dst - 2]; dst == -1: skipped.
 void launch_scatter_values(const double* vals, const int64_t* dst, int64_t nnz, double* arena, double* elim,
                            int32_t* flag, hipStream_t s);
+// Batched GEMM over 64x64 output tiles on the matrix cores (kernels_mfma.hip);
+// prec: 0 FP64, 1 FP32, 2 BF16x3.  Carries the trailing updates of the blocked
+// Cholesky, the SYRK of the Schur update (Sec. 2.4) and the left scaling (Sec. 2.5).
 void launch_gemm(const GemmDesc* d, const TileRef* tiles, int64_t ntiles, int prec, hipStream_t s);
 void launch_reduce(const ReduceDesc* d, int32_t count, const ContribDesc* c, hipStream_t s);
 void launch_copy(const CopyDesc* d, int64_t count, hipStream_t s);

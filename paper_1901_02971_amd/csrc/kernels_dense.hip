@@ -1,8 +1,5 @@
 // Dense batched kernels of the factorization (gfx950, wave64).
 //
-//  * k_gemm       batched variable-size GEMM over a flat list of 64x64 output tiles;
-//                 carries the trailing updates of the blocked Cholesky, the SYRK of
-//                 the Schur update (Sec. 2.4) and the left scaling of Sec. 2.5.
 //  * k_reduce     deterministic Schur-complement accumulation: every target block
 //                 subtracts its contributions in ascending eliminated-cluster order.
 //  * k_copy       strided (optionally transposed) block copies for the merge (Sec. 2.7).
@@ -77,93 +74,6 @@ void launch_scatter_values(const double* vals, const int64_t* dst, int64_t nnz, 
                            int32_t* flag, hipStream_t s) {
   if (nnz == 0) return;
   hipLaunchKernelGGL(k_scatter_values, dim3((nnz + 255) / 256), dim3(256), 0, s, vals, dst, nnz, arena, elim, flag);
-}
-
-// ---------------------------------------------------------------- batched GEMM
-// 64x64 output tile per workgroup, 256 threads as 16x16, 4x4 outputs each
-// (rows ty + 16*a, columns tx + 16*b), K staged through LDS 16 at a time.
-// prec 0: FP64 multiply-add; prec 1: operands rounded to FP32, FP32 products and
-// FP32 accumulation (the result is stored to the FP64 target).
-template <typename T>
-__global__ void __launch_bounds__(WG) k_gemm(const GemmDesc* __restrict__ descs, const TileRef* __restrict__ tiles) {
-  constexpr int BM = 64, BN = 64, BK = 16;
-  __shared__ T As[BK][BM + 1];
-  __shared__ T Bs[BK][BN + 1];
-  const TileRef tr = tiles[blockIdx.x];
-  const GemmDesc d = descs[tr.desc];
-  const int m0 = tr.tm * BM, n0 = tr.tn * BN;
-  const bool ta = d.flags & G_TA, tb = d.flags & G_TB;
-  int kmax = d.K;
-  if (d.flags & G_TRIA) kmax = min(kmax, m0 + BM);
-  if (d.flags & G_TRIB) kmax = min(kmax, n0 + BN);
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  T acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
-  for (int k0 = 0; k0 < kmax; k0 += BK) {
-    // load op(A)[m0:m0+64, k0:k0+16] and op(B)[k0:k0+16, n0:n0+64]
-#pragma unroll
-    for (int q = 0; q < (BM * BK) / WG; ++q) {
-      const int e = threadIdx.x + q * WG;
-      int mm, kk;
-      if (!ta) { mm = e & 63; kk = e >> 6; } else { kk = e & 15; mm = e >> 4; }
-      const int gm = m0 + mm, gk = k0 + kk;
-      double v = 0.0;
-      if (gm < d.M && gk < kmax && !((d.flags & G_TRIA) && gk > gm))
-        v = ta ? d.A[gk + (int64_t)gm * d.lda] : d.A[gm + (int64_t)gk * d.lda];
-      As[kk][mm] = T(v);
-    }
-#pragma unroll
-    for (int q = 0; q < (BN * BK) / WG; ++q) {
-      const int e = threadIdx.x + q * WG;
-      int nn, kk;
-      if (!tb) { kk = e & 15; nn = e >> 4; } else { nn = e & 63; kk = e >> 6; }
-      const int gn = n0 + nn, gk = k0 + kk;
-      double v = 0.0;
-      if (gn < d.N && gk < kmax && !((d.flags & G_TRIB) && gk > gn))
-        v = tb ? d.B[gn + (int64_t)gk * d.ldb] : d.B[gk + (int64_t)gn * d.ldb];
-      Bs[kk][nn] = T(v);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < BK; ++kk) {
-      T a[4], b[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        a[q] = As[kk][ty + 16 * q];
-        b[q] = Bs[kk][tx + 16 * q];
-      }
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[p][q] = fma(a[p], b[q], acc[p][q]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    const int gm = m0 + ty + 16 * p;
-    if (gm >= d.M) continue;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int gn = n0 + tx + 16 * q;
-      if (gn >= d.N) continue;
-      double* c = d.C + gm + (int64_t)gn * d.ldc;
-      double v = d.alpha * (double)acc[p][q];
-      if (d.beta != 0.0) v += d.beta * (*c);
-      *c = v;
-    }
-  }
-}
-
-void launch_gemm(const GemmDesc* d, const TileRef* tiles, int64_t ntiles, int prec, hipStream_t s) {
-  if (ntiles == 0) return;
-  if (prec == 0)
-    hipLaunchKernelGGL(k_gemm<double>, dim3(ntiles), dim3(WG), 0, s, d, tiles);
-  else
-    hipLaunchKernelGGL(k_gemm<float>, dim3(ntiles), dim3(WG), 0, s, d, tiles);
 }
 
 // ---------------------------------------------------------------- Schur reduce

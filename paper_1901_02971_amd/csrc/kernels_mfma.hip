@@ -1,0 +1,203 @@
+// Batched variable-size GEMM on the CDNA4 matrix cores.
+//
+// Descriptor/tile queue built by the host: one 64x64 output tile per workgroup of 4
+// waves; wave (wm, wn) owns the 32x32 quadrant (wm, wn) as 2x2 blocks of 16x16
+// MFMA outputs.  Operand tiles are staged k-major in LDS so that the 16 lanes
+// reading one fragment touch consecutive addresses.
+//
+//   MODE 0  FP64 operands, v_mfma_f64_16x16x4f64, FP64 accumulation
+//   MODE 1  operands rounded to FP32, v_mfma_f32_16x16x4f32, FP32 accumulation
+//   MODE 2  BF16x3: each FP32-rounded operand is split a = hi + lo (hi = bf16(a),
+//           lo = bf16(a - hi)); a*b ~ hi*hi + hi*lo + lo*hi with
+//           v_mfma_f32_16x16x32_bf16, FP32 accumulation (the split product of
+//           Henry, Tang and Heinecke, ARITH 2019)
+//
+// Lane layout of the 16x16 blocks (lane l, 0..63): A fragment row l%16, k-group
+// l/16; B fragment column l%16, k-group l/16; accumulator layout in store_block.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "kernels.h"
+
+namespace spand {
+
+#define MW 256
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+
+namespace {
+
+__device__ inline double load_a(const GemmDesc& d, int gm, int gk, int kmax) {
+  if (gm >= d.M || gk >= kmax || ((d.flags & G_TRIA) && gk > gm)) return 0.0;
+  return (d.flags & G_TA) ? d.A[gk + (int64_t)gm * d.lda] : d.A[gm + (int64_t)gk * d.lda];
+}
+__device__ inline double load_b(const GemmDesc& d, int gk, int gn, int kmax) {
+  if (gn >= d.N || gk >= kmax || ((d.flags & G_TRIB) && gk > gn)) return 0.0;
+  return (d.flags & G_TB) ? d.B[gn + (int64_t)gk * d.ldb] : d.B[gk + (int64_t)gn * d.ldb];
+}
+
+// Global -> LDS index of element q (0..64*BK) of a 64 x BK operand tile, chosen so
+// that consecutive threads read consecutive global addresses.
+__device__ inline void tile_index(bool trans_major, int q, int BK, int& mm, int& kk) {
+  if (!trans_major) { mm = q & 63; kk = q >> 6; } else { kk = q % BK; mm = q / BK; }
+}
+
+// Accumulator entry i of lane l sits at column l%16 and row 4*(l/16)+i for the
+// FP32-accumulating instructions but at row l/16+4*i for v_mfma_f64_16x16x4f64
+// (both measured on gfx950).
+template <bool F64, typename C4>
+__device__ inline void store_block(const GemmDesc& d, int row0, int col0, const C4& acc) {
+  const int lane = threadIdx.x & 63;
+  const int gn = col0 + (lane & 15);
+  if (gn >= d.N) return;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int gm = row0 + (F64 ? (lane >> 4) + 4 * i : 4 * (lane >> 4) + i);
+    if (gm >= d.M) continue;
+    double* c = d.C + gm + (int64_t)gn * d.ldc;
+    double v = d.alpha * (double)acc[i];
+    if (d.beta != 0.0) v += d.beta * (*c);
+    *c = v;
+  }
+}
+
+}  // namespace
+
+// MODE 0 / 1: K staged 16 at a time, four k=4 MFMA steps per stage.
+template <int MODE>
+__global__ void __launch_bounds__(MW) k_gemm_mfma(const GemmDesc* __restrict__ descs,
+                                                  const TileRef* __restrict__ tiles) {
+  typedef typename std::conditional<MODE == 0, double, float>::type T;
+  typedef typename std::conditional<MODE == 0, d4_t, f4_t>::type C4;
+  constexpr int BK = 16;
+  __shared__ T As[BK][64 + 1];
+  __shared__ T Bs[BK][64 + 1];
+  const TileRef tr = tiles[blockIdx.x];
+  const GemmDesc d = descs[tr.desc];
+  const int m0 = tr.tm * 64, n0 = tr.tn * 64;
+  int kmax = d.K;
+  if (d.flags & G_TRIA) kmax = min(kmax, m0 + 64);
+  if (d.flags & G_TRIB) kmax = min(kmax, n0 + 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  C4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = C4{0, 0, 0, 0};
+  const bool ta = d.flags & G_TA, tb = d.flags & G_TB;
+  for (int k0 = 0; k0 < kmax; k0 += BK) {
+#pragma unroll
+    for (int q = threadIdx.x; q < 64 * BK; q += MW) {
+      int mm, kk;
+      tile_index(ta, q, BK, mm, kk);
+      As[kk][mm] = (T)load_a(d, m0 + mm, k0 + kk, kmax);
+      int nn, kb;
+      tile_index(!tb, q, BK, nn, kb);
+      Bs[kb][nn] = (T)load_b(d, k0 + kb, n0 + nn, kmax);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      const int kk = ks + (lane >> 4);
+      T a[2], b[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        a[q] = As[kk][wm * 32 + q * 16 + (lane & 15)];
+        b[q] = Bs[kk][wn * 32 + q * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          if constexpr (MODE == 0)
+            acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p], b[q], acc[p][q], 0, 0, 0);
+          else
+            acc[p][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[p], b[q], acc[p][q], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) store_block<MODE == 0>(d, m0 + wm * 32 + p * 16, n0 + wn * 32 + q * 16, acc[p][q]);
+}
+
+// MODE 2 (BF16x3): K staged 32 at a time, one k=32 step (three MFMAs) per stage.
+__global__ void __launch_bounds__(MW) k_gemm_bf16x3(const GemmDesc* __restrict__ descs,
+                                                    const TileRef* __restrict__ tiles) {
+  constexpr int BK = 32;
+  constexpr int LDK = BK + 8;  // row pitch in bf16 (80 bytes)
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[64 * LDK], Al[64 * LDK], Bh[64 * LDK], Bl[64 * LDK];
+  const TileRef tr = tiles[blockIdx.x];
+  const GemmDesc d = descs[tr.desc];
+  const int m0 = tr.tm * 64, n0 = tr.tn * 64;
+  int kmax = d.K;
+  if (d.flags & G_TRIA) kmax = min(kmax, m0 + 64);
+  if (d.flags & G_TRIB) kmax = min(kmax, n0 + 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  f4_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f4_t{0, 0, 0, 0};
+  const bool ta = d.flags & G_TA, tb = d.flags & G_TB;
+  for (int k0 = 0; k0 < kmax; k0 += BK) {
+    for (int q = threadIdx.x; q < 64 * BK; q += MW) {
+      int mm, kk;
+      tile_index(ta, q, BK, mm, kk);
+      const float a = (float)load_a(d, m0 + mm, k0 + kk, kmax);
+      const __bf16 ah = (__bf16)a;
+      Ah[mm * LDK + kk] = ah;
+      Al[mm * LDK + kk] = (__bf16)(a - (float)ah);
+      int nn, kb;
+      tile_index(!tb, q, BK, nn, kb);
+      const float b = (float)load_b(d, k0 + kb, n0 + nn, kmax);
+      const __bf16 bh = (__bf16)b;
+      Bh[nn * LDK + kb] = bh;
+      Bl[nn * LDK + kb] = (__bf16)(b - (float)bh);
+    }
+    __syncthreads();
+    const int kof = 8 * (lane >> 4);
+    bf8_t ahi[2], alo[2], bhi[2], blo[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int ra = (wm * 32 + q * 16 + (lane & 15)) * LDK + kof;
+      const int rb = (wn * 32 + q * 16 + (lane & 15)) * LDK + kof;
+      ahi[q] = *reinterpret_cast<const bf8_t*>(Ah + ra);
+      alo[q] = *reinterpret_cast<const bf8_t*>(Al + ra);
+      bhi[q] = *reinterpret_cast<const bf8_t*>(Bh + rb);
+      blo[q] = *reinterpret_cast<const bf8_t*>(Bl + rb);
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        acc[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[p], bhi[q], acc[p][q], 0, 0, 0);
+        acc[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[p], blo[q], acc[p][q], 0, 0, 0);
+        acc[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[p], bhi[q], acc[p][q], 0, 0, 0);
+      }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) store_block<false>(d, m0 + wm * 32 + p * 16, n0 + wn * 32 + q * 16, acc[p][q]);
+}
+
+void launch_gemm(const GemmDesc* d, const TileRef* tiles, int64_t ntiles, int prec, hipStream_t s) {
+  if (ntiles == 0) return;
+  if (prec == 0)
+    hipLaunchKernelGGL(k_gemm_mfma<0>, dim3(ntiles), dim3(MW), 0, s, d, tiles);
+  else if (prec == 1)
+    hipLaunchKernelGGL(k_gemm_mfma<1>, dim3(ntiles), dim3(MW), 0, s, d, tiles);
+  else
+    hipLaunchKernelGGL(k_gemm_bf16x3, dim3(ntiles), dim3(MW), 0, s, d, tiles);
+}
+
+}  // namespace spand

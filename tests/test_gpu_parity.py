@@ -176,3 +176,32 @@ def test_noconv_reports_iterations():
     x, it, rr, st = gpu_solve(s, b, maxit=1, check=False)
     assert st == 3   # SPAND_E_NOCONV
     assert np.all(it == 1) and np.all(rr > 1e-12) and np.all(np.isfinite(x))
+
+
+# ------------------------------------------------------------------ Schur-product precisions
+@pytest.mark.parametrize("prec,bound", [(1, 1e-5), (2, 1e-4)], ids=["fp32", "bf16x3"])
+def test_exact_factorization_reduced_precision(prec, bound):
+    """With eps = 0 the FP32-MFMA and BF16x3 Schur products give an approximate
+    inverse accurate to their precision; FP64 PCG still reaches 1e-12."""
+    p = gridgen.laplacian((10, 9, 8))
+    b = gridgen.rhs(np.random.default_rng(6), p.n, 2)
+    s = gpu_factor(p, 5, 0.0, 0, prec)
+    z = gpu_apply(s, b)
+    x_ref = sla.cho_solve(sla.cho_factor(p.scipy().toarray()), b)
+    err = np.abs(z - x_ref).max() / np.abs(x_ref).max()
+    note(f"prec {prec}: exact-factorization apply error {err:.2e}")
+    assert 1e-14 < err <= bound
+    x, it, rr, _ = gpu_solve(s, b)
+    assert np.all(it <= 3) and np.all(rr <= 1e-12)
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["fp32", "bf16x3"])
+def test_c2_reduced_precision_iterations(prec):
+    """32^3 Laplacian, eps = 1e-2: PCG iteration counts within +-1 of the FP64 oracle."""
+    p, b, L = gridgen.config_problem("c2")
+    an, fac = oracle_run(p, L, 1e-2)
+    _, it_ref, _ = O.pcg(p.scipy(), b, lambda r: O.apply(fac, r))
+    s = gpu_factor(p, L, 1e-2, 0, prec)
+    x, it, rr, _ = gpu_solve(s, b)
+    note(f"c2 prec {prec}: iters {it} oracle {it_ref} relres {rr}")
+    assert np.all(np.abs(it - it_ref) <= 1) and np.all(rr <= 1e-12)
