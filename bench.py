@@ -26,7 +26,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "spaND factor+PCG seconds to 1e-12 residual at 128^3; Schur TFLOP/s vs FP64 form"
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+# MI355X dense MFMA peaks of the Schur products' arithmetic; BF16x3 spends three
+# bf16 products per FP32-equivalent one, so its FP32-equivalent ceiling is 1/3 of bf16.
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3.0}
+# FP64 vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
+FP64_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 HBM_GBS = 8000.0
 
 
@@ -128,19 +132,47 @@ def main():
     tS = float(np.mean([r[1]["t_solve"] for r in recs]))
     st = recs[-1][1]
     it, rr = recs[-1][2], recs[-1][3]
+    fs = [r[0] for r in recs]
+    ss = [r[1] for r in recs]
     schur_flops = st["schur_flops"]
-    schur_s = float(np.mean([r[0]["schur_seconds"] for r in recs]))
+    schur_s = float(np.mean([f["schur_seconds"] for f in fs]))
     schur_tf = schur_flops / schur_s / 1e12 if schur_s > 0 else 0.0
-    roof = {"bound": "mfma", "kernel": "k_gemm (elimination TRSM-by-inverse + SYRK)",
-            "achieved": round(schur_tf, 3), "peak": PEAK_TFLOPS[args.prec], "unit": "TFLOP/s",
-            "frac": round(schur_tf / PEAK_TFLOPS[args.prec], 4), "traffic": None}
+    # per-kernel-class device time (HIP events on the library's stream, summed
+    # over the launches of one step) and algorithmic work per launch
+    cpqr_s = float(np.mean([f["cpqr_seconds"] for f in fs]))
+    cpqr_n = int(fs[-1]["cpqr_launches"])
+    cpqr_tf = fs[-1]["cpqr_flops"] / cpqr_s / 1e12 if cpqr_s > 0 else 0.0
+    apply_s = float(np.mean([x["apply_seconds"] / max(1, x["apply_calls"]) for x in ss]))
+    apply_gbs = ss[-1]["apply_bytes"] / apply_s / 1e9 if apply_s > 0 else 0.0
+    kernels = {
+        "cpqr": {"kernel": "k_sparsify (truncated CPQR of every interface, Sec. 2.6.1)", "bound": "alu",
+                 "launches": cpqr_n, "ms_total": round(cpqr_s * 1e3, 2),
+                 "avg_launch_us": round(cpqr_s / max(cpqr_n, 1) * 1e6, 1),
+                 "flops_per_launch": fs[-1]["cpqr_flops"] / max(cpqr_n, 1),
+                 "achieved": round(cpqr_tf, 4), "peak": round(FP64_VALU_TFLOPS, 1), "unit": "TFLOP/s",
+                 "frac": round(cpqr_tf / FP64_VALU_TFLOPS, 5)},
+        "apply": {"kernel": "preconditioner apply M M^T (Sec. 2.8), all levels", "bound": "hbm",
+                  "calls_per_step": int(ss[-1]["apply_calls"]), "ms_per_apply": round(apply_s * 1e3, 3),
+                  "bytes_per_apply": ss[-1]["apply_bytes"], "achieved": round(apply_gbs, 1), "peak": HBM_GBS,
+                  "unit": "GB/s", "frac": round(apply_gbs / HBM_GBS, 4)},
+        "schur": {"kernel": "elimination phase: blocked Cholesky + MFMA TRSM/SYRK + ordered reduce (Sec. 2.4)",
+                  "bound": "mfma", "ms_total": round(schur_s * 1e3, 2), "flops": schur_flops,
+                  "achieved": round(schur_tf, 3), "peak": round(PEAK_TFLOPS[args.prec], 1), "unit": "TFLOP/s",
+                  "frac": round(schur_tf / PEAK_TFLOPS[args.prec], 4)},
+    }
+    share = {"cpqr": cpqr_s, "apply": apply_s * ss[-1]["apply_calls"], "schur": schur_s}
+    dom = max(share, key=share.get)
+    k = kernels[dom]
+    roof = {"bound": k["bound"], "kernel": k["kernel"], "achieved": k["achieved"], "peak": k["peak"],
+            "unit": k["unit"], "frac": k["frac"], "traffic": None,
+            "seconds_per_step": round(share[dom], 4)}
     out = {"metric": METRIC, "value": round(per, 4), "unit": "s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(per * 1e3, 2), "higher_is_better": False,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.prec == "fp64" else args.prec,
            "data": "synthetic", "config": describe(args.config, p, L, args.tol, nrhs, args.prec),
            "t_P": round(t_P, 3), "t_F": round(tF, 4), "t_S": round(tS, 4),
            "pcg_iters": [int(v) for v in it], "relres_max": float(np.max(rr)), "s_top": int(st["s_top"]),
-           "m_F": int(st["m_F"]), "schur_tflops": round(schur_tf, 3), "roofline": roof}
+           "m_F": int(st["m_F"]), "schur_tflops": round(schur_tf, 3), "roofline": roof, "kernels": kernels}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.tol)
     print(json.dumps(out), flush=True)

@@ -60,8 +60,10 @@ typedef struct {
   int32_t last_iters;    /* max PCG iteration count over the RHS of the last solve */
   int32_t s_top;         /* size of the top separator right before its elimination */
   int64_t m_F;           /* stored factor entries (L_s, G_ns, L_p, Householder) */
-  double schur_flops;    /* algorithmic flops of the elimination TRSM + SYRK */
-  double schur_seconds;  /* summed device time of those kernels (HIP events) */
+  double schur_flops;    /* algorithmic flops of the elimination's Schur products (Sec. 2.4):
+                            sum over eliminated s of |N_s||s|^2 (TRSM) + |N_s|(|N_s|+1)|s| (SYRK) */
+  double schur_seconds;  /* device time of the whole elimination phase (HIP events); it also
+                            holds the pivot-block Cholesky and the ordered Schur reduction */
   int32_t fail_step;     /* on SPAND_E_NOT_SPD: elimination step (1-based) */
   int32_t fail_cluster;  /* ... cluster id within that step */
   int32_t fail_phase;    /* ... 0 = elimination, 1 = scaling */
@@ -72,6 +74,19 @@ typedef struct {
    * and the cumulative stored factor entries after step t. */
   double step_phase_seconds[32][4];
   int64_t step_m_F[32];
+  /* The truncated CPQRs of the last factor (Sec. 2.6.1).  For an interface with an
+   * m x n block A_pn and k Householder steps the algorithmic work is
+   *   sum_{j<k} [2(m-j)(n-j) + 4(m-j)(n-j-1) + 3(m-j)]  (column norms, reflector, update)
+   *   + 2(m-k)(n-k) when it stops before min(m, n)      (the norms that end it). */
+  double cpqr_flops;
+  double cpqr_seconds;    /* summed device time of the CPQR launches (HIP events) */
+  int64_t cpqr_launches;
+  /* The preconditioner applies of the last solve (Sec. 2.8).  Algorithmic HBM bytes
+   * of one apply on nrhs columns: every stored factor entry read twice (forward and
+   * backward sweep, 8 B each) plus the n x nrhs vector read and written per sweep. */
+  double apply_bytes;
+  double apply_seconds;   /* summed device time of the applies (HIP events) */
+  int64_t apply_calls;
 } spand_stats;
 
 /* Ordering, clustering and symbolic factorization (Algorithm 2 with a geometric

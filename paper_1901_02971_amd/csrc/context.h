@@ -34,6 +34,27 @@ struct DevBuf {
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 
+// Reusable HIP events for per-launch device timing.
+struct EventPool {
+  std::vector<hipEvent_t> ev;
+  EventPool() = default;
+  EventPool(const EventPool&) = delete;
+  EventPool& operator=(const EventPool&) = delete;
+  ~EventPool() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+  hipError_t get(size_t i, hipEvent_t* out) {
+    while (ev.size() <= i) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      ev.push_back(e);
+    }
+    *out = ev[i];
+    return hipSuccess;
+  }
+};
+
 struct StepNum {
   std::vector<int32_t> size;    // cluster sizes before elimination
   std::vector<int32_t> rank;    // kept size after sparsification (-1: eliminated)
@@ -68,6 +89,7 @@ struct spand_ctx {
   spand::DevBuf d_dst1;                         // step-1 destination of every CSR entry (pattern-only)
   int64_t max_tmp = 0;                          // doubles per RHS for apply scratch
   int64_t max_gather = 0;                       // doubles per RHS for gathered neighbours
+  spand::EventPool evpool;                      // per-launch timing of CPQR and apply
   // PCG / apply scratch, grown on demand
   spand::DevBuf work;
   size_t work_bytes = 0;

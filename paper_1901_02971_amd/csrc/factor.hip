@@ -22,6 +22,7 @@
 //   5. plan the next step's layout from the ranks.
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cstring>
 #include <numeric>
 
@@ -302,6 +303,8 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
 
   int64_t m_F = 0;
   double elim_flops = 0.0, elim_ms = 0.0;
+  double cpqr_flops = 0.0, cpqr_ms = 0.0;
+  int64_t cpqr_launches = 0;
   int32_t s_top = 0;
 
   DevBuf arena_prev;
@@ -431,7 +434,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       ed_off[s] = ed_total;
       ed_total += dinv_size(sn.size[s]);
       const double ns = sn.size[s], nn = nN[s];
-      elim_flops += ns * ns * ns / 3.0 + nn * ns * ns + nn * (nn + 1.0) * ns;
+      elim_flops += nn * ns * ns + nn * (nn + 1.0) * ns;
       m_F += int64_t(sn.size[s]) * (sn.size[s] + 1) / 2 + int64_t(sn.size[s]) * nN[s];
     }
     if ((st = dalloc(h, sn.edinv, size_t(ed_total) * sizeof(double))) != SPAND_OK) return st;
@@ -597,15 +600,15 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
                                                std::to_string(flags[1]) + " (scaling)");
       }
 
-      // sparsification, colour by colour.  Interface classes: 0 = A_pn fits the LDS
-      // of one workgroup; 2 = several LDS slabs with barriers (cooperative launch);
-      // 1 = one workgroup with A_pn in a global workspace, only when not even one
-      // column fits the LDS (streaming from L2 is latency bound otherwise).
+      // sparsification, colour by colour.  A_pn of interface p lives in the registers
+      // of slabS[p] workgroups with tg[p] lanes per column.  Interfaces of one slab go
+      // in one plain launch per team size; interfaces of several slabs go in
+      // cooperative launches of at most the co-resident number of workgroups.
       std::vector<int64_t> ncols(nc, 0);
       int32_t ncolour = 0;
-      int64_t house_total = 0, ws_total = 0, xch_total = 0, xc_total = 0;
-      std::vector<int64_t> ws_off(nc, -1), xch_off(nc, -1), xc_off(nc, -1);
-      std::vector<int32_t> slabS(nc, 0), slabC(nc, 0), nseg(nc, 0), klass(nc, -1);
+      int64_t house_total = 0, xch_total = 0;
+      std::vector<int64_t> xch_off(nc, -1);
+      std::vector<int32_t> slabS(nc, 0), tg(nc, 0), nseg(nc, 0);
       int32_t nmulti = 0;
       for (int32_t p = ne; p < nc; ++p) {
         for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e)
@@ -616,27 +619,16 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
         if (sn.size[p] == 0 || ncols[p] == 0) continue;
         ncolour = std::max(ncolour, sy.colour[p] + 1);
         const int64_t m = sn.size[p];
-        const int64_t budget = int64_t(sparsify_lds_limit()) - 64 - 4 * (nseg[p] + 1) - 8 * m;
-        const int64_t cfit = budget / (8 * (m + 1) + 4);
-        if (ncols[p] <= std::min<int64_t>(cfit, 1024)) {
-          klass[p] = 0;
-          slabS[p] = 1;
-          slabC[p] = int32_t(ncols[p]);
-        } else if (cfit < 1) {
-          klass[p] = 1;
-          slabS[p] = 1;
-          slabC[p] = int32_t(ncols[p]);
-          ws_off[p] = ws_total;
-          ws_total += (m + 1) * ncols[p] + (ncols[p] + 1) / 2 + 1;
-        } else {
-          // as few slabs as the LDS allows: the slab barrier costs grow with their number
-          klass[p] = 2;
-          slabC[p] = int32_t(std::min<int64_t>(cfit, 512));
-          slabS[p] = int32_t((ncols[p] + slabC[p] - 1) / slabC[p]);
+        const int32_t G = cpqr_team(sn.size[p]);
+        if (G < 0)
+          return set_err(h, SPAND_E_INVALID, "interface of " + std::to_string(m) +
+                                                 " dofs exceeds the largest CPQR team (2048 rows)");
+        tg[p] = G;
+        const int64_t cap = cpqr_capacity(G);
+        slabS[p] = int32_t((ncols[p] + cap - 1) / cap);
+        if (slabS[p] > 1) {
           xch_off[p] = xch_total;
-          xch_total += 3 * int64_t(slabS[p]) * (m + 2);  // three exchange buffers
-          xc_off[p] = xc_total;
-          xc_total += 3 * slabS[p];
+          xch_total += 3 * int64_t(slabS[p]) * cpqr_record(G);  // three exchange buffers
           ++nmulti;
         }
         const int64_t kmax = std::min<int64_t>(sn.size[p], ncols[p]);
@@ -648,12 +640,13 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
         house_total += kmax * kmax;
       }
       if ((st = dalloc(h, sn.house, size_t(house_total) * sizeof(double))) != SPAND_OK) return st;
-      DevBuf wsb, xchb, xcb, cntb, curb, nrefb, errb;
-      if ((st = dalloc(h, wsb, size_t(ws_total) * sizeof(double))) != SPAND_OK) return st;
+      DevBuf xchb, cntb, curb, nrefb, errb;
       if ((st = dalloc(h, xchb, size_t(xch_total) * sizeof(double))) != SPAND_OK) return st;
-      if ((st = dalloc(h, xcb, size_t(xc_total) * sizeof(int32_t))) != SPAND_OK) return st;
-      if ((st = dalloc(h, cntb, size_t(std::max(nmulti, 1)) * sizeof(int32_t))) != SPAND_OK) return st;
-      HIPCHK(hipMemsetAsync(cntb.p, 0, size_t(std::max(nmulti, 1)) * sizeof(int32_t), h->stream));
+      // one barrier counter per multi-slab interface, 128 bytes apart (no shared lines)
+      constexpr int32_t CNT_PAD = 32;
+      const size_t ncnt = size_t(std::max(nmulti, 1)) * CNT_PAD;
+      if ((st = dalloc(h, cntb, ncnt * sizeof(int32_t))) != SPAND_OK) return st;
+      HIPCHK(hipMemsetAsync(cntb.p, 0, ncnt * sizeof(int32_t), h->stream));
       if ((st = dalloc(h, errb, sizeof(int32_t))) != SPAND_OK) return st;
       HIPCHK(hipMemsetAsync(errb.p, 0, sizeof(int32_t), h->stream));
       // current sizes: interfaces shrink to their rank as their colour class finishes
@@ -664,87 +657,90 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
         if (v_off[p] >= 0) by_colour[sy.colour[p]].push_back(p);
       std::vector<DevBuf> keep;
       int32_t multi_idx = 0;
+      size_t nlaunch = 0;
       for (int32_t c = 0; c < ncolour; ++c) {
         if (by_colour[c].empty()) continue;
-        for (int cls = 0; cls < 3; ++cls) {
-          std::vector<int32_t> plist;
-          for (int32_t p : by_colour[c])
-            if (klass[p] == cls) plist.push_back(p);
-          // similar sizes in one launch: ranks (step counts) then match within a chunk
-          std::stable_sort(plist.begin(), plist.end(), [&](int32_t x, int32_t y) {
-            return int64_t(sn.size[x]) * ncols[x] > int64_t(sn.size[y]) * ncols[y];
-          });
-          size_t pos = 0;
-          while (pos < plist.size()) {
-            std::vector<SparsDesc> sds;
-            std::vector<SegDesc> segs;
-            std::vector<SlabRef> slabs;
+        for (int32_t G = 1; G <= 64; G <<= 1)
+          for (int multi = 0; multi < 2; ++multi) {
+            std::vector<int32_t> plist;
+            for (int32_t p : by_colour[c])
+              if (tg[p] == G && (slabS[p] > 1) == (multi == 1)) plist.push_back(p);
+            if (plist.empty()) continue;
+            // largest first: similar step counts share a launch
+            std::stable_sort(plist.begin(), plist.end(), [&](int32_t x, int32_t y) {
+              return int64_t(sn.size[x]) * ncols[x] > int64_t(sn.size[y]) * ncols[y];
+            });
             size_t lds = 0;
-            int cap = 0;
-            if (cls == 2) {
-              size_t lmax = 0;
-              for (int32_t p : plist) lmax = std::max(lmax, sparsify_lds_bytes(sn.size[p], slabC[p], nseg[p], false));
-              cap = sparsify_max_coresident(lmax);
-              lds = lmax;
-              if (cap <= 0) return set_err(h, SPAND_E_HIP, "occupancy query for the sparsification kernel failed");
+            for (int32_t p : plist) lds = std::max(lds, cpqr_lds_bytes(G, nseg[p]));
+            int cap = INT_MAX;
+            if (multi) {
+              cap = cpqr_max_coresident(G, lds);
+              if (cap <= 0) return set_err(h, SPAND_E_HIP, "occupancy query for the CPQR kernel failed");
             }
+            size_t pos = 0;
             while (pos < plist.size()) {
-              const int32_t p = plist[pos];
-              if (cls == 2 && !slabs.empty() && int(slabs.size()) + slabS[p] > cap) break;
-              if (cls == 2 && slabS[p] > cap)
-                return set_err(h, SPAND_E_INVALID, "interface needs more co-resident workgroups than the GPU holds");
-              SparsDesc d{};
-              d.V = sn.house.as<double>() + v_off[p];
-              d.tau = sn.house.as<double>() + tau_off[p];
-              d.diag = A + lay.base[p];
-              d.ldd = int32_t(lay.H[p]);
-              d.m = sn.size[p];
-              d.id = p;
-              d.S = slabS[p];
-              d.C = slabC[p];
-              if (cls == 1) d.ws = wsb.as<double>() + ws_off[p];
-              if (cls == 2) {
-                d.xch = xchb.as<double>() + xch_off[p];
-                d.xcand = xcb.as<int32_t>() + xc_off[p];
-                d.cnt = cntb.as<int32_t>() + multi_idx++;
-              }
-              d.seg_begin = int32_t(segs.size());
-              for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e) {
-                const int32_t q = sy.nb[e];
-                if (sn.size[q] == 0) continue;
-                SegDesc g{};
-                if (q < p) {  // block (p, q) in panel q
-                  g.blk = A + lay.base[q] + lay.find(p, q);
-                  g.ld = int32_t(lay.H[q]);
-                  g.trans = 0;
-                } else {      // block (q, p) in panel p holds A_pq^T
-                  g.blk = A + lay.base[p] + lay.find(q, p);
-                  g.ld = int32_t(lay.H[p]);
-                  g.trans = 1;
+              std::vector<SparsDesc> sds;
+              std::vector<SegDesc> segs;
+              std::vector<SlabRef> slabs;
+              while (pos < plist.size()) {
+                const int32_t p = plist[pos];
+                if (multi && slabS[p] > cap)
+                  return set_err(h, SPAND_E_INVALID, "interface needs more co-resident workgroups than the GPU holds");
+                if (multi && !slabs.empty() && int64_t(slabs.size()) + slabS[p] > cap) break;
+                SparsDesc d{};
+                d.V = sn.house.as<double>() + v_off[p];
+                d.tau = sn.house.as<double>() + tau_off[p];
+                d.diag = A + lay.base[p];
+                d.ldd = int32_t(lay.H[p]);
+                d.m = sn.size[p];
+                d.id = p;
+                d.S = slabS[p];
+                if (multi) {
+                  d.xch = xchb.as<double>() + xch_off[p];
+                  d.cnt = cntb.as<int32_t>() + size_t(multi_idx++) * CNT_PAD;
                 }
-                g.q = q;
-                segs.push_back(g);
+                d.seg_begin = int32_t(segs.size());
+                for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e) {
+                  const int32_t q = sy.nb[e];
+                  if (sn.size[q] == 0) continue;
+                  SegDesc g{};
+                  if (q < p) {  // block (p, q) in panel q
+                    g.blk = A + lay.base[q] + lay.find(p, q);
+                    g.ld = int32_t(lay.H[q]);
+                    g.trans = 0;
+                  } else {      // block (q, p) in panel p holds A_pq^T
+                    g.blk = A + lay.base[p] + lay.find(q, p);
+                    g.ld = int32_t(lay.H[p]);
+                    g.trans = 1;
+                  }
+                  g.q = q;
+                  segs.push_back(g);
+                }
+                d.seg_end = int32_t(segs.size());
+                for (int32_t w = 0; w < slabS[p]; ++w) slabs.push_back(SlabRef{int32_t(sds.size()), w});
+                sds.push_back(d);
+                ++pos;
               }
-              d.seg_end = int32_t(segs.size());
-              for (int32_t w = 0; w < slabS[p]; ++w) slabs.push_back(SlabRef{int32_t(sds.size()), w});
-              lds = std::max(lds, sparsify_lds_bytes(d.m, d.C, d.seg_end - d.seg_begin, cls == 1));
-              sds.push_back(d);
-              ++pos;
+              DevBuf a, b, sl;
+              if ((st = upload(h, a, sds)) != SPAND_OK) return st;
+              if ((st = upload(h, b, segs)) != SPAND_OK) return st;
+              if ((st = upload(h, sl, slabs)) != SPAND_OK) return st;
+              hipEvent_t e0, e1;
+              HIPCHK(h->evpool.get(2 * nlaunch, &e0));
+              HIPCHK(h->evpool.get(2 * nlaunch + 1, &e1));
+              HIPCHK(hipEventRecord(e0, h->stream));
+              hipError_t le = launch_cpqr(G, a.as<SparsDesc>(), sl.as<SlabRef>(), int32_t(slabs.size()),
+                                          b.as<SegDesc>(), tol, curb.as<int32_t>(), nrefb.as<int32_t>(),
+                                          errb.as<int32_t>(), lds, multi == 1, h->stream);
+              if (le != hipSuccess)
+                return set_err(h, SPAND_E_HIP, std::string("sparsification launch: ") + hipGetErrorString(le));
+              HIPCHK(hipEventRecord(e1, h->stream));
+              ++nlaunch;
+              keep.push_back(std::move(a));
+              keep.push_back(std::move(b));
+              keep.push_back(std::move(sl));
             }
-            DevBuf a, b, sl;
-            if ((st = upload(h, a, sds)) != SPAND_OK) return st;
-            if ((st = upload(h, b, segs)) != SPAND_OK) return st;
-            if ((st = upload(h, sl, slabs)) != SPAND_OK) return st;
-            hipError_t le = launch_sparsify(a.as<SparsDesc>(), sl.as<SlabRef>(), int32_t(slabs.size()),
-                                            b.as<SegDesc>(), tol, curb.as<int32_t>(), nrefb.as<int32_t>(),
-                                            errb.as<int32_t>(), lds, cls == 2, cls == 1, h->stream);
-            if (le != hipSuccess)
-              return set_err(h, SPAND_E_HIP, std::string("sparsification launch: ") + hipGetErrorString(le));
-            keep.push_back(std::move(a));
-            keep.push_back(std::move(b));
-            keep.push_back(std::move(sl));
           }
-        }
       }
       std::vector<int32_t> rk(nc, -1);
       HIPCHK(hipEventRecord(ph[4], h->stream));
@@ -754,11 +750,23 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       int32_t serr = 0;
       HIPCHK(hipMemcpy(&serr, errb.p, sizeof(int32_t), hipMemcpyDeviceToHost));
       if (serr) return set_err(h, SPAND_E_HIP, "sparsification slab barrier timed out");
+      for (size_t q = 0; q < nlaunch; ++q) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, h->evpool.ev[2 * q], h->evpool.ev[2 * q + 1]));
+        cpqr_ms += ms;
+      }
+      cpqr_launches += int64_t(nlaunch);
       std::vector<TDesc> tds;
       for (int32_t p = ne; p < nc; ++p)
         if (v_off[p] >= 0) {
           sn.rank[p] = rk[p];
           const int64_t r = nref[p];
+          {
+            const double m = sn.size[p], nq = double(ncols[p]);
+            for (int64_t j = 0; j < r; ++j)
+              cpqr_flops += 2.0 * (m - j) * (nq - j) + 4.0 * (m - j) * (nq - j - 1) + 3.0 * (m - j);
+            if (r < std::min<int64_t>(sn.size[p], ncols[p])) cpqr_flops += 2.0 * (m - r) * (nq - r);
+          }
           m_F += (2 * int64_t(sn.size[p]) - r + 1) * r / 2 + r;
           if (r > 4096) return set_err(h, SPAND_E_INVALID, "interface rank above 4096 is not supported");
           if (r > 0)
@@ -887,6 +895,9 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
   h->stats.s_top = s_top;
   h->stats.schur_flops = elim_flops;
   h->stats.schur_seconds = elim_ms * 1e-3;
+  h->stats.cpqr_flops = cpqr_flops;
+  h->stats.cpqr_seconds = cpqr_ms * 1e-3;
+  h->stats.cpqr_launches = cpqr_launches;
   return SPAND_OK;
 }
 

@@ -68,20 +68,17 @@ struct CopyDesc {
   int32_t lds, ldd, rows, cols, trans, pad;
 };
 
-// Sparsification of one interface p (Sec. 2.6.1).  A_pn is split into S column
-// slabs of width C.  Slabs live in the LDS of one workgroup each, or (S = 1 only,
-// interfaces too large for one LDS) in a global workspace.  The width of A_pn is
-// known only on the device: a neighbour q sparsified in an earlier colour class
-// has shrunk to its rank, read from cursize[q].
+// Sparsification of one interface p (Sec. 2.6.1).  A_pn is held in the registers of
+// S workgroups (slabs) of CAP = cpqr_capacity(G) columns each.  The width of A_pn is
+// known only on the device: a neighbour q sparsified in an earlier colour class has
+// shrunk to its rank, read from cursize[q].
 struct SparsDesc {
   double* V;       // m x min(m, ncols_max) reflectors, column-major, ld m
   double* tau;     // min(m, ncols_max)
   double* diag;    // diagonal block of p (ld ldd), set to I_r on exit
-  double* ws;      // global slab (m x C), column norms (C) and pivot steps (C ints): global mode
-  double* xch;     // slab exchange (S > 1): S maxima, S candidate norms, S*m staged columns
-  int32_t* xcand;  // S candidate column indices (S > 1)
-  int32_t* cnt;    // barrier counter of the slabs (zeroed before the launch)
-  int32_t m, ldd, seg_begin, seg_end, id, S, C, pad;
+  double* xch;     // slab exchange (S > 1): 3 buffers x S records of cpqr_record(G) doubles
+  int32_t* cnt;    // barrier counter of the slabs (S > 1, zeroed before the launch)
+  int32_t m, ldd, seg_begin, seg_end, id, S;
 };
 struct SegDesc {
   double* blk;  // block holding A_pq: trans=0 -> A_pq[r][c] = blk[r + c*ld]; trans=1 -> blk[c + r*ld]
@@ -106,14 +103,16 @@ void launch_set_identity(double* const* diag, const int32_t* n, const int32_t* l
 // stored (0 when no coupled dofs were left and p was not sparsified).  err
 // receives bit 2 if a slab barrier timed out.  Launches with more than one slab
 // per interface are cooperative (all workgroups resident).
-size_t sparsify_lds_bytes(int32_t m, int32_t C, int32_t nseg, bool global_slab);
-size_t sparsify_lds_limit();
-int sparsify_max_coresident(size_t lds_bytes);
-hipError_t launch_sparsify(const SparsDesc* d, const SlabRef* slabs, int32_t nslab, const SegDesc* seg, double eps,
-                           int32_t* cursize, int32_t* nref, int32_t* err, size_t lds_bytes, bool cooperative,
-                           bool global_slab, hipStream_t s);
-
-// Compact WY factor T of the reflectors of one interface (r <= 4096).
+// Team size G (lanes per column, a power of two) for m rows; -1 if m is too large.
+int32_t cpqr_team(int32_t m);
+int32_t cpqr_capacity(int32_t G);
+// Doubles of one slab's exchange record (S > 1): 4 scalars + the rows of a team.
+int32_t cpqr_record(int32_t G);
+size_t cpqr_lds_bytes(int32_t G, int32_t nseg);
+int cpqr_max_coresident(int32_t G, size_t lds_bytes);
+hipError_t launch_cpqr(int32_t G, const SparsDesc* d, const SlabRef* slabs, int32_t nslab, const SegDesc* seg,
+                       double eps, int32_t* cursize, int32_t* nref, int32_t* err, size_t lds_bytes, bool cooperative,
+                       hipStream_t s);
 struct TDesc {
   const double* V;    // m x r, ld m
   const double* tau;  // r

@@ -1,64 +1,107 @@
 // Truncated column-pivoted QR of the interfaces (Sec. 2.6.1; ratio rule of Sec. 4
-// intro), distributed over LDS-resident column slabs.
+// intro) with the block A_pn held in registers.
 //
-// Interface p couples its m dofs to ncols neighbour dofs through A_pn (m x ncols).
-// Its columns are cut into S slabs of C columns; workgroup w holds slab w in LDS
-// (row-major, m x C).  Step j of Householder QR with column pivoting:
-//   1. every slab finds the largest exact norm of its remaining columns (rows
-//      j..m-1, recomputed from the updated entries, never downdated) and, after a
-//      barrier, the global largest;
-//   2. each slab stages its first column within a relative 1e-10 of that maximum;
-//      after a second barrier every workgroup takes the smallest such column index
-//      as the pivot; stop when |R_jj| < eps |R_00|;
-//   3. every workgroup forms the reflector from the staged pivot column (LAPACK
-//      dlarfg convention, identical arithmetic everywhere) and applies it to its
-//      own remaining columns.
-// Interfaces too large for one LDS but moderate in size use one workgroup with the
-// slab in a global workspace (no barriers).
-// Columns are not swapped: a column pivoted at step j keeps R_0j..R_jj in rows
-// 0..j of its slab.  With S > 1 the slabs exchange only their largest norm, their
-// first candidate column and its entries.  At the end every slab writes W_cn = R[:r, :] P^T straight
-// into the blocks of p, and workgroup 0 stores the reflectors, sets A_cc = I and
-// publishes the rank.  With S = 1 the barriers reduce to __syncthreads.
+// Interface p couples its m dofs to nc neighbour dofs through A_pn (m x nc).  A
+// workgroup of CQ_NT = 512 threads (two waves per SIMD, so the whole register file
+// of a CU) holds a slab of CAP = CQ_CPL * CQ_NT / G columns: a team of G
+// consecutive lanes (G a power of two, G * CQ_MR >= m) owns CQ_CPL columns, and
+// lane g of the team keeps rows i = q * G + g (q < CQ_MR) of each of them in
+// registers.  Column c of A_pn lives in slab c / CAP, team (c % CAP) % (CQ_NT / G),
+// register slot (c % CAP) / (CQ_NT / G).  Interface p uses S = ceil(nc / CAP) slabs.
+//
+// Step j of Householder QR with column pivoting:
+//   1. every column knows the exact norm of its rows j..m-1 (recomputed from the
+//      updated entries at the end of the previous step, never downdated);
+//   2. pivot = among the remaining columns whose norm is within a relative 1e-10 of
+//      the largest, the smallest column index.  One fused reduction carries
+//      (largest norm, smallest index within the window of that partial maximum,
+//      its norm) through the lanes, the waves and, for S > 1, the slabs; when a
+//      partial maximum grows past a side's own window the exact index is found in
+//      a second round.  Stop when |R_jj| < eps |R_00|;
+//   3. the team owning the pivot column publishes its rows j..m-1 (LDS for S = 1,
+//      the slab exchange buffer for S > 1, one slab barrier per step) and every
+//      lane forms the reflector (LAPACK dlarfg convention) from it with identical
+//      arithmetic;
+//   4. every remaining column is updated in registers, a <- a - tau v (v^T a), and
+//      its new trailing norm formed (team sums by lane shuffles).
+// Columns are never moved: a column pivoted at step j keeps R_0j..R_jj in its rows
+// 0..j.  At the end every slab writes W_cn = R[:r, :] P^T straight into the blocks of
+// p, and slab 0 stores the reflectors, sets A_cc = I and publishes the rank.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cmath>
 
 #include "kernels.h"
 
 namespace spand {
 
-#define CW 256
+#define CQ_NT 512
+#define CQ_MR 32
+#define CQ_CPL 2
+#define CW 256  // threads of k_build_t
 #define TIE_RTOL 1e-10
 #define SPIN_LIMIT (1L << 22)
 #define T_MAX_R 4096
 
 namespace {
 
-__device__ inline double wsum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// Pivot candidate of a set of columns: the largest norm mx, the smallest column
+// index cd among the columns with norm >= mx (1 - TIE_RTOL), its norm cn, and amb
+// set when the exact smallest index at a larger threshold is not known.
+struct Cand {
+  double mx, cn;
+  int cd, amb;
+};
+
+__device__ inline Cand cand_combine(const Cand& a, const Cand& b) {
+  Cand o;
+  o.mx = fmax(a.mx, b.mx);
+  const double thr = o.mx * (1.0 - TIE_RTOL);
+  const bool oka = a.cd != INT_MAX && a.cn >= thr;
+  const bool okb = b.cd != INT_MAX && b.cn >= thr;
+  o.amb = a.amb | b.amb | ((!oka && a.mx >= thr) ? 1 : 0) | ((!okb && b.mx >= thr) ? 1 : 0);
+  o.cd = INT_MAX;
+  o.cn = -1.0;
+  if (oka) {
+    o.cd = a.cd;
+    o.cn = a.cn;
+  }
+  if (okb && b.cd < o.cd) {
+    o.cd = b.cd;
+    o.cn = b.cn;
+  }
+  return o;
+}
+
+template <int G>
+__device__ inline double team_sum(double v) {
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
-__device__ inline double wmax(double v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ inline int wmini(int v) {
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+
+__device__ inline int wave_min(int v) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) v = min(v, __shfl_xor(v, o, 64));
   return v;
 }
 
 // Barrier among the S workgroups of one interface: a monotone counter; barrier
-// number b completes when the counter reaches b*S.  Bounded spin: on time-out the
-// error flag is raised and the workgroup continues, so every wave terminates.
+// number b completes when the counter reaches b*S.  Everything the slabs exchange
+// is written and read with agent-scope atomic accesses, which are coherent across
+// the L2 caches of the XCDs; each wave waits for its own stores to complete before
+// the counter is raised, so no L2 writeback or invalidation is needed.  Bounded
+// spin: on time-out the error flag is raised and the workgroup continues, so every
+// wave terminates.
 __device__ inline void slab_barrier(int32_t* cnt, int32_t target, int32_t* err) {
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's exchange stores have completed
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
-    atomicAdd(cnt, 1);
+    __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     long spins = 0;
     while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(2);
+      __builtin_amdgcn_s_sleep(1);
       if (++spins > SPIN_LIMIT) {
         atomicOr(err, 4);
         break;
@@ -66,7 +109,6 @@ __device__ inline void slab_barrier(int32_t* cnt, int32_t target, int32_t* err) 
       // after any time-out every later barrier falls through at once
       if ((spins & 1023) == 0 && (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 4)) break;
     }
-    __threadfence();
   }
   __syncthreads();
 }
@@ -74,84 +116,52 @@ __device__ inline void slab_barrier(int32_t* cnt, int32_t target, int32_t* err) 
 __device__ inline double shared_load(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ inline void shared_store(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Address of column c of A_pn: entry i at base[i * stride].
+__device__ inline void column_ptr(const SegDesc* sg, const int* segoff, int c, double*& base, int64_t& stride) {
+  int s = 0;
+  while (segoff[s + 1] <= c) ++s;
+  const SegDesc g = sg[s];
+  const int cs = c - segoff[s];
+  if (g.trans) {
+    base = g.blk + cs;
+    stride = g.ld;
+  } else {
+    base = g.blk + (int64_t)cs * g.ld;
+    stride = 1;
+  }
+}
 
 }  // namespace
 
-// Block reductions with four rotating LDS slots: one __syncthreads each.  A slot
-// is reused only four reductions later, after at least three intervening barriers.
-struct RedSlots {
-  double d[4][CW / 64];
-  int i[4][CW / 64];
-};
-__device__ inline double rmax(double v, RedSlots& rs, int& k) {
-  v = wmax(v);
-  double* r = rs.d[k & 3];
-  ++k;
-  if ((threadIdx.x & 63) == 0) r[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double s = r[0];
-  for (int q = 1; q < CW / 64; ++q) s = fmax(s, r[q]);
-  return s;
-}
-__device__ inline double rsum(double v, RedSlots& rs, int& k) {
-  v = wsum(v);
-  double* r = rs.d[k & 3];
-  ++k;
-  if ((threadIdx.x & 63) == 0) r[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int q = 0; q < CW / 64; ++q) s += r[q];
-  return s;
-}
-__device__ inline int rmini(int v, RedSlots& rs, int& k) {
-  v = wmini(v);
-  int* r = rs.i[k & 3];
-  ++k;
-  if ((threadIdx.x & 63) == 0) r[threadIdx.x >> 6] = v;
-  __syncthreads();
-  int s = r[0];
-  for (int q = 1; q < CW / 64; ++q) s = min(s, r[q]);
-  return s;
-}
-
-template <bool GLOBAL>
-__global__ void __launch_bounds__(CW) k_sparsify(const SparsDesc* __restrict__ descs, const SlabRef* __restrict__ slabs,
-                                                 const SegDesc* __restrict__ segs, double eps, int32_t* cursize,
-                                                 int32_t* nref, int32_t* err) {
+template <int G, bool MULTI>
+__global__ void __launch_bounds__(CQ_NT) k_cpqr(const SparsDesc* __restrict__ descs, const SlabRef* __restrict__ slabs,
+                                                const SegDesc* __restrict__ segs, double eps, int32_t* cursize,
+                                                int32_t* nref, int32_t* err) {
+  constexpr int NTEAM = CQ_NT / G;
+  constexpr int CAP = CQ_CPL * NTEAM;
+  constexpr int NW = CQ_NT / 64;
+  constexpr int ROWS = G * CQ_MR;  // rows a team can hold (>= m)
   extern __shared__ double lds[];
-  __shared__ RedSlots rs;
-  __shared__ double redc[2][CW / 64][64];
-  __shared__ double sh_pn;
-  __shared__ int sh_piv, sh_owner;
+  __shared__ Cand red[2][NW], redx[2][NW];
+  __shared__ int red2[NW];
+  __shared__ double sh_pn, sh_tau;
   const SlabRef sr = slabs[blockIdx.x];
   const SparsDesc d = descs[sr.desc];
-  const int m = d.m, S = d.S, C = d.C, w = sr.w;
+  const int m = d.m, S = MULTI ? d.S : 1, w = MULTI ? sr.w : 0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane & (G - 1), team = tid / G;
   const int nseg = d.seg_end - d.seg_begin;
   const SegDesc* sg = segs + d.seg_begin;
-  double* slab;  // m x C, row-major
-  double* nrm;   // C: squared norms of the remaining columns (rows j..m-1)
-  int* colstep;  // C: step at which a column was pivoted (-1 remaining, -2 absent)
-  double* vbuf;  // m
-  int* segoff;   // nseg + 1
-  if (GLOBAL) {
-    slab = d.ws;
-    nrm = d.ws + (size_t)m * C;
-    colstep = reinterpret_cast<int*>(nrm + C);
-    vbuf = lds;
-    segoff = reinterpret_cast<int*>(vbuf + m);
-  } else {
-    slab = lds;
-    nrm = slab + (size_t)m * C;
-    vbuf = nrm + C;
-    colstep = reinterpret_cast<int*>(vbuf + m);
-    segoff = colstep + C;
-  }
-  const int tid = threadIdx.x;
-  int rk = 0;  // reduction slot counter
-  // Slab exchange: three buffers of [S maxima | S candidate norms | S*m staged
-  // columns] and S candidate indices.  Buffer (j & 1) serves step j (a slab can be
-  // one step ahead of another, never two) and buffer 2 the near-tie second round.
-  auto xbuf = [&](int b) { return d.xch + (size_t)b * S * (m + 2); };
+  // vm[i] = (v_i, [i > j]): the reflector of the current step, v_i = 0 above row j,
+  // v_j = 1, zero below row m; the flag selects the rows of the trailing norms
+  double2* vm = reinterpret_cast<double2*>(lds);
+  int* segoff = reinterpret_cast<int*>(lds + 2 * ROWS);  // nseg + 1
+  // exchange record of slab q in buffer b: [max, cand norm, cand xn2, cand index, ROWS column rows]
+  auto xrec = [&](int b, int q) { return d.xch + ((size_t)b * S + q) * (size_t)(ROWS + 4); };
 
   // column layout of A_pn from the neighbours' current sizes
   if (tid == 0) {
@@ -168,260 +178,356 @@ __global__ void __launch_bounds__(CW) k_sparsify(const SparsDesc* __restrict__ d
     if (w == 0 && tid == 0) nref[d.id] = 0;
     return;
   }
-  const int c0 = w * C;
-  const int c1 = min(c0 + C, nc);
-  const int nloc = max(0, c1 - c0);
 
-  // gather this slab of A_pn
-  for (int s = 0; s < nseg; ++s) {
-    const int a = max(segoff[s], c0), b = min(segoff[s + 1], c1);
-    if (a >= b) continue;
-    const SegDesc g = sg[s];
-    const int wdt = b - a;
-    const int64_t cntE = (int64_t)m * wdt;
-    for (int64_t e = tid; e < cntE; e += CW) {
-      int r, cc;
-      if (g.trans) { cc = (int)(e % wdt); r = (int)(e / wdt); } else { r = (int)(e % m); cc = (int)(e / m); }
-      const int lcs = a + cc - segoff[s];
-      const double v = g.trans ? g.blk[lcs + (int64_t)r * g.ld] : g.blk[r + (int64_t)lcs * g.ld];
-      slab[(size_t)r * C + (a + cc - c0)] = v;
+  double a[CQ_CPL][CQ_MR];
+  double nrm[CQ_CPL];  // squared norm of rows j..m-1 (identical in the lanes of a team)
+  int col[CQ_CPL];     // column index in A_pn, -1 if the slot is empty
+  int pst[CQ_CPL];     // -1 remaining, >= 0 step at which the column was the pivot, -2 empty
+#pragma unroll
+  for (int k = 0; k < CQ_CPL; ++k) {
+    const int c = w * CAP + k * NTEAM + team;
+    col[k] = c < nc ? c : -1;
+    pst[k] = c < nc ? -1 : -2;
+    double* base = nullptr;
+    int64_t stride = 0;
+    if (c < nc) column_ptr(sg, segoff, c, base, stride);
+    const int rows = (c < nc) ? m : 0;
+    double sq = 0.0;
+#pragma unroll
+    for (int q = 0; q < CQ_MR; ++q) {
+      const int i = q * G + g;
+      const double v = (i < rows) ? base[(int64_t)i * stride] : 0.0;
+      a[k][q] = v;
+      sq = fma(v, v, sq);
     }
+    nrm[k] = team_sum<G>(sq);
   }
-  if (GLOBAL) __threadfence_block();
-  __syncthreads();
-  for (int lc = tid; lc < C; lc += CW) {
-    double s = -1.0;
-    if (lc < nloc) {
-      s = 0.0;
-      for (int i = 0; i < m; ++i) {
-        const double v = slab[(size_t)i * C + lc];
-        s += v * v;
-      }
-    }
-    nrm[lc] = s;
-    colstep[lc] = (lc < nloc) ? -1 : -2;
-  }
-  if (GLOBAL) __threadfence_block();
-  __syncthreads();
+
   const int kmax = min(m, nc);
   int r = kmax;
   double r00 = 0.0;
   int bar = 0;
   for (int j = 0; j < kmax; ++j) {
-    // ---- pivot.  Rule: among all remaining columns whose norm is within TIE_RTOL of
-    // the largest, the smallest column index.
-    double lmax = 0.0;
-    for (int lc = tid; lc < nloc; lc += CW)
-      if (colstep[lc] == -1) lmax = fmax(lmax, sqrt(nrm[lc]));
-    lmax = rmax(lmax, rs, rk);
-    int lidx = 0x7fffffff;
+    // ---- pivot candidate of this lane, then of the wave and the workgroup
+    double nv[CQ_CPL];
+    Cand t;
+    t.mx = -1.0;
+#pragma unroll
+    for (int k = 0; k < CQ_CPL; ++k) {
+      nv[k] = (pst[k] == -1) ? sqrt(nrm[k]) : -1.0;
+      t.mx = fmax(t.mx, nv[k]);
+    }
+    t.cd = INT_MAX;
+    t.cn = -1.0;
+    t.amb = 0;
     {
-      const double lthr = lmax * (1.0 - TIE_RTOL);
-      for (int lc = tid; lc < nloc; lc += CW)
-        if (colstep[lc] == -1 && sqrt(nrm[lc]) >= lthr) { lidx = c0 + lc; break; }
-    }
-    int cand = rmini(lidx, rs, rk);
-    int xb = 0;  // exchange buffer holding the pivot column
-    if (S > 1) {
-      // publish (slab max, first column within the window of the slab max, its
-      // norm and entries); one barrier
-      xb = j & 1;
-      double* xmax = xbuf(xb);
-      double* xnrm = xmax + S;
-      double* xcol = xmax + 2 * S;
-      int* xcand = d.xcand + (size_t)xb * S;
-      if (cand < nc)
-        for (int i = j + tid; i < m; i += CW) xcol[(size_t)w * m + i] = slab[(size_t)i * C + (cand - c0)];
-      if (tid == 0) {
-        xmax[w] = lmax;
-        xcand[w] = cand;
-        xnrm[w] = (cand < nc) ? sqrt(nrm[cand - c0]) : 0.0;
-      }
-      slab_barrier(d.cnt, ++bar * S, err);
-      if (tid == 0) {
-        double gmax = 0.0;
-        for (int q = 0; q < S; ++q) gmax = fmax(gmax, shared_load(xmax + q));
-        const double thr = gmax * (1.0 - TIE_RTOL);
-        int best = 0x7fffffff, own = -1;
-        bool ambiguous = false;
-        for (int q = 0; q < S; ++q) {
-          const int c = __hip_atomic_load(xcand + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if (c >= nc) continue;
-          if (shared_load(xnrm + q) >= thr) {
-            if (c < best) { best = c; own = q; }
-          } else if (shared_load(xmax + q) >= thr) {
-            ambiguous = true;  // the slab's first column at the global threshold lies further on
-          }
+      const double thr = t.mx * (1.0 - TIE_RTOL);
+#pragma unroll
+      for (int k = 0; k < CQ_CPL; ++k)
+        if (pst[k] == -1 && nv[k] >= thr && col[k] < t.cd) {
+          t.cd = col[k];
+          t.cn = nv[k];
         }
-        sh_piv = ambiguous ? -1 : best;
-        sh_owner = own;
-        sh_pn = ambiguous ? gmax : ((own >= 0) ? shared_load(xnrm + own) : 0.0);
+    }
+#pragma unroll
+    for (int o = G; o < 64; o <<= 1) {
+      Cand u;
+      u.mx = __shfl_xor(t.mx, o, 64);
+      u.cn = __shfl_xor(t.cn, o, 64);
+      u.cd = __shfl_xor(t.cd, o, 64);
+      u.amb = __shfl_xor(t.amb, o, 64);
+      t = cand_combine(t, u);
+    }
+    if (lane == 0) red[j & 1][wave] = t;
+    __syncthreads();
+    Cand wg = red[j & 1][0];
+#pragma unroll
+    for (int q = 1; q < NW; ++q) wg = cand_combine(wg, red[j & 1][q]);
+    if (wg.amb) {  // exact smallest index at the workgroup's threshold
+      const double thr = wg.mx * (1.0 - TIE_RTOL);
+      int c2 = INT_MAX;
+#pragma unroll
+      for (int k = 0; k < CQ_CPL; ++k)
+        if (pst[k] == -1 && nv[k] >= thr) c2 = min(c2, col[k]);
+      c2 = wave_min(c2);
+      if (lane == 0) red2[wave] = c2;
+      __syncthreads();
+      int best = red2[0];
+#pragma unroll
+      for (int q = 1; q < NW; ++q) best = min(best, red2[q]);
+      __syncthreads();  // red2 is rewritten by its next use
+      wg.cd = best;
+    }
+    if (!MULTI && wg.cd == INT_MAX) {  // only non-finite norms left
+      r = j;
+      break;
+    }
+    // team and register slot of this slab's candidate
+    const int lc = wg.cd - w * CAP;
+    const bool own = wg.cd != INT_MAX && team == lc % NTEAM;
+    const int pk = own ? lc / NTEAM : 0;
+    int piv;
+    if constexpr (!MULTI) {
+      // the owner team forms the reflector from its column and publishes it
+      if (own) {
+#pragma unroll
+        for (int k = 0; k < CQ_CPL; ++k)
+          if (k == pk) {
+            double x2 = 0.0, al = 0.0;
+#pragma unroll
+            for (int q = 0; q < CQ_MR; ++q) {
+              const int jq = j - q * G;
+              x2 = (g > jq) ? fma(a[k][q], a[k][q], x2) : x2;
+              al = (g == jq) ? a[k][q] : al;
+            }
+            x2 = team_sum<G>(x2);
+            const double alpha = team_sum<G>(al);  // one lane holds row j, the others add 0
+            const double pn = nv[k];
+            const double r0 = (j == 0) ? pn : r00;
+            const bool stop = (r0 == 0.0) || (pn < eps * r0);
+            double tau = 0.0, scale = 0.0, beta = alpha;
+            if (x2 != 0.0) {
+              beta = -copysign(sqrt(alpha * alpha + x2), alpha);
+              tau = (beta - alpha) / beta;
+              scale = 1.0 / (alpha - beta);
+            }
+            if (!stop) {
+#pragma unroll
+              for (int q = 0; q < CQ_MR; ++q) {
+                const int jq = j - q * G;
+                const double x = a[k][q];
+                vm[q * G + g] = make_double2((g > jq) ? x * scale : ((g == jq) ? 1.0 : 0.0), (g > jq) ? 1.0 : 0.0);
+                a[k][q] = (g == jq) ? beta : ((g > jq) ? 0.0 : x);  // column j of R
+              }
+              pst[k] = j;
+            }
+            if (g == 0) {
+              sh_pn = pn;
+              sh_tau = tau;
+            }
+          }
       }
       __syncthreads();
-      if (sh_piv == -1) {  // second round with the exact global threshold (near-ties across slabs)
-        const double thr = sh_pn * (1.0 - TIE_RTOL);
-        xb = 2;
-        double* xnrm2 = xbuf(2) + S;
-        double* xcol2 = xbuf(2) + 2 * S;
-        int* xcand2 = d.xcand + 2 * (size_t)S;
-        int l2 = 0x7fffffff;
-        for (int lc = tid; lc < nloc; lc += CW)
-          if (colstep[lc] == -1 && sqrt(nrm[lc]) >= thr) { l2 = c0 + lc; break; }
-        const int c2 = rmini(l2, rs, rk);
-        if (c2 < nc)
-          for (int i = j + tid; i < m; i += CW) xcol2[(size_t)w * m + i] = slab[(size_t)i * C + (c2 - c0)];
-        if (tid == 0) {
-          xcand2[w] = c2;
-          xnrm2[w] = (c2 < nc) ? sqrt(nrm[c2 - c0]) : 0.0;
-        }
-        slab_barrier(d.cnt, ++bar * S, err);
-        if (tid == 0) {
-          int best = 0x7fffffff, own = -1;
-          for (int q = 0; q < S; ++q) {
-            const int c = __hip_atomic_load(xcand2 + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (c < best) { best = c; own = q; }
-          }
-          sh_piv = best;
-          sh_owner = own;
-          sh_pn = (own >= 0 && best < nc) ? shared_load(xnrm2 + own) : 0.0;
-        }
-        __syncthreads();
-      }
+      piv = wg.cd;
     } else {
+      // publish (slab max, slab candidate, its norm, its rows); one barrier
+      {
+        double* rc = xrec(j & 1, w);
+        if (own) {
+#pragma unroll
+          for (int k = 0; k < CQ_CPL; ++k)
+            if (k == pk) {
+              double x2 = 0.0;
+#pragma unroll
+              for (int q = 0; q < CQ_MR; ++q) {
+                shared_store(rc + 4 + q * G + g, a[k][q]);
+                x2 = (g > j - q * G) ? fma(a[k][q], a[k][q], x2) : x2;
+              }
+              x2 = team_sum<G>(x2);
+              if (g == 0) {
+                shared_store(rc + 1, nv[k]);
+                shared_store(rc + 2, x2);
+              }
+            }
+        }
+        if (tid == 0) {
+          shared_store(rc, wg.mx);
+          shared_store(rc + 3, (wg.cd == INT_MAX) ? -1.0 : (double)wg.cd);
+          if (wg.cd == INT_MAX) shared_store(rc + 1, -1.0);
+        }
+      }
+      int xb = j & 1;
+      slab_barrier(d.cnt, ++bar * S, err);
+      // the S records are read in parallel (one memory round trip) and reduced like
+      // the lanes; the owning slab of column c is c / CAP
+      Cand u;
+      u.mx = -1.0;
+      u.cn = -1.0;
+      u.cd = INT_MAX;
+      u.amb = 0;
+      if (tid < S) {
+        const double* rc = xrec(xb, tid);
+        const double mx = shared_load(rc), cn = shared_load(rc + 1), cq = shared_load(rc + 3);
+        u.mx = mx;
+        if (cq >= 0.0) {
+          u.cd = (int)cq;
+          u.cn = cn;
+        }
+      }
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        Cand v;
+        v.mx = __shfl_xor(u.mx, o, 64);
+        v.cn = __shfl_xor(u.cn, o, 64);
+        v.cd = __shfl_xor(u.cd, o, 64);
+        v.amb = __shfl_xor(u.amb, o, 64);
+        u = cand_combine(u, v);
+      }
+      if (lane == 0) redx[j & 1][wave] = u;
+      __syncthreads();
+      Cand gc = redx[j & 1][0];
+#pragma unroll
+      for (int q = 1; q < NW; ++q) gc = cand_combine(gc, redx[j & 1][q]);
+      piv = gc.cd;
+      if (gc.amb) {  // second round with the exact global threshold (near-ties across slabs)
+        xb = 2;
+        const double thr = gc.mx * (1.0 - TIE_RTOL);
+        int c2 = INT_MAX;
+#pragma unroll
+        for (int k = 0; k < CQ_CPL; ++k)
+          if (pst[k] == -1 && nv[k] >= thr) c2 = min(c2, col[k]);
+        c2 = wave_min(c2);
+        if (lane == 0) red2[wave] = c2;
+        __syncthreads();
+        int best = red2[0];
+#pragma unroll
+        for (int q = 1; q < NW; ++q) best = min(best, red2[q]);
+        const int lc2 = best - w * CAP;
+        double* rc = xrec(2, w);
+        if (best != INT_MAX && team == lc2 % NTEAM) {
+          const int pk2 = lc2 / NTEAM;
+#pragma unroll
+          for (int k = 0; k < CQ_CPL; ++k)
+            if (k == pk2) {
+              double x2 = 0.0;
+#pragma unroll
+              for (int q = 0; q < CQ_MR; ++q) {
+                shared_store(rc + 4 + q * G + g, a[k][q]);
+                x2 = (g > j - q * G) ? fma(a[k][q], a[k][q], x2) : x2;
+              }
+              x2 = team_sum<G>(x2);
+              if (g == 0) {
+                shared_store(rc + 1, nv[k]);
+                shared_store(rc + 2, x2);
+              }
+            }
+        }
+        if (tid == 0) shared_store(rc + 3, (best == INT_MAX) ? -1.0 : (double)best);
+        slab_barrier(d.cnt, ++bar * S, err);
+        int b2 = INT_MAX;
+        if (tid < S) {
+          const double cq = shared_load(xrec(2, tid) + 3);
+          if (cq >= 0.0) b2 = (int)cq;
+        }
+        b2 = wave_min(b2);
+        if (lane == 0) red2[wave] = b2;
+        __syncthreads();
+        piv = red2[0];
+#pragma unroll
+        for (int q = 1; q < NW; ++q) piv = min(piv, red2[q]);
+        __syncthreads();  // red2 is rewritten by its next use
+      }
+      if (piv == INT_MAX) {  // only non-finite norms left
+        r = j;
+        break;
+      }
+      // every thread forms the reflector from the winning record (identical arithmetic)
+      const double* rc = xrec(xb, piv / CAP);
+      const double pn = shared_load(rc + 1);
+      const double x2 = shared_load(rc + 2);
+      const double alpha = shared_load(rc + 4 + j);
+      const double r0 = (j == 0) ? pn : r00;
+      const bool stop = (r0 == 0.0) || (pn < eps * r0);
+      double tau = 0.0, scale = 0.0, beta = alpha;
+      if (x2 != 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + x2), alpha);
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      if (!stop) {
+        for (int i = tid; i < ROWS; i += CQ_NT) {
+          const double x = (i > j) ? shared_load(rc + 4 + i) : 0.0;
+          vm[i] = make_double2((i > j) ? x * scale : ((i == j) ? 1.0 : 0.0), (i > j) ? 1.0 : 0.0);
+        }
+        const int plc = piv - w * CAP;
+        if (plc >= 0 && plc < CAP && team == plc % NTEAM) {
+          const int ppk = plc / NTEAM;
+#pragma unroll
+          for (int k = 0; k < CQ_CPL; ++k)
+            if (k == ppk) {
+#pragma unroll
+              for (int q = 0; q < CQ_MR; ++q) {
+                const int jq = j - q * G;
+                a[k][q] = (g == jq) ? beta : ((g > jq) ? 0.0 : a[k][q]);  // column j of R
+              }
+              pst[k] = j;
+            }
+        }
+      }
       if (tid == 0) {
-        sh_piv = cand;
-        sh_owner = 0;
-        sh_pn = (cand < nc) ? sqrt(nrm[cand - c0]) : 0.0;
+        sh_pn = pn;
+        sh_tau = tau;
       }
       __syncthreads();
     }
-    const int piv = sh_piv, owner = sh_owner;
-    if (piv >= nc) { r = j; break; }  // only non-finite norms left
     const double pn = sh_pn;
     if (j == 0) {
       r00 = pn;
-      if (r00 == 0.0) { r = 0; break; }
-    }
-    if (pn < eps * r00) { r = j; break; }
-    // ---- pivot column rows j..m-1 into vbuf; reflector (dlarfg convention)
-    if (S > 1) {
-      const double* xcol = xbuf(xb) + 2 * S;
-      for (int i = j + tid; i < m; i += CW) vbuf[i] = shared_load(xcol + (size_t)owner * m + i);
-    } else {
-      for (int i = j + tid; i < m; i += CW) vbuf[i] = slab[(size_t)i * C + (piv - c0)];
-    }
-    __syncthreads();
-    const double alpha = vbuf[j];
-    double part = 0.0;
-    for (int i = j + 1 + tid; i < m; i += CW) part += vbuf[i] * vbuf[i];
-    const double xn2 = rsum(part, rs, rk);
-    double tau, scale, beta;
-    if (xn2 == 0.0) {
-      tau = 0.0; beta = alpha; scale = 0.0;
-    } else {
-      beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-      tau = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
-    }
-    __syncthreads();  // everyone has read vbuf[j] and the pivot column
-    for (int i = j + 1 + tid; i < m; i += CW) vbuf[i] *= scale;
-    if (tid == 0) vbuf[j] = 1.0;
-    if (owner == w) {
-      const int lc = piv - c0;
-      for (int i = j + tid; i < m; i += CW) slab[(size_t)i * C + lc] = (i == j) ? beta : 0.0;
-      if (tid == 0) {
-        colstep[lc] = j;
-        nrm[lc] = -1.0;
+      if (r00 == 0.0) {
+        r = 0;
+        break;
       }
     }
-    if (GLOBAL) __threadfence_block();
-    __syncthreads();
+    if (pn < eps * r00) {
+      r = j;
+      break;
+    }
+    const double tau = sh_tau;
     if (w == 0) {
       double* V = d.V + (int64_t)j * m;
-      for (int i = tid; i < m; i += CW) V[i] = (i < j) ? 0.0 : vbuf[i];
+      for (int i = tid; i < m; i += CQ_NT) V[i] = vm[i].x;
       if (tid == 0) d.tau[j] = tau;
     }
-    // ---- apply H_j to the remaining columns of this slab; recompute their norms
-    if (m <= 64) {  // short columns: one thread per column
-      for (int lc = tid; lc < nloc; lc += CW) {
-        if (colstep[lc] != -1) continue;
-        double dot = slab[(size_t)j * C + lc];
-        for (int i = j + 1; i < m; ++i) dot += vbuf[i] * slab[(size_t)i * C + lc];
-        const double wv = tau * dot;
-        slab[(size_t)j * C + lc] -= wv;
-        double s = 0.0;
-        for (int i = j + 1; i < m; ++i) {
-          const double x = slab[(size_t)i * C + lc] - wv * vbuf[i];
-          slab[(size_t)i * C + lc] = x;
-          s += x * x;
-        }
-        nrm[lc] = s;
-      }
-    } else {  // tall columns: 64 columns per pass, the 4 waves split the rows
-      const int lane = tid & 63, wv4 = tid >> 6;
-      for (int t0 = 0; t0 < nloc; t0 += 64) {
-        const int lc = t0 + lane;
-        const bool act = lc < nloc && colstep[lc] == -1;
-        double d0 = 0.0, d1 = 0.0;
-        if (act) {
-          int i = j + wv4;
-          for (; i + 4 < m; i += 8) {
-            d0 += vbuf[i] * slab[(size_t)i * C + lc];
-            d1 += vbuf[i + 4] * slab[(size_t)(i + 4) * C + lc];
-          }
-          if (i < m) d0 += vbuf[i] * slab[(size_t)i * C + lc];
-        }
-        redc[0][wv4][lane] = d0 + d1;
-        __syncthreads();
-        const double wvv = tau * (redc[0][0][lane] + redc[0][1][lane] + redc[0][2][lane] + redc[0][3][lane]);
-        double s0 = 0.0, s1 = 0.0;
-        if (act) {
-          int i = j + wv4;
-          for (; i + 4 < m; i += 8) {
-            const double x0 = slab[(size_t)i * C + lc] - wvv * vbuf[i];
-            const double x1 = slab[(size_t)(i + 4) * C + lc] - wvv * vbuf[i + 4];
-            slab[(size_t)i * C + lc] = x0;
-            slab[(size_t)(i + 4) * C + lc] = x1;
-            if (i > j) s0 += x0 * x0;
-            s1 += x1 * x1;
-          }
-          if (i < m) {
-            const double x0 = slab[(size_t)i * C + lc] - wvv * vbuf[i];
-            slab[(size_t)i * C + lc] = x0;
-            if (i > j) s0 += x0 * x0;
-          }
-        }
-        redc[1][wv4][lane] = s0 + s1;
-        __syncthreads();
-        if (act && wv4 == 0) nrm[lc] = redc[1][0][lane] + redc[1][1][lane] + redc[1][2][lane] + redc[1][3][lane];
-      }
+    // ---- apply H_j to the remaining columns; new trailing norms (rows j+1..)
+    const double2* vl = vm + g;
+    double dot[CQ_CPL];
+#pragma unroll
+    for (int k = 0; k < CQ_CPL; ++k) dot[k] = 0.0;
+#pragma unroll
+    for (int q = 0; q < CQ_MR; ++q) {
+      const double vq = vl[q * G].x;
+#pragma unroll
+      for (int k = 0; k < CQ_CPL; ++k) dot[k] = fma(vq, a[k][q], dot[k]);
+      if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bound the LDS loads in flight
     }
-    if (GLOBAL) __threadfence_block();
-    __syncthreads();
+    double wv[CQ_CPL], sq[CQ_CPL];
+#pragma unroll
+    for (int k = 0; k < CQ_CPL; ++k) {
+      dot[k] = team_sum<G>(dot[k]);
+      wv[k] = (pst[k] == -1) ? tau * dot[k] : 0.0;
+      sq[k] = 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < CQ_MR; ++q) {
+      const double2 vf = vl[q * G];
+#pragma unroll
+      for (int k = 0; k < CQ_CPL; ++k) {
+        const double x = fma(-wv[k], vf.x, a[k][q]);
+        a[k][q] = x;
+        sq[k] = fma(x * vf.y, x, sq[k]);
+      }
+      if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int k = 0; k < CQ_CPL; ++k) nrm[k] = team_sum<G>(sq[k]);
   }
-  __syncthreads();
   // ---- W_cn = R[:r, :] (column order of A_pn) into the blocks of p
-  for (int s = 0; s < nseg; ++s) {
-    const int a = max(segoff[s], c0), b = min(segoff[s + 1], c1);
-    if (a >= b || r == 0) continue;
-    const SegDesc g = sg[s];
-    const int wdt = b - a;
-    const int64_t cntE = (int64_t)r * wdt;
-    for (int64_t e = tid; e < cntE; e += CW) {
-      int i, cc;
-      if (g.trans) { cc = (int)(e % wdt); i = (int)(e / wdt); } else { i = (int)(e % r); cc = (int)(e / r); }
-      const int lc = a + cc - c0;
-      const int lcs = a + cc - segoff[s];
-      const int cs = colstep[lc];
-      const double v = (cs >= 0 && i > cs) ? 0.0 : slab[(size_t)i * C + lc];
-      if (g.trans) g.blk[lcs + (int64_t)i * g.ld] = v;
-      else g.blk[i + (int64_t)lcs * g.ld] = v;
+#pragma unroll
+  for (int k = 0; k < CQ_CPL; ++k) {
+    if (col[k] < 0 || r == 0) continue;
+    double* base;
+    int64_t stride;
+    column_ptr(sg, segoff, col[k], base, stride);
+#pragma unroll
+    for (int q = 0; q < CQ_MR; ++q) {
+      const int i = q * G + g;
+      if (i < r) base[(int64_t)i * stride] = a[k][q];
     }
   }
   if (w == 0) {
-    for (int64_t e = tid; e < (int64_t)r * r; e += CW) {
-      const int a = (int)(e % r), b = (int)(e / r);
-      d.diag[a + (int64_t)b * d.ldd] = (a == b) ? 1.0 : 0.0;
+    for (int64_t e = tid; e < (int64_t)r * r; e += CQ_NT) {
+      const int x = (int)(e % r), y = (int)(e / r);
+      d.diag[x + (int64_t)y * d.ldd] = (x == y) ? 1.0 : 0.0;
     }
     if (tid == 0) {
       cursize[d.id] = r;
@@ -475,53 +581,71 @@ void launch_build_t(const TDesc* d, int32_t count, hipStream_t s) {
   hipLaunchKernelGGL(k_build_t, dim3(count), dim3(CW), 0, s, d);
 }
 
-size_t sparsify_lds_bytes(int32_t m, int32_t C, int32_t nseg, bool global_slab) {
-  if (global_slab) return size_t(m) * sizeof(double) + (size_t(nseg) + 1) * sizeof(int32_t) + 64;
-  return (size_t(m) * C + C + m) * sizeof(double) + (size_t(C) + nseg + 1) * sizeof(int32_t) + 64;
+int32_t cpqr_team(int32_t m) {
+  int32_t G = 1;
+  while (G * CQ_MR < m) G <<= 1;
+  return G <= 64 ? G : -1;
 }
 
-size_t sparsify_lds_limit() { return 150 * 1024; }
+int32_t cpqr_capacity(int32_t G) { return CQ_CPL * CQ_NT / G; }
+
+size_t cpqr_lds_bytes(int32_t G, int32_t nseg) {
+  return 2 * size_t(G) * CQ_MR * sizeof(double) + (size_t(nseg) + 1) * sizeof(int32_t) + 16;
+}
+
+int32_t cpqr_record(int32_t G) { return G * CQ_MR + 4; }
 
 namespace {
-void set_lds_attr() {
-  static bool done = false;
-  if (done) return;
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sparsify<false>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, int(sparsify_lds_limit()));
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sparsify<true>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, int(sparsify_lds_limit()));
-  done = true;
+template <int G>
+hipError_t launch_g(const SparsDesc* d, const SlabRef* slabs, int32_t nslab, const SegDesc* seg, double eps,
+                    int32_t* cursize, int32_t* nref, int32_t* err, size_t lds, bool cooperative, hipStream_t s) {
+  if (!cooperative) {
+    hipLaunchKernelGGL((k_cpqr<G, false>), dim3(nslab), dim3(CQ_NT), lds, s, d, slabs, seg, eps, cursize, nref, err);
+    return hipGetLastError();
+  }
+  void* args[] = {(void*)&d, (void*)&slabs, (void*)&seg, (void*)&eps, (void*)&cursize, (void*)&nref, (void*)&err};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_cpqr<G, true>), dim3(nslab), dim3(CQ_NT), args,
+                                    (unsigned int)lds, s);
 }
-}  // namespace
 
-int sparsify_max_coresident(size_t lds_bytes) {
-  set_lds_attr();
+template <int G>
+int coresident_g(size_t lds) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sparsify<false>, CW, lds_bytes) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cpqr<G, true>, CQ_NT, lds) != hipSuccess) return 0;
   int dev = 0, cus = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   return per_cu * cus;
 }
+}  // namespace
 
-hipError_t launch_sparsify(const SparsDesc* d, const SlabRef* slabs, int32_t nslab, const SegDesc* seg, double eps,
-                           int32_t* cursize, int32_t* nref, int32_t* err, size_t lds_bytes, bool cooperative,
-                           bool global_slab, hipStream_t s) {
+int cpqr_max_coresident(int32_t G, size_t lds) {
+  switch (G) {
+    case 1: return coresident_g<1>(lds);
+    case 2: return coresident_g<2>(lds);
+    case 4: return coresident_g<4>(lds);
+    case 8: return coresident_g<8>(lds);
+    case 16: return coresident_g<16>(lds);
+    case 32: return coresident_g<32>(lds);
+    case 64: return coresident_g<64>(lds);
+  }
+  return 0;
+}
+
+hipError_t launch_cpqr(int32_t G, const SparsDesc* d, const SlabRef* slabs, int32_t nslab, const SegDesc* seg,
+                       double eps, int32_t* cursize, int32_t* nref, int32_t* err, size_t lds, bool cooperative,
+                       hipStream_t s) {
   if (nslab == 0) return hipSuccess;
-  set_lds_attr();
-  if (global_slab) {
-    hipLaunchKernelGGL(k_sparsify<true>, dim3(nslab), dim3(CW), lds_bytes, s, d, slabs, seg, eps, cursize, nref,
-                       err);
-    return hipGetLastError();
+  switch (G) {
+    case 1: return launch_g<1>(d, slabs, nslab, seg, eps, cursize, nref, err, lds, cooperative, s);
+    case 2: return launch_g<2>(d, slabs, nslab, seg, eps, cursize, nref, err, lds, cooperative, s);
+    case 4: return launch_g<4>(d, slabs, nslab, seg, eps, cursize, nref, err, lds, cooperative, s);
+    case 8: return launch_g<8>(d, slabs, nslab, seg, eps, cursize, nref, err, lds, cooperative, s);
+    case 16: return launch_g<16>(d, slabs, nslab, seg, eps, cursize, nref, err, lds, cooperative, s);
+    case 32: return launch_g<32>(d, slabs, nslab, seg, eps, cursize, nref, err, lds, cooperative, s);
+    case 64: return launch_g<64>(d, slabs, nslab, seg, eps, cursize, nref, err, lds, cooperative, s);
   }
-  if (!cooperative) {
-    hipLaunchKernelGGL(k_sparsify<false>, dim3(nslab), dim3(CW), lds_bytes, s, d, slabs, seg, eps, cursize, nref,
-                       err);
-    return hipGetLastError();
-  }
-  void* args[] = {(void*)&d, (void*)&slabs, (void*)&seg, (void*)&eps, (void*)&cursize, (void*)&nref, (void*)&err};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_sparsify<false>), dim3(nslab), dim3(CW), args,
-                                    (unsigned int)lds_bytes, s);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace spand

@@ -121,6 +121,19 @@ spand_status pcg_solve(spand_ctx* h, int32_t nrhs, const double* b, double* x, d
 
   std::vector<double> hb(nrhs), hr(nrhs);
   std::vector<int32_t> act(nrhs, 0);
+  // device time of every apply, from a pair of events around it
+  size_t napply = 0;
+  auto timed_apply = [&]() -> spand_status {
+    hipEvent_t e0, e1;
+    HIPCHK(h->evpool.get(2 * napply, &e0));
+    HIPCHK(h->evpool.get(2 * napply + 1, &e1));
+    HIPCHK(hipEventRecord(e0, s));
+    spand_status sa = apply_precond(h, nrhs, r, z, scratch);
+    if (sa != SPAND_OK) return sa;
+    HIPCHK(hipEventRecord(e1, s));
+    ++napply;
+    return SPAND_OK;
+  };
   launch_dot(b, b, n, nrhs, partial, nblk, bb, s);
   HIPCHK(hipMemcpyAsync(hb.data(), bb, scal * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -135,7 +148,7 @@ spand_status pcg_solve(spand_ctx* h, int32_t nrhs, const double* b, double* x, d
   HIPCHK(hipMemcpyAsync(active_d, act.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
   bool any = std::any_of(act.begin(), act.end(), [](int a) { return a != 0; });
   if (any) {
-    if ((st = apply_precond(h, nrhs, r, z, scratch)) != SPAND_OK) return st;
+    if ((st = timed_apply()) != SPAND_OK) return st;
     HIPCHK(hipMemcpyAsync(p, z, vec * sizeof(double), hipMemcpyDeviceToDevice, s));
     launch_dot(r, z, n, nrhs, partial, nblk, rz, s);
   }
@@ -157,7 +170,7 @@ spand_status pcg_solve(spand_ctx* h, int32_t nrhs, const double* b, double* x, d
     any = std::any_of(act.begin(), act.end(), [](int a) { return a != 0; });
     if (!any || it >= maxit) break;
     HIPCHK(hipMemcpyAsync(active_d, act.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    if ((st = apply_precond(h, nrhs, r, z, scratch)) != SPAND_OK) return st;
+    if ((st = timed_apply()) != SPAND_OK) return st;
     launch_dot(r, z, n, nrhs, partial, nblk, rz_new, s);
     launch_update_p(n, nrhs, rz_new, rz, active_d, z, p, s);
     HIPCHK(hipMemcpyAsync(rz, rz_new, scal * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -175,6 +188,15 @@ spand_status pcg_solve(spand_ctx* h, int32_t nrhs, const double* b, double* x, d
     relres[c] = hb[c] > 0.0 ? std::sqrt(hr[c]) / hb[c] : 0.0;
     if (act[c]) noconv = true;
   }
+  double apply_ms = 0.0;
+  for (size_t q = 0; q < napply; ++q) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, h->evpool.ev[2 * q], h->evpool.ev[2 * q + 1]));
+    apply_ms += ms;
+  }
+  h->stats.apply_seconds = apply_ms * 1e-3;
+  h->stats.apply_calls = int64_t(napply);
+  h->stats.apply_bytes = 16.0 * double(h->stats.m_F) + 4.0 * 8.0 * double(n) * nrhs;
   h->stats.last_iters = 0;
   for (int c = 0; c < nrhs; ++c) h->stats.last_iters = std::max(h->stats.last_iters, iters[c]);
   if (noconv) return set_err(h, SPAND_E_NOCONV, "PCG reached maxit = " + std::to_string(maxit));

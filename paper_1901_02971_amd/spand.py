@@ -34,7 +34,9 @@ class Stats(C.Structure):
                 ("s_top", C.c_int32), ("m_F", C.c_int64), ("schur_flops", C.c_double),
                 ("schur_seconds", C.c_double), ("fail_step", C.c_int32), ("fail_cluster", C.c_int32),
                 ("fail_phase", C.c_int32), ("reserved", C.c_int32),
-                ("step_phase_seconds", (C.c_double * 4) * 32), ("step_m_F", C.c_int64 * 32)]
+                ("step_phase_seconds", (C.c_double * 4) * 32), ("step_m_F", C.c_int64 * 32),
+                ("cpqr_flops", C.c_double), ("cpqr_seconds", C.c_double), ("cpqr_launches", C.c_int64),
+                ("apply_bytes", C.c_double), ("apply_seconds", C.c_double), ("apply_calls", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_

@@ -1,0 +1,70 @@
+"""GPU parity at the workload sizes, against the oracle's stored results.
+
+The stored files (tests/golden/oracle_<name>_tol<eps>.json) were written by
+tests/golden/make_oracle_stats.py, which runs only the FP64 oracle on the seeded
+grid problems of gridgen.config_problem.  Bars: every step's cluster sizes and kept
+ranks identical (SHA-256 of the int32 arrays, sums reported on mismatch); s_top and
+m_F identical; PCG iterations within +-1 of the oracle's for every right-hand side
+and the true relative residual <= 1e-12.  The 64^3 variable-coefficient and 128^3
+Laplacian cases put interfaces across several register slabs, so they cover the
+multi-workgroup CPQR with its slab barriers.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import gridgen
+from tests.gpu_util import gpu_factor, gpu_solve, note
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu(request):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    note(request.node.nodeid)
+
+
+def digest(a):
+    return hashlib.sha256(np.ascontiguousarray(a, dtype="<i4").tobytes()).hexdigest()
+
+
+def cases():
+    out = []
+    for name in ("c2", "c3", "c4"):
+        path = os.path.join(GOLDEN, f"oracle_{name}_tol1e-2.json")
+        if os.path.exists(path):
+            out.append(pytest.param(path, id=f"{name}_tol1e-2"))
+    return out
+
+
+@pytest.mark.parametrize("path", cases())
+def test_workload_matches_oracle(path):
+    with open(path) as f:
+        ref = json.load(f)
+    p, b, levels = gridgen.config_problem(ref["workload"])
+    assert levels == ref["levels"] and p.n == ref["n"]
+    s = gpu_factor(p, levels, ref["tol"], ref["skip"])
+    bad = []
+    for st in ref["steps"]:
+        t = st["step"]
+        sizes, ranks = s.step_ranks(t)
+        c = s.step_counts(t)
+        kept = ranks.astype(np.int64).copy()
+        kept[:c["ne"]] = -1
+        if digest(sizes) != st["sizes_sha256"] or digest(kept) != st["kept_sha256"]:
+            bad.append((t, int(sizes.sum()), st["size_sum"], int(kept[kept >= 0].sum()), st["kept_sum"]))
+    assert not bad, f"steps whose sizes or ranks differ (step, size sum, oracle, kept sum, oracle): {bad}"
+    stats = s.stats()
+    assert stats["s_top"] == ref["s_top"]
+    assert stats["m_F"] == ref["m_F"]
+    _, it, rr, _ = gpu_solve(s, b, ref["rtol"], ref["maxit"])
+    assert np.all(np.abs(it - np.array(ref["pcg_iters"])) <= 1), (it.tolist(), ref["pcg_iters"])
+    assert np.all(rr <= 1e-12), rr
