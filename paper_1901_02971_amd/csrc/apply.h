@@ -16,8 +16,11 @@ struct ElimAp {
   int64_t slot_N;      // offset of s's neighbour slots in the step neighbour-slot array
   int64_t tmp;         // offset of s's rows in the apply scratch
 };
-struct TargetAp {
-  int32_t nn, cbeg, cend, pad;
+struct ElimTile {     // columns [k0, min(k0 + 64, ns)) of eliminated cluster s
+  int32_t s, k0;
+};
+struct TargetAp {     // rows [r0, min(r0 + 64, nn)) of receiving cluster n
+  int32_t nn, cbeg, cend, r0;
   int64_t slot_n;
 };
 struct TargetContrib {
@@ -37,7 +40,10 @@ struct HouseAp {
   const double* T;    // r x r upper-triangular factor of Q = I - V T V^T, ld r
   int32_t np, r;
   int64_t slot_p;
-  int64_t tmp;        // 3*np rows of scratch: x, V^T x, T-product
+  int64_t tmp;        // 2*r rows of scratch: V^T x, then the T-product
+};
+struct HouseTile {    // 64 reflectors [j0, j0 + 64) or 64 rows [j0, j0 + 64) of interface p
+  int32_t p, j0;
 };
 
 // Device-side view of one step for the apply.
@@ -47,10 +53,13 @@ struct StepDev {
   const TargetContrib* contrib;
   const ScaleAp* scale;
   const HouseAp* house;
+  const ElimTile* etile;
+  const HouseTile* hr;   // reflector tiles of every Q_p
+  const HouseTile* hv;   // row tiles of every Q_p
   const int32_t* slot;
   const int32_t* nslot;
   int64_t nslot_len;
-  int32_t n_elim, n_target, n_scale, n_house;
+  int32_t n_elim, n_target, n_scale, n_house, n_etile, n_hr, n_hv, pad;
 };
 
 struct ApplyArgs {

@@ -64,8 +64,8 @@ struct StepNum {
   DevBuf edinv, sdinv;          // inverses of the CHOL_NB-wide diagonal blocks of L_s, L_p
   DevBuf d_slot, d_nslot;       // slot arrays on the device
   // apply descriptors
-  DevBuf d_elim, d_target, d_contrib, d_scale, d_house;
-  int32_t n_elim_ap = 0, n_target = 0, n_scale = 0, n_house = 0;
+  DevBuf d_elim, d_target, d_contrib, d_scale, d_house, d_etile, d_hr, d_hv;
+  int32_t n_elim_ap = 0, n_target = 0, n_scale = 0, n_house = 0, n_etile = 0, n_hr = 0, n_hv = 0;
   int64_t nslot_len = 0;
   int64_t tmp_elim = 0, tmp_scale = 0;  // doubles per RHS of temp needed
   std::vector<ElimAp> h_elim;
@@ -73,6 +73,8 @@ struct StepNum {
   std::vector<TargetContrib> h_contrib;
   std::vector<ScaleAp> h_scale;
   std::vector<HouseAp> h_house;
+  std::vector<ElimTile> h_etile;
+  std::vector<HouseTile> h_hr, h_hv;
 };
 
 }  // namespace spand

@@ -112,11 +112,12 @@ void build_layout(const SymStep& st, const std::vector<int32_t>& size, Layout& L
   L.total_arena = ta;
 }
 
-void add_tiles(std::vector<TileRef>& tiles, int32_t desc, int32_t M, int32_t N, bool lower) {
+// part: 0 every tile, 1 tiles on or below the diagonal, 2 tiles on or above it
+void add_tiles(std::vector<TileRef>& tiles, int32_t desc, int32_t M, int32_t N, int part) {
   const int32_t tm = (M + GEMM_TILE - 1) / GEMM_TILE, tn = (N + GEMM_TILE - 1) / GEMM_TILE;
   for (int32_t a = 0; a < tm; ++a)
     for (int32_t b = 0; b < tn; ++b) {
-      if (lower && b > a) continue;
+      if ((part == 1 && b > a) || (part == 2 && b < a)) continue;
       tiles.push_back(TileRef{desc, a, b, 0});
     }
 }
@@ -128,10 +129,10 @@ struct GemmSeq {
   std::vector<int64_t> cut;  // tile range end of every launch
   std::vector<int> prec;
   DevBuf dd, dt;
-  void add(const GemmDesc& g, bool lower) {
+  void add(const GemmDesc& g, int part) {
     if (g.M <= 0 || g.N <= 0 || g.K <= 0) return;
     d.push_back(g);
-    add_tiles(t, int32_t(d.size() - 1), g.M, g.N, lower);
+    add_tiles(t, int32_t(d.size() - 1), g.M, g.N, part);
   }
   void end_launch(int p) {
     cut.push_back(int64_t(t.size()));
@@ -187,7 +188,7 @@ spand_status blocked_cholesky(spand_ctx* h, const std::vector<Front>& F, int32_t
       q.C = f.P + (kb + w) + int64_t(kb + w) * f.ld; q.ldc = f.ld;
       q.M = f.n - kb - w; q.N = f.n - kb - w; q.K = w;
       q.flags = G_TB | G_LOWERC; q.alpha = -1.0; q.beta = 1.0;
-      g.add(q, true);
+      g.add(q, 1);
     }
     g.end_launch(0);
     for (const Front& f : F) {  // rows below the pivot block
@@ -199,7 +200,7 @@ spand_status blocked_cholesky(spand_ctx* h, const std::vector<Front>& F, int32_t
       q.C = f.P + f.n + int64_t(kb + w) * f.ld; q.ldc = f.ld;
       q.M = f.m - f.n; q.N = f.n - kb - w; q.K = w;
       q.flags = G_TB; q.alpha = -1.0; q.beta = 1.0;
-      g.add(q, false);
+      g.add(q, 0);
     }
     g.end_launch(prec_below);
   }
@@ -249,7 +250,7 @@ spand_status left_trsm(spand_ctx* h, const std::vector<LeftBlock>& B) {
       q.C = b.X + kb + w; q.ldc = b.ldx;
       q.M = b.nrows - kb - w; q.N = b.ncols; q.K = w;
       q.flags = 0; q.alpha = -1.0; q.beta = 1.0;
-      g.add(q, false);
+      g.add(q, 0);
     }
     lcut.push_back(int64_t(ld.size()));
     g.end_launch(0);
@@ -457,7 +458,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
         y.M = nn; y.N = nn; y.K = ns;
         y.flags = G_TB | G_LOWERC;
         y.alpha = 1.0; y.beta = 0.0;
-        syrk.add(y, true);
+        syrk.add(y, 1);
       }
       syrk.end_launch(gemm_prec);
       if ((st = syrk.upload_all(h)) != SPAND_OK) return st;
@@ -773,6 +774,22 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
             tds.push_back(TDesc{sn.house.as<double>() + v_off[p], sn.house.as<double>() + tau_off[p],
                                 sn.house.as<double>() + t_off[p], sn.size[p], int32_t(r)});
         }
+      // S = V^T V into the T blocks (MFMA, upper tiles), then the T recurrence
+      GemmSeq vtv;
+      for (const TDesc& td : tds) {
+        GemmDesc q{};
+        q.A = td.V; q.lda = td.m;
+        q.B = td.V; q.ldb = td.m;
+        q.C = td.T; q.ldc = td.r;
+        q.M = td.r; q.N = td.r; q.K = td.m;
+        q.flags = G_TA;
+        q.alpha = 1.0; q.beta = 0.0;
+        vtv.add(q, 2);
+      }
+      vtv.end_launch(0);
+      if ((st = vtv.upload_all(h)) != SPAND_OK) return st;
+      vtv.launch(h, 0);
+      HIPCHK(hipGetLastError());
       DevBuf dtd;
       if ((st = upload(h, dtd, tds)) != SPAND_OK) return st;
       launch_build_t(dtd.as<TDesc>(), int32_t(tds.size()), h->stream);
@@ -814,6 +831,9 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
         sn.h_elim.push_back(e);
       }
       sn.tmp_elim = tmp;
+      sn.h_etile.clear();
+      for (int32_t s = 0; s < ne; ++s)
+        for (int32_t k0 = 0; k0 < sn.h_elim[s].ns; k0 += 64) sn.h_etile.push_back(ElimTile{s, k0});
       // forward target updates, grouped by receiving cluster in ascending s
       struct TI { int32_t n, s; int64_t row; };
       std::vector<TI> tis;
@@ -840,11 +860,16 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
           ++r;
         }
         ta.cend = int32_t(sn.h_contrib.size());
-        sn.h_target.push_back(ta);
+        for (int32_t r0 = 0; r0 < ta.nn; r0 += 64) {  // one workgroup per 64-row tile
+          ta.r0 = r0;
+          sn.h_target.push_back(ta);
+        }
         q = r;
       }
       sn.h_scale.clear();
       sn.h_house.clear();
+      sn.h_hr.clear();
+      sn.h_hv.clear();
       int64_t tmp2 = 0, tmp3 = 0;
       for (int32_t p = ne; p < nc; ++p) {
         if (sc_off[p] >= 0) {
@@ -865,7 +890,10 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
           hp.r = nref[p];
           hp.slot_p = sn.slot_ptr[p];
           hp.tmp = tmp3;
-          tmp3 += 3 * int64_t(sn.size[p]);
+          tmp3 += 2 * int64_t(nref[p]);
+          const int32_t hid = int32_t(sn.h_house.size());
+          for (int32_t j0 = 0; j0 < hp.r; j0 += 64) sn.h_hr.push_back(HouseTile{hid, j0});
+          for (int32_t r0 = 0; r0 < hp.np; r0 += 64) sn.h_hv.push_back(HouseTile{hid, r0});
           sn.h_house.push_back(hp);
         }
       }
@@ -877,6 +905,9 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       sn.n_target = int32_t(sn.h_target.size());
       sn.n_scale = int32_t(sn.h_scale.size());
       sn.n_house = int32_t(sn.h_house.size());
+      sn.n_etile = int32_t(sn.h_etile.size());
+      sn.n_hr = int32_t(sn.h_hr.size());
+      sn.n_hv = int32_t(sn.h_hv.size());
       if ((st = upload(h, sn.d_slot, sn.slot)) != SPAND_OK) return st;
       if ((st = upload(h, sn.d_nslot, nslot)) != SPAND_OK) return st;
       if ((st = upload(h, sn.d_elim, sn.h_elim)) != SPAND_OK) return st;
@@ -884,6 +915,9 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       if ((st = upload(h, sn.d_contrib, sn.h_contrib)) != SPAND_OK) return st;
       if ((st = upload(h, sn.d_scale, sn.h_scale)) != SPAND_OK) return st;
       if ((st = upload(h, sn.d_house, sn.h_house)) != SPAND_OK) return st;
+      if ((st = upload(h, sn.d_etile, sn.h_etile)) != SPAND_OK) return st;
+      if ((st = upload(h, sn.d_hr, sn.h_hr)) != SPAND_OK) return st;
+      if ((st = upload(h, sn.d_hv, sn.h_hv)) != SPAND_OK) return st;
       HIPCHK(hipStreamSynchronize(h->stream));
     }
 

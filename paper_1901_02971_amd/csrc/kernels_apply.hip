@@ -6,15 +6,17 @@
 //   k_elim_fwd    x_s <- L_s^{-1} x_s            (one workgroup per eliminated s;
 //                                                  blocked substitution with the
 //                                                  inverses of the diagonal blocks)
-//   k_target_fwd  x_n <- x_n - sum_s G_ns x_s     (one workgroup per receiving n,
-//                                                  contributions in ascending s)
+//   k_target_fwd  x_n <- x_n - sum_s G_ns x_s     (one workgroup per 64-row tile of a
+//                                                  receiving n, contributions in
+//                                                  ascending s)
 //   k_scale_fwd   x_p <- L_p^{-1} x_p
-//   k_house<1>    x_p <- Q_p^T x_p                (compact WY form)
+//   k_house_*     x_p <- Q_p^T x_p                (compact WY form, three tile launches)
 // Backward sweep (levels 1 -> L), the transposes in reverse order:
-//   k_house<-1>   x_p <- Q_p x_p
+//   k_house_*     x_p <- Q_p x_p
 //   k_scale_bwd   x_p <- L_p^{-T} x_p
-//   k_gather      neighbour dofs of every s into a contiguous buffer
-//   k_elim_bwd    x_s <- L_s^{-T} (x_s - G_{N_s s}^T x_{N_s})
+//   k_gather         neighbour dofs of every s into a contiguous buffer
+//   k_elim_bwd_gemv  t_s <- x_s - G_{N_s s}^T x_{N_s}  (one workgroup per 64 columns of s)
+//   k_elim_bwd       x_s <- L_s^{-T} t_s
 #include <hip/hip_runtime.h>
 
 #include "apply.h"
@@ -34,28 +36,68 @@ __device__ inline double wsum(double v) {
 // Both products stage 64x64 tiles of the matrix in LDS with coalesced loads (lanes
 // run down a column) and compute from LDS.  Thread (t & 63, t >> 6) owns row or
 // column t & 63 of the tile and right-hand sides g and g + 4 (g = t >> 6); `acc`
-// accumulates across calls.
+// accumulates across calls.  The next tile is loaded into registers while the
+// current one is used; loads go through the global address space so that waiting
+// for LDS results never waits for them.
 struct TileShared {
   double A[64][65];
   double x[64][RB];
   double out[64][RB];
 };
 
+typedef __attribute__((address_space(1))) const double gdouble;
+__device__ inline double gld(const double* p) { return *(gdouble*)p; }
+
+// A tile (64 x 64, rows [r0, r0 + 64) of a column-major matrix, columns [k0, k0 + 64))
+// and an x tile (64 x RB), held in registers between load and store.
+struct TileRegs {
+  double a[64 * 64 / AW];
+  double x[64 * RB / AW];
+};
+
+// x rows are x[k] or, with a slot list, x[xsl[k]]
+__device__ inline void tile_load(const double* __restrict__ A, int ld, int r0, int nrows, int k0, int ncols,
+                                 const double* __restrict__ x, int64_t ldx, int xrow0, int xrows, int nr,
+                                 const int32_t* __restrict__ xsl, TileRegs& t) {
+#pragma unroll
+  for (int u = 0; u < 64 * 64 / AW; ++u) {
+    const int e = threadIdx.x + u * AW;
+    const int r = e & 63, k = e >> 6;
+    t.a[u] = (r0 + r < nrows && k0 + k < ncols) ? gld(A + (r0 + r) + (int64_t)(k0 + k) * ld) : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < 64 * RB / AW; ++u) {
+    const int e = threadIdx.x + u * AW;
+    const int k = e & 63, c = e >> 6;
+    const int64_t xr = (xrow0 + k < xrows) ? (xsl ? (int64_t)xsl[xrow0 + k] : (int64_t)(xrow0 + k)) : 0;
+    t.x[u] = (xrow0 + k < xrows && c < nr) ? gld(x + xr + (int64_t)c * ldx) : 0.0;
+  }
+}
+
+__device__ inline void tile_store(const TileRegs& t, TileShared& sh) {
+#pragma unroll
+  for (int u = 0; u < 64 * 64 / AW; ++u) {
+    const int e = threadIdx.x + u * AW;
+    sh.A[e & 63][e >> 6] = t.a[u];
+  }
+#pragma unroll
+  for (int u = 0; u < 64 * RB / AW; ++u) {
+    const int e = threadIdx.x + u * AW;
+    sh.x[e & 63][e >> 6] = t.x[u];
+  }
+}
+
 // acc += A[(r0 + rr) + k*ld] x[k], k < ncols (rows beyond nrows read as zero)
 __device__ void tile_gemv_n(const double* __restrict__ A, int ld, int r0, int nrows, int ncols,
-                            const double* __restrict__ x, int64_t ldx, int nr, TileShared& sh, double acc[2]) {
+                            const double* __restrict__ x, int64_t ldx, int nr, TileShared& sh, double acc[2],
+                            const int32_t* __restrict__ xsl = nullptr) {
   const int rr = threadIdx.x & 63, g = threadIdx.x >> 6;
+  TileRegs t;
+  if (ncols > 0) tile_load(A, ld, r0, nrows, 0, ncols, x, ldx, 0, ncols, nr, xsl, t);
   for (int k0 = 0; k0 < ncols; k0 += 64) {
-    const int kw = min(64, ncols - k0);
-    for (int e = threadIdx.x; e < 64 * 64; e += AW) {
-      const int r = e & 63, k = e >> 6;
-      sh.A[r][k] = (r0 + r < nrows && k < kw) ? A[(r0 + r) + (int64_t)(k0 + k) * ld] : 0.0;
-    }
-    for (int e = threadIdx.x; e < 64 * RB; e += AW) {
-      const int k = e & 63, c = e >> 6;
-      sh.x[k][c] = (k < kw && c < nr) ? x[k0 + k + (int64_t)c * ldx] : 0.0;
-    }
+    tile_store(t, sh);
     __syncthreads();
+    if (k0 + 64 < ncols) tile_load(A, ld, r0, nrows, k0 + 64, ncols, x, ldx, k0 + 64, ncols, nr, xsl, t);
 #pragma unroll 8
     for (int k = 0; k < 64; ++k) {
       const double a = sh.A[rr][k];
@@ -68,19 +110,15 @@ __device__ void tile_gemv_n(const double* __restrict__ A, int ld, int r0, int nr
 
 // acc += sum_{r < nrows} A[r + (c0 + cc)*ld] x[r] for columns c0 + cc < ncols
 __device__ void tile_gemv_t(const double* __restrict__ A, int ld, int c0, int ncols, int nrows,
-                            const double* __restrict__ x, int64_t ldx, int nr, TileShared& sh, double acc[2]) {
+                            const double* __restrict__ x, int64_t ldx, int nr, TileShared& sh, double acc[2],
+                            const int32_t* __restrict__ xsl = nullptr) {
   const int cc = threadIdx.x & 63, g = threadIdx.x >> 6;
+  TileRegs t;
+  if (nrows > 0) tile_load(A, ld, 0, nrows, c0, ncols, x, ldx, 0, nrows, nr, xsl, t);
   for (int r0 = 0; r0 < nrows; r0 += 64) {
-    const int rw = min(64, nrows - r0);
-    for (int e = threadIdx.x; e < 64 * 64; e += AW) {
-      const int r = e & 63, k = e >> 6;
-      sh.A[r][k] = (r < rw && c0 + k < ncols) ? A[(r0 + r) + (int64_t)(c0 + k) * ld] : 0.0;
-    }
-    for (int e = threadIdx.x; e < 64 * RB; e += AW) {
-      const int r = e & 63, c = e >> 6;
-      sh.x[r][c] = (r < rw && c < nr) ? x[r0 + r + (int64_t)c * ldx] : 0.0;
-    }
+    tile_store(t, sh);
     __syncthreads();
+    if (r0 + 64 < nrows) tile_load(A, ld, r0 + 64, nrows, c0, ncols, x, ldx, r0 + 64, nrows, nr, xsl, t);
 #pragma unroll 8
     for (int r = 0; r < 64; ++r) {
       const double a = sh.A[r][cc];
@@ -94,8 +132,25 @@ __device__ void tile_gemv_t(const double* __restrict__ A, int ld, int c0, int nc
 // ---------------------------------------------------------------- triangular solves
 // Blocked solves on a vector segment v (n rows, nr <= RB columns, ld ldv) in the
 // apply scratch.  L is lower triangular (ld); its CHOL_NB-wide diagonal blocks have
-// the inverses Dinv (block k at k*CHOL_NB^2, ld = block width).
+// the inverses Dinv (block k at k*CHOL_NB^2, ld = block width), staged in LDS like
+// the matrix tiles.
 static_assert(CHOL_NB == 64, "tile solves assume 64-wide diagonal blocks");
+
+// sh.A <- the w x w inverse block D (ld w, zero outside), sh.x <- out (already in sh.out)
+__device__ inline void stage_dinv(const double* __restrict__ D, int w, TileShared& sh) {
+  double d[64 * 64 / AW];
+#pragma unroll
+  for (int u = 0; u < 64 * 64 / AW; ++u) {
+    const int e = threadIdx.x + u * AW;
+    const int r = e & 63, k = e >> 6;
+    d[u] = (r < w && k < w) ? gld(D + r + k * w) : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < 64 * 64 / AW; ++u) {
+    const int e = threadIdx.x + u * AW;
+    sh.A[e & 63][e >> 6] = d[u];
+  }
+}
 
 // L y = v in place: y_k = D_k^{-1} (v_k - L[k, :k] y[:k])
 __device__ void trsv_fwd(const double* __restrict__ L, int ld, const double* __restrict__ Dinv, int n, double* v,
@@ -108,13 +163,17 @@ __device__ void trsv_fwd(const double* __restrict__ L, int ld, const double* __r
     if (rr < w) {
       sh.out[rr][g] = (g < nr ? v[kb + rr + (int64_t)g * ldv] : 0.0) - acc[0];
       sh.out[rr][g + 4] = (g + 4 < nr ? v[kb + rr + (int64_t)(g + 4) * ldv] : 0.0) - acc[1];
+    } else {
+      sh.out[rr][g] = 0.0;
+      sh.out[rr][g + 4] = 0.0;
     }
+    stage_dinv(Dinv + (int64_t)(kb / 64) * 64 * 64, w, sh);
     __syncthreads();
     if (rr < w) {
-      const double* Dk = Dinv + (int64_t)(kb / 64) * 64 * 64;
       double y0 = 0.0, y1 = 0.0;
-      for (int k = 0; k <= rr; ++k) {
-        const double dv = Dk[rr + k * w];
+#pragma unroll 8
+      for (int k = 0; k < 64; ++k) {
+        const double dv = sh.A[rr][k];
         y0 += dv * sh.out[k][g];
         y1 += dv * sh.out[k][g + 4];
       }
@@ -139,13 +198,17 @@ __device__ void trsv_bwd(const double* __restrict__ L, int ld, const double* __r
     if (cc < w) {
       sh.out[cc][g] = (g < nr ? v[kb + cc + (int64_t)g * ldv] : 0.0) - acc[0];
       sh.out[cc][g + 4] = (g + 4 < nr ? v[kb + cc + (int64_t)(g + 4) * ldv] : 0.0) - acc[1];
+    } else {
+      sh.out[cc][g] = 0.0;
+      sh.out[cc][g + 4] = 0.0;
     }
+    stage_dinv(Dinv + (int64_t)bi * 64 * 64, w, sh);
     __syncthreads();
     if (cc < w) {
-      const double* Dk = Dinv + (int64_t)bi * 64 * 64;
       double x0 = 0.0, x1 = 0.0;
-      for (int q = cc; q < w; ++q) {
-        const double dv = Dk[q + cc * w];
+#pragma unroll 8
+      for (int q = 0; q < 64; ++q) {
+        const double dv = sh.A[q][cc];
         x0 += dv * sh.out[q][g];
         x1 += dv * sh.out[q][g + 4];
       }
@@ -187,20 +250,20 @@ __global__ void __launch_bounds__(AW) k_target_fwd(const TargetAp* __restrict__ 
   const TargetAp t = ts[blockIdx.x];
   const int32_t* sl = a.slot + t.slot_n;
   const int rr = threadIdx.x & 63, g = threadIdx.x >> 6;
-  for (int r0 = 0; r0 < t.nn; r0 += 64)
-    for (int c0 = 0; c0 < a.nrhs; c0 += RB) {
-      const int nr = min(RB, a.nrhs - c0);
-      double acc[2] = {0.0, 0.0};
-      for (int q = t.cbeg; q < t.cend; ++q) {
-        const TargetContrib tc = cs[q];
-        tile_gemv_n(tc.G, tc.ldG, r0, t.nn, tc.ns, a.tmp + tc.tmp_s + (int64_t)c0 * a.ldt, a.ldt, nr, sh, acc);
-      }
-      if (r0 + rr < t.nn) {
-        double* xp = a.x + sl[r0 + rr] + (int64_t)c0 * a.ldx;
-        if (g < nr) xp[(int64_t)g * a.ldx] -= acc[0];
-        if (g + 4 < nr) xp[(int64_t)(g + 4) * a.ldx] -= acc[1];
-      }
+  const int r0 = t.r0;
+  for (int c0 = 0; c0 < a.nrhs; c0 += RB) {
+    const int nr = min(RB, a.nrhs - c0);
+    double acc[2] = {0.0, 0.0};
+    for (int q = t.cbeg; q < t.cend; ++q) {
+      const TargetContrib tc = cs[q];
+      tile_gemv_n(tc.G, tc.ldG, r0, t.nn, tc.ns, a.tmp + tc.tmp_s + (int64_t)c0 * a.ldt, a.ldt, nr, sh, acc);
     }
+    if (r0 + rr < t.nn) {
+      double* xp = a.x + sl[r0 + rr] + (int64_t)c0 * a.ldx;
+      if (g < nr) xp[(int64_t)g * a.ldx] -= acc[0];
+      if (g + 4 < nr) xp[(int64_t)(g + 4) * a.ldx] -= acc[1];
+    }
+  }
 }
 
 __global__ void __launch_bounds__(AW) k_scale_fwd(const ScaleAp* __restrict__ ds, ApplyArgs a) {
@@ -223,69 +286,76 @@ __global__ void __launch_bounds__(AW) k_scale_bwd(const ScaleAp* __restrict__ ds
   scatter_seg(sl, e.np, a, e.tmp);
 }
 
-// Q_p in compact WY form, Q = I - V T V^T (T upper triangular r x r):
-// DIR = +1 applies Q^T = I - V T^T V^T, DIR = -1 applies Q.  Scratch of p:
-// [x: np][w: np][u: np] per right-hand side.
-template <int DIR>
-__global__ void __launch_bounds__(AW) k_house(const HouseAp* __restrict__ ds, ApplyArgs a) {
+// Q_p in compact WY form, Q = I - V T V^T (T upper triangular r x r).  DIR = +1
+// applies Q^T = I - V T^T V^T, DIR = -1 applies Q, in three launches over 64-wide
+// tiles (scratch of p: [w: r][u: r] per right-hand side):
+//   k_house_w    w = V^T x_p           one workgroup per 64 reflectors (x_p read through its slots)
+//   k_house_t    u = T^T w or u = T w  one workgroup per 64 reflectors
+//   k_house_v    x_p -= V u            one workgroup per 64 rows of p
+__global__ void __launch_bounds__(AW) k_house_w(const HouseAp* __restrict__ ds, const HouseTile* __restrict__ tl,
+                                                ApplyArgs a) {
   __shared__ TileShared sh;
-  const HouseAp e = ds[blockIdx.x];
-  const int np = e.np, r = e.r;
+  const HouseTile ht = tl[blockIdx.x];
+  const HouseAp e = ds[ht.p];
+  const int np = e.np, r = e.r, j0 = ht.j0;
   const int32_t* sl = a.slot + e.slot_p;
   const int cc = threadIdx.x & 63, g = threadIdx.x >> 6;
-  gather_seg(sl, np, a, e.tmp);
-  double* xs = a.tmp + e.tmp;
-  double* ws = xs + np;
-  double* us = ws + np;
+  double* ws = a.tmp + e.tmp;
+  for (int c0 = 0; c0 < a.nrhs; c0 += RB) {
+    const int nr = min(RB, a.nrhs - c0);
+    double acc[2] = {0.0, 0.0};
+    tile_gemv_t(e.V, np, j0, r, np, a.x + (int64_t)c0 * a.ldx, a.ldx, nr, sh, acc, sl);
+    if (j0 + cc < r) {
+      if (g < nr) ws[j0 + cc + (int64_t)(c0 + g) * a.ldt] = acc[0];
+      if (g + 4 < nr) ws[j0 + cc + (int64_t)(c0 + g + 4) * a.ldt] = acc[1];
+    }
+  }
+}
+
+template <int DIR>
+__global__ void __launch_bounds__(AW) k_house_t(const HouseAp* __restrict__ ds, const HouseTile* __restrict__ tl,
+                                                ApplyArgs a) {
+  __shared__ TileShared sh;
+  const HouseTile ht = tl[blockIdx.x];
+  const HouseAp e = ds[ht.p];
+  const int r = e.r, j0 = ht.j0;
+  const int cc = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const double* ws = a.tmp + e.tmp;
+  double* us = a.tmp + e.tmp + r;
   for (int c0 = 0; c0 < a.nrhs; c0 += RB) {
     const int nr = min(RB, a.nrhs - c0);
     const int64_t co = (int64_t)c0 * a.ldt;
-    for (int j0 = 0; j0 < r; j0 += 64) {  // w = V^T x
-      double acc[2] = {0.0, 0.0};
-      tile_gemv_t(e.V, np, j0, r, np, xs + co, a.ldt, nr, sh, acc);
-      if (j0 + cc < r) {
-        if (g < nr) ws[co + j0 + cc + (int64_t)g * a.ldt] = acc[0];
-        if (g + 4 < nr) ws[co + j0 + cc + (int64_t)(g + 4) * a.ldt] = acc[1];
-      }
+    double acc[2] = {0.0, 0.0};
+    if (DIR > 0)
+      tile_gemv_t(e.T, r, j0, r, r, ws + co, a.ldt, nr, sh, acc);
+    else
+      tile_gemv_n(e.T, r, j0, r, r, ws + co, a.ldt, nr, sh, acc);
+    if (j0 + cc < r) {
+      if (g < nr) us[co + j0 + cc + (int64_t)g * a.ldt] = acc[0];
+      if (g + 4 < nr) us[co + j0 + cc + (int64_t)(g + 4) * a.ldt] = acc[1];
     }
-    __threadfence_block();
-    __syncthreads();
-    for (int j = cc; j < r; j += 64) {  // u = T^T w (DIR > 0) or T w (DIR < 0)
-      double u0 = 0.0, u1 = 0.0;
-      const double* w0 = ws + co + (int64_t)g * a.ldt;        // valid when g < nr
-      const double* w1 = ws + co + (int64_t)(g + 4) * a.ldt;  // valid when g + 4 < nr
-      const bool h0 = g < nr, h1 = g + 4 < nr;
-      if (DIR > 0) {
-        const double* Tj = e.T + (int64_t)j * r;
-        for (int i = 0; i <= j; ++i) {
-          const double tv = Tj[i];
-          if (h0) u0 += tv * w0[i];
-          if (h1) u1 += tv * w1[i];
-        }
-      } else {
-        for (int i = j; i < r; ++i) {
-          const double tv = e.T[j + (int64_t)i * r];
-          if (h0) u0 += tv * w0[i];
-          if (h1) u1 += tv * w1[i];
-        }
-      }
-      if (g < nr) us[co + j + (int64_t)g * a.ldt] = u0;
-      if (g + 4 < nr) us[co + j + (int64_t)(g + 4) * a.ldt] = u1;
-    }
-    __threadfence_block();
-    __syncthreads();
-    for (int r0 = 0; r0 < np; r0 += 64) {  // x -= V u
-      double acc[2] = {0.0, 0.0};
-      tile_gemv_n(e.V, np, r0, np, r, us + co, a.ldt, nr, sh, acc);
-      if (r0 + cc < np) {
-        if (g < nr) xs[co + r0 + cc + (int64_t)g * a.ldt] -= acc[0];
-        if (g + 4 < nr) xs[co + r0 + cc + (int64_t)(g + 4) * a.ldt] -= acc[1];
-      }
-    }
-    __threadfence_block();
-    __syncthreads();
   }
-  scatter_seg(sl, np, a, e.tmp);
+}
+
+__global__ void __launch_bounds__(AW) k_house_v(const HouseAp* __restrict__ ds, const HouseTile* __restrict__ tl,
+                                                ApplyArgs a) {
+  __shared__ TileShared sh;
+  const HouseTile ht = tl[blockIdx.x];
+  const HouseAp e = ds[ht.p];
+  const int np = e.np, r = e.r, r0 = ht.j0;
+  const int32_t* sl = a.slot + e.slot_p;
+  const int rr = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const double* us = a.tmp + e.tmp + r;
+  for (int c0 = 0; c0 < a.nrhs; c0 += RB) {
+    const int nr = min(RB, a.nrhs - c0);
+    double acc[2] = {0.0, 0.0};
+    tile_gemv_n(e.V, np, r0, np, r, us + (int64_t)c0 * a.ldt, a.ldt, nr, sh, acc);
+    if (r0 + rr < np) {
+      double* xp = a.x + sl[r0 + rr] + (int64_t)c0 * a.ldx;
+      if (g < nr) xp[(int64_t)g * a.ldx] -= acc[0];
+      if (g + 4 < nr) xp[(int64_t)(g + 4) * a.ldx] -= acc[1];
+    }
+  }
 }
 
 __global__ void k_gather(const int32_t* __restrict__ nslot, int64_t len, ApplyArgs a) {
@@ -295,47 +365,62 @@ __global__ void k_gather(const int32_t* __restrict__ nslot, int64_t len, ApplyAr
   for (int c = 0; c < a.nrhs; ++c) a.gbuf[q + (int64_t)c * a.ldg] = a.x[s + (int64_t)c * a.ldx];
 }
 
-// t = x_s - G_{N_s s}^T x_{N_s}, then x_s = L_s^{-T} t
-__global__ void __launch_bounds__(AW) k_elim_bwd(const ElimAp* __restrict__ ds, ApplyArgs a) {
+// t = x_s - G_{N_s s}^T x_{N_s} for the 64 columns [k0, k0 + 64) of s: one
+// workgroup per column tile, t into the apply scratch of s
+__global__ void __launch_bounds__(AW) k_elim_bwd_gemv(const ElimAp* __restrict__ ds, const ElimTile* __restrict__ tl,
+                                                      ApplyArgs a) {
   __shared__ TileShared sh;
-  const ElimAp e = ds[blockIdx.x];
-  const int ns = e.ns;
+  const ElimTile et = tl[blockIdx.x];
+  const ElimAp e = ds[et.s];
+  const int ns = e.ns, k0 = et.k0;
   const int32_t* sl = a.slot + e.slot_s;
   const int cc = threadIdx.x & 63, g = threadIdx.x >> 6;
   for (int c0 = 0; c0 < a.nrhs; c0 += RB) {
     const int nr = min(RB, a.nrhs - c0);
-    for (int k0 = 0; k0 < ns; k0 += 64) {
-      double acc[2] = {0.0, 0.0};
-      tile_gemv_t(e.G, e.ld, k0, ns, e.nN, a.gbuf + e.slot_N + (int64_t)c0 * a.ldg, a.ldg, nr, sh, acc);
-      const int k = k0 + cc;
-      if (k < ns) {
-        if (g < nr)
-          a.tmp[e.tmp + k + (int64_t)(c0 + g) * a.ldt] = a.x[sl[k] + (int64_t)(c0 + g) * a.ldx] - acc[0];
-        if (g + 4 < nr)
-          a.tmp[e.tmp + k + (int64_t)(c0 + g + 4) * a.ldt] = a.x[sl[k] + (int64_t)(c0 + g + 4) * a.ldx] - acc[1];
-      }
+    double acc[2] = {0.0, 0.0};
+    tile_gemv_t(e.G, e.ld, k0, ns, e.nN, a.gbuf + e.slot_N + (int64_t)c0 * a.ldg, a.ldg, nr, sh, acc);
+    const int k = k0 + cc;
+    if (k < ns) {
+      if (g < nr)
+        a.tmp[e.tmp + k + (int64_t)(c0 + g) * a.ldt] = a.x[sl[k] + (int64_t)(c0 + g) * a.ldx] - acc[0];
+      if (g + 4 < nr)
+        a.tmp[e.tmp + k + (int64_t)(c0 + g + 4) * a.ldt] = a.x[sl[k] + (int64_t)(c0 + g + 4) * a.ldx] - acc[1];
     }
   }
-  __threadfence_block();
-  __syncthreads();
+}
+
+// x_s = L_s^{-T} t
+__global__ void __launch_bounds__(AW) k_elim_bwd(const ElimAp* __restrict__ ds, ApplyArgs a) {
+  __shared__ TileShared sh;
+  const ElimAp e = ds[blockIdx.x];
+  const int32_t* sl = a.slot + e.slot_s;
   for (int c0 = 0; c0 < a.nrhs; c0 += RB)
-    trsv_bwd(e.L, e.ld, e.Dinv, ns, a.tmp + e.tmp + (int64_t)c0 * a.ldt, a.ldt, min(RB, a.nrhs - c0), sh);
-  scatter_seg(sl, ns, a, e.tmp);
+    trsv_bwd(e.L, e.ld, e.Dinv, e.ns, a.tmp + e.tmp + (int64_t)c0 * a.ldt, a.ldt, min(RB, a.nrhs - c0), sh);
+  scatter_seg(sl, e.ns, a, e.tmp);
 }
 
 void apply_step_forward(const StepDev& s, const ApplyArgs& a, hipStream_t st) {
   if (s.n_elim) hipLaunchKernelGGL(k_elim_fwd, dim3(s.n_elim), dim3(AW), 0, st, s.elim, a);
   if (s.n_target) hipLaunchKernelGGL(k_target_fwd, dim3(s.n_target), dim3(AW), 0, st, s.target, s.contrib, a);
   if (s.n_scale) hipLaunchKernelGGL(k_scale_fwd, dim3(s.n_scale), dim3(AW), 0, st, s.scale, a);
-  if (s.n_house) hipLaunchKernelGGL(k_house<1>, dim3(s.n_house), dim3(AW), 0, st, s.house, a);
+  if (s.n_hr) {
+    hipLaunchKernelGGL(k_house_w, dim3(s.n_hr), dim3(AW), 0, st, s.house, s.hr, a);
+    hipLaunchKernelGGL(k_house_t<1>, dim3(s.n_hr), dim3(AW), 0, st, s.house, s.hr, a);
+    hipLaunchKernelGGL(k_house_v, dim3(s.n_hv), dim3(AW), 0, st, s.house, s.hv, a);
+  }
 }
 
 void apply_step_backward(const StepDev& s, const ApplyArgs& a, hipStream_t st) {
-  if (s.n_house) hipLaunchKernelGGL(k_house<-1>, dim3(s.n_house), dim3(AW), 0, st, s.house, a);
+  if (s.n_hr) {
+    hipLaunchKernelGGL(k_house_w, dim3(s.n_hr), dim3(AW), 0, st, s.house, s.hr, a);
+    hipLaunchKernelGGL(k_house_t<-1>, dim3(s.n_hr), dim3(AW), 0, st, s.house, s.hr, a);
+    hipLaunchKernelGGL(k_house_v, dim3(s.n_hv), dim3(AW), 0, st, s.house, s.hv, a);
+  }
   if (s.n_scale) hipLaunchKernelGGL(k_scale_bwd, dim3(s.n_scale), dim3(AW), 0, st, s.scale, a);
   if (s.n_elim) {
     if (s.nslot_len)
       hipLaunchKernelGGL(k_gather, dim3((s.nslot_len + 255) / 256), dim3(256), 0, st, s.nslot, s.nslot_len, a);
+    if (s.n_etile) hipLaunchKernelGGL(k_elim_bwd_gemv, dim3(s.n_etile), dim3(AW), 0, st, s.elim, s.etile, a);
     hipLaunchKernelGGL(k_elim_bwd, dim3(s.n_elim), dim3(AW), 0, st, s.elim, a);
   }
 }

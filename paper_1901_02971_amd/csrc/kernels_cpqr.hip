@@ -537,30 +537,21 @@ __global__ void __launch_bounds__(CQ_NT) k_cpqr(const SparsDesc* __restrict__ de
 }
 
 // Compact WY factor of Q = H_0 ... H_{r-1} = I - V T V^T (T upper triangular):
-// T_jj = tau_j, T[:j, j] = -tau_j T[:j, :j] (V[:, :j]^T v_j).  One workgroup per
-// interface; the strict upper part of T first holds V^T V.
+// T_jj = tau_j, T[:j, j] = -tau_j T[:j, :j] (V[:, :j]^T v_j).  On entry the upper
+// triangle of T holds S = V^T V (a batched GEMM); one workgroup per interface runs
+// the recurrence column by column, S[:j, j] staged in LDS before column j is
+// overwritten.  The strict lower triangle is set to zero for the tiled products of
+// the apply.
 __global__ void __launch_bounds__(CW) k_build_t(const TDesc* __restrict__ descs) {
   const TDesc d = descs[blockIdx.x];
-  const int m = d.m, r = d.r;
+  const int r = d.r;
   __shared__ double y[T_MAX_R];
-  const int64_t npair = (int64_t)r * (r - 1) / 2;
-  for (int64_t q = threadIdx.x; q < npair; q += CW) {  // pair (i, j), i < j, packed by columns
-    int j = (int)((1.0 + sqrt(1.0 + 8.0 * (double)q)) * 0.5);
-    while ((int64_t)j * (j - 1) / 2 > q) --j;
-    while ((int64_t)(j + 1) * j / 2 <= q) ++j;
-    const int i = (int)(q - (int64_t)j * (j - 1) / 2);
-    const double* vi = d.V + (int64_t)i * m;
-    const double* vj = d.V + (int64_t)j * m;
-    double s = vi[j];  // v_j[j] = 1
-    for (int k = j + 1; k < m; ++k) s += vi[k] * vj[k];
-    d.T[i + (int64_t)j * r] = s;
+  for (int64_t q = threadIdx.x; q < (int64_t)r * r; q += CW) {
+    const int i = (int)(q % r), j = (int)(q / r);
+    if (i > j) d.T[q] = 0.0;
   }
-  __threadfence_block();
-  __syncthreads();
   for (int j = 0; j < r; ++j) {
     const double tj = d.tau[j];
-    // T[i][j] = -tau_j sum_{l=i}^{j-1} T[i][l] Y[l][j]; Y[:j, j] is staged in LDS
-    // before column j is overwritten (r <= T_MAX_R, checked by the host)
     if (j > 0) {
       for (int i = threadIdx.x; i < j; i += CW) y[i] = d.T[i + (int64_t)j * r];
       __syncthreads();

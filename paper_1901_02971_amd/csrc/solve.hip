@@ -30,6 +30,12 @@ StepDev step_dev(const StepNum& s) {
   d.contrib = s.d_contrib.as<TargetContrib>();
   d.scale = s.d_scale.as<ScaleAp>();
   d.house = s.d_house.as<HouseAp>();
+  d.etile = s.d_etile.as<ElimTile>();
+  d.n_etile = s.n_etile;
+  d.hr = s.d_hr.as<HouseTile>();
+  d.hv = s.d_hv.as<HouseTile>();
+  d.n_hr = s.n_hr;
+  d.n_hv = s.n_hv;
   d.slot = s.d_slot.as<int32_t>();
   d.nslot = s.d_nslot.as<int32_t>();
   d.nslot_len = s.nslot_len;
