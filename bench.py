@@ -14,8 +14,10 @@ Prints one JSON line (see the repository's benchmark contract).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -32,6 +34,40 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3.0}
 # FP64 vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
 FP64_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 HBM_GBS = 8000.0
+
+
+CPQR_SRC = os.path.join(ROOT, "paper_1901_02971_amd", "csrc", "kernels_cpqr.hip")
+TRAFFIC_MD = os.path.join(ROOT, "profiles", "k_cpqr_lap128_tol1e-2_traffic.md")
+
+
+def cpqr_traffic():
+    """HBM bytes per CPQR launch measured with rocprofv3 --pmc (FETCH_SIZE + WRITE_SIZE,
+    scaled by a plain-copy calibration), from the committed summary.  None unless the
+    summary was taken on the kernel source as it is now."""
+    try:
+        with open(CPQR_SRC, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+        with open(TRAFFIC_MD) as f:
+            txt = f.read()
+    except OSError:
+        return None
+    m_sha = re.search(r"kernel source sha256: `([0-9a-f]{64})`", txt)
+    m_val = re.search(r"HBM bytes per launch: `([0-9.eE+]+)`", txt)
+    if not m_sha or not m_val or m_sha.group(1) != sha:
+        return None
+    return float(m_val.group(1))
+
+
+def copy_calibration(mib=1024, reps=3):
+    """A plain device copy of known size for scaling the FETCH_SIZE / WRITE_SIZE
+    counters: reads and writes exactly mib MiB per dispatch."""
+    import torch
+    x = torch.ones(mib * 1024 * 1024 // 8, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": x.numel() * 8, "dispatches": reps}), flush=True)
 
 
 def workload(name):
@@ -89,12 +125,17 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-2)
     ap.add_argument("--prec", default="fp64", choices=list(PREC))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration for the traffic figure)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is a design, "
               f"not part of this build", file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import torch
     from paper_1901_02971_amd import Solver
     assert torch.cuda.is_available(), "needs a GPU"
@@ -145,7 +186,7 @@ def main():
     apply_s = float(np.mean([x["apply_seconds"] / max(1, x["apply_calls"]) for x in ss]))
     apply_gbs = ss[-1]["apply_bytes"] / apply_s / 1e9 if apply_s > 0 else 0.0
     kernels = {
-        "cpqr": {"kernel": "k_sparsify (truncated CPQR of every interface, Sec. 2.6.1)", "bound": "alu",
+        "cpqr": {"kernel": "k_cpqr (register-resident truncated CPQR of every interface, Sec. 2.6.1)", "bound": "alu",
                  "launches": cpqr_n, "ms_total": round(cpqr_s * 1e3, 2),
                  "avg_launch_us": round(cpqr_s / max(cpqr_n, 1) * 1e6, 1),
                  "flops_per_launch": fs[-1]["cpqr_flops"] / max(cpqr_n, 1),
@@ -163,8 +204,9 @@ def main():
     share = {"cpqr": cpqr_s, "apply": apply_s * ss[-1]["apply_calls"], "schur": schur_s}
     dom = max(share, key=share.get)
     k = kernels[dom]
+    traffic = cpqr_traffic() if dom == "cpqr" else None
     roof = {"bound": k["bound"], "kernel": k["kernel"], "achieved": k["achieved"], "peak": k["peak"],
-            "unit": k["unit"], "frac": k["frac"], "traffic": None,
+            "unit": k["unit"], "frac": k["frac"], "traffic": traffic,
             "seconds_per_step": round(share[dom], 4)}
     out = {"metric": METRIC, "value": round(per, 4), "unit": "s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(per * 1e3, 2), "higher_is_better": False,
