@@ -116,6 +116,50 @@ def cpu_baseline(tol, budget_s=30.0):
                        f"relres {rr[0]:.1e}); scaled x{scale:.0f} in N and x8 in RHS for t_S")}
 
 
+def bench_batch(args):
+    """The batched workload: P variable-coefficient grids (edges U{24..48}, coefficients
+    10^U(-2,2)), 16 right-hand sides each, factored with spand_factor_batch and solved
+    with spand_solve_batch; one step = factor + solve of all P problems."""
+    import gridgen
+    import torch
+    from paper_1901_02971_amd import Solver, factor_batch, solve_batch
+    dev = torch.device("cuda:0")
+    P = args.problems
+    probs = [gridgen.batched_problem(j) for j in range(P)]
+    t0 = time.perf_counter()
+    solvers = [Solver.from_problem(p, L) for p, _, L in probs]
+    t_P = time.perf_counter() - t0
+    vals = [torch.from_numpy(p.values).to(dev) for p, _, _ in probs]
+    bt = [torch.from_numpy(np.ascontiguousarray(b.T)).to(dev) for _, b, _ in probs]
+    xt = [torch.empty_like(t) for t in bt]
+    prec = PREC[args.prec]
+
+    def step():
+        factor_batch(solvers, vals, args.tol, 0, prec)
+        return solve_batch(solvers, bt, xt, 1e-12, 500)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        it, rr, _ = step()
+    torch.cuda.synchronize()
+    per = (time.perf_counter() - t0) / args.steps
+    ntot = sum(p.n for p, _, _ in probs)
+    out = {"metric": "spaND batched factor+PCG problems/s (variable-coefficient grids, 16 RHS each, to 1e-12)",
+           "value": round(P / per, 2), "unit": "problems/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(per * 1e3, 2), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.prec == "fp64" else args.prec,
+           "data": "synthetic",
+           "config": {"workload": f"{P} variable-coefficient 3D grids, edges U{{24..48}}, 10^U(-2,2), "
+                                  f"16 RHS each, eps={args.tol:g}, PCG to 1e-12",
+                      "problems": P, "total_N": int(ntot), "tol": args.tol, "nrhs": 16, "schur_prec": args.prec},
+           "t_P": round(t_P, 2), "pcg_iters_max": int(it.max()), "pcg_iters_mean": round(float(it.mean()), 2),
+           "relres_max": float(rr.max())}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +169,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-2)
     ap.add_argument("--prec", default="fp64", choices=list(PREC))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--problems", type=int, default=256, help="problems of the batched workload (--config c5)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration for the traffic figure)")
     args = ap.parse_args()
@@ -136,6 +181,13 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.config == "c5":
+        # Two runs of the 64-problem batch printed their result line and then ended
+        # with a segmentation fault while the process shut down; the cause is not
+        # known, so this mode stays off until it is.
+        raise SystemExit("bench.py --config c5 is disabled: the batched run crashed at process exit "
+                         "after printing its result (cause not yet found); the batched entry points are "
+                         "exercised by tests/test_gpu_batch.py and tests/test_gpu_golden.py")
     import torch
     from paper_1901_02971_amd import Solver
     assert torch.cuda.is_available(), "needs a GPU"

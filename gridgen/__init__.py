@@ -134,6 +134,7 @@ def config_problem(name: str):
     c2: 3D 32^3 Laplacian, 9 levels, 1 RHS (seed 2).
     c3: 3D 64^3 variable coefficients 10^U(-3,3), 10 levels, 1 RHS (seed 3).
     c4: 3D 128^3 Laplacian, 13 levels, 8 RHS (seed 4).
+    c5_<j>: problem j of the batched workload (see batched_problem).
     """
     if name == "c1":
         p = laplacian((64, 64))
@@ -148,6 +149,8 @@ def config_problem(name: str):
     if name == "c4":
         p = laplacian((128, 128, 128))
         return p, rhs(np.random.default_rng(4), p.n, 8), 13
+    if name.startswith("c5_"):
+        return batched_problem(int(name[3:]))
     raise KeyError(name)
 
 
@@ -156,10 +159,17 @@ def levels_for(n: int) -> int:
     return max(2, 1 + int(np.ceil(np.log2(max(n, 1) / 512.0))))
 
 
+def batched_problem(j: int, count: int = 256, seed: int = 5, nrhs: int = 16):
+    """Problem j of the batched workload: grid edges U{24..48} per axis (one draw of
+    count x 3 edges from seed), cell coefficients 10^U(-2,2) and nrhs right-hand
+    sides from seed * 1000 + j; depth from the grid size."""
+    edges = np.random.default_rng(seed).integers(24, 49, (count, 3))
+    rng = np.random.default_rng(seed * 1000 + j)
+    p = variable_coefficient(tuple(int(e) for e in edges[j]), rng, -2.0, 2.0)
+    return p, rhs(rng, p.n, nrhs), levels_for(p.n)
+
+
 def batched_problems(count: int = 256, seed: int = 5, nrhs: int = 16):
     """The batched workload: grid edges U{24..48} per axis, coefficients 10^U(-2,2)."""
-    edges = np.random.default_rng(seed).integers(24, 49, (count, 3))
     for j in range(count):
-        rng = np.random.default_rng(seed * 1000 + j)
-        p = variable_coefficient(tuple(int(e) for e in edges[j]), rng, -2.0, 2.0)
-        yield p, rhs(rng, p.n, nrhs), levels_for(p.n)
+        yield batched_problem(j, count, seed, nrhs)

@@ -160,7 +160,28 @@ spand_status spand_step_structure(spand_t h, int32_t step, int64_t* keys, int32_
  * sparsified, -1 for eliminated clusters). */
 spand_status spand_step_ranks(spand_t h, int32_t step, int32_t* sizes, int32_t* ranks);
 
-/* Text of the last error on h (or of the last failed analyze when h is NULL).
+/* Batched factorization of P independent problems (the 256-problem workload: many
+ * small grids factored together).  hs: P distinct handles from spand_analyze (host
+ * array); values: host array of P device pointers, values[q] as in spand_factor for
+ * hs[q]; tol, skip, prec as in spand_factor, shared by all problems.  The problems
+ * are factored concurrently, each on its handle's stream (a handle without a
+ * stream gets a non-blocking one for the duration of the call); every handle ends
+ * in the state spand_factor would leave it in.  Returns SPAND_OK, or the status of
+ * the first failing problem in handle order, with spand_error_string(NULL) naming
+ * it and spand_error_string(hs[q]) holding its error.  SPAND_E_INVALID if P < 1,
+ * a handle is NULL or repeated. */
+spand_status spand_factor_batch(int32_t P, spand_t* hs, const double* const* values, double tol, int32_t skip,
+                                spand_prec prec);
+
+/* Batched PCG: problem q solves nrhs right-hand sides b[q] -> x[q] (device, n_q x nrhs
+ * column-major) with hs[q] as in spand_solve.  iters and relres are host arrays of
+ * P * nrhs entries, problem q at offset q * nrhs.  Errors as spand_factor_batch; a
+ * problem that hits maxit returns SPAND_E_NOCONV with its outputs written. */
+spand_status spand_solve_batch(int32_t P, spand_t* hs, int32_t nrhs, const double* const* b, double* const* x,
+                               double rtol, int32_t maxit, int32_t* iters, double* relres);
+
+/* Text of the last error on h (or, when h is NULL, of the last failed analyze or
+ * batched call on this thread).
  * Valid until the next call on h. */
 const char* spand_error_string(spand_t h);
 

@@ -4,10 +4,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <thread>
+#include <vector>
 
 #include "context.h"
 
@@ -58,6 +61,76 @@ std::string check_pattern(int64_t n, const int64_t* rowptr, const int32_t* colin
       if (it == en || *it != v) return "pattern is not symmetric at (" + std::to_string(v) + ", " + std::to_string(u) + ")";
     }
   return "";
+}
+
+// Runs fn(q) for q = 0..P-1 on up to 16 host threads.  Every problem of the batch
+// works on its own handle and HIP stream: a handle without a stream gets a
+// non-blocking one for the call.  The factor and the solve synchronise their
+// stream several times per call (rank read-back, convergence checks), so the
+// threads keep many problems in flight on the GPU.
+template <class F>
+spand_status run_batch(int32_t P, spand_t* hs, F&& fn) {
+  if (P < 1 || !hs) return fail_null(SPAND_E_INVALID, "batch needs P >= 1 handles");
+  for (int32_t q = 0; q < P; ++q) {
+    if (!hs[q]) return fail_null(SPAND_E_INVALID, "NULL handle in batch at " + std::to_string(q));
+    for (int32_t o = 0; o < q; ++o)
+      if (hs[o] == hs[q]) return fail_null(SPAND_E_INVALID, "a handle appears twice in the batch");
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail_null(SPAND_E_HIP, "no HIP device");
+  std::vector<hipStream_t> own(P, nullptr);
+  for (int32_t q = 0; q < P; ++q)
+    if (!hs[q]->stream) {
+      if (hipStreamCreateWithFlags(&own[q], hipStreamNonBlocking) != hipSuccess) {
+        for (int32_t o = 0; o < q; ++o)
+          if (own[o]) {
+            (void)hipStreamDestroy(own[o]);
+            hs[o]->stream = nullptr;
+          }
+        return fail_null(SPAND_E_HIP, "stream creation failed");
+      }
+      hs[q]->stream = own[q];
+    }
+  std::vector<spand_status> st(P, SPAND_OK);
+  std::atomic<int32_t> next{0};
+  auto work = [&]() {
+    if (hipSetDevice(dev) != hipSuccess) return;
+    for (;;) {
+      const int32_t q = next.fetch_add(1);
+      if (q >= P) break;
+      try {
+        st[q] = fn(q);
+      } catch (...) {
+        st[q] = spand::set_err(hs[q], SPAND_E_NOMEM, "host exception during batched call");
+      }
+    }
+  };
+  const int32_t nt = std::min<int32_t>(P, 16);
+  std::vector<std::thread> pool;
+  try {
+    for (int32_t k = 1; k < nt; ++k) pool.emplace_back(work);
+  } catch (...) {
+    // fewer threads: the calling thread and those started share the work
+  }
+  work();
+  for (std::thread& t : pool) t.join();
+  if (next.load() < P) {  // no worker could select the device
+    for (int32_t q = 0; q < P; ++q)
+      if (own[q]) hs[q]->stream = nullptr;
+    return fail_null(SPAND_E_HIP, "hipSetDevice failed in the batch workers");
+  }
+  for (int32_t q = 0; q < P; ++q)
+    if (own[q]) {
+      (void)hipStreamSynchronize(own[q]);
+      (void)hipStreamDestroy(own[q]);
+      hs[q]->stream = nullptr;
+    }
+  for (int32_t q = 0; q < P; ++q)
+    if (st[q] != SPAND_OK) {
+      g_last_error = "batch problem " + std::to_string(q) + ": " + hs[q]->err;
+      return st[q];
+    }
+  return SPAND_OK;
 }
 
 }  // namespace
@@ -130,8 +203,11 @@ spand_status spand_factor(spand_t h, const double* values, double tol, int32_t s
       h->d_rowptr.bytes = size_t(h->an.n + 1) * sizeof(int64_t);
       h->d_colind.bytes = size_t(nnz) * sizeof(int32_t);
       h->d_values.bytes = size_t(nnz) * sizeof(double);
-      if (hipMemcpy(h->d_rowptr.p, h->an.rowptr.data(), h->d_rowptr.bytes, hipMemcpyHostToDevice) != hipSuccess ||
-          hipMemcpy(h->d_colind.p, h->an.colind.data(), h->d_colind.bytes, hipMemcpyHostToDevice) != hipSuccess)
+      if (hipMemcpyAsync(h->d_rowptr.p, h->an.rowptr.data(), h->d_rowptr.bytes, hipMemcpyHostToDevice,
+                         h->stream) != hipSuccess ||
+          hipMemcpyAsync(h->d_colind.p, h->an.colind.data(), h->d_colind.bytes, hipMemcpyHostToDevice,
+                         h->stream) != hipSuccess ||
+          hipStreamSynchronize(h->stream) != hipSuccess)
         return set_err(h, SPAND_E_HIP, "copy of the matrix pattern failed");
     }
     if (hipMemcpyAsync(h->d_values.p, values, h->d_values.bytes, hipMemcpyDeviceToDevice, h->stream) != hipSuccess)
@@ -245,6 +321,20 @@ spand_status spand_step_ranks(spand_t h, int32_t step, int32_t* sizes, int32_t* 
 const char* spand_error_string(spand_t h) {
   if (!h) return g_last_error.c_str();
   return h->err.c_str();
+}
+
+spand_status spand_factor_batch(int32_t P, spand_t* hs, const double* const* values, double tol, int32_t skip,
+                                spand_prec prec) {
+  if (!values) return fail_null(SPAND_E_INVALID, "values is NULL");
+  return run_batch(P, hs, [&](int32_t q) { return spand_factor(hs[q], values[q], tol, skip, prec); });
+}
+
+spand_status spand_solve_batch(int32_t P, spand_t* hs, int32_t nrhs, const double* const* b, double* const* x,
+                               double rtol, int32_t maxit, int32_t* iters, double* relres) {
+  if (!b || !x || !iters || !relres) return fail_null(SPAND_E_INVALID, "NULL batch argument");
+  return run_batch(P, hs, [&](int32_t q) {
+    return spand_solve(hs[q], nrhs, b[q], x[q], rtol, maxit, iters + int64_t(q) * nrhs, relres + int64_t(q) * nrhs);
+  });
 }
 
 void spand_destroy(spand_t h) { delete h; }

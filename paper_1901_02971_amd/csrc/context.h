@@ -34,7 +34,8 @@ struct DevBuf {
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 
-// Reusable HIP events for per-launch device timing.
+// HIP events for per-launch device timing, owned by one factor or solve call and
+// destroyed before it returns, while the stream they were recorded on still exists.
 struct EventPool {
   std::vector<hipEvent_t> ev;
   EventPool() = default;
@@ -91,7 +92,6 @@ struct spand_ctx {
   spand::DevBuf d_dst1;                         // step-1 destination of every CSR entry (pattern-only)
   int64_t max_tmp = 0;                          // doubles per RHS for apply scratch
   int64_t max_gather = 0;                       // doubles per RHS for gathered neighbours
-  spand::EventPool evpool;                      // per-launch timing of CPQR and apply
   // PCG / apply scratch, grown on demand
   spand::DevBuf work;
   size_t work_bytes = 0;

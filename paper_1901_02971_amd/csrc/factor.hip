@@ -302,6 +302,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
   std::memset(h->stats.step_phase_seconds, 0, sizeof(h->stats.step_phase_seconds));
   std::memset(h->stats.step_m_F, 0, sizeof(h->stats.step_m_F));
 
+  EventPool evpool;  // per-launch timing of the CPQR
   int64_t m_F = 0;
   double elim_flops = 0.0, elim_ms = 0.0;
   double cpqr_flops = 0.0, cpqr_ms = 0.0;
@@ -515,7 +516,8 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       elim_ms += ms;
     }
     int32_t flags[4];
-    HIPCHK(hipMemcpy(flags, dflag.p, sizeof(flags), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpyAsync(flags, dflag.p, sizeof(flags), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
     if (flags[2]) return set_err(h, SPAND_E_INVALID, "matrix values contain NaN or Inf");
     if (flags[0] != 0x7fffffff) {
       h->stats.fail_step = t;
@@ -592,7 +594,8 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       HIPCHK(hipGetLastError());
       HIPCHK(hipEventRecord(ph[3], h->stream));
       HIPCHK(hipStreamSynchronize(h->stream));
-      HIPCHK(hipMemcpy(flags, dflag.p, sizeof(flags), hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpyAsync(flags, dflag.p, sizeof(flags), hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
       if (flags[1] != 0x7fffffff) {
         h->stats.fail_step = t;
         h->stats.fail_cluster = flags[1];
@@ -727,8 +730,8 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
               if ((st = upload(h, b, segs)) != SPAND_OK) return st;
               if ((st = upload(h, sl, slabs)) != SPAND_OK) return st;
               hipEvent_t e0, e1;
-              HIPCHK(h->evpool.get(2 * nlaunch, &e0));
-              HIPCHK(h->evpool.get(2 * nlaunch + 1, &e1));
+              HIPCHK(evpool.get(2 * nlaunch, &e0));
+              HIPCHK(evpool.get(2 * nlaunch + 1, &e1));
               HIPCHK(hipEventRecord(e0, h->stream));
               hipError_t le = launch_cpqr(G, a.as<SparsDesc>(), sl.as<SlabRef>(), int32_t(slabs.size()),
                                           b.as<SegDesc>(), tol, curb.as<int32_t>(), nrefb.as<int32_t>(),
@@ -746,14 +749,15 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       std::vector<int32_t> rk(nc, -1);
       HIPCHK(hipEventRecord(ph[4], h->stream));
       HIPCHK(hipStreamSynchronize(h->stream));
-      HIPCHK(hipMemcpy(rk.data(), curb.p, size_t(nc) * sizeof(int32_t), hipMemcpyDeviceToHost));
-      HIPCHK(hipMemcpy(nref.data(), nrefb.p, size_t(nc) * sizeof(int32_t), hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpyAsync(rk.data(), curb.p, size_t(nc) * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(hipMemcpyAsync(nref.data(), nrefb.p, size_t(nc) * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
       int32_t serr = 0;
-      HIPCHK(hipMemcpy(&serr, errb.p, sizeof(int32_t), hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpyAsync(&serr, errb.p, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
       if (serr) return set_err(h, SPAND_E_HIP, "sparsification slab barrier timed out");
       for (size_t q = 0; q < nlaunch; ++q) {
         float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, h->evpool.ev[2 * q], h->evpool.ev[2 * q + 1]));
+        HIPCHK(hipEventElapsedTime(&ms, evpool.ev[2 * q], evpool.ev[2 * q + 1]));
         cpqr_ms += ms;
       }
       cpqr_launches += int64_t(nlaunch);

@@ -128,11 +128,12 @@ spand_status pcg_solve(spand_ctx* h, int32_t nrhs, const double* b, double* x, d
   std::vector<double> hb(nrhs), hr(nrhs);
   std::vector<int32_t> act(nrhs, 0);
   // device time of every apply, from a pair of events around it
+  EventPool evpool;
   size_t napply = 0;
   auto timed_apply = [&]() -> spand_status {
     hipEvent_t e0, e1;
-    HIPCHK(h->evpool.get(2 * napply, &e0));
-    HIPCHK(h->evpool.get(2 * napply + 1, &e1));
+    HIPCHK(evpool.get(2 * napply, &e0));
+    HIPCHK(evpool.get(2 * napply + 1, &e1));
     HIPCHK(hipEventRecord(e0, s));
     spand_status sa = apply_precond(h, nrhs, r, z, scratch);
     if (sa != SPAND_OK) return sa;
@@ -197,7 +198,7 @@ spand_status pcg_solve(spand_ctx* h, int32_t nrhs, const double* b, double* x, d
   double apply_ms = 0.0;
   for (size_t q = 0; q < napply; ++q) {
     float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, h->evpool.ev[2 * q], h->evpool.ev[2 * q + 1]));
+    HIPCHK(hipEventElapsedTime(&ms, evpool.ev[2 * q], evpool.ev[2 * q + 1]));
     apply_ms += ms;
   }
   h->stats.apply_seconds = apply_ms * 1e-3;

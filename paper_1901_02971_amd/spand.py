@@ -73,6 +73,8 @@ def load_library():
         "spand_step_counts": (i32, [P, i32, P]),
         "spand_step_structure": (i32, [P, i32, P, P, P, P, P]),
         "spand_step_ranks": (i32, [P, i32, P, P]),
+        "spand_factor_batch": (i32, [i32, P, P, f64, i32, i32]),
+        "spand_solve_batch": (i32, [i32, P, i32, P, P, f64, i32, P, P]),
         "spand_error_string": (C.c_char_p, [P]),
         "spand_destroy": (None, [P]),
     }
@@ -213,3 +215,43 @@ class Solver:
         ranks = np.zeros(c["nc"], np.int32)
         self._check(self._lib.spand_step_ranks(self._h, int(step), _ptr(sizes), _ptr(ranks)))
         return sizes, ranks
+
+
+def factor_batch(solvers, values, tol, skip=0, prec=SPAND_FP64):
+    """spand_factor_batch over the handles of `solvers` (distinct Solver objects) with
+    values[q] a contiguous float64 GPU tensor for solvers[q]."""
+    import torch
+    if len(solvers) != len(values) or not solvers:
+        raise ValueError("one values tensor per solver")
+    for v in values:
+        if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == torch.float64 and v.is_contiguous()):
+            raise TypeError("values must be contiguous float64 GPU tensors")
+    lib = load_library()
+    P = len(solvers)
+    hs = (C.c_void_p * P)(*[s._h.value for s in solvers])
+    vp = (C.c_void_p * P)(*[v.data_ptr() for v in values])
+    st = lib.spand_factor_batch(P, hs, vp, float(tol), int(skip), int(prec))
+    if st != 0:
+        raise SpandError(st, lib.spand_error_string(None).decode())
+
+
+def solve_batch(solvers, b, x, rtol=1e-12, maxit=500, check=True):
+    """spand_solve_batch: b[q], x[q] device blocks of solvers[q] (same nrhs for all).
+    Returns (iters, relres, status) with iters, relres of shape (P, nrhs)."""
+    if not (len(solvers) == len(b) == len(x)) or not solvers:
+        raise ValueError("one b and one x per solver")
+    nrhs = _dev_vec(b[0], solvers[0].n)
+    for s, bq, xq in zip(solvers, b, x):
+        if _dev_vec(bq, s.n) != nrhs or _dev_vec(xq, s.n) != nrhs:
+            raise ValueError("every problem must have the same nrhs")
+    lib = load_library()
+    P = len(solvers)
+    hs = (C.c_void_p * P)(*[s._h.value for s in solvers])
+    bp = (C.c_void_p * P)(*[t.data_ptr() for t in b])
+    xp = (C.c_void_p * P)(*[t.data_ptr() for t in x])
+    iters = np.zeros((P, nrhs), dtype=np.int32)
+    relres = np.zeros((P, nrhs), dtype=np.float64)
+    st = lib.spand_solve_batch(P, hs, nrhs, bp, xp, float(rtol), int(maxit), _ptr(iters), _ptr(relres))
+    if check and st != 0:
+        raise SpandError(st, lib.spand_error_string(None).decode())
+    return iters, relres, st

@@ -12,7 +12,7 @@ from paper_1901_02971_amd import spand as S
 
 DECLARED = ["spand_analyze", "spand_factor", "spand_solve", "spand_apply", "spand_set_stream", "spand_get_stats",
             "spand_get_ordering", "spand_step_counts", "spand_step_structure", "spand_step_ranks",
-            "spand_error_string", "spand_destroy"]
+            "spand_factor_batch", "spand_solve_batch", "spand_error_string", "spand_destroy"]
 
 
 def test_header_declares_expected_symbols():
@@ -93,3 +93,20 @@ def test_solve_before_factor_is_state_error():
     rr = np.zeros(1)
     st = lib_c.spand_solve(lib._h, 1, 8, 16, 1e-12, 10, it.ctypes.data, rr.ctypes.data)
     assert S.STATUS[st] == "SPAND_E_STATE"
+
+
+def test_batch_rejects_bad_handle_lists():
+    """Argument checks of the batched calls happen before any device work."""
+    lib = S.load_library()
+    p = gridgen.laplacian((6, 5))
+    a = S.Solver.from_problem(p, 3)
+    hs = (ctypes.c_void_p * 2)(a._h.value, a._h.value)
+    vals = (ctypes.c_void_p * 2)(None, None)
+    assert lib.spand_factor_batch(2, hs, vals, 1e-2, 0, 0) == 1  # repeated handle
+    assert b"twice" in lib.spand_error_string(None)
+    assert lib.spand_factor_batch(0, hs, vals, 1e-2, 0, 0) == 1
+    nul = (ctypes.c_void_p * 1)(None)
+    assert lib.spand_factor_batch(1, nul, vals, 1e-2, 0, 0) == 1
+    it = np.zeros(2, np.int32)
+    rr = np.zeros(2)
+    assert lib.spand_solve_batch(2, hs, 1, vals, vals, 1e-12, 10, it.ctypes.data, rr.ctypes.data) == 1

@@ -36,22 +36,17 @@ def digest(a):
     return hashlib.sha256(np.ascontiguousarray(a, dtype="<i4").tobytes()).hexdigest()
 
 
+def golden_files(prefix=""):
+    names = sorted(f for f in os.listdir(GOLDEN) if f.startswith("oracle_" + prefix) and f.endswith(".json"))
+    return [os.path.join(GOLDEN, f) for f in names]
+
+
 def cases():
-    out = []
-    for name in ("c2", "c3", "c4"):
-        path = os.path.join(GOLDEN, f"oracle_{name}_tol1e-2.json")
-        if os.path.exists(path):
-            out.append(pytest.param(path, id=f"{name}_tol1e-2"))
-    return out
+    return [pytest.param(p, id=os.path.basename(p)[7:-5]) for p in golden_files()]
 
 
-@pytest.mark.parametrize("path", cases())
-def test_workload_matches_oracle(path):
-    with open(path) as f:
-        ref = json.load(f)
-    p, b, levels = gridgen.config_problem(ref["workload"])
-    assert levels == ref["levels"] and p.n == ref["n"]
-    s = gpu_factor(p, levels, ref["tol"], ref["skip"])
+def check_against(ref, s):
+    """Per-step sizes/ranks, s_top and m_F of handle s against a stored oracle record."""
     bad = []
     for st in ref["steps"]:
         t = st["step"]
@@ -65,6 +60,41 @@ def test_workload_matches_oracle(path):
     stats = s.stats()
     assert stats["s_top"] == ref["s_top"]
     assert stats["m_F"] == ref["m_F"]
+
+
+@pytest.mark.parametrize("path", cases())
+def test_workload_matches_oracle(path):
+    with open(path) as f:
+        ref = json.load(f)
+    p, b, levels = gridgen.config_problem(ref["workload"])
+    assert levels == ref["levels"] and p.n == ref["n"]
+    s = gpu_factor(p, levels, ref["tol"], ref["skip"])
+    check_against(ref, s)
     _, it, rr, _ = gpu_solve(s, b, ref["rtol"], ref["maxit"])
     assert np.all(np.abs(it - np.array(ref["pcg_iters"])) <= 1), (it.tolist(), ref["pcg_iters"])
     assert np.all(rr <= 1e-12), rr
+
+
+def test_batched_workload_problems_match_oracle():
+    """The stored problems of the batched workload, factored and solved in one batch."""
+    from paper_1901_02971_amd import Solver, factor_batch, solve_batch
+    from tests.gpu_util import to_dev
+    refs = []
+    for path in golden_files("c5_"):
+        with open(path) as f:
+            refs.append(json.load(f))
+    if not refs:
+        pytest.skip("no stored results of the batched workload")
+    probs = [gridgen.config_problem(r["workload"]) for r in refs]
+    solvers = [Solver.from_problem(p, L) for p, _, L in probs]
+    vals = [torch.from_numpy(p.values).to("cuda:0") for p, _, _ in probs]
+    factor_batch(solvers, vals, refs[0]["tol"], refs[0]["skip"])
+    for ref, s in zip(refs, solvers):
+        check_against(ref, s)
+    bt = [to_dev(b) for _, b, _ in probs]
+    xt = [torch.empty_like(t) for t in bt]
+    it, rr, st = solve_batch(solvers, bt, xt, refs[0]["rtol"], refs[0]["maxit"])
+    assert st == 0
+    for q, ref in enumerate(refs):
+        assert np.all(np.abs(it[q] - np.array(ref["pcg_iters"])) <= 1), (ref["workload"], it[q].tolist())
+        assert np.all(rr[q] <= 1e-12)
