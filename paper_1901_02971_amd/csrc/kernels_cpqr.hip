@@ -2,12 +2,12 @@
 // intro) with the block A_pn held in registers.
 //
 // Interface p couples its m dofs to nc neighbour dofs through A_pn (m x nc).  A
-// workgroup of CQ_NT = 512 threads (two waves per SIMD, so the whole register file
-// of a CU) holds a slab of CAP = CQ_CPL * CQ_NT / G columns: a team of G
-// consecutive lanes (G a power of two, G * CQ_MR >= m) owns CQ_CPL columns, and
-// lane g of the team keeps rows i = q * G + g (q < CQ_MR) of each of them in
-// registers.  Column c of A_pn lives in slab c / CAP, team (c % CAP) % (CQ_NT / G),
-// register slot (c % CAP) / (CQ_NT / G).  Interface p uses S = ceil(nc / CAP) slabs.
+// workgroup of NT = 512 threads (two waves per SIMD, so the whole register file of
+// a CU) holds a slab of CAP = CQ_CPL * NT / G columns: a team of G consecutive
+// lanes (G a power of two, G * CQ_MR >= m) owns CQ_CPL columns, and lane g of the
+// team keeps rows i = q * G + g (q < CQ_MR) of each of them in registers.  Column c
+// of A_pn lives in slab c / CAP, team (c % CAP) % (NT / G), register slot
+// (c % CAP) / (NT / G).  Interface p uses S = ceil(nc / CAP) slabs.
 //
 // Step j of Householder QR with column pivoting:
 //   1. every column knows the exact norm of its rows j..m-1 (recomputed from the
@@ -141,9 +141,10 @@ template <int G, bool MULTI>
 __global__ void __launch_bounds__(CQ_NT) k_cpqr(const SparsDesc* __restrict__ descs, const SlabRef* __restrict__ slabs,
                                                 const SegDesc* __restrict__ segs, double eps, int32_t* cursize,
                                                 int32_t* nref, int32_t* err) {
-  constexpr int NTEAM = CQ_NT / G;
+  constexpr int NT = CQ_NT;
+  constexpr int NTEAM = NT / G;
   constexpr int CAP = CQ_CPL * NTEAM;
-  constexpr int NW = CQ_NT / 64;
+  constexpr int NW = NT / 64;
   constexpr int ROWS = G * CQ_MR;  // rows a team can hold (>= m)
   extern __shared__ double lds[];
   __shared__ Cand red[2][NW], redx[2][NW];
@@ -345,14 +346,15 @@ __global__ void __launch_bounds__(CQ_NT) k_cpqr(const SparsDesc* __restrict__ de
       u.cn = -1.0;
       u.cd = INT_MAX;
       u.amb = 0;
-      if (tid < S) {
-        const double* rc = xrec(xb, tid);
+      for (int q = tid; q < S; q += NT) {  // S may exceed the workgroup size
+        const double* rc = xrec(xb, q);
         const double mx = shared_load(rc), cn = shared_load(rc + 1), cq = shared_load(rc + 3);
-        u.mx = mx;
-        if (cq >= 0.0) {
-          u.cd = (int)cq;
-          u.cn = cn;
-        }
+        Cand v;
+        v.mx = mx;
+        v.cn = (cq >= 0.0) ? cn : -1.0;
+        v.cd = (cq >= 0.0) ? (int)cq : INT_MAX;
+        v.amb = 0;
+        u = cand_combine(u, v);
       }
 #pragma unroll
       for (int o = 1; o < 64; o <<= 1) {
@@ -405,9 +407,9 @@ __global__ void __launch_bounds__(CQ_NT) k_cpqr(const SparsDesc* __restrict__ de
         if (tid == 0) shared_store(rc + 3, (best == INT_MAX) ? -1.0 : (double)best);
         slab_barrier(d.cnt, ++bar * S, err);
         int b2 = INT_MAX;
-        if (tid < S) {
-          const double cq = shared_load(xrec(2, tid) + 3);
-          if (cq >= 0.0) b2 = (int)cq;
+        for (int q = tid; q < S; q += NT) {
+          const double cq = shared_load(xrec(2, q) + 3);
+          if (cq >= 0.0) b2 = min(b2, (int)cq);
         }
         b2 = wave_min(b2);
         if (lane == 0) red2[wave] = b2;
@@ -435,7 +437,7 @@ __global__ void __launch_bounds__(CQ_NT) k_cpqr(const SparsDesc* __restrict__ de
         scale = 1.0 / (alpha - beta);
       }
       if (!stop) {
-        for (int i = tid; i < ROWS; i += CQ_NT) {
+        for (int i = tid; i < ROWS; i += NT) {
           const double x = (i > j) ? shared_load(rc + 4 + i) : 0.0;
           vm[i] = make_double2((i > j) ? x * scale : ((i == j) ? 1.0 : 0.0), (i > j) ? 1.0 : 0.0);
         }
@@ -475,20 +477,33 @@ __global__ void __launch_bounds__(CQ_NT) k_cpqr(const SparsDesc* __restrict__ de
     const double tau = sh_tau;
     if (w == 0) {
       double* V = d.V + (int64_t)j * m;
-      for (int i = tid; i < m; i += CQ_NT) V[i] = vm[i].x;
+      for (int i = tid; i < m; i += NT) V[i] = vm[i].x;
       if (tid == 0) d.tau[j] = tau;
     }
-    // ---- apply H_j to the remaining columns; new trailing norms (rows j+1..)
+    // ---- apply H_j to the remaining columns; new trailing norms (rows j+1..).  The
+    // (v_i, [i > j]) pairs are read four rows ahead of their use (two passes).
     const double2* vl = vm + g;
     double dot[CQ_CPL];
 #pragma unroll
     for (int k = 0; k < CQ_CPL; ++k) dot[k] = 0.0;
+    {
+      double2 cur[4], nxt[4];
 #pragma unroll
-    for (int q = 0; q < CQ_MR; ++q) {
-      const double vq = vl[q * G].x;
+      for (int u = 0; u < 4; ++u) cur[u] = vl[u * G];
 #pragma unroll
-      for (int k = 0; k < CQ_CPL; ++k) dot[k] = fma(vq, a[k][q], dot[k]);
-      if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bound the LDS loads in flight
+      for (int q0 = 0; q0 < CQ_MR; q0 += 4) {
+        if (q0 + 4 < CQ_MR) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) nxt[u] = vl[(q0 + 4 + u) * G];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int k = 0; k < CQ_CPL; ++k) dot[k] = fma(cur[u].x, a[k][q0 + u], dot[k]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) cur[u] = nxt[u];
+      }
     }
     double wv[CQ_CPL], sq[CQ_CPL];
 #pragma unroll
@@ -497,16 +512,28 @@ __global__ void __launch_bounds__(CQ_NT) k_cpqr(const SparsDesc* __restrict__ de
       wv[k] = (pst[k] == -1) ? tau * dot[k] : 0.0;
       sq[k] = 0.0;
     }
+    {
+      double2 cur[4], nxt[4];
 #pragma unroll
-    for (int q = 0; q < CQ_MR; ++q) {
-      const double2 vf = vl[q * G];
+      for (int u = 0; u < 4; ++u) cur[u] = vl[u * G];
 #pragma unroll
-      for (int k = 0; k < CQ_CPL; ++k) {
-        const double x = fma(-wv[k], vf.x, a[k][q]);
-        a[k][q] = x;
-        sq[k] = fma(x * vf.y, x, sq[k]);
+      for (int q0 = 0; q0 < CQ_MR; q0 += 4) {
+        if (q0 + 4 < CQ_MR) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) nxt[u] = vl[(q0 + 4 + u) * G];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int k = 0; k < CQ_CPL; ++k) {
+            const double x = fma(-wv[k], cur[u].x, a[k][q0 + u]);
+            a[k][q0 + u] = x;
+            sq[k] = fma(x * cur[u].y, x, sq[k]);
+          }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) cur[u] = nxt[u];
       }
-      if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int k = 0; k < CQ_CPL; ++k) nrm[k] = team_sum<G>(sq[k]);
@@ -525,7 +552,7 @@ __global__ void __launch_bounds__(CQ_NT) k_cpqr(const SparsDesc* __restrict__ de
     }
   }
   if (w == 0) {
-    for (int64_t e = tid; e < (int64_t)r * r; e += CQ_NT) {
+    for (int64_t e = tid; e < (int64_t)r * r; e += NT) {
       const int x = (int)(e % r), y = (int)(e / r);
       d.diag[x + (int64_t)y * d.ldd] = (x == y) ? 1.0 : 0.0;
     }
