@@ -245,6 +245,7 @@ def main():
                  "achieved": round(cpqr_tf, 4), "peak": round(FP64_VALU_TFLOPS, 1), "unit": "TFLOP/s",
                  "frac": round(cpqr_tf / FP64_VALU_TFLOPS, 5)},
         "apply": {"kernel": "preconditioner apply M M^T (Sec. 2.8), all levels", "bound": "hbm",
+                  "hip_graph": bool(ss[-1]["apply_graph"]),
                   "calls_per_step": int(ss[-1]["apply_calls"]), "ms_per_apply": round(apply_s * 1e3, 3),
                   "bytes_per_apply": ss[-1]["apply_bytes"], "achieved": round(apply_gbs, 1), "peak": HBM_GBS,
                   "unit": "GB/s", "frac": round(apply_gbs / HBM_GBS, 4)},

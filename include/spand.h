@@ -87,6 +87,8 @@ typedef struct {
   double apply_bytes;
   double apply_seconds;   /* summed device time of the applies (HIP events) */
   int64_t apply_calls;
+  int32_t apply_graph;    /* 1 if the last solve replayed its apply from a captured graph */
+  int32_t reserved2;
 } spand_stats;
 
 /* Ordering, clustering and symbolic factorization (Algorithm 2 with a geometric
@@ -132,6 +134,13 @@ spand_status spand_apply(spand_t h, int32_t nrhs, const double* r, double* z);
 /* Use this HIP stream (hipStream_t passed as void*) for all later device work of
  * the handle; NULL selects the default stream. */
 spand_status spand_set_stream(spand_t h, void* hip_stream);
+
+/* Inside spand_solve the preconditioner apply of every PCG iteration works on the
+ * same vectors, so by default it is captured once per solve into a HIP graph (on a
+ * private stream) and replayed on the handle's stream.  enable = 0 launches it
+ * kernel by kernel instead; results are identical.  If the runtime refuses the
+ * capture, spand_solve falls back to kernel-by-kernel launches. */
+spand_status spand_set_apply_graph(spand_t h, int32_t enable);
 
 /* Copy the statistics of the last analyze/factor/solve into *s. */
 spand_status spand_get_stats(spand_t h, spand_stats* s);

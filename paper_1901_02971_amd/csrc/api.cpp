@@ -259,6 +259,12 @@ spand_status spand_set_stream(spand_t h, void* hip_stream) {
   return SPAND_OK;
 }
 
+spand_status spand_set_apply_graph(spand_t h, int32_t enable) {
+  if (!h) return fail_null(SPAND_E_INVALID, "handle is NULL");
+  h->apply_graph = enable != 0;
+  return SPAND_OK;
+}
+
 spand_status spand_get_stats(spand_t h, spand_stats* s) {
   if (!h || !s) return fail_null(SPAND_E_INVALID, "NULL argument");
   *s = h->stats;

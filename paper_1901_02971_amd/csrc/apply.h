@@ -29,11 +29,13 @@ struct TargetContrib {
   int64_t tmp_s;    // where L_s^{-1} x_s lives in the apply scratch
 };
 struct ScaleAp {
-  const double* L;     // np x np lower-triangular L_p, ld np
-  const double* Dinv;  // inverses of its diagonal blocks
+  const double* Linv;  // np x np lower-triangular L_p^{-1}, ld np
   int32_t np, pad;
   int64_t slot_p;
-  int64_t tmp;
+  int64_t tmp;         // np rows of scratch: x_p gathered
+};
+struct ScaleTile {    // rows [r0, r0 + 64) of the product with L_p^{-1} (or its transpose)
+  int32_t p, r0;
 };
 struct HouseAp {
   const double* V;    // np x r reflectors, ld np (unit diagonal, zeros above)
@@ -54,12 +56,15 @@ struct StepDev {
   const ScaleAp* scale;
   const HouseAp* house;
   const ElimTile* etile;
+  const ScaleTile* stile;  // row tiles of every L_p^{-1}
+  const int32_t* sgather;  // slot of every scratch row of the scaled interfaces
+  int64_t sgather_len;
   const HouseTile* hr;   // reflector tiles of every Q_p
   const HouseTile* hv;   // row tiles of every Q_p
   const int32_t* slot;
   const int32_t* nslot;
   int64_t nslot_len;
-  int32_t n_elim, n_target, n_scale, n_house, n_etile, n_hr, n_hv, pad;
+  int32_t n_elim, n_target, n_scale, n_house, n_etile, n_hr, n_hv, n_stile;
 };
 
 struct ApplyArgs {
@@ -85,5 +90,6 @@ void launch_update_xr(int64_t n, int nrhs, const double* rz, const double* pq, c
 void launch_update_p(int64_t n, int nrhs, const double* rz_new, const double* rz, const int32_t* active,
                      const double* z, double* p, hipStream_t s);
 void launch_residual(int64_t len, const double* b, double* y, hipStream_t s);
+void launch_copy_vec(const double* r, double* z, int64_t len, hipStream_t s);
 
 }  // namespace spand

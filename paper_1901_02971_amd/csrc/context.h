@@ -63,10 +63,12 @@ struct StepNum {
   std::vector<int32_t> slot;    // current dofs of every cluster (vertex ids)
   DevBuf elim, scale, house;    // factor pieces: [L_s; G_s] panels, L_p, reflectors
   DevBuf edinv, sdinv;          // inverses of the CHOL_NB-wide diagonal blocks of L_s, L_p
+                                // (scale holds L_p^{-1} itself)
   DevBuf d_slot, d_nslot;       // slot arrays on the device
   // apply descriptors
-  DevBuf d_elim, d_target, d_contrib, d_scale, d_house, d_etile, d_hr, d_hv;
-  int32_t n_elim_ap = 0, n_target = 0, n_scale = 0, n_house = 0, n_etile = 0, n_hr = 0, n_hv = 0;
+  DevBuf d_elim, d_target, d_contrib, d_scale, d_house, d_etile, d_hr, d_hv, d_stile, d_sgather;
+  int32_t n_elim_ap = 0, n_target = 0, n_scale = 0, n_house = 0, n_etile = 0, n_hr = 0, n_hv = 0, n_stile = 0;
+  int64_t sgather_len = 0;
   int64_t nslot_len = 0;
   int64_t tmp_elim = 0, tmp_scale = 0;  // doubles per RHS of temp needed
   std::vector<ElimAp> h_elim;
@@ -76,6 +78,8 @@ struct StepNum {
   std::vector<HouseAp> h_house;
   std::vector<ElimTile> h_etile;
   std::vector<HouseTile> h_hr, h_hv;
+  std::vector<ScaleTile> h_stile;
+  std::vector<int32_t> h_sgather;
 };
 
 }  // namespace spand
@@ -95,11 +99,18 @@ struct spand_ctx {
   // PCG / apply scratch, grown on demand
   spand::DevBuf work;
   size_t work_bytes = 0;
+  // The apply inside PCG, captured once per solve as a HIP graph and replayed on
+  // the handle's stream (apply_graph = false launches it kernel by kernel).
+  bool apply_graph = true;
+  hipGraphExec_t graph_exec = nullptr;
+  ~spand_ctx() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+  }
 };
 
 namespace spand {
 spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int32_t skip, spand_prec prec);
-spand_status apply_precond(spand_ctx* h, int32_t nrhs, const double* r, double* z, double* tmp);
+spand_status apply_precond(spand_ctx* h, int32_t nrhs, const double* r, double* z, double* tmp, hipStream_t st);
 spand_status pcg_solve(spand_ctx* h, int32_t nrhs, const double* b, double* x, double rtol, int32_t maxit,
                        int32_t* iters, double* relres);
 spand_status set_err(spand_ctx* h, spand_status st, const std::string& msg);

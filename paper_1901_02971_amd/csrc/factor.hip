@@ -554,18 +554,18 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
         if (sn.size[p] > 0)
           fr.push_back(Front{A + lay.base[p], SD + sd_off[p], int32_t(lay.H[p]), sn.size[p], int32_t(lay.H[p]), p});
       if ((st = blocked_cholesky(h, fr, d_fail_scale, 0)) != SPAND_OK) return st;
-      // keep L_p for the apply, then L_i^{-1} from the left on every block (i, p)
-      std::vector<CopyDesc> lcopy;
+      // L_p^{-1} for the apply (the identity solved against L_p), and L_i^{-1} from the
+      // left on every block (i, p), in one blocked left solve
       std::vector<LeftBlock> lb;
+      std::vector<double*> iptr;
+      std::vector<int32_t> in_, ild;
       for (int32_t p = ne; p < nc; ++p) {
         if (sn.size[p] == 0) continue;
-        CopyDesc cd{};
-        cd.src = A + lay.base[p];
-        cd.lds = int32_t(lay.H[p]);
-        cd.dst = SC + sc_off[p];
-        cd.ldd = sn.size[p];
-        cd.rows = cd.cols = sn.size[p];
-        lcopy.push_back(cd);
+        iptr.push_back(SC + sc_off[p]);
+        in_.push_back(sn.size[p]);
+        ild.push_back(sn.size[p]);
+        lb.push_back(LeftBlock{SC + sc_off[p], A + lay.base[p], SD + sd_off[p], sn.size[p], int32_t(lay.H[p]),
+                               sn.size[p], sn.size[p]});
         for (int64_t e = lay.pan_ptr[p] + 1; e < lay.pan_ptr[p + 1]; ++e) {
           const int32_t i = lay.prow[e];
           if (sn.size[i] == 0) continue;
@@ -573,11 +573,15 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
                                  int32_t(lay.H[i]), sn.size[i], sn.size[p]});
         }
       }
-      DevBuf dlc;
-      if ((st = upload(h, dlc, lcopy)) != SPAND_OK) return st;
-      launch_copy(dlc.as<CopyDesc>(), int64_t(lcopy.size()), h->stream);
-      HIPCHK(hipGetLastError());
-      if ((st = left_trsm(h, lb)) != SPAND_OK) return st;
+      {
+        DevBuf d1, d2, d3;
+        if ((st = upload(h, d1, iptr)) != SPAND_OK) return st;
+        if ((st = upload(h, d2, in_)) != SPAND_OK) return st;
+        if ((st = upload(h, d3, ild)) != SPAND_OK) return st;
+        launch_set_identity(d1.as<double*>(), d2.as<int32_t>(), d3.as<int32_t>(), int32_t(iptr.size()), h->stream);
+        HIPCHK(hipGetLastError());
+        if ((st = left_trsm(h, lb)) != SPAND_OK) return st;
+      }
       std::vector<double*> dptr;
       std::vector<int32_t> dn, dld;
       for (int32_t p = ne; p < nc; ++p)
@@ -795,8 +799,11 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       vtv.launch(h, 0);
       HIPCHK(hipGetLastError());
       DevBuf dtd;
+      std::stable_partition(tds.begin(), tds.end(), [](const TDesc& x) { return x.r <= build_t_lds_max(); });
+      int32_t nsmall = 0;
+      for (const TDesc& x : tds) nsmall += (x.r <= build_t_lds_max()) ? 1 : 0;
       if ((st = upload(h, dtd, tds)) != SPAND_OK) return st;
-      launch_build_t(dtd.as<TDesc>(), int32_t(tds.size()), h->stream);
+      launch_build_t(dtd.as<TDesc>(), int32_t(tds.size()), nsmall, h->stream);
       HIPCHK(hipGetLastError());
       HIPCHK(hipStreamSynchronize(h->stream));
     }
@@ -871,6 +878,8 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
         q = r;
       }
       sn.h_scale.clear();
+      sn.h_stile.clear();
+      sn.h_sgather.clear();
       sn.h_house.clear();
       sn.h_hr.clear();
       sn.h_hv.clear();
@@ -878,12 +887,15 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       for (int32_t p = ne; p < nc; ++p) {
         if (sc_off[p] >= 0) {
           ScaleAp a{};
-          a.L = sn.scale.as<double>() + sc_off[p];
-          a.Dinv = sn.sdinv.as<double>() + sd_off[p];
+          a.Linv = sn.scale.as<double>() + sc_off[p];
           a.np = sn.size[p];
           a.slot_p = sn.slot_ptr[p];
           a.tmp = tmp2;
           tmp2 += sn.size[p];
+          const int32_t sid = int32_t(sn.h_scale.size());
+          for (int32_t r0 = 0; r0 < a.np; r0 += 64) sn.h_stile.push_back(ScaleTile{sid, r0});
+          sn.h_sgather.insert(sn.h_sgather.end(), sn.slot.begin() + sn.slot_ptr[p],
+                              sn.slot.begin() + sn.slot_ptr[p] + sn.size[p]);
           sn.h_scale.push_back(a);
         }
         if (v_off[p] >= 0 && nref[p] > 0) {
@@ -910,6 +922,8 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       sn.n_scale = int32_t(sn.h_scale.size());
       sn.n_house = int32_t(sn.h_house.size());
       sn.n_etile = int32_t(sn.h_etile.size());
+      sn.n_stile = int32_t(sn.h_stile.size());
+      sn.sgather_len = int64_t(sn.h_sgather.size());
       sn.n_hr = int32_t(sn.h_hr.size());
       sn.n_hv = int32_t(sn.h_hv.size());
       if ((st = upload(h, sn.d_slot, sn.slot)) != SPAND_OK) return st;
@@ -920,6 +934,8 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       if ((st = upload(h, sn.d_scale, sn.h_scale)) != SPAND_OK) return st;
       if ((st = upload(h, sn.d_house, sn.h_house)) != SPAND_OK) return st;
       if ((st = upload(h, sn.d_etile, sn.h_etile)) != SPAND_OK) return st;
+      if ((st = upload(h, sn.d_stile, sn.h_stile)) != SPAND_OK) return st;
+      if ((st = upload(h, sn.d_sgather, sn.h_sgather)) != SPAND_OK) return st;
       if ((st = upload(h, sn.d_hr, sn.h_hr)) != SPAND_OK) return st;
       if ((st = upload(h, sn.d_hv, sn.h_hv)) != SPAND_OK) return st;
       HIPCHK(hipStreamSynchronize(h->stream));

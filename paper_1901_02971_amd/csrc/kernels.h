@@ -119,7 +119,9 @@ struct TDesc {
   double* T;          // r x r output, ld r
   int32_t m, r;
 };
-void launch_build_t(const TDesc* d, int32_t count, hipStream_t s);
+// d: the interfaces with r <= build_t_lds_max() first (nsmall of them), then the rest.
+void launch_build_t(const TDesc* d, int32_t count, int32_t nsmall, hipStream_t s);
+int32_t build_t_lds_max();
 
 constexpr int GEMM_TILE = 64;
 

@@ -9,11 +9,11 @@
 //   k_target_fwd  x_n <- x_n - sum_s G_ns x_s     (one workgroup per 64-row tile of a
 //                                                  receiving n, contributions in
 //                                                  ascending s)
-//   k_scale_fwd   x_p <- L_p^{-1} x_p
+//   k_scale<1>    x_p <- L_p^{-1} x_p                (explicit inverse, 64-row tiles)
 //   k_house_*     x_p <- Q_p^T x_p                (compact WY form, three tile launches)
 // Backward sweep (levels 1 -> L), the transposes in reverse order:
 //   k_house_*     x_p <- Q_p x_p
-//   k_scale_bwd   x_p <- L_p^{-T} x_p
+//   k_scale<-1>   x_p <- L_p^{-T} x_p
 //   k_gather         neighbour dofs of every s into a contiguous buffer
 //   k_elim_bwd_gemv  t_s <- x_s - G_{N_s s}^T x_{N_s}  (one workgroup per 64 columns of s)
 //   k_elim_bwd       x_s <- L_s^{-T} t_s
@@ -266,24 +266,40 @@ __global__ void __launch_bounds__(AW) k_target_fwd(const TargetAp* __restrict__ 
   }
 }
 
-__global__ void __launch_bounds__(AW) k_scale_fwd(const ScaleAp* __restrict__ ds, ApplyArgs a) {
-  __shared__ TileShared sh;
-  const ScaleAp e = ds[blockIdx.x];
-  const int32_t* sl = a.slot + e.slot_p;
-  gather_seg(sl, e.np, a, e.tmp);
-  for (int c0 = 0; c0 < a.nrhs; c0 += RB)
-    trsv_fwd(e.L, e.np, e.Dinv, e.np, a.tmp + e.tmp + (int64_t)c0 * a.ldt, a.ldt, min(RB, a.nrhs - c0), sh);
-  scatter_seg(sl, e.np, a, e.tmp);
+// x_p <- L_p^{-1} x_p (DIR = +1) or L_p^{-T} x_p (DIR = -1) with the explicit inverse:
+// x_p is gathered into the scratch first (k_gather_rows), then one workgroup per
+// 64 rows writes its rows of the product back through the slots.
+__global__ void k_gather_rows(const int32_t* __restrict__ sg, int64_t len, ApplyArgs a) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= len) return;
+  const int32_t v = sg[t];
+  for (int c = 0; c < a.nrhs; ++c) a.tmp[t + (int64_t)c * a.ldt] = a.x[v + (int64_t)c * a.ldx];
 }
 
-__global__ void __launch_bounds__(AW) k_scale_bwd(const ScaleAp* __restrict__ ds, ApplyArgs a) {
+template <int DIR>
+__global__ void __launch_bounds__(AW) k_scale(const ScaleAp* __restrict__ ds, const ScaleTile* __restrict__ tl,
+                                              ApplyArgs a) {
   __shared__ TileShared sh;
-  const ScaleAp e = ds[blockIdx.x];
+  const ScaleTile st = tl[blockIdx.x];
+  const ScaleAp e = ds[st.p];
+  const int np = e.np, r0 = st.r0;
   const int32_t* sl = a.slot + e.slot_p;
-  gather_seg(sl, e.np, a, e.tmp);
-  for (int c0 = 0; c0 < a.nrhs; c0 += RB)
-    trsv_bwd(e.L, e.np, e.Dinv, e.np, a.tmp + e.tmp + (int64_t)c0 * a.ldt, a.ldt, min(RB, a.nrhs - c0), sh);
-  scatter_seg(sl, e.np, a, e.tmp);
+  const int rr = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const double* xs = a.tmp + e.tmp;
+  for (int c0 = 0; c0 < a.nrhs; c0 += RB) {
+    const int nr = min(RB, a.nrhs - c0);
+    const int64_t co = (int64_t)c0 * a.ldt;
+    double acc[2] = {0.0, 0.0};
+    if (DIR > 0)  // rows r0.. of L^{-1} x: columns up to the diagonal tile
+      tile_gemv_n(e.Linv, np, r0, np, min(np, r0 + 64), xs + co, a.ldt, nr, sh, acc);
+    else          // rows r0.. of L^{-T} x: rows r0.. of L^{-1}
+      tile_gemv_t(e.Linv + r0, np, r0, np, np - r0, xs + co + r0, a.ldt, nr, sh, acc);
+    if (r0 + rr < np) {
+      double* xp = a.x + sl[r0 + rr] + (int64_t)c0 * a.ldx;
+      if (g < nr) xp[(int64_t)g * a.ldx] = acc[0];
+      if (g + 4 < nr) xp[(int64_t)(g + 4) * a.ldx] = acc[1];
+    }
+  }
 }
 
 // Q_p in compact WY form, Q = I - V T V^T (T upper triangular r x r).  DIR = +1
@@ -402,7 +418,11 @@ __global__ void __launch_bounds__(AW) k_elim_bwd(const ElimAp* __restrict__ ds, 
 void apply_step_forward(const StepDev& s, const ApplyArgs& a, hipStream_t st) {
   if (s.n_elim) hipLaunchKernelGGL(k_elim_fwd, dim3(s.n_elim), dim3(AW), 0, st, s.elim, a);
   if (s.n_target) hipLaunchKernelGGL(k_target_fwd, dim3(s.n_target), dim3(AW), 0, st, s.target, s.contrib, a);
-  if (s.n_scale) hipLaunchKernelGGL(k_scale_fwd, dim3(s.n_scale), dim3(AW), 0, st, s.scale, a);
+  if (s.n_stile) {
+    hipLaunchKernelGGL(k_gather_rows, dim3((s.sgather_len + 255) / 256), dim3(256), 0, st, s.sgather,
+                       s.sgather_len, a);
+    hipLaunchKernelGGL(k_scale<1>, dim3(s.n_stile), dim3(AW), 0, st, s.scale, s.stile, a);
+  }
   if (s.n_hr) {
     hipLaunchKernelGGL(k_house_w, dim3(s.n_hr), dim3(AW), 0, st, s.house, s.hr, a);
     hipLaunchKernelGGL(k_house_t<1>, dim3(s.n_hr), dim3(AW), 0, st, s.house, s.hr, a);
@@ -416,7 +436,11 @@ void apply_step_backward(const StepDev& s, const ApplyArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_house_t<-1>, dim3(s.n_hr), dim3(AW), 0, st, s.house, s.hr, a);
     hipLaunchKernelGGL(k_house_v, dim3(s.n_hv), dim3(AW), 0, st, s.house, s.hv, a);
   }
-  if (s.n_scale) hipLaunchKernelGGL(k_scale_bwd, dim3(s.n_scale), dim3(AW), 0, st, s.scale, a);
+  if (s.n_stile) {
+    hipLaunchKernelGGL(k_gather_rows, dim3((s.sgather_len + 255) / 256), dim3(256), 0, st, s.sgather,
+                       s.sgather_len, a);
+    hipLaunchKernelGGL(k_scale<-1>, dim3(s.n_stile), dim3(AW), 0, st, s.scale, s.stile, a);
+  }
   if (s.n_elim) {
     if (s.nslot_len)
       hipLaunchKernelGGL(k_gather, dim3((s.nslot_len + 255) / 256), dim3(256), 0, st, s.nslot, s.nslot_len, a);
@@ -496,6 +520,12 @@ __global__ void k_update_p(int64_t n, int nrhs, const double* __restrict__ rz_ne
   }
 }
 
+// z = r (plain copy; a kernel so that the apply can be captured into a graph)
+__global__ void k_copy_vec(const double* __restrict__ r, double* __restrict__ z, int64_t len) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < len) z[i] = r[i];
+}
+
 // y = b - y (true residual)
 __global__ void k_residual(int64_t len, const double* __restrict__ b, double* __restrict__ y) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -518,6 +548,9 @@ void launch_update_xr(int64_t n, int nrhs, const double* rz, const double* pq, c
 void launch_update_p(int64_t n, int nrhs, const double* rz_new, const double* rz, const int32_t* active,
                      const double* z, double* p, hipStream_t s) {
   hipLaunchKernelGGL(k_update_p, dim3((n + 255) / 256), dim3(256), 0, s, n, nrhs, rz_new, rz, active, z, p);
+}
+void launch_copy_vec(const double* r, double* z, int64_t len, hipStream_t s) {
+  if (len > 0) hipLaunchKernelGGL(k_copy_vec, dim3((len + 255) / 256), dim3(256), 0, s, r, z, len);
 }
 void launch_residual(int64_t len, const double* b, double* y, hipStream_t s) {
   hipLaunchKernelGGL(k_residual, dim3((len + 255) / 256), dim3(256), 0, s, len, b, y);

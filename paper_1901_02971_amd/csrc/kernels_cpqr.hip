@@ -566,9 +566,33 @@ __global__ void __launch_bounds__(CQ_NT) k_cpqr(const SparsDesc* __restrict__ de
 // Compact WY factor of Q = H_0 ... H_{r-1} = I - V T V^T (T upper triangular):
 // T_jj = tau_j, T[:j, j] = -tau_j T[:j, :j] (V[:, :j]^T v_j).  On entry the upper
 // triangle of T holds S = V^T V (a batched GEMM); one workgroup per interface runs
-// the recurrence column by column, S[:j, j] staged in LDS before column j is
+// the recurrence column by column, column j of S being read before it is
 // overwritten.  The strict lower triangle is set to zero for the tiled products of
-// the apply.
+// the apply.  k_build_t_lds keeps T in LDS (r <= T_LDS_R); k_build_t works in place
+// in global memory with S[:j, j] staged in LDS.
+#define T_LDS_R 64
+__global__ void __launch_bounds__(CW) k_build_t_lds(const TDesc* __restrict__ descs) {
+  const TDesc d = descs[blockIdx.x];
+  const int r = d.r, ld = r + 1;  // padded leading dimension in LDS
+  __shared__ double tl[T_LDS_R * (T_LDS_R + 1)];
+  for (int q = threadIdx.x; q < r * r; q += CW) {
+    const int i = q % r, j = q / r;
+    tl[i + j * ld] = (i < j) ? d.T[q] : 0.0;
+  }
+  __syncthreads();
+  const int i = threadIdx.x;
+  for (int j = 0; j < r; ++j) {
+    double s = 0.0;
+    if (i < j)
+      for (int l = i; l < j; ++l) s += tl[i + l * ld] * tl[l + j * ld];
+    __syncthreads();
+    if (i < j) tl[i + j * ld] = -d.tau[j] * s;
+    if (i == j) tl[j + j * ld] = d.tau[j];
+    __syncthreads();
+  }
+  for (int q = threadIdx.x; q < r * r; q += CW) d.T[q] = tl[q % r + (q / r) * ld];
+}
+
 __global__ void __launch_bounds__(CW) k_build_t(const TDesc* __restrict__ descs) {
   const TDesc d = descs[blockIdx.x];
   const int r = d.r;
@@ -594,10 +618,13 @@ __global__ void __launch_bounds__(CW) k_build_t(const TDesc* __restrict__ descs)
   }
 }
 
-void launch_build_t(const TDesc* d, int32_t count, hipStream_t s) {
-  if (count == 0) return;
-  hipLaunchKernelGGL(k_build_t, dim3(count), dim3(CW), 0, s, d);
+// descs: the interfaces with r <= T_LDS_R first (nsmall of them), then the others
+void launch_build_t(const TDesc* d, int32_t count, int32_t nsmall, hipStream_t s) {
+  if (nsmall > 0) hipLaunchKernelGGL(k_build_t_lds, dim3(nsmall), dim3(CW), 0, s, d);
+  if (count > nsmall) hipLaunchKernelGGL(k_build_t, dim3(count - nsmall), dim3(CW), 0, s, d + nsmall);
 }
+
+int32_t build_t_lds_max() { return T_LDS_R; }
 
 int32_t cpqr_team(int32_t m) {
   int32_t G = 1;

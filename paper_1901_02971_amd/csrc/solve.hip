@@ -32,6 +32,10 @@ StepDev step_dev(const StepNum& s) {
   d.house = s.d_house.as<HouseAp>();
   d.etile = s.d_etile.as<ElimTile>();
   d.n_etile = s.n_etile;
+  d.stile = s.d_stile.as<ScaleTile>();
+  d.n_stile = s.n_stile;
+  d.sgather = s.d_sgather.as<int32_t>();
+  d.sgather_len = s.sgather_len;
   d.hr = s.d_hr.as<HouseTile>();
   d.hv = s.d_hv.as<HouseTile>();
   d.n_hr = s.n_hr;
@@ -61,10 +65,12 @@ spand_status ensure_work(spand_ctx* h, size_t bytes) {
 
 }  // namespace
 
-// z = M M^T r; scratch holds (max_tmp + max_gather) * nrhs doubles.
-spand_status apply_precond(spand_ctx* h, int32_t nrhs, const double* r, double* z, double* scratch) {
+// z = M M^T r on stream st; scratch holds (max_tmp + max_gather) * nrhs doubles.
+// Only kernels are launched (no memset or memcpy nodes), so the sequence can be
+// captured into a graph.
+spand_status apply_precond(spand_ctx* h, int32_t nrhs, const double* r, double* z, double* scratch, hipStream_t st) {
   const int64_t n = h->an.n;
-  if (z != r) HIPCHK(hipMemcpyAsync(z, r, size_t(n) * nrhs * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  if (z != r) launch_copy_vec(r, z, n * nrhs, st);
   ApplyArgs a{};
   a.x = z;
   a.ldx = n;
@@ -76,16 +82,43 @@ spand_status apply_precond(spand_ctx* h, int32_t nrhs, const double* r, double* 
   for (size_t t = 0; t < h->num.size(); ++t) {
     const StepDev d = step_dev(h->num[t]);
     a.slot = d.slot;
-    apply_step_forward(d, a, h->stream);
+    apply_step_forward(d, a, st);
   }
   for (size_t t = h->num.size(); t-- > 0;) {
     const StepDev d = step_dev(h->num[t]);
     a.slot = d.slot;
-    apply_step_backward(d, a, h->stream);
+    apply_step_backward(d, a, st);
   }
   HIPCHK(hipGetLastError());
   return SPAND_OK;
 }
+
+namespace {
+
+// Capture the apply for (nrhs, r, z, scratch) on a private stream into h->graph_exec.
+// Returns false (and leaves no graph) if the runtime refuses the capture.
+bool capture_apply(spand_ctx* h, int32_t nrhs, const double* r, double* z, double* scratch) {
+  if (h->graph_exec) {
+    (void)hipGraphExecDestroy(h->graph_exec);
+    h->graph_exec = nullptr;
+  }
+  hipStream_t cap = nullptr;
+  if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return false;
+  hipGraph_t graph = nullptr;
+  bool ok = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed) == hipSuccess;
+  if (ok) {
+    const spand_status st = apply_precond(h, nrhs, r, z, scratch, cap);
+    ok = (hipStreamEndCapture(cap, &graph) == hipSuccess) && st == SPAND_OK && graph;
+  }
+  if (ok) ok = hipGraphInstantiate(&h->graph_exec, graph, nullptr, nullptr, 0) == hipSuccess;
+  if (!ok) h->graph_exec = nullptr;
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(cap);
+  (void)hipGetLastError();
+  return ok;
+}
+
+}  // namespace
 
 size_t apply_scratch_doubles(const spand_ctx* h, int32_t nrhs) {
   return size_t(std::max<int64_t>(h->max_tmp, 1) + std::max<int64_t>(h->max_gather, 1)) * size_t(nrhs);
@@ -94,7 +127,7 @@ size_t apply_scratch_doubles(const spand_ctx* h, int32_t nrhs) {
 spand_status apply_public(spand_ctx* h, int32_t nrhs, const double* r, double* z) {
   spand_status st = ensure_work(h, apply_scratch_doubles(h, nrhs) * sizeof(double));
   if (st != SPAND_OK) return st;
-  st = apply_precond(h, nrhs, r, z, h->work.as<double>());
+  st = apply_precond(h, nrhs, r, z, h->work.as<double>(), h->stream);
   if (st != SPAND_OK) return st;
   HIPCHK(hipStreamSynchronize(h->stream));
   return SPAND_OK;
@@ -127,7 +160,10 @@ spand_status pcg_solve(spand_ctx* h, int32_t nrhs, const double* b, double* x, d
 
   std::vector<double> hb(nrhs), hr(nrhs);
   std::vector<int32_t> act(nrhs, 0);
-  // device time of every apply, from a pair of events around it
+  // the apply of this solve: one captured graph (same vectors every iteration),
+  // replayed on the handle's stream; device time of every apply from a pair of
+  // events around it
+  const bool use_graph = h->apply_graph && capture_apply(h, nrhs, r, z, scratch);
   EventPool evpool;
   size_t napply = 0;
   auto timed_apply = [&]() -> spand_status {
@@ -135,8 +171,12 @@ spand_status pcg_solve(spand_ctx* h, int32_t nrhs, const double* b, double* x, d
     HIPCHK(evpool.get(2 * napply, &e0));
     HIPCHK(evpool.get(2 * napply + 1, &e1));
     HIPCHK(hipEventRecord(e0, s));
-    spand_status sa = apply_precond(h, nrhs, r, z, scratch);
-    if (sa != SPAND_OK) return sa;
+    if (use_graph) {
+      HIPCHK(hipGraphLaunch(h->graph_exec, s));
+    } else {
+      spand_status sa = apply_precond(h, nrhs, r, z, scratch, s);
+      if (sa != SPAND_OK) return sa;
+    }
     HIPCHK(hipEventRecord(e1, s));
     ++napply;
     return SPAND_OK;
@@ -203,6 +243,7 @@ spand_status pcg_solve(spand_ctx* h, int32_t nrhs, const double* b, double* x, d
   }
   h->stats.apply_seconds = apply_ms * 1e-3;
   h->stats.apply_calls = int64_t(napply);
+  h->stats.apply_graph = use_graph ? 1 : 0;
   h->stats.apply_bytes = 16.0 * double(h->stats.m_F) + 4.0 * 8.0 * double(n) * nrhs;
   h->stats.last_iters = 0;
   for (int c = 0; c < nrhs; ++c) h->stats.last_iters = std::max(h->stats.last_iters, iters[c]);

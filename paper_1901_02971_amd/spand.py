@@ -36,11 +36,12 @@ class Stats(C.Structure):
                 ("fail_phase", C.c_int32), ("reserved", C.c_int32),
                 ("step_phase_seconds", (C.c_double * 4) * 32), ("step_m_F", C.c_int64 * 32),
                 ("cpqr_flops", C.c_double), ("cpqr_seconds", C.c_double), ("cpqr_launches", C.c_int64),
-                ("apply_bytes", C.c_double), ("apply_seconds", C.c_double), ("apply_calls", C.c_int64)]
+                ("apply_bytes", C.c_double), ("apply_seconds", C.c_double), ("apply_calls", C.c_int64),
+                ("apply_graph", C.c_int32), ("reserved2", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_
-             if k not in ("reserved", "step_phase_seconds", "step_m_F")}
+             if k not in ("reserved", "reserved2", "step_phase_seconds", "step_m_F")}
         L = max(0, min(32, int(self.n_steps)))
         d["step_phase_seconds"] = [[self.step_phase_seconds[t][q] for q in range(4)] for t in range(L)]
         d["step_m_F"] = [int(self.step_m_F[t]) for t in range(L)]
@@ -68,6 +69,7 @@ def load_library():
         "spand_solve": (i32, [P, i32, P, P, f64, i32, P, P]),
         "spand_apply": (i32, [P, i32, P, P]),
         "spand_set_stream": (i32, [P, P]),
+        "spand_set_apply_graph": (i32, [P, i32]),
         "spand_get_stats": (i32, [P, C.POINTER(Stats)]),
         "spand_get_ordering": (i32, [P, P, P, P]),
         "spand_step_counts": (i32, [P, i32, P]),
@@ -158,6 +160,10 @@ class Solver:
         """Run on a torch.cuda.Stream (or raw hipStream_t int); None = default stream."""
         raw = None if stream is None else (stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
         self._check(self._lib.spand_set_stream(self._h, raw))
+
+    def set_apply_graph(self, enable):
+        """Replay the PCG apply as a captured HIP graph (default) or launch it eagerly."""
+        self._check(self._lib.spand_set_apply_graph(self._h, 1 if enable else 0))
 
     def factor(self, values, tol, skip=0, prec=SPAND_FP64):
         import torch

@@ -10,7 +10,8 @@ import gridgen
 from oracle import spand_oracle as O
 from paper_1901_02971_amd import spand as S
 
-DECLARED = ["spand_analyze", "spand_factor", "spand_solve", "spand_apply", "spand_set_stream", "spand_get_stats",
+DECLARED = ["spand_analyze", "spand_factor", "spand_solve", "spand_apply", "spand_set_stream",
+            "spand_set_apply_graph", "spand_get_stats",
             "spand_get_ordering", "spand_step_counts", "spand_step_structure", "spand_step_ranks",
             "spand_factor_batch", "spand_solve_batch", "spand_error_string", "spand_destroy"]
 
