@@ -666,89 +666,96 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       std::vector<DevBuf> keep;
       int32_t multi_idx = 0;
       size_t nlaunch = 0;
+      // launch groups of one colour: single-slab interfaces per team size G
+      // (group G), then every multi-slab interface of the colour together (group 0)
       for (int32_t c = 0; c < ncolour; ++c) {
         if (by_colour[c].empty()) continue;
-        for (int32_t G = 1; G <= 64; G <<= 1)
-          for (int multi = 0; multi < 2; ++multi) {
-            std::vector<int32_t> plist;
-            for (int32_t p : by_colour[c])
-              if (tg[p] == G && (slabS[p] > 1) == (multi == 1)) plist.push_back(p);
-            if (plist.empty()) continue;
-            // largest first: similar step counts share a launch
-            std::stable_sort(plist.begin(), plist.end(), [&](int32_t x, int32_t y) {
-              return int64_t(sn.size[x]) * ncols[x] > int64_t(sn.size[y]) * ncols[y];
-            });
-            size_t lds = 0;
-            for (int32_t p : plist) lds = std::max(lds, cpqr_lds_bytes(G, nseg[p]));
-            int cap = INT_MAX;
-            if (multi) {
-              cap = cpqr_max_coresident(G, lds);
-              if (cap <= 0) return set_err(h, SPAND_E_HIP, "occupancy query for the CPQR kernel failed");
-            }
-            size_t pos = 0;
-            while (pos < plist.size()) {
-              std::vector<SparsDesc> sds;
-              std::vector<SegDesc> segs;
-              std::vector<SlabRef> slabs;
-              while (pos < plist.size()) {
-                const int32_t p = plist[pos];
-                if (multi && slabS[p] > cap)
-                  return set_err(h, SPAND_E_INVALID, "interface needs more co-resident workgroups than the GPU holds");
-                if (multi && !slabs.empty() && int64_t(slabs.size()) + slabS[p] > cap) break;
-                SparsDesc d{};
-                d.V = sn.house.as<double>() + v_off[p];
-                d.tau = sn.house.as<double>() + tau_off[p];
-                d.diag = A + lay.base[p];
-                d.ldd = int32_t(lay.H[p]);
-                d.m = sn.size[p];
-                d.id = p;
-                d.S = slabS[p];
-                if (multi) {
-                  d.xch = xchb.as<double>() + xch_off[p];
-                  d.cnt = cntb.as<int32_t>() + size_t(multi_idx++) * CNT_PAD;
-                }
-                d.seg_begin = int32_t(segs.size());
-                for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e) {
-                  const int32_t q = sy.nb[e];
-                  if (sn.size[q] == 0) continue;
-                  SegDesc g{};
-                  if (q < p) {  // block (p, q) in panel q
-                    g.blk = A + lay.base[q] + lay.find(p, q);
-                    g.ld = int32_t(lay.H[q]);
-                    g.trans = 0;
-                  } else {      // block (q, p) in panel p holds A_pq^T
-                    g.blk = A + lay.base[p] + lay.find(q, p);
-                    g.ld = int32_t(lay.H[p]);
-                    g.trans = 1;
-                  }
-                  g.q = q;
-                  segs.push_back(g);
-                }
-                d.seg_end = int32_t(segs.size());
-                for (int32_t w = 0; w < slabS[p]; ++w) slabs.push_back(SlabRef{int32_t(sds.size()), w});
-                sds.push_back(d);
-                ++pos;
-              }
-              DevBuf a, b, sl;
-              if ((st = upload(h, a, sds)) != SPAND_OK) return st;
-              if ((st = upload(h, b, segs)) != SPAND_OK) return st;
-              if ((st = upload(h, sl, slabs)) != SPAND_OK) return st;
-              hipEvent_t e0, e1;
-              HIPCHK(evpool.get(2 * nlaunch, &e0));
-              HIPCHK(evpool.get(2 * nlaunch + 1, &e1));
-              HIPCHK(hipEventRecord(e0, h->stream));
-              hipError_t le = launch_cpqr(G, a.as<SparsDesc>(), sl.as<SlabRef>(), int32_t(slabs.size()),
-                                          b.as<SegDesc>(), tol, curb.as<int32_t>(), nrefb.as<int32_t>(),
-                                          errb.as<int32_t>(), lds, multi == 1, h->stream);
-              if (le != hipSuccess)
-                return set_err(h, SPAND_E_HIP, std::string("sparsification launch: ") + hipGetErrorString(le));
-              HIPCHK(hipEventRecord(e1, h->stream));
-              ++nlaunch;
-              keep.push_back(std::move(a));
-              keep.push_back(std::move(b));
-              keep.push_back(std::move(sl));
-            }
+        for (int32_t grp = 1; grp <= 128; grp <<= 1) {
+          const bool multi = grp == 128;
+          std::vector<int32_t> plist;
+          for (int32_t p : by_colour[c])
+            if (multi ? slabS[p] > 1 : (slabS[p] == 1 && tg[p] == grp)) plist.push_back(p);
+          if (plist.empty()) continue;
+          // largest first: interfaces of similar step counts share a launch
+          std::stable_sort(plist.begin(), plist.end(), [&](int32_t x, int32_t y) {
+            if (multi) return sn.size[x] > sn.size[y];
+            return int64_t(sn.size[x]) * ncols[x] > int64_t(sn.size[y]) * ncols[y];
+          });
+          size_t lds = 0;
+          for (int32_t p : plist) lds = std::max(lds, cpqr_lds_bytes(tg[p], nseg[p]));
+          int cap = INT_MAX;
+          if (multi) {
+            cap = cpqr_max_coresident(lds);
+            if (cap <= 0) return set_err(h, SPAND_E_HIP, "occupancy query for the CPQR kernel failed");
           }
+          size_t pos = 0;
+          while (pos < plist.size()) {
+            std::vector<SparsDesc> sds;
+            std::vector<SegDesc> segs;
+            std::vector<SlabRef> slabs;
+            while (pos < plist.size()) {
+              const int32_t p = plist[pos];
+              if (multi && slabS[p] > cap)
+                return set_err(h, SPAND_E_INVALID, "interface needs more co-resident workgroups than the GPU holds");
+              if (multi && !slabs.empty() && int64_t(slabs.size()) + slabS[p] > cap) break;
+              SparsDesc d{};
+              d.V = sn.house.as<double>() + v_off[p];
+              d.tau = sn.house.as<double>() + tau_off[p];
+              d.diag = A + lay.base[p];
+              d.ldd = int32_t(lay.H[p]);
+              d.m = sn.size[p];
+              d.id = p;
+              d.S = slabS[p];
+              d.G = tg[p];
+              if (multi) {
+                d.xch = xchb.as<double>() + xch_off[p];
+                d.cnt = cntb.as<int32_t>() + size_t(multi_idx++) * CNT_PAD;
+              }
+              d.seg_begin = int32_t(segs.size());
+              for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e) {
+                const int32_t q = sy.nb[e];
+                if (sn.size[q] == 0) continue;
+                SegDesc g{};
+                if (q < p) {  // block (p, q) in panel q
+                  g.blk = A + lay.base[q] + lay.find(p, q);
+                  g.ld = int32_t(lay.H[q]);
+                  g.trans = 0;
+                } else {      // block (q, p) in panel p holds A_pq^T
+                  g.blk = A + lay.base[p] + lay.find(q, p);
+                  g.ld = int32_t(lay.H[p]);
+                  g.trans = 1;
+                }
+                g.q = q;
+                segs.push_back(g);
+              }
+              d.seg_end = int32_t(segs.size());
+              for (int32_t w = 0; w < slabS[p]; ++w) slabs.push_back(SlabRef{int32_t(sds.size()), w});
+              sds.push_back(d);
+              ++pos;
+            }
+            DevBuf a, b, sl;
+            if ((st = upload(h, a, sds)) != SPAND_OK) return st;
+            if ((st = upload(h, b, segs)) != SPAND_OK) return st;
+            if ((st = upload(h, sl, slabs)) != SPAND_OK) return st;
+            hipEvent_t e0, e1;
+            HIPCHK(evpool.get(2 * nlaunch, &e0));
+            HIPCHK(evpool.get(2 * nlaunch + 1, &e1));
+            HIPCHK(hipEventRecord(e0, h->stream));
+            hipError_t le = multi ? launch_cpqr_multi(a.as<SparsDesc>(), sl.as<SlabRef>(), int32_t(slabs.size()),
+                                                      b.as<SegDesc>(), tol, curb.as<int32_t>(), nrefb.as<int32_t>(),
+                                                      errb.as<int32_t>(), lds, h->stream)
+                                  : launch_cpqr_one(grp, a.as<SparsDesc>(), sl.as<SlabRef>(), int32_t(slabs.size()),
+                                                    b.as<SegDesc>(), tol, curb.as<int32_t>(), nrefb.as<int32_t>(),
+                                                    errb.as<int32_t>(), lds, h->stream);
+            if (le != hipSuccess)
+              return set_err(h, SPAND_E_HIP, std::string("sparsification launch: ") + hipGetErrorString(le));
+            HIPCHK(hipEventRecord(e1, h->stream));
+            ++nlaunch;
+            keep.push_back(std::move(a));
+            keep.push_back(std::move(b));
+            keep.push_back(std::move(sl));
+          }
+        }
       }
       std::vector<int32_t> rk(nc, -1);
       HIPCHK(hipEventRecord(ph[4], h->stream));

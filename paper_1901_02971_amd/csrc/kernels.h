@@ -78,7 +78,7 @@ struct SparsDesc {
   double* diag;    // diagonal block of p (ld ldd), set to I_r on exit
   double* xch;     // slab exchange (S > 1): 3 buffers x S records of cpqr_record(G) doubles
   int32_t* cnt;    // barrier counter of the slabs (S > 1, zeroed before the launch)
-  int32_t m, ldd, seg_begin, seg_end, id, S;
+  int32_t m, ldd, seg_begin, seg_end, id, S, G, pad;  // G: lanes per column (team size)
 };
 struct SegDesc {
   double* blk;  // block holding A_pq: trans=0 -> A_pq[r][c] = blk[r + c*ld]; trans=1 -> blk[c + r*ld]
@@ -109,10 +109,14 @@ int32_t cpqr_capacity(int32_t G);
 // Doubles of one slab's exchange record (S > 1): 4 scalars + the rows of a team.
 int32_t cpqr_record(int32_t G);
 size_t cpqr_lds_bytes(int32_t G, int32_t nseg);
-int cpqr_max_coresident(int32_t G, size_t lds_bytes);
-hipError_t launch_cpqr(int32_t G, const SparsDesc* d, const SlabRef* slabs, int32_t nslab, const SegDesc* seg,
-                       double eps, int32_t* cursize, int32_t* nref, int32_t* err, size_t lds_bytes, bool cooperative,
-                       hipStream_t s);
+// Co-resident workgroups of the multi-slab kernel at this dynamic LDS size.
+int cpqr_max_coresident(size_t lds_bytes);
+// Single-slab interfaces of team size G (plain launch), and multi-slab interfaces of
+// any team size (cooperative launch: all nslab workgroups resident).
+hipError_t launch_cpqr_one(int32_t G, const SparsDesc* d, const SlabRef* slabs, int32_t nslab, const SegDesc* seg,
+                           double eps, int32_t* cursize, int32_t* nref, int32_t* err, size_t lds_bytes, hipStream_t s);
+hipError_t launch_cpqr_multi(const SparsDesc* d, const SlabRef* slabs, int32_t nslab, const SegDesc* seg, double eps,
+                             int32_t* cursize, int32_t* nref, int32_t* err, size_t lds_bytes, hipStream_t s);
 struct TDesc {
   const double* V;    // m x r, ld m
   const double* tau;  // r

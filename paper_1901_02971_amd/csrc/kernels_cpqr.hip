@@ -137,10 +137,10 @@ __device__ inline void column_ptr(const SegDesc* sg, const int* segoff, int c, d
 
 }  // namespace
 
+// Slab w of interface d (w = 0, S = 1 when MULTI is false).
 template <int G, bool MULTI>
-__global__ void __launch_bounds__(CQ_NT) k_cpqr(const SparsDesc* __restrict__ descs, const SlabRef* __restrict__ slabs,
-                                                const SegDesc* __restrict__ segs, double eps, int32_t* cursize,
-                                                int32_t* nref, int32_t* err) {
+__device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const SegDesc* __restrict__ segs, double eps,
+                                          int32_t* cursize, int32_t* nref, int32_t* err) {
   constexpr int NT = CQ_NT;
   constexpr int NTEAM = NT / G;
   constexpr int CAP = CQ_CPL * NTEAM;
@@ -150,9 +150,7 @@ __global__ void __launch_bounds__(CQ_NT) k_cpqr(const SparsDesc* __restrict__ de
   __shared__ Cand red[2][NW], redx[2][NW];
   __shared__ int red2[NW];
   __shared__ double sh_pn, sh_tau;
-  const SlabRef sr = slabs[blockIdx.x];
-  const SparsDesc d = descs[sr.desc];
-  const int m = d.m, S = MULTI ? d.S : 1, w = MULTI ? sr.w : 0;
+  const int m = d.m, S = MULTI ? d.S : 1, w = MULTI ? wslab : 0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane & (G - 1), team = tid / G;
   const int nseg = d.seg_end - d.seg_begin;
@@ -563,6 +561,37 @@ __global__ void __launch_bounds__(CQ_NT) k_cpqr(const SparsDesc* __restrict__ de
   }
 }
 
+// Single-slab interfaces: one launch per team size.
+template <int G>
+__global__ void __launch_bounds__(CQ_NT) k_cpqr_one(const SparsDesc* __restrict__ descs,
+                                                    const SlabRef* __restrict__ slabs,
+                                                    const SegDesc* __restrict__ segs, double eps, int32_t* cursize,
+                                                    int32_t* nref, int32_t* err) {
+  const SlabRef sr = slabs[blockIdx.x];
+  cpqr_slab<G, false>(descs[sr.desc], 0, segs, eps, cursize, nref, err);
+}
+
+// Multi-slab interfaces of every team size in one cooperative launch: each
+// workgroup takes the code path of its interface's G.
+__global__ void __launch_bounds__(CQ_NT) k_cpqr_multi(const SparsDesc* __restrict__ descs,
+                                                      const SlabRef* __restrict__ slabs,
+                                                      const SegDesc* __restrict__ segs, double eps,
+                                                      int32_t* cursize, int32_t* nref, int32_t* err) {
+  const SlabRef sr = slabs[blockIdx.x];
+  const SparsDesc d = descs[sr.desc];
+  switch (d.G) {
+    case 1: cpqr_slab<1, true>(d, sr.w, segs, eps, cursize, nref, err); break;
+    case 2: cpqr_slab<2, true>(d, sr.w, segs, eps, cursize, nref, err); break;
+    case 4: cpqr_slab<4, true>(d, sr.w, segs, eps, cursize, nref, err); break;
+    case 8: cpqr_slab<8, true>(d, sr.w, segs, eps, cursize, nref, err); break;
+    case 16: cpqr_slab<16, true>(d, sr.w, segs, eps, cursize, nref, err); break;
+    case 32: cpqr_slab<32, true>(d, sr.w, segs, eps, cursize, nref, err); break;
+    case 64: cpqr_slab<64, true>(d, sr.w, segs, eps, cursize, nref, err); break;
+    default: break;  // the host only builds the team sizes above
+  }
+}
+
+
 // Compact WY factor of Q = H_0 ... H_{r-1} = I - V T V^T (T upper triangular):
 // T_jj = tau_j, T[:j, j] = -tau_j T[:j, :j] (V[:, :j]^T v_j).  On entry the upper
 // triangle of T holds S = V^T V (a batched GEMM); one workgroup per interface runs
@@ -640,57 +669,34 @@ size_t cpqr_lds_bytes(int32_t G, int32_t nseg) {
 
 int32_t cpqr_record(int32_t G) { return G * CQ_MR + 4; }
 
-namespace {
-template <int G>
-hipError_t launch_g(const SparsDesc* d, const SlabRef* slabs, int32_t nslab, const SegDesc* seg, double eps,
-                    int32_t* cursize, int32_t* nref, int32_t* err, size_t lds, bool cooperative, hipStream_t s) {
-  if (!cooperative) {
-    hipLaunchKernelGGL((k_cpqr<G, false>), dim3(nslab), dim3(CQ_NT), lds, s, d, slabs, seg, eps, cursize, nref, err);
-    return hipGetLastError();
-  }
-  void* args[] = {(void*)&d, (void*)&slabs, (void*)&seg, (void*)&eps, (void*)&cursize, (void*)&nref, (void*)&err};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_cpqr<G, true>), dim3(nslab), dim3(CQ_NT), args,
-                                    (unsigned int)lds, s);
-}
-
-template <int G>
-int coresident_g(size_t lds) {
+int cpqr_max_coresident(size_t lds) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cpqr<G, true>, CQ_NT, lds) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cpqr_multi, CQ_NT, lds) != hipSuccess) return 0;
   int dev = 0, cus = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   return per_cu * cus;
 }
-}  // namespace
 
-int cpqr_max_coresident(int32_t G, size_t lds) {
-  switch (G) {
-    case 1: return coresident_g<1>(lds);
-    case 2: return coresident_g<2>(lds);
-    case 4: return coresident_g<4>(lds);
-    case 8: return coresident_g<8>(lds);
-    case 16: return coresident_g<16>(lds);
-    case 32: return coresident_g<32>(lds);
-    case 64: return coresident_g<64>(lds);
-  }
-  return 0;
-}
-
-hipError_t launch_cpqr(int32_t G, const SparsDesc* d, const SlabRef* slabs, int32_t nslab, const SegDesc* seg,
-                       double eps, int32_t* cursize, int32_t* nref, int32_t* err, size_t lds, bool cooperative,
-                       hipStream_t s) {
+hipError_t launch_cpqr_one(int32_t G, const SparsDesc* d, const SlabRef* slabs, int32_t nslab, const SegDesc* seg,
+                           double eps, int32_t* cursize, int32_t* nref, int32_t* err, size_t lds, hipStream_t s) {
   if (nslab == 0) return hipSuccess;
   switch (G) {
-    case 1: return launch_g<1>(d, slabs, nslab, seg, eps, cursize, nref, err, lds, cooperative, s);
-    case 2: return launch_g<2>(d, slabs, nslab, seg, eps, cursize, nref, err, lds, cooperative, s);
-    case 4: return launch_g<4>(d, slabs, nslab, seg, eps, cursize, nref, err, lds, cooperative, s);
-    case 8: return launch_g<8>(d, slabs, nslab, seg, eps, cursize, nref, err, lds, cooperative, s);
-    case 16: return launch_g<16>(d, slabs, nslab, seg, eps, cursize, nref, err, lds, cooperative, s);
-    case 32: return launch_g<32>(d, slabs, nslab, seg, eps, cursize, nref, err, lds, cooperative, s);
-    case 64: return launch_g<64>(d, slabs, nslab, seg, eps, cursize, nref, err, lds, cooperative, s);
+#define ONE(GG) \
+  case GG: hipLaunchKernelGGL(k_cpqr_one<GG>, dim3(nslab), dim3(CQ_NT), lds, s, d, slabs, seg, eps, cursize, nref, err); break;
+    ONE(1) ONE(2) ONE(4) ONE(8) ONE(16) ONE(32) ONE(64)
+#undef ONE
+    default: return hipErrorInvalidValue;
   }
-  return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_cpqr_multi(const SparsDesc* d, const SlabRef* slabs, int32_t nslab, const SegDesc* seg, double eps,
+                             int32_t* cursize, int32_t* nref, int32_t* err, size_t lds, hipStream_t s) {
+  if (nslab == 0) return hipSuccess;
+  void* args[] = {(void*)&d, (void*)&slabs, (void*)&seg, (void*)&eps, (void*)&cursize, (void*)&nref, (void*)&err};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_cpqr_multi), dim3(nslab), dim3(CQ_NT), args,
+                                    (unsigned int)lds, s);
 }
 
 }  // namespace spand
