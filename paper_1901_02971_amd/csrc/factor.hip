@@ -784,7 +784,6 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
             if (r < std::min<int64_t>(sn.size[p], ncols[p])) cpqr_flops += 2.0 * (m - r) * (nq - r);
           }
           m_F += (2 * int64_t(sn.size[p]) - r + 1) * r / 2 + r;
-          if (r > 4096) return set_err(h, SPAND_E_INVALID, "interface rank above 4096 is not supported");
           if (r > 0)
             tds.push_back(TDesc{sn.house.as<double>() + v_off[p], sn.house.as<double>() + tau_off[p],
                                 sn.house.as<double>() + t_off[p], sn.size[p], int32_t(r)});
@@ -805,12 +804,60 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       if ((st = vtv.upload_all(h)) != SPAND_OK) return st;
       vtv.launch(h, 0);
       HIPCHK(hipGetLastError());
-      DevBuf dtd;
-      std::stable_partition(tds.begin(), tds.end(), [](const TDesc& x) { return x.r <= build_t_lds_max(); });
-      int32_t nsmall = 0;
-      for (const TDesc& x : tds) nsmall += (x.r <= build_t_lds_max()) ? 1 : 0;
-      if ((st = upload(h, dtd, tds)) != SPAND_OK) return st;
-      launch_build_t(dtd.as<TDesc>(), int32_t(tds.size()), nsmall, h->stream);
+      // T by 64-wide block columns: the diagonal blocks, then for J = 1, 2, ...
+      // X = S[:J0, J] T_JJ and T[:J0, J] = -T[:J0, :J0] X (GEMMs across interfaces)
+      std::vector<TBlock> tbs;
+      int32_t rmax = 0;
+      int64_t x_total = 0;
+      std::vector<int64_t> x_off(tds.size(), -1);
+      for (size_t q = 0; q < tds.size(); ++q) {
+        const TDesc& td = tds[q];
+        for (int32_t j0 = 0; j0 < td.r; j0 += 64) tbs.push_back(TBlock{td.T, td.tau, td.r, j0});
+        rmax = std::max(rmax, td.r);
+        if (td.r > 64) {
+          x_off[q] = x_total;
+          x_total += int64_t(td.r) * 64;
+        }
+      }
+      DevBuf dtb, xb;
+      if ((st = upload(h, dtb, tbs)) != SPAND_OK) return st;
+      launch_build_t_diag(dtb.as<TBlock>(), int32_t(tbs.size()), h->stream);
+      HIPCHK(hipGetLastError());
+      if (rmax > 64) {
+        if ((st = dalloc(h, xb, size_t(x_total) * sizeof(double))) != SPAND_OK) return st;
+        GemmSeq tg2;
+        for (int32_t j0 = 64; j0 < rmax; j0 += 64) {
+          for (size_t q = 0; q < tds.size(); ++q) {
+            const TDesc& td = tds[q];
+            if (td.r <= j0) continue;
+            const int32_t w = std::min(64, td.r - j0);
+            GemmDesc g{};  // X = S[:j0, J] T_JJ
+            g.A = td.T + int64_t(j0) * td.r; g.lda = td.r;
+            g.B = td.T + j0 + int64_t(j0) * td.r; g.ldb = td.r;
+            g.C = xb.as<double>() + x_off[q]; g.ldc = td.r;
+            g.M = j0; g.N = w; g.K = w;
+            g.alpha = 1.0; g.beta = 0.0;
+            tg2.add(g, 0);
+          }
+          tg2.end_launch(0);
+          for (size_t q = 0; q < tds.size(); ++q) {
+            const TDesc& td = tds[q];
+            if (td.r <= j0) continue;
+            const int32_t w = std::min(64, td.r - j0);
+            GemmDesc g{};  // T[:j0, J] = -T[:j0, :j0] X
+            g.A = td.T; g.lda = td.r;
+            g.B = xb.as<double>() + x_off[q]; g.ldb = td.r;
+            g.C = td.T + int64_t(j0) * td.r; g.ldc = td.r;
+            g.M = j0; g.N = w; g.K = j0;
+            g.alpha = -1.0; g.beta = 0.0;
+            tg2.add(g, 0);
+          }
+          tg2.end_launch(0);
+        }
+        if ((st = tg2.upload_all(h)) != SPAND_OK) return st;
+        for (size_t q = 0; q < tg2.cut.size(); ++q) tg2.launch(h, q);
+        HIPCHK(hipGetLastError());
+      }
       HIPCHK(hipGetLastError());
       HIPCHK(hipStreamSynchronize(h->stream));
     }

@@ -123,9 +123,14 @@ struct TDesc {
   double* T;          // r x r output, ld r
   int32_t m, r;
 };
-// d: the interfaces with r <= build_t_lds_max() first (nsmall of them), then the rest.
-void launch_build_t(const TDesc* d, int32_t count, int32_t nsmall, hipStream_t s);
-int32_t build_t_lds_max();
+// Diagonal 64-wide block j0 of the compact-WY factor T (r x r, ld r) of one
+// interface; on entry the upper triangle of T holds V^T V.
+struct TBlock {
+  double* T;
+  const double* tau;
+  int32_t r, j0;
+};
+void launch_build_t_diag(const TBlock* blocks, int32_t count, hipStream_t s);
 
 constexpr int GEMM_TILE = 64;
 

@@ -42,7 +42,6 @@ namespace spand {
 #define CW 256  // threads of k_build_t
 #define TIE_RTOL 1e-10
 #define SPIN_LIMIT (1L << 22)
-#define T_MAX_R 4096
 
 namespace {
 
@@ -594,66 +593,46 @@ __global__ void __launch_bounds__(CQ_NT) k_cpqr_multi(const SparsDesc* __restric
 
 // Compact WY factor of Q = H_0 ... H_{r-1} = I - V T V^T (T upper triangular):
 // T_jj = tau_j, T[:j, j] = -tau_j T[:j, :j] (V[:, :j]^T v_j).  On entry the upper
-// triangle of T holds S = V^T V (a batched GEMM); one workgroup per interface runs
-// the recurrence column by column, column j of S being read before it is
-// overwritten.  The strict lower triangle is set to zero for the tiled products of
-// the apply.  k_build_t_lds keeps T in LDS (r <= T_LDS_R); k_build_t works in place
-// in global memory with S[:j, j] staged in LDS.
-#define T_LDS_R 64
-__global__ void __launch_bounds__(CW) k_build_t_lds(const TDesc* __restrict__ descs) {
-  const TDesc d = descs[blockIdx.x];
-  const int r = d.r, ld = r + 1;  // padded leading dimension in LDS
-  __shared__ double tl[T_LDS_R * (T_LDS_R + 1)];
-  for (int q = threadIdx.x; q < r * r; q += CW) {
-    const int i = q % r, j = q / r;
-    tl[i + j * ld] = (i < j) ? d.T[q] : 0.0;
+// triangle of T holds S = V^T V (a batched GEMM).  T is built by 64-wide block
+// columns: every diagonal block T_JJ follows from S_JJ and the taus of its columns
+// alone (k_build_t_diag, all blocks of all interfaces in one launch, recurrence in
+// LDS); the blocks above it follow from splitting Q = Q_1 Q_2 at column J0,
+//   T[:J0, J] = -T[:J0, :J0] (S[:J0, J] T_JJ),
+// two batched GEMMs per block column J = 1, 2, ... issued by the host.  The strict
+// lower triangle is set to zero (the tiled products of the apply read it).
+__global__ void __launch_bounds__(CW) k_build_t_diag(const TBlock* __restrict__ blocks) {
+  const TBlock b = blocks[blockIdx.x];
+  const int r = b.r, j0 = b.j0, w = min(64, r - j0);
+  __shared__ double tl[64 * 65];
+  const int below = r - j0;
+  for (int q = threadIdx.x; q < below * w; q += CW) {  // zeros under the diagonal of this block column
+    const int i = j0 + q % below, j = j0 + q / below;
+    if (i > j) b.T[i + (int64_t)j * r] = 0.0;
+  }
+  for (int q = threadIdx.x; q < w * w; q += CW) {
+    const int i = q % w, j = q / w;
+    tl[i + j * 65] = (i < j) ? b.T[(j0 + i) + (int64_t)(j0 + j) * r] : 0.0;
   }
   __syncthreads();
   const int i = threadIdx.x;
-  for (int j = 0; j < r; ++j) {
-    double s = 0.0;
+  for (int j = 0; j < w; ++j) {
+    double acc = 0.0;
     if (i < j)
-      for (int l = i; l < j; ++l) s += tl[i + l * ld] * tl[l + j * ld];
+      for (int l = i; l < j; ++l) acc += tl[i + l * 65] * tl[l + j * 65];
     __syncthreads();
-    if (i < j) tl[i + j * ld] = -d.tau[j] * s;
-    if (i == j) tl[j + j * ld] = d.tau[j];
+    if (i < j) tl[i + j * 65] = -b.tau[j0 + j] * acc;
+    if (i == j) tl[j + j * 65] = b.tau[j0 + j];
     __syncthreads();
   }
-  for (int q = threadIdx.x; q < r * r; q += CW) d.T[q] = tl[q % r + (q / r) * ld];
-}
-
-__global__ void __launch_bounds__(CW) k_build_t(const TDesc* __restrict__ descs) {
-  const TDesc d = descs[blockIdx.x];
-  const int r = d.r;
-  __shared__ double y[T_MAX_R];
-  for (int64_t q = threadIdx.x; q < (int64_t)r * r; q += CW) {
-    const int i = (int)(q % r), j = (int)(q / r);
-    if (i > j) d.T[q] = 0.0;
-  }
-  for (int j = 0; j < r; ++j) {
-    const double tj = d.tau[j];
-    if (j > 0) {
-      for (int i = threadIdx.x; i < j; i += CW) y[i] = d.T[i + (int64_t)j * r];
-      __syncthreads();
-      for (int i = threadIdx.x; i < j; i += CW) {
-        double s = 0.0;
-        for (int l = i; l < j; ++l) s += d.T[i + (int64_t)l * r] * y[l];
-        d.T[i + (int64_t)j * r] = -tj * s;
-      }
-    }
-    if (threadIdx.x == 0) d.T[j + (int64_t)j * r] = tj;
-    __threadfence_block();
-    __syncthreads();
+  for (int q = threadIdx.x; q < w * w; q += CW) {
+    const int ii = q % w, jj = q / w;
+    if (ii <= jj) b.T[(j0 + ii) + (int64_t)(j0 + jj) * r] = tl[ii + jj * 65];
   }
 }
 
-// descs: the interfaces with r <= T_LDS_R first (nsmall of them), then the others
-void launch_build_t(const TDesc* d, int32_t count, int32_t nsmall, hipStream_t s) {
-  if (nsmall > 0) hipLaunchKernelGGL(k_build_t_lds, dim3(nsmall), dim3(CW), 0, s, d);
-  if (count > nsmall) hipLaunchKernelGGL(k_build_t, dim3(count - nsmall), dim3(CW), 0, s, d + nsmall);
+void launch_build_t_diag(const TBlock* blocks, int32_t count, hipStream_t s) {
+  if (count > 0) hipLaunchKernelGGL(k_build_t_diag, dim3(count), dim3(CW), 0, s, blocks);
 }
-
-int32_t build_t_lds_max() { return T_LDS_R; }
 
 int32_t cpqr_team(int32_t m) {
   int32_t G = 1;

@@ -77,17 +77,20 @@ void launch_scatter_values(const double* vals, const int64_t* dst, int64_t nnz, 
 }
 
 // ---------------------------------------------------------------- Schur reduce
+// Only the lower triangle of a diagonal target block is accumulated: its upper
+// triangle is never read again (Cholesky, the left solves, the merge and the CPQR
+// read lower triangles and off-diagonal blocks only).
 __global__ void __launch_bounds__(WG) k_reduce(const ReduceDesc* __restrict__ descs,
                                                const ContribDesc* __restrict__ cs) {
   const ReduceDesc d = descs[blockIdx.x];
-  const int64_t cnt = (int64_t)d.rows * d.cols;
-  for (int64_t e = threadIdx.x; e < cnt; e += WG) {
-    const int r = (int)(e % d.rows), c = (int)(e / d.rows);
-    const bool mirror = d.diag && r < c;
+  const uint32_t rows = (uint32_t)d.rows, cnt = rows * (uint32_t)d.cols;
+  for (uint32_t e = threadIdx.x; e < cnt; e += WG) {
+    const uint32_t c = e / rows, r = e - c * rows;
+    if (d.diag && r < c) continue;
     double sum = 0.0;
     for (int q = d.c_begin; q < d.c_end; ++q) {
       const ContribDesc cd = cs[q];
-      sum += mirror ? cd.C[c + (int64_t)r * cd.ldC] : cd.C[r + (int64_t)c * cd.ldC];
+      sum += cd.C[r + (int64_t)c * cd.ldC];
     }
     d.T[r + (int64_t)c * d.ldT] -= sum;
   }
