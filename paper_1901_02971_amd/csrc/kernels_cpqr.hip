@@ -73,17 +73,66 @@ __device__ inline Cand cand_combine(const Cand& a, const Cand& b) {
   return o;
 }
 
+// Cross-lane moves inside rows of 16 lanes (DPP): quad_perm [1,0,3,2] and
+// [2,3,0,1] exchange with lane^1 and lane^2, row_half_mirror pairs lane i with
+// 7 - i of its 8-lane half, row_mirror pairs i with 15 - i.  Applied in this order
+// a combine of the two operands reaches every lane of a group of 2, 4, 8, 16 lanes.
+constexpr int DPP_X1 = 0xB1, DPP_X2 = 0x4E, DPP_HMIR = 0x141, DPP_MIR = 0x140;
+
+template <int CTRL>
+__device__ inline int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+// lane ^ 16 inside each half of the wave (ds_swizzle, bit-mask mode)
+__device__ inline double swz_x16(double v) {
+  const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x401F);
+  const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x401F);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline double read_lane(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// Sum over the G lanes of a team (G consecutive lanes, G a power of two <= 64).
+// Every step adds two partial sums in either order, so all lanes of the team end
+// with the same bits.
 template <int G>
 __device__ inline double team_sum(double v) {
-#pragma unroll
-  for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o, 64);
+  if constexpr (G >= 2) v += dpp_d<DPP_X1>(v);
+  if constexpr (G >= 4) v += dpp_d<DPP_X2>(v);
+  if constexpr (G >= 8) v += dpp_d<DPP_HMIR>(v);
+  if constexpr (G >= 16) v += dpp_d<DPP_MIR>(v);
+  if constexpr (G >= 32) v += swz_x16(v);
+  if constexpr (G >= 64) v = read_lane(v, 0) + read_lane(v, 32);
   return v;
 }
 
+// Largest value / smallest int of the wave, returned wave-uniform.
+__device__ inline double wave_max(double v) {
+  v = fmax(v, dpp_d<DPP_X1>(v));
+  v = fmax(v, dpp_d<DPP_X2>(v));
+  v = fmax(v, dpp_d<DPP_HMIR>(v));
+  v = fmax(v, dpp_d<DPP_MIR>(v));
+  return fmax(fmax(read_lane(v, 0), read_lane(v, 16)), fmax(read_lane(v, 32), read_lane(v, 48)));
+}
 __device__ inline int wave_min(int v) {
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) v = min(v, __shfl_xor(v, o, 64));
-  return v;
+  v = min(v, dpp_i<DPP_X1>(v));
+  v = min(v, dpp_i<DPP_X2>(v));
+  v = min(v, dpp_i<DPP_HMIR>(v));
+  v = min(v, dpp_i<DPP_MIR>(v));
+  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+__device__ inline double first_lane(double v) {
+  return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                          __builtin_amdgcn_readfirstlane(__double2loint(v)));
 }
 
 // Barrier among the S workgroups of one interface: a monotone counter; barrier
@@ -144,20 +193,25 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
   constexpr int NTEAM = NT / G;
   constexpr int CAP = CQ_CPL * NTEAM;
   constexpr int NW = NT / 64;
-  constexpr int ROWS = G * CQ_MR;  // rows a team can hold (>= m)
+  constexpr int ROWS = G * CQ_MR;    // rows a team can hold (>= m)
+  constexpr int NGRP = CQ_MR / 4;    // row groups: group u is rows [4uG, 4uG + 4G), registers 4u..4u+3
+  constexpr int RPT = (ROWS + NT - 1) / NT;  // reflector rows formed per thread
   extern __shared__ double lds[];
-  __shared__ Cand red[2][NW], redx[2][NW];
-  __shared__ int red2[NW];
-  __shared__ double sh_pn, sh_tau;
+  __shared__ double pmx[2][NW];
+  __shared__ int pcd[2][NW];
+  __shared__ double sh_pn, sh_x2;
   const int m = d.m, S = MULTI ? d.S : 1, w = MULTI ? wslab : 0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane & (G - 1), team = tid / G;
   const int nseg = d.seg_end - d.seg_begin;
   const SegDesc* sg = segs + d.seg_begin;
-  // vm[i] = (v_i, [i > j]): the reflector of the current step, v_i = 0 above row j,
-  // v_j = 1, zero below row m; the flag selects the rows of the trailing norms
-  double2* vm = reinterpret_cast<double2*>(lds);
-  int* segoff = reinterpret_cast<int*>(lds + 2 * ROWS);  // nseg + 1
+  // vv: the reflector of the current step (v_i = 0 above row j and from row m on,
+  // v_j = 1); cv: the pivot column as its team publishes it (single slab); rb:
+  // R_jj of every step, written into the pivot columns at the end
+  double* vv = lds;
+  double* cv = lds + ROWS;
+  double* rb = lds + 2 * ROWS;
+  int* segoff = reinterpret_cast<int*>(lds + 3 * ROWS);  // nseg + 1
   // exchange record of slab q in buffer b: [max, cand norm, cand xn2, cand index, ROWS column rows]
   auto xrec = [&](int b, int q) { return d.xch + ((size_t)b * S + q) * (size_t)(ROWS + 4); };
 
@@ -202,150 +256,133 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
   }
 
   const int kmax = min(m, nc);
+  const int uend = (m + 4 * G - 1) / (4 * G);  // groups holding rows below m
   int r = kmax;
   double r00 = 0.0;
   int bar = 0;
   for (int j = 0; j < kmax; ++j) {
-    // ---- pivot candidate of this lane, then of the wave and the workgroup
+    const int jg = j - g;  // row q * G + g of this lane lies below row j iff q * G > jg
+    // ---- pivot of this slab: the largest remaining norm M, then the smallest column
+    // index whose norm is >= M (1 - TIE_RTOL); two exact reductions
     double nv[CQ_CPL];
-    Cand t;
-    t.mx = -1.0;
+    double lmx = -1.0;
 #pragma unroll
     for (int k = 0; k < CQ_CPL; ++k) {
       nv[k] = (pst[k] == -1) ? sqrt(nrm[k]) : -1.0;
-      t.mx = fmax(t.mx, nv[k]);
+      lmx = fmax(lmx, nv[k]);
     }
-    t.cd = INT_MAX;
-    t.cn = -1.0;
-    t.amb = 0;
-    {
-      const double thr = t.mx * (1.0 - TIE_RTOL);
-#pragma unroll
-      for (int k = 0; k < CQ_CPL; ++k)
-        if (pst[k] == -1 && nv[k] >= thr && col[k] < t.cd) {
-          t.cd = col[k];
-          t.cn = nv[k];
-        }
-    }
-#pragma unroll
-    for (int o = G; o < 64; o <<= 1) {
-      Cand u;
-      u.mx = __shfl_xor(t.mx, o, 64);
-      u.cn = __shfl_xor(t.cn, o, 64);
-      u.cd = __shfl_xor(t.cd, o, 64);
-      u.amb = __shfl_xor(t.amb, o, 64);
-      t = cand_combine(t, u);
-    }
-    if (lane == 0) red[j & 1][wave] = t;
+    lmx = wave_max(lmx);
+    if (lane == 0) pmx[j & 1][wave] = lmx;
     __syncthreads();
-    Cand wg = red[j & 1][0];
+    double smx = pmx[j & 1][0];
 #pragma unroll
-    for (int q = 1; q < NW; ++q) wg = cand_combine(wg, red[j & 1][q]);
-    if (wg.amb) {  // exact smallest index at the workgroup's threshold
-      const double thr = wg.mx * (1.0 - TIE_RTOL);
-      int c2 = INT_MAX;
+    for (int q = 1; q < NW; ++q) smx = fmax(smx, pmx[j & 1][q]);
+    int scd;
+    {
+      const double thr = smx * (1.0 - TIE_RTOL);
+      int c = INT_MAX;
 #pragma unroll
       for (int k = 0; k < CQ_CPL; ++k)
-        if (pst[k] == -1 && nv[k] >= thr) c2 = min(c2, col[k]);
-      c2 = wave_min(c2);
-      if (lane == 0) red2[wave] = c2;
+        if (pst[k] == -1 && nv[k] >= thr) c = min(c, col[k]);
+      c = wave_min(c);
+      if (lane == 0) pcd[j & 1][wave] = c;
       __syncthreads();
-      int best = red2[0];
+      scd = pcd[j & 1][0];
 #pragma unroll
-      for (int q = 1; q < NW; ++q) best = min(best, red2[q]);
-      __syncthreads();  // red2 is rewritten by its next use
-      wg.cd = best;
+      for (int q = 1; q < NW; ++q) scd = min(scd, pcd[j & 1][q]);
     }
-    if (!MULTI && wg.cd == INT_MAX) {  // only non-finite norms left
+    if (!MULTI && scd == INT_MAX) {  // only non-finite norms left
       r = j;
       break;
     }
     // team and register slot of this slab's candidate
-    const int lc = wg.cd - w * CAP;
-    const bool own = wg.cd != INT_MAX && team == lc % NTEAM;
+    const int lc = scd - w * CAP;
+    const bool own = scd != INT_MAX && team == lc % NTEAM;
     const int pk = own ? lc / NTEAM : 0;
+    const int ujp = j / (4 * G);  // row group holding row j
     int piv;
+    double pn, x2, alpha;
+    const double* rc = nullptr;
     if constexpr (!MULTI) {
-      // the owner team forms the reflector from its column and publishes it
+      // the owner team publishes its column and the squared norm of its rows below j
       if (own) {
 #pragma unroll
         for (int k = 0; k < CQ_CPL; ++k)
           if (k == pk) {
-            double x2 = 0.0, al = 0.0;
+            double s2 = 0.0;
 #pragma unroll
-            for (int q = 0; q < CQ_MR; ++q) {
-              const int jq = j - q * G;
-              x2 = (g > jq) ? fma(a[k][q], a[k][q], x2) : x2;
-              al = (g == jq) ? a[k][q] : al;
-            }
-            x2 = team_sum<G>(x2);
-            const double alpha = team_sum<G>(al);  // one lane holds row j, the others add 0
-            const double pn = nv[k];
-            const double r0 = (j == 0) ? pn : r00;
-            const bool stop = (r0 == 0.0) || (pn < eps * r0);
-            double tau = 0.0, scale = 0.0, beta = alpha;
-            if (x2 != 0.0) {
-              beta = -copysign(sqrt(alpha * alpha + x2), alpha);
-              tau = (beta - alpha) / beta;
-              scale = 1.0 / (alpha - beta);
-            }
-            if (!stop) {
+            for (int gi = 0; gi < NGRP; ++gi) {
+              if (gi >= ujp && gi < uend) {
 #pragma unroll
-              for (int q = 0; q < CQ_MR; ++q) {
-                const int jq = j - q * G;
-                const double x = a[k][q];
-                vm[q * G + g] = make_double2((g > jq) ? x * scale : ((g == jq) ? 1.0 : 0.0), (g > jq) ? 1.0 : 0.0);
-                a[k][q] = (g == jq) ? beta : ((g > jq) ? 0.0 : x);  // column j of R
+                for (int u = 0; u < 4; ++u) {
+                  const int q = 4 * gi + u;
+                  cv[q * G + g] = a[k][q];
+                  s2 = (gi > ujp || q * G > jg) ? fma(a[k][q], a[k][q], s2) : s2;
+                }
               }
-              pst[k] = j;
             }
+            s2 = team_sum<G>(s2);
             if (g == 0) {
-              sh_pn = pn;
-              sh_tau = tau;
+              sh_pn = nv[k];
+              sh_x2 = s2;
             }
           }
       }
       __syncthreads();
-      piv = wg.cd;
+      piv = scd;
+      pn = sh_pn;
+      x2 = sh_x2;
+      alpha = cv[j];
     } else {
-      // publish (slab max, slab candidate, its norm, its rows); one barrier
+      // publish (slab max, slab candidate, its norm, its rows); one barrier.  The
+      // rows of a record are stored lane-major: row q * G + g at g * CQ_MR + q.
       {
-        double* rc = xrec(j & 1, w);
+        double* rw = xrec(j & 1, w);
         if (own) {
 #pragma unroll
           for (int k = 0; k < CQ_CPL; ++k)
             if (k == pk) {
-              double x2 = 0.0;
+              double* rl = rw + 4 + g * CQ_MR;
+              double s2 = 0.0;
 #pragma unroll
-              for (int q = 0; q < CQ_MR; ++q) {
-                shared_store(rc + 4 + q * G + g, a[k][q]);
-                x2 = (g > j - q * G) ? fma(a[k][q], a[k][q], x2) : x2;
+              for (int gi = 0; gi < NGRP; ++gi) {
+                if (gi >= ujp && gi < uend) {
+#pragma unroll
+                  for (int u = 0; u < 4; ++u) {
+                    const int q = 4 * gi + u;
+                    shared_store(rl + q, a[k][q]);
+                    s2 = (gi > ujp || q * G > jg) ? fma(a[k][q], a[k][q], s2) : s2;
+                  }
+                }
               }
-              x2 = team_sum<G>(x2);
+              s2 = team_sum<G>(s2);
               if (g == 0) {
-                shared_store(rc + 1, nv[k]);
-                shared_store(rc + 2, x2);
+                shared_store(rw + 1, nv[k]);
+                shared_store(rw + 2, s2);
               }
             }
         }
         if (tid == 0) {
-          shared_store(rc, wg.mx);
-          shared_store(rc + 3, (wg.cd == INT_MAX) ? -1.0 : (double)wg.cd);
-          if (wg.cd == INT_MAX) shared_store(rc + 1, -1.0);
+          shared_store(rw, smx);
+          shared_store(rw + 3, (scd == INT_MAX) ? -1.0 : (double)scd);
+          if (scd == INT_MAX) shared_store(rw + 1, -1.0);
         }
       }
       int xb = j & 1;
       slab_barrier(d.cnt, ++bar * S, err);
-      // the S records are read in parallel (one memory round trip) and reduced like
-      // the lanes; the owning slab of column c is c / CAP
+      // every wave reads the S records (one memory round trip) and reduces them
+      // itself; lanes 0..P-1 end with the same result.  The owning slab of column c
+      // is c / CAP.
+      int P = 1;
+      while (P < S && P < 64) P <<= 1;
       Cand u;
       u.mx = -1.0;
       u.cn = -1.0;
       u.cd = INT_MAX;
       u.amb = 0;
-      for (int q = tid; q < S; q += NT) {  // S may exceed the workgroup size
-        const double* rc = xrec(xb, q);
-        const double mx = shared_load(rc), cn = shared_load(rc + 1), cq = shared_load(rc + 3);
+      for (int q = lane; q < S; q += 64) {  // S may exceed the wave size
+        const double* rq = xrec(xb, q);
+        const double mx = shared_load(rq), cn = shared_load(rq + 1), cq = shared_load(rq + 3);
         Cand v;
         v.mx = mx;
         v.cn = (cq >= 0.0) ? cn : -1.0;
@@ -353,8 +390,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
         v.amb = 0;
         u = cand_combine(u, v);
       }
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
+      for (int o = 1; o < P; o <<= 1) {
         Cand v;
         v.mx = __shfl_xor(u.mx, o, 64);
         v.cn = __shfl_xor(u.cn, o, 64);
@@ -362,104 +398,60 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
         v.amb = __shfl_xor(u.amb, o, 64);
         u = cand_combine(u, v);
       }
-      if (lane == 0) redx[j & 1][wave] = u;
-      __syncthreads();
-      Cand gc = redx[j & 1][0];
-#pragma unroll
-      for (int q = 1; q < NW; ++q) gc = cand_combine(gc, redx[j & 1][q]);
-      piv = gc.cd;
-      if (gc.amb) {  // second round with the exact global threshold (near-ties across slabs)
+      const double gmx = first_lane(u.mx);
+      piv = __builtin_amdgcn_readfirstlane(u.cd);
+      if (__builtin_amdgcn_readfirstlane(u.amb)) {  // second round with the exact global threshold
         xb = 2;
-        const double thr = gc.mx * (1.0 - TIE_RTOL);
+        const double thr = gmx * (1.0 - TIE_RTOL);
         int c2 = INT_MAX;
 #pragma unroll
         for (int k = 0; k < CQ_CPL; ++k)
           if (pst[k] == -1 && nv[k] >= thr) c2 = min(c2, col[k]);
         c2 = wave_min(c2);
-        if (lane == 0) red2[wave] = c2;
+        if (lane == 0) pcd[j & 1][wave] = c2;  // free: every wave has read pcd[j & 1]
         __syncthreads();
-        int best = red2[0];
+        int best = pcd[j & 1][0];
 #pragma unroll
-        for (int q = 1; q < NW; ++q) best = min(best, red2[q]);
+        for (int q = 1; q < NW; ++q) best = min(best, pcd[j & 1][q]);
         const int lc2 = best - w * CAP;
-        double* rc = xrec(2, w);
+        double* rw = xrec(2, w);
         if (best != INT_MAX && team == lc2 % NTEAM) {
           const int pk2 = lc2 / NTEAM;
 #pragma unroll
           for (int k = 0; k < CQ_CPL; ++k)
             if (k == pk2) {
-              double x2 = 0.0;
+              double* rl = rw + 4 + g * CQ_MR;
+              double s2 = 0.0;
 #pragma unroll
               for (int q = 0; q < CQ_MR; ++q) {
-                shared_store(rc + 4 + q * G + g, a[k][q]);
-                x2 = (g > j - q * G) ? fma(a[k][q], a[k][q], x2) : x2;
+                shared_store(rl + q, a[k][q]);
+                s2 = (q * G > jg) ? fma(a[k][q], a[k][q], s2) : s2;
               }
-              x2 = team_sum<G>(x2);
+              s2 = team_sum<G>(s2);
               if (g == 0) {
-                shared_store(rc + 1, nv[k]);
-                shared_store(rc + 2, x2);
+                shared_store(rw + 1, nv[k]);
+                shared_store(rw + 2, s2);
               }
             }
         }
-        if (tid == 0) shared_store(rc + 3, (best == INT_MAX) ? -1.0 : (double)best);
+        if (tid == 0) shared_store(rw + 3, (best == INT_MAX) ? -1.0 : (double)best);
         slab_barrier(d.cnt, ++bar * S, err);
         int b2 = INT_MAX;
-        for (int q = tid; q < S; q += NT) {
+        for (int q = lane; q < S; q += 64) {
           const double cq = shared_load(xrec(2, q) + 3);
           if (cq >= 0.0) b2 = min(b2, (int)cq);
         }
-        b2 = wave_min(b2);
-        if (lane == 0) red2[wave] = b2;
-        __syncthreads();
-        piv = red2[0];
-#pragma unroll
-        for (int q = 1; q < NW; ++q) piv = min(piv, red2[q]);
-        __syncthreads();  // red2 is rewritten by its next use
+        piv = wave_min(b2);
       }
       if (piv == INT_MAX) {  // only non-finite norms left
         r = j;
         break;
       }
-      // every thread forms the reflector from the winning record (identical arithmetic)
-      const double* rc = xrec(xb, piv / CAP);
-      const double pn = shared_load(rc + 1);
-      const double x2 = shared_load(rc + 2);
-      const double alpha = shared_load(rc + 4 + j);
-      const double r0 = (j == 0) ? pn : r00;
-      const bool stop = (r0 == 0.0) || (pn < eps * r0);
-      double tau = 0.0, scale = 0.0, beta = alpha;
-      if (x2 != 0.0) {
-        beta = -copysign(sqrt(alpha * alpha + x2), alpha);
-        tau = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
-      }
-      if (!stop) {
-        for (int i = tid; i < ROWS; i += NT) {
-          const double x = (i > j) ? shared_load(rc + 4 + i) : 0.0;
-          vm[i] = make_double2((i > j) ? x * scale : ((i == j) ? 1.0 : 0.0), (i > j) ? 1.0 : 0.0);
-        }
-        const int plc = piv - w * CAP;
-        if (plc >= 0 && plc < CAP && team == plc % NTEAM) {
-          const int ppk = plc / NTEAM;
-#pragma unroll
-          for (int k = 0; k < CQ_CPL; ++k)
-            if (k == ppk) {
-#pragma unroll
-              for (int q = 0; q < CQ_MR; ++q) {
-                const int jq = j - q * G;
-                a[k][q] = (g == jq) ? beta : ((g > jq) ? 0.0 : a[k][q]);  // column j of R
-              }
-              pst[k] = j;
-            }
-        }
-      }
-      if (tid == 0) {
-        sh_pn = pn;
-        sh_tau = tau;
-      }
-      __syncthreads();
+      rc = xrec(xb, piv / CAP);
+      pn = shared_load(rc + 1);
+      x2 = shared_load(rc + 2);
+      alpha = shared_load(rc + 4 + (j % G) * CQ_MR + j / G);
     }
-    const double pn = sh_pn;
     if (j == 0) {
       r00 = pn;
       if (r00 == 0.0) {
@@ -471,35 +463,78 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
       r = j;
       break;
     }
-    const double tau = sh_tau;
-    if (w == 0) {
-      double* V = d.V + (int64_t)j * m;
-      for (int i = tid; i < m; i += NT) V[i] = vm[i].x;
-      if (tid == 0) d.tau[j] = tau;
+    // every thread forms the reflector (LAPACK dlarfg convention) with identical
+    // arithmetic, then its share of the rows of v
+    double tau = 0.0, scale = 0.0, beta = alpha;
+    if (x2 != 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + x2), alpha);
+      tau = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
     }
-    // ---- apply H_j to the remaining columns; new trailing norms (rows j+1..).  The
-    // (v_i, [i > j]) pairs are read four rows ahead of their use (two passes).
-    const double2* vl = vm + g;
+    {
+      double xs[RPT];
+#pragma unroll
+      for (int u = 0; u < RPT; ++u) {
+        const int i = tid + u * NT;
+        if constexpr (MULTI)
+          xs[u] = (i > j && i < m) ? shared_load(rc + 4 + (i % G) * CQ_MR + i / G) : 0.0;
+        else
+          xs[u] = (i < ROWS) ? cv[i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < RPT; ++u) {
+        const int i = tid + u * NT;
+        if (i < ROWS) {
+          const double v = (i > j) ? xs[u] * scale : ((i == j) ? 1.0 : 0.0);
+          vv[i] = v;
+          if (w == 0 && i < m) d.V[(int64_t)j * m + i] = v;
+        }
+      }
+    }
+    if (tid == 0) {
+      rb[j] = beta;
+      if (w == 0) d.tau[j] = tau;
+    }
+    {  // the pivot column becomes column j of R (its rows are set at the write-back)
+      const int plc = piv - w * CAP;
+      if (plc >= 0 && plc < CAP && team == plc % NTEAM) {
+#pragma unroll
+        for (int k = 0; k < CQ_CPL; ++k)
+          if (k == plc / NTEAM) pst[k] = j;
+      }
+    }
+    __syncthreads();
+    // ---- apply H_j to the remaining columns and form their new trailing norms.
+    // Only the row groups uj..uend-1 take part: rows above j have v = 0 and leave
+    // the norms, rows from m on are zero.  Group uj holds row j and is the only one
+    // with rows on both sides of it.
+    const int uj = j / (4 * G);
+    const double* vl = vv + g;
     double dot[CQ_CPL];
 #pragma unroll
     for (int k = 0; k < CQ_CPL; ++k) dot[k] = 0.0;
     {
-      double2 cur[4], nxt[4];
+      double cur[4], nxt[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) cur[u] = vl[u * G];
+      for (int u = 0; u < 4; ++u) cur[u] = nxt[u] = 0.0;
 #pragma unroll
-      for (int q0 = 0; q0 < CQ_MR; q0 += 4) {
-        if (q0 + 4 < CQ_MR) {
+      for (int gi = 0; gi < NGRP; ++gi) {
+        if (gi >= uj && gi < uend) {
+          if (gi == uj) {
 #pragma unroll
-          for (int u = 0; u < 4; ++u) nxt[u] = vl[(q0 + 4 + u) * G];
+            for (int u = 0; u < 4; ++u) cur[u] = vl[(4 * gi + u) * G];
+          }
+          if (gi + 1 < NGRP && gi + 1 < uend) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) nxt[u] = vl[(4 * gi + 4 + u) * G];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int k = 0; k < CQ_CPL; ++k) dot[k] = fma(cur[u], a[k][4 * gi + u], dot[k]);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) cur[u] = nxt[u];
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int k = 0; k < CQ_CPL; ++k) dot[k] = fma(cur[u].x, a[k][q0 + u], dot[k]);
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) cur[u] = nxt[u];
       }
     }
     double wv[CQ_CPL], sq[CQ_CPL];
@@ -510,42 +545,62 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
       sq[k] = 0.0;
     }
     {
-      double2 cur[4], nxt[4];
+      double cur[4], nxt[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) cur[u] = vl[u * G];
+      for (int u = 0; u < 4; ++u) cur[u] = nxt[u] = 0.0;
 #pragma unroll
-      for (int q0 = 0; q0 < CQ_MR; q0 += 4) {
-        if (q0 + 4 < CQ_MR) {
+      for (int gi = 0; gi < NGRP; ++gi) {
+        if (gi >= uj && gi < uend) {
+          if (gi == uj) {
 #pragma unroll
-          for (int u = 0; u < 4; ++u) nxt[u] = vl[(q0 + 4 + u) * G];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int k = 0; k < CQ_CPL; ++k) {
-            const double x = fma(-wv[k], cur[u].x, a[k][q0 + u]);
-            a[k][q0 + u] = x;
-            sq[k] = fma(x * cur[u].y, x, sq[k]);
+            for (int u = 0; u < 4; ++u) cur[u] = vl[(4 * gi + u) * G];
           }
-        __builtin_amdgcn_sched_barrier(0);
+          if (gi + 1 < NGRP && gi + 1 < uend) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) cur[u] = nxt[u];
+            for (int u = 0; u < 4; ++u) nxt[u] = vl[(4 * gi + 4 + u) * G];
+          }
+          if (gi == uj) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+              for (int k = 0; k < CQ_CPL; ++k) {
+                const double x = fma(-wv[k], cur[u], a[k][4 * gi + u]);
+                a[k][4 * gi + u] = x;
+                sq[k] = ((4 * gi + u) * G > jg) ? fma(x, x, sq[k]) : sq[k];
+              }
+          } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+              for (int k = 0; k < CQ_CPL; ++k) {
+                const double x = fma(-wv[k], cur[u], a[k][4 * gi + u]);
+                a[k][4 * gi + u] = x;
+                sq[k] = fma(x, x, sq[k]);
+              }
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) cur[u] = nxt[u];
+        }
       }
     }
 #pragma unroll
     for (int k = 0; k < CQ_CPL; ++k) nrm[k] = team_sum<G>(sq[k]);
   }
-  // ---- W_cn = R[:r, :] (column order of A_pn) into the blocks of p
+  __syncthreads();  // rb complete
+  // ---- W_cn = R[:r, :] (column order of A_pn) into the blocks of p.  A pivot
+  // column of step s holds R_ij for i < s; its row s is R_ss and the rows below are 0.
 #pragma unroll
   for (int k = 0; k < CQ_CPL; ++k) {
     if (col[k] < 0 || r == 0) continue;
     double* base;
     int64_t stride;
     column_ptr(sg, segoff, col[k], base, stride);
+    const int ps = pst[k];
+    const double rss = (ps >= 0) ? rb[ps] : 0.0;
 #pragma unroll
     for (int q = 0; q < CQ_MR; ++q) {
       const int i = q * G + g;
-      if (i < r) base[(int64_t)i * stride] = a[k][q];
+      if (i < r) base[(int64_t)i * stride] = (ps >= 0 && i >= ps) ? ((i == ps) ? rss : 0.0) : a[k][q];
     }
   }
   if (w == 0) {
@@ -643,7 +698,7 @@ int32_t cpqr_team(int32_t m) {
 int32_t cpqr_capacity(int32_t G) { return CQ_CPL * CQ_NT / G; }
 
 size_t cpqr_lds_bytes(int32_t G, int32_t nseg) {
-  return 2 * size_t(G) * CQ_MR * sizeof(double) + (size_t(nseg) + 1) * sizeof(int32_t) + 16;
+  return 3 * size_t(G) * CQ_MR * sizeof(double) + (size_t(nseg) + 1) * sizeof(int32_t) + 16;
 }
 
 int32_t cpqr_record(int32_t G) { return G * CQ_MR + 4; }
