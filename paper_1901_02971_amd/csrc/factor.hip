@@ -617,7 +617,6 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       int64_t house_total = 0, xch_total = 0;
       std::vector<int64_t> xch_off(nc, -1);
       std::vector<int32_t> slabS(nc, 0), tg(nc, 0), nseg(nc, 0);
-      int32_t nmulti = 0;
       for (int32_t p = ne; p < nc; ++p) {
         for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e)
           if (sn.size[sy.nb[e]] > 0) {
@@ -637,7 +636,6 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
         if (slabS[p] > 1) {
           xch_off[p] = xch_total;
           xch_total += 3 * int64_t(slabS[p]) * cpqr_record(G);  // three exchange buffers
-          ++nmulti;
         }
         const int64_t kmax = std::min<int64_t>(sn.size[p], ncols[p]);
         v_off[p] = house_total;
@@ -648,13 +646,10 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
         house_total += kmax * kmax;
       }
       if ((st = dalloc(h, sn.house, size_t(house_total) * sizeof(double))) != SPAND_OK) return st;
-      DevBuf xchb, cntb, curb, nrefb, errb;
+      DevBuf xchb, curb, nrefb, errb;
       if ((st = dalloc(h, xchb, size_t(xch_total) * sizeof(double))) != SPAND_OK) return st;
-      // one barrier counter per multi-slab interface, 128 bytes apart (no shared lines)
-      constexpr int32_t CNT_PAD = 32;
-      const size_t ncnt = size_t(std::max(nmulti, 1)) * CNT_PAD;
-      if ((st = dalloc(h, cntb, ncnt * sizeof(int32_t))) != SPAND_OK) return st;
-      HIPCHK(hipMemsetAsync(cntb.p, 0, ncnt * sizeof(int32_t), h->stream));
+      // the exchange headers start with tag 0; the first exchange of a buffer uses tag 1
+      if (xch_total > 0) HIPCHK(hipMemsetAsync(xchb.p, 0, size_t(xch_total) * sizeof(double), h->stream));
       if ((st = dalloc(h, errb, sizeof(int32_t))) != SPAND_OK) return st;
       HIPCHK(hipMemsetAsync(errb.p, 0, sizeof(int32_t), h->stream));
       // current sizes: interfaces shrink to their rank as their colour class finishes
@@ -664,7 +659,6 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       for (int32_t p = ne; p < nc; ++p)
         if (v_off[p] >= 0) by_colour[sy.colour[p]].push_back(p);
       std::vector<DevBuf> keep;
-      int32_t multi_idx = 0;
       size_t nlaunch = 0;
       // launch groups of one colour: single-slab interfaces per team size G
       // (group G), then every multi-slab interface of the colour together (group 0)
@@ -707,10 +701,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
               d.id = p;
               d.S = slabS[p];
               d.G = tg[p];
-              if (multi) {
-                d.xch = xchb.as<double>() + xch_off[p];
-                d.cnt = cntb.as<int32_t>() + size_t(multi_idx++) * CNT_PAD;
-              }
+              if (multi) d.xch = xchb.as<double>() + xch_off[p];
               d.seg_begin = int32_t(segs.size());
               for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e) {
                 const int32_t q = sy.nb[e];

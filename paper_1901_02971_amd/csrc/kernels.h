@@ -76,8 +76,8 @@ struct SparsDesc {
   double* V;       // m x min(m, ncols_max) reflectors, column-major, ld m
   double* tau;     // min(m, ncols_max)
   double* diag;    // diagonal block of p (ld ldd), set to I_r on exit
-  double* xch;     // slab exchange (S > 1): 3 buffers x S records of cpqr_record(G) doubles
-  int32_t* cnt;    // barrier counter of the slabs (S > 1, zeroed before the launch)
+  double* xch;     // slab exchange (S > 1): 3 buffers x S records of cpqr_record(G) doubles, zeroed
+                   // before the launch
   int32_t m, ldd, seg_begin, seg_end, id, S, G, pad;  // G: lanes per column (team size)
 };
 struct SegDesc {

@@ -13,19 +13,20 @@
 //   1. every column knows the exact norm of its rows j..m-1 (recomputed from the
 //      updated entries at the end of the previous step, never downdated);
 //   2. pivot = among the remaining columns whose norm is within a relative 1e-10 of
-//      the largest, the smallest column index.  One fused reduction carries
-//      (largest norm, smallest index within the window of that partial maximum,
-//      its norm) through the lanes, the waves and, for S > 1, the slabs; when a
-//      partial maximum grows past a side's own window the exact index is found in
-//      a second round.  Stop when |R_jj| < eps |R_00|;
-//   3. the team owning the pivot column publishes its rows j..m-1 (LDS for S = 1,
-//      the slab exchange buffer for S > 1, one slab barrier per step) and every
-//      lane forms the reflector (LAPACK dlarfg convention) from it with identical
+//      the largest, the smallest column index.  A workgroup finds its largest norm,
+//      then its smallest index inside that window (two exact reductions); for
+//      S > 1 the slabs exchange (largest norm, candidate, its norm) and combine
+//      them like the lanes, and when a slab's largest norm lies inside the window
+//      of a larger one without its candidate, a second exchange finds the exact
+//      index.  Stop when |R_jj| < eps |R_00|;
+//   3. the team owning the pivot column publishes its rows (LDS for S = 1, the
+//      slab's exchange record for S > 1, one exchange per step) and every thread
+//      forms its rows of the reflector (LAPACK dlarfg convention) with identical
 //      arithmetic;
 //   4. every remaining column is updated in registers, a <- a - tau v (v^T a), and
 //      its new trailing norm formed (team sums by lane shuffles).
-// Columns are never moved: a column pivoted at step j keeps R_0j..R_jj in its rows
-// 0..j.  At the end every slab writes W_cn = R[:r, :] P^T straight into the blocks of
+// Columns are never moved: a column pivoted at step j keeps R_0j..R_j-1,j in its
+// rows 0..j-1 and R_jj is set at the end.  At the end every slab writes W_cn = R[:r, :] P^T straight into the blocks of
 // p, and slab 0 stores the reflectors, sets A_cc = I and publishes the rank.
 #include <hip/hip_runtime.h>
 
@@ -135,30 +136,23 @@ __device__ inline double first_lane(double v) {
                           __builtin_amdgcn_readfirstlane(__double2loint(v)));
 }
 
-// Barrier among the S workgroups of one interface: a monotone counter; barrier
-// number b completes when the counter reaches b*S.  Everything the slabs exchange
-// is written and read with agent-scope atomic accesses, which are coherent across
-// the L2 caches of the XCDs; each wave waits for its own stores to complete before
-// the counter is raised, so no L2 writeback or invalidation is needed.  Bounded
-// spin: on time-out the error flag is raised and the workgroup continues, so every
-// wave terminates.
-__device__ inline void slab_barrier(int32_t* cnt, int32_t target, int32_t* err) {
-  __builtin_amdgcn_s_waitcnt(0);  // this wave's exchange stores have completed
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    long spins = 0;
-    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins > SPIN_LIMIT) {
-        atomicOr(err, 4);
-        break;
-      }
-      // after any time-out every later barrier falls through at once
-      if ((spins & 1023) == 0 && (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 4)) break;
-    }
-  }
-  __syncthreads();
+// Exchange among the S workgroups of one interface.  Every exchanged value is
+// written and read with agent-scope atomic accesses, which are coherent across the
+// L2 caches of the XCDs.  A slab stores the rows of its record first; once each of
+// its waves has seen its own stores complete, one thread stores the header words.
+// Every header word carries the exchange's tag in its sign bit (the values are
+// >= 0), so a reader that finds the current tag in all words of a header holds that
+// slab's header and may read its rows.  A record buffer is reused every other
+// exchange and the tag alternates between its uses; the buffers start zeroed and
+// the first tag is 1.  Polls are bounded: on time-out the error flag is raised and
+// the workgroup goes on with what it read, so every wave terminates.
+__device__ inline double tag_word(double v, int tag) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v) & 0x7FFFFFFFFFFFFFFFull;
+  return __longlong_as_double((long long)(b | ((unsigned long long)tag << 63)));
+}
+__device__ inline int word_tag(double x) { return (int)((unsigned long long)__double_as_longlong(x) >> 63); }
+__device__ inline double word_val(double x) {
+  return __longlong_as_double((long long)((unsigned long long)__double_as_longlong(x) & 0x7FFFFFFFFFFFFFFFull));
 }
 
 __device__ inline double shared_load(const double* p) {
@@ -166,6 +160,10 @@ __device__ inline double shared_load(const double* p) {
 }
 __device__ inline void shared_store(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// the error flag of the launch, read by a poll so that it stops after a time-out
+__device__ inline bool timed_out(int32_t* err) {
+  return (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 4) != 0;
 }
 
 // Address of column c of A_pn: entry i at base[i * stride].
@@ -200,6 +198,8 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
   __shared__ double pmx[2][NW];
   __shared__ int pcd[2][NW];
   __shared__ double sh_pn, sh_x2;
+  __shared__ double xg_mx;  // result of the header reduction of the current exchange
+  __shared__ int xg_cd, xg_amb;
   const int m = d.m, S = MULTI ? d.S : 1, w = MULTI ? wslab : 0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane & (G - 1), team = tid / G;
@@ -259,7 +259,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
   const int uend = (m + 4 * G - 1) / (4 * G);  // groups holding rows below m
   int r = kmax;
   double r00 = 0.0;
-  int bar = 0;
+  int namb = 0;  // second exchange rounds so far (identical in all slabs)
   for (int j = 0; j < kmax; ++j) {
     const int jg = j - g;  // row q * G + g of this lane lies below row j iff q * G > jg
     // ---- pivot of this slab: the largest remaining norm M, then the smallest column
@@ -334,8 +334,10 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
       x2 = sh_x2;
       alpha = cv[j];
     } else {
-      // publish (slab max, slab candidate, its norm, its rows); one barrier.  The
-      // rows of a record are stored lane-major: row q * G + g at g * CQ_MR + q.
+      // publish (slab max, slab candidate + 1, its norm, its rows and its squared
+      // norm below j).  The rows of a record are stored lane-major: row q * G + g
+      // at g * CQ_MR + q.
+      const int tg = ((j >> 1) & 1) ^ 1;
       {
         double* rw = xrec(j & 1, w);
         if (own) {
@@ -357,52 +359,75 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
               }
               s2 = team_sum<G>(s2);
               if (g == 0) {
-                shared_store(rw + 1, nv[k]);
                 shared_store(rw + 2, s2);
+                sh_pn = nv[k];
               }
             }
         }
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's record stores have completed
+        __syncthreads();
         if (tid == 0) {
-          shared_store(rw, smx);
-          shared_store(rw + 3, (scd == INT_MAX) ? -1.0 : (double)scd);
-          if (scd == INT_MAX) shared_store(rw + 1, -1.0);
+          const bool none = scd == INT_MAX;
+          shared_store(rw, tag_word(none ? 0.0 : smx, tg));
+          shared_store(rw + 1, tag_word(none ? 0.0 : sh_pn, tg));
+          shared_store(rw + 3, tag_word(none ? 0.0 : (double)scd + 1.0, tg));
         }
       }
       int xb = j & 1;
-      slab_barrier(d.cnt, ++bar * S, err);
-      // every wave reads the S records (one memory round trip) and reduces them
-      // itself; lanes 0..P-1 end with the same result.  The owning slab of column c
-      // is c / CAP.
-      int P = 1;
-      while (P < S && P < 64) P <<= 1;
-      Cand u;
-      u.mx = -1.0;
-      u.cn = -1.0;
-      u.cd = INT_MAX;
-      u.amb = 0;
-      for (int q = lane; q < S; q += 64) {  // S may exceed the wave size
-        const double* rq = xrec(xb, q);
-        const double mx = shared_load(rq), cn = shared_load(rq + 1), cq = shared_load(rq + 3);
-        Cand v;
-        v.mx = mx;
-        v.cn = (cq >= 0.0) ? cn : -1.0;
-        v.cd = (cq >= 0.0) ? (int)cq : INT_MAX;
-        v.amb = 0;
-        u = cand_combine(u, v);
+      // wave 0 polls the S headers (one memory round trip per poll) and reduces them
+      // like the lanes: lanes 0..P-1 end with the same result.  The owning slab of
+      // column c is c / CAP.
+      if (wave == 0) {
+        int P = 1;
+        while (P < S && P < 64) P <<= 1;
+        Cand u;
+        for (long spins = 0;; ++spins) {
+          u.mx = -1.0;
+          u.cn = -1.0;
+          u.cd = INT_MAX;
+          u.amb = 0;
+          int ok = 1;
+          for (int q = lane; q < S; q += 64) {  // S may exceed the wave size
+            const double* rq = xrec(xb, q);
+            const double w0 = shared_load(rq), w1 = shared_load(rq + 1), w3 = shared_load(rq + 3);
+            ok &= (word_tag(w0) == tg) & (word_tag(w1) == tg) & (word_tag(w3) == tg);
+            const double cq = word_val(w3);
+            Cand v;
+            v.mx = (cq > 0.0) ? word_val(w0) : -1.0;
+            v.cn = (cq > 0.0) ? word_val(w1) : -1.0;
+            v.cd = (cq > 0.0) ? (int)cq - 1 : INT_MAX;
+            v.amb = 0;
+            u = cand_combine(u, v);
+          }
+          if (__all(ok)) break;
+          if (spins > SPIN_LIMIT) {
+            if (lane == 0) atomicOr(err, 4);
+            break;
+          }
+          if ((spins & 1023) == 1023 && timed_out(err)) break;  // after a time-out the polls give up at once
+          __builtin_amdgcn_s_sleep(1);
+        }
+        for (int o = 1; o < P; o <<= 1) {
+          Cand v;
+          v.mx = __shfl_xor(u.mx, o, 64);
+          v.cn = __shfl_xor(u.cn, o, 64);
+          v.cd = __shfl_xor(u.cd, o, 64);
+          v.amb = __shfl_xor(u.amb, o, 64);
+          u = cand_combine(u, v);
+        }
+        if (lane == 0) {
+          xg_mx = u.mx;
+          xg_cd = u.cd;
+          xg_amb = u.amb;
+        }
       }
-      for (int o = 1; o < P; o <<= 1) {
-        Cand v;
-        v.mx = __shfl_xor(u.mx, o, 64);
-        v.cn = __shfl_xor(u.cn, o, 64);
-        v.cd = __shfl_xor(u.cd, o, 64);
-        v.amb = __shfl_xor(u.amb, o, 64);
-        u = cand_combine(u, v);
-      }
-      const double gmx = first_lane(u.mx);
-      piv = __builtin_amdgcn_readfirstlane(u.cd);
-      if (__builtin_amdgcn_readfirstlane(u.amb)) {  // second round with the exact global threshold
+      __syncthreads();
+      piv = xg_cd;
+      if (xg_amb) {  // second round with the exact global threshold (near-ties across slabs)
         xb = 2;
-        const double thr = gmx * (1.0 - TIE_RTOL);
+        const int tg2 = (namb & 1) ^ 1;
+        ++namb;
+        const double thr = xg_mx * (1.0 - TIE_RTOL);
         int c2 = INT_MAX;
 #pragma unroll
         for (int k = 0; k < CQ_CPL; ++k)
@@ -429,26 +454,50 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
               }
               s2 = team_sum<G>(s2);
               if (g == 0) {
-                shared_store(rw + 1, nv[k]);
                 shared_store(rw + 2, s2);
+                sh_pn = nv[k];
               }
             }
         }
-        if (tid == 0) shared_store(rw + 3, (best == INT_MAX) ? -1.0 : (double)best);
-        slab_barrier(d.cnt, ++bar * S, err);
-        int b2 = INT_MAX;
-        for (int q = lane; q < S; q += 64) {
-          const double cq = shared_load(xrec(2, q) + 3);
-          if (cq >= 0.0) b2 = min(b2, (int)cq);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (tid == 0) {
+          const bool none = best == INT_MAX;
+          shared_store(rw + 1, tag_word(none ? 0.0 : sh_pn, tg2));
+          shared_store(rw + 3, tag_word(none ? 0.0 : (double)best + 1.0, tg2));
         }
-        piv = wave_min(b2);
+        if (wave == 0) {
+          int b2;
+          for (long spins = 0;; ++spins) {
+            b2 = INT_MAX;
+            int ok = 1;
+            for (int q = lane; q < S; q += 64) {
+              const double* rq = xrec(2, q);
+              const double w1 = shared_load(rq + 1), w3 = shared_load(rq + 3);
+              ok &= (word_tag(w1) == tg2) & (word_tag(w3) == tg2);
+              const double cq = word_val(w3);
+              if (cq > 0.0) b2 = min(b2, (int)cq - 1);
+            }
+            if (__all(ok)) break;
+            if (spins > SPIN_LIMIT) {
+              if (lane == 0) atomicOr(err, 4);
+              break;
+            }
+            if ((spins & 1023) == 1023 && timed_out(err)) break;
+            __builtin_amdgcn_s_sleep(1);
+          }
+          b2 = wave_min(b2);
+          if (lane == 0) xg_cd = b2;
+        }
+        __syncthreads();
+        piv = xg_cd;
       }
       if (piv == INT_MAX) {  // only non-finite norms left
         r = j;
         break;
       }
       rc = xrec(xb, piv / CAP);
-      pn = shared_load(rc + 1);
+      pn = word_val(shared_load(rc + 1));
       x2 = shared_load(rc + 2);
       alpha = shared_load(rc + 4 + (j % G) * CQ_MR + j / G);
     }
