@@ -40,6 +40,7 @@ namespace spand {
 #define CQ_NT 512
 #define CQ_MR 32
 #define CQ_CPL 2
+#define CQ_XH 16  // doubles of an exchange record's header: a 128-byte line of its own
 #define CW 256  // threads of k_build_t
 #define TIE_RTOL 1e-10
 #define SPIN_LIMIT (1L << 22)
@@ -183,6 +184,47 @@ __device__ inline void column_ptr(const SegDesc* sg, const int* segoff, int c, d
 
 }  // namespace
 
+// Row group gi of the update loops: register rows 4 gi .. 4 gi + 3 of every
+// column, i.e. rows [4 gi G, 4 gi G + 4 G) of A_pn across the team.
+template <int G>
+__device__ __forceinline__ void cpqr_load_group(const double* vl, int gi, double (&v)[4]) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) v[u] = vl[(4 * gi + u) * G];
+}
+__device__ __forceinline__ void cpqr_dot_group(const double (&a)[CQ_CPL][CQ_MR], int gi, const double (&v)[4],
+                                               double (&dot)[CQ_CPL]) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int k = 0; k < CQ_CPL; ++k) dot[k] = fma(v[u], a[k][4 * gi + u], dot[k]);
+}
+// a <- a - w v and the squared norm of the rows below j (jg = j - g); only the
+// group holding row j (mixed) has rows on both sides of it.
+template <int G>
+__device__ __forceinline__ void cpqr_update_group(double (&a)[CQ_CPL][CQ_MR], int gi, const double (&v)[4],
+                                                  const double (&wv)[CQ_CPL], double (&sq)[CQ_CPL], bool mixed,
+                                                  int jg) {
+  if (mixed) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < CQ_CPL; ++k) {
+        const double x = fma(-wv[k], v[u], a[k][4 * gi + u]);
+        a[k][4 * gi + u] = x;
+        sq[k] = ((4 * gi + u) * G > jg) ? fma(x, x, sq[k]) : sq[k];
+      }
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < CQ_CPL; ++k) {
+        const double x = fma(-wv[k], v[u], a[k][4 * gi + u]);
+        a[k][4 * gi + u] = x;
+        sq[k] = fma(x, x, sq[k]);
+      }
+  }
+}
+
 // Slab w of interface d (w = 0, S = 1 when MULTI is false).
 template <int G, bool MULTI>
 __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const SegDesc* __restrict__ segs, double eps,
@@ -212,8 +254,9 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
   double* cv = lds + ROWS;
   double* rb = lds + 2 * ROWS;
   int* segoff = reinterpret_cast<int*>(lds + 3 * ROWS);  // nseg + 1
-  // exchange record of slab q in buffer b: [max, cand norm, cand xn2, cand index, ROWS column rows]
-  auto xrec = [&](int b, int q) { return d.xch + ((size_t)b * S + q) * (size_t)(ROWS + 4); };
+  // exchange record of slab q in buffer b: header [max, cand norm, cand xn2, cand index + 1,
+  // unused up to CQ_XH], then ROWS column rows
+  auto xrec = [&](int b, int q) { return d.xch + ((size_t)b * S + q) * (size_t)(ROWS + CQ_XH); };
 
   // column layout of A_pn from the neighbours' current sizes
   if (tid == 0) {
@@ -344,7 +387,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
 #pragma unroll
           for (int k = 0; k < CQ_CPL; ++k)
             if (k == pk) {
-              double* rl = rw + 4 + g * CQ_MR;
+              double* rl = rw + CQ_XH + g * CQ_MR;
               double s2 = 0.0;
 #pragma unroll
               for (int gi = 0; gi < NGRP; ++gi) {
@@ -360,17 +403,21 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
               s2 = team_sum<G>(s2);
               if (g == 0) {
                 shared_store(rw + 2, s2);
-                sh_pn = nv[k];
+                // the team lies in one wave: once this wave's stores have completed
+                // the rows are visible, and the header may follow
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                __builtin_amdgcn_s_waitcnt(0);
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                shared_store(rw, tag_word(smx, tg));
+                shared_store(rw + 1, tag_word(nv[k], tg));
+                shared_store(rw + 3, tag_word((double)scd + 1.0, tg));
               }
             }
         }
-        __builtin_amdgcn_s_waitcnt(0);  // this wave's record stores have completed
-        __syncthreads();
-        if (tid == 0) {
-          const bool none = scd == INT_MAX;
-          shared_store(rw, tag_word(none ? 0.0 : smx, tg));
-          shared_store(rw + 1, tag_word(none ? 0.0 : sh_pn, tg));
-          shared_store(rw + 3, tag_word(none ? 0.0 : (double)scd + 1.0, tg));
+        if (scd == INT_MAX && tid == 0) {  // no candidate left in this slab
+          shared_store(rw, tag_word(0.0, tg));
+          shared_store(rw + 1, tag_word(0.0, tg));
+          shared_store(rw + 3, tag_word(0.0, tg));
         }
       }
       int xb = j & 1;
@@ -445,7 +492,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
 #pragma unroll
           for (int k = 0; k < CQ_CPL; ++k)
             if (k == pk2) {
-              double* rl = rw + 4 + g * CQ_MR;
+              double* rl = rw + CQ_XH + g * CQ_MR;
               double s2 = 0.0;
 #pragma unroll
               for (int q = 0; q < CQ_MR; ++q) {
@@ -499,7 +546,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
       rc = xrec(xb, piv / CAP);
       pn = word_val(shared_load(rc + 1));
       x2 = shared_load(rc + 2);
-      alpha = shared_load(rc + 4 + (j % G) * CQ_MR + j / G);
+      alpha = shared_load(rc + CQ_XH + (j % G) * CQ_MR + j / G);
     }
     if (j == 0) {
       r00 = pn;
@@ -526,7 +573,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
       for (int u = 0; u < RPT; ++u) {
         const int i = tid + u * NT;
         if constexpr (MULTI)
-          xs[u] = (i > j && i < m) ? shared_load(rc + 4 + (i % G) * CQ_MR + i / G) : 0.0;
+          xs[u] = (i > j && i < m) ? shared_load(rc + CQ_XH + (i % G) * CQ_MR + i / G) : 0.0;
         else
           xs[u] = (i < ROWS) ? cv[i] : 0.0;
       }
@@ -559,31 +606,28 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
     // with rows on both sides of it.
     const int uj = j / (4 * G);
     const double* vl = vv + g;
+    // v of a group is read one group ahead into two register sets used by even
+    // and odd groups in turn, so the reads overlap the previous group's FMAs
+    double va[4], vb[4];
     double dot[CQ_CPL];
 #pragma unroll
     for (int k = 0; k < CQ_CPL; ++k) dot[k] = 0.0;
-    {
-      double cur[4], nxt[4];
+    if (uj & 1) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) cur[u] = nxt[u] = 0.0;
+      for (int u = 0; u < 4; ++u) vb[u] = vl[(4 * uj + u) * G];
+    } else {
 #pragma unroll
-      for (int gi = 0; gi < NGRP; ++gi) {
-        if (gi >= uj && gi < uend) {
-          if (gi == uj) {
+      for (int u = 0; u < 4; ++u) va[u] = vl[(4 * uj + u) * G];
+    }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) cur[u] = vl[(4 * gi + u) * G];
-          }
-          if (gi + 1 < NGRP && gi + 1 < uend) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) nxt[u] = vl[(4 * gi + 4 + u) * G];
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int k = 0; k < CQ_CPL; ++k) dot[k] = fma(cur[u], a[k][4 * gi + u], dot[k]);
-#pragma unroll
-          for (int u = 0; u < 4; ++u) cur[u] = nxt[u];
-        }
+    for (int gp = 0; gp < NGRP; gp += 2) {
+      if (gp >= uj && gp < uend) {
+        cpqr_load_group<G>(vl, gp + 1, vb);  // unconditional: a fixed count of LDS reads in flight
+        cpqr_dot_group(a, gp, va, dot);
+      }
+      if (gp + 1 >= uj && gp + 1 < uend) {
+        if (gp + 2 < NGRP) cpqr_load_group<G>(vl, gp + 2, va);
+        cpqr_dot_group(a, gp + 1, vb, dot);
       }
     }
     double wv[CQ_CPL], sq[CQ_CPL];
@@ -593,43 +637,22 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
       wv[k] = (pst[k] == -1) ? tau * dot[k] : 0.0;
       sq[k] = 0.0;
     }
-    {
-      double cur[4], nxt[4];
+    if (uj & 1) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) cur[u] = nxt[u] = 0.0;
+      for (int u = 0; u < 4; ++u) vb[u] = vl[(4 * uj + u) * G];
+    } else {
 #pragma unroll
-      for (int gi = 0; gi < NGRP; ++gi) {
-        if (gi >= uj && gi < uend) {
-          if (gi == uj) {
+      for (int u = 0; u < 4; ++u) va[u] = vl[(4 * uj + u) * G];
+    }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) cur[u] = vl[(4 * gi + u) * G];
-          }
-          if (gi + 1 < NGRP && gi + 1 < uend) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) nxt[u] = vl[(4 * gi + 4 + u) * G];
-          }
-          if (gi == uj) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-              for (int k = 0; k < CQ_CPL; ++k) {
-                const double x = fma(-wv[k], cur[u], a[k][4 * gi + u]);
-                a[k][4 * gi + u] = x;
-                sq[k] = ((4 * gi + u) * G > jg) ? fma(x, x, sq[k]) : sq[k];
-              }
-          } else {
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-              for (int k = 0; k < CQ_CPL; ++k) {
-                const double x = fma(-wv[k], cur[u], a[k][4 * gi + u]);
-                a[k][4 * gi + u] = x;
-                sq[k] = fma(x, x, sq[k]);
-              }
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u) cur[u] = nxt[u];
-        }
+    for (int gp = 0; gp < NGRP; gp += 2) {
+      if (gp >= uj && gp < uend) {
+        cpqr_load_group<G>(vl, gp + 1, vb);  // unconditional: a fixed count of LDS reads in flight
+        cpqr_update_group<G>(a, gp, va, wv, sq, gp == uj, jg);
+      }
+      if (gp + 1 >= uj && gp + 1 < uend) {
+        if (gp + 2 < NGRP) cpqr_load_group<G>(vl, gp + 2, va);
+        cpqr_update_group<G>(a, gp + 1, vb, wv, sq, gp + 1 == uj, jg);
       }
     }
 #pragma unroll
@@ -750,7 +773,7 @@ size_t cpqr_lds_bytes(int32_t G, int32_t nseg) {
   return 3 * size_t(G) * CQ_MR * sizeof(double) + (size_t(nseg) + 1) * sizeof(int32_t) + 16;
 }
 
-int32_t cpqr_record(int32_t G) { return G * CQ_MR + 4; }
+int32_t cpqr_record(int32_t G) { return G * CQ_MR + CQ_XH; }
 
 int cpqr_max_coresident(size_t lds) {
   int per_cu = 0;
