@@ -4,7 +4,11 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstddef>
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "apply.h"
@@ -13,23 +17,145 @@
 
 namespace spand {
 
-// Owning device allocation.
+// Device blocks of one handle, recycled instead of returned to the driver (whose
+// free synchronizes the device).  A released block goes back to the free list; a
+// later request takes the smallest free block that holds it if that block is at
+// most twice its size, else a new block is allocated.  All work of a handle runs on
+// its stream and every call synchronizes that stream before it returns, so a block
+// reused inside a call is ordered after its last use on the stream, and one reused
+// in a later call is idle.
+struct DevPool {
+  std::multimap<size_t, void*> free_blocks;  // capacity -> block
+  std::vector<void*> owned;
+  DevPool() = default;
+  DevPool(const DevPool&) = delete;
+  DevPool& operator=(const DevPool&) = delete;
+  ~DevPool() {
+    for (void* p : owned) (void)hipFree(p);
+  }
+  static size_t round(size_t bytes) {
+    const size_t q = bytes >= (size_t(1) << 24) ? (size_t(1) << 21) : 4096;
+    return (bytes + q - 1) / q * q;
+  }
+  hipError_t get(size_t bytes, void** p, size_t* cap) {
+    auto it = free_blocks.lower_bound(bytes);
+    if (it != free_blocks.end() && it->first <= 2 * bytes + 65536) {
+      *p = it->second;
+      *cap = it->first;
+      free_blocks.erase(it);
+      return hipSuccess;
+    }
+    const size_t c = round(bytes);
+    hipError_t e = hipMalloc(p, c);
+    if (e != hipSuccess && !free_blocks.empty()) {  // give the cached blocks back and retry
+      (void)hipGetLastError();
+      (void)hipDeviceSynchronize();
+      for (auto& fb : free_blocks) {
+        (void)hipFree(fb.second);
+        for (auto& o : owned)
+          if (o == fb.second) o = nullptr;
+      }
+      free_blocks.clear();
+      std::vector<void*> keep;
+      for (void* o : owned)
+        if (o) keep.push_back(o);
+      owned.swap(keep);
+      e = hipMalloc(p, c);
+    }
+    if (e != hipSuccess) return e;
+    owned.push_back(*p);
+    *cap = c;
+    return hipSuccess;
+  }
+  void put(void* p, size_t cap) { free_blocks.emplace(cap, p); }
+};
+
+// Pinned host staging for the descriptor uploads of one call: bump allocation,
+// reset at the start of the next call (the previous call's copies have completed
+// by then).  A call that outgrows the current chunk adds one; the next reset
+// replaces the chunks by one of their total size.
+struct HostStage {
+  std::vector<std::pair<char*, size_t>> chunks;
+  size_t cur = 0, used = 0;
+  HostStage() = default;
+  HostStage(const HostStage&) = delete;
+  HostStage& operator=(const HostStage&) = delete;
+  ~HostStage() {
+    for (auto& c : chunks) (void)hipHostFree(c.first);
+  }
+  void reset() {
+    if (chunks.size() > 1) {
+      size_t total = 0;
+      for (auto& c : chunks) {
+        total += c.second;
+        (void)hipHostFree(c.first);
+      }
+      chunks.clear();
+      void* p = nullptr;
+      if (hipHostMalloc(&p, total, hipHostMallocDefault) == hipSuccess) chunks.emplace_back(static_cast<char*>(p), total);
+    }
+    cur = 0;
+    used = 0;
+  }
+  char* get(size_t bytes) {
+    bytes = (bytes + 255) / 256 * 256;
+    while (cur < chunks.size() && used + bytes > chunks[cur].second) {
+      ++cur;
+      used = 0;
+    }
+    if (cur == chunks.size()) {
+      size_t sz = std::max<size_t>(bytes, size_t(4) << 20);
+      if (!chunks.empty()) sz = std::max(sz, 2 * chunks.back().second);
+      void* p = nullptr;
+      if (hipHostMalloc(&p, sz, hipHostMallocDefault) != hipSuccess) return nullptr;
+      chunks.emplace_back(static_cast<char*>(p), sz);
+      used = 0;
+    }
+    char* r = chunks[cur].first + used;
+    used += bytes;
+    return r;
+  }
+};
+
+// Owning device allocation (from a handle's DevPool, or from the driver when pool
+// is null).
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  size_t cap = 0;
+  DevPool* pool = nullptr;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), cap(o.cap), pool(o.pool) {
+    o.p = nullptr;
+    o.bytes = o.cap = 0;
+    o.pool = nullptr;
+  }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    if (this != &o) {
+      release();
+      p = o.p;
+      bytes = o.bytes;
+      cap = o.cap;
+      pool = o.pool;
+      o.p = nullptr;
+      o.bytes = o.cap = 0;
+      o.pool = nullptr;
+    }
     return *this;
   }
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (pool)
+        pool->put(p, cap);
+      else
+        (void)hipFree(p);
+    }
     p = nullptr;
-    bytes = 0;
+    bytes = cap = 0;
+    pool = nullptr;
   }
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
@@ -91,6 +217,9 @@ struct spand_ctx {
   spand_stats stats{};
   bool factored = false;
   int device = -1;
+  // declared before every DevBuf of the handle, so destroyed after them
+  spand::DevPool pool;
+  spand::HostStage stage;
   std::vector<spand::StepNum> num;
   spand::DevBuf d_rowptr, d_colind, d_values;  // CSR of A for the SpMV
   spand::DevBuf d_dst1;                         // step-1 destination of every CSR entry (pattern-only)

@@ -41,13 +41,28 @@ namespace {
 spand_status dalloc(spand_ctx* h, DevBuf& b, size_t bytes) {
   b.release();
   if (bytes == 0) return SPAND_OK;
-  hipError_t e = hipMalloc(&b.p, bytes);
+  void* p = nullptr;
+  size_t cap = 0;
+  hipError_t e = h->pool.get(bytes, &p, &cap);
   if (e != hipSuccess) {
-    b.p = nullptr;
     (void)hipGetLastError();
     return set_err(h, SPAND_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
   }
+  b.p = p;
   b.bytes = bytes;
+  b.cap = cap;
+  b.pool = &h->pool;
+  return SPAND_OK;
+}
+
+// Host-to-device copy through the call's pinned staging (asynchronous on the
+// handle's stream).
+spand_status stage_copy(spand_ctx* h, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return SPAND_OK;
+  char* hp = h->stage.get(bytes);
+  if (!hp) return set_err(h, SPAND_E_NOMEM, "pinned staging of " + std::to_string(bytes) + " bytes failed");
+  std::memcpy(hp, src, bytes);
+  HIPCHK(hipMemcpyAsync(dst, hp, bytes, hipMemcpyHostToDevice, h->stream));
   return SPAND_OK;
 }
 
@@ -55,8 +70,7 @@ template <typename T>
 spand_status upload(spand_ctx* h, DevBuf& b, const std::vector<T>& v) {
   spand_status st = dalloc(h, b, v.size() * sizeof(T));
   if (st != SPAND_OK) return st;
-  if (!v.empty()) HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
-  return SPAND_OK;
+  return stage_copy(h, b.p, v.data(), v.size() * sizeof(T));
 }
 
 // Column-panel layout of one step.  Panels of eliminated clusters (j < ne) are
@@ -217,8 +231,8 @@ spand_status blocked_cholesky(spand_ctx* h, const std::vector<Front>& F, int32_t
     g.launch(h, 2 * q + 1);
   }
   HIPCHK(hipGetLastError());
-  // descriptors must outlive the launches
-  HIPCHK(hipStreamSynchronize(h->stream));
+  // the descriptor blocks go back to the handle's pool; a later allocation that
+  // reuses them is ordered after these launches on the stream
   return SPAND_OK;
 }
 
@@ -265,16 +279,156 @@ spand_status left_trsm(spand_ctx* h, const std::vector<LeftBlock>& B) {
     g.launch(h, q);
   }
   HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(h->stream));
   return SPAND_OK;
 }
 
 }  // namespace
 
+// Apply descriptors of step t (its eliminations, target updates, scalings and
+// Householder products), built from the step's stored sizes, slots and factor
+// offsets.  The factorization calls this while the next step's kernels run.
+struct ApplyPlan {
+  int32_t t = 0;
+  std::vector<int64_t> ed_off, sc_off, v_off, t_off;
+  std::vector<int32_t> nN, nref;
+};
+
+spand_status build_apply(spand_ctx* h, const SymStep& sy, StepNum& sn, const Layout& lay, const ApplyPlan& pl) {
+  const int32_t nc = sy.nc, ne = sy.ne;
+  const double* E = sn.elim.as<double>();
+  const std::vector<int64_t>& ed_off = pl.ed_off;
+  const std::vector<int64_t>& sc_off = pl.sc_off;
+  const std::vector<int64_t>& v_off = pl.v_off;
+  const std::vector<int64_t>& t_off = pl.t_off;
+  const std::vector<int32_t>& nN = pl.nN;
+  const std::vector<int32_t>& nref = pl.nref;
+  spand_status st;
+  std::vector<int32_t> nslot;
+  int64_t tmp = 0;
+  sn.h_elim.clear();
+  for (int32_t s = 0; s < ne; ++s) {
+    ElimAp e{};
+    e.L = E + lay.base[s];
+    e.G = E + lay.base[s] + sn.size[s];
+    e.Dinv = sn.edinv.as<double>() + ed_off[s];
+    e.ld = int32_t(lay.H[s]);
+    e.ns = sn.size[s];
+    e.nN = nN[s];
+    e.slot_s = sn.slot_ptr[s];
+    e.slot_N = int64_t(nslot.size());
+    for (int64_t q = sy.enb_ptr[s]; q < sy.enb_ptr[s + 1]; ++q) {
+      const int32_t nb = sy.enb[q];
+      nslot.insert(nslot.end(), sn.slot.begin() + sn.slot_ptr[nb], sn.slot.begin() + sn.slot_ptr[nb + 1]);
+    }
+    e.tmp = tmp;
+    tmp += std::max(e.ns, 1);
+    sn.h_elim.push_back(e);
+  }
+  sn.tmp_elim = tmp;
+  sn.h_etile.clear();
+  for (int32_t s = 0; s < ne; ++s)
+    for (int32_t k0 = 0; k0 < sn.h_elim[s].ns; k0 += 64) sn.h_etile.push_back(ElimTile{s, k0});
+  // forward target updates, grouped by receiving cluster in ascending s
+  struct TI { int32_t n, s; int64_t row; };
+  std::vector<TI> tis;
+  for (int32_t s = 0; s < ne; ++s) {
+    int64_t row = 0;
+    for (int64_t q = sy.enb_ptr[s]; q < sy.enb_ptr[s + 1]; ++q) {
+      const int32_t nb = sy.enb[q];
+      if (sn.size[nb] > 0 && sn.size[s] > 0) tis.push_back(TI{nb, s, row});
+      row += sn.size[nb];
+    }
+  }
+  std::stable_sort(tis.begin(), tis.end(), [](const TI& x, const TI& y) { return x.n < y.n; });
+  sn.h_target.clear();
+  sn.h_contrib.clear();
+  for (size_t q = 0; q < tis.size();) {
+    size_t r = q;
+    TargetAp ta{};
+    ta.nn = sn.size[tis[q].n];
+    ta.slot_n = sn.slot_ptr[tis[q].n];
+    ta.cbeg = int32_t(sn.h_contrib.size());
+    while (r < tis.size() && tis[r].n == tis[q].n) {
+      const int32_t s = tis[r].s;
+      sn.h_contrib.push_back(TargetContrib{sn.h_elim[s].G + tis[r].row, sn.h_elim[s].ld, sn.size[s], sn.h_elim[s].tmp});
+      ++r;
+    }
+    ta.cend = int32_t(sn.h_contrib.size());
+    for (int32_t r0 = 0; r0 < ta.nn; r0 += 64) {  // one workgroup per 64-row tile
+      ta.r0 = r0;
+      sn.h_target.push_back(ta);
+    }
+    q = r;
+  }
+  sn.h_scale.clear();
+  sn.h_stile.clear();
+  sn.h_sgather.clear();
+  sn.h_house.clear();
+  sn.h_hr.clear();
+  sn.h_hv.clear();
+  int64_t tmp2 = 0, tmp3 = 0;
+  for (int32_t p = ne; p < nc; ++p) {
+    if (sc_off[p] >= 0) {
+      ScaleAp a{};
+      a.Linv = sn.scale.as<double>() + sc_off[p];
+      a.np = sn.size[p];
+      a.slot_p = sn.slot_ptr[p];
+      a.tmp = tmp2;
+      tmp2 += sn.size[p];
+      const int32_t sid = int32_t(sn.h_scale.size());
+      for (int32_t r0 = 0; r0 < a.np; r0 += 64) sn.h_stile.push_back(ScaleTile{sid, r0});
+      sn.h_sgather.insert(sn.h_sgather.end(), sn.slot.begin() + sn.slot_ptr[p],
+                          sn.slot.begin() + sn.slot_ptr[p] + sn.size[p]);
+      sn.h_scale.push_back(a);
+    }
+    if (v_off[p] >= 0 && nref[p] > 0) {
+      HouseAp hp{};
+      hp.V = sn.house.as<double>() + v_off[p];
+      hp.T = sn.house.as<double>() + t_off[p];
+      hp.np = sn.size[p];
+      hp.r = nref[p];
+      hp.slot_p = sn.slot_ptr[p];
+      hp.tmp = tmp3;
+      tmp3 += 2 * int64_t(nref[p]);
+      const int32_t hid = int32_t(sn.h_house.size());
+      for (int32_t j0 = 0; j0 < hp.r; j0 += 64) sn.h_hr.push_back(HouseTile{hid, j0});
+      for (int32_t r0 = 0; r0 < hp.np; r0 += 64) sn.h_hv.push_back(HouseTile{hid, r0});
+      sn.h_house.push_back(hp);
+    }
+  }
+  sn.tmp_scale = std::max(tmp2, tmp3);
+  sn.nslot_len = int64_t(nslot.size());
+  h->max_tmp = std::max(h->max_tmp, std::max(sn.tmp_elim, sn.tmp_scale));
+  h->max_gather = std::max(h->max_gather, sn.nslot_len);
+  sn.n_elim_ap = int32_t(sn.h_elim.size());
+  sn.n_target = int32_t(sn.h_target.size());
+  sn.n_scale = int32_t(sn.h_scale.size());
+  sn.n_house = int32_t(sn.h_house.size());
+  sn.n_etile = int32_t(sn.h_etile.size());
+  sn.n_stile = int32_t(sn.h_stile.size());
+  sn.sgather_len = int64_t(sn.h_sgather.size());
+  sn.n_hr = int32_t(sn.h_hr.size());
+  sn.n_hv = int32_t(sn.h_hv.size());
+  if ((st = upload(h, sn.d_slot, sn.slot)) != SPAND_OK) return st;
+  if ((st = upload(h, sn.d_nslot, nslot)) != SPAND_OK) return st;
+  if ((st = upload(h, sn.d_elim, sn.h_elim)) != SPAND_OK) return st;
+  if ((st = upload(h, sn.d_target, sn.h_target)) != SPAND_OK) return st;
+  if ((st = upload(h, sn.d_contrib, sn.h_contrib)) != SPAND_OK) return st;
+  if ((st = upload(h, sn.d_scale, sn.h_scale)) != SPAND_OK) return st;
+  if ((st = upload(h, sn.d_house, sn.h_house)) != SPAND_OK) return st;
+  if ((st = upload(h, sn.d_etile, sn.h_etile)) != SPAND_OK) return st;
+  if ((st = upload(h, sn.d_stile, sn.h_stile)) != SPAND_OK) return st;
+  if ((st = upload(h, sn.d_sgather, sn.h_sgather)) != SPAND_OK) return st;
+  if ((st = upload(h, sn.d_hr, sn.h_hr)) != SPAND_OK) return st;
+  if ((st = upload(h, sn.d_hv, sn.h_hv)) != SPAND_OK) return st;
+  return SPAND_OK;
+}
+
 spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int32_t skip, spand_prec prec) {
   Analysis& an = h->an;
   const int32_t Lv = an.levels;
   const int gemm_prec = (prec == SPAND_FP64) ? 0 : (prec == SPAND_FP32 ? 1 : 2);
+  h->stage.reset();
   h->num.clear();
   h->num.resize(Lv);
   h->max_tmp = 0;
@@ -284,21 +438,38 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
   DevBuf dflag;  // [0] elimination failure id, [1] scaling failure id, [2] non-finite input
   if ((st = dalloc(h, dflag, 4 * sizeof(int32_t))) != SPAND_OK) return st;
   const int32_t flag_init[4] = {0x7fffffff, 0x7fffffff, 0, 0};
-  HIPCHK(hipMemcpyAsync(dflag.p, flag_init, sizeof(flag_init), hipMemcpyHostToDevice, h->stream));
+  if ((st = stage_copy(h, dflag.p, flag_init, sizeof(flag_init))) != SPAND_OK) return st;
   int32_t* d_fail_elim = dflag.as<int32_t>();
   int32_t* d_fail_scale = dflag.as<int32_t>() + 1;
   int32_t* d_nonfinite = dflag.as<int32_t>() + 2;
 
-  // ph[0..4]: phase boundaries of a step
-  hipEvent_t ph[5];
-  struct EvGuard {
-    hipEvent_t* e;
-    int n = 0;
-    ~EvGuard() {
-      for (int q = 0; q < n; ++q) (void)hipEventDestroy(e[q]);
+  // phase boundaries of every step (5 events per step), read after the last sync
+  EventPool phev;
+  std::vector<char> elim_ran(size_t(Lv) + 1, 0);
+  // The device flags are read at one sync per step: the rank read-back of a
+  // sparsified step, or the end of any other step.  Kernels that run after a
+  // failure in the same step only see bad values, never bad indices.
+  auto check_flags = [&](int32_t t) -> spand_status {
+    int32_t flags[4];
+    HIPCHK(hipMemcpyAsync(flags, dflag.p, sizeof(flags), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (flags[2]) return set_err(h, SPAND_E_INVALID, "matrix values contain NaN or Inf");
+    if (flags[0] != 0x7fffffff) {
+      h->stats.fail_step = t;
+      h->stats.fail_cluster = flags[0];
+      h->stats.fail_phase = 0;
+      return set_err(h, SPAND_E_NOT_SPD, "pivot block not SPD at step " + std::to_string(t) + ", cluster " +
+                                             std::to_string(flags[0]) + " (elimination)");
     }
-  } g2{ph};
-  for (int q = 0; q < 5; ++q, ++g2.n) HIPCHK(hipEventCreate(&ph[q]));
+    if (flags[1] != 0x7fffffff) {
+      h->stats.fail_step = t;
+      h->stats.fail_cluster = flags[1];
+      h->stats.fail_phase = 1;
+      return set_err(h, SPAND_E_NOT_SPD, "interface block not SPD at step " + std::to_string(t) + ", cluster " +
+                                             std::to_string(flags[1]) + " (scaling)");
+    }
+    return SPAND_OK;
+  };
   std::memset(h->stats.step_phase_seconds, 0, sizeof(h->stats.step_phase_seconds));
   std::memset(h->stats.step_m_F, 0, sizeof(h->stats.step_m_F));
 
@@ -311,12 +482,24 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
 
   DevBuf arena_prev;
   Layout lay_prev;
+  // apply descriptors of the previous step, built while the current step runs
+  // (lay_prev is that step's layout until the end of the current one)
+  ApplyPlan pending;
+  auto flush_apply = [&]() -> spand_status {
+    if (pending.t == 0) return SPAND_OK;
+    const int32_t pt = pending.t;
+    pending.t = 0;
+    return build_apply(h, an.steps[pt - 1], h->num[pt - 1], lay_prev, pending);
+  };
 
   for (int32_t t = 1; t <= Lv; ++t) {
     const SymStep& sy = an.steps[t - 1];
     StepNum& sn = h->num[t - 1];
     const int32_t nc = sy.nc, ne = sy.ne;
     const bool sparsify = (t > skip) && (sy.level > 1);
+    bool flags_read = false;  // this step's flags were checked at its rank read-back
+    hipEvent_t ph[5];
+    for (int q = 0; q < 5; ++q) HIPCHK(phev.get(5 * size_t(t - 1) + q, &ph[q]));
 
     // ---- sizes and slots of this step's clusters
     sn.size.assign(nc, 0);
@@ -426,6 +609,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
 
     // ---- elimination (Sec. 2.4)
     HIPCHK(hipEventRecord(ph[1], h->stream));
+    HIPCHK(hipEventRecord(ph[2], h->stream));  // recorded again after the reduction
     std::vector<int64_t> c_off(ne), ed_off(ne);
     std::vector<int32_t> nN(ne);
     int64_t cbuf_total = 0, ed_total = 0;
@@ -510,21 +694,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       launch_reduce(drd.as<ReduceDesc>(), int32_t(rds.size()), dcd.as<ContribDesc>(), h->stream);
       HIPCHK(hipGetLastError());
       HIPCHK(hipEventRecord(ph[2], h->stream));
-      HIPCHK(hipStreamSynchronize(h->stream));
-      float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, ph[1], ph[2]));
-      elim_ms += ms;
-    }
-    int32_t flags[4];
-    HIPCHK(hipMemcpyAsync(flags, dflag.p, sizeof(flags), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
-    if (flags[2]) return set_err(h, SPAND_E_INVALID, "matrix values contain NaN or Inf");
-    if (flags[0] != 0x7fffffff) {
-      h->stats.fail_step = t;
-      h->stats.fail_cluster = flags[0];
-      h->stats.fail_phase = 0;
-      return set_err(h, SPAND_E_NOT_SPD, "pivot block not SPD at step " + std::to_string(t) + ", cluster " +
-                                             std::to_string(flags[0]) + " (elimination)");
+      elim_ran[t] = 1;
     }
     cbuf.release();
 
@@ -597,16 +767,6 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       launch_set_identity(d1.as<double*>(), d2.as<int32_t>(), d3.as<int32_t>(), int32_t(dptr.size()), h->stream);
       HIPCHK(hipGetLastError());
       HIPCHK(hipEventRecord(ph[3], h->stream));
-      HIPCHK(hipStreamSynchronize(h->stream));
-      HIPCHK(hipMemcpyAsync(flags, dflag.p, sizeof(flags), hipMemcpyDeviceToHost, h->stream));
-      HIPCHK(hipStreamSynchronize(h->stream));
-      if (flags[1] != 0x7fffffff) {
-        h->stats.fail_step = t;
-        h->stats.fail_cluster = flags[1];
-        h->stats.fail_phase = 1;
-        return set_err(h, SPAND_E_NOT_SPD, "interface block not SPD at step " + std::to_string(t) + ", cluster " +
-                                               std::to_string(flags[1]) + " (scaling)");
-      }
 
       // sparsification, colour by colour.  A_pn of interface p lives in the registers
       // of slabS[p] workgroups with tg[p] lanes per column.  Interfaces of one slab go
@@ -750,13 +910,15 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       }
       std::vector<int32_t> rk(nc, -1);
       HIPCHK(hipEventRecord(ph[4], h->stream));
-      HIPCHK(hipStreamSynchronize(h->stream));
+      if ((st = flush_apply()) != SPAND_OK) return st;  // the previous step's, while this one runs
+      if ((st = check_flags(t)) != SPAND_OK) return st;
+      flags_read = true;
       HIPCHK(hipMemcpyAsync(rk.data(), curb.p, size_t(nc) * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
       HIPCHK(hipMemcpyAsync(nref.data(), nrefb.p, size_t(nc) * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
       int32_t serr = 0;
       HIPCHK(hipMemcpyAsync(&serr, errb.p, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
       HIPCHK(hipStreamSynchronize(h->stream));
-      if (serr) return set_err(h, SPAND_E_HIP, "sparsification slab barrier timed out");
+      if (serr) return set_err(h, SPAND_E_HIP, "sparsification slab exchange timed out");
       for (size_t q = 0; q < nlaunch; ++q) {
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, evpool.ev[2 * q], evpool.ev[2 * q + 1]));
@@ -850,144 +1012,32 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
         HIPCHK(hipGetLastError());
       }
       HIPCHK(hipGetLastError());
-      HIPCHK(hipStreamSynchronize(h->stream));
     }
-    HIPCHK(hipStreamSynchronize(h->stream));
-    if (t <= 32) {
-      float ms[4] = {0.f, 0.f, 0.f, 0.f};
-      HIPCHK(hipEventElapsedTime(&ms[0], ph[0], ph[1]));
-      HIPCHK(hipEventElapsedTime(&ms[1], ph[1], ph[2]));
-      HIPCHK(hipEventElapsedTime(&ms[2], ph[2], ph[3]));
-      HIPCHK(hipEventElapsedTime(&ms[3], ph[3], ph[4]));
-      for (int q = 0; q < 4; ++q) h->stats.step_phase_seconds[t - 1][q] = 1e-3 * ms[q];
-      h->stats.step_m_F[t - 1] = m_F;
-    }
+    if (t <= 32) h->stats.step_m_F[t - 1] = m_F;
 
-    // ---- apply descriptors of this step
-    {
-      std::vector<int32_t> nslot;
-      int64_t tmp = 0;
-      sn.h_elim.clear();
-      for (int32_t s = 0; s < ne; ++s) {
-        ElimAp e{};
-        e.L = E + lay.base[s];
-        e.G = E + lay.base[s] + sn.size[s];
-        e.Dinv = sn.edinv.as<double>() + ed_off[s];
-        e.ld = int32_t(lay.H[s]);
-        e.ns = sn.size[s];
-        e.nN = nN[s];
-        e.slot_s = sn.slot_ptr[s];
-        e.slot_N = int64_t(nslot.size());
-        for (int64_t q = sy.enb_ptr[s]; q < sy.enb_ptr[s + 1]; ++q) {
-          const int32_t nb = sy.enb[q];
-          nslot.insert(nslot.end(), sn.slot.begin() + sn.slot_ptr[nb], sn.slot.begin() + sn.slot_ptr[nb + 1]);
-        }
-        e.tmp = tmp;
-        tmp += std::max(e.ns, 1);
-        sn.h_elim.push_back(e);
-      }
-      sn.tmp_elim = tmp;
-      sn.h_etile.clear();
-      for (int32_t s = 0; s < ne; ++s)
-        for (int32_t k0 = 0; k0 < sn.h_elim[s].ns; k0 += 64) sn.h_etile.push_back(ElimTile{s, k0});
-      // forward target updates, grouped by receiving cluster in ascending s
-      struct TI { int32_t n, s; int64_t row; };
-      std::vector<TI> tis;
-      for (int32_t s = 0; s < ne; ++s) {
-        int64_t row = 0;
-        for (int64_t q = sy.enb_ptr[s]; q < sy.enb_ptr[s + 1]; ++q) {
-          const int32_t nb = sy.enb[q];
-          if (sn.size[nb] > 0 && sn.size[s] > 0) tis.push_back(TI{nb, s, row});
-          row += sn.size[nb];
-        }
-      }
-      std::stable_sort(tis.begin(), tis.end(), [](const TI& x, const TI& y) { return x.n < y.n; });
-      sn.h_target.clear();
-      sn.h_contrib.clear();
-      for (size_t q = 0; q < tis.size();) {
-        size_t r = q;
-        TargetAp ta{};
-        ta.nn = sn.size[tis[q].n];
-        ta.slot_n = sn.slot_ptr[tis[q].n];
-        ta.cbeg = int32_t(sn.h_contrib.size());
-        while (r < tis.size() && tis[r].n == tis[q].n) {
-          const int32_t s = tis[r].s;
-          sn.h_contrib.push_back(TargetContrib{sn.h_elim[s].G + tis[r].row, sn.h_elim[s].ld, sn.size[s], sn.h_elim[s].tmp});
-          ++r;
-        }
-        ta.cend = int32_t(sn.h_contrib.size());
-        for (int32_t r0 = 0; r0 < ta.nn; r0 += 64) {  // one workgroup per 64-row tile
-          ta.r0 = r0;
-          sn.h_target.push_back(ta);
-        }
-        q = r;
-      }
-      sn.h_scale.clear();
-      sn.h_stile.clear();
-      sn.h_sgather.clear();
-      sn.h_house.clear();
-      sn.h_hr.clear();
-      sn.h_hv.clear();
-      int64_t tmp2 = 0, tmp3 = 0;
-      for (int32_t p = ne; p < nc; ++p) {
-        if (sc_off[p] >= 0) {
-          ScaleAp a{};
-          a.Linv = sn.scale.as<double>() + sc_off[p];
-          a.np = sn.size[p];
-          a.slot_p = sn.slot_ptr[p];
-          a.tmp = tmp2;
-          tmp2 += sn.size[p];
-          const int32_t sid = int32_t(sn.h_scale.size());
-          for (int32_t r0 = 0; r0 < a.np; r0 += 64) sn.h_stile.push_back(ScaleTile{sid, r0});
-          sn.h_sgather.insert(sn.h_sgather.end(), sn.slot.begin() + sn.slot_ptr[p],
-                              sn.slot.begin() + sn.slot_ptr[p] + sn.size[p]);
-          sn.h_scale.push_back(a);
-        }
-        if (v_off[p] >= 0 && nref[p] > 0) {
-          HouseAp hp{};
-          hp.V = sn.house.as<double>() + v_off[p];
-          hp.T = sn.house.as<double>() + t_off[p];
-          hp.np = sn.size[p];
-          hp.r = nref[p];
-          hp.slot_p = sn.slot_ptr[p];
-          hp.tmp = tmp3;
-          tmp3 += 2 * int64_t(nref[p]);
-          const int32_t hid = int32_t(sn.h_house.size());
-          for (int32_t j0 = 0; j0 < hp.r; j0 += 64) sn.h_hr.push_back(HouseTile{hid, j0});
-          for (int32_t r0 = 0; r0 < hp.np; r0 += 64) sn.h_hv.push_back(HouseTile{hid, r0});
-          sn.h_house.push_back(hp);
-        }
-      }
-      sn.tmp_scale = std::max(tmp2, tmp3);
-      sn.nslot_len = int64_t(nslot.size());
-      h->max_tmp = std::max(h->max_tmp, std::max(sn.tmp_elim, sn.tmp_scale));
-      h->max_gather = std::max(h->max_gather, sn.nslot_len);
-      sn.n_elim_ap = int32_t(sn.h_elim.size());
-      sn.n_target = int32_t(sn.h_target.size());
-      sn.n_scale = int32_t(sn.h_scale.size());
-      sn.n_house = int32_t(sn.h_house.size());
-      sn.n_etile = int32_t(sn.h_etile.size());
-      sn.n_stile = int32_t(sn.h_stile.size());
-      sn.sgather_len = int64_t(sn.h_sgather.size());
-      sn.n_hr = int32_t(sn.h_hr.size());
-      sn.n_hv = int32_t(sn.h_hv.size());
-      if ((st = upload(h, sn.d_slot, sn.slot)) != SPAND_OK) return st;
-      if ((st = upload(h, sn.d_nslot, nslot)) != SPAND_OK) return st;
-      if ((st = upload(h, sn.d_elim, sn.h_elim)) != SPAND_OK) return st;
-      if ((st = upload(h, sn.d_target, sn.h_target)) != SPAND_OK) return st;
-      if ((st = upload(h, sn.d_contrib, sn.h_contrib)) != SPAND_OK) return st;
-      if ((st = upload(h, sn.d_scale, sn.h_scale)) != SPAND_OK) return st;
-      if ((st = upload(h, sn.d_house, sn.h_house)) != SPAND_OK) return st;
-      if ((st = upload(h, sn.d_etile, sn.h_etile)) != SPAND_OK) return st;
-      if ((st = upload(h, sn.d_stile, sn.h_stile)) != SPAND_OK) return st;
-      if ((st = upload(h, sn.d_sgather, sn.h_sgather)) != SPAND_OK) return st;
-      if ((st = upload(h, sn.d_hr, sn.h_hr)) != SPAND_OK) return st;
-      if ((st = upload(h, sn.d_hv, sn.h_hv)) != SPAND_OK) return st;
-      HIPCHK(hipStreamSynchronize(h->stream));
+    if (!flags_read) {
+      if ((st = flush_apply()) != SPAND_OK) return st;
+      if ((st = check_flags(t)) != SPAND_OK) return st;
     }
+    pending = ApplyPlan{t, std::move(ed_off), std::move(sc_off), std::move(v_off), std::move(t_off), std::move(nN),
+                        std::move(nref)};
 
     arena_prev = std::move(arena);
     lay_prev = std::move(lay);
+  }
+  if ((st = flush_apply()) != SPAND_OK) return st;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  for (int32_t t = 1; t <= Lv; ++t) {  // phase times from the events of every step
+    hipEvent_t ph[5];
+    for (int q = 0; q < 5; ++q) ph[q] = phev.ev[5 * size_t(t - 1) + q];
+    float ms[4] = {0.f, 0.f, 0.f, 0.f};
+    HIPCHK(hipEventElapsedTime(&ms[0], ph[0], ph[1]));
+    HIPCHK(hipEventElapsedTime(&ms[1], ph[1], ph[2]));
+    HIPCHK(hipEventElapsedTime(&ms[2], ph[2], ph[3]));
+    HIPCHK(hipEventElapsedTime(&ms[3], ph[3], ph[4]));
+    if (t <= 32)
+      for (int q = 0; q < 4; ++q) h->stats.step_phase_seconds[t - 1][q] = 1e-3 * ms[q];
+    if (elim_ran[t]) elim_ms += ms[1];
   }
   arena_prev.release();
   h->stats.m_F = m_F;
