@@ -126,40 +126,36 @@ void build_layout(const SymStep& st, const std::vector<int32_t>& size, Layout& L
   L.total_arena = ta;
 }
 
-// part: 0 every tile, 1 tiles on or below the diagonal, 2 tiles on or above it
-void add_tiles(std::vector<TileRef>& tiles, int32_t desc, int32_t M, int32_t N, int part) {
-  const int32_t tm = (M + GEMM_TILE - 1) / GEMM_TILE, tn = (N + GEMM_TILE - 1) / GEMM_TILE;
-  for (int32_t a = 0; a < tm; ++a)
-    for (int32_t b = 0; b < tn; ++b) {
-      if ((part == 1 && b > a) || (part == 2 && b < a)) continue;
-      tiles.push_back(TileRef{desc, a, b, 0});
-    }
-}
-
-// A sequence of batched-GEMM launches whose descriptors and tiles are uploaded once.
+// A sequence of batched-GEMM launches.  The host uploads the products only; a
+// device kernel expands them into the tile -> product map the launches read.
+// part: 0 every tile, 1 tiles on or below the diagonal, 2 tiles on or above it.
 struct GemmSeq {
   std::vector<GemmDesc> d;
-  std::vector<TileRef> t;
   std::vector<int64_t> cut;  // tile range end of every launch
   std::vector<int> prec;
-  DevBuf dd, dt;
-  void add(const GemmDesc& g, int part) {
+  int64_t ntiles = 0;
+  DevBuf dd, dmap;
+  void add(GemmDesc g, int part) {
     if (g.M <= 0 || g.N <= 0 || g.K <= 0) return;
+    g.part = part;
+    g.t0 = ntiles;
+    ntiles += gemm_tiles(g.M, g.N, part);
     d.push_back(g);
-    add_tiles(t, int32_t(d.size() - 1), g.M, g.N, part);
   }
   void end_launch(int p) {
-    cut.push_back(int64_t(t.size()));
+    cut.push_back(ntiles);
     prec.push_back(p);
   }
   spand_status upload_all(spand_ctx* h) {
     spand_status st = upload(h, dd, d);
     if (st != SPAND_OK) return st;
-    return upload(h, dt, t);
+    if ((st = dalloc(h, dmap, size_t(ntiles) * sizeof(int32_t))) != SPAND_OK) return st;
+    launch_expand_tiles(dd.as<GemmDesc>(), int32_t(d.size()), dmap.as<int32_t>(), h->stream);
+    return SPAND_OK;
   }
   void launch(spand_ctx* h, size_t q) const {
     const int64_t b = q ? cut[q - 1] : 0;
-    if (cut[q] > b) launch_gemm(dd.as<GemmDesc>(), dt.as<TileRef>() + b, cut[q] - b, prec[q], h->stream);
+    if (cut[q] > b) launch_gemm(dd.as<GemmDesc>(), dmap.as<int32_t>(), b, cut[q] - b, prec[q], h->stream);
   }
 };
 
@@ -818,7 +814,15 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       std::vector<std::vector<int32_t>> by_colour(ncolour);
       for (int32_t p = ne; p < nc; ++p)
         if (v_off[p] >= 0) by_colour[sy.colour[p]].push_back(p);
-      std::vector<DevBuf> keep;
+      struct CpqrLaunch {
+        bool multi;
+        int32_t G, nslab;
+        size_t lds, d0, s0;
+      };
+      std::vector<CpqrLaunch> launches;
+      std::vector<SparsDesc> all_sds;
+      std::vector<SegDesc> all_segs;
+      std::vector<SlabRef> all_slabs;
       size_t nlaunch = 0;
       // launch groups of one colour: single-slab interfaces per team size G
       // (group G), then every multi-slab interface of the colour together (group 0)
@@ -844,14 +848,18 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
           }
           size_t pos = 0;
           while (pos < plist.size()) {
-            std::vector<SparsDesc> sds;
-            std::vector<SegDesc> segs;
-            std::vector<SlabRef> slabs;
+            CpqrLaunch L{};
+            L.multi = multi;
+            L.G = multi ? 0 : grp;
+            L.lds = lds;
+            L.d0 = all_sds.size();
+            L.s0 = all_slabs.size();
+            int32_t nsl = 0;
             while (pos < plist.size()) {
               const int32_t p = plist[pos];
               if (multi && slabS[p] > cap)
                 return set_err(h, SPAND_E_INVALID, "interface needs more co-resident workgroups than the GPU holds");
-              if (multi && !slabs.empty() && int64_t(slabs.size()) + slabS[p] > cap) break;
+              if (multi && nsl > 0 && int64_t(nsl) + slabS[p] > cap) break;
               SparsDesc d{};
               d.V = sn.house.as<double>() + v_off[p];
               d.tau = sn.house.as<double>() + tau_off[p];
@@ -862,7 +870,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
               d.S = slabS[p];
               d.G = tg[p];
               if (multi) d.xch = xchb.as<double>() + xch_off[p];
-              d.seg_begin = int32_t(segs.size());
+              d.seg_begin = int32_t(all_segs.size());
               for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e) {
                 const int32_t q = sy.nb[e];
                 if (sn.size[q] == 0) continue;
@@ -877,36 +885,40 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
                   g.trans = 1;
                 }
                 g.q = q;
-                segs.push_back(g);
+                all_segs.push_back(g);
               }
-              d.seg_end = int32_t(segs.size());
-              for (int32_t w = 0; w < slabS[p]; ++w) slabs.push_back(SlabRef{int32_t(sds.size()), w});
-              sds.push_back(d);
+              d.seg_end = int32_t(all_segs.size());
+              for (int32_t w = 0; w < slabS[p]; ++w)
+                all_slabs.push_back(SlabRef{int32_t(all_sds.size() - L.d0), w});
+              nsl += slabS[p];
+              all_sds.push_back(d);
               ++pos;
             }
-            DevBuf a, b, sl;
-            if ((st = upload(h, a, sds)) != SPAND_OK) return st;
-            if ((st = upload(h, b, segs)) != SPAND_OK) return st;
-            if ((st = upload(h, sl, slabs)) != SPAND_OK) return st;
-            hipEvent_t e0, e1;
-            HIPCHK(evpool.get(2 * nlaunch, &e0));
-            HIPCHK(evpool.get(2 * nlaunch + 1, &e1));
-            HIPCHK(hipEventRecord(e0, h->stream));
-            hipError_t le = multi ? launch_cpqr_multi(a.as<SparsDesc>(), sl.as<SlabRef>(), int32_t(slabs.size()),
-                                                      b.as<SegDesc>(), tol, curb.as<int32_t>(), nrefb.as<int32_t>(),
-                                                      errb.as<int32_t>(), lds, h->stream)
-                                  : launch_cpqr_one(grp, a.as<SparsDesc>(), sl.as<SlabRef>(), int32_t(slabs.size()),
-                                                    b.as<SegDesc>(), tol, curb.as<int32_t>(), nrefb.as<int32_t>(),
-                                                    errb.as<int32_t>(), lds, h->stream);
-            if (le != hipSuccess)
-              return set_err(h, SPAND_E_HIP, std::string("sparsification launch: ") + hipGetErrorString(le));
-            HIPCHK(hipEventRecord(e1, h->stream));
-            ++nlaunch;
-            keep.push_back(std::move(a));
-            keep.push_back(std::move(b));
-            keep.push_back(std::move(sl));
+            L.nslab = nsl;
+            launches.push_back(L);
           }
         }
+      }
+      // every launch of the step is planned: one upload, then the launches back to back
+      DevBuf a, b, sl;
+      if ((st = upload(h, a, all_sds)) != SPAND_OK) return st;
+      if ((st = upload(h, b, all_segs)) != SPAND_OK) return st;
+      if ((st = upload(h, sl, all_slabs)) != SPAND_OK) return st;
+      for (const CpqrLaunch& L : launches) {
+        hipEvent_t e0, e1;
+        HIPCHK(evpool.get(2 * nlaunch, &e0));
+        HIPCHK(evpool.get(2 * nlaunch + 1, &e1));
+        HIPCHK(hipEventRecord(e0, h->stream));
+        const SparsDesc* dd = a.as<SparsDesc>() + L.d0;
+        const SlabRef* ss = sl.as<SlabRef>() + L.s0;
+        hipError_t le = L.multi ? launch_cpqr_multi(dd, ss, L.nslab, b.as<SegDesc>(), tol, curb.as<int32_t>(),
+                                                    nrefb.as<int32_t>(), errb.as<int32_t>(), L.lds, h->stream)
+                                : launch_cpqr_one(L.G, dd, ss, L.nslab, b.as<SegDesc>(), tol, curb.as<int32_t>(),
+                                                  nrefb.as<int32_t>(), errb.as<int32_t>(), L.lds, h->stream);
+        if (le != hipSuccess)
+          return set_err(h, SPAND_E_HIP, std::string("sparsification launch: ") + hipGetErrorString(le));
+        HIPCHK(hipEventRecord(e1, h->stream));
+        ++nlaunch;
       }
       std::vector<int32_t> rk(nc, -1);
       HIPCHK(hipEventRecord(ph[4], h->stream));

@@ -43,12 +43,15 @@ struct GemmDesc {
   int32_t M, N, K;
   int32_t lda, ldb, ldc;
   int32_t flags;
-  int32_t pad;
+  int32_t part;  // 64x64 output tiles produced: 0 all, 1 on or below the diagonal, 2 on or above (M == N)
   double alpha, beta;
+  int64_t t0;    // first tile of this product in the numbering of its launch sequence
 };
-struct TileRef {
-  int32_t desc, tm, tn, pad;
-};
+// Output tiles of one product (part != 0 requires M == N).
+__host__ __device__ inline int64_t gemm_tiles(int32_t M, int32_t N, int32_t part) {
+  const int64_t tm = (M + 63) / 64, tn = (N + 63) / 64;
+  return part == 0 ? tm * tn : tm * (tm + 1) / 2;
+}
 
 // Target block of the Schur complement reduction.
 struct ReduceDesc {
@@ -94,7 +97,10 @@ void launch_scatter_values(const double* vals, const int64_t* dst, int64_t nnz, 
 // Batched GEMM over 64x64 output tiles on the matrix cores (kernels_mfma.hip);
 // prec: 0 FP64, 1 FP32, 2 BF16x3.  Carries the trailing updates of the blocked
 // Cholesky, the SYRK of the Schur update (Sec. 2.4) and the left scaling (Sec. 2.5).
-void launch_gemm(const GemmDesc* d, const TileRef* tiles, int64_t ntiles, int prec, hipStream_t s);
+// tile_desc[t] = product of tile t, for the tiles of nd products numbered by their t0.
+void launch_expand_tiles(const GemmDesc* d, int32_t nd, int32_t* tile_desc, hipStream_t s);
+// Tiles [tile0, tile0 + ntiles) of a sequence, one workgroup each.
+void launch_gemm(const GemmDesc* d, const int32_t* tile_desc, int64_t tile0, int64_t ntiles, int prec, hipStream_t s);
 void launch_reduce(const ReduceDesc* d, int32_t count, const ContribDesc* c, hipStream_t s);
 void launch_copy(const CopyDesc* d, int64_t count, hipStream_t s);
 void launch_set_identity(double* const* diag, const int32_t* n, const int32_t* ld, int32_t count, hipStream_t s);

@@ -1,6 +1,7 @@
 // Batched variable-size GEMM on the CDNA4 matrix cores.
 //
-// Descriptor/tile queue built by the host: one 64x64 output tile per workgroup of 4
+// Descriptors built by the host, expanded on the device into a tile -> product map:
+// one 64x64 output tile per workgroup of 4
 // waves; wave (wm, wn) owns the 32x32 quadrant (wm, wn) as 2x2 blocks of 16x16
 // MFMA outputs.  Operand tiles are staged k-major in LDS so that the 16 lanes
 // reading one fragment touch consecutive addresses.
@@ -64,20 +65,44 @@ __device__ inline void store_block(const GemmDesc& d, int row0, int col0, const 
   }
 }
 
+// Tile (row, column) of the local-th output tile of a product: row-major over all
+// tiles, or row-major over the lower triangle (part 1), or its transpose (part 2).
+__device__ inline void tile_coords(const GemmDesc& d, int64_t local, int& tm, int& tn) {
+  if (d.part == 0) {
+    const int64_t ntn = (d.N + 63) / 64;
+    tm = (int)(local / ntn);
+    tn = (int)(local - (int64_t)tm * ntn);
+    return;
+  }
+  int a = (int)((sqrt(8.0 * (double)local + 1.0) - 1.0) * 0.5);
+  while ((int64_t)(a + 1) * (a + 2) / 2 <= local) ++a;
+  while ((int64_t)a * (a + 1) / 2 > local) --a;
+  const int b = (int)(local - (int64_t)a * (a + 1) / 2);
+  if (d.part == 1) {
+    tm = a;
+    tn = b;
+  } else {
+    tm = b;
+    tn = a;
+  }
+}
+
 }  // namespace
 
 // MODE 0 / 1: K staged 16 at a time, four k=4 MFMA steps per stage.
 template <int MODE>
 __global__ void __launch_bounds__(MW) k_gemm_mfma(const GemmDesc* __restrict__ descs,
-                                                  const TileRef* __restrict__ tiles) {
+                                                  const int32_t* __restrict__ tile_desc, int64_t tile0) {
   typedef typename std::conditional<MODE == 0, double, float>::type T;
   typedef typename std::conditional<MODE == 0, d4_t, f4_t>::type C4;
   constexpr int BK = 16;
   __shared__ T As[BK][64 + 1];
   __shared__ T Bs[BK][64 + 1];
-  const TileRef tr = tiles[blockIdx.x];
-  const GemmDesc d = descs[tr.desc];
-  const int m0 = tr.tm * 64, n0 = tr.tn * 64;
+  const int64_t tile = tile0 + blockIdx.x;
+  const GemmDesc d = descs[tile_desc[tile]];
+  int tmi, tni;
+  tile_coords(d, tile - d.t0, tmi, tni);
+  const int m0 = tmi * 64, n0 = tni * 64;
   int kmax = d.K;
   if (d.flags & G_TRIA) kmax = min(kmax, m0 + 64);
   if (d.flags & G_TRIB) kmax = min(kmax, n0 + 64);
@@ -129,13 +154,15 @@ __global__ void __launch_bounds__(MW) k_gemm_mfma(const GemmDesc* __restrict__ d
 
 // MODE 2 (BF16x3): K staged 32 at a time, one k=32 step (three MFMAs) per stage.
 __global__ void __launch_bounds__(MW) k_gemm_bf16x3(const GemmDesc* __restrict__ descs,
-                                                    const TileRef* __restrict__ tiles) {
+                                                    const int32_t* __restrict__ tile_desc, int64_t tile0) {
   constexpr int BK = 32;
   constexpr int LDK = BK + 8;  // row pitch in bf16 (80 bytes)
   __shared__ __attribute__((aligned(16))) __bf16 Ah[64 * LDK], Al[64 * LDK], Bh[64 * LDK], Bl[64 * LDK];
-  const TileRef tr = tiles[blockIdx.x];
-  const GemmDesc d = descs[tr.desc];
-  const int m0 = tr.tm * 64, n0 = tr.tn * 64;
+  const int64_t tile = tile0 + blockIdx.x;
+  const GemmDesc d = descs[tile_desc[tile]];
+  int tmi, tni;
+  tile_coords(d, tile - d.t0, tmi, tni);
+  const int m0 = tmi * 64, n0 = tni * 64;
   int kmax = d.K;
   if (d.flags & G_TRIA) kmax = min(kmax, m0 + 64);
   if (d.flags & G_TRIB) kmax = min(kmax, n0 + 64);
@@ -190,14 +217,25 @@ __global__ void __launch_bounds__(MW) k_gemm_bf16x3(const GemmDesc* __restrict__
     for (int q = 0; q < 2; ++q) store_block<false>(d, m0 + wm * 32 + p * 16, n0 + wn * 32 + q * 16, acc[p][q]);
 }
 
-void launch_gemm(const GemmDesc* d, const TileRef* tiles, int64_t ntiles, int prec, hipStream_t s) {
+__global__ void k_expand_tiles(const GemmDesc* __restrict__ descs, int32_t* __restrict__ tile_desc) {
+  const GemmDesc d = descs[blockIdx.x];
+  const int64_t n = gemm_tiles(d.M, d.N, d.part);
+  for (int64_t q = threadIdx.x; q < n; q += blockDim.x) tile_desc[d.t0 + q] = (int32_t)blockIdx.x;
+}
+
+void launch_expand_tiles(const GemmDesc* d, int32_t nd, int32_t* tile_desc, hipStream_t s) {
+  if (nd > 0) hipLaunchKernelGGL(k_expand_tiles, dim3(nd), dim3(64), 0, s, d, tile_desc);
+}
+
+void launch_gemm(const GemmDesc* d, const int32_t* tile_desc, int64_t tile0, int64_t ntiles, int prec,
+                 hipStream_t s) {
   if (ntiles == 0) return;
   if (prec == 0)
-    hipLaunchKernelGGL(k_gemm_mfma<0>, dim3(ntiles), dim3(MW), 0, s, d, tiles);
+    hipLaunchKernelGGL(k_gemm_mfma<0>, dim3(ntiles), dim3(MW), 0, s, d, tile_desc, tile0);
   else if (prec == 1)
-    hipLaunchKernelGGL(k_gemm_mfma<1>, dim3(ntiles), dim3(MW), 0, s, d, tiles);
+    hipLaunchKernelGGL(k_gemm_mfma<1>, dim3(ntiles), dim3(MW), 0, s, d, tile_desc, tile0);
   else
-    hipLaunchKernelGGL(k_gemm_bf16x3, dim3(ntiles), dim3(MW), 0, s, d, tiles);
+    hipLaunchKernelGGL(k_gemm_bf16x3, dim3(ntiles), dim3(MW), 0, s, d, tile_desc, tile0);
 }
 
 }  // namespace spand
