@@ -44,6 +44,15 @@ struct HouseAp {
   int64_t slot_p;
   int64_t tmp;        // 2*r rows of scratch: V^T x, then the T-product
 };
+// A small interface p (np <= 128) whose scaling and Householder product are
+// applied together by one wave (k_iface).
+struct IfaceAp {
+  const double* Linv;  // np x np lower-triangular L_p^{-1}, ld np
+  const double* V;     // np x r reflectors, ld np (unused when r == 0)
+  const double* T;     // r x r upper-triangular T, ld r
+  int32_t np, r;
+  int64_t slot_p;
+};
 struct HouseTile {    // 64 reflectors [j0, j0 + 64) or 64 rows [j0, j0 + 64) of interface p
   int32_t p, j0;
 };
@@ -61,6 +70,8 @@ struct StepDev {
   int64_t sgather_len;
   const HouseTile* hr;   // reflector tiles of every Q_p
   const HouseTile* hv;   // row tiles of every Q_p
+  const IfaceAp* iface;  // small interfaces: np <= 64 first (n_iface1), then np <= 128 (n_iface2)
+  int32_t n_iface1, n_iface2;
   const int32_t* slot;
   const int32_t* nslot;
   int64_t nslot_len;

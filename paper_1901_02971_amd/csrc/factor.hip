@@ -363,7 +363,28 @@ spand_status build_apply(spand_ctx* h, const SymStep& sy, StepNum& sn, const Lay
   sn.h_hr.clear();
   sn.h_hv.clear();
   int64_t tmp2 = 0, tmp3 = 0;
+  // interfaces of at most 64 dofs, and of at most 128 when a step has enough of
+  // them to fill the GPU: scaling and Householder product in one wave (np <= 64
+  // first, then np <= 128); the others by the tiled kernels
+  std::vector<IfaceAp> if1, if2;
+  int32_t n128 = 0;
+  for (int32_t p = ne; p < nc; ++p)
+    if (sc_off[p] >= 0 && sn.size[p] > 64 && sn.size[p] <= 128) ++n128;
+  const int32_t fuse_max = n128 >= 256 ? 128 : 64;
   for (int32_t p = ne; p < nc; ++p) {
+    if (sc_off[p] >= 0 && sn.size[p] <= fuse_max) {
+      IfaceAp f{};
+      f.Linv = sn.scale.as<double>() + sc_off[p];
+      f.np = sn.size[p];
+      f.slot_p = sn.slot_ptr[p];
+      if (v_off[p] >= 0 && nref[p] > 0) {
+        f.V = sn.house.as<double>() + v_off[p];
+        f.T = sn.house.as<double>() + t_off[p];
+        f.r = nref[p];
+      }
+      (f.np <= 64 ? if1 : if2).push_back(f);
+      continue;
+    }
     if (sc_off[p] >= 0) {
       ScaleAp a{};
       a.Linv = sn.scale.as<double>() + sc_off[p];
@@ -392,6 +413,10 @@ spand_status build_apply(spand_ctx* h, const SymStep& sy, StepNum& sn, const Lay
       sn.h_house.push_back(hp);
     }
   }
+  sn.n_iface1 = int32_t(if1.size());
+  sn.n_iface2 = int32_t(if2.size());
+  sn.h_iface = std::move(if1);
+  sn.h_iface.insert(sn.h_iface.end(), if2.begin(), if2.end());
   sn.tmp_scale = std::max(tmp2, tmp3);
   sn.nslot_len = int64_t(nslot.size());
   h->max_tmp = std::max(h->max_tmp, std::max(sn.tmp_elim, sn.tmp_scale));
@@ -417,6 +442,7 @@ spand_status build_apply(spand_ctx* h, const SymStep& sy, StepNum& sn, const Lay
   if ((st = upload(h, sn.d_sgather, sn.h_sgather)) != SPAND_OK) return st;
   if ((st = upload(h, sn.d_hr, sn.h_hr)) != SPAND_OK) return st;
   if ((st = upload(h, sn.d_hv, sn.h_hv)) != SPAND_OK) return st;
+  if ((st = upload(h, sn.d_iface, sn.h_iface)) != SPAND_OK) return st;
   return SPAND_OK;
 }
 

@@ -9,9 +9,11 @@
 //   k_target_fwd  x_n <- x_n - sum_s G_ns x_s     (one workgroup per 64-row tile of a
 //                                                  receiving n, contributions in
 //                                                  ascending s)
-//   k_scale<1>    x_p <- L_p^{-1} x_p                (explicit inverse, 64-row tiles)
+//   k_iface<1>    x_p <- Q_p^T L_p^{-1} x_p      (interfaces of at most 128 dofs, one wave each)
+//   k_scale<1>    x_p <- L_p^{-1} x_p                (larger interfaces: explicit inverse, 64-row tiles)
 //   k_house_*     x_p <- Q_p^T x_p                (compact WY form, three tile launches)
 // Backward sweep (levels 1 -> L), the transposes in reverse order:
+//   k_iface<-1>   x_p <- L_p^{-T} Q_p x_p
 //   k_house_*     x_p <- Q_p x_p
 //   k_scale<-1>   x_p <- L_p^{-T} x_p
 //   k_gather         neighbour dofs of every s into a contiguous buffer
@@ -374,6 +376,142 @@ __global__ void __launch_bounds__(AW) k_house_v(const HouseAp* __restrict__ ds, 
   }
 }
 
+// ---------------------------------------------------------------- small interfaces
+// One wave per interface p with np <= 64 RPL: scaling and Householder product in
+// one pass over L_p^{-1}, V and T.  Lane l owns rows l + 64 q (q < RPL) of x_p in
+// registers; products whose rows run down a column (L^{-1} x, V u, T w) read the
+// matrix with consecutive lanes on consecutive rows, the transposed ones (V^T y,
+// T^T w, L^{-T} y) let lane j walk its own column.  The vector being consumed is
+// broadcast from LDS.
+//   DIR = +1: x_p <- Q_p^T L_p^{-1} x_p      DIR = -1: x_p <- L_p^{-T} Q_p x_p
+template <int RPL>
+__device__ inline void iface_put(double (*buf)[RB], const double (&v)[RPL][RB]) {
+#pragma unroll
+  for (int q = 0; q < RPL; ++q)
+#pragma unroll
+    for (int c = 0; c < RB; ++c) buf[threadIdx.x + 64 * q][c] = v[q][c];
+  __syncthreads();
+}
+__device__ inline void iface_get(const double (*buf)[RB], int k, double (&b)[RB]) {
+#pragma unroll
+  for (int c = 0; c < RB; ++c) b[c] = buf[k][c];
+}
+
+// Products of a matrix M (ld ld, nrows x ncols, restricted to mode 0: every entry,
+// 1: the upper triangle row <= column, 2: the lower triangle row >= column) with
+// the vector vb broadcast from LDS:
+//   COLWALK  out[j] = sum_i M[i + j ld] vb_i   lane j walks column j = lane + 64 q
+//   else     out[i] = sum_k M[i + k ld] vb_k   lanes run down column k, row i = lane + 64 q
+// The matrix is read in chunks of IFC entries (reads past the end are masked and
+// give 0; rows of vb beyond the matrix hold 0); the many waves of a launch hide the
+// latency of a chunk.
+#define IFC 8
+template <int RPL, bool COLWALK>
+__device__ inline void iface_chunk(const double* __restrict__ M, int ld, int nrows, int ncols, int mode, int k0,
+                                   double (&m)[IFC][RPL]) {
+#pragma unroll
+  for (int u = 0; u < IFC; ++u)
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int own = threadIdx.x + 64 * q, s = k0 + u;  // own: this lane's column (COLWALK) or row
+      const int i = COLWALK ? s : own, j = COLWALK ? own : s;
+            const bool on = i < nrows && j < ncols && (mode == 0 || (mode == 1 ? i <= j : i >= j));
+      m[u][q] = on ? gld(M + i + (int64_t)j * ld) : 0.0;
+    }
+}
+template <int RPL>
+__device__ inline void iface_fma(const double (&m)[IFC][RPL], const double (*vb)[RB], int k0,
+                                 double (&out)[RPL][RB]) {
+#pragma unroll
+  for (int u = 0; u < IFC; ++u) {
+    double b[RB];
+    iface_get(vb, k0 + u, b);
+#pragma unroll
+    for (int q = 0; q < RPL; ++q)
+#pragma unroll
+      for (int c = 0; c < RB; ++c) out[q][c] = fma(m[u][q], b[c], out[q][c]);
+  }
+}
+template <int RPL, bool COLWALK>
+__device__ inline void iface_product(const double* __restrict__ M, int ld, int nrows, int ncols, int mode,
+                                     const double (*vb)[RB], double (&out)[RPL][RB]) {
+#pragma unroll
+  for (int q = 0; q < RPL; ++q)
+#pragma unroll
+    for (int c = 0; c < RB; ++c) out[q][c] = 0.0;
+  const int n = COLWALK ? nrows : ncols;  // length of the sum
+  for (int k0 = 0; k0 < n; k0 += IFC) {
+    double m[IFC][RPL];
+    iface_chunk<RPL, COLWALK>(M, ld, nrows, ncols, mode, k0, m);
+    iface_fma<RPL>(m, vb, k0, out);
+  }
+}
+
+template <int DIR, int RPL>
+__global__ void __launch_bounds__(64) k_iface(const IfaceAp* __restrict__ ds, ApplyArgs a) {
+  __shared__ double xb[64 * RPL][RB];  // vector broadcast: x, then y
+  __shared__ double wb[64 * RPL][RB];  // w, then u
+  const IfaceAp e = ds[blockIdx.x];
+  const int np = e.np, r = e.r;
+  const int32_t* sl = a.slot + e.slot_p;
+#pragma unroll 1
+  for (int c0 = 0; c0 < a.nrhs; c0 += RB) {
+    const int nr = min(RB, a.nrhs - c0);
+    double x[RPL][RB], y[RPL][RB];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int i = threadIdx.x + 64 * q;
+      const int64_t v = i < np ? (int64_t)sl[i] : 0;
+#pragma unroll
+      for (int c = 0; c < RB; ++c) x[q][c] = (i < np && c < nr) ? a.x[v + (int64_t)(c0 + c) * a.ldx] : 0.0;
+    }
+    if (DIR > 0) {
+      iface_put<RPL>(xb, x);
+      iface_product<RPL, false>(e.Linv, np, np, np, 2, xb, y);  // y = L^{-1} x (lower: i >= k)
+    } else {
+#pragma unroll
+      for (int q = 0; q < RPL; ++q)
+#pragma unroll
+        for (int c = 0; c < RB; ++c) y[q][c] = x[q][c];
+    }
+    if (r > 0) {  // y <- Q^T y (DIR +1) or Q y (DIR -1), Q = I - V T V^T
+      double w[RPL][RB], u[RPL][RB];
+      __syncthreads();
+      iface_put<RPL>(xb, y);
+      iface_product<RPL, true>(e.V, np, np, r, 0, xb, w);  // w = V^T y
+      iface_put<RPL>(wb, w);
+      if (DIR > 0)
+        iface_product<RPL, true>(e.T, r, r, r, 1, wb, u);  // u = T^T w (upper: k <= j)
+      else
+        iface_product<RPL, false>(e.T, r, r, r, 1, wb, u);  // u = T w (upper: i <= k)
+      __syncthreads();
+      iface_put<RPL>(wb, u);
+      double vu[RPL][RB];
+      iface_product<RPL, false>(e.V, np, np, r, 0, wb, vu);  // V u
+#pragma unroll
+      for (int q = 0; q < RPL; ++q)
+#pragma unroll
+        for (int c = 0; c < RB; ++c) y[q][c] -= vu[q][c];
+    }
+    if (DIR < 0) {
+      __syncthreads();
+      iface_put<RPL>(xb, y);
+      iface_product<RPL, true>(e.Linv, np, np, np, 2, xb, y);  // y = L^{-T} y (column j of L^{-1}, rows i >= j)
+    }
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int i = threadIdx.x + 64 * q;
+      if (i < np) {
+        const int64_t v = sl[i];
+#pragma unroll
+        for (int c = 0; c < RB; ++c)
+          if (c < nr) a.x[v + (int64_t)(c0 + c) * a.ldx] = y[q][c];
+      }
+    }
+    __syncthreads();  // xb, wb are rewritten by the next right-hand-side block
+  }
+}
+
 __global__ void k_gather(const int32_t* __restrict__ nslot, int64_t len, ApplyArgs a) {
   const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (q >= len) return;
@@ -418,6 +556,8 @@ __global__ void __launch_bounds__(AW) k_elim_bwd(const ElimAp* __restrict__ ds, 
 void apply_step_forward(const StepDev& s, const ApplyArgs& a, hipStream_t st) {
   if (s.n_elim) hipLaunchKernelGGL(k_elim_fwd, dim3(s.n_elim), dim3(AW), 0, st, s.elim, a);
   if (s.n_target) hipLaunchKernelGGL(k_target_fwd, dim3(s.n_target), dim3(AW), 0, st, s.target, s.contrib, a);
+  if (s.n_iface1) hipLaunchKernelGGL((k_iface<1, 1>), dim3(s.n_iface1), dim3(64), 0, st, s.iface, a);
+  if (s.n_iface2) hipLaunchKernelGGL((k_iface<1, 2>), dim3(s.n_iface2), dim3(64), 0, st, s.iface + s.n_iface1, a);
   if (s.n_stile) {
     hipLaunchKernelGGL(k_gather_rows, dim3((s.sgather_len + 255) / 256), dim3(256), 0, st, s.sgather,
                        s.sgather_len, a);
@@ -431,6 +571,8 @@ void apply_step_forward(const StepDev& s, const ApplyArgs& a, hipStream_t st) {
 }
 
 void apply_step_backward(const StepDev& s, const ApplyArgs& a, hipStream_t st) {
+  if (s.n_iface1) hipLaunchKernelGGL((k_iface<-1, 1>), dim3(s.n_iface1), dim3(64), 0, st, s.iface, a);
+  if (s.n_iface2) hipLaunchKernelGGL((k_iface<-1, 2>), dim3(s.n_iface2), dim3(64), 0, st, s.iface + s.n_iface1, a);
   if (s.n_hr) {
     hipLaunchKernelGGL(k_house_w, dim3(s.n_hr), dim3(AW), 0, st, s.house, s.hr, a);
     hipLaunchKernelGGL(k_house_t<-1>, dim3(s.n_hr), dim3(AW), 0, st, s.house, s.hr, a);
@@ -450,17 +592,30 @@ void apply_step_backward(const StepDev& s, const ApplyArgs& a, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------- PCG vector kernels
-__global__ void k_spmv(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
-                       const double* __restrict__ val, int64_t n, int nrhs, const double* __restrict__ x,
-                       double* __restrict__ y) {
+// y = A x for up to RB right-hand sides at a time: one row per thread, its entries
+// read once per block of right-hand sides.
+__global__ void __launch_bounds__(256) k_spmv(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+                                              const double* __restrict__ val, int64_t n, int nrhs,
+                                              const double* __restrict__ x, double* __restrict__ y) {
   const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (v >= n) return;
   const int64_t b = rowptr[v], e = rowptr[v + 1];
-  for (int c = 0; c < nrhs; ++c) {
-    const double* xc = x + (int64_t)c * n;
-    double s = 0.0;
-    for (int64_t q = b; q < e; ++q) s += val[q] * xc[colind[q]];
-    y[v + (int64_t)c * n] = s;
+  for (int c0 = 0; c0 < nrhs; c0 += RB) {
+    const int nr = min(RB, nrhs - c0);
+    const double* xc = x + (int64_t)c0 * n;
+    double s[RB];
+#pragma unroll
+    for (int c = 0; c < RB; ++c) s[c] = 0.0;
+    for (int64_t q = b; q < e; ++q) {
+      const double a = val[q];
+      const int64_t col = colind[q];
+#pragma unroll
+      for (int c = 0; c < RB; ++c)
+        if (c < nr) s[c] = fma(a, xc[col + (int64_t)c * n], s[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < RB; ++c)
+      if (c < nr) y[v + (int64_t)(c0 + c) * n] = s[c];
   }
 }
 

@@ -40,6 +40,9 @@ StepDev step_dev(const StepNum& s) {
   d.hv = s.d_hv.as<HouseTile>();
   d.n_hr = s.n_hr;
   d.n_hv = s.n_hv;
+  d.iface = s.d_iface.as<IfaceAp>();
+  d.n_iface1 = s.n_iface1;
+  d.n_iface2 = s.n_iface2;
   d.slot = s.d_slot.as<int32_t>();
   d.nslot = s.d_nslot.as<int32_t>();
   d.nslot_len = s.nslot_len;
