@@ -11,14 +11,16 @@ struct ElimAp {
   const double* L;     // ns x ns lower-triangular factor L_s (top of the panel), ld ld
   const double* G;     // nN x ns, A_{N_s s} L_s^{-T} (below L_s in the panel), ld ld
   const double* Dinv;  // inverses of the diagonal blocks of L_s (CHOL_NB^2 doubles each)
-  int32_t ld, ns, nN, pad;
+  int32_t ld, ns, nN;
+  int32_t nchunk;      // row chunks of G in the backward product (their partial sums follow t in the scratch)
   int64_t slot_s;      // offset of s's slots in the step slot array
   int64_t slot_N;      // offset of s's neighbour slots in the step neighbour-slot array
-  int64_t tmp;         // offset of s's rows in the apply scratch
+  int64_t tmp;         // offset of s's rows in the apply scratch: t, then nchunk > 1 partial sums
 };
-struct ElimTile {     // columns [k0, min(k0 + 64, ns)) of eliminated cluster s
-  int32_t s, k0;
+struct ElimTile {     // columns [k0, min(k0 + 64, ns)) of eliminated cluster s, rows of G in chunk c
+  int32_t s, k0, c, pad;
 };
+#define ELIM_RC 512  // rows of G per chunk of the backward product
 struct TargetAp {     // rows [r0, min(r0 + 64, nn)) of receiving cluster n
   int32_t nn, cbeg, cend, r0;
   int64_t slot_n;

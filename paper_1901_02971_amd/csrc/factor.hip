@@ -316,14 +316,16 @@ spand_status build_apply(spand_ctx* h, const SymStep& sy, StepNum& sn, const Lay
       const int32_t nb = sy.enb[q];
       nslot.insert(nslot.end(), sn.slot.begin() + sn.slot_ptr[nb], sn.slot.begin() + sn.slot_ptr[nb + 1]);
     }
+    e.nchunk = std::max(1, (e.nN + ELIM_RC - 1) / ELIM_RC);
     e.tmp = tmp;
-    tmp += std::max(e.ns, 1);
+    tmp += int64_t(std::max(e.ns, 1)) * (e.nchunk > 1 ? 1 + e.nchunk : 1);
     sn.h_elim.push_back(e);
   }
   sn.tmp_elim = tmp;
   sn.h_etile.clear();
   for (int32_t s = 0; s < ne; ++s)
-    for (int32_t k0 = 0; k0 < sn.h_elim[s].ns; k0 += 64) sn.h_etile.push_back(ElimTile{s, k0});
+    for (int32_t c = 0; c < sn.h_elim[s].nchunk; ++c)
+      for (int32_t k0 = 0; k0 < sn.h_elim[s].ns; k0 += 64) sn.h_etile.push_back(ElimTile{s, k0, c, 0});
   // forward target updates, grouped by receiving cluster in ascending s
   struct TI { int32_t n, s; int64_t row; };
   std::vector<TI> tis;

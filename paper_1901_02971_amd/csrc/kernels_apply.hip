@@ -245,26 +245,80 @@ __global__ void __launch_bounds__(AW) k_elim_fwd(const ElimAp* __restrict__ ds, 
   scatter_seg(sl, e.ns, a, e.tmp);
 }
 
+// Non-transposed product without staging the matrix: acc[c] += sum_k A[(r0 + rr) +
+// k ld] x[k][c] over this thread's columns.  Thread (rr = t & 63, ks = t >> 6): wave
+// ks reads columns ks * 16 .. ks * 16 + 15 of every 64-column tile straight into
+// registers (lanes down a column), the 64 x RB tile of x is staged in LDS and read
+// as a broadcast.  The four waves' partial sums are combined by the caller.
+struct DirectShared {
+  double x[64][RB];
+  double red[3][64][RB];
+};
+__device__ void gemv_n_direct(const double* __restrict__ A, int ld, int r0, int nrows, int ncols,
+                              const double* __restrict__ x, int64_t ldx, int nr, DirectShared& sh, double (&acc)[RB]) {
+  const int rr = threadIdx.x & 63, ks = threadIdx.x >> 6;
+  const bool rowok = r0 + rr < nrows;
+  for (int k0 = 0; k0 < ncols; k0 += 64) {
+    double a[16];
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const int k = k0 + ks * 16 + kk;
+      a[kk] = (rowok && k < ncols) ? gld(A + (r0 + rr) + (int64_t)k * ld) : 0.0;
+    }
+    __syncthreads();  // the previous tile's x has been read
+#pragma unroll
+    for (int u = 0; u < 64 * RB / AW; ++u) {
+      const int e = threadIdx.x + u * AW;
+      const int k = e & 63, c = e >> 6;
+      sh.x[k][c] = (k0 + k < ncols && c < nr) ? gld(x + (k0 + k) + (int64_t)c * ldx) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const double* xk = sh.x[ks * 16 + kk];
+#pragma unroll
+      for (int c = 0; c < RB; ++c) acc[c] = fma(a[kk], xk[c], acc[c]);
+    }
+  }
+}
+// Sum of the four waves' partial sums: wave 0 returns the total of row rr.
+__device__ inline void direct_reduce(DirectShared& sh, double (&acc)[RB]) {
+  const int rr = threadIdx.x & 63, ks = threadIdx.x >> 6;
+  __syncthreads();
+  if (ks > 0)
+#pragma unroll
+    for (int c = 0; c < RB; ++c) sh.red[ks - 1][rr][c] = acc[c];
+  __syncthreads();
+  if (ks == 0)
+#pragma unroll
+    for (int c = 0; c < RB; ++c) acc[c] += sh.red[0][rr][c] + sh.red[1][rr][c] + sh.red[2][rr][c];
+}
+
 // x_n -= sum_s G_ns y_s over the contributions of n in ascending s
 __global__ void __launch_bounds__(AW) k_target_fwd(const TargetAp* __restrict__ ts, const TargetContrib* __restrict__ cs,
                                                    ApplyArgs a) {
-  __shared__ TileShared sh;
+  __shared__ DirectShared sh;
   const TargetAp t = ts[blockIdx.x];
   const int32_t* sl = a.slot + t.slot_n;
-  const int rr = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int rr = threadIdx.x & 63, ks = threadIdx.x >> 6;
   const int r0 = t.r0;
   for (int c0 = 0; c0 < a.nrhs; c0 += RB) {
     const int nr = min(RB, a.nrhs - c0);
-    double acc[2] = {0.0, 0.0};
+    double acc[RB];
+#pragma unroll
+    for (int c = 0; c < RB; ++c) acc[c] = 0.0;
     for (int q = t.cbeg; q < t.cend; ++q) {
       const TargetContrib tc = cs[q];
-      tile_gemv_n(tc.G, tc.ldG, r0, t.nn, tc.ns, a.tmp + tc.tmp_s + (int64_t)c0 * a.ldt, a.ldt, nr, sh, acc);
+      gemv_n_direct(tc.G, tc.ldG, r0, t.nn, tc.ns, a.tmp + tc.tmp_s + (int64_t)c0 * a.ldt, a.ldt, nr, sh, acc);
     }
-    if (r0 + rr < t.nn) {
+    direct_reduce(sh, acc);
+    if (ks == 0 && r0 + rr < t.nn) {
       double* xp = a.x + sl[r0 + rr] + (int64_t)c0 * a.ldx;
-      if (g < nr) xp[(int64_t)g * a.ldx] -= acc[0];
-      if (g + 4 < nr) xp[(int64_t)(g + 4) * a.ldx] -= acc[1];
+#pragma unroll
+      for (int c = 0; c < RB; ++c)
+        if (c < nr) xp[(int64_t)c * a.ldx] -= acc[c];
     }
+    __syncthreads();  // sh is reused by the next block of right-hand sides
   }
 }
 
@@ -520,25 +574,34 @@ __global__ void k_gather(const int32_t* __restrict__ nslot, int64_t len, ApplyAr
 }
 
 // t = x_s - G_{N_s s}^T x_{N_s} for the 64 columns [k0, k0 + 64) of s: one
-// workgroup per column tile, t into the apply scratch of s
+// workgroup per column tile and chunk of ELIM_RC rows of G.  With one chunk t goes
+// straight into the apply scratch of s; with several, each chunk stores its partial
+// sum after t and k_elim_bwd forms t from them in chunk order.
 __global__ void __launch_bounds__(AW) k_elim_bwd_gemv(const ElimAp* __restrict__ ds, const ElimTile* __restrict__ tl,
                                                       ApplyArgs a) {
   __shared__ TileShared sh;
   const ElimTile et = tl[blockIdx.x];
   const ElimAp e = ds[et.s];
   const int ns = e.ns, k0 = et.k0;
+  const int i0 = et.c * ELIM_RC, i1 = min(e.nN, i0 + ELIM_RC);
   const int32_t* sl = a.slot + e.slot_s;
   const int cc = threadIdx.x & 63, g = threadIdx.x >> 6;
   for (int c0 = 0; c0 < a.nrhs; c0 += RB) {
     const int nr = min(RB, a.nrhs - c0);
     double acc[2] = {0.0, 0.0};
-    tile_gemv_t(e.G, e.ld, k0, ns, e.nN, a.gbuf + e.slot_N + (int64_t)c0 * a.ldg, a.ldg, nr, sh, acc);
+    tile_gemv_t(e.G + i0, e.ld, k0, ns, i1 - i0, a.gbuf + e.slot_N + i0 + (int64_t)c0 * a.ldg, a.ldg, nr, sh, acc);
     const int k = k0 + cc;
     if (k < ns) {
-      if (g < nr)
-        a.tmp[e.tmp + k + (int64_t)(c0 + g) * a.ldt] = a.x[sl[k] + (int64_t)(c0 + g) * a.ldx] - acc[0];
-      if (g + 4 < nr)
-        a.tmp[e.tmp + k + (int64_t)(c0 + g + 4) * a.ldt] = a.x[sl[k] + (int64_t)(c0 + g + 4) * a.ldx] - acc[1];
+      if (e.nchunk == 1) {
+        if (g < nr)
+          a.tmp[e.tmp + k + (int64_t)(c0 + g) * a.ldt] = a.x[sl[k] + (int64_t)(c0 + g) * a.ldx] - acc[0];
+        if (g + 4 < nr)
+          a.tmp[e.tmp + k + (int64_t)(c0 + g + 4) * a.ldt] = a.x[sl[k] + (int64_t)(c0 + g + 4) * a.ldx] - acc[1];
+      } else {
+        const int64_t pofs = e.tmp + (int64_t)ns * (1 + et.c) + k;
+        if (g < nr) a.tmp[pofs + (int64_t)(c0 + g) * a.ldt] = acc[0];
+        if (g + 4 < nr) a.tmp[pofs + (int64_t)(c0 + g + 4) * a.ldt] = acc[1];
+      }
     }
   }
 }
@@ -548,6 +611,16 @@ __global__ void __launch_bounds__(AW) k_elim_bwd(const ElimAp* __restrict__ ds, 
   __shared__ TileShared sh;
   const ElimAp e = ds[blockIdx.x];
   const int32_t* sl = a.slot + e.slot_s;
+  if (e.nchunk > 1) {  // t = x_s - sum of the chunk partial sums, in chunk order
+    for (int c = 0; c < a.nrhs; ++c)
+      for (int k = threadIdx.x; k < e.ns; k += AW) {
+        double v = a.x[sl[k] + (int64_t)c * a.ldx];
+        for (int q = 0; q < e.nchunk; ++q) v -= a.tmp[e.tmp + (int64_t)e.ns * (1 + q) + k + (int64_t)c * a.ldt];
+        a.tmp[e.tmp + k + (int64_t)c * a.ldt] = v;
+      }
+    __threadfence_block();
+    __syncthreads();
+  }
   for (int c0 = 0; c0 < a.nrhs; c0 += RB)
     trsv_bwd(e.L, e.ld, e.Dinv, e.ns, a.tmp + e.tmp + (int64_t)c0 * a.ldt, a.ldt, min(RB, a.nrhs - c0), sh);
   scatter_seg(sl, e.ns, a, e.tmp);
