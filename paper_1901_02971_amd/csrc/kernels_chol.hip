@@ -23,17 +23,22 @@ namespace spand {
 
 #define PW 256
 
+// One diagonal block per workgroup.  Cholesky column by column in LDS: thread t
+// updates column j = t % 64 of rows t / 64, t / 64 + 4, ... (no index division);
+// then lane c of wave 0 forms column c of L^{-1} by forward substitution, entirely
+// in registers (the rows of L are broadcast from LDS).
 __global__ void __launch_bounds__(PW) k_potrf_diag(const PotrfDesc* __restrict__ descs, int32_t* fail) {
   const PotrfDesc d = descs[blockIdx.x];
   const int w = d.w;
   __shared__ double D[CHOL_NB][CHOL_NB + 1];
-  __shared__ double X[CHOL_NB][CHOL_NB + 1];
   __shared__ int bad;
   const int tid = threadIdx.x;
+  const int jc = tid & 63, i0 = tid >> 6;  // column and first row of this thread's share
   if (tid == 0) bad = 0;
-  for (int e = tid; e < w * w; e += PW) {
-    const int r = e % w, c = e / w;
-    D[r][c] = (r >= c) ? d.P[r + (int64_t)c * d.ld] : 0.0;
+#pragma unroll
+  for (int s = 0; s < CHOL_NB / 4; ++s) {
+    const int r = i0 + 4 * s;
+    D[r][jc] = (r < w && jc < w && r >= jc) ? d.P[r + (int64_t)jc * d.ld] : 0.0;
   }
   __syncthreads();
   for (int k = 0; k < w; ++k) {
@@ -43,30 +48,42 @@ __global__ void __launch_bounds__(PW) k_potrf_diag(const PotrfDesc* __restrict__
       if (tid == 0) bad = 1;
     }
     const double rk = sqrt(piv);
+    __syncthreads();  // every thread has read D[k][k]
+    if (tid < 64) {
+      if (tid == k) D[k][k] = rk;
+      if (tid > k && tid < w) D[tid][k] /= rk;
+    }
     __syncthreads();
-    if (tid == 0) D[k][k] = rk;
-    for (int i = k + 1 + tid; i < w; i += PW) D[i][k] /= rk;
-    __syncthreads();
-    const int m = w - k - 1;
-    for (int e = tid; e < m * m; e += PW) {
-      const int i = k + 1 + e % m, j = k + 1 + e / m;
-      if (i >= j) D[i][j] -= D[i][k] * D[j][k];
+    if (jc > k && jc < w) {
+      const double ljk = D[jc][k];
+#pragma unroll
+      for (int s = 0; s < CHOL_NB / 4; ++s) {
+        const int r = i0 + 4 * s;
+        if (r >= jc && r < w) D[r][jc] -= D[r][k] * ljk;
+      }
     }
     __syncthreads();
   }
-  // X = L^{-1}, row by row: X[i][c] = (delta_ic - sum_{c<=q<i} L[i][q] X[q][c]) / L[i][i]
-  for (int i = 0; i < w; ++i) {
-    for (int c = tid; c < w; c += PW) {
-      double acc = (c == i) ? 1.0 : 0.0;
-      for (int q = c; q < i; ++q) acc -= D[i][q] * X[q][c];
-      X[i][c] = (c <= i) ? acc / D[i][i] : 0.0;
+  // L^{-1}: column c, X[i][c] = (delta_ic - sum_{c <= q < i} L[i][q] X[q][c]) / L[i][i]
+  if (tid < 64) {
+    const int c = tid;
+    double x[CHOL_NB];
+#pragma unroll
+    for (int i = 0; i < CHOL_NB; ++i) {
+      double acc = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+      for (int q = 0; q < i; ++q) acc = fma(-D[i][q], x[q], acc);
+      x[i] = (i >= c && i < w) ? acc / D[i][i] : 0.0;
     }
-    __syncthreads();
+    if (c < w)
+#pragma unroll
+      for (int i = 0; i < CHOL_NB; ++i)
+        if (i < w) d.Dinv[i + (int64_t)c * w] = x[i];
   }
-  for (int e = tid; e < w * w; e += PW) {
-    const int r = e % w, c = e / w;
-    if (r >= c) d.P[r + (int64_t)c * d.ld] = D[r][c];
-    d.Dinv[r + (int64_t)c * w] = X[r][c];
+#pragma unroll
+  for (int s = 0; s < CHOL_NB / 4; ++s) {
+    const int r = i0 + 4 * s;
+    if (r < w && jc < w && r >= jc) d.P[r + (int64_t)jc * d.ld] = D[r][jc];
   }
   if (bad && tid == 0) atomicMin(fail, d.id);
 }
