@@ -709,7 +709,13 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
           ++r;
         }
         rd.c_end = int32_t(cds2.size());
-        rds.push_back(rd);
+        // large blocks are split into ranges of entries, one workgroup each
+        const int64_t cnt = int64_t(rd.rows) * rd.cols;
+        for (int64_t e0 = 0; e0 < cnt; e0 += REDUCE_CHUNK) {
+          rd.e0 = int32_t(e0);
+          rd.e1 = int32_t(std::min<int64_t>(cnt, e0 + REDUCE_CHUNK));
+          rds.push_back(rd);
+        }
         q = r;
       }
       DevBuf drd, dcd;

@@ -58,7 +58,9 @@ struct ReduceDesc {
   double* T;          // target block, ld ldT
   int32_t ldT, rows, cols, diag;  // diag: target is a diagonal (square) block
   int32_t c_begin, c_end;         // contributions [c_begin, c_end) in ascending s
+  int32_t e0, e1;                 // entries [e0, e1) of the block (column-major index) for this workgroup
 };
+#define REDUCE_CHUNK 16384  // block entries per workgroup of the Schur reduction
 struct ContribDesc {
   const double* C;  // contribution block start inside C_s, ld ldC
   int32_t ldC, pad;

@@ -1,7 +1,8 @@
 // Dense batched kernels of the factorization (gfx950, wave64).
 //
 //  * k_reduce     deterministic Schur-complement accumulation: every target block
-//                 subtracts its contributions in ascending eliminated-cluster order.
+//                 subtracts its contributions in ascending eliminated-cluster order
+//                 (one workgroup per range of at most REDUCE_CHUNK entries).
 //  * k_copy       strided (optionally transposed) block copies for the merge (Sec. 2.7).
 #include <hip/hip_runtime.h>
 
@@ -83,8 +84,8 @@ void launch_scatter_values(const double* vals, const int64_t* dst, int64_t nnz, 
 __global__ void __launch_bounds__(WG) k_reduce(const ReduceDesc* __restrict__ descs,
                                                const ContribDesc* __restrict__ cs) {
   const ReduceDesc d = descs[blockIdx.x];
-  const uint32_t rows = (uint32_t)d.rows, cnt = rows * (uint32_t)d.cols;
-  for (uint32_t e = threadIdx.x; e < cnt; e += WG) {
+  const uint32_t rows = (uint32_t)d.rows;
+  for (uint32_t e = (uint32_t)d.e0 + threadIdx.x; e < (uint32_t)d.e1; e += WG) {
     const uint32_t c = e / rows, r = e - c * rows;
     if (d.diag && r < c) continue;
     double sum = 0.0;
