@@ -166,6 +166,12 @@ struct Front {
   int32_t ld, n, m, id;
 };
 
+// I_n into the n x n block D (ld ld), in column ranges of at most COPY_CHUNK entries
+void add_identity(std::vector<IdentDesc>& v, double* D, int32_t n, int32_t ld) {
+  const int32_t step = std::max(1, COPY_CHUNK / std::max(n, 1));
+  for (int32_t c0 = 0; c0 < n; c0 += step) v.push_back(IdentDesc{D, n, ld, c0, std::min(n, c0 + step)});
+}
+
 int64_t dinv_size(int32_t n) { return int64_t((n + CHOL_NB - 1) / CHOL_NB) * CHOL_NB * CHOL_NB; }
 
 // Right-looking blocked Cholesky of every front in lockstep over its diagonal
@@ -614,11 +620,14 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
                 cd.lds = int32_t(lay_prev.H[lo]);
                 cd.trans = (i < j) ? 1 : 0;
                 cd.rows = ri;
-                cd.cols = rj;
                 cd.dst = dbase + ro + co * lay.H[J];
                 cd.ldd = int32_t(lay.H[J]);
-                cd.pad = 0;
-                copies.push_back(cd);
+                const int32_t step = std::max(1, COPY_CHUNK / ri);  // column ranges of at most COPY_CHUNK entries
+                for (int32_t c0 = 0; c0 < rj; c0 += step) {
+                  cd.c0 = c0;
+                  cd.c1 = std::min(rj, c0 + step);
+                  copies.push_back(cd);
+                }
               }
             }
             co += rj;
@@ -757,13 +766,10 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       // L_p^{-1} for the apply (the identity solved against L_p), and L_i^{-1} from the
       // left on every block (i, p), in one blocked left solve
       std::vector<LeftBlock> lb;
-      std::vector<double*> iptr;
-      std::vector<int32_t> in_, ild;
+      std::vector<IdentDesc> ids;
       for (int32_t p = ne; p < nc; ++p) {
         if (sn.size[p] == 0) continue;
-        iptr.push_back(SC + sc_off[p]);
-        in_.push_back(sn.size[p]);
-        ild.push_back(sn.size[p]);
+        add_identity(ids, SC + sc_off[p], sn.size[p], sn.size[p]);
         lb.push_back(LeftBlock{SC + sc_off[p], A + lay.base[p], SD + sd_off[p], sn.size[p], int32_t(lay.H[p]),
                                sn.size[p], sn.size[p]});
         for (int64_t e = lay.pan_ptr[p] + 1; e < lay.pan_ptr[p + 1]; ++e) {
@@ -774,27 +780,18 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
         }
       }
       {
-        DevBuf d1, d2, d3;
-        if ((st = upload(h, d1, iptr)) != SPAND_OK) return st;
-        if ((st = upload(h, d2, in_)) != SPAND_OK) return st;
-        if ((st = upload(h, d3, ild)) != SPAND_OK) return st;
-        launch_set_identity(d1.as<double*>(), d2.as<int32_t>(), d3.as<int32_t>(), int32_t(iptr.size()), h->stream);
+        DevBuf d1;
+        if ((st = upload(h, d1, ids)) != SPAND_OK) return st;
+        launch_set_identity(d1.as<IdentDesc>(), int32_t(ids.size()), h->stream);
         HIPCHK(hipGetLastError());
         if ((st = left_trsm(h, lb)) != SPAND_OK) return st;
       }
-      std::vector<double*> dptr;
-      std::vector<int32_t> dn, dld;
+      std::vector<IdentDesc> did;
       for (int32_t p = ne; p < nc; ++p)
-        if (sn.size[p] > 0) {
-          dptr.push_back(A + lay.base[p]);
-          dn.push_back(sn.size[p]);
-          dld.push_back(int32_t(lay.H[p]));
-        }
-      DevBuf d1, d2, d3;
-      if ((st = upload(h, d1, dptr)) != SPAND_OK) return st;
-      if ((st = upload(h, d2, dn)) != SPAND_OK) return st;
-      if ((st = upload(h, d3, dld)) != SPAND_OK) return st;
-      launch_set_identity(d1.as<double*>(), d2.as<int32_t>(), d3.as<int32_t>(), int32_t(dptr.size()), h->stream);
+        if (sn.size[p] > 0) add_identity(did, A + lay.base[p], sn.size[p], int32_t(lay.H[p]));
+      DevBuf d1;
+      if ((st = upload(h, d1, did)) != SPAND_OK) return st;
+      launch_set_identity(d1.as<IdentDesc>(), int32_t(did.size()), h->stream);
       HIPCHK(hipGetLastError());
       HIPCHK(hipEventRecord(ph[3], h->stream));
 

@@ -67,11 +67,17 @@ struct ContribDesc {
 };
 
 // Strided copy (optionally transposed) used by merge and assembly.
-struct CopyDesc {
+struct CopyDesc {      // columns [c0, c1) of a rows-row block (or of its transpose when trans)
   const double* src;
   double* dst;
-  int32_t lds, ldd, rows, cols, trans, pad;
+  int32_t lds, ldd, rows, c0, c1, trans;
 };
+// I_n into columns [c0, c1) of the n x n block D (ld ld)
+struct IdentDesc {
+  double* D;
+  int32_t n, ld, c0, c1;
+};
+#define COPY_CHUNK 16384  // entries per workgroup of the copies and identity fills
 
 // Sparsification of one interface p (Sec. 2.6.1).  A_pn is held in the registers of
 // S workgroups (slabs) of CAP = cpqr_capacity(G) columns each.  The width of A_pn is
@@ -105,7 +111,7 @@ void launch_expand_tiles(const GemmDesc* d, int32_t nd, int32_t* tile_desc, hipS
 void launch_gemm(const GemmDesc* d, const int32_t* tile_desc, int64_t tile0, int64_t ntiles, int prec, hipStream_t s);
 void launch_reduce(const ReduceDesc* d, int32_t count, const ContribDesc* c, hipStream_t s);
 void launch_copy(const CopyDesc* d, int64_t count, hipStream_t s);
-void launch_set_identity(double* const* diag, const int32_t* n, const int32_t* ld, int32_t count, hipStream_t s);
+void launch_set_identity(const IdentDesc* d, int32_t count, hipStream_t s);
 // cursize: current size of every cluster of the step; the kernel sets
 // cursize[p] = kept rank when it finishes p and nref[p] = number of reflectors
 // stored (0 when no coupled dofs were left and p was not sparsified).  err

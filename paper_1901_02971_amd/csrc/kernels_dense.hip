@@ -103,13 +103,17 @@ void launch_reduce(const ReduceDesc* d, int32_t count, const ContribDesc* c, hip
 }
 
 // ---------------------------------------------------------------- copies
+// One workgroup per column range of a block.  Thread t takes row t % h of column
+// c0 + t / h, h = min(rows, WG), and steps by WG / h columns (one division per
+// thread, none per entry).
 __global__ void __launch_bounds__(WG) k_copy(const CopyDesc* __restrict__ descs) {
   const CopyDesc d = descs[blockIdx.x];
-  const int64_t cnt = (int64_t)d.rows * d.cols;
-  for (int64_t e = threadIdx.x; e < cnt; e += WG) {
-    const int r = (int)(e % d.rows), c = (int)(e / d.rows);
-    d.dst[r + (int64_t)c * d.ldd] = d.trans ? d.src[c + (int64_t)r * d.lds] : d.src[r + (int64_t)c * d.lds];
-  }
+  const int h = min(d.rows, WG), cs = WG / h;
+  const int r0 = threadIdx.x % h, dc = threadIdx.x / h;
+  if (dc >= cs) return;
+  for (int c = d.c0 + dc; c < d.c1; c += cs)
+    for (int r = r0; r < d.rows; r += h)
+      d.dst[r + (int64_t)c * d.ldd] = d.trans ? d.src[c + (int64_t)r * d.lds] : d.src[r + (int64_t)c * d.lds];
 }
 
 void launch_copy(const CopyDesc* d, int64_t count, hipStream_t s) {
@@ -117,18 +121,18 @@ void launch_copy(const CopyDesc* d, int64_t count, hipStream_t s) {
   hipLaunchKernelGGL(k_copy, dim3(count), dim3(WG), 0, s, d);
 }
 
-__global__ void k_set_identity(double* const* diag, const int32_t* n, const int32_t* ld) {
-  double* D = diag[blockIdx.x];
-  const int m = n[blockIdx.x], l = ld[blockIdx.x];
-  for (int64_t e = threadIdx.x; e < (int64_t)m * m; e += blockDim.x) {
-    const int r = (int)(e % m), c = (int)(e / m);
-    D[r + (int64_t)c * l] = (r == c) ? 1.0 : 0.0;
-  }
+__global__ void __launch_bounds__(WG) k_set_identity(const IdentDesc* __restrict__ descs) {
+  const IdentDesc d = descs[blockIdx.x];
+  const int h = min(d.n, WG), cs = WG / h;
+  const int r0 = threadIdx.x % h, dc = threadIdx.x / h;
+  if (dc >= cs) return;
+  for (int c = d.c0 + dc; c < d.c1; c += cs)
+    for (int r = r0; r < d.n; r += h) d.D[r + (int64_t)c * d.ld] = (r == c) ? 1.0 : 0.0;
 }
 
-void launch_set_identity(double* const* diag, const int32_t* n, const int32_t* ld, int32_t count, hipStream_t s) {
+void launch_set_identity(const IdentDesc* d, int32_t count, hipStream_t s) {
   if (count == 0) return;
-  hipLaunchKernelGGL(k_set_identity, dim3(count), dim3(WG), 0, s, diag, n, ld);
+  hipLaunchKernelGGL(k_set_identity, dim3(count), dim3(WG), 0, s, d);
 }
 
 }  // namespace spand
