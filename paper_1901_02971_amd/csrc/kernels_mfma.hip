@@ -89,13 +89,15 @@ __device__ inline void tile_coords(const GemmDesc& d, int64_t local, int& tm, in
 
 }  // namespace
 
-// MODE 0 / 1: K staged 16 at a time, four k=4 MFMA steps per stage.
+// MODE 0 / 1: K staged 32 at a time (the next stage read into registers while the
+// current one is multiplied), eight k=4 MFMA steps per stage.
 template <int MODE>
 __global__ void __launch_bounds__(MW) k_gemm_mfma(const GemmDesc* __restrict__ descs,
                                                   const int32_t* __restrict__ tile_desc, int64_t tile0) {
   typedef typename std::conditional<MODE == 0, double, float>::type T;
   typedef typename std::conditional<MODE == 0, d4_t, f4_t>::type C4;
-  constexpr int BK = 16;
+  constexpr int BK = 32;
+  constexpr int PER = 64 * BK / MW;  // operand entries per thread and stage
   __shared__ T As[BK][64 + 1];
   __shared__ T Bs[BK][64 + 1];
   const int64_t tile = tile0 + blockIdx.x;
@@ -114,17 +116,32 @@ __global__ void __launch_bounds__(MW) k_gemm_mfma(const GemmDesc* __restrict__ d
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = C4{0, 0, 0, 0};
   const bool ta = d.flags & G_TA, tb = d.flags & G_TB;
+  // the next stage is read into registers while the current one is multiplied
+  T ra[PER], rb[PER];
+  auto load_stage = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int q = threadIdx.x + u * MW;
+      int mm, kk, nn, kb;
+      tile_index(ta, q, BK, mm, kk);
+      tile_index(!tb, q, BK, nn, kb);
+      ra[u] = (T)load_a(d, m0 + mm, k0 + kk, kmax);
+      rb[u] = (T)load_b(d, k0 + kb, n0 + nn, kmax);
+    }
+  };
+  if (kmax > 0) load_stage(0);
   for (int k0 = 0; k0 < kmax; k0 += BK) {
 #pragma unroll
-    for (int q = threadIdx.x; q < 64 * BK; q += MW) {
-      int mm, kk;
+    for (int u = 0; u < PER; ++u) {
+      const int q = threadIdx.x + u * MW;
+      int mm, kk, nn, kb;
       tile_index(ta, q, BK, mm, kk);
-      As[kk][mm] = (T)load_a(d, m0 + mm, k0 + kk, kmax);
-      int nn, kb;
       tile_index(!tb, q, BK, nn, kb);
-      Bs[kb][nn] = (T)load_b(d, k0 + kb, n0 + nn, kmax);
+      As[kk][mm] = ra[u];
+      Bs[kb][nn] = rb[u];
     }
     __syncthreads();
+    if (k0 + BK < kmax) load_stage(k0 + BK);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       const int kk = ks + (lane >> 4);
