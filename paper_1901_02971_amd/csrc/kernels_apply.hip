@@ -35,122 +35,202 @@ __device__ inline double wsum(double v) {
 }
 
 // ---------------------------------------------------------------- tile GEMVs
-// Both products stage 64x64 tiles of the matrix in LDS with coalesced loads (lanes
-// run down a column) and compute from LDS.  Thread (t & 63, t >> 6) owns row or
-// column t & 63 of the tile and right-hand sides g and g + 4 (g = t >> 6); `acc`
-// accumulates across calls.  The next tile is loaded into registers while the
-// current one is used; loads go through the global address space so that waiting
-// for LDS results never waits for them.
+// The products of a 64 x 64 tile of a factor block with a 64 x RB block of
+// right-hand sides run on the FP64 matrix cores (v_mfma_f64_16x16x4f64: C 16x16 +=
+// A 16x4 B 4x16; lane l holds A[l%16][l/16] and B[l/16][l%16], and entry q of the
+// result C[l/16 + 4q][l%16]).  Wave w owns output rows (or columns) 16w..16w+15 of
+// the tile over all of k, so its sums need no combining with the other waves; the
+// RB right-hand sides fill half of the 16 B columns, the other half is zero.  Each
+// step adds its four products to the accumulator in k order, as a plain FMA loop
+// would.  The x tile is staged in LDS (double buffered, one barrier per tile) and
+// two tiles are in flight: tile t + 2 is requested into the registers that tile t
+// has just left.  Matrix entries are read with buffer loads: a 32-bit offset per
+// entry from a descriptor of the block; an entry outside the matrix gets an offset
+// past the descriptor's range and reads as zero, so no loaded value is consumed
+// before its use.  Vector entries outside x read a zero constant instead.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+static_assert(RB == 8, "the MFMA tiles fill 8 of the 16 B columns");
+__device__ const double g_zero[1] = {0.0};
+
 struct TileShared {
-  double A[64][65];
-  double x[64][RB];
-  double out[64][RB];
+  double A[64][65];     // staged tile of the transposed product
+  double x[2][64][RB];  // x tiles
+  double out[64][RB];   // results handed to the row-per-thread layout
 };
 
 typedef __attribute__((address_space(1))) const double gdouble;
 __device__ inline double gld(const double* p) { return *(gdouble*)p; }
 
-// A tile (64 x 64, rows [r0, r0 + 64) of a column-major matrix, columns [k0, k0 + 64))
-// and an x tile (64 x RB), held in registers between load and store.
-struct TileRegs {
-  double a[64 * 64 / AW];
-  double x[64 * RB / AW];
-};
-
-// x rows are x[k] or, with a slot list, x[xsl[k]]
-__device__ inline void tile_load(const double* __restrict__ A, int ld, int r0, int nrows, int k0, int ncols,
-                                 const double* __restrict__ x, int64_t ldx, int xrow0, int xrows, int nr,
-                                 const int32_t* __restrict__ xsl, TileRegs& t) {
-#pragma unroll
-  for (int u = 0; u < 64 * 64 / AW; ++u) {
-    const int e = threadIdx.x + u * AW;
-    const int r = e & 63, k = e >> 6;
-    t.a[u] = (r0 + r < nrows && k0 + k < ncols) ? gld(A + (r0 + r) + (int64_t)(k0 + k) * ld) : 0.0;
-  }
-#pragma unroll
-  for (int u = 0; u < 64 * RB / AW; ++u) {
-    const int e = threadIdx.x + u * AW;
-    const int k = e & 63, c = e >> 6;
-    const int64_t xr = (xrow0 + k < xrows) ? (xsl ? (int64_t)xsl[xrow0 + k] : (int64_t)(xrow0 + k)) : 0;
-    t.x[u] = (xrow0 + k < xrows && c < nr) ? gld(x + xr + (int64_t)c * ldx) : 0.0;
-  }
+// Descriptor of the entries [0, n) of a block (n * 8 < 2^31 bytes for the factor
+// blocks), and entry e of it, or zero when !ok.
+__device__ inline __amdgpu_buffer_rsrc_t block_rsrc(const double* A, int64_t n) {
+  const int64_t bytes = n * 8 < 0x7FFFFFF0LL ? n * 8 : 0x7FFFFFF0LL;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(A), 0, (int)bytes, 0x00020000);
+}
+__device__ inline double bld(__amdgpu_buffer_rsrc_t r, unsigned e, bool ok) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, ok ? e * 8u : 0x80000000u, 0, 0));
 }
 
-__device__ inline void tile_store(const TileRegs& t, TileShared& sh) {
+// x rows k0 + lane of the RB right-hand sides owned by this thread: x[k] or, with a
+// slot list, x[xsl[k]]
+__device__ inline void xtile_load(const double* __restrict__ x, int64_t ldx, int k0, int nk, int nr,
+                                  const int32_t* __restrict__ xsl, double (&xv)[2]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const bool kok = k0 + lane < nk;
+  const int64_t xr = kok ? (xsl ? (int64_t)xsl[k0 + lane] : (int64_t)(k0 + lane)) : 0;
 #pragma unroll
-  for (int u = 0; u < 64 * 64 / AW; ++u) {
-    const int e = threadIdx.x + u * AW;
-    sh.A[e & 63][e >> 6] = t.a[u];
-  }
-#pragma unroll
-  for (int u = 0; u < 64 * RB / AW; ++u) {
-    const int e = threadIdx.x + u * AW;
-    sh.x[e & 63][e >> 6] = t.x[u];
+  for (int u = 0; u < 2; ++u) {
+    const int c = w + 4 * u;
+    xv[u] = gld(kok && c < nr ? x + xr + (int64_t)c * ldx : g_zero);
   }
 }
+__device__ inline void xtile_store(const double (&xv)[2], double (*xs)[RB]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  xs[lane][w] = xv[0];
+  xs[lane][w + 4] = xv[1];
+}
+// 16 MFMA steps over a 64-deep k tile; av[j] is this lane's A entry of step j, the
+// B entries come from the k x RB block xs
+__device__ inline void mfma_tile(const double (&av)[16], const double (*xs)[RB], dbl4& c) {
+  const int lane = threadIdx.x & 63, i = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const double bv = xs[4 * j + kq][i & 7];
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j], i < RB ? bv : 0.0, c, 0, 0, 0);
+  }
+}
+// acc[0], acc[1] += rows (lane, w) and (lane, w + 4) of the 64 x RB result c of the waves
+__device__ inline void mfma_out(const dbl4& c, TileShared& sh, double acc[2]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, i = lane & 15, kq = lane >> 4;
+  if (i < RB) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sh.out[16 * w + kq + 4 * q][i] = c[q];
+  }
+  __syncthreads();
+  acc[0] += sh.out[lane][w];
+  acc[1] += sh.out[lane][w + 4];
+  __syncthreads();
+}
 
-// acc += A[(r0 + rr) + k*ld] x[k], k < ncols (rows beyond nrows read as zero)
+// acc += A[(r0 + rr) + k*ld] x[k], k < ncols (rows beyond nrows read as zero).  The A
+// entries go straight into registers: the 16 lanes of a step read 16 consecutive
+// rows of one column.
 __device__ void tile_gemv_n(const double* __restrict__ A, int ld, int r0, int nrows, int ncols,
                             const double* __restrict__ x, int64_t ldx, int nr, TileShared& sh, double acc[2],
                             const int32_t* __restrict__ xsl = nullptr) {
-  const int rr = threadIdx.x & 63, g = threadIdx.x >> 6;
-  TileRegs t;
-  if (ncols > 0) tile_load(A, ld, r0, nrows, 0, ncols, x, ldx, 0, ncols, nr, xsl, t);
-  for (int k0 = 0; k0 < ncols; k0 += 64) {
-    tile_store(t, sh);
-    __syncthreads();
-    if (k0 + 64 < ncols) tile_load(A, ld, r0, nrows, k0 + 64, ncols, x, ldx, k0 + 64, ncols, nr, xsl, t);
-#pragma unroll 8
-    for (int k = 0; k < 64; ++k) {
-      const double a = sh.A[rr][k];
-      acc[0] += a * sh.x[k][g];
-      acc[1] += a * sh.x[k][g + 4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, i = lane & 15, kq = lane >> 4;
+  const int row = r0 + 16 * w + i;
+  const bool rok = row < nrows;
+  const int nt = (ncols + 63) >> 6;
+  const __amdgpu_buffer_rsrc_t ar = block_rsrc(A, ncols > 0 ? (int64_t)(ncols - 1) * ld + nrows : 0);
+  dbl4 c = {0.0, 0.0, 0.0, 0.0};
+  double a0[16], a1[16], x0[2], x1[2];
+  auto load = [&](int t, double (&a)[16], double (&xv)[2]) {
+    const int k0 = 64 * t;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int k = k0 + 4 * j + kq;
+      a[j] = bld(ar, (unsigned)row + (unsigned)k * (unsigned)ld, rok && k < ncols);
     }
+    xtile_load(x, ldx, k0, ncols, nr, xsl, xv);
+  };
+  auto use = [&](int t, const double (&a)[16], const double (&xv)[2]) {
+    xtile_store(xv, sh.x[t & 1]);
     __syncthreads();
+    mfma_tile(a, sh.x[t & 1], c);
+  };
+  if (nt > 0) load(0, a0, x0);
+  if (nt > 1) load(1, a1, x1);
+  for (int t = 0; t < nt; t += 2) {
+    use(t, a0, x0);
+    if (t + 2 < nt) load(t + 2, a0, x0);
+    if (t + 1 < nt) {
+      use(t + 1, a1, x1);
+      if (t + 3 < nt) load(t + 3, a1, x1);
+    }
   }
+  __syncthreads();  // the last x tile has been read
+  mfma_out(c, sh, acc);
 }
 
-// acc += sum_{r < nrows} A[r + (c0 + cc)*ld] x[r] for columns c0 + cc < ncols
+// acc += sum_{r < nrows} A[r + (c0 + cc)*ld] x[r] for columns c0 + cc < ncols.  The
+// tile is read with lanes down a column and staged in LDS; the MFMA steps read it
+// across columns.
 __device__ void tile_gemv_t(const double* __restrict__ A, int ld, int c0, int ncols, int nrows,
                             const double* __restrict__ x, int64_t ldx, int nr, TileShared& sh, double acc[2],
                             const int32_t* __restrict__ xsl = nullptr) {
-  const int cc = threadIdx.x & 63, g = threadIdx.x >> 6;
-  TileRegs t;
-  if (nrows > 0) tile_load(A, ld, 0, nrows, c0, ncols, x, ldx, 0, nrows, nr, xsl, t);
-  for (int r0 = 0; r0 < nrows; r0 += 64) {
-    tile_store(t, sh);
-    __syncthreads();
-    if (r0 + 64 < nrows) tile_load(A, ld, r0 + 64, nrows, c0, ncols, x, ldx, r0 + 64, nrows, nr, xsl, t);
-#pragma unroll 8
-    for (int r = 0; r < 64; ++r) {
-      const double a = sh.A[r][cc];
-      acc[0] += a * sh.x[r][g];
-      acc[1] += a * sh.x[r][g + 4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, i = lane & 15, kq = lane >> 4;
+  const int nt = (nrows + 63) >> 6;
+  const __amdgpu_buffer_rsrc_t ar = block_rsrc(A, nrows > 0 ? (int64_t)(ncols - 1) * ld + nrows : 0);
+  dbl4 c = {0.0, 0.0, 0.0, 0.0};
+  double a0[16], a1[16], x0[2], x1[2];
+  auto load = [&](int t, double (&a)[16], double (&xv)[2]) {
+    const int k0 = 64 * t;
+    const bool rok = k0 + lane < nrows;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int col = c0 + w + 4 * u;
+      a[u] = bld(ar, (unsigned)(k0 + lane) + (unsigned)col * (unsigned)ld, rok && col < ncols);
     }
+    xtile_load(x, ldx, k0, nrows, nr, xsl, xv);
+  };
+  auto use = [&](int t, const double (&a)[16], const double (&xv)[2]) {
+    __syncthreads();  // the previous tile's A has been read
+#pragma unroll
+    for (int u = 0; u < 16; ++u) sh.A[lane][w + 4 * u] = a[u];
+    xtile_store(xv, sh.x[t & 1]);
     __syncthreads();
+    double av[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) av[j] = sh.A[4 * j + kq][16 * w + i];
+    mfma_tile(av, sh.x[t & 1], c);
+  };
+  if (nt > 0) load(0, a0, x0);
+  if (nt > 1) load(1, a1, x1);
+  for (int t = 0; t < nt; t += 2) {
+    use(t, a0, x0);
+    if (t + 2 < nt) load(t + 2, a0, x0);
+    if (t + 1 < nt) {
+      use(t + 1, a1, x1);
+      if (t + 3 < nt) load(t + 3, a1, x1);
+    }
   }
+  __syncthreads();
+  mfma_out(c, sh, acc);
 }
 
 // ---------------------------------------------------------------- triangular solves
 // Blocked solves on a vector segment v (n rows, nr <= RB columns, ld ldv) in the
 // apply scratch.  L is lower triangular (ld); its CHOL_NB-wide diagonal blocks have
-// the inverses Dinv (block k at k*CHOL_NB^2, ld = block width), staged in LDS like
-// the matrix tiles.
+// the inverses Dinv (block k at k*CHOL_NB^2, ld = block width).  The product with a
+// diagonal block runs on the matrix cores like the tiles above; its entries are
+// requested before the block's off-diagonal product so that the two loads overlap.
 static_assert(CHOL_NB == 64, "tile solves assume 64-wide diagonal blocks");
 
-// sh.A <- the w x w inverse block D (ld w, zero outside), sh.x <- out (already in sh.out)
-__device__ inline void stage_dinv(const double* __restrict__ D, int w, TileShared& sh) {
-  double d[64 * 64 / AW];
+// this lane's MFMA entries of D (w x w, ld w, zero outside): D[16 wave + l%16][4 j + l/16],
+// or of D^T when TR
+template <bool TR>
+__device__ inline void load_dinv(const double* __restrict__ D, int wd, double (&d)[16]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, i = lane & 15, kq = lane >> 4;
+  const int o = 16 * w + i;
+  const __amdgpu_buffer_rsrc_t dr = block_rsrc(D, (int64_t)wd * wd);
 #pragma unroll
-  for (int u = 0; u < 64 * 64 / AW; ++u) {
-    const int e = threadIdx.x + u * AW;
-    const int r = e & 63, k = e >> 6;
-    d[u] = (r < w && k < w) ? gld(D + r + k * w) : 0.0;
+  for (int j = 0; j < 16; ++j) {
+    const int k = 4 * j + kq;
+    d[j] = bld(dr, TR ? (unsigned)(k + o * wd) : (unsigned)(o + k * wd), o < wd && k < wd);
   }
+}
+// v[kb + row] (row < wd) <- the rows of D sh.out (or D^T sh.out) held by this lane
+__device__ inline void dinv_apply(const double (&d)[16], TileShared& sh, int wd, double* v, int64_t ldv, int nr) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, i = lane & 15, kq = lane >> 4;
+  dbl4 c = {0.0, 0.0, 0.0, 0.0};
+  mfma_tile(d, sh.out, c);
+  if (i < nr) {
 #pragma unroll
-  for (int u = 0; u < 64 * 64 / AW; ++u) {
-    const int e = threadIdx.x + u * AW;
-    sh.A[e & 63][e >> 6] = d[u];
+    for (int q = 0; q < 4; ++q) {
+      const int row = 16 * w + kq + 4 * q;
+      if (row < wd) v[row + (int64_t)i * ldv] = c[q];
+    }
   }
 }
 
@@ -160,6 +240,8 @@ __device__ void trsv_fwd(const double* __restrict__ L, int ld, const double* __r
   const int rr = threadIdx.x & 63, g = threadIdx.x >> 6;
   for (int kb = 0; kb < n; kb += 64) {
     const int w = min(64, n - kb);
+    double d[16];
+    load_dinv<false>(Dinv + (int64_t)(kb / 64) * 64 * 64, w, d);
     double acc[2] = {0.0, 0.0};
     tile_gemv_n(L + kb, ld, 0, w, kb, v, ldv, nr, sh, acc);
     if (rr < w) {
@@ -169,19 +251,8 @@ __device__ void trsv_fwd(const double* __restrict__ L, int ld, const double* __r
       sh.out[rr][g] = 0.0;
       sh.out[rr][g + 4] = 0.0;
     }
-    stage_dinv(Dinv + (int64_t)(kb / 64) * 64 * 64, w, sh);
     __syncthreads();
-    if (rr < w) {
-      double y0 = 0.0, y1 = 0.0;
-#pragma unroll 8
-      for (int k = 0; k < 64; ++k) {
-        const double dv = sh.A[rr][k];
-        y0 += dv * sh.out[k][g];
-        y1 += dv * sh.out[k][g + 4];
-      }
-      if (g < nr) v[kb + rr + (int64_t)g * ldv] = y0;
-      if (g + 4 < nr) v[kb + rr + (int64_t)(g + 4) * ldv] = y1;
-    }
+    dinv_apply(d, sh, w, v + kb, ldv, nr);
     __threadfence_block();
     __syncthreads();
   }
@@ -195,6 +266,8 @@ __device__ void trsv_bwd(const double* __restrict__ L, int ld, const double* __r
   for (int bi = nblk - 1; bi >= 0; --bi) {
     const int kb = bi * 64;
     const int w = min(64, n - kb);
+    double d[16];
+    load_dinv<true>(Dinv + (int64_t)bi * 64 * 64, w, d);
     double acc[2] = {0.0, 0.0};
     tile_gemv_t(L + kb + w, ld, kb, kb + w, n - kb - w, v + kb + w, ldv, nr, sh, acc);
     if (cc < w) {
@@ -204,33 +277,60 @@ __device__ void trsv_bwd(const double* __restrict__ L, int ld, const double* __r
       sh.out[cc][g] = 0.0;
       sh.out[cc][g + 4] = 0.0;
     }
-    stage_dinv(Dinv + (int64_t)bi * 64 * 64, w, sh);
     __syncthreads();
-    if (cc < w) {
-      double x0 = 0.0, x1 = 0.0;
-#pragma unroll 8
-      for (int q = 0; q < 64; ++q) {
-        const double dv = sh.A[q][cc];
-        x0 += dv * sh.out[q][g];
-        x1 += dv * sh.out[q][g + 4];
-      }
-      if (g < nr) v[kb + cc + (int64_t)g * ldv] = x0;
-      if (g + 4 < nr) v[kb + cc + (int64_t)(g + 4) * ldv] = x1;
-    }
+    dinv_apply(d, sh, w, v + kb, ldv, nr);
     __threadfence_block();
     __syncthreads();
   }
 }
 
+// Row moves between x (through the slots) and the scratch.  The source and the
+// destination may alias as far as the compiler knows, so every load of a pass is
+// written before its stores; otherwise each load would wait for the store before it.
+#define MV_ROWS 4  // rows per thread and pass
+template <bool TO_TMP>
+__device__ inline void move_seg(const int32_t* sl, int n, const ApplyArgs& a, int64_t off) {
+  for (int rb = 0; rb < n; rb += AW * MV_ROWS) {
+    int64_t xo[MV_ROWS];
+#pragma unroll
+    for (int u = 0; u < MV_ROWS; ++u) {  // every slot load issued: rows past n read slot n - 1
+      const int r = rb + threadIdx.x + u * AW;
+      const int64_t v = sl[r < n ? r : n - 1];
+      xo[u] = r < n ? v : -1;
+    }
+    for (int c0 = 0; c0 < a.nrhs; c0 += RB) {
+      double b[MV_ROWS][RB];
+#pragma unroll
+      for (int u = 0; u < MV_ROWS; ++u) {
+        const int64_t to = off + rb + threadIdx.x + u * AW;
+#pragma unroll
+        for (int c = 0; c < RB; ++c) {
+          const bool ok = xo[u] >= 0 && c0 + c < a.nrhs;
+          b[u][c] = ok ? (TO_TMP ? a.x[xo[u] + (int64_t)(c0 + c) * a.ldx] : a.tmp[to + (int64_t)(c0 + c) * a.ldt]) : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < MV_ROWS; ++u) {
+        const int64_t to = off + rb + threadIdx.x + u * AW;
+#pragma unroll
+        for (int c = 0; c < RB; ++c)
+          if (xo[u] >= 0 && c0 + c < a.nrhs) {
+            if (TO_TMP)
+              a.tmp[to + (int64_t)(c0 + c) * a.ldt] = b[u][c];
+            else
+              a.x[xo[u] + (int64_t)(c0 + c) * a.ldx] = b[u][c];
+          }
+      }
+    }
+  }
+}
 __device__ inline void gather_seg(const int32_t* sl, int n, const ApplyArgs& a, int64_t off) {
-  for (int c = 0; c < a.nrhs; ++c)
-    for (int r = threadIdx.x; r < n; r += AW) a.tmp[off + r + (int64_t)c * a.ldt] = a.x[sl[r] + (int64_t)c * a.ldx];
+  move_seg<true>(sl, n, a, off);
   __threadfence_block();
   __syncthreads();
 }
 __device__ inline void scatter_seg(const int32_t* sl, int n, const ApplyArgs& a, int64_t off) {
-  for (int c = 0; c < a.nrhs; ++c)
-    for (int r = threadIdx.x; r < n; r += AW) a.x[sl[r] + (int64_t)c * a.ldx] = a.tmp[off + r + (int64_t)c * a.ldt];
+  move_seg<false>(sl, n, a, off);
 }
 
 // ---------------------------------------------------------------- sweep kernels
@@ -314,9 +414,12 @@ __global__ void __launch_bounds__(AW) k_target_fwd(const TargetAp* __restrict__ 
     direct_reduce(sh, acc);
     if (ks == 0 && r0 + rr < t.nn) {
       double* xp = a.x + sl[r0 + rr] + (int64_t)c0 * a.ldx;
+      double xv[RB];
+#pragma unroll
+      for (int c = 0; c < RB; ++c) xv[c] = c < nr ? xp[(int64_t)c * a.ldx] : 0.0;
 #pragma unroll
       for (int c = 0; c < RB; ++c)
-        if (c < nr) xp[(int64_t)c * a.ldx] -= acc[c];
+        if (c < nr) xp[(int64_t)c * a.ldx] = xv[c] - acc[c];
     }
     __syncthreads();  // sh is reused by the next block of right-hand sides
   }
@@ -329,7 +432,14 @@ __global__ void k_gather_rows(const int32_t* __restrict__ sg, int64_t len, Apply
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= len) return;
   const int32_t v = sg[t];
-  for (int c = 0; c < a.nrhs; ++c) a.tmp[t + (int64_t)c * a.ldt] = a.x[v + (int64_t)c * a.ldx];
+  for (int c0 = 0; c0 < a.nrhs; c0 += RB) {
+    double b[RB];
+#pragma unroll
+    for (int c = 0; c < RB; ++c) b[c] = c0 + c < a.nrhs ? a.x[v + (int64_t)(c0 + c) * a.ldx] : 0.0;
+#pragma unroll
+    for (int c = 0; c < RB; ++c)
+      if (c0 + c < a.nrhs) a.tmp[t + (int64_t)(c0 + c) * a.ldt] = b[c];
+  }
 }
 
 template <int DIR>
@@ -424,8 +534,10 @@ __global__ void __launch_bounds__(AW) k_house_v(const HouseAp* __restrict__ ds, 
     tile_gemv_n(e.V, np, r0, np, r, us + (int64_t)c0 * a.ldt, a.ldt, nr, sh, acc);
     if (r0 + rr < np) {
       double* xp = a.x + sl[r0 + rr] + (int64_t)c0 * a.ldx;
-      if (g < nr) xp[(int64_t)g * a.ldx] -= acc[0];
-      if (g + 4 < nr) xp[(int64_t)(g + 4) * a.ldx] -= acc[1];
+      const double x0 = g < nr ? xp[(int64_t)g * a.ldx] : 0.0;
+      const double x1 = g + 4 < nr ? xp[(int64_t)(g + 4) * a.ldx] : 0.0;
+      if (g < nr) xp[(int64_t)g * a.ldx] = x0 - acc[0];
+      if (g + 4 < nr) xp[(int64_t)(g + 4) * a.ldx] = x1 - acc[1];
     }
   }
 }
@@ -570,7 +682,14 @@ __global__ void k_gather(const int32_t* __restrict__ nslot, int64_t len, ApplyAr
   const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (q >= len) return;
   const int32_t s = nslot[q];
-  for (int c = 0; c < a.nrhs; ++c) a.gbuf[q + (int64_t)c * a.ldg] = a.x[s + (int64_t)c * a.ldx];
+  for (int c0 = 0; c0 < a.nrhs; c0 += RB) {
+    double b[RB];
+#pragma unroll
+    for (int c = 0; c < RB; ++c) b[c] = c0 + c < a.nrhs ? a.x[s + (int64_t)(c0 + c) * a.ldx] : 0.0;
+#pragma unroll
+    for (int c = 0; c < RB; ++c)
+      if (c0 + c < a.nrhs) a.gbuf[q + (int64_t)(c0 + c) * a.ldg] = b[c];
+  }
 }
 
 // t = x_s - G_{N_s s}^T x_{N_s} for the 64 columns [k0, k0 + 64) of s: one
@@ -593,10 +712,11 @@ __global__ void __launch_bounds__(AW) k_elim_bwd_gemv(const ElimAp* __restrict__
     const int k = k0 + cc;
     if (k < ns) {
       if (e.nchunk == 1) {
-        if (g < nr)
-          a.tmp[e.tmp + k + (int64_t)(c0 + g) * a.ldt] = a.x[sl[k] + (int64_t)(c0 + g) * a.ldx] - acc[0];
-        if (g + 4 < nr)
-          a.tmp[e.tmp + k + (int64_t)(c0 + g + 4) * a.ldt] = a.x[sl[k] + (int64_t)(c0 + g + 4) * a.ldx] - acc[1];
+        const int64_t xo = sl[k];
+        const double x0 = g < nr ? a.x[xo + (int64_t)(c0 + g) * a.ldx] : 0.0;
+        const double x1 = g + 4 < nr ? a.x[xo + (int64_t)(c0 + g + 4) * a.ldx] : 0.0;
+        if (g < nr) a.tmp[e.tmp + k + (int64_t)(c0 + g) * a.ldt] = x0 - acc[0];
+        if (g + 4 < nr) a.tmp[e.tmp + k + (int64_t)(c0 + g + 4) * a.ldt] = x1 - acc[1];
       } else {
         const int64_t pofs = e.tmp + (int64_t)ns * (1 + et.c) + k;
         if (g < nr) a.tmp[pofs + (int64_t)(c0 + g) * a.ldt] = acc[0];
@@ -612,12 +732,23 @@ __global__ void __launch_bounds__(AW) k_elim_bwd(const ElimAp* __restrict__ ds, 
   const ElimAp e = ds[blockIdx.x];
   const int32_t* sl = a.slot + e.slot_s;
   if (e.nchunk > 1) {  // t = x_s - sum of the chunk partial sums, in chunk order
-    for (int c = 0; c < a.nrhs; ++c)
-      for (int k = threadIdx.x; k < e.ns; k += AW) {
-        double v = a.x[sl[k] + (int64_t)c * a.ldx];
-        for (int q = 0; q < e.nchunk; ++q) v -= a.tmp[e.tmp + (int64_t)e.ns * (1 + q) + k + (int64_t)c * a.ldt];
-        a.tmp[e.tmp + k + (int64_t)c * a.ldt] = v;
+    for (int k = threadIdx.x; k < e.ns; k += AW) {
+      const int64_t xo = sl[k];
+      for (int c0 = 0; c0 < a.nrhs; c0 += RB) {
+        double v[RB];
+#pragma unroll
+        for (int c = 0; c < RB; ++c) v[c] = c0 + c < a.nrhs ? a.x[xo + (int64_t)(c0 + c) * a.ldx] : 0.0;
+        for (int q = 0; q < e.nchunk; ++q) {
+          const double* pq = a.tmp + e.tmp + (int64_t)e.ns * (1 + q) + k;
+#pragma unroll
+          for (int c = 0; c < RB; ++c)
+            if (c0 + c < a.nrhs) v[c] -= pq[(int64_t)(c0 + c) * a.ldt];
+        }
+#pragma unroll
+        for (int c = 0; c < RB; ++c)
+          if (c0 + c < a.nrhs) a.tmp[e.tmp + k + (int64_t)(c0 + c) * a.ldt] = v[c];
       }
+    }
     __threadfence_block();
     __syncthreads();
   }
