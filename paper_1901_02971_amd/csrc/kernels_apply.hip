@@ -112,18 +112,18 @@ __device__ inline void mfma_out(const dbl4& c, TileShared& sh, double acc[2]) {
   __syncthreads();
 }
 
-// acc += A[(r0 + rr) + k*ld] x[k], k < ncols (rows beyond nrows read as zero).  The A
-// entries go straight into registers: the 16 lanes of a step read 16 consecutive
-// rows of one column.
-__device__ void tile_gemv_n(const double* __restrict__ A, int ld, int r0, int nrows, int ncols,
-                            const double* __restrict__ x, int64_t ldx, int nr, TileShared& sh, double acc[2],
-                            const int32_t* __restrict__ xsl = nullptr) {
+// c += A[r0 + 16 wave + .., k] x[k], k < ncols (rows beyond nrows read as zero), in
+// the MFMA layout.  The A entries go straight into registers: the 16 lanes of a step
+// read 16 consecutive rows of one column.  tpar counts the x tiles staged so far, so
+// that consecutive calls keep alternating the two x buffers.
+__device__ void mfma_n_acc(const double* __restrict__ A, int ld, int r0, int nrows, int ncols,
+                           const double* __restrict__ x, int64_t ldx, int nr, TileShared& sh, dbl4& c, int& tpar,
+                           const int32_t* __restrict__ xsl = nullptr) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, i = lane & 15, kq = lane >> 4;
   const int row = r0 + 16 * w + i;
   const bool rok = row < nrows;
   const int nt = (ncols + 63) >> 6;
   const __amdgpu_buffer_rsrc_t ar = block_rsrc(A, ncols > 0 ? (int64_t)(ncols - 1) * ld + nrows : 0);
-  dbl4 c = {0.0, 0.0, 0.0, 0.0};
   double a0[16], a1[16], x0[2], x1[2];
   auto load = [&](int t, double (&a)[16], double (&xv)[2]) {
     const int k0 = 64 * t;
@@ -135,9 +135,10 @@ __device__ void tile_gemv_n(const double* __restrict__ A, int ld, int r0, int nr
     xtile_load(x, ldx, k0, ncols, nr, xsl, xv);
   };
   auto use = [&](int t, const double (&a)[16], const double (&xv)[2]) {
-    xtile_store(xv, sh.x[t & 1]);
+    const int b = (tpar + t) & 1;
+    xtile_store(xv, sh.x[b]);
     __syncthreads();
-    mfma_tile(a, sh.x[t & 1], c);
+    mfma_tile(a, sh.x[b], c);
   };
   if (nt > 0) load(0, a0, x0);
   if (nt > 1) load(1, a1, x1);
@@ -149,6 +150,16 @@ __device__ void tile_gemv_n(const double* __restrict__ A, int ld, int r0, int nr
       if (t + 3 < nt) load(t + 3, a1, x1);
     }
   }
+  tpar += nt;
+}
+
+// acc += A[(r0 + rr) + k*ld] x[k], k < ncols (rows beyond nrows read as zero)
+__device__ void tile_gemv_n(const double* __restrict__ A, int ld, int r0, int nrows, int ncols,
+                            const double* __restrict__ x, int64_t ldx, int nr, TileShared& sh, double acc[2],
+                            const int32_t* __restrict__ xsl = nullptr) {
+  dbl4 c = {0.0, 0.0, 0.0, 0.0};
+  int tpar = 0;
+  mfma_n_acc(A, ld, r0, nrows, ncols, x, ldx, nr, sh, c, tpar, xsl);
   __syncthreads();  // the last x tile has been read
   mfma_out(c, sh, acc);
 }
@@ -345,83 +356,32 @@ __global__ void __launch_bounds__(AW) k_elim_fwd(const ElimAp* __restrict__ ds, 
   scatter_seg(sl, e.ns, a, e.tmp);
 }
 
-// Non-transposed product without staging the matrix: acc[c] += sum_k A[(r0 + rr) +
-// k ld] x[k][c] over this thread's columns.  Thread (rr = t & 63, ks = t >> 6): wave
-// ks reads columns ks * 16 .. ks * 16 + 15 of every 64-column tile straight into
-// registers (lanes down a column), the 64 x RB tile of x is staged in LDS and read
-// as a broadcast.  The four waves' partial sums are combined by the caller.
-struct DirectShared {
-  double x[64][RB];
-  double red[3][64][RB];
-};
-__device__ void gemv_n_direct(const double* __restrict__ A, int ld, int r0, int nrows, int ncols,
-                              const double* __restrict__ x, int64_t ldx, int nr, DirectShared& sh, double (&acc)[RB]) {
-  const int rr = threadIdx.x & 63, ks = threadIdx.x >> 6;
-  const bool rowok = r0 + rr < nrows;
-  for (int k0 = 0; k0 < ncols; k0 += 64) {
-    double a[16];
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      const int k = k0 + ks * 16 + kk;
-      a[kk] = (rowok && k < ncols) ? gld(A + (r0 + rr) + (int64_t)k * ld) : 0.0;
-    }
-    __syncthreads();  // the previous tile's x has been read
-#pragma unroll
-    for (int u = 0; u < 64 * RB / AW; ++u) {
-      const int e = threadIdx.x + u * AW;
-      const int k = e & 63, c = e >> 6;
-      sh.x[k][c] = (k0 + k < ncols && c < nr) ? gld(x + (k0 + k) + (int64_t)c * ldx) : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      const double* xk = sh.x[ks * 16 + kk];
-#pragma unroll
-      for (int c = 0; c < RB; ++c) acc[c] = fma(a[kk], xk[c], acc[c]);
-    }
-  }
-}
-// Sum of the four waves' partial sums: wave 0 returns the total of row rr.
-__device__ inline void direct_reduce(DirectShared& sh, double (&acc)[RB]) {
-  const int rr = threadIdx.x & 63, ks = threadIdx.x >> 6;
-  __syncthreads();
-  if (ks > 0)
-#pragma unroll
-    for (int c = 0; c < RB; ++c) sh.red[ks - 1][rr][c] = acc[c];
-  __syncthreads();
-  if (ks == 0)
-#pragma unroll
-    for (int c = 0; c < RB; ++c) acc[c] += sh.red[0][rr][c] + sh.red[1][rr][c] + sh.red[2][rr][c];
-}
-
 // x_n -= sum_s G_ns y_s over the contributions of n in ascending s
 __global__ void __launch_bounds__(AW) k_target_fwd(const TargetAp* __restrict__ ts, const TargetContrib* __restrict__ cs,
                                                    ApplyArgs a) {
-  __shared__ DirectShared sh;
+  __shared__ TileShared sh;
   const TargetAp t = ts[blockIdx.x];
   const int32_t* sl = a.slot + t.slot_n;
-  const int rr = threadIdx.x & 63, ks = threadIdx.x >> 6;
+  const int rr = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int r0 = t.r0;
   for (int c0 = 0; c0 < a.nrhs; c0 += RB) {
     const int nr = min(RB, a.nrhs - c0);
-    double acc[RB];
-#pragma unroll
-    for (int c = 0; c < RB; ++c) acc[c] = 0.0;
+    dbl4 c = {0.0, 0.0, 0.0, 0.0};
+    int tpar = 0;
     for (int q = t.cbeg; q < t.cend; ++q) {
       const TargetContrib tc = cs[q];
-      gemv_n_direct(tc.G, tc.ldG, r0, t.nn, tc.ns, a.tmp + tc.tmp_s + (int64_t)c0 * a.ldt, a.ldt, nr, sh, acc);
+      mfma_n_acc(tc.G, tc.ldG, r0, t.nn, tc.ns, a.tmp + tc.tmp_s + (int64_t)c0 * a.ldt, a.ldt, nr, sh, c, tpar);
     }
-    direct_reduce(sh, acc);
-    if (ks == 0 && r0 + rr < t.nn) {
+    __syncthreads();  // the last x tile has been read
+    double acc[2] = {0.0, 0.0};
+    mfma_out(c, sh, acc);
+    if (r0 + rr < t.nn) {
       double* xp = a.x + sl[r0 + rr] + (int64_t)c0 * a.ldx;
-      double xv[RB];
-#pragma unroll
-      for (int c = 0; c < RB; ++c) xv[c] = c < nr ? xp[(int64_t)c * a.ldx] : 0.0;
-#pragma unroll
-      for (int c = 0; c < RB; ++c)
-        if (c < nr) xp[(int64_t)c * a.ldx] = xv[c] - acc[c];
+      const double x0 = g < nr ? xp[(int64_t)g * a.ldx] : 0.0;
+      const double x1 = g + 4 < nr ? xp[(int64_t)(g + 4) * a.ldx] : 0.0;
+      if (g < nr) xp[(int64_t)g * a.ldx] = x0 - acc[0];
+      if (g + 4 < nr) xp[(int64_t)(g + 4) * a.ldx] = x1 - acc[1];
     }
-    __syncthreads();  // sh is reused by the next block of right-hand sides
   }
 }
 
