@@ -346,7 +346,7 @@ __device__ inline void scatter_seg(const int32_t* sl, int n, const ApplyArgs& a,
 
 // ---------------------------------------------------------------- sweep kernels
 // y_s = L_s^{-1} x_s; y_s stays in the scratch for the target updates and replaces x_s.
-__global__ void __launch_bounds__(AW) k_elim_fwd(const ElimAp* __restrict__ ds, ApplyArgs a) {
+__global__ void __launch_bounds__(AW, 2) k_elim_fwd(const ElimAp* __restrict__ ds, ApplyArgs a) {
   __shared__ TileShared sh;
   const ElimAp e = ds[blockIdx.x];
   const int32_t* sl = a.slot + e.slot_s;
