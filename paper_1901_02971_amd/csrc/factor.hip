@@ -797,8 +797,9 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
 
       // sparsification, colour by colour.  A_pn of interface p lives in the registers
       // of slabS[p] workgroups with tg[p] lanes per column.  Interfaces of one slab go
-      // in one plain launch per team size; interfaces of several slabs go in
-      // cooperative launches of at most the co-resident number of workgroups.
+      // in one plain launch per team size; interfaces of several slabs go in one
+      // cooperative launch per colour, as rounds of at most the co-resident number of
+      // workgroups.
       std::vector<int64_t> ncols(nc, 0);
       int32_t ncolour = 0;
       int64_t house_total = 0, xch_total = 0;
@@ -847,7 +848,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
         if (v_off[p] >= 0) by_colour[sy.colour[p]].push_back(p);
       struct CpqrLaunch {
         bool multi;
-        int32_t G, nslab;
+        int32_t G, nslab, nround;
         size_t lds, d0, s0;
       };
       std::vector<CpqrLaunch> launches;
@@ -877,20 +878,22 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
             cap = cpqr_max_coresident(lds);
             if (cap <= 0) return set_err(h, SPAND_E_HIP, "occupancy query for the CPQR kernel failed");
           }
+          // The chunks of at most cap co-resident slabs: one plain launch each for the
+          // single-slab interfaces; for the multi-slab ones, the rounds of one launch.
+          CpqrLaunch L{};
+          L.multi = multi;
+          L.G = multi ? 0 : grp;
+          L.lds = lds;
+          L.d0 = all_sds.size();
+          std::vector<std::vector<SlabRef>> rounds;
           size_t pos = 0;
           while (pos < plist.size()) {
-            CpqrLaunch L{};
-            L.multi = multi;
-            L.G = multi ? 0 : grp;
-            L.lds = lds;
-            L.d0 = all_sds.size();
-            L.s0 = all_slabs.size();
-            int32_t nsl = 0;
+            std::vector<SlabRef> rd;
             while (pos < plist.size()) {
               const int32_t p = plist[pos];
               if (multi && slabS[p] > cap)
                 return set_err(h, SPAND_E_INVALID, "interface needs more co-resident workgroups than the GPU holds");
-              if (multi && nsl > 0 && int64_t(nsl) + slabS[p] > cap) break;
+              if (multi && !rd.empty() && int64_t(rd.size()) + slabS[p] > cap) break;
               SparsDesc d{};
               d.V = sn.house.as<double>() + v_off[p];
               d.tau = sn.house.as<double>() + tau_off[p];
@@ -919,13 +922,29 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
                 all_segs.push_back(g);
               }
               d.seg_end = int32_t(all_segs.size());
-              for (int32_t w = 0; w < slabS[p]; ++w)
-                all_slabs.push_back(SlabRef{int32_t(all_sds.size() - L.d0), w});
-              nsl += slabS[p];
+              for (int32_t w = 0; w < slabS[p]; ++w) rd.push_back(SlabRef{int32_t(all_sds.size() - L.d0), w});
               all_sds.push_back(d);
               ++pos;
             }
-            L.nslab = nsl;
+            rounds.push_back(std::move(rd));
+          }
+          if (!multi) {
+            for (const auto& rd : rounds) {
+              CpqrLaunch P = L;
+              P.s0 = all_slabs.size();
+              P.nslab = int32_t(rd.size());
+              P.nround = 1;
+              all_slabs.insert(all_slabs.end(), rd.begin(), rd.end());
+              launches.push_back(P);
+            }
+          } else {
+            size_t grid = 0;
+            for (const auto& rd : rounds) grid = std::max(grid, rd.size());
+            L.s0 = all_slabs.size();
+            L.nslab = int32_t(grid);
+            L.nround = int32_t(rounds.size());
+            for (const auto& rd : rounds)
+              for (size_t b = 0; b < grid; ++b) all_slabs.push_back(b < rd.size() ? rd[b] : SlabRef{-1, 0});
             launches.push_back(L);
           }
         }
@@ -942,8 +961,9 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
         HIPCHK(hipEventRecord(e0, h->stream));
         const SparsDesc* dd = a.as<SparsDesc>() + L.d0;
         const SlabRef* ss = sl.as<SlabRef>() + L.s0;
-        hipError_t le = L.multi ? launch_cpqr_multi(dd, ss, L.nslab, b.as<SegDesc>(), tol, curb.as<int32_t>(),
-                                                    nrefb.as<int32_t>(), errb.as<int32_t>(), L.lds, h->stream)
+        hipError_t le = L.multi ? launch_cpqr_multi(dd, ss, L.nslab, L.nround, b.as<SegDesc>(), tol,
+                                                    curb.as<int32_t>(), nrefb.as<int32_t>(), errb.as<int32_t>(),
+                                                    L.lds, h->stream)
                                 : launch_cpqr_one(L.G, dd, ss, L.nslab, b.as<SegDesc>(), tol, curb.as<int32_t>(),
                                                   nrefb.as<int32_t>(), errb.as<int32_t>(), L.lds, h->stream);
         if (le != hipSuccess)

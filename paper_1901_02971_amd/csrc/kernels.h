@@ -96,7 +96,7 @@ struct SegDesc {
   int32_t ld, trans, q, pad;
 };
 struct SlabRef {
-  int32_t desc, w;
+  int32_t desc, w;  // desc < 0: an unused place of a multi-slab round
 };
 
 // dst >= 0: arena[dst]; dst <= -2: elim[-dst - 2]; dst == -1: skipped.
@@ -129,8 +129,10 @@ int cpqr_max_coresident(size_t lds_bytes);
 // any team size (cooperative launch: all nslab workgroups resident).
 hipError_t launch_cpqr_one(int32_t G, const SparsDesc* d, const SlabRef* slabs, int32_t nslab, const SegDesc* seg,
                            double eps, int32_t* cursize, int32_t* nref, int32_t* err, size_t lds_bytes, hipStream_t s);
-hipError_t launch_cpqr_multi(const SparsDesc* d, const SlabRef* slabs, int32_t nslab, const SegDesc* seg, double eps,
-                             int32_t* cursize, int32_t* nref, int32_t* err, size_t lds_bytes, hipStream_t s);
+// The multi-slab launch runs nround rounds of nslab places (slabs[k * nslab + b]).
+hipError_t launch_cpqr_multi(const SparsDesc* d, const SlabRef* slabs, int32_t nslab, int32_t nround,
+                             const SegDesc* seg, double eps, int32_t* cursize, int32_t* nref, int32_t* err,
+                             size_t lds_bytes, hipStream_t s);
 struct TDesc {
   const double* V;    // m x r, ld m
   const double* tau;  // r

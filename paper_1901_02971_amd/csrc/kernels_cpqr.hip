@@ -698,22 +698,31 @@ __global__ void __launch_bounds__(CQ_NT) k_cpqr_one(const SparsDesc* __restrict_
 }
 
 // Multi-slab interfaces of every team size in one cooperative launch: each
-// workgroup takes the code path of its interface's G.
+// workgroup takes the code path of its interface's G.  The launch runs nround
+// rounds; place b of round k is slabs[k * gridDim.x + b] (a negative descriptor
+// index leaves it unused).  All slabs of an interface lie in one round, and a
+// workgroup starts round k only after its slab of round k - 1 has finished, so every
+// slab it waits for is in the same round on a workgroup that has finished the
+// earlier rounds: round 0 completes, and by induction every later one.
 __global__ void __launch_bounds__(CQ_NT) k_cpqr_multi(const SparsDesc* __restrict__ descs,
-                                                      const SlabRef* __restrict__ slabs,
+                                                      const SlabRef* __restrict__ slabs, int32_t nround,
                                                       const SegDesc* __restrict__ segs, double eps,
                                                       int32_t* cursize, int32_t* nref, int32_t* err) {
-  const SlabRef sr = slabs[blockIdx.x];
-  const SparsDesc d = descs[sr.desc];
-  switch (d.G) {
-    case 1: cpqr_slab<1, true>(d, sr.w, segs, eps, cursize, nref, err); break;
-    case 2: cpqr_slab<2, true>(d, sr.w, segs, eps, cursize, nref, err); break;
-    case 4: cpqr_slab<4, true>(d, sr.w, segs, eps, cursize, nref, err); break;
-    case 8: cpqr_slab<8, true>(d, sr.w, segs, eps, cursize, nref, err); break;
-    case 16: cpqr_slab<16, true>(d, sr.w, segs, eps, cursize, nref, err); break;
-    case 32: cpqr_slab<32, true>(d, sr.w, segs, eps, cursize, nref, err); break;
-    case 64: cpqr_slab<64, true>(d, sr.w, segs, eps, cursize, nref, err); break;
-    default: break;  // the host only builds the team sizes above
+  for (int32_t rd = 0; rd < nround; ++rd) {
+    const SlabRef sr = slabs[(size_t)rd * gridDim.x + blockIdx.x];
+    if (sr.desc < 0) continue;
+    const SparsDesc d = descs[sr.desc];
+    switch (d.G) {
+      case 1: cpqr_slab<1, true>(d, sr.w, segs, eps, cursize, nref, err); break;
+      case 2: cpqr_slab<2, true>(d, sr.w, segs, eps, cursize, nref, err); break;
+      case 4: cpqr_slab<4, true>(d, sr.w, segs, eps, cursize, nref, err); break;
+      case 8: cpqr_slab<8, true>(d, sr.w, segs, eps, cursize, nref, err); break;
+      case 16: cpqr_slab<16, true>(d, sr.w, segs, eps, cursize, nref, err); break;
+      case 32: cpqr_slab<32, true>(d, sr.w, segs, eps, cursize, nref, err); break;
+      case 64: cpqr_slab<64, true>(d, sr.w, segs, eps, cursize, nref, err); break;
+      default: break;  // the host only builds the team sizes above
+    }
+    __syncthreads();  // the LDS of this slab is reused by the next round's
   }
 }
 
@@ -797,10 +806,12 @@ hipError_t launch_cpqr_one(int32_t G, const SparsDesc* d, const SlabRef* slabs, 
   return hipGetLastError();
 }
 
-hipError_t launch_cpqr_multi(const SparsDesc* d, const SlabRef* slabs, int32_t nslab, const SegDesc* seg, double eps,
-                             int32_t* cursize, int32_t* nref, int32_t* err, size_t lds, hipStream_t s) {
-  if (nslab == 0) return hipSuccess;
-  void* args[] = {(void*)&d, (void*)&slabs, (void*)&seg, (void*)&eps, (void*)&cursize, (void*)&nref, (void*)&err};
+hipError_t launch_cpqr_multi(const SparsDesc* d, const SlabRef* slabs, int32_t nslab, int32_t nround,
+                             const SegDesc* seg, double eps, int32_t* cursize, int32_t* nref, int32_t* err,
+                             size_t lds, hipStream_t s) {
+  if (nslab == 0 || nround == 0) return hipSuccess;
+  void* args[] = {(void*)&d,   (void*)&slabs,   (void*)&nround, (void*)&seg,
+                  (void*)&eps, (void*)&cursize, (void*)&nref,   (void*)&err};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_cpqr_multi), dim3(nslab), dim3(CQ_NT), args,
                                     (unsigned int)lds, s);
 }
