@@ -23,6 +23,33 @@ namespace spand {
 
 #define PW 256
 
+// Loads below are issued from addresses clamped into the block, never behind a
+// branch, so that a thread's loads are all in flight together; entries read past
+// the block are replaced or never used in a stored result.
+typedef __attribute__((address_space(1))) const double gdouble_c;
+typedef __attribute__((address_space(1))) double gdouble_w;
+__device__ inline double gldc(const double* p) { return *(gdouble_c*)p; }
+// stores through the global address space do not count against the LDS counter,
+// so a later LDS read never waits for them
+__device__ inline void gstc(double* p, double v) { *(gdouble_w*)p = v; }
+
+// Xi[r][c] = D[r + c * w] for r, c < w (the entries beyond w are left as they are)
+__device__ inline void stage_inverse(const double* __restrict__ D, int w, double (*Xi)[CHOL_NB + 1]) {
+  const int r = threadIdx.x & 63, c0 = threadIdx.x >> 6;
+  const int rc = r < w ? r : w - 1;
+  double v[CHOL_NB / 4];
+#pragma unroll
+  for (int u = 0; u < CHOL_NB / 4; ++u) {
+    const int c = c0 + 4 * u;
+    v[u] = gldc(D + rc + (c < w ? c : w - 1) * w);
+  }
+#pragma unroll
+  for (int u = 0; u < CHOL_NB / 4; ++u) {
+    const int c = c0 + 4 * u;
+    if (r < w && c < w) Xi[r][c] = v[u];
+  }
+}
+
 // One diagonal block per workgroup.  Cholesky column by column in LDS: thread t
 // updates column j = t % 64 of rows t / 64, t / 64 + 4, ... (no index division);
 // then lane c of wave 0 forms column c of L^{-1} by forward substitution, entirely
@@ -35,10 +62,19 @@ __global__ void __launch_bounds__(PW) k_potrf_diag(const PotrfDesc* __restrict__
   const int tid = threadIdx.x;
   const int jc = tid & 63, i0 = tid >> 6;  // column and first row of this thread's share
   if (tid == 0) bad = 0;
+  {
+    const int jcc = jc < w ? jc : w - 1;
+    double v[CHOL_NB / 4];
 #pragma unroll
-  for (int s = 0; s < CHOL_NB / 4; ++s) {
-    const int r = i0 + 4 * s;
-    D[r][jc] = (r < w && jc < w && r >= jc) ? d.P[r + (int64_t)jc * d.ld] : 0.0;
+    for (int s = 0; s < CHOL_NB / 4; ++s) {
+      const int r = i0 + 4 * s;
+      v[s] = gldc(d.P + (r < w ? r : w - 1) + (int64_t)jcc * d.ld);
+    }
+#pragma unroll
+    for (int s = 0; s < CHOL_NB / 4; ++s) {
+      const int r = i0 + 4 * s;
+      D[r][jc] = (r < w && jc < w && r >= jc) ? v[s] : 0.0;
+    }
   }
   __syncthreads();
   for (int k = 0; k < w; ++k) {
@@ -78,12 +114,12 @@ __global__ void __launch_bounds__(PW) k_potrf_diag(const PotrfDesc* __restrict__
     if (c < w)
 #pragma unroll
       for (int i = 0; i < CHOL_NB; ++i)
-        if (i < w) d.Dinv[i + (int64_t)c * w] = x[i];
+        if (i < w) gstc(d.Dinv + i + (int64_t)c * w, x[i]);
   }
 #pragma unroll
   for (int s = 0; s < CHOL_NB / 4; ++s) {
     const int r = i0 + 4 * s;
-    if (r < w && jc < w && r >= jc) d.P[r + (int64_t)jc * d.ld] = D[r][jc];
+    if (r < w && jc < w && r >= jc) gstc(d.P + r + (int64_t)jc * d.ld, D[r][jc]);
   }
   if (bad && tid == 0) atomicMin(fail, d.id);
 }
@@ -93,21 +129,21 @@ __global__ void __launch_bounds__(PW) k_panel_trsm(const PanelDesc* __restrict__
   const PanelDesc d = descs[blockIdx.x];
   const int w = d.w;
   __shared__ double Xi[CHOL_NB][CHOL_NB + 1];
-  for (int e = threadIdx.x; e < w * w; e += PW) Xi[e % w][e / w] = d.Dinv[e];
+  stage_inverse(d.Dinv, w, Xi);
   __syncthreads();
   const int r = d.r0 + threadIdx.x;
   if (r >= d.r1) return;
   double* row = d.P + r;
-  double x[CHOL_NB];
+  double x[CHOL_NB];  // x[k] for k >= w is read from column w - 1 and only enters outputs c >= w
 #pragma unroll
-  for (int k = 0; k < CHOL_NB; ++k) x[k] = (k < w) ? row[(int64_t)k * d.ld] : 0.0;
+  for (int k = 0; k < CHOL_NB; ++k) x[k] = gldc(row + (int64_t)(k < w ? k : w - 1) * d.ld);
   // out[c] = sum_{k <= c} x[k] Xi[c][k]; fully unrolled so x stays in registers
 #pragma unroll
   for (int c = 0; c < CHOL_NB; ++c) {
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k <= c; ++k) s = fma(x[k], Xi[c][k], s);
-    if (c < w) row[(int64_t)c * d.ld] = s;
+    if (c < w) gstc(row + (int64_t)c * d.ld, s);
   }
 }
 
@@ -116,21 +152,21 @@ __global__ void __launch_bounds__(PW) k_left_trsm_diag(const LeftDesc* __restric
   const LeftDesc d = descs[blockIdx.x];
   const int w = d.w;
   __shared__ double Xi[CHOL_NB][CHOL_NB + 1];
-  for (int e = threadIdx.x; e < w * w; e += PW) Xi[e % w][e / w] = d.Dinv[e];
+  stage_inverse(d.Dinv, w, Xi);
   __syncthreads();
   const int c = d.c0 + threadIdx.x;
   if (c >= d.c1) return;
   double* col = d.X + (int64_t)c * d.ldx;
-  double x[CHOL_NB];
+  double x[CHOL_NB];  // x[k] for k >= w is read from row w - 1 and only enters outputs i >= w
 #pragma unroll
-  for (int k = 0; k < CHOL_NB; ++k) x[k] = (k < w) ? col[k] : 0.0;
+  for (int k = 0; k < CHOL_NB; ++k) x[k] = gldc(col + (k < w ? k : w - 1));
   // out[i] = sum_{k <= i} Xi[i][k] x[k]
 #pragma unroll
   for (int i = 0; i < CHOL_NB; ++i) {
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k <= i; ++k) s = fma(Xi[i][k], x[k], s);
-    if (i < w) col[i] = s;
+    if (i < w) gstc(col + i, s);
   }
 }
 

@@ -14,7 +14,7 @@
 //           Henry, Tang and Heinecke, ARITH 2019)
 //
 // Lane layout of the 16x16 blocks (lane l, 0..63): A fragment row l%16, k-group
-// l/16; B fragment column l%16, k-group l/16; accumulator layout in store_block.
+// l/16; B fragment column l%16, k-group l/16; accumulator layout in store_blocks.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -31,13 +31,22 @@ typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 
 namespace {
 
+// Operand entries outside the product read a zero constant instead of branching
+// around the load, so that a thread's loads are all in flight together.
+__device__ const double g_gemm_zero[1] = {0.0};
+typedef __attribute__((address_space(1))) const double gdouble_m;
+typedef __attribute__((address_space(1))) double gdouble_mw;
+__device__ inline double gldm(const double* p) { return *(gdouble_m*)p; }
+
 __device__ inline double load_a(const GemmDesc& d, int gm, int gk, int kmax) {
-  if (gm >= d.M || gk >= kmax || ((d.flags & G_TRIA) && gk > gm)) return 0.0;
-  return (d.flags & G_TA) ? d.A[gk + (int64_t)gm * d.lda] : d.A[gm + (int64_t)gk * d.lda];
+  const bool ok = !(gm >= d.M || gk >= kmax || ((d.flags & G_TRIA) && gk > gm));
+  const double* p = (d.flags & G_TA) ? d.A + gk + (int64_t)gm * d.lda : d.A + gm + (int64_t)gk * d.lda;
+  return gldm(ok ? p : g_gemm_zero);
 }
 __device__ inline double load_b(const GemmDesc& d, int gk, int gn, int kmax) {
-  if (gn >= d.N || gk >= kmax || ((d.flags & G_TRIB) && gk > gn)) return 0.0;
-  return (d.flags & G_TB) ? d.B[gn + (int64_t)gk * d.ldb] : d.B[gk + (int64_t)gn * d.ldb];
+  const bool ok = !(gn >= d.N || gk >= kmax || ((d.flags & G_TRIB) && gk > gn));
+  const double* p = (d.flags & G_TB) ? d.B + gn + (int64_t)gk * d.ldb : d.B + gk + (int64_t)gn * d.ldb;
+  return gldm(ok ? p : g_gemm_zero);
 }
 
 // Global -> LDS index of element q (0..64*BK) of a 64 x BK operand tile, chosen so
@@ -49,20 +58,44 @@ __device__ inline void tile_index(bool trans_major, int q, int BK, int& mm, int&
 // Accumulator entry i of lane l sits at column l%16 and row 4*(l/16)+i for the
 // FP32-accumulating instructions but at row l/16+4*i for v_mfma_f64_16x16x4f64
 // (both measured on gfx950).
+// C <- alpha acc + beta C over the four 16 x 16 blocks of a wave: every read of C
+// (from a clamped address) is issued before the first store.
 template <bool F64, typename C4>
-__device__ inline void store_block(const GemmDesc& d, int row0, int col0, const C4& acc) {
+__device__ inline void store_blocks(const GemmDesc& d, int row0, int col0, const C4 (&acc)[2][2]) {
   const int lane = threadIdx.x & 63;
-  const int gn = col0 + (lane & 15);
-  if (gn >= d.N) return;
+  double cv[2][2][4];
+  int64_t off[2][2][4];
+  bool ok[2][2][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int gm = row0 + (F64 ? (lane >> 4) + 4 * i : 4 * (lane >> 4) + i);
-    if (gm >= d.M) continue;
-    double* c = d.C + gm + (int64_t)gn * d.ldc;
-    double v = d.alpha * (double)acc[i];
-    if (d.beta != 0.0) v += d.beta * (*c);
-    *c = v;
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gn = col0 + q * 16 + (lane & 15);
+        const int gm = row0 + p * 16 + (F64 ? (lane >> 4) + 4 * i : 4 * (lane >> 4) + i);
+        ok[p][q][i] = gm < d.M && gn < d.N;
+        off[p][q][i] = ok[p][q][i] ? gm + (int64_t)gn * d.ldc : 0;
+      }
+  if (d.beta != 0.0) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) cv[p][q][i] = gldm(d.C + off[p][q][i]);
   }
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (!ok[p][q][i]) continue;
+        double v = d.alpha * (double)acc[p][q][i];
+        if (d.beta != 0.0) v += d.beta * cv[p][q][i];
+        *(gdouble_mw*)(d.C + off[p][q][i]) = v;
+      }
 }
 
 // Tile (row, column) of the local-th output tile of a product: row-major over all
@@ -163,10 +196,7 @@ __global__ void __launch_bounds__(MW) k_gemm_mfma(const GemmDesc* __restrict__ d
     }
     __syncthreads();
   }
-#pragma unroll
-  for (int p = 0; p < 2; ++p)
-#pragma unroll
-    for (int q = 0; q < 2; ++q) store_block<MODE == 0>(d, m0 + wm * 32 + p * 16, n0 + wn * 32 + q * 16, acc[p][q]);
+  store_blocks<MODE == 0>(d, m0 + wm * 32, n0 + wn * 32, acc);
 }
 
 // MODE 2 (BF16x3): K staged 32 at a time, one k=32 step (three MFMAs) per stage.
@@ -228,10 +258,7 @@ __global__ void __launch_bounds__(MW) k_gemm_bf16x3(const GemmDesc* __restrict__
       }
     __syncthreads();
   }
-#pragma unroll
-  for (int p = 0; p < 2; ++p)
-#pragma unroll
-    for (int q = 0; q < 2; ++q) store_block<false>(d, m0 + wm * 32 + p * 16, n0 + wn * 32 + q * 16, acc[p][q]);
+  store_blocks<false>(d, m0 + wm * 32, n0 + wn * 32, acc);
 }
 
 __global__ void k_expand_tiles(const GemmDesc* __restrict__ descs, int32_t* __restrict__ tile_desc) {
