@@ -14,6 +14,13 @@ namespace spand {
 
 #define WG 256
 
+// Accesses through the global address space: flat accesses also count against the
+// LDS counter, and the compiler then waits for every store before the next one.
+typedef __attribute__((address_space(1))) const double gdouble_r;
+typedef __attribute__((address_space(1))) double gdouble_d;
+__device__ inline double gldd(const double* p) { return *(gdouble_r*)p; }
+__device__ inline void gstd(double* p, double v) { *(gdouble_d*)p = v; }
+
 // ---------------------------------------------------------------- reductions
 __device__ inline double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -81,19 +88,39 @@ void launch_scatter_values(const double* vals, const int64_t* dst, int64_t nnz, 
 // Only the lower triangle of a diagonal target block is accumulated: its upper
 // triangle is never read again (Cholesky, the left solves, the merge and the CPQR
 // read lower triangles and off-diagonal blocks only).
+// A thread takes RU entries at a time and reads all their contributions and target
+// values before it stores any: the target and the contributions may alias as far as
+// the compiler knows, so an interleaved loop would wait for every store.  Entries
+// outside the range read the first entry of the block and are not stored.
+#define RU 8
 __global__ void __launch_bounds__(WG) k_reduce(const ReduceDesc* __restrict__ descs,
                                                const ContribDesc* __restrict__ cs) {
   const ReduceDesc d = descs[blockIdx.x];
   const uint32_t rows = (uint32_t)d.rows;
-  for (uint32_t e = (uint32_t)d.e0 + threadIdx.x; e < (uint32_t)d.e1; e += WG) {
-    const uint32_t c = e / rows, r = e - c * rows;
-    if (d.diag && r < c) continue;
-    double sum = 0.0;
+  for (uint32_t eb = (uint32_t)d.e0 + threadIdx.x; eb < (uint32_t)d.e1; eb += WG * RU) {
+    bool ok[RU];
+    uint32_t rr[RU], cc[RU];
+    double sum[RU];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const uint32_t e = eb + u * WG;
+      const uint32_t c = e / rows, r = e - c * rows;
+      ok[u] = e < (uint32_t)d.e1 && !(d.diag && r < c);
+      rr[u] = ok[u] ? r : 0;
+      cc[u] = ok[u] ? c : 0;
+      sum[u] = 0.0;
+    }
     for (int q = d.c_begin; q < d.c_end; ++q) {
       const ContribDesc cd = cs[q];
-      sum += cd.C[r + (int64_t)c * cd.ldC];
+#pragma unroll
+      for (int u = 0; u < RU; ++u) sum[u] += gldd(cd.C + rr[u] + (int64_t)cc[u] * cd.ldC);
     }
-    d.T[r + (int64_t)c * d.ldT] -= sum;
+    double tv[RU];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) tv[u] = gldd(d.T + rr[u] + (int64_t)cc[u] * d.ldT);
+#pragma unroll
+    for (int u = 0; u < RU; ++u)
+      if (ok[u]) gstd(d.T + rr[u] + (int64_t)cc[u] * d.ldT, tv[u] - sum[u]);
   }
 }
 
@@ -106,14 +133,35 @@ void launch_reduce(const ReduceDesc* d, int32_t count, const ContribDesc* c, hip
 // One workgroup per column range of a block.  Thread t takes row t % h of column
 // c0 + t / h, h = min(rows, WG), and steps by WG / h columns (one division per
 // thread, none per entry).
+// Entries are moved RU at a time, all loads before the stores (source and
+// destination may alias as far as the compiler knows); a slot past the range reads
+// the first entry of the source and is not stored.
 __global__ void __launch_bounds__(WG) k_copy(const CopyDesc* __restrict__ descs) {
   const CopyDesc d = descs[blockIdx.x];
   const int h = min(d.rows, WG), cs = WG / h;
   const int r0 = threadIdx.x % h, dc = threadIdx.x / h;
   if (dc >= cs) return;
-  for (int c = d.c0 + dc; c < d.c1; c += cs)
-    for (int r = r0; r < d.rows; r += h)
-      d.dst[r + (int64_t)c * d.ldd] = d.trans ? d.src[c + (int64_t)r * d.lds] : d.src[r + (int64_t)c * d.lds];
+  int c = d.c0 + dc, r = r0;
+  while (c < d.c1) {
+    bool ok[RU];
+    int64_t to[RU];
+    double v[RU];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      ok[u] = c < d.c1;
+      const int64_t so = ok[u] ? (d.trans ? c + (int64_t)r * d.lds : r + (int64_t)c * d.lds) : 0;
+      to[u] = r + (int64_t)c * d.ldd;
+      v[u] = gldd(d.src + so);
+      r += h;
+      if (r >= d.rows) {
+        r = r0;
+        c += cs;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u)
+      if (ok[u]) gstd(d.dst + to[u], v[u]);
+  }
 }
 
 void launch_copy(const CopyDesc* d, int64_t count, hipStream_t s) {
