@@ -515,6 +515,88 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
   // apply descriptors of the previous step, built while the current step runs
   // (lay_prev is that step's layout until the end of the current one)
   ApplyPlan pending;
+  // Compact-WY factors T_p of the interfaces sparsified in the last step: launched
+  // after the next step's sparsification (or at the end) so that their planning is
+  // off the path between a rank read-back and the next step's first kernels.
+  std::vector<TDesc> t_pending;
+  auto flush_t = [&]() -> spand_status {
+    if (t_pending.empty()) return SPAND_OK;
+    const std::vector<TDesc> tds = std::move(t_pending);
+    t_pending.clear();
+    spand_status st = SPAND_OK;
+    // S = V^T V into the T blocks (MFMA, upper tiles), then the T recurrence
+    GemmSeq vtv;
+    for (const TDesc& td : tds) {
+      GemmDesc q{};
+      q.A = td.V; q.lda = td.m;
+      q.B = td.V; q.ldb = td.m;
+      q.C = td.T; q.ldc = td.r;
+      q.M = td.r; q.N = td.r; q.K = td.m;
+      q.flags = G_TA;
+      q.alpha = 1.0; q.beta = 0.0;
+      vtv.add(q, 2);
+    }
+    vtv.end_launch(0);
+    if ((st = vtv.upload_all(h)) != SPAND_OK) return st;
+    vtv.launch(h, 0);
+    HIPCHK(hipGetLastError());
+    // T by 64-wide block columns: the diagonal blocks, then for J = 1, 2, ...
+    // X = S[:J0, J] T_JJ and T[:J0, J] = -T[:J0, :J0] X (GEMMs across interfaces)
+    std::vector<TBlock> tbs;
+    int32_t rmax = 0;
+    int64_t x_total = 0;
+    std::vector<int64_t> x_off(tds.size(), -1);
+    for (size_t q = 0; q < tds.size(); ++q) {
+      const TDesc& td = tds[q];
+      for (int32_t j0 = 0; j0 < td.r; j0 += 64) tbs.push_back(TBlock{td.T, td.tau, td.r, j0});
+      rmax = std::max(rmax, td.r);
+      if (td.r > 64) {
+        x_off[q] = x_total;
+        x_total += int64_t(td.r) * 64;
+      }
+    }
+    DevBuf dtb, xb;
+    if ((st = upload(h, dtb, tbs)) != SPAND_OK) return st;
+    launch_build_t_diag(dtb.as<TBlock>(), int32_t(tbs.size()), h->stream);
+    HIPCHK(hipGetLastError());
+    if (rmax > 64) {
+      if ((st = dalloc(h, xb, size_t(x_total) * sizeof(double))) != SPAND_OK) return st;
+      GemmSeq tg2;
+      for (int32_t j0 = 64; j0 < rmax; j0 += 64) {
+        for (size_t q = 0; q < tds.size(); ++q) {
+          const TDesc& td = tds[q];
+          if (td.r <= j0) continue;
+          const int32_t w = std::min(64, td.r - j0);
+          GemmDesc g{};  // X = S[:j0, J] T_JJ
+          g.A = td.T + int64_t(j0) * td.r; g.lda = td.r;
+          g.B = td.T + j0 + int64_t(j0) * td.r; g.ldb = td.r;
+          g.C = xb.as<double>() + x_off[q]; g.ldc = td.r;
+          g.M = j0; g.N = w; g.K = w;
+          g.alpha = 1.0; g.beta = 0.0;
+          tg2.add(g, 0);
+        }
+        tg2.end_launch(0);
+        for (size_t q = 0; q < tds.size(); ++q) {
+          const TDesc& td = tds[q];
+          if (td.r <= j0) continue;
+          const int32_t w = std::min(64, td.r - j0);
+          GemmDesc g{};  // T[:j0, J] = -T[:j0, :j0] X
+          g.A = td.T; g.lda = td.r;
+          g.B = xb.as<double>() + x_off[q]; g.ldb = td.r;
+          g.C = td.T + int64_t(j0) * td.r; g.ldc = td.r;
+          g.M = j0; g.N = w; g.K = j0;
+          g.alpha = -1.0; g.beta = 0.0;
+          tg2.add(g, 0);
+        }
+        tg2.end_launch(0);
+      }
+      if ((st = tg2.upload_all(h)) != SPAND_OK) return st;
+      for (size_t q = 0; q < tg2.cut.size(); ++q) tg2.launch(h, q);
+      HIPCHK(hipGetLastError());
+    }
+    return SPAND_OK;
+  };
+
   auto flush_apply = [&]() -> spand_status {
     if (pending.t == 0) return SPAND_OK;
     const int32_t pt = pending.t;
@@ -973,7 +1055,8 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       }
       std::vector<int32_t> rk(nc, -1);
       HIPCHK(hipEventRecord(ph[4], h->stream));
-      if ((st = flush_apply()) != SPAND_OK) return st;  // the previous step's, while this one runs
+      if ((st = flush_t()) != SPAND_OK) return st;      // the previous step's, while this one runs
+      if ((st = flush_apply()) != SPAND_OK) return st;
       if ((st = check_flags(t)) != SPAND_OK) return st;
       flags_read = true;
       HIPCHK(hipMemcpyAsync(rk.data(), curb.p, size_t(nc) * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
@@ -1004,81 +1087,14 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
             tds.push_back(TDesc{sn.house.as<double>() + v_off[p], sn.house.as<double>() + tau_off[p],
                                 sn.house.as<double>() + t_off[p], sn.size[p], int32_t(r)});
         }
-      // S = V^T V into the T blocks (MFMA, upper tiles), then the T recurrence
-      GemmSeq vtv;
-      for (const TDesc& td : tds) {
-        GemmDesc q{};
-        q.A = td.V; q.lda = td.m;
-        q.B = td.V; q.ldb = td.m;
-        q.C = td.T; q.ldc = td.r;
-        q.M = td.r; q.N = td.r; q.K = td.m;
-        q.flags = G_TA;
-        q.alpha = 1.0; q.beta = 0.0;
-        vtv.add(q, 2);
-      }
-      vtv.end_launch(0);
-      if ((st = vtv.upload_all(h)) != SPAND_OK) return st;
-      vtv.launch(h, 0);
-      HIPCHK(hipGetLastError());
-      // T by 64-wide block columns: the diagonal blocks, then for J = 1, 2, ...
-      // X = S[:J0, J] T_JJ and T[:J0, J] = -T[:J0, :J0] X (GEMMs across interfaces)
-      std::vector<TBlock> tbs;
-      int32_t rmax = 0;
-      int64_t x_total = 0;
-      std::vector<int64_t> x_off(tds.size(), -1);
-      for (size_t q = 0; q < tds.size(); ++q) {
-        const TDesc& td = tds[q];
-        for (int32_t j0 = 0; j0 < td.r; j0 += 64) tbs.push_back(TBlock{td.T, td.tau, td.r, j0});
-        rmax = std::max(rmax, td.r);
-        if (td.r > 64) {
-          x_off[q] = x_total;
-          x_total += int64_t(td.r) * 64;
-        }
-      }
-      DevBuf dtb, xb;
-      if ((st = upload(h, dtb, tbs)) != SPAND_OK) return st;
-      launch_build_t_diag(dtb.as<TBlock>(), int32_t(tbs.size()), h->stream);
-      HIPCHK(hipGetLastError());
-      if (rmax > 64) {
-        if ((st = dalloc(h, xb, size_t(x_total) * sizeof(double))) != SPAND_OK) return st;
-        GemmSeq tg2;
-        for (int32_t j0 = 64; j0 < rmax; j0 += 64) {
-          for (size_t q = 0; q < tds.size(); ++q) {
-            const TDesc& td = tds[q];
-            if (td.r <= j0) continue;
-            const int32_t w = std::min(64, td.r - j0);
-            GemmDesc g{};  // X = S[:j0, J] T_JJ
-            g.A = td.T + int64_t(j0) * td.r; g.lda = td.r;
-            g.B = td.T + j0 + int64_t(j0) * td.r; g.ldb = td.r;
-            g.C = xb.as<double>() + x_off[q]; g.ldc = td.r;
-            g.M = j0; g.N = w; g.K = w;
-            g.alpha = 1.0; g.beta = 0.0;
-            tg2.add(g, 0);
-          }
-          tg2.end_launch(0);
-          for (size_t q = 0; q < tds.size(); ++q) {
-            const TDesc& td = tds[q];
-            if (td.r <= j0) continue;
-            const int32_t w = std::min(64, td.r - j0);
-            GemmDesc g{};  // T[:j0, J] = -T[:j0, :j0] X
-            g.A = td.T; g.lda = td.r;
-            g.B = xb.as<double>() + x_off[q]; g.ldb = td.r;
-            g.C = td.T + int64_t(j0) * td.r; g.ldc = td.r;
-            g.M = j0; g.N = w; g.K = j0;
-            g.alpha = -1.0; g.beta = 0.0;
-            tg2.add(g, 0);
-          }
-          tg2.end_launch(0);
-        }
-        if ((st = tg2.upload_all(h)) != SPAND_OK) return st;
-        for (size_t q = 0; q < tg2.cut.size(); ++q) tg2.launch(h, q);
-        HIPCHK(hipGetLastError());
-      }
-      HIPCHK(hipGetLastError());
+      // the compact-WY factors are only read by the apply: they are built while the
+      // next step runs (flush_t)
+      t_pending = std::move(tds);
     }
     if (t <= 32) h->stats.step_m_F[t - 1] = m_F;
 
     if (!flags_read) {
+      if ((st = flush_t()) != SPAND_OK) return st;
       if ((st = flush_apply()) != SPAND_OK) return st;
       if ((st = check_flags(t)) != SPAND_OK) return st;
     }
@@ -1088,6 +1104,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
     arena_prev = std::move(arena);
     lay_prev = std::move(lay);
   }
+  if ((st = flush_t()) != SPAND_OK) return st;
   if ((st = flush_apply()) != SPAND_OK) return st;
   HIPCHK(hipStreamSynchronize(h->stream));
   for (int32_t t = 1; t <= Lv; ++t) {  // phase times from the events of every step
