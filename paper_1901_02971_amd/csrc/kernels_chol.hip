@@ -124,27 +124,79 @@ __global__ void __launch_bounds__(PW) k_potrf_diag(const PotrfDesc* __restrict__
   if (bad && tid == 0) atomicMin(fail, d.id);
 }
 
-// rows [r0, r1) of the panel below the diagonal block: x <- x L_kk^{-T}
+// rows [r0, r1) of the panel below the diagonal block: x <- x L_kk^{-T}, computed as
+// the transposed rows Y^T = L_kk^{-1} X^T on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64; lane l holds A[l%16][l/16], B[l/16][l%16], and entry q
+// of the result C[l/16 + 4q][l%16]).  Wave v takes rows r0 + 64 v .. + 63: the B
+// entries are 16 consecutive rows of one column of the panel, the A entries come
+// from the inverse staged in LDS (zero outside w x w; it is zero above its
+// diagonal), and the results go back with 16 lanes on 16 consecutive rows.  Every
+// row of a wave is read before the wave stores any, so the update is in place.
+// Each step adds its four products in k order, as a plain FMA loop would.
+typedef double dbl4_c __attribute__((ext_vector_type(4)));
+__device__ const double g_chol_zero[1] = {0.0};
 __global__ void __launch_bounds__(PW) k_panel_trsm(const PanelDesc* __restrict__ descs) {
   const PanelDesc d = descs[blockIdx.x];
   const int w = d.w;
-  __shared__ double Xi[CHOL_NB][CHOL_NB + 1];
-  stage_inverse(d.Dinv, w, Xi);
-  __syncthreads();
-  const int r = d.r0 + threadIdx.x;
-  if (r >= d.r1) return;
-  double* row = d.P + r;
-  double x[CHOL_NB];  // x[k] for k >= w is read from column w - 1 and only enters outputs c >= w
+  __shared__ double Xi[CHOL_NB][CHOL_NB + 1];  // Xi[c][k] = L_kk^{-1}[c][k]
+  {
+    const int r = threadIdx.x & 63, c0 = threadIdx.x >> 6;
+    const int rc = r < w ? r : w - 1;
+    double v[CHOL_NB / 4];
 #pragma unroll
-  for (int k = 0; k < CHOL_NB; ++k) x[k] = gldc(row + (int64_t)(k < w ? k : w - 1) * d.ld);
-  // out[c] = sum_{k <= c} x[k] Xi[c][k]; fully unrolled so x stays in registers
+    for (int u = 0; u < CHOL_NB / 4; ++u) {
+      const int c = c0 + 4 * u;
+      v[u] = gldc(d.Dinv + rc + (c < w ? c : w - 1) * w);
+    }
 #pragma unroll
-  for (int c = 0; c < CHOL_NB; ++c) {
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k <= c; ++k) s = fma(x[k], Xi[c][k], s);
-    if (c < w) gstc(row + (int64_t)c * d.ld, s);
+    for (int u = 0; u < CHOL_NB / 4; ++u) {
+      const int c = c0 + 4 * u;
+      Xi[r][c] = (r < w && c < w) ? v[u] : 0.0;
+    }
   }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, i = lane & 15, kq = lane >> 4;
+  const int rb0 = d.r0 + 64 * (threadIdx.x >> 6);
+  if (rb0 >= d.r1) return;  // no barrier follows
+  dbl4_c acc[4][4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) acc[cb][rb] = dbl4_c{0.0, 0.0, 0.0, 0.0};
+  // entries past r1 or w read a zero constant
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    double b[8][4];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        const int r = rb0 + 16 * rb + i, k = 4 * (8 * h + j) + kq;
+        const bool ok = r < d.r1 && k < w;
+        b[j][rb] = gldc(ok ? d.P + r + (int64_t)k * d.ld : g_chol_zero);
+      }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = 4 * (8 * h + j) + kq;
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        const double a = Xi[16 * cb + i][k];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) acc[cb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[j][rb], acc[cb][rb], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      const int r = rb0 + 16 * rb + i;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = 16 * cb + kq + 4 * q;
+        if (r < d.r1 && c < w) gstc(d.P + r + (int64_t)c * d.ld, acc[cb][rb][q]);
+      }
+    }
 }
 
 // columns [c0, c1) of X (rows kb..kb+w): x <- L_kk^{-1} x
