@@ -25,6 +25,7 @@
 #include <climits>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 #include "context.h"
 
@@ -682,43 +683,83 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       HIPCHK(hipGetLastError());
     } else {
       const StepNum& pv = h->num[t - 2];
-      for (uint64_t pr : sy.before) {
-        const int32_t I = pair_i(pr), J = pair_j(pr);
-        double* dbase = lay.panel(J, E, A) + lay.find(I, J);
-        int64_t ro = 0;
-        for (int64_t a = sy.child_ptr[I]; a < sy.child_ptr[I + 1]; ++a) {
-          const int32_t i = sy.child[a];
-          const int32_t ri = pv.rank[i];
-          int64_t co = 0;
-          for (int64_t b = sy.child_ptr[J]; b < sy.child_ptr[J + 1]; ++b) {
-            const int32_t j = sy.child[b];
-            const int32_t rj = pv.rank[j];
-            if (ri > 0 && rj > 0) {
-              const int32_t hi = std::max(i, j), lo = std::min(i, j);
-              const int64_t so = lay_prev.find(hi, lo);
-              if (so >= 0) {
-                CopyDesc cd;
-                cd.src = arena_prev.as<double>() + lay_prev.base[lo] + so;
-                cd.lds = int32_t(lay_prev.H[lo]);
-                cd.trans = (i < j) ? 1 : 0;
-                cd.rows = ri;
-                cd.dst = dbase + ro + co * lay.H[J];
-                cd.ldd = int32_t(lay.H[J]);
-                const int32_t step = std::max(1, COPY_CHUNK / ri);  // column ranges of at most COPY_CHUNK entries
-                for (int32_t c0 = 0; c0 < rj; c0 += step) {
-                  cd.c0 = c0;
-                  cd.c1 = std::min(rj, c0 + step);
-                  copies.push_back(cd);
+      // the copies of the pairs [q0, q1) of `before`, in order
+      auto plan_copies = [&](size_t q0, size_t q1, std::vector<CopyDesc>& out) {
+        for (size_t q = q0; q < q1; ++q) {
+          const uint64_t pr = sy.before[q];
+          const int32_t I = pair_i(pr), J = pair_j(pr);
+          double* dbase = lay.panel(J, E, A) + lay.find(I, J);
+          int64_t ro = 0;
+          for (int64_t a = sy.child_ptr[I]; a < sy.child_ptr[I + 1]; ++a) {
+            const int32_t i = sy.child[a];
+            const int32_t ri = pv.rank[i];
+            int64_t co = 0;
+            for (int64_t b = sy.child_ptr[J]; b < sy.child_ptr[J + 1]; ++b) {
+              const int32_t j = sy.child[b];
+              const int32_t rj = pv.rank[j];
+              if (ri > 0 && rj > 0) {
+                const int32_t hi = std::max(i, j), lo = std::min(i, j);
+                const int64_t so = lay_prev.find(hi, lo);
+                if (so >= 0) {
+                  CopyDesc cd;
+                  cd.src = arena_prev.as<double>() + lay_prev.base[lo] + so;
+                  cd.lds = int32_t(lay_prev.H[lo]);
+                  cd.trans = (i < j) ? 1 : 0;
+                  cd.rows = ri;
+                  cd.dst = dbase + ro + co * lay.H[J];
+                  cd.ldd = int32_t(lay.H[J]);
+                  const int32_t step = std::max(1, COPY_CHUNK / ri);  // column ranges of at most COPY_CHUNK entries
+                  for (int32_t c0 = 0; c0 < rj; c0 += step) {
+                    cd.c0 = c0;
+                    cd.c1 = std::min(rj, c0 + step);
+                    out.push_back(cd);
+                  }
                 }
               }
+              co += rj;
             }
-            co += rj;
+            ro += ri;
           }
-          ro += ri;
+        }
+      };
+      // large steps are planned by several host threads over contiguous ranges of
+      // pairs (they only read); each thread then writes its part into the pinned
+      // staging buffer at its offset, so the list is the same as one thread's
+      const size_t npair = sy.before.size();
+      const size_t nth = std::min<size_t>(8, std::max<size_t>(1, npair / 4096));
+      if (nth == 1) {
+        plan_copies(0, npair, copies);
+        if ((st = upload(h, d_copy, copies)) != SPAND_OK) return st;
+        launch_copy(d_copy.as<CopyDesc>(), int64_t(copies.size()), h->stream);
+      } else {
+        std::vector<std::vector<CopyDesc>> part(nth);
+        {
+          std::vector<std::thread> pool;
+          for (size_t k = 1; k < nth; ++k)
+            pool.emplace_back(plan_copies, npair * k / nth, npair * (k + 1) / nth, std::ref(part[k]));
+          plan_copies(0, npair / nth, part[0]);
+          for (std::thread& th : pool) th.join();
+        }
+        std::vector<size_t> off(nth + 1, 0);
+        for (size_t k = 0; k < nth; ++k) off[k + 1] = off[k] + part[k].size();
+        const size_t bytes = off[nth] * sizeof(CopyDesc);
+        if ((st = dalloc(h, d_copy, bytes)) != SPAND_OK) return st;
+        char* hp = h->stage.get(bytes);
+        if (bytes > 0 && !hp) return set_err(h, SPAND_E_NOMEM, "pinned staging of " + std::to_string(bytes) + " bytes failed");
+        {
+          auto put = [&](size_t k) {
+            if (!part[k].empty()) std::memcpy(hp + off[k] * sizeof(CopyDesc), part[k].data(), part[k].size() * sizeof(CopyDesc));
+          };
+          std::vector<std::thread> pool;
+          for (size_t k = 1; k < nth; ++k) pool.emplace_back(put, k);
+          put(0);
+          for (std::thread& th : pool) th.join();
+        }
+        if (bytes > 0) {
+          HIPCHK(hipMemcpyAsync(d_copy.p, hp, bytes, hipMemcpyHostToDevice, h->stream));
+          launch_copy(d_copy.as<CopyDesc>(), int64_t(off[nth]), h->stream);
         }
       }
-      if ((st = upload(h, d_copy, copies)) != SPAND_OK) return st;
-      launch_copy(d_copy.as<CopyDesc>(), int64_t(copies.size()), h->stream);
       HIPCHK(hipGetLastError());
     }
 
