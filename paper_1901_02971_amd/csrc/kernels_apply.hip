@@ -531,7 +531,7 @@ __device__ inline void iface_get(const double (*buf)[RB], int k, double (&b)[RB]
 // The matrix is read in chunks of IFC entries (reads past the end are masked and
 // give 0; rows of vb beyond the matrix hold 0); the many waves of a launch hide the
 // latency of a chunk.
-#define IFC 8
+#define IFC 16
 template <int RPL, bool COLWALK>
 __device__ inline void iface_chunk(const double* __restrict__ M, int ld, int nrows, int ncols, int mode, int k0,
                                    double (&m)[IFC][RPL]) {
