@@ -54,14 +54,16 @@ __device__ inline void stage_inverse(const double* __restrict__ D, int w, double
 // updates column j = t % 64 of rows t / 64, t / 64 + 4, ... (no index division);
 // then lane c of wave 0 forms column c of L^{-1} by forward substitution, entirely
 // in registers (the rows of L are broadcast from LDS).
-__global__ void __launch_bounds__(PW) k_potrf_diag(const PotrfDesc* __restrict__ descs, int32_t* fail) {
+__global__ void __launch_bounds__(PW, 2) k_potrf_diag(const PotrfDesc* __restrict__ descs, int32_t* fail) {
   const PotrfDesc d = descs[blockIdx.x];
   const int w = d.w;
   __shared__ double D[CHOL_NB][CHOL_NB + 1];
+  __shared__ double diag[CHOL_NB];  // L_kk; D[k][k] keeps the pivot, so it is read without a barrier
   __shared__ int bad;
   const int tid = threadIdx.x;
   const int jc = tid & 63, i0 = tid >> 6;  // column and first row of this thread's share
   if (tid == 0) bad = 0;
+  if (tid < CHOL_NB) diag[tid] = 1.0;
   {
     const int jcc = jc < w ? jc : w - 1;
     double v[CHOL_NB / 4];
@@ -84,9 +86,8 @@ __global__ void __launch_bounds__(PW) k_potrf_diag(const PotrfDesc* __restrict__
       if (tid == 0) bad = 1;
     }
     const double rk = sqrt(piv);
-    __syncthreads();  // every thread has read D[k][k]
-    if (tid < 64) {
-      if (tid == k) D[k][k] = rk;
+    if (tid < 64) {  // nobody reads column k below the diagonal in this phase
+      if (tid == k) diag[k] = rk;
       if (tid > k && tid < w) D[tid][k] /= rk;
     }
     __syncthreads();
@@ -109,7 +110,7 @@ __global__ void __launch_bounds__(PW) k_potrf_diag(const PotrfDesc* __restrict__
       double acc = (i == c) ? 1.0 : 0.0;
 #pragma unroll
       for (int q = 0; q < i; ++q) acc = fma(-D[i][q], x[q], acc);
-      x[i] = (i >= c && i < w) ? acc / D[i][i] : 0.0;
+      x[i] = (i >= c && i < w) ? acc / diag[i] : 0.0;
     }
     if (c < w)
 #pragma unroll
@@ -119,7 +120,7 @@ __global__ void __launch_bounds__(PW) k_potrf_diag(const PotrfDesc* __restrict__
 #pragma unroll
   for (int s = 0; s < CHOL_NB / 4; ++s) {
     const int r = i0 + 4 * s;
-    if (r < w && jc < w && r >= jc) gstc(d.P + r + (int64_t)jc * d.ld, D[r][jc]);
+    if (r < w && jc < w && r >= jc) gstc(d.P + r + (int64_t)jc * d.ld, r == jc ? diag[jc] : D[r][jc]);
   }
   if (bad && tid == 0) atomicMin(fail, d.id);
 }
