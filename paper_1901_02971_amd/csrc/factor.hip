@@ -928,6 +928,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       int64_t house_total = 0, xch_total = 0;
       std::vector<int64_t> xch_off(nc, -1);
       std::vector<int32_t> slabS(nc, 0), tg(nc, 0), nseg(nc, 0);
+      std::vector<char> wide(nc, 0);  // single slab of the wide layout (teams of 2)
       for (int32_t p = ne; p < nc; ++p) {
         for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e)
           if (sn.size[sy.nb[e]] > 0) {
@@ -944,6 +945,10 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
         tg[p] = G;
         const int64_t cap = cpqr_capacity(G);
         slabS[p] = int32_t((ncols[p] + cap - 1) / cap);
+        if (slabS[p] > 1 && G == 2 && m <= cpqr_wide_rows() && ncols[p] <= cpqr_wide_capacity()) {
+          wide[p] = 1;  // fits one workgroup of the wide layout: no exchange between slabs
+          slabS[p] = 1;
+        }
         if (slabS[p] > 1) {
           xch_off[p] = xch_total;
           xch_total += 3 * int64_t(slabS[p]) * cpqr_record(G);  // three exchange buffers
@@ -980,14 +985,16 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       std::vector<SlabRef> all_slabs;
       size_t nlaunch = 0;
       // launch groups of one colour: single-slab interfaces per team size G
-      // (group G), then every multi-slab interface of the colour together (group 0)
+      // (group G), the wide single-slab ones (group 128), then every multi-slab
+      // interface of the colour together (group 256)
       for (int32_t c = 0; c < ncolour; ++c) {
         if (by_colour[c].empty()) continue;
-        for (int32_t grp = 1; grp <= 128; grp <<= 1) {
-          const bool multi = grp == 128;
+        for (int32_t grp = 1; grp <= 256; grp <<= 1) {
+          const bool multi = grp == 256, wgrp = grp == 128;
           std::vector<int32_t> plist;
           for (int32_t p : by_colour[c])
-            if (multi ? slabS[p] > 1 : (slabS[p] == 1 && tg[p] == grp)) plist.push_back(p);
+            if (multi ? slabS[p] > 1 : wgrp ? wide[p] != 0 : (slabS[p] == 1 && !wide[p] && tg[p] == grp))
+              plist.push_back(p);
           if (plist.empty()) continue;
           // largest first: interfaces of similar step counts share a launch
           std::stable_sort(plist.begin(), plist.end(), [&](int32_t x, int32_t y) {
@@ -995,7 +1002,8 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
             return int64_t(sn.size[x]) * ncols[x] > int64_t(sn.size[y]) * ncols[y];
           });
           size_t lds = 0;
-          for (int32_t p : plist) lds = std::max(lds, cpqr_lds_bytes(tg[p], nseg[p]));
+          for (int32_t p : plist)
+            lds = std::max(lds, wgrp ? cpqr_wide_lds_bytes(nseg[p]) : cpqr_lds_bytes(tg[p], nseg[p]));
           int cap = INT_MAX;
           if (multi) {
             cap = cpqr_max_coresident(lds);
@@ -1005,7 +1013,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
           // single-slab interfaces; for the multi-slab ones, the rounds of one launch.
           CpqrLaunch L{};
           L.multi = multi;
-          L.G = multi ? 0 : grp;
+          L.G = multi ? 0 : grp;  // 128: the wide layout
           L.lds = lds;
           L.d0 = all_sds.size();
           std::vector<std::vector<SlabRef>> rounds;
@@ -1087,8 +1095,10 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
         hipError_t le = L.multi ? launch_cpqr_multi(dd, ss, L.nslab, L.nround, b.as<SegDesc>(), tol,
                                                     curb.as<int32_t>(), nrefb.as<int32_t>(), errb.as<int32_t>(),
                                                     L.lds, h->stream)
-                                : launch_cpqr_one(L.G, dd, ss, L.nslab, b.as<SegDesc>(), tol, curb.as<int32_t>(),
-                                                  nrefb.as<int32_t>(), errb.as<int32_t>(), L.lds, h->stream);
+                    : L.G == 128 ? launch_cpqr_one_wide(dd, ss, L.nslab, b.as<SegDesc>(), tol, curb.as<int32_t>(),
+                                                        nrefb.as<int32_t>(), errb.as<int32_t>(), L.lds, h->stream)
+                                 : launch_cpqr_one(L.G, dd, ss, L.nslab, b.as<SegDesc>(), tol, curb.as<int32_t>(),
+                                                   nrefb.as<int32_t>(), errb.as<int32_t>(), L.lds, h->stream);
         if (le != hipSuccess)
           return set_err(h, SPAND_E_HIP, std::string("sparsification launch: ") + hipGetErrorString(le));
         HIPCHK(hipEventRecord(e1, h->stream));

@@ -123,6 +123,14 @@ int32_t cpqr_capacity(int32_t G);
 // Doubles of one slab's exchange record (S > 1): 4 scalars + the rows of a team.
 int32_t cpqr_record(int32_t G);
 size_t cpqr_lds_bytes(int32_t G, int32_t nseg);
+// The wide single-slab layout (teams of 2 lanes, more columns per lane): the rows
+// and columns one workgroup holds, and its dynamic LDS size.
+int32_t cpqr_wide_rows();
+int32_t cpqr_wide_capacity();
+size_t cpqr_wide_lds_bytes(int32_t nseg);
+hipError_t launch_cpqr_one_wide(const SparsDesc* d, const SlabRef* slabs, int32_t nslab, const SegDesc* seg,
+                                double eps, int32_t* cursize, int32_t* nref, int32_t* err, size_t lds_bytes,
+                                hipStream_t s);
 // Co-resident workgroups of the multi-slab kernel at this dynamic LDS size.
 int cpqr_max_coresident(size_t lds_bytes);
 // Single-slab interfaces of team size G (plain launch), and multi-slab interfaces of

@@ -40,6 +40,8 @@ namespace spand {
 #define CQ_NT 512
 #define CQ_MR 32
 #define CQ_CPL 2
+#define CQ_MR_W 28  // the wide single-slab layout for teams of 2 (k_cpqr_one_w2)
+#define CQ_CPL_W 3
 #define CQ_XH 16  // doubles of an exchange record's header: a 128-byte line of its own
 #define CW 256  // threads of k_build_t
 #define TIE_RTOL 1e-10
@@ -191,24 +193,25 @@ __device__ __forceinline__ void cpqr_load_group(const double* vl, int gi, double
 #pragma unroll
   for (int u = 0; u < 4; ++u) v[u] = vl[(4 * gi + u) * G];
 }
-__device__ __forceinline__ void cpqr_dot_group(const double (&a)[CQ_CPL][CQ_MR], int gi, const double (&v)[4],
-                                               double (&dot)[CQ_CPL]) {
+template <int MR, int CPL>
+__device__ __forceinline__ void cpqr_dot_group(const double (&a)[CPL][MR], int gi, const double (&v)[4],
+                                               double (&dot)[CPL]) {
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int k = 0; k < CQ_CPL; ++k) dot[k] = fma(v[u], a[k][4 * gi + u], dot[k]);
+    for (int k = 0; k < CPL; ++k) dot[k] = fma(v[u], a[k][4 * gi + u], dot[k]);
 }
 // a <- a - w v and the squared norm of the rows below j (jg = j - g); only the
 // group holding row j (mixed) has rows on both sides of it.
-template <int G>
-__device__ __forceinline__ void cpqr_update_group(double (&a)[CQ_CPL][CQ_MR], int gi, const double (&v)[4],
-                                                  const double (&wv)[CQ_CPL], double (&sq)[CQ_CPL], bool mixed,
+template <int G, int MR, int CPL>
+__device__ __forceinline__ void cpqr_update_group(double (&a)[CPL][MR], int gi, const double (&v)[4],
+                                                  const double (&wv)[CPL], double (&sq)[CPL], bool mixed,
                                                   int jg) {
   if (mixed) {
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int k = 0; k < CQ_CPL; ++k) {
+      for (int k = 0; k < CPL; ++k) {
         const double x = fma(-wv[k], v[u], a[k][4 * gi + u]);
         a[k][4 * gi + u] = x;
         sq[k] = ((4 * gi + u) * G > jg) ? fma(x, x, sq[k]) : sq[k];
@@ -217,7 +220,7 @@ __device__ __forceinline__ void cpqr_update_group(double (&a)[CQ_CPL][CQ_MR], in
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int k = 0; k < CQ_CPL; ++k) {
+      for (int k = 0; k < CPL; ++k) {
         const double x = fma(-wv[k], v[u], a[k][4 * gi + u]);
         a[k][4 * gi + u] = x;
         sq[k] = fma(x, x, sq[k]);
@@ -225,16 +228,17 @@ __device__ __forceinline__ void cpqr_update_group(double (&a)[CQ_CPL][CQ_MR], in
   }
 }
 
-// Slab w of interface d (w = 0, S = 1 when MULTI is false).
-template <int G, bool MULTI>
+// Slab w of interface d (w = 0, S = 1 when MULTI is false); a lane keeps MR rows
+// of CPL columns.
+template <int G, bool MULTI, int MR = CQ_MR, int CPL = CQ_CPL>
 __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const SegDesc* __restrict__ segs, double eps,
                                           int32_t* cursize, int32_t* nref, int32_t* err) {
   constexpr int NT = CQ_NT;
   constexpr int NTEAM = NT / G;
-  constexpr int CAP = CQ_CPL * NTEAM;
+  constexpr int CAP = CPL * NTEAM;
   constexpr int NW = NT / 64;
-  constexpr int ROWS = G * CQ_MR;    // rows a team can hold (>= m)
-  constexpr int NGRP = CQ_MR / 4;    // row groups: group u is rows [4uG, 4uG + 4G), registers 4u..4u+3
+  constexpr int ROWS = G * MR;    // rows a team can hold (>= m)
+  constexpr int NGRP = MR / 4;    // row groups: group u is rows [4uG, 4uG + 4G), registers 4u..4u+3
   constexpr int RPT = (ROWS + NT - 1) / NT;  // reflector rows formed per thread
   extern __shared__ double lds[];
   __shared__ double pmx[2][NW];
@@ -274,12 +278,12 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
     return;
   }
 
-  double a[CQ_CPL][CQ_MR];
-  double nrm[CQ_CPL];  // squared norm of rows j..m-1 (identical in the lanes of a team)
-  int col[CQ_CPL];     // column index in A_pn, -1 if the slot is empty
-  int pst[CQ_CPL];     // -1 remaining, >= 0 step at which the column was the pivot, -2 empty
+  double a[CPL][MR];
+  double nrm[CPL];  // squared norm of rows j..m-1 (identical in the lanes of a team)
+  int col[CPL];     // column index in A_pn, -1 if the slot is empty
+  int pst[CPL];     // -1 remaining, >= 0 step at which the column was the pivot, -2 empty
 #pragma unroll
-  for (int k = 0; k < CQ_CPL; ++k) {
+  for (int k = 0; k < CPL; ++k) {
     const int c = w * CAP + k * NTEAM + team;
     col[k] = c < nc ? c : -1;
     pst[k] = c < nc ? -1 : -2;
@@ -289,7 +293,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
     const int rows = (c < nc) ? m : 0;
     double sq = 0.0;
 #pragma unroll
-    for (int q = 0; q < CQ_MR; ++q) {
+    for (int q = 0; q < MR; ++q) {
       const int i = q * G + g;
       const double v = (i < rows) ? base[(int64_t)i * stride] : 0.0;
       a[k][q] = v;
@@ -307,10 +311,10 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
     const int jg = j - g;  // row q * G + g of this lane lies below row j iff q * G > jg
     // ---- pivot of this slab: the largest remaining norm M, then the smallest column
     // index whose norm is >= M (1 - TIE_RTOL); two exact reductions
-    double nv[CQ_CPL];
+    double nv[CPL];
     double lmx = -1.0;
 #pragma unroll
-    for (int k = 0; k < CQ_CPL; ++k) {
+    for (int k = 0; k < CPL; ++k) {
       nv[k] = (pst[k] == -1) ? sqrt(nrm[k]) : -1.0;
       lmx = fmax(lmx, nv[k]);
     }
@@ -325,7 +329,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
       const double thr = smx * (1.0 - TIE_RTOL);
       int c = INT_MAX;
 #pragma unroll
-      for (int k = 0; k < CQ_CPL; ++k)
+      for (int k = 0; k < CPL; ++k)
         if (pst[k] == -1 && nv[k] >= thr) c = min(c, col[k]);
       c = wave_min(c);
       if (lane == 0) pcd[j & 1][wave] = c;
@@ -350,7 +354,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
       // the owner team publishes its column and the squared norm of its rows below j
       if (own) {
 #pragma unroll
-        for (int k = 0; k < CQ_CPL; ++k)
+        for (int k = 0; k < CPL; ++k)
           if (k == pk) {
             double s2 = 0.0;
 #pragma unroll
@@ -379,15 +383,15 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
     } else {
       // publish (slab max, slab candidate + 1, its norm, its rows and its squared
       // norm below j).  The rows of a record are stored lane-major: row q * G + g
-      // at g * CQ_MR + q.
+      // at g * MR + q.
       const int tg = ((j >> 1) & 1) ^ 1;
       {
         double* rw = xrec(j & 1, w);
         if (own) {
 #pragma unroll
-          for (int k = 0; k < CQ_CPL; ++k)
+          for (int k = 0; k < CPL; ++k)
             if (k == pk) {
-              double* rl = rw + CQ_XH + g * CQ_MR;
+              double* rl = rw + CQ_XH + g * MR;
               double s2 = 0.0;
 #pragma unroll
               for (int gi = 0; gi < NGRP; ++gi) {
@@ -477,7 +481,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
         const double thr = xg_mx * (1.0 - TIE_RTOL);
         int c2 = INT_MAX;
 #pragma unroll
-        for (int k = 0; k < CQ_CPL; ++k)
+        for (int k = 0; k < CPL; ++k)
           if (pst[k] == -1 && nv[k] >= thr) c2 = min(c2, col[k]);
         c2 = wave_min(c2);
         if (lane == 0) pcd[j & 1][wave] = c2;  // free: every wave has read pcd[j & 1]
@@ -490,12 +494,12 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
         if (best != INT_MAX && team == lc2 % NTEAM) {
           const int pk2 = lc2 / NTEAM;
 #pragma unroll
-          for (int k = 0; k < CQ_CPL; ++k)
+          for (int k = 0; k < CPL; ++k)
             if (k == pk2) {
-              double* rl = rw + CQ_XH + g * CQ_MR;
+              double* rl = rw + CQ_XH + g * MR;
               double s2 = 0.0;
 #pragma unroll
-              for (int q = 0; q < CQ_MR; ++q) {
+              for (int q = 0; q < MR; ++q) {
                 shared_store(rl + q, a[k][q]);
                 s2 = (q * G > jg) ? fma(a[k][q], a[k][q], s2) : s2;
               }
@@ -546,7 +550,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
       rc = xrec(xb, piv / CAP);
       pn = word_val(shared_load(rc + 1));
       x2 = shared_load(rc + 2);
-      alpha = shared_load(rc + CQ_XH + (j % G) * CQ_MR + j / G);
+      alpha = shared_load(rc + CQ_XH + (j % G) * MR + j / G);
     }
     if (j == 0) {
       r00 = pn;
@@ -573,7 +577,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
       for (int u = 0; u < RPT; ++u) {
         const int i = tid + u * NT;
         if constexpr (MULTI)
-          xs[u] = (i > j && i < m) ? shared_load(rc + CQ_XH + (i % G) * CQ_MR + i / G) : 0.0;
+          xs[u] = (i > j && i < m) ? shared_load(rc + CQ_XH + (i % G) * MR + i / G) : 0.0;
         else
           xs[u] = (i < ROWS) ? cv[i] : 0.0;
       }
@@ -595,7 +599,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
       const int plc = piv - w * CAP;
       if (plc >= 0 && plc < CAP && team == plc % NTEAM) {
 #pragma unroll
-        for (int k = 0; k < CQ_CPL; ++k)
+        for (int k = 0; k < CPL; ++k)
           if (k == plc / NTEAM) pst[k] = j;
       }
     }
@@ -609,9 +613,9 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
     // v of a group is read one group ahead into two register sets used by even
     // and odd groups in turn, so the reads overlap the previous group's FMAs
     double va[4], vb[4];
-    double dot[CQ_CPL];
+    double dot[CPL];
 #pragma unroll
-    for (int k = 0; k < CQ_CPL; ++k) dot[k] = 0.0;
+    for (int k = 0; k < CPL; ++k) dot[k] = 0.0;
     if (uj & 1) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) vb[u] = vl[(4 * uj + u) * G];
@@ -623,16 +627,16 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
     for (int gp = 0; gp < NGRP; gp += 2) {
       if (gp >= uj && gp < uend) {
         cpqr_load_group<G>(vl, gp + 1, vb);  // unconditional: a fixed count of LDS reads in flight
-        cpqr_dot_group(a, gp, va, dot);
+        cpqr_dot_group<MR, CPL>(a, gp, va, dot);
       }
       if (gp + 1 >= uj && gp + 1 < uend) {
         if (gp + 2 < NGRP) cpqr_load_group<G>(vl, gp + 2, va);
-        cpqr_dot_group(a, gp + 1, vb, dot);
+        cpqr_dot_group<MR, CPL>(a, gp + 1, vb, dot);
       }
     }
-    double wv[CQ_CPL], sq[CQ_CPL];
+    double wv[CPL], sq[CPL];
 #pragma unroll
-    for (int k = 0; k < CQ_CPL; ++k) {
+    for (int k = 0; k < CPL; ++k) {
       dot[k] = team_sum<G>(dot[k]);
       wv[k] = (pst[k] == -1) ? tau * dot[k] : 0.0;
       sq[k] = 0.0;
@@ -648,21 +652,21 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
     for (int gp = 0; gp < NGRP; gp += 2) {
       if (gp >= uj && gp < uend) {
         cpqr_load_group<G>(vl, gp + 1, vb);  // unconditional: a fixed count of LDS reads in flight
-        cpqr_update_group<G>(a, gp, va, wv, sq, gp == uj, jg);
+        cpqr_update_group<G, MR, CPL>(a, gp, va, wv, sq, gp == uj, jg);
       }
       if (gp + 1 >= uj && gp + 1 < uend) {
         if (gp + 2 < NGRP) cpqr_load_group<G>(vl, gp + 2, va);
-        cpqr_update_group<G>(a, gp + 1, vb, wv, sq, gp + 1 == uj, jg);
+        cpqr_update_group<G, MR, CPL>(a, gp + 1, vb, wv, sq, gp + 1 == uj, jg);
       }
     }
 #pragma unroll
-    for (int k = 0; k < CQ_CPL; ++k) nrm[k] = team_sum<G>(sq[k]);
+    for (int k = 0; k < CPL; ++k) nrm[k] = team_sum<G>(sq[k]);
   }
   __syncthreads();  // rb complete
   // ---- W_cn = R[:r, :] (column order of A_pn) into the blocks of p.  A pivot
   // column of step s holds R_ij for i < s; its row s is R_ss and the rows below are 0.
 #pragma unroll
-  for (int k = 0; k < CQ_CPL; ++k) {
+  for (int k = 0; k < CPL; ++k) {
     if (col[k] < 0 || r == 0) continue;
     double* base;
     int64_t stride;
@@ -670,7 +674,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
     const int ps = pst[k];
     const double rss = (ps >= 0) ? rb[ps] : 0.0;
 #pragma unroll
-    for (int q = 0; q < CQ_MR; ++q) {
+    for (int q = 0; q < MR; ++q) {
       const int i = q * G + g;
       if (i < r) base[(int64_t)i * stride] = (ps >= 0 && i >= ps) ? ((i == ps) ? rss : 0.0) : a[k][q];
     }
@@ -695,6 +699,17 @@ __global__ void __launch_bounds__(CQ_NT) k_cpqr_one(const SparsDesc* __restrict_
                                                     int32_t* nref, int32_t* err) {
   const SlabRef sr = slabs[blockIdx.x];
   cpqr_slab<G, false>(descs[sr.desc], 0, segs, eps, cursize, nref, err);
+}
+
+// Single-slab interfaces of at most 2 * CQ_MR_W rows whose width needs more than
+// one slab of the standard layout: teams of 2 lanes with CQ_MR_W rows and
+// CQ_CPL_W columns per lane, so one workgroup holds CQ_CPL_W * CQ_NT / 2 columns.
+__global__ void __launch_bounds__(CQ_NT) k_cpqr_one_w2(const SparsDesc* __restrict__ descs,
+                                                       const SlabRef* __restrict__ slabs,
+                                                       const SegDesc* __restrict__ segs, double eps, int32_t* cursize,
+                                                       int32_t* nref, int32_t* err) {
+  const SlabRef sr = slabs[blockIdx.x];
+  cpqr_slab<2, false, CQ_MR_W, CQ_CPL_W>(descs[sr.desc], 0, segs, eps, cursize, nref, err);
 }
 
 // Multi-slab interfaces of every team size in one cooperative launch: each
@@ -783,6 +798,19 @@ size_t cpqr_lds_bytes(int32_t G, int32_t nseg) {
 }
 
 int32_t cpqr_record(int32_t G) { return G * CQ_MR + CQ_XH; }
+
+int32_t cpqr_wide_rows() { return 2 * CQ_MR_W; }
+int32_t cpqr_wide_capacity() { return CQ_CPL_W * CQ_NT / 2; }
+size_t cpqr_wide_lds_bytes(int32_t nseg) {
+  return 3 * size_t(2) * CQ_MR_W * sizeof(double) + (size_t(nseg) + 1) * sizeof(int32_t) + 16;
+}
+hipError_t launch_cpqr_one_wide(const SparsDesc* d, const SlabRef* slabs, int32_t nslab, const SegDesc* seg,
+                                double eps, int32_t* cursize, int32_t* nref, int32_t* err, size_t lds,
+                                hipStream_t s) {
+  if (nslab == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cpqr_one_w2, dim3(nslab), dim3(CQ_NT), lds, s, d, slabs, seg, eps, cursize, nref, err);
+  return hipGetLastError();
+}
 
 int cpqr_max_coresident(size_t lds) {
   int per_cu = 0;
