@@ -1069,13 +1069,48 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
               launches.push_back(P);
             }
           } else {
-            size_t grid = 0;
-            for (const auto& rd : rounds) grid = std::max(grid, rd.size());
+            // List scheduling over the co-resident workgroups: each interface, in
+            // plist order, takes the slabS workgroups that free up first, by an
+            // estimate of the steps (min(m, ncols) bounds the rank).  A workgroup runs
+            // its slabs in that same order, so the earliest unfinished interface has
+            // all its slabs at the heads of their lists: no cycle of waits.
+            std::vector<std::pair<const SlabRef*, int32_t>> ifs;  // first slab, count
+            for (const auto& rd : rounds)
+              for (size_t k = 0; k < rd.size();) {
+                size_t e = k;
+                while (e < rd.size() && rd[e].desc == rd[k].desc) ++e;
+                ifs.emplace_back(&rd[k], int32_t(e - k));
+                k = e;
+              }
+            if (ifs.size() != plist.size()) return set_err(h, SPAND_E_INVALID, "sparsification schedule: interfaces and slabs disagree");
+            size_t total = 0;
+            for (const auto& f : ifs) total += size_t(f.second);
+            const size_t grid = std::min(total, size_t(cap));
+            std::vector<double> busy(grid, 0.0);
+            std::vector<std::vector<SlabRef>> lists(grid);
+            std::vector<int32_t> wg(grid);
+            for (size_t q = 0; q < ifs.size(); ++q) {
+              const int32_t p = plist[q];
+              const int32_t S = ifs[q].second;
+              std::iota(wg.begin(), wg.end(), 0);
+              std::partial_sort(wg.begin(), wg.begin() + S, wg.end(), [&](int32_t x, int32_t y) {
+                return busy[x] < busy[y] || (busy[x] == busy[y] && x < y);
+              });
+              double t = 0.0;
+              for (int32_t k = 0; k < S; ++k) t = std::max(t, busy[wg[k]]);
+              t += double(std::min<int64_t>(sn.size[p], ncols[p]));
+              for (int32_t k = 0; k < S; ++k) {
+                lists[wg[k]].push_back(ifs[q].first[k]);
+                busy[wg[k]] = t;
+              }
+            }
+            size_t nround = 0;
+            for (const auto& l : lists) nround = std::max(nround, l.size());
             L.s0 = all_slabs.size();
             L.nslab = int32_t(grid);
-            L.nround = int32_t(rounds.size());
-            for (const auto& rd : rounds)
-              for (size_t b = 0; b < grid; ++b) all_slabs.push_back(b < rd.size() ? rd[b] : SlabRef{-1, 0});
+            L.nround = int32_t(nround);
+            for (size_t k = 0; k < nround; ++k)
+              for (size_t b = 0; b < grid; ++b) all_slabs.push_back(k < lists[b].size() ? lists[b][k] : SlabRef{-1, 0});
             launches.push_back(L);
           }
         }

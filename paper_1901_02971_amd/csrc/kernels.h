@@ -137,7 +137,8 @@ int cpqr_max_coresident(size_t lds_bytes);
 // any team size (cooperative launch: all nslab workgroups resident).
 hipError_t launch_cpqr_one(int32_t G, const SparsDesc* d, const SlabRef* slabs, int32_t nslab, const SegDesc* seg,
                            double eps, int32_t* cursize, int32_t* nref, int32_t* err, size_t lds_bytes, hipStream_t s);
-// The multi-slab launch runs nround rounds of nslab places (slabs[k * nslab + b]).
+// The multi-slab launch gives workgroup b the places slabs[k * nslab + b], k < nround,
+// in turn; the interfaces must appear in one order in every workgroup's places.
 hipError_t launch_cpqr_multi(const SparsDesc* d, const SlabRef* slabs, int32_t nslab, int32_t nround,
                              const SegDesc* seg, double eps, int32_t* cursize, int32_t* nref, int32_t* err,
                              size_t lds_bytes, hipStream_t s);

@@ -53,7 +53,7 @@ namespace {
 // index cd among the columns with norm >= mx (1 - TIE_RTOL), its norm cn, and amb
 // set when the exact smallest index at a larger threshold is not known.
 struct Cand {
-  double mx, cn;
+  double mx, cn, x2;  // x2: squared norm below row j of candidate cd
   int cd, amb;
 };
 
@@ -66,13 +66,16 @@ __device__ inline Cand cand_combine(const Cand& a, const Cand& b) {
   o.amb = a.amb | b.amb | ((!oka && a.mx >= thr) ? 1 : 0) | ((!okb && b.mx >= thr) ? 1 : 0);
   o.cd = INT_MAX;
   o.cn = -1.0;
+  o.x2 = 0.0;
   if (oka) {
     o.cd = a.cd;
     o.cn = a.cn;
+    o.x2 = a.x2;
   }
   if (okb && b.cd < o.cd) {
     o.cd = b.cd;
     o.cn = b.cn;
+    o.x2 = b.x2;
   }
   return o;
 }
@@ -158,11 +161,14 @@ __device__ inline double word_val(double x) {
   return __longlong_as_double((long long)((unsigned long long)__double_as_longlong(x) & 0x7FFFFFFFFFFFFFFFull));
 }
 
+// Global-space accesses: flat ones would also hold up every wait for LDS.
+typedef __attribute__((address_space(1))) double gdouble;
+__device__ double g_cq_zero;  // read by the loads of an empty column slot
 __device__ inline double shared_load(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load((const gdouble*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ inline void shared_store(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store((gdouble*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // the error flag of the launch, read by a poll so that it stops after a time-out
 __device__ inline bool timed_out(int32_t* err) {
@@ -244,10 +250,14 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
   __shared__ double pmx[2][NW];
   __shared__ int pcd[2][NW];
   __shared__ double sh_pn, sh_x2;
-  __shared__ double xg_mx;  // result of the header reduction of the current exchange
+  __shared__ double xg_mx, xg_pn, xg_x2;  // result of the header reduction of the current exchange
   __shared__ int xg_cd, xg_amb;
   const int m = d.m, S = MULTI ? d.S : 1, w = MULTI ? wslab : 0;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int tid = threadIdx.x;
+  // the round loop of the multi-slab kernel would otherwise hoist the row indices
+  // of every slab out of the loop and keep them live, in scratch, for its duration
+  if constexpr (MULTI) asm volatile("" : "+v"(tid));
+  const int lane = tid & 63, wave = tid >> 6;
   const int g = lane & (G - 1), team = tid / G;
   const int nseg = d.seg_end - d.seg_begin;
   const SegDesc* sg = segs + d.seg_begin;
@@ -287,15 +297,28 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
     const int c = w * CAP + k * NTEAM + team;
     col[k] = c < nc ? c : -1;
     pst[k] = c < nc ? -1 : -2;
-    double* base = nullptr;
+    // every load is issued (a row outside the column reads row 0, an empty slot
+    // reads g_cq_zero), so the loads of a column are in flight together
+    const gdouble* base = (const gdouble*)&g_cq_zero;
     int64_t stride = 0;
-    if (c < nc) column_ptr(sg, segoff, c, base, stride);
+    if (c < nc) {
+      double* b;
+      column_ptr(sg, segoff, c, b, stride);
+      base = (const gdouble*)b;
+    }
     const int rows = (c < nc) ? m : 0;
-    double sq = 0.0;
 #pragma unroll
     for (int q = 0; q < MR; ++q) {
       const int i = q * G + g;
-      const double v = (i < rows) ? base[(int64_t)i * stride] : 0.0;
+      a[k][q] = base[(i < rows ? i : 0) * (int)stride];
+    }
+    // keep the loads ahead of their uses: scheduled among them the loads would
+    // be issued one at a time
+    __builtin_amdgcn_sched_barrier(0);
+    double sq = 0.0;
+#pragma unroll
+    for (int q = 0; q < MR; ++q) {
+      const double v = (q * G + g < rows) ? a[k][q] : 0.0;
       a[k][q] = v;
       sq = fma(v, v, sq);
     }
@@ -379,7 +402,6 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
       piv = scd;
       pn = sh_pn;
       x2 = sh_x2;
-      alpha = cv[j];
     } else {
       // publish (slab max, slab candidate + 1, its norm, its rows and its squared
       // norm below j).  The rows of a record are stored lane-major: row q * G + g
@@ -406,7 +428,6 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
               }
               s2 = team_sum<G>(s2);
               if (g == 0) {
-                shared_store(rw + 2, s2);
                 // the team lies in one wave: once this wave's stores have completed
                 // the rows are visible, and the header may follow
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -414,6 +435,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
                 shared_store(rw, tag_word(smx, tg));
                 shared_store(rw + 1, tag_word(nv[k], tg));
+                shared_store(rw + 2, tag_word(s2, tg));
                 shared_store(rw + 3, tag_word((double)scd + 1.0, tg));
               }
             }
@@ -421,13 +443,14 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
         if (scd == INT_MAX && tid == 0) {  // no candidate left in this slab
           shared_store(rw, tag_word(0.0, tg));
           shared_store(rw + 1, tag_word(0.0, tg));
+          shared_store(rw + 2, tag_word(0.0, tg));
           shared_store(rw + 3, tag_word(0.0, tg));
         }
       }
       int xb = j & 1;
       // wave 0 polls the S headers (one memory round trip per poll) and reduces them
-      // like the lanes: lanes 0..P-1 end with the same result.  The owning slab of
-      // column c is c / CAP.
+      // like the lanes: lanes 0..P-1 end with the same result, which carries the
+      // winner's norm and squared norm below j.  The owning slab of column c is c / CAP.
       if (wave == 0) {
         int P = 1;
         while (P < S && P < 64) P <<= 1;
@@ -435,17 +458,20 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
         for (long spins = 0;; ++spins) {
           u.mx = -1.0;
           u.cn = -1.0;
+          u.x2 = 0.0;
           u.cd = INT_MAX;
           u.amb = 0;
           int ok = 1;
           for (int q = lane; q < S; q += 64) {  // S may exceed the wave size
             const double* rq = xrec(xb, q);
-            const double w0 = shared_load(rq), w1 = shared_load(rq + 1), w3 = shared_load(rq + 3);
-            ok &= (word_tag(w0) == tg) & (word_tag(w1) == tg) & (word_tag(w3) == tg);
+            const double w0 = shared_load(rq), w1 = shared_load(rq + 1), w2 = shared_load(rq + 2),
+                         w3 = shared_load(rq + 3);
+            ok &= (word_tag(w0) == tg) & (word_tag(w1) == tg) & (word_tag(w2) == tg) & (word_tag(w3) == tg);
             const double cq = word_val(w3);
             Cand v;
             v.mx = (cq > 0.0) ? word_val(w0) : -1.0;
             v.cn = (cq > 0.0) ? word_val(w1) : -1.0;
+            v.x2 = word_val(w2);
             v.cd = (cq > 0.0) ? (int)cq - 1 : INT_MAX;
             v.amb = 0;
             u = cand_combine(u, v);
@@ -462,6 +488,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
           Cand v;
           v.mx = __shfl_xor(u.mx, o, 64);
           v.cn = __shfl_xor(u.cn, o, 64);
+          v.x2 = __shfl_xor(u.x2, o, 64);
           v.cd = __shfl_xor(u.cd, o, 64);
           v.amb = __shfl_xor(u.amb, o, 64);
           u = cand_combine(u, v);
@@ -470,6 +497,8 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
           xg_mx = u.mx;
           xg_cd = u.cd;
           xg_amb = u.amb;
+          xg_pn = u.cn;
+          xg_x2 = u.x2;
         }
       }
       __syncthreads();
@@ -548,9 +577,13 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
         break;
       }
       rc = xrec(xb, piv / CAP);
-      pn = word_val(shared_load(rc + 1));
-      x2 = shared_load(rc + 2);
-      alpha = shared_load(rc + CQ_XH + (j % G) * MR + j / G);
+      if (xb == 2) {  // second round: its header is read here
+        pn = word_val(shared_load(rc + 1));
+        x2 = shared_load(rc + 2);
+      } else {
+        pn = xg_pn;
+        x2 = xg_x2;
+      }
     }
     if (j == 0) {
       r00 = pn;
@@ -564,22 +597,33 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
       break;
     }
     // every thread forms the reflector (LAPACK dlarfg convention) with identical
-    // arithmetic, then its share of the rows of v
-    double tau = 0.0, scale = 0.0, beta = alpha;
-    if (x2 != 0.0) {
-      beta = -copysign(sqrt(alpha * alpha + x2), alpha);
-      tau = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
-    }
+    // arithmetic, then its share of the rows of v; alpha (row j of the pivot column)
+    // and the rows are read together
+    double tau = 0.0, scale = 0.0, beta;
     {
       double xs[RPT];
 #pragma unroll
       for (int u = 0; u < RPT; ++u) {
         const int i = tid + u * NT;
-        if constexpr (MULTI)
-          xs[u] = (i > j && i < m) ? shared_load(rc + CQ_XH + (i % G) * MR + i / G) : 0.0;
-        else
+        if constexpr (MULTI) {
+          // every thread loads (row j when its row is not below j): the loads of
+          // all rows are in flight together
+          const bool use = i > j && i < m;
+          const int ir = use ? i : j;
+          const double x = shared_load(rc + CQ_XH + (ir % G) * MR + ir / G);
+          xs[u] = use ? x : 0.0;
+        } else
           xs[u] = (i < ROWS) ? cv[i] : 0.0;
+      }
+      if constexpr (MULTI)
+        alpha = shared_load(rc + CQ_XH + (j % G) * MR + j / G);
+      else
+        alpha = cv[j];
+      beta = alpha;
+      if (x2 != 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + x2), alpha);
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
       }
 #pragma unroll
       for (int u = 0; u < RPT; ++u) {
@@ -713,12 +757,12 @@ __global__ void __launch_bounds__(CQ_NT) k_cpqr_one_w2(const SparsDesc* __restri
 }
 
 // Multi-slab interfaces of every team size in one cooperative launch: each
-// workgroup takes the code path of its interface's G.  The launch runs nround
-// rounds; place b of round k is slabs[k * gridDim.x + b] (a negative descriptor
-// index leaves it unused).  All slabs of an interface lie in one round, and a
-// workgroup starts round k only after its slab of round k - 1 has finished, so every
-// slab it waits for is in the same round on a workgroup that has finished the
-// earlier rounds: round 0 completes, and by induction every later one.
+// workgroup takes the code path of its interface's G.  Workgroup b runs the slabs
+// slabs[k * gridDim.x + b], k = 0 .. nround - 1, in turn (a negative descriptor
+// index is an unused place).  The host numbers the interfaces and every workgroup's
+// slabs come in that order, so the lowest-numbered unfinished interface has each of
+// its slabs at the head of its workgroup's remaining list (all workgroups are
+// resident): it completes, and by induction every later one.
 __global__ void __launch_bounds__(CQ_NT) k_cpqr_multi(const SparsDesc* __restrict__ descs,
                                                       const SlabRef* __restrict__ slabs, int32_t nround,
                                                       const SegDesc* __restrict__ segs, double eps,
