@@ -929,6 +929,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       std::vector<int64_t> xch_off(nc, -1);
       std::vector<int32_t> slabS(nc, 0), tg(nc, 0), nseg(nc, 0);
       std::vector<char> wide(nc, 0);  // single slab of the wide layout (teams of 2)
+      std::vector<int32_t> rlay(nc, 0);  // register layout of a multi-slab interface
       for (int32_t p = ne; p < nc; ++p) {
         for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e)
           if (sn.size[sy.nb[e]] > 0) {
@@ -949,9 +950,19 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
           wide[p] = 1;  // fits one workgroup of the wide layout: no exchange between slabs
           slabS[p] = 1;
         }
-        if (slabS[p] > 1) {
+        if (slabS[p] > 1) {  // layout 1 when it needs fewer slabs (and still more than one)
+          const int32_t G1 = cpqr_team(sn.size[p], 1);
+          if (G1 > 0) {
+            const int64_t cap1 = cpqr_capacity(G1, 1);
+            const int32_t S1 = int32_t((ncols[p] + cap1 - 1) / cap1);
+            if (S1 > 1 && S1 < slabS[p]) {
+              rlay[p] = 1;
+              tg[p] = G1;
+              slabS[p] = S1;
+            }
+          }
           xch_off[p] = xch_total;
-          xch_total += 3 * int64_t(slabS[p]) * cpqr_record(G);  // three exchange buffers
+          xch_total += 3 * int64_t(slabS[p]) * cpqr_record(tg[p], rlay[p]);  // three exchange buffers
         }
         const int64_t kmax = std::min<int64_t>(sn.size[p], ncols[p]);
         v_off[p] = house_total;
@@ -1003,7 +1014,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
           });
           size_t lds = 0;
           for (int32_t p : plist)
-            lds = std::max(lds, wgrp ? cpqr_wide_lds_bytes(nseg[p]) : cpqr_lds_bytes(tg[p], nseg[p]));
+            lds = std::max(lds, wgrp ? cpqr_wide_lds_bytes(nseg[p]) : cpqr_lds_bytes(tg[p], rlay[p], nseg[p]));
           int cap = INT_MAX;
           if (multi) {
             cap = cpqr_max_coresident(lds);
@@ -1034,6 +1045,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
               d.id = p;
               d.S = slabS[p];
               d.G = tg[p];
+              d.lay = rlay[p];
               if (multi) d.xch = xchb.as<double>() + xch_off[p];
               d.seg_begin = int32_t(all_segs.size());
               for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e) {

@@ -89,7 +89,8 @@ struct SparsDesc {
   double* diag;    // diagonal block of p (ld ldd), set to I_r on exit
   double* xch;     // slab exchange (S > 1): 3 buffers x S records of cpqr_record(G) doubles, zeroed
                    // before the launch
-  int32_t m, ldd, seg_begin, seg_end, id, S, G, pad;  // G: lanes per column (team size)
+  int32_t m, ldd, seg_begin, seg_end, id, S, G, lay;  // G: lanes per column (team size);
+                                                      // lay: register layout (multi-slab kernel)
 };
 struct SegDesc {
   double* blk;  // block holding A_pq: trans=0 -> A_pq[r][c] = blk[r + c*ld]; trans=1 -> blk[c + r*ld]
@@ -117,12 +118,14 @@ void launch_set_identity(const IdentDesc* d, int32_t count, hipStream_t s);
 // stored (0 when no coupled dofs were left and p was not sparsified).  err
 // receives bit 2 if a slab barrier timed out.  Launches with more than one slab
 // per interface are cooperative (all workgroups resident).
+// Register layouts of a slab: lay 0 keeps 32 rows of 2 columns per lane (every
+// kernel), lay 1 20 rows of 3 columns (multi-slab kernel only).
 // Team size G (lanes per column, a power of two) for m rows; -1 if m is too large.
-int32_t cpqr_team(int32_t m);
-int32_t cpqr_capacity(int32_t G);
-// Doubles of one slab's exchange record (S > 1): 4 scalars + the rows of a team.
-int32_t cpqr_record(int32_t G);
-size_t cpqr_lds_bytes(int32_t G, int32_t nseg);
+int32_t cpqr_team(int32_t m, int32_t lay = 0);
+int32_t cpqr_capacity(int32_t G, int32_t lay = 0);
+// Doubles of one slab's exchange record (S > 1): the header + the rows of a team.
+int32_t cpqr_record(int32_t G, int32_t lay = 0);
+size_t cpqr_lds_bytes(int32_t G, int32_t lay, int32_t nseg);
 // The wide single-slab layout (teams of 2 lanes, more columns per lane): the rows
 // and columns one workgroup holds, and its dynamic LDS size.
 int32_t cpqr_wide_rows();

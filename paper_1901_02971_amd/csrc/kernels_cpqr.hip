@@ -42,6 +42,8 @@ namespace spand {
 #define CQ_CPL 2
 #define CQ_MR_W 28  // the wide single-slab layout for teams of 2 (k_cpqr_one_w2)
 #define CQ_CPL_W 3
+#define CQ_MR_1 20  // layout 1 of the multi-slab kernel: fewer rows, more columns per lane
+#define CQ_CPL_1 3
 #define CQ_XH 16  // doubles of an exchange record's header: a 128-byte line of its own
 #define CW 256  // threads of k_build_t
 #define TIE_RTOL 1e-10
@@ -771,16 +773,20 @@ __global__ void __launch_bounds__(CQ_NT) k_cpqr_multi(const SparsDesc* __restric
     const SlabRef sr = slabs[(size_t)rd * gridDim.x + blockIdx.x];
     if (sr.desc < 0) continue;
     const SparsDesc d = descs[sr.desc];
-    switch (d.G) {
-      case 1: cpqr_slab<1, true>(d, sr.w, segs, eps, cursize, nref, err); break;
-      case 2: cpqr_slab<2, true>(d, sr.w, segs, eps, cursize, nref, err); break;
-      case 4: cpqr_slab<4, true>(d, sr.w, segs, eps, cursize, nref, err); break;
-      case 8: cpqr_slab<8, true>(d, sr.w, segs, eps, cursize, nref, err); break;
-      case 16: cpqr_slab<16, true>(d, sr.w, segs, eps, cursize, nref, err); break;
-      case 32: cpqr_slab<32, true>(d, sr.w, segs, eps, cursize, nref, err); break;
-      case 64: cpqr_slab<64, true>(d, sr.w, segs, eps, cursize, nref, err); break;
-      default: break;  // the host only builds the team sizes above
+#define CQ_CASE(GG)                                                                   \
+  case GG: cpqr_slab<GG, true>(d, sr.w, segs, eps, cursize, nref, err); break;       \
+  case GG | 256: cpqr_slab<GG, true, CQ_MR_1, CQ_CPL_1>(d, sr.w, segs, eps, cursize, nref, err); break;
+    switch (d.G | (d.lay << 8)) {
+      CQ_CASE(1)
+      CQ_CASE(2)
+      CQ_CASE(4)
+      CQ_CASE(8)
+      CQ_CASE(16)
+      CQ_CASE(32)
+      CQ_CASE(64)
+      default: break;  // the host only builds the team sizes and layouts above
     }
+#undef CQ_CASE
     __syncthreads();  // the LDS of this slab is reused by the next round's
   }
 }
@@ -829,19 +835,20 @@ void launch_build_t_diag(const TBlock* blocks, int32_t count, hipStream_t s) {
   if (count > 0) hipLaunchKernelGGL(k_build_t_diag, dim3(count), dim3(CW), 0, s, blocks);
 }
 
-int32_t cpqr_team(int32_t m) {
+static int32_t layout_rows(int32_t lay) { return lay == 1 ? CQ_MR_1 : CQ_MR; }
+int32_t cpqr_team(int32_t m, int32_t lay) {
   int32_t G = 1;
-  while (G * CQ_MR < m) G <<= 1;
+  while (G * layout_rows(lay) < m) G <<= 1;
   return G <= 64 ? G : -1;
 }
 
-int32_t cpqr_capacity(int32_t G) { return CQ_CPL * CQ_NT / G; }
+int32_t cpqr_capacity(int32_t G, int32_t lay) { return (lay == 1 ? CQ_CPL_1 : CQ_CPL) * CQ_NT / G; }
 
-size_t cpqr_lds_bytes(int32_t G, int32_t nseg) {
-  return 3 * size_t(G) * CQ_MR * sizeof(double) + (size_t(nseg) + 1) * sizeof(int32_t) + 16;
+size_t cpqr_lds_bytes(int32_t G, int32_t lay, int32_t nseg) {
+  return 3 * size_t(G) * layout_rows(lay) * sizeof(double) + (size_t(nseg) + 1) * sizeof(int32_t) + 16;
 }
 
-int32_t cpqr_record(int32_t G) { return G * CQ_MR + CQ_XH; }
+int32_t cpqr_record(int32_t G, int32_t lay) { return G * layout_rows(lay) + CQ_XH; }
 
 int32_t cpqr_wide_rows() { return 2 * CQ_MR_W; }
 int32_t cpqr_wide_capacity() { return CQ_CPL_W * CQ_NT / 2; }
