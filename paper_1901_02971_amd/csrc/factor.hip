@@ -24,6 +24,7 @@
 #include <chrono>
 #include <climits>
 #include <cstring>
+#include <functional>
 #include <numeric>
 #include <thread>
 
@@ -1098,22 +1099,29 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
             size_t total = 0;
             for (const auto& f : ifs) total += size_t(f.second);
             const size_t grid = std::min(total, size_t(cap));
-            std::vector<double> busy(grid, 0.0);
             std::vector<std::vector<SlabRef>> lists(grid);
-            std::vector<int32_t> wg(grid);
+            // min-heap of (time the workgroup frees up, workgroup)
+            using Slot = std::pair<int64_t, int32_t>;
+            std::vector<Slot> heap(grid);
+            for (size_t b = 0; b < grid; ++b) heap[b] = Slot{0, int32_t(b)};
+            std::make_heap(heap.begin(), heap.end(), std::greater<Slot>());
+            std::vector<int32_t> wg;
             for (size_t q = 0; q < ifs.size(); ++q) {
               const int32_t p = plist[q];
               const int32_t S = ifs[q].second;
-              std::iota(wg.begin(), wg.end(), 0);
-              std::partial_sort(wg.begin(), wg.begin() + S, wg.end(), [&](int32_t x, int32_t y) {
-                return busy[x] < busy[y] || (busy[x] == busy[y] && x < y);
-              });
-              double t = 0.0;
-              for (int32_t k = 0; k < S; ++k) t = std::max(t, busy[wg[k]]);
-              t += double(std::min<int64_t>(sn.size[p], ncols[p]));
+              wg.clear();
+              int64_t t = 0;
+              for (int32_t k = 0; k < S; ++k) {
+                std::pop_heap(heap.begin(), heap.end(), std::greater<Slot>());
+                t = std::max(t, heap.back().first);
+                wg.push_back(heap.back().second);
+                heap.pop_back();
+              }
+              t += std::min<int64_t>(sn.size[p], ncols[p]);
               for (int32_t k = 0; k < S; ++k) {
                 lists[wg[k]].push_back(ifs[q].first[k]);
-                busy[wg[k]] = t;
+                heap.push_back(Slot{t, wg[k]});
+                std::push_heap(heap.begin(), heap.end(), std::greater<Slot>());
               }
             }
             size_t nround = 0;
@@ -1175,10 +1183,13 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
           sn.rank[p] = rk[p];
           const int64_t r = nref[p];
           {
-            const double m = sn.size[p], nq = double(ncols[p]);
-            for (int64_t j = 0; j < r; ++j)
-              cpqr_flops += 2.0 * (m - j) * (nq - j) + 4.0 * (m - j) * (nq - j - 1) + 3.0 * (m - j);
-            if (r < std::min<int64_t>(sn.size[p], ncols[p])) cpqr_flops += 2.0 * (m - r) * (nq - r);
+            // sum over steps j < r of 2 (m-j)(n-j) + 4 (m-j)(n-j-1) + 3 (m-j)
+            // = 6 (m-j)(n-j) - (m-j), in closed form (exact in 64-bit integers)
+            const int64_t m = sn.size[p], nq = ncols[p];
+            const int64_t s1 = r * (r - 1) / 2, s2 = (r - 1) * r * (2 * r - 1) / 6;
+            const int64_t f = 6 * (r * m * nq - (m + nq) * s1 + s2) - (r * m - s1);
+            cpqr_flops += double(f);
+            if (r < std::min<int64_t>(m, nq)) cpqr_flops += 2.0 * double(m - r) * double(nq - r);
           }
           m_F += (2 * int64_t(sn.size[p]) - r + 1) * r / 2 + r;
           if (r > 0)
