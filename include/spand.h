@@ -89,6 +89,10 @@ typedef struct {
   int64_t apply_calls;
   int32_t apply_graph;    /* 1 if the last solve replayed its apply from a captured graph */
   int32_t reserved2;
+  /* Interfaces of the last factor by the register layout of their CPQR: one workgroup
+   * (32 rows x 2 columns per lane), one workgroup of the wide layout (teams of 2
+   * lanes, 28 rows x 3 columns), several workgroups with 32 x 2, several with 20 x 3. */
+  int64_t cpqr_interfaces[4];
 } spand_stats;
 
 /* Ordering, clustering and symbolic factorization (Algorithm 2 with a geometric

@@ -510,6 +510,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
   double elim_flops = 0.0, elim_ms = 0.0;
   double cpqr_flops = 0.0, cpqr_ms = 0.0;
   int64_t cpqr_launches = 0;
+  int64_t cpqr_ifaces[4] = {0, 0, 0, 0};  // single, wide, multi (32 x 2), multi (20 x 3)
   int32_t s_top = 0;
 
   DevBuf arena_prev;
@@ -983,6 +984,8 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       // current sizes: interfaces shrink to their rank as their colour class finishes
       if ((st = upload(h, curb, sn.size)) != SPAND_OK) return st;
       if ((st = upload(h, nrefb, std::vector<int32_t>(nc, 0))) != SPAND_OK) return st;
+      for (int32_t p = ne; p < nc; ++p)
+        if (v_off[p] >= 0) ++cpqr_ifaces[slabS[p] > 1 ? 2 + rlay[p] : (wide[p] ? 1 : 0)];
       std::vector<std::vector<int32_t>> by_colour(ncolour);
       for (int32_t p = ne; p < nc; ++p)
         if (v_off[p] >= 0) by_colour[sy.colour[p]].push_back(p);
@@ -1236,6 +1239,7 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
   h->stats.cpqr_flops = cpqr_flops;
   h->stats.cpqr_seconds = cpqr_ms * 1e-3;
   h->stats.cpqr_launches = cpqr_launches;
+  for (int q = 0; q < 4; ++q) h->stats.cpqr_interfaces[q] = cpqr_ifaces[q];
   return SPAND_OK;
 }
 

@@ -37,11 +37,12 @@ class Stats(C.Structure):
                 ("step_phase_seconds", (C.c_double * 4) * 32), ("step_m_F", C.c_int64 * 32),
                 ("cpqr_flops", C.c_double), ("cpqr_seconds", C.c_double), ("cpqr_launches", C.c_int64),
                 ("apply_bytes", C.c_double), ("apply_seconds", C.c_double), ("apply_calls", C.c_int64),
-                ("apply_graph", C.c_int32), ("reserved2", C.c_int32)]
+                ("apply_graph", C.c_int32), ("reserved2", C.c_int32), ("cpqr_interfaces", C.c_int64 * 4)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_
-             if k not in ("reserved", "reserved2", "step_phase_seconds", "step_m_F")}
+             if k not in ("reserved", "reserved2", "step_phase_seconds", "step_m_F", "cpqr_interfaces")}
+        d["cpqr_interfaces"] = [int(v) for v in self.cpqr_interfaces]
         L = max(0, min(32, int(self.n_steps)))
         d["step_phase_seconds"] = [[self.step_phase_seconds[t][q] for q in range(4)] for t in range(L)]
         d["step_m_F"] = [int(self.step_m_F[t]) for t in range(L)]

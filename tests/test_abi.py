@@ -26,6 +26,32 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+def test_stats_struct_matches_header(tmp_path):
+    """The ctypes mirror of spand_stats has the size and field offsets the C compiler
+    gives the header's struct (a C program built with the host compiler prints them)."""
+    import os
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    fields = [name for name, _ in S.Stats._fields_]
+    src = ["#include <stddef.h>", "#include <stdio.h>", '#include "spand.h"', "int main(void) {",
+           '  printf("%zu\\n", sizeof(spand_stats));']
+    src += [f'  printf("%zu\\n", offsetof(spand_stats, {f}));' for f in fields]
+    src += ["  return 0;", "}"]
+    c = tmp_path / "stats.c"
+    c.write_text("\n".join(src) + "\n")
+    exe = tmp_path / "stats"
+    r = subprocess.run([cc, "-std=c11", "-I", inc, str(c), "-o", str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert vals[0] == ctypes.sizeof(S.Stats)
+    for f, off in zip(fields, vals[1:]):
+        assert getattr(S.Stats, f).offset == off, f
+
+
 CASES = [((7, 7), 3), ((6, 4), 2), ((16, 16), 5), ((64, 64), 6), ((9, 7, 6), 4), ((8, 8, 8), 5),
          ((24, 31, 40), 7), ((32, 32, 32), 9), ((5, 5, 5), 1), ((3, 2), 4)]
 

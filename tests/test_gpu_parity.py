@@ -102,13 +102,18 @@ def test_multi_rhs_columns_independent():
 def test_apply_many_rhs_matches_oracle():
     """Eleven right-hand sides (a full block of eight and a ragged block of three) through
     the tiled apply products, on a 24^3 Laplacian at 5 levels whose upper clusters span
-    several 64-wide tiles with a ragged last tile."""
+    several 64-wide tiles with a ragged last tile.  Its interfaces take every CPQR
+    register layout: one workgroup, the wide single workgroup, and several workgroups
+    in each of the two multi-slab layouts; the ranks and the apply (which reads the
+    reflectors, T factors and W blocks they wrote) are checked against the oracle."""
     p = gridgen.laplacian((24, 24, 24))
     b = gridgen.rhs(np.random.default_rng(12), p.n, 11)
     an, fac = oracle_run(p, 5, 1e-2)
     s = gpu_factor(p, 5, 1e-2)
     assert rank_mismatches(s, an, fac) == 0
-    assert s.stats()["s_top"] > 64
+    st = s.stats()
+    assert st["s_top"] > 64
+    assert all(k > 0 for k in st["cpqr_interfaces"]), st["cpqr_interfaces"]
     z = gpu_apply(s, b)
     zr = O.apply(fac, b)
     assert np.abs(z - zr).max() <= 1e-10 * np.abs(zr).max()
