@@ -197,26 +197,42 @@ spand_status blocked_cholesky(spand_ctx* h, const std::vector<Front>& F, int32_t
     }
     pcut.push_back(int64_t(pd.size()));
     tcut.push_back(int64_t(td.size()));
-    for (const Front& f : F) {  // trailing update inside the pivot block (FP64, lower tiles)
+    // Trailing updates, two block columns at a time: after an even block column only
+    // the next one is updated (it is factored next); after an odd one, the last two
+    // block columns go into every column beyond in one product of depth 2 NB, so the
+    // far trailing matrix is read and written half as often.
+    const bool pair = (kb / CHOL_NB) & 1;
+    for (const Front& f : F) {  // trailing update inside the pivot block (FP64)
       if (f.n <= kb) continue;
       const int32_t w = std::min(CHOL_NB, f.n - kb);
+      const int32_t ks = pair ? kb - CHOL_NB : kb, c0 = kb + w;
+      const int32_t c1 = pair ? f.n : std::min(f.n, c0 + CHOL_NB);
+      if (c1 <= c0) continue;
       GemmDesc q{};
-      q.A = f.P + (kb + w) + int64_t(kb) * f.ld; q.lda = f.ld;
+      q.A = f.P + c0 + int64_t(ks) * f.ld; q.lda = f.ld;
       q.B = q.A; q.ldb = f.ld;
-      q.C = f.P + (kb + w) + int64_t(kb + w) * f.ld; q.ldc = f.ld;
-      q.M = f.n - kb - w; q.N = f.n - kb - w; q.K = w;
-      q.flags = G_TB | G_LOWERC; q.alpha = -1.0; q.beta = 1.0;
-      g.add(q, 1);
+      q.C = f.P + c0 + int64_t(c0) * f.ld; q.ldc = f.ld;
+      q.M = f.n - c0; q.N = c1 - c0; q.K = kb + w - ks;
+      q.flags = G_TB; q.alpha = -1.0; q.beta = 1.0;
+      if (pair) {  // square: the lower tiles only
+        q.flags |= G_LOWERC;
+        g.add(q, 1);
+      } else {     // one block column: every tile is on or below the diagonal
+        g.add(q, 0);
+      }
     }
     g.end_launch(0);
     for (const Front& f : F) {  // rows below the pivot block
       if (f.n <= kb) continue;
       const int32_t w = std::min(CHOL_NB, f.n - kb);
+      const int32_t ks = pair ? kb - CHOL_NB : kb, c0 = kb + w;
+      const int32_t c1 = pair ? f.n : std::min(f.n, c0 + CHOL_NB);
+      if (c1 <= c0 || f.m <= f.n) continue;
       GemmDesc q{};
-      q.A = f.P + f.n + int64_t(kb) * f.ld; q.lda = f.ld;
-      q.B = f.P + (kb + w) + int64_t(kb) * f.ld; q.ldb = f.ld;
-      q.C = f.P + f.n + int64_t(kb + w) * f.ld; q.ldc = f.ld;
-      q.M = f.m - f.n; q.N = f.n - kb - w; q.K = w;
+      q.A = f.P + f.n + int64_t(ks) * f.ld; q.lda = f.ld;
+      q.B = f.P + c0 + int64_t(ks) * f.ld; q.ldb = f.ld;
+      q.C = f.P + f.n + int64_t(c0) * f.ld; q.ldc = f.ld;
+      q.M = f.m - f.n; q.N = c1 - c0; q.K = kb + w - ks;
       q.flags = G_TB; q.alpha = -1.0; q.beta = 1.0;
       g.add(q, 0);
     }
