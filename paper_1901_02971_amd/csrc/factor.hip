@@ -272,17 +272,22 @@ spand_status left_trsm(spand_ctx* h, const std::vector<LeftBlock>& B) {
   std::vector<int64_t> lcut;
   GemmSeq g;
   for (int32_t kb = 0; kb < nmax; kb += CHOL_NB) {
+    // as in blocked_cholesky: after an even block row only the next one is updated,
+    // after an odd one the last two go into every row below at depth 2 NB
+    const bool pair = (kb / CHOL_NB) & 1;
     for (const LeftBlock& b : B) {
       if (b.nrows <= kb) continue;
       const int32_t w = std::min(CHOL_NB, b.nrows - kb);
       const double* Dk = b.dinv + int64_t(kb / CHOL_NB) * CHOL_NB * CHOL_NB;
       for (int32_t c0 = 0; c0 < b.ncols; c0 += 256)
         ld.push_back(LeftDesc{b.X + kb, Dk, b.ldx, w, c0, std::min(b.ncols, c0 + 256)});
+      const int32_t ks = pair ? kb - CHOL_NB : kb, r0 = kb + w;
+      const int32_t r1 = pair ? b.nrows : std::min(b.nrows, r0 + CHOL_NB);
       GemmDesc q{};
-      q.A = b.L + (kb + w) + int64_t(kb) * b.ldl; q.lda = b.ldl;
-      q.B = b.X + kb; q.ldb = b.ldx;
-      q.C = b.X + kb + w; q.ldc = b.ldx;
-      q.M = b.nrows - kb - w; q.N = b.ncols; q.K = w;
+      q.A = b.L + r0 + int64_t(ks) * b.ldl; q.lda = b.ldl;
+      q.B = b.X + ks; q.ldb = b.ldx;
+      q.C = b.X + r0; q.ldc = b.ldx;
+      q.M = r1 - r0; q.N = b.ncols; q.K = kb + w - ks;
       q.flags = 0; q.alpha = -1.0; q.beta = 1.0;
       g.add(q, 0);
     }
