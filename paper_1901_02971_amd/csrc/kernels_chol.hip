@@ -54,7 +54,7 @@ __device__ inline void stage_inverse(const double* __restrict__ D, int w, double
 // updates column j = t % 64 of rows t / 64, t / 64 + 4, ... (no index division);
 // then lane c of wave 0 forms column c of L^{-1} by forward substitution, entirely
 // in registers (the rows of L are broadcast from LDS).
-__global__ void __launch_bounds__(PW, 2) k_potrf_diag(const PotrfDesc* __restrict__ descs, int32_t* fail) {
+__global__ void __launch_bounds__(PW, 3) k_potrf_diag(const PotrfDesc* __restrict__ descs, int32_t* fail) {
   const PotrfDesc d = descs[blockIdx.x];
   const int w = d.w;
   __shared__ double D[CHOL_NB][CHOL_NB + 1];
