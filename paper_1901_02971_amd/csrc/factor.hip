@@ -179,6 +179,8 @@ int64_t dinv_size(int32_t n) { return int64_t((n + CHOL_NB - 1) / CHOL_NB) * CHO
 // Right-looking blocked Cholesky of every front in lockstep over its diagonal
 // blocks.  Updates inside the n x n pivot block are FP64; `prec_below` selects the
 // arithmetic of the rows below it (the TRSM and Schur-side updates).
+#define CHOL_GROUP 3  // block columns per trailing-update group
+
 spand_status blocked_cholesky(spand_ctx* h, const std::vector<Front>& F, int32_t* d_fail, int prec_below) {
   int32_t nmax = 0;
   for (const Front& f : F) nmax = std::max(nmax, f.n);
@@ -197,15 +199,18 @@ spand_status blocked_cholesky(spand_ctx* h, const std::vector<Front>& F, int32_t
     }
     pcut.push_back(int64_t(pd.size()));
     tcut.push_back(int64_t(td.size()));
-    // Trailing updates, two block columns at a time: after an even block column only
-    // the next one is updated (it is factored next); after an odd one, the last two
-    // block columns go into every column beyond in one product of depth 2 NB, so the
-    // far trailing matrix is read and written half as often.
-    const bool pair = (kb / CHOL_NB) & 1;
+    // Trailing updates in groups of CHOL_GROUP block columns: inside a group only the
+    // next block column is updated (it is factored next), with every block of the
+    // group so far; at the group's last block, the group goes into every column beyond
+    // in one product of depth CHOL_GROUP NB, so the far trailing matrix is read and
+    // written once per group.
+    const int32_t kblk = kb / CHOL_NB;
+    const bool pair = (kblk % CHOL_GROUP) == CHOL_GROUP - 1;
+    const int32_t kg = (kblk / CHOL_GROUP) * CHOL_GROUP * CHOL_NB;  // first column of the group
     for (const Front& f : F) {  // trailing update inside the pivot block (FP64)
       if (f.n <= kb) continue;
       const int32_t w = std::min(CHOL_NB, f.n - kb);
-      const int32_t ks = pair ? kb - CHOL_NB : kb, c0 = kb + w;
+      const int32_t ks = kg, c0 = kb + w;
       const int32_t c1 = pair ? f.n : std::min(f.n, c0 + CHOL_NB);
       if (c1 <= c0) continue;
       GemmDesc q{};
@@ -225,7 +230,7 @@ spand_status blocked_cholesky(spand_ctx* h, const std::vector<Front>& F, int32_t
     for (const Front& f : F) {  // rows below the pivot block
       if (f.n <= kb) continue;
       const int32_t w = std::min(CHOL_NB, f.n - kb);
-      const int32_t ks = pair ? kb - CHOL_NB : kb, c0 = kb + w;
+      const int32_t ks = kg, c0 = kb + w;
       const int32_t c1 = pair ? f.n : std::min(f.n, c0 + CHOL_NB);
       if (c1 <= c0 || f.m <= f.n) continue;
       GemmDesc q{};
@@ -272,16 +277,18 @@ spand_status left_trsm(spand_ctx* h, const std::vector<LeftBlock>& B) {
   std::vector<int64_t> lcut;
   GemmSeq g;
   for (int32_t kb = 0; kb < nmax; kb += CHOL_NB) {
-    // as in blocked_cholesky: after an even block row only the next one is updated,
-    // after an odd one the last two go into every row below at depth 2 NB
-    const bool pair = (kb / CHOL_NB) & 1;
+    // grouped as in blocked_cholesky: inside a group only the next block row is
+    // updated, at the group's end every row below, at depth CHOL_GROUP NB
+    const int32_t kblk = kb / CHOL_NB;
+    const bool pair = (kblk % CHOL_GROUP) == CHOL_GROUP - 1;
+    const int32_t kg = (kblk / CHOL_GROUP) * CHOL_GROUP * CHOL_NB;
     for (const LeftBlock& b : B) {
       if (b.nrows <= kb) continue;
       const int32_t w = std::min(CHOL_NB, b.nrows - kb);
       const double* Dk = b.dinv + int64_t(kb / CHOL_NB) * CHOL_NB * CHOL_NB;
       for (int32_t c0 = 0; c0 < b.ncols; c0 += 256)
         ld.push_back(LeftDesc{b.X + kb, Dk, b.ldx, w, c0, std::min(b.ncols, c0 + 256)});
-      const int32_t ks = pair ? kb - CHOL_NB : kb, r0 = kb + w;
+      const int32_t ks = kg, r0 = kb + w;
       const int32_t r1 = pair ? b.nrows : std::min(b.nrows, r0 + CHOL_NB);
       GemmDesc q{};
       q.A = b.L + r0 + int64_t(ks) * b.ldl; q.lda = b.ldl;
