@@ -39,7 +39,8 @@ typedef enum {
   SPAND_E_NOCONV = 3,  /* PCG hit maxit; x, iters, relres are still written */
   SPAND_E_NOMEM = 4,   /* device or host allocation failed */
   SPAND_E_HIP = 5,     /* a HIP runtime call failed (text in spand_error_string) */
-  SPAND_E_STATE = 6    /* call out of order (e.g. solve before factor) */
+  SPAND_E_STATE = 6,   /* call out of order (e.g. solve before factor) */
+  SPAND_E_BREAKDOWN = 7 /* PCG produced a non-finite residual; x, iters, relres are still written */
 } spand_status;
 
 /* Arithmetic of the dense Schur-complement products (TRSM-by-inverse and SYRK of
@@ -93,7 +94,31 @@ typedef struct {
    * (32 rows x 2 columns per lane), one workgroup of the wide layout (teams of 2
    * lanes, 28 rows x 3 columns), several workgroups with 32 x 2, several with 20 x 3. */
   int64_t cpqr_interfaces[4];
+  /* Interfaces of the last factor by the kernels of their apply (Sec. 2.8 scaling and
+   * Householder products): the fused one-wave kernel for at most 64 dofs, the fused
+   * kernel for 65..fuse_max dofs (see spand_tuning), the tiled kernels otherwise. */
+  int64_t apply_interfaces[3];
+  /* Residual replacements in the last solve: columns whose recursive residual met
+   * rtol while the true residual did not, and which went on from the true one. */
+  int64_t pcg_replacements;
 } spand_stats;
+
+/* Kernel-shape and path parameters of a handle.  None of them changes what is
+ * computed; they change how the work is cut into launches (and, for chol_group,
+ * the order of the roundings inside the blocked Cholesky updates).
+ *   chol_group    64-wide block columns per trailing-update group of the blocked
+ *                 Cholesky and of the left scaling (1..4; default 3)
+ *   fuse128_min   the apply's fused one-wave kernel also takes interfaces of 65..128
+ *                 dofs when a step has at least this many of them (default 256;
+ *                 0 = always, -1 = never)
+ *   gemm_variant  output tile of the batched matrix-core GEMM (see spand_autotune)
+ */
+typedef struct {
+  int32_t chol_group;
+  int32_t fuse128_min;
+  int32_t gemm_variant;
+  int32_t reserved[5];
+} spand_tuning;
 
 /* Ordering, clustering and symbolic factorization (Algorithm 2 with a geometric
  * vertex separator, Sec. 2.3; cluster hierarchy, Sec. 2.7; fill pattern, Sec. 2.4).
@@ -119,6 +144,8 @@ spand_status spand_analyze(int64_t n, const int64_t* rowptr, const int32_t* coli
 spand_status spand_factor(spand_t h, const double* values, double tol, int32_t skip, spand_prec prec);
 
 /* PCG with the preconditioner M M^T, x0 = 0, FP64 (Sec. 4: stop at ||Ax-b||/||b|| <= rtol).
+ * A column stops when its true residual meets rtol; the recursive residual is the
+ * cheap test that triggers forming the true one (residual replacement otherwise).
  *   nrhs     number of right-hand sides (>= 1)
  *   b        device, n x nrhs column-major
  *   x        device, n x nrhs column-major, output
@@ -127,7 +154,9 @@ spand_status spand_factor(spand_t h, const double* values, double tol, int32_t s
  *   iters    host, nrhs ints: iterations taken per RHS (0 for b = 0)
  *   relres   host, nrhs doubles: true relative residual ||b - A x|| / ||b|| at exit
  * Errors: SPAND_E_STATE (no factor), SPAND_E_INVALID (non-finite b),
- * SPAND_E_NOCONV (some RHS hit maxit; outputs still written), SPAND_E_HIP. */
+ * SPAND_E_BREAKDOWN (a residual norm became NaN or Inf, e.g. from a corrupted factor;
+ * that column stops, outputs still written), SPAND_E_NOCONV (some RHS hit maxit;
+ * outputs still written), SPAND_E_HIP. */
 spand_status spand_solve(spand_t h, int32_t nrhs, const double* b, double* x, double rtol,
                          int32_t maxit, int32_t* iters, double* relres);
 
@@ -145,6 +174,11 @@ spand_status spand_set_stream(spand_t h, void* hip_stream);
  * kernel by kernel instead; results are identical.  If the runtime refuses the
  * capture, spand_solve falls back to kernel-by-kernel launches. */
 spand_status spand_set_apply_graph(spand_t h, int32_t enable);
+
+/* Set or read the tuning parameters of h (spand_tuning).  The set applies from the
+ * next factor on.  Errors: SPAND_E_INVALID for a value out of range. */
+spand_status spand_set_tuning(spand_t h, const spand_tuning* t);
+spand_status spand_get_tuning(spand_t h, spand_tuning* t);
 
 /* Copy the statistics of the last analyze/factor/solve into *s. */
 spand_status spand_get_stats(spand_t h, spand_stats* s);

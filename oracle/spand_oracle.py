@@ -18,7 +18,7 @@ Contents, each following the cited passage:
                       truncation rule of Sec. 4 (intro), merge (Sec. 2.7).
   * ``apply``         z = M M^T r with M from Sec. 2.8 (operator order of the
                       caption of the spaND illustration figure).
-  * ``pcg``           CG preconditioned by M M^T, stopped at ||r||/||b|| <= rtol (Sec. 4).
+  * ``pcg``           CG preconditioned by M M^T, stopped at ||b-Ax||/||b|| <= rtol (Sec. 4).
   * ``cpqr``          column-pivoted Householder QR (Businger-Golub pivoting).
 
 Readings of points the paper leaves open are listed where they are used and are
@@ -32,9 +32,13 @@ from dataclasses import dataclass, field
 import numpy as np
 from scipy.linalg import solve_triangular
 
-# Relative window inside which CPQR column norms count as tied; among tied
-# columns the one with the smallest original index is the pivot.
+# Relative window inside which CPQR column norms count as tied.  Among tied
+# columns the pivot is the one with the smallest original column index
+# (tie="original", the default), or the one at the smallest current position
+# after the swaps of the earlier steps (tie="position", the rule of LAPACK's
+# geqp3, whose idamax takes the first maximum).
 TIE_RTOL = 1e-10
+TIE_RULES = ("original", "position")
 
 
 class NotSPD(Exception):
@@ -293,18 +297,21 @@ def householder(x):
     return v, tau, beta
 
 
-def cpqr(A, eps):
+def cpqr(A, eps, tie="original"):
     """Truncated column-pivoted Householder QR of A (m x n) (Sec. 2.6.1, Sec. 4 intro).
 
     At step j the norms of the trailing columns A[j:, j:] are recomputed; the pivot
     is, among the columns whose norm is within TIE_RTOL of the largest, the one
-    with the smallest original column index (ties are a reading: the paper's
-    routine, geqp3, does not define them as part of the method).  The rank r
+    with the smallest original column index (tie="original") or the one at the
+    smallest current position (tie="position").  Ties are a reading: the paper's
+    routine, geqp3, does not define them as part of the method.  The rank r
     is the number of leading steps with |R_jj| >= eps |R_00| (r = 0 when R_00 = 0,
     r = min(m, n) when no step fails).  Returns (r, V, tau, W, perm) where V (m x r)
     holds the reflectors (unit first entry, zero above), and W = (Q^T A)[:r, :],
     i.e. R[:r, :] with the column permutation undone.
     """
+    if tie not in TIE_RULES:
+        raise ValueError(f"tie must be one of {TIE_RULES}")
     A = np.array(A, dtype=np.float64, copy=True)
     m, n = A.shape
     perm = np.arange(n)
@@ -317,7 +324,10 @@ def cpqr(A, eps):
         norms = np.sqrt(np.sum(A[j:, j:] ** 2, axis=0))
         cmax = norms.max()
         cand = np.nonzero(norms >= cmax * (1.0 - TIE_RTOL))[0]
-        piv = j + int(cand[np.argmin(perm[j + cand])])
+        if tie == "original":
+            piv = j + int(cand[np.argmin(perm[j + cand])])
+        else:
+            piv = j + int(cand[0])
         if j == 0:
             r00 = norms[piv - j]
             if r00 == 0.0:
@@ -395,8 +405,16 @@ def _get(blocks, i, j):
     return blocks[(j, i)].T
 
 
-def factor(an: Analysis, values, tol):
-    """Algorithm 3: returns a Factor, or raises NotSPD(step, cluster, phase)."""
+def factor(an: Analysis, values, tol, tie="original", on_sparsify=None):
+    """Algorithm 3: returns a Factor, or raises NotSPD(step, cluster, phase).
+
+    ``tie`` selects the CPQR tie rule (see ``cpqr``).  ``on_sparsify``, when given,
+    is called as on_sparsify(t, p, nbrs, sizes, blocks, Apn, result) right before the
+    sparsification of interface p at step t writes its result back: ``blocks`` is the
+    live trailing matrix (scaled, so A_pp = I), ``Apn`` the gathered row block and
+    ``result`` the tuple returned by ``cpqr``.  It lets tests inspect the step in
+    context; it must not modify anything.
+    """
     n = an.n
     steps = an.steps
     values = np.asarray(values, dtype=np.float64)
@@ -474,7 +492,10 @@ def factor(an: Analysis, values, tol):
                     sf.ranks[p] = sizes[p]
                     continue
                 Apn = np.hstack([_get(blocks, p, q) for q in nb])
-                r, V, tau, W, _ = cpqr(Apn, tol)
+                res = cpqr(Apn, tol, tie)
+                if on_sparsify is not None:
+                    on_sparsify(t, p, nb, list(sizes), blocks, Apn, res)
+                r, V, tau, W, _ = res
                 col = 0
                 for q in nb:
                     wq = W[:, col:col + sizes[q]]
@@ -548,11 +569,23 @@ def apply(fac: Factor, r):
     return x
 
 
+class Breakdown(Exception):
+    """PCG produced a non-finite residual norm (column, iteration)."""
+
+    def __init__(self, column, iteration):
+        super().__init__(f"PCG breakdown in column {column} at iteration {iteration}")
+        self.column, self.iteration = column, iteration
+
+
 def pcg(A, b, precond, rtol=1e-12, maxit=500):
     """Preconditioned CG (Hestenes-Stiefel), x0 = 0, one right-hand side per column.
 
-    Stops a column when its recursive residual satisfies ||r|| <= rtol ||b||; the
-    iteration count is the number of updates of x.  Returns (x, iters, true relres).
+    The target is the true residual, ||b - A x|| <= rtol ||b|| (Sec. 4).  The
+    recursive residual r is the cheap test: when it passes, the true residual is
+    formed; if that also passes the column stops, otherwise r is replaced by the
+    true residual and the iteration goes on (residual replacement).  The iteration
+    count is the number of updates of x.  A non-finite residual norm raises
+    Breakdown.  Returns (x, iters, true relres).
     """
     b = np.asarray(b, dtype=np.float64)
     if b.ndim == 1:
@@ -578,8 +611,14 @@ def pcg(A, b, precond, rtol=1e-12, maxit=500):
             x += alpha * p
             r -= alpha * q
             it += 1
-            if np.linalg.norm(r) <= rtol * nb:
-                break
+            rn = np.linalg.norm(r)
+            if not np.isfinite(rn):
+                raise Breakdown(c, it)
+            if rn <= rtol * nb:
+                rt = bc - A @ x
+                if np.linalg.norm(rt) <= rtol * nb:
+                    break
+                r = rt
             z = precond(r[:, None])[:, 0]
             rz_new = r @ z
             p = z + (rz_new / rz) * p

@@ -265,6 +265,22 @@ spand_status spand_set_apply_graph(spand_t h, int32_t enable) {
   return SPAND_OK;
 }
 
+spand_status spand_set_tuning(spand_t h, const spand_tuning* t) {
+  if (!h || !t) return fail_null(SPAND_E_INVALID, "NULL argument");
+  if (t->chol_group < 1 || t->chol_group > 4) return set_err(h, SPAND_E_INVALID, "chol_group must be in [1, 4]");
+  if (t->fuse128_min < -1) return set_err(h, SPAND_E_INVALID, "fuse128_min must be >= -1");
+  if (t->gemm_variant < 0 || t->gemm_variant >= spand::gemm_variant_count())
+    return set_err(h, SPAND_E_INVALID, "unknown gemm_variant");
+  h->tune = *t;
+  return SPAND_OK;
+}
+
+spand_status spand_get_tuning(spand_t h, spand_tuning* t) {
+  if (!h || !t) return fail_null(SPAND_E_INVALID, "NULL argument");
+  *t = h->tune;
+  return SPAND_OK;
+}
+
 spand_status spand_get_stats(spand_t h, spand_stats* s) {
   if (!h || !s) return fail_null(SPAND_E_INVALID, "NULL argument");
   *s = h->stats;

@@ -214,6 +214,7 @@ struct StepNum {
 
 struct spand_ctx {
   spand::Analysis an;
+  spand_tuning tune = spand::default_tuning();
   std::string err;
   hipStream_t stream = nullptr;
   spand_stats stats{};

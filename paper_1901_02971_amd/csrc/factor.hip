@@ -179,9 +179,9 @@ int64_t dinv_size(int32_t n) { return int64_t((n + CHOL_NB - 1) / CHOL_NB) * CHO
 // Right-looking blocked Cholesky of every front in lockstep over its diagonal
 // blocks.  Updates inside the n x n pivot block are FP64; `prec_below` selects the
 // arithmetic of the rows below it (the TRSM and Schur-side updates).
-#define CHOL_GROUP 3  // block columns per trailing-update group
-
+// The trailing updates go in groups of h->tune.chol_group block columns.
 spand_status blocked_cholesky(spand_ctx* h, const std::vector<Front>& F, int32_t* d_fail, int prec_below) {
+  const int32_t CHOL_GROUP = std::max(1, h->tune.chol_group);
   int32_t nmax = 0;
   for (const Front& f : F) nmax = std::max(nmax, f.n);
   std::vector<PotrfDesc> pd;
@@ -271,6 +271,7 @@ struct LeftBlock {
 };
 
 spand_status left_trsm(spand_ctx* h, const std::vector<LeftBlock>& B) {
+  const int32_t CHOL_GROUP = std::max(1, h->tune.chol_group);
   int32_t nmax = 0;
   for (const LeftBlock& b : B) nmax = std::max(nmax, b.nrows);
   std::vector<LeftDesc> ld;
@@ -408,7 +409,7 @@ spand_status build_apply(spand_ctx* h, const SymStep& sy, StepNum& sn, const Lay
   int32_t n128 = 0;
   for (int32_t p = ne; p < nc; ++p)
     if (sc_off[p] >= 0 && sn.size[p] > 64 && sn.size[p] <= 128) ++n128;
-  const int32_t fuse_max = n128 >= 256 ? 128 : 64;
+  const int32_t fuse_max = (h->tune.fuse128_min >= 0 && n128 >= h->tune.fuse128_min) ? 128 : 64;
   for (int32_t p = ne; p < nc; ++p) {
     if (sc_off[p] >= 0 && sn.size[p] <= fuse_max) {
       IfaceAp f{};
@@ -1268,6 +1269,12 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
   h->stats.cpqr_seconds = cpqr_ms * 1e-3;
   h->stats.cpqr_launches = cpqr_launches;
   for (int q = 0; q < 4; ++q) h->stats.cpqr_interfaces[q] = cpqr_ifaces[q];
+  for (int q = 0; q < 3; ++q) h->stats.apply_interfaces[q] = 0;
+  for (const StepNum& sn : h->num) {
+    h->stats.apply_interfaces[0] += sn.n_iface1;
+    h->stats.apply_interfaces[1] += sn.n_iface2;
+    h->stats.apply_interfaces[2] += sn.n_scale;
+  }
   return SPAND_OK;
 }
 

@@ -110,6 +110,8 @@ void launch_scatter_values(const double* vals, const int64_t* dst, int64_t nnz, 
 void launch_expand_tiles(const GemmDesc* d, int32_t nd, int32_t* tile_desc, hipStream_t s);
 // Tiles [tile0, tile0 + ntiles) of a sequence, one workgroup each.
 void launch_gemm(const GemmDesc* d, const int32_t* tile_desc, int64_t tile0, int64_t ntiles, int prec, hipStream_t s);
+// Number of output-tile variants of the batched GEMM (spand_tuning.gemm_variant).
+int gemm_variant_count();
 void launch_reduce(const ReduceDesc* d, int32_t count, const ContribDesc* c, hipStream_t s);
 void launch_copy(const CopyDesc* d, int64_t count, hipStream_t s);
 void launch_set_identity(const IdentDesc* d, int32_t count, hipStream_t s);

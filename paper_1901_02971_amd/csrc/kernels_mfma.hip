@@ -271,6 +271,8 @@ void launch_expand_tiles(const GemmDesc* d, int32_t nd, int32_t* tile_desc, hipS
   if (nd > 0) hipLaunchKernelGGL(k_expand_tiles, dim3(nd), dim3(64), 0, s, d, tile_desc);
 }
 
+int gemm_variant_count() { return 1; }
+
 void launch_gemm(const GemmDesc* d, const int32_t* tile_desc, int64_t tile0, int64_t ntiles, int prec,
                  hipStream_t s) {
   if (ntiles == 0) return;

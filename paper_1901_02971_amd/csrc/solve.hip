@@ -3,10 +3,12 @@
 // PCG (Hestenes-Stiefel), x0 = 0, independent per right-hand side:
 //   r = b, z = M M^T r, p = z, rz = r.z
 //   repeat: q = A p; alpha = rz / p.q; x += alpha p; r -= alpha q;
-//           stop a column when ||r|| <= rtol ||b||; z = M M^T r;
-//           beta = r.z / rz; p = z + beta p.
-// Scalars stay on the device; the host reads the residual norms once per
-// iteration to retire converged columns.
+//           if ||r|| <= rtol ||b||: form the true residual b - A x; stop the column
+//           if it passes too, else replace r by it (residual replacement);
+//           z = M M^T r; beta = r.z / rz; p = z + beta p.
+// The target is the true residual (Sec. 4); the recursive one is the cheap test.
+// A non-finite residual norm is a breakdown.  Scalars stay on the device; the
+// host reads the residual norms once per iteration to retire converged columns.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -161,8 +163,11 @@ spand_status pcg_solve(spand_ctx* h, int32_t nrhs, const double* b, double* x, d
   int32_t* active_d = reinterpret_cast<int32_t*>(scratch + apply_scratch_doubles(h, nrhs) + 16);
   const hipStream_t s = h->stream;
 
-  std::vector<double> hb(nrhs), hr(nrhs);
+  std::vector<double> hb(nrhs), hr(nrhs), ht(nrhs);
   std::vector<int32_t> act(nrhs, 0);
+  bool broke = false;
+  int broke_col = -1;
+  int64_t replaced = 0;
   // the apply of this solve: one captured graph (same vectors every iteration),
   // replayed on the handle's stream; device time of every apply from a pair of
   // events around it
@@ -212,10 +217,35 @@ spand_status pcg_solve(spand_ctx* h, int32_t nrhs, const double* b, double* x, d
     HIPCHK(hipMemcpyAsync(hr.data(), rr, scal * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     ++it;
+    bool check_true = false;
     for (int c = 0; c < nrhs; ++c) {
       if (!act[c]) continue;
       iters[c] = it;
-      if (std::sqrt(hr[c]) <= rtol * hb[c] || !std::isfinite(hr[c])) act[c] = 0;
+      if (!std::isfinite(hr[c])) {
+        act[c] = 0;
+        broke = true;
+        if (broke_col < 0) broke_col = c;
+      } else if (std::sqrt(hr[c]) <= rtol * hb[c]) {
+        check_true = true;
+      }
+    }
+    if (check_true) {  // true residuals of the columns whose recursive residual passed
+      launch_spmv(h->d_rowptr.as<int64_t>(), h->d_colind.as<int32_t>(), h->d_values.as<double>(), n, nrhs, x, q, s);
+      launch_residual(int64_t(vec), b, q, s);
+      launch_dot(q, q, n, nrhs, partial, nblk, rr, s);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(ht.data(), rr, scal * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (int c = 0; c < nrhs; ++c) {
+        if (!act[c] || !std::isfinite(hr[c]) || std::sqrt(hr[c]) > rtol * hb[c]) continue;
+        if (std::sqrt(ht[c]) <= rtol * hb[c]) {
+          act[c] = 0;
+        } else {  // the recursive residual drifted: continue from the true one
+          HIPCHK(hipMemcpyAsync(r + size_t(c) * n, q + size_t(c) * n, size_t(n) * sizeof(double),
+                                hipMemcpyDeviceToDevice, s));
+          ++replaced;
+        }
+      }
     }
     any = std::any_of(act.begin(), act.end(), [](int a) { return a != 0; });
     if (!any || it >= maxit) break;
@@ -250,6 +280,10 @@ spand_status pcg_solve(spand_ctx* h, int32_t nrhs, const double* b, double* x, d
   h->stats.apply_bytes = 16.0 * double(h->stats.m_F) + 4.0 * 8.0 * double(n) * nrhs;
   h->stats.last_iters = 0;
   for (int c = 0; c < nrhs; ++c) h->stats.last_iters = std::max(h->stats.last_iters, iters[c]);
+  h->stats.pcg_replacements = replaced;
+  if (broke)
+    return set_err(h, SPAND_E_BREAKDOWN, "PCG breakdown: non-finite residual in right-hand side " +
+                                             std::to_string(broke_col));
   if (noconv) return set_err(h, SPAND_E_NOCONV, "PCG reached maxit = " + std::to_string(maxit));
   return SPAND_OK;
 }

@@ -57,6 +57,15 @@ struct Analysis {
   std::vector<SymStep> steps;
 };
 
+// Kernel-shape and path parameters of a handle before any tuning.
+inline spand_tuning default_tuning() {
+  spand_tuning t{};
+  t.chol_group = 3;
+  t.fuse128_min = 256;
+  t.gemm_variant = 0;
+  return t;
+}
+
 // Runs Algorithm 2 and the symbolic factorization; returns an error text or "".
 std::string analyze_pattern(Analysis& an);
 

@@ -7,9 +7,12 @@ or a Fortran-ordered (n, nrhs) view); host arrays are numpy arrays.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
 import re
+import sys
+import weakref
 
 import numpy as np
 
@@ -18,7 +21,7 @@ _LIB = None
 
 SPAND_FP64, SPAND_FP32, SPAND_BF16X3 = 0, 1, 2
 STATUS = {0: "SPAND_OK", 1: "SPAND_E_INVALID", 2: "SPAND_E_NOT_SPD", 3: "SPAND_E_NOCONV",
-          4: "SPAND_E_NOMEM", 5: "SPAND_E_HIP", 6: "SPAND_E_STATE"}
+          4: "SPAND_E_NOMEM", 5: "SPAND_E_HIP", 6: "SPAND_E_STATE", 7: "SPAND_E_BREAKDOWN"}
 
 
 class SpandError(RuntimeError):
@@ -26,6 +29,14 @@ class SpandError(RuntimeError):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
         self.status = status
         self.name = STATUS.get(status, str(status))
+
+
+class Tuning(C.Structure):
+    _fields_ = [("chol_group", C.c_int32), ("fuse128_min", C.c_int32), ("gemm_variant", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
+
+    def as_dict(self):
+        return {"chol_group": self.chol_group, "fuse128_min": self.fuse128_min, "gemm_variant": self.gemm_variant}
 
 
 class Stats(C.Structure):
@@ -37,12 +48,15 @@ class Stats(C.Structure):
                 ("step_phase_seconds", (C.c_double * 4) * 32), ("step_m_F", C.c_int64 * 32),
                 ("cpqr_flops", C.c_double), ("cpqr_seconds", C.c_double), ("cpqr_launches", C.c_int64),
                 ("apply_bytes", C.c_double), ("apply_seconds", C.c_double), ("apply_calls", C.c_int64),
-                ("apply_graph", C.c_int32), ("reserved2", C.c_int32), ("cpqr_interfaces", C.c_int64 * 4)]
+                ("apply_graph", C.c_int32), ("reserved2", C.c_int32), ("cpqr_interfaces", C.c_int64 * 4),
+                ("apply_interfaces", C.c_int64 * 3), ("pcg_replacements", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_
-             if k not in ("reserved", "reserved2", "step_phase_seconds", "step_m_F", "cpqr_interfaces")}
+             if k not in ("reserved", "reserved2", "step_phase_seconds", "step_m_F", "cpqr_interfaces",
+                          "apply_interfaces")}
         d["cpqr_interfaces"] = [int(v) for v in self.cpqr_interfaces]
+        d["apply_interfaces"] = [int(v) for v in self.apply_interfaces]
         L = max(0, min(32, int(self.n_steps)))
         d["step_phase_seconds"] = [[self.step_phase_seconds[t][q] for q in range(4)] for t in range(L)]
         d["step_m_F"] = [int(self.step_m_F[t]) for t in range(L)]
@@ -72,6 +86,8 @@ def load_library():
         "spand_set_stream": (i32, [P, P]),
         "spand_set_apply_graph": (i32, [P, i32]),
         "spand_get_stats": (i32, [P, C.POINTER(Stats)]),
+        "spand_set_tuning": (i32, [P, C.POINTER(Tuning)]),
+        "spand_get_tuning": (i32, [P, C.POINTER(Tuning)]),
         "spand_get_ordering": (i32, [P, P, P, P]),
         "spand_step_counts": (i32, [P, i32, P]),
         "spand_step_structure": (i32, [P, i32, P, P, P, P, P]),
@@ -120,8 +136,27 @@ def _dev_vec(t, n):
     raise ValueError("expected shape (nrhs, n) contiguous or a column-major (n, nrhs) view")
 
 
+# Every live handle, so that they are all released while the HIP runtime and torch
+# are still up: the exit hook below is registered when this module is imported,
+# after torch, so it runs before torch's own exit hooks.
+_LIVE = weakref.WeakSet()
+
+
+def close_all():
+    """Release every open handle (idempotent)."""
+    for s in list(_LIVE):
+        s.close()
+
+
+atexit.register(close_all)
+
+
 class Solver:
-    """One spaND handle: analyze on construction, then factor / solve / apply."""
+    """One spaND handle: analyze on construction, then factor / solve / apply.
+
+    Call close() (or use the Solver as a context manager) to release the handle's
+    device memory deterministically; handles still open at interpreter exit are
+    released by an exit hook, never from a finalizer during shutdown."""
 
     def __init__(self, n, rowptr, colind, coords, levels):
         lib = load_library()
@@ -137,6 +172,13 @@ class Solver:
         if st != 0:
             raise SpandError(st, lib.spand_error_string(None).decode())
         self._h = h
+        _LIVE.add(self)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     @classmethod
     def from_problem(cls, problem, levels):
@@ -146,8 +188,13 @@ class Solver:
         if getattr(self, "_h", None):
             self._lib.spand_destroy(self._h)
             self._h = None
+        _LIVE.discard(self)
 
     def __del__(self):
+        # during interpreter shutdown the exit hook has already released the handle;
+        # device teardown from a finalizer at that point is not safe
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -187,6 +234,20 @@ class Solver:
     def apply(self, r, z):
         nrhs = _dev_vec(r, self.n)
         self._check(self._lib.spand_apply(self._h, nrhs, _ptr(r), _ptr(z)))
+
+    def tuning(self):
+        t = Tuning()
+        self._check(self._lib.spand_get_tuning(self._h, C.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        t = Tuning()
+        self._check(self._lib.spand_get_tuning(self._h, C.byref(t)))
+        for k, v in kw.items():
+            if k not in ("chol_group", "fuse128_min", "gemm_variant"):
+                raise KeyError(k)
+            setattr(t, k, int(v))
+        self._check(self._lib.spand_set_tuning(self._h, C.byref(t)))
 
     def stats(self):
         s = Stats()

@@ -11,7 +11,7 @@ from oracle import spand_oracle as O
 from paper_1901_02971_amd import spand as S
 
 DECLARED = ["spand_analyze", "spand_factor", "spand_solve", "spand_apply", "spand_set_stream",
-            "spand_set_apply_graph", "spand_get_stats",
+            "spand_set_apply_graph", "spand_get_stats", "spand_set_tuning", "spand_get_tuning",
             "spand_get_ordering", "spand_step_counts", "spand_step_structure", "spand_step_ranks",
             "spand_factor_batch", "spand_solve_batch", "spand_error_string", "spand_destroy"]
 
@@ -26,9 +26,10 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
-def test_stats_struct_matches_header(tmp_path):
-    """The ctypes mirror of spand_stats has the size and field offsets the C compiler
-    gives the header's struct (a C program built with the host compiler prints them)."""
+@pytest.mark.parametrize("cname,mirror", [("spand_stats", "Stats"), ("spand_tuning", "Tuning")])
+def test_stats_struct_matches_header(tmp_path, cname, mirror):
+    """The ctypes mirrors of the header's structs have the size and field offsets the
+    C compiler gives them (a C program built with the host compiler prints them)."""
     import os
     import shutil
     import subprocess
@@ -36,10 +37,11 @@ def test_stats_struct_matches_header(tmp_path):
     if cc is None:
         pytest.skip("no host C compiler")
     inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
-    fields = [name for name, _ in S.Stats._fields_]
+    M = getattr(S, mirror)
+    fields = [name for name, _ in M._fields_]
     src = ["#include <stddef.h>", "#include <stdio.h>", '#include "spand.h"', "int main(void) {",
-           '  printf("%zu\\n", sizeof(spand_stats));']
-    src += [f'  printf("%zu\\n", offsetof(spand_stats, {f}));' for f in fields]
+           f'  printf("%zu\\n", sizeof({cname}));']
+    src += [f'  printf("%zu\\n", offsetof({cname}, {f}));' for f in fields]
     src += ["  return 0;", "}"]
     c = tmp_path / "stats.c"
     c.write_text("\n".join(src) + "\n")
@@ -47,9 +49,9 @@ def test_stats_struct_matches_header(tmp_path):
     r = subprocess.run([cc, "-std=c11", "-I", inc, str(c), "-o", str(exe)], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
-    assert vals[0] == ctypes.sizeof(S.Stats)
+    assert vals[0] == ctypes.sizeof(M)
     for f, off in zip(fields, vals[1:]):
-        assert getattr(S.Stats, f).offset == off, f
+        assert getattr(M, f).offset == off, f
 
 
 CASES = [((7, 7), 3), ((6, 4), 2), ((16, 16), 5), ((64, 64), 6), ((9, 7, 6), 4), ((8, 8, 8), 5),

@@ -75,6 +75,33 @@ def test_workload_matches_oracle(path):
     assert np.all(rr <= 1e-12), rr
 
 
+def reduced_cases():
+    out = []
+    for path in golden_files():
+        name = os.path.basename(path)[7:-5]
+        if name.startswith(("c3_", "c4_")):
+            for prec, tag in ((1, "fp32"), (2, "bf16x3")):
+                out.append(pytest.param(path, prec, id=f"{name}-{tag}"))
+    return out
+
+
+@pytest.mark.parametrize("path,prec", reduced_cases())
+def test_workload_reduced_precision(path, prec):
+    """FP32-MFMA and BF16x3 Schur products at the workload sizes (the 64^3
+    high-contrast and the 128^3 benchmark problems): PCG iterations within +-1 of the
+    FP64 oracle's for every right-hand side and the true relative residual <= 1e-12.
+    A pivot that stops being SPD in reduced precision would raise SPAND_E_NOT_SPD;
+    nothing falls back silently."""
+    with open(path) as f:
+        ref = json.load(f)
+    p, b, levels = gridgen.config_problem(ref["workload"])
+    s = gpu_factor(p, levels, ref["tol"], ref["skip"], prec)
+    _, it, rr, _ = gpu_solve(s, b, ref["rtol"], ref["maxit"])
+    note(f"{ref['workload']} prec {prec}: iters {it.tolist()} oracle {ref['pcg_iters']} relres {rr.max():.2e}")
+    assert np.all(np.abs(it - np.array(ref["pcg_iters"])) <= 1), (it.tolist(), ref["pcg_iters"])
+    assert np.all(rr <= 1e-12), rr
+
+
 def test_batched_workload_problems_match_oracle():
     """The stored problems of the batched workload, factored and solved in one batch."""
     from paper_1901_02971_amd import Solver, factor_batch, solve_batch

@@ -198,6 +198,75 @@ def test_noconv_reports_iterations():
     assert np.all(it == 1) and np.all(rr > 1e-12) and np.all(np.isfinite(x))
 
 
+def test_pcg_breakdown_reported():
+    """A residual norm that overflows is a breakdown, reported as such by both sides.
+    b is the smoothest grid mode with ||b||^2 just below the FP64 maximum, so
+    r.z = b^T M M^T b ~ ||b||^2 / lambda_min overflows in the first iteration."""
+    from paper_1901_02971_amd import SpandError  # noqa: F401
+    shape = (12, 12, 12)
+    p = gridgen.laplacian(shape)
+    i, j, k = (np.arange(s) + 1.0 for s in shape)
+    mode = np.einsum("k,j,i->kji", np.sin(np.pi * k / 13), np.sin(np.pi * j / 13), np.sin(np.pi * i / 13)).ravel()
+    b = (1.3e154 * mode / np.linalg.norm(mode))[:, None]
+    assert np.isfinite(float(b[:, 0] @ b[:, 0]))
+    an, fac = oracle_run(p, 6, 1e-2)
+    with pytest.raises(O.Breakdown):
+        O.pcg(p.scipy(), b, lambda r: O.apply(fac, r))
+    s = gpu_factor(p, 6, 1e-2)
+    x, it, rr, st = gpu_solve(s, b, check=False)
+    assert st == 7, st   # SPAND_E_BREAKDOWN
+    assert it[0] == 1
+    # the handle stays usable
+    b2 = gridgen.rhs(np.random.default_rng(4), p.n, 1)
+    _, it2, rr2, st2 = gpu_solve(s, b2)
+    assert st2 == 0 and rr2[0] <= 1e-12
+
+
+@pytest.mark.parametrize("fuse", [0, -1], ids=["fused128", "tiled"])
+def test_apply_paths_match_oracle(fuse):
+    """Interfaces of 65..128 dofs through the fused one-wave apply kernel (forced on
+    with fuse128_min = 0) or through the tiled kernels (fuse128_min = -1): the apply
+    equals the oracle's element by element, and the path counters show which ran."""
+    p = gridgen.laplacian((24, 24, 24))
+    b = gridgen.rhs(np.random.default_rng(12), p.n, 5)
+    an, fac = oracle_run(p, 5, 1e-2)
+    from paper_1901_02971_amd import Solver
+    s = Solver.from_problem(p, 5)
+    s.set_tuning(fuse128_min=fuse)
+    s.factor(torch.from_numpy(p.values).to("cuda:0"), 1e-2)
+    assert rank_mismatches(s, an, fac) == 0
+    ai = s.stats()["apply_interfaces"]
+    note(f"apply interfaces (fused <= 64, fused 65..128, tiled): {ai}")
+    if fuse == 0:
+        assert ai[1] > 0
+    else:
+        assert ai[1] == 0 and ai[2] > 0
+    z = gpu_apply(s, b)
+    zr = O.apply(fac, b)
+    assert np.abs(z - zr).max() <= 1e-10 * np.abs(zr).max()
+    x, it, rr, _ = gpu_solve(s, b)
+    assert np.all(rr <= 1e-12)
+
+
+@pytest.mark.parametrize("group", [1, 2, 4])
+def test_cholesky_group_tuning_keeps_parity(group):
+    """The trailing-update grouping of the blocked Cholesky (a tuning parameter)
+    changes only the order of roundings: ranks stay the oracle's and the apply stays
+    within 1e-10 of it."""
+    p = gridgen.variable_coefficient((22, 20, 24), np.random.default_rng(41), -3, 3)
+    b = gridgen.rhs(np.random.default_rng(42), p.n, 2)
+    an, fac = oracle_run(p, 6, 1e-2)
+    from paper_1901_02971_amd import Solver
+    s = Solver.from_problem(p, 6)
+    s.set_tuning(chol_group=group)
+    assert s.tuning()["chol_group"] == group
+    s.factor(torch.from_numpy(p.values).to("cuda:0"), 1e-2)
+    assert rank_mismatches(s, an, fac) == 0
+    z = gpu_apply(s, b)
+    zr = O.apply(fac, b)
+    assert np.abs(z - zr).max() <= 1e-10 * np.abs(zr).max()
+
+
 # ------------------------------------------------------------------ Schur-product precisions
 @pytest.mark.parametrize("prec,bound", [(1, 1e-5), (2, 1e-4)], ids=["fp32", "bf16x3"])
 def test_exact_factorization_reduced_precision(prec, bound):

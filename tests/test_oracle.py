@@ -42,6 +42,30 @@ def test_alg2_hand_stepped(fname, shape, levels):
             assert (S[v], L[v], R[v]) == (_code(s), _code(l), _code(r)), (x, y)
 
 
+@pytest.mark.parametrize("fname,shape,levels", [("nd_4x4x4_L3.txt", (4, 4, 4), 3),
+                                                ("nd_3x3x5_L3.txt", (3, 3, 5), 3)])
+def test_alg2_hand_stepped_3d(fname, shape, levels):
+    """Algorithm 2 (Sec. 2.3) on small 3D grids against hand-stepped runs: the axis
+    tie-break (x, y and z tied, then y and z), a cut along z, and boundary vertices
+    of the middle set keeping their pointers."""
+    nx, ny, nz = shape
+    rows = {}
+    for ln in open(os.path.join(GOLDEN, fname)):
+        if ln.startswith("z"):
+            head, body = ln.split(":")
+            z, y = (int(w[1:]) for w in head.split())
+            rows[(z, y)] = body.split()
+    assert len(rows) == ny * nz
+    p = gridgen.laplacian(shape)
+    S, L, R = O.nd_order(p.n, p.rowptr, p.colind, p.coords, levels)
+    for (z, y), row in rows.items():
+        assert len(row) == nx
+        for x, ent in enumerate(row):
+            s, l, r = ent.split("/")
+            v = x + nx * (y + ny * z)
+            assert (S[v], L[v], R[v]) == (_code(s), _code(l), _code(r)), (x, y, z)
+
+
 @pytest.mark.parametrize("shape,levels", [((7, 7), 3), ((16, 16), 5), ((9, 7, 6), 4), ((8, 8, 8), 5)])
 def test_alg2_invariants(shape, levels):
     """ND invariants: an edge never joins two different separators unless one is an
@@ -74,6 +98,31 @@ def test_each_separator_is_one_cluster(shape, levels):
         ids = st.keys[: st.n_elim, 0]
         assert len(np.unique(ids)) == st.n_elim
         assert np.all(O.lev_of(ids) == st.level)
+
+
+@pytest.mark.parametrize("shape,levels", [((16, 16), 5), ((9, 7, 6), 4), ((12, 12, 12), 6)])
+def test_colouring_proper_and_greedy(shape, levels):
+    """The sparsification colouring lets a GPU run one colour class at once with the
+    result of the sequential order: no two interfaces joined by a block may share a
+    colour.  It is also the greedy one in ascending cluster id: every colour below
+    p's is taken by a lower-numbered neighbour of p, and p's is not."""
+    p = gridgen.laplacian(shape)
+    an = O.Analysis(p.n, p.rowptr, p.colind, p.coords, levels)
+    checked = 0
+    for st in an.steps:
+        if not st.sparsify:
+            assert np.all(st.colour == -1)
+            continue
+        assert np.all(st.colour[: st.n_elim] == -1)
+        for (i, j) in st.after:
+            if i != j:
+                assert st.colour[i] != st.colour[j], (st.level, i, j)
+                checked += 1
+        for q in range(st.n_elim, len(st.keys)):
+            lower = {int(st.colour[u]) for u in st.nbrs[q] if u < q}
+            c = int(st.colour[q])
+            assert c >= 0 and c not in lower and all(k in lower for k in range(c))
+    assert checked > 0
 
 
 def _brute_force_pattern(p, an):
@@ -260,6 +309,107 @@ def test_cpqr_tie_goes_to_smallest_original_column():
     assert list(perm) == [3, 0, 1, 2]
 
 
+def test_cpqr_position_rule_matches_geqp3_on_exact_ties():
+    """The tie="position" rule is LAPACK's: with exact ties after a swap, geqp3 takes
+    the first column at its current position."""
+    B = np.diag([1.0, 1.0, 1.0, 2.0])
+    _, _, P = sla.qr(B, pivoting=True)
+    r, V, tau, W, perm = O.cpqr(B, 0.0, tie="position")
+    assert list(perm) == list(P) == [3, 1, 2, 0]
+    # the two rules agree whenever no tie is met
+    A = np.random.default_rng(8).standard_normal((15, 40))
+    assert np.array_equal(O.cpqr(A, 1e-3, tie="position")[4], O.cpqr(A, 1e-3)[4])
+    with pytest.raises(ValueError):
+        O.cpqr(B, 0.0, tie="other")
+
+
+def _dense_trailing(blocks, sizes, ids):
+    """Dense matrix of the clusters `ids` (in that order) from the block dict."""
+    off = np.concatenate([[0], np.cumsum([sizes[c] for c in ids])]).astype(int)
+    T = np.zeros((off[-1], off[-1]))
+    for a, i in enumerate(ids):
+        for b, j in enumerate(ids):
+            key = (max(i, j), min(i, j))
+            if key in blocks:
+                blk = blocks[key] if i >= j else blocks[key].T
+                T[off[a]:off[a + 1], off[b]:off[b + 1]] = blk
+    return T, off
+
+
+def _explicit_q(V, tau, m):
+    """Q = H_0 H_1 ... H_{r-1} as a dense matrix, from its reflectors."""
+    Q = np.eye(m)
+    for j in range(V.shape[1]):
+        v = V[:, j]
+        Q = Q @ (np.eye(m) - tau[j] * np.outer(v, v))
+    return Q
+
+
+@pytest.mark.parametrize("tol", [0.3, 1e-2])
+def test_sparsification_in_context(tol):
+    """Orthogonal sparsification inside Algorithm 3 at eps > 0, on the live trailing
+    matrix of a small 3D grid (Sec. 2.6.1 and the stability theorem of Sec. 3.2):
+    the scaled A_pp is I; with A_pn = Q [W_cn; W_fn], the Schur complement onto the
+    rest after dropping f is S_B = S_A + W_fn^T W_fn, i.e. the error is
+    E_nn = W_fn^T W_fn >= 0; the new trailing matrix stays SPD; and what the step
+    writes back is W_cn in row block p with A_cc = I_r."""
+    p = gridgen.variable_coefficient((7, 6, 8), np.random.default_rng(21), -2, 2)
+    an = O.Analysis(p.n, p.rowptr, p.colind, p.coords, 4)
+    seen = {"n": 0, "dropped": 0, "writeback": 0}
+    prev = {}
+
+    def hook(t, q, nb, sizes, blocks, Apn, res):
+        # the previous interface of this step wrote back its kept rows
+        if prev.get("t") == t:
+            pq, W, pnb, psz = prev["p"], prev["W"], prev["nb"], prev["sizes"]
+            r = W.shape[0]
+            assert np.array_equal(blocks[(pq, pq)], np.eye(r))
+            col = 0
+            for u in pnb:
+                wu = W[:, col:col + psz[u]]
+                col += psz[u]
+                got = blocks[(pq, u)] if pq >= u else blocks[(u, pq)].T
+                assert np.array_equal(got, wu)
+            seen["writeback"] += 1
+        r, V, tau, W, perm = res
+        alive = sorted({i for key in blocks for i in key})
+        rest = [c for c in alive if c != q]
+        T, off = _dense_trailing(blocks, sizes, [q] + rest)
+        k = sizes[q]
+        assert np.abs(T[:k, :k] - np.eye(k)).max() < 1e-13      # scaled: A_pp = I
+        Apn_dense = T[:k, k:]
+        # the gathered row block is A_pn on the neighbour columns, zero elsewhere
+        noff = dict(zip(rest, off[1:-1] - k))
+        cols = np.concatenate([np.arange(noff[u], noff[u] + sizes[u]) for u in nb]).astype(int)
+        assert np.array_equal(Apn_dense[:, cols], Apn)
+        mask = np.ones(Apn_dense.shape[1], bool)
+        mask[cols] = False
+        assert not np.any(Apn_dense[:, mask])
+        Q = _explicit_q(V, tau, k)
+        assert np.abs(Q.T @ Q - np.eye(k)).max() < 1e-13
+        full = Q.T @ Apn
+        Wc, Wf = full[:r], full[r:]
+        assert np.abs(Wc - W).max() <= 1e-12 * max(1.0, np.abs(Apn).max())
+        Ann = T[k:, k:]
+        Wc_d = np.zeros((r, Ann.shape[0]))
+        Wc_d[:, cols] = W
+        Wf_d = np.zeros((k - r, Ann.shape[0]))
+        Wf_d[:, cols] = Wf
+        S_A = Ann - Apn_dense.T @ Apn_dense
+        S_B = Ann - Wc_d.T @ Wc_d
+        E = S_B - S_A
+        assert np.abs(E - Wf_d.T @ Wf_d).max() <= 1e-12 * max(1.0, np.abs(Ann).max())
+        assert np.linalg.eigvalsh(E).min() >= -1e-12 * max(1.0, np.abs(E).max())
+        newT = np.block([[np.eye(r), Wc_d], [Wc_d.T, Ann]])
+        assert np.linalg.eigvalsh(newT).min() > 0
+        seen["n"] += 1
+        seen["dropped"] += int(r < k)
+        prev.update(t=t, p=q, W=W.copy(), nb=list(nb), sizes=list(sizes))
+
+    O.factor(an, p.values, tol, on_sparsify=hook)
+    assert seen["n"] > 20 and seen["dropped"] > 5 and seen["writeback"] > 10, seen
+
+
 def test_sparsification_schur_identity():
     """Theorem of Sec. 3.2: with A_pp = I and A_pn = Q [W_cn; W_fn], the n-n Schur
     complement after dropping f is S_B = S_A + W_fn^T W_fn, and B_p is SPD."""
@@ -323,6 +473,28 @@ def test_pcg_zero_rhs_and_solution():
     xs = spla.spsolve(A.tocsc(), b[:, 0])
     assert rr[0] <= 1e-12
     assert np.abs(x[:, 0] - xs).max() <= 1e-10 * np.abs(xs).max()
+
+
+def test_pcg_checks_the_true_residual():
+    """The stop rule is on the true residual: a target below what FP64 can reach
+    runs to maxit instead of stopping on a recursive residual that keeps falling."""
+    p = gridgen.laplacian((20, 20))
+    b = gridgen.rhs(np.random.default_rng(3), p.n, 1)
+    an = O.Analysis(p.n, p.rowptr, p.colind, p.coords, 4)
+    fac = O.factor(an, p.values, 0.3)
+    A = p.scipy()
+    _, it, rr = O.pcg(A, b, lambda r: O.apply(fac, r), rtol=1e-19, maxit=40)
+    assert it[0] == 40 and rr[0] > 1e-19
+    _, it, rr = O.pcg(A, b, lambda r: O.apply(fac, r), rtol=1e-12, maxit=40)
+    assert it[0] < 40 and rr[0] <= 1e-12
+
+
+def test_pcg_breakdown_is_reported():
+    p = gridgen.laplacian((6, 6))
+    b = gridgen.rhs(np.random.default_rng(3), p.n, 2)
+    with pytest.raises(O.Breakdown) as e:
+        O.pcg(p.scipy(), b, lambda r: np.full_like(r, np.nan))
+    assert e.value.column == 0 and e.value.iteration == 1
 
 
 def test_generator_operator():
