@@ -121,6 +121,44 @@ def variable_coefficient(shape, rng: np.random.Generator, log10_lo: float, log10
     return _assemble(shape, faces)
 
 
+def _harmonic_faces(c):
+    """Face coefficients of a cell-coefficient array c (numpy axes reversed from the
+    grid axes): harmonic mean of the two cells inside, the cell's own value on the
+    boundary."""
+    dim = c.ndim
+    faces = []
+    for d in range(dim):
+        ax = dim - 1 - d
+        n_ax = c.shape[ax]
+        c0 = np.take(c, np.arange(0, n_ax - 1), axis=ax)
+        c1 = np.take(c, np.arange(1, n_ax), axis=ax)
+        inner = 2.0 * c0 * c1 / (c0 + c1)
+        first = np.take(c, [0], axis=ax)
+        last = np.take(c, [n_ax - 1], axis=ax)
+        faces.append(np.concatenate([first, inner, last], axis=ax))
+    return faces
+
+
+def high_contrast_field(shape, rng: np.random.Generator, rho: float) -> np.ndarray:
+    """Quantized high-contrast cell field of Sec. 4.1.1, in any dimension: a random
+    U(0,1) array, smoothed by convolution with a unit-width Gaussian (standard
+    deviation one cell, reflected at the boundary), then rho where the smoothed
+    value is >= 0.5 and 1/rho elsewhere.  Returned with numpy axes reversed from the
+    grid axes ([k, j, i])."""
+    from scipy.ndimage import gaussian_filter
+    grid_shape = tuple(reversed(tuple(int(s) for s in shape)))
+    a_hat = gaussian_filter(rng.random(grid_shape), sigma=1.0, mode="reflect")
+    return np.where(a_hat >= 0.5, float(rho), 1.0 / float(rho))
+
+
+def high_contrast(shape, rng: np.random.Generator, rho: float) -> GridProblem:
+    """The high-contrast operator of Sec. 4.1.1 (5-point in 2D, 7-point in 3D): cell
+    coefficients from high_contrast_field, faces by harmonic mean.  rho = 1 gives the
+    constant-coefficient Laplacian."""
+    shape = tuple(int(s) for s in shape)
+    return _assemble(shape, _harmonic_faces(high_contrast_field(shape, rng, rho)))
+
+
 def rhs(rng: np.random.Generator, n: int, nrhs: int) -> np.ndarray:
     """Right-hand sides b ~ N(0,1), returned column-major as an (n, nrhs) Fortran array."""
     return np.asfortranarray(rng.standard_normal((nrhs, n)).T)
@@ -151,7 +189,21 @@ def config_problem(name: str):
         return p, rhs(np.random.default_rng(4), p.n, 8), 13
     if name.startswith("c5_"):
         return batched_problem(int(name[3:]))
+    if name.startswith("x4_"):
+        return sweep_problem(name)
     raise KeyError(name)
+
+
+def sweep_problem(name: str):
+    """A point of the 3D size sweep of Sec. 4.2: "x4_<n>_rho<rho>" is the n^3 grid with
+    the high-contrast field of contrast rho (rho = 1: the Laplacian), seed 40000 + n,
+    one RHS drawn next from the same generator, depth 1 + ceil(log2(n^3 / 512))."""
+    body = name[3:]
+    n_s, rho_s = body.split("_rho")
+    n, rho = int(n_s), float(rho_s)
+    rng = np.random.default_rng(40000 + n)
+    p = high_contrast((n, n, n), rng, rho)
+    return p, rhs(rng, p.n, 1), levels_for(p.n)
 
 
 def levels_for(n: int) -> int:
