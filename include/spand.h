@@ -210,20 +210,31 @@ spand_status spand_step_ranks(spand_t h, int32_t step, int32_t* sizes, int32_t* 
 /* Batched factorization of P independent problems (the 256-problem workload: many
  * small grids factored together).  hs: P distinct handles from spand_analyze (host
  * array); values: host array of P device pointers, values[q] as in spand_factor for
- * hs[q]; tol, skip, prec as in spand_factor, shared by all problems.  The problems
- * are factored concurrently, each on its handle's stream (a handle without a
- * stream gets a non-blocking one for the duration of the call); every handle ends
- * in the state spand_factor would leave it in.  Returns SPAND_OK, or the status of
- * the first failing problem in handle order, with spand_error_string(NULL) naming
- * it and spand_error_string(hs[q]) holding its error.  SPAND_E_INVALID if P < 1,
- * a handle is NULL or repeated. */
+ * hs[q]; tol, skip, prec as in spand_factor, shared by all problems.
+ * The problems are factored in lockstep: step t of every problem runs in the same
+ * launches (one set of elimination, scaling, sparsification and merge kernels per
+ * step for the whole batch, with the descriptors of all problems concatenated), on
+ * one stream: that of hs[0], or a stream created for the call when hs[0] has none.
+ * The tuning of hs[0] applies to all.  Each problem's result is the one spand_factor
+ * gives it alone (no problem's arithmetic depends on another's).  Every handle ends
+ * in the state spand_factor would leave it in: a problem that fails (not SPD,
+ * non-finite values) is dropped from the run and the others go on.  The device
+ * times in each handle's stats are those of the shared launches.
+ * Returns SPAND_OK, or the status of the first failing problem in handle order, with
+ * spand_error_string(NULL) naming it and spand_error_string(hs[q]) holding its error.
+ * SPAND_E_INVALID if P < 1, a handle is NULL or repeated. */
 spand_status spand_factor_batch(int32_t P, spand_t* hs, const double* const* values, double tol, int32_t skip,
                                 spand_prec prec);
 
 /* Batched PCG: problem q solves nrhs right-hand sides b[q] -> x[q] (device, n_q x nrhs
  * column-major) with hs[q] as in spand_solve.  iters and relres are host arrays of
- * P * nrhs entries, problem q at offset q * nrhs.  Errors as spand_factor_batch; a
- * problem that hits maxit returns SPAND_E_NOCONV with its outputs written. */
+ * P * nrhs entries, problem q at offset q * nrhs.  The problems iterate in lockstep on
+ * the stream of hs[0] (or one created for the call): each half of an iteration of
+ * every problem (SpMV, dot products and updates; the preconditioner applies) is one
+ * captured HIP graph, replayed every iteration, and one copy per iteration brings
+ * every residual norm to the host.  Each problem's iterates are those spand_solve
+ * gives it alone.  Errors as spand_factor_batch; a problem that hits maxit returns
+ * SPAND_E_NOCONV with its outputs written, one that breaks down SPAND_E_BREAKDOWN. */
 spand_status spand_solve_batch(int32_t P, spand_t* hs, int32_t nrhs, const double* const* b, double* const* x,
                                double rtol, int32_t maxit, int32_t* iters, double* relres);
 

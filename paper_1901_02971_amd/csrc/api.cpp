@@ -4,12 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <new>
-#include <thread>
 #include <vector>
 
 #include "context.h"
@@ -26,6 +24,8 @@ spand_status apply_public(spand_ctx* h, int32_t nrhs, const double* r, double* z
 }  // namespace spand
 
 namespace {
+
+using spand::set_err;
 
 thread_local std::string g_last_error;
 
@@ -63,75 +63,89 @@ std::string check_pattern(int64_t n, const int64_t* rowptr, const int32_t* colin
   return "";
 }
 
-// Runs fn(q) for q = 0..P-1 on up to 16 host threads.  Every problem of the batch
-// works on its own handle and HIP stream: a handle without a stream gets a
-// non-blocking one for the call.  The factor and the solve synchronise their
-// stream several times per call (rank read-back, convergence checks), so the
-// threads keep many problems in flight on the GPU.
-template <class F>
-spand_status run_batch(int32_t P, spand_t* hs, F&& fn) {
-  if (P < 1 || !hs) return fail_null(SPAND_E_INVALID, "batch needs P >= 1 handles");
-  for (int32_t q = 0; q < P; ++q) {
-    if (!hs[q]) return fail_null(SPAND_E_INVALID, "NULL handle in batch at " + std::to_string(q));
-    for (int32_t o = 0; o < q; ++o)
-      if (hs[o] == hs[q]) return fail_null(SPAND_E_INVALID, "a handle appears twice in the batch");
-  }
+std::string check_factor_args(double tol, int32_t skip, spand_prec prec) {
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return "tol must be finite and >= 0";
+  if (skip < 0) return "skip must be >= 0";
+  if (prec != SPAND_FP64 && prec != SPAND_FP32 && prec != SPAND_BF16X3) return "unknown precision";
+  return "";
+}
+
+// Device copies of the matrix pattern (on the first factor) and of the values (on
+// every factor) of h, on its stream.
+spand_status load_values(spand_ctx* h, const double* values) {
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return fail_null(SPAND_E_HIP, "no HIP device");
-  std::vector<hipStream_t> own(P, nullptr);
-  for (int32_t q = 0; q < P; ++q)
-    if (!hs[q]->stream) {
-      if (hipStreamCreateWithFlags(&own[q], hipStreamNonBlocking) != hipSuccess) {
-        for (int32_t o = 0; o < q; ++o)
-          if (own[o]) {
-            (void)hipStreamDestroy(own[o]);
-            hs[o]->stream = nullptr;
-          }
-        return fail_null(SPAND_E_HIP, "stream creation failed");
-      }
-      hs[q]->stream = own[q];
+  if (hipGetDevice(&dev) != hipSuccess) return set_err(h, SPAND_E_HIP, "no HIP device");
+  h->device = dev;
+  const int64_t nnz = h->an.rowptr[h->an.n];
+  if (!h->d_rowptr.p) {
+    if (hipMalloc(&h->d_rowptr.p, size_t(h->an.n + 1) * sizeof(int64_t)) != hipSuccess ||
+        hipMalloc(&h->d_colind.p, size_t(nnz) * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&h->d_values.p, size_t(nnz) * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      return set_err(h, SPAND_E_NOMEM, "device allocation of the matrix failed");
     }
-  std::vector<spand_status> st(P, SPAND_OK);
-  std::atomic<int32_t> next{0};
-  auto work = [&]() {
-    if (hipSetDevice(dev) != hipSuccess) return;
-    for (;;) {
-      const int32_t q = next.fetch_add(1);
-      if (q >= P) break;
-      try {
-        st[q] = fn(q);
-      } catch (...) {
-        st[q] = spand::set_err(hs[q], SPAND_E_NOMEM, "host exception during batched call");
-      }
-    }
-  };
-  const int32_t nt = std::min<int32_t>(P, 16);
-  std::vector<std::thread> pool;
-  try {
-    for (int32_t k = 1; k < nt; ++k) pool.emplace_back(work);
-  } catch (...) {
-    // fewer threads: the calling thread and those started share the work
+    h->d_rowptr.bytes = size_t(h->an.n + 1) * sizeof(int64_t);
+    h->d_colind.bytes = size_t(nnz) * sizeof(int32_t);
+    h->d_values.bytes = size_t(nnz) * sizeof(double);
+    if (hipMemcpyAsync(h->d_rowptr.p, h->an.rowptr.data(), h->d_rowptr.bytes, hipMemcpyHostToDevice, h->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(h->d_colind.p, h->an.colind.data(), h->d_colind.bytes, hipMemcpyHostToDevice, h->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+      return set_err(h, SPAND_E_HIP, "copy of the matrix pattern failed");
   }
-  work();
-  for (std::thread& t : pool) t.join();
-  if (next.load() < P) {  // no worker could select the device
-    for (int32_t q = 0; q < P; ++q)
-      if (own[q]) hs[q]->stream = nullptr;
-    return fail_null(SPAND_E_HIP, "hipSetDevice failed in the batch workers");
-  }
-  for (int32_t q = 0; q < P; ++q)
-    if (own[q]) {
-      (void)hipStreamSynchronize(own[q]);
-      (void)hipStreamDestroy(own[q]);
-      hs[q]->stream = nullptr;
-    }
-  for (int32_t q = 0; q < P; ++q)
-    if (st[q] != SPAND_OK) {
-      g_last_error = "batch problem " + std::to_string(q) + ": " + hs[q]->err;
-      return st[q];
-    }
+  if (hipMemcpyAsync(h->d_values.p, values, h->d_values.bytes, hipMemcpyDeviceToDevice, h->stream) != hipSuccess)
+    return set_err(h, SPAND_E_HIP, "copy of the matrix values failed");
   return SPAND_OK;
 }
+
+// The handles of a batched call, distinct and non-NULL, all run on one stream for
+// the duration of the call: the first handle's, or a non-blocking stream created for
+// the call.  The destructor restores every handle's own stream.
+struct BatchStream {
+  int32_t P = 0;
+  spand_t* hs = nullptr;
+  std::vector<hipStream_t> saved;
+  hipStream_t own = nullptr, s = nullptr;
+  std::string err;
+  BatchStream(int32_t P_, spand_t* hs_) : P(P_), hs(hs_) {
+    if (P < 1 || !hs) {
+      err = "batch needs P >= 1 handles";
+      return;
+    }
+    for (int32_t q = 0; q < P; ++q) {
+      if (!hs[q]) {
+        err = "NULL handle in batch at " + std::to_string(q);
+        return;
+      }
+    }
+    std::vector<spand_t> sorted(hs, hs + P);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) {
+      err = "a handle appears twice in the batch";
+      return;
+    }
+    s = hs[0]->stream;
+    if (!s) {
+      if (hipStreamCreateWithFlags(&own, hipStreamNonBlocking) != hipSuccess) {
+        err = "stream creation failed";
+        return;
+      }
+      s = own;
+    }
+    saved.resize(P);
+    for (int32_t q = 0; q < P; ++q) {
+      saved[q] = hs[q]->stream;
+      hs[q]->stream = s;
+    }
+  }
+  bool ok() const { return err.empty(); }
+  ~BatchStream() {
+    if (s) (void)hipStreamSynchronize(s);
+    for (size_t q = 0; q < saved.size(); ++q) hs[q]->stream = saved[q];
+    if (own) (void)hipStreamDestroy(own);
+  }
+};
 
 }  // namespace
 
@@ -181,38 +195,15 @@ spand_status spand_analyze(int64_t n, const int64_t* rowptr, const int32_t* coli
 spand_status spand_factor(spand_t h, const double* values, double tol, int32_t skip, spand_prec prec) {
   if (!h) return fail_null(SPAND_E_INVALID, "handle is NULL");
   if (!values) return set_err(h, SPAND_E_INVALID, "values is NULL");
-  if (!(tol >= 0.0) || !std::isfinite(tol)) return set_err(h, SPAND_E_INVALID, "tol must be finite and >= 0");
-  if (skip < 0) return set_err(h, SPAND_E_INVALID, "skip must be >= 0");
-  if (prec != SPAND_FP64 && prec != SPAND_FP32 && prec != SPAND_BF16X3)
-    return set_err(h, SPAND_E_INVALID, "unknown precision");
+  std::string msg = check_factor_args(tol, skip, prec);
+  if (!msg.empty()) return set_err(h, SPAND_E_INVALID, msg);
   h->factored = false;
   h->stats.fail_step = h->stats.fail_cluster = h->stats.fail_phase = -1;
   const double t0 = now();
   try {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return set_err(h, SPAND_E_HIP, "no HIP device");
-    h->device = dev;
-    const int64_t nnz = h->an.rowptr[h->an.n];
-    if (!h->d_rowptr.p) {
-      if (hipMalloc(&h->d_rowptr.p, size_t(h->an.n + 1) * sizeof(int64_t)) != hipSuccess ||
-          hipMalloc(&h->d_colind.p, size_t(nnz) * sizeof(int32_t)) != hipSuccess ||
-          hipMalloc(&h->d_values.p, size_t(nnz) * sizeof(double)) != hipSuccess) {
-        (void)hipGetLastError();
-        return set_err(h, SPAND_E_NOMEM, "device allocation of the matrix failed");
-      }
-      h->d_rowptr.bytes = size_t(h->an.n + 1) * sizeof(int64_t);
-      h->d_colind.bytes = size_t(nnz) * sizeof(int32_t);
-      h->d_values.bytes = size_t(nnz) * sizeof(double);
-      if (hipMemcpyAsync(h->d_rowptr.p, h->an.rowptr.data(), h->d_rowptr.bytes, hipMemcpyHostToDevice,
-                         h->stream) != hipSuccess ||
-          hipMemcpyAsync(h->d_colind.p, h->an.colind.data(), h->d_colind.bytes, hipMemcpyHostToDevice,
-                         h->stream) != hipSuccess ||
-          hipStreamSynchronize(h->stream) != hipSuccess)
-        return set_err(h, SPAND_E_HIP, "copy of the matrix pattern failed");
-    }
-    if (hipMemcpyAsync(h->d_values.p, values, h->d_values.bytes, hipMemcpyDeviceToDevice, h->stream) != hipSuccess)
-      return set_err(h, SPAND_E_HIP, "copy of the matrix values failed");
-    spand_status st = spand::factor_numeric(h, h->d_values.as<double>(), tol, skip, prec);
+    spand_status st = load_values(h, values);
+    if (st != SPAND_OK) return st;
+    st = spand::factor_numeric(h, h->d_values.as<double>(), tol, skip, prec);
     if (hipStreamSynchronize(h->stream) != hipSuccess && st == SPAND_OK)
       st = set_err(h, SPAND_E_HIP, "stream synchronisation failed after factor");
     if (st != SPAND_OK) {
@@ -348,15 +339,85 @@ const char* spand_error_string(spand_t h) {
 spand_status spand_factor_batch(int32_t P, spand_t* hs, const double* const* values, double tol, int32_t skip,
                                 spand_prec prec) {
   if (!values) return fail_null(SPAND_E_INVALID, "values is NULL");
-  return run_batch(P, hs, [&](int32_t q) { return spand_factor(hs[q], values[q], tol, skip, prec); });
+  BatchStream bs(P, hs);
+  if (!bs.ok()) return fail_null(SPAND_E_INVALID, bs.err);
+  const std::string msg = check_factor_args(tol, skip, prec);
+  if (!msg.empty()) return fail_null(SPAND_E_INVALID, msg);
+  for (int32_t q = 0; q < P; ++q)
+    if (!values[q]) return fail_null(SPAND_E_INVALID, "values[" + std::to_string(q) + "] is NULL");
+  const double t0 = now();
+  std::vector<spand_status> per(P, SPAND_OK);
+  std::vector<const double*> dv(P);
+  spand_status st = SPAND_OK;
+  try {
+    for (int32_t q = 0; q < P && st == SPAND_OK; ++q) {
+      hs[q]->factored = false;
+      hs[q]->stats.fail_step = hs[q]->stats.fail_cluster = hs[q]->stats.fail_phase = -1;
+      st = load_values(hs[q], values[q]);
+      if (st != SPAND_OK) per[q] = st;
+      dv[q] = hs[q]->d_values.as<double>();
+    }
+    if (st == SPAND_OK) st = spand::factor_numeric_batch(hs, dv.data(), P, tol, skip, prec, per.data());
+    if (hipStreamSynchronize(bs.s) != hipSuccess && st == SPAND_OK) {
+      st = set_err(hs[0], SPAND_E_HIP, "stream synchronisation failed after the batched factor");
+      for (int32_t q = 0; q < P; ++q) per[q] = st;
+    }
+  } catch (const std::bad_alloc&) {
+    st = set_err(hs[0], SPAND_E_NOMEM, "host allocation failed during the batched factor");
+    for (int32_t q = 0; q < P; ++q) per[q] = st;
+  }
+  const double t1 = now();
+  for (int32_t q = 0; q < P; ++q) {
+    if (per[q] == SPAND_OK) {
+      hs[q]->factored = true;
+      hs[q]->stats.t_factor = t1 - t0;
+    } else {
+      hs[q]->num.clear();
+    }
+  }
+  for (int32_t q = 0; q < P; ++q)
+    if (per[q] != SPAND_OK) {
+      g_last_error = "batch problem " + std::to_string(q) + ": " + hs[q]->err;
+      return per[q];
+    }
+  return SPAND_OK;
 }
 
 spand_status spand_solve_batch(int32_t P, spand_t* hs, int32_t nrhs, const double* const* b, double* const* x,
                                double rtol, int32_t maxit, int32_t* iters, double* relres) {
   if (!b || !x || !iters || !relres) return fail_null(SPAND_E_INVALID, "NULL batch argument");
-  return run_batch(P, hs, [&](int32_t q) {
-    return spand_solve(hs[q], nrhs, b[q], x[q], rtol, maxit, iters + int64_t(q) * nrhs, relres + int64_t(q) * nrhs);
-  });
+  BatchStream bs(P, hs);
+  if (!bs.ok()) return fail_null(SPAND_E_INVALID, bs.err);
+  if (nrhs < 1) return fail_null(SPAND_E_INVALID, "nrhs must be >= 1");
+  if (!(rtol >= 0.0) || maxit < 1) return fail_null(SPAND_E_INVALID, "rtol must be >= 0 and maxit >= 1");
+  for (int32_t q = 0; q < P; ++q) {
+    if (!hs[q]->factored) {
+      set_err(hs[q], SPAND_E_STATE, "solve called before a successful factor");
+      g_last_error = "batch problem " + std::to_string(q) + ": " + hs[q]->err;
+      return SPAND_E_STATE;
+    }
+    if (!b[q] || !x[q] || b[q] == x[q]) return fail_null(SPAND_E_INVALID, "bad b/x of batch problem " + std::to_string(q));
+  }
+  const double t0 = now();
+  std::vector<spand_status> per(P, SPAND_OK);
+  spand_status st;
+  try {
+    st = spand::pcg_solve_batch(hs, P, nrhs, b, x, rtol, maxit, iters, relres, per.data());
+  } catch (const std::bad_alloc&) {
+    st = set_err(hs[0], SPAND_E_NOMEM, "host allocation failed during the batched solve");
+  }
+  const double t1 = now();
+  if (st != SPAND_OK) {
+    g_last_error = "batched solve: " + hs[0]->err;
+    return st;
+  }
+  for (int32_t q = 0; q < P; ++q) hs[q]->stats.t_solve = t1 - t0;
+  for (int32_t q = 0; q < P; ++q)
+    if (per[q] != SPAND_OK) {
+      g_last_error = "batch problem " + std::to_string(q) + ": " + hs[q]->err;
+      return per[q];
+    }
+  return SPAND_OK;
 }
 
 void spand_destroy(spand_t h) { delete h; }

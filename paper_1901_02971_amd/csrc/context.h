@@ -242,8 +242,18 @@ struct spand_ctx {
 
 namespace spand {
 spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int32_t skip, spand_prec prec);
+// Several problems in lockstep with shared launches on the stream of hs[0] (every
+// handle's stream must be that one); per[q] receives each problem's status.  The
+// return value is SPAND_OK unless the run as a whole failed (then every problem has it).
+spand_status factor_numeric_batch(spand_ctx* const* hs, const double* const* values, int32_t np, double tol,
+                                  int32_t skip, spand_prec prec, spand_status* per);
 spand_status apply_precond(spand_ctx* h, int32_t nrhs, const double* r, double* z, double* tmp, hipStream_t st);
 spand_status pcg_solve(spand_ctx* h, int32_t nrhs, const double* b, double* x, double rtol, int32_t maxit,
                        int32_t* iters, double* relres);
 spand_status set_err(spand_ctx* h, spand_status st, const std::string& msg);
+// PCG on several factored problems in lockstep on the stream of hs[0] (every handle's
+// stream must be that one); per[q] receives each problem's status.
+spand_status pcg_solve_batch(spand_ctx* const* hs, int32_t P, int32_t nrhs, const double* const* b,
+                             double* const* x, double rtol, int32_t maxit, int32_t* iters, double* relres,
+                             spand_status* per);
 }  // namespace spand

@@ -166,6 +166,7 @@ struct Front {
   double* P;
   double* dinv;  // ceil(n / CHOL_NB) blocks of CHOL_NB^2 doubles
   int32_t ld, n, m, id;
+  int32_t* fail;  // the problem's failure flag word (atomicMin of the cluster id)
 };
 
 // I_n into the n x n block D (ld ld), in column ranges of at most COPY_CHUNK entries
@@ -180,7 +181,7 @@ int64_t dinv_size(int32_t n) { return int64_t((n + CHOL_NB - 1) / CHOL_NB) * CHO
 // blocks.  Updates inside the n x n pivot block are FP64; `prec_below` selects the
 // arithmetic of the rows below it (the TRSM and Schur-side updates).
 // The trailing updates go in groups of h->tune.chol_group block columns.
-spand_status blocked_cholesky(spand_ctx* h, const std::vector<Front>& F, int32_t* d_fail, int prec_below) {
+spand_status blocked_cholesky(spand_ctx* h, const std::vector<Front>& F, int prec_below) {
   const int32_t CHOL_GROUP = std::max(1, h->tune.chol_group);
   int32_t nmax = 0;
   for (const Front& f : F) nmax = std::max(nmax, f.n);
@@ -193,7 +194,7 @@ spand_status blocked_cholesky(spand_ctx* h, const std::vector<Front>& F, int32_t
       if (f.n <= kb) continue;
       const int32_t w = std::min(CHOL_NB, f.n - kb);
       double* Dk = f.dinv + int64_t(kb / CHOL_NB) * CHOL_NB * CHOL_NB;
-      pd.push_back(PotrfDesc{f.P + kb + int64_t(kb) * f.ld, Dk, f.ld, w, f.id, 0});
+      pd.push_back(PotrfDesc{f.P + kb + int64_t(kb) * f.ld, Dk, f.fail, f.ld, w, f.id, 0});
       for (int32_t r0 = kb + w; r0 < f.m; r0 += 256)
         td.push_back(PanelDesc{f.P + int64_t(kb) * f.ld, Dk, f.ld, w, r0, std::min(f.m, r0 + 256)});
     }
@@ -250,7 +251,7 @@ spand_status blocked_cholesky(spand_ctx* h, const std::vector<Front>& F, int32_t
   if ((st = g.upload_all(h)) != SPAND_OK) return st;
   for (size_t q = 0; q < pcut.size(); ++q) {
     const int64_t pb = q ? pcut[q - 1] : 0, tb = q ? tcut[q - 1] : 0;
-    launch_potrf_diag(dp.as<PotrfDesc>() + pb, int32_t(pcut[q] - pb), d_fail, h->stream);
+    launch_potrf_diag(dp.as<PotrfDesc>() + pb, int32_t(pcut[q] - pb), h->stream);
     launch_panel_trsm(dt.as<PanelDesc>() + tb, int32_t(tcut[q] - tb), h->stream);
     g.launch(h, 2 * q);
     g.launch(h, 2 * q + 1);
@@ -485,539 +486,617 @@ spand_status build_apply(spand_ctx* h, const SymStep& sy, StepNum& sn, const Lay
   return SPAND_OK;
 }
 
-spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int32_t skip, spand_prec prec) {
-  Analysis& an = h->an;
-  const int32_t Lv = an.levels;
-  const int gemm_prec = (prec == SPAND_FP64) ? 0 : (prec == SPAND_FP32 ? 1 : 2);
-  h->stage.reset();
-  h->num.clear();
-  h->num.resize(Lv);
-  h->max_tmp = 0;
-  h->max_gather = 0;
-  spand_status st;
+namespace {
 
-  DevBuf dflag;  // [0] elimination failure id, [1] scaling failure id, [2] non-finite input
-  if ((st = dalloc(h, dflag, 4 * sizeof(int32_t))) != SPAND_OK) return st;
-  const int32_t flag_init[4] = {0x7fffffff, 0x7fffffff, 0, 0};
-  if ((st = stage_copy(h, dflag.p, flag_init, sizeof(flag_init))) != SPAND_OK) return st;
-  int32_t* d_fail_elim = dflag.as<int32_t>();
-  int32_t* d_fail_scale = dflag.as<int32_t>() + 1;
-  int32_t* d_nonfinite = dflag.as<int32_t>() + 2;
-
-  // phase boundaries of every step (5 events per step), read after the last sync
-  EventPool phev;
-  std::vector<char> elim_ran(size_t(Lv) + 1, 0);
-  // The device flags are read at one sync per step: the rank read-back of a
-  // sparsified step, or the end of any other step.  Kernels that run after a
-  // failure in the same step only see bad values, never bad indices.
-  auto check_flags = [&](int32_t t) -> spand_status {
-    int32_t flags[4];
-    HIPCHK(hipMemcpyAsync(flags, dflag.p, sizeof(flags), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
-    if (flags[2]) return set_err(h, SPAND_E_INVALID, "matrix values contain NaN or Inf");
-    if (flags[0] != 0x7fffffff) {
-      h->stats.fail_step = t;
-      h->stats.fail_cluster = flags[0];
-      h->stats.fail_phase = 0;
-      return set_err(h, SPAND_E_NOT_SPD, "pivot block not SPD at step " + std::to_string(t) + ", cluster " +
-                                             std::to_string(flags[0]) + " (elimination)");
-    }
-    if (flags[1] != 0x7fffffff) {
-      h->stats.fail_step = t;
-      h->stats.fail_cluster = flags[1];
-      h->stats.fail_phase = 1;
-      return set_err(h, SPAND_E_NOT_SPD, "interface block not SPD at step " + std::to_string(t) + ", cluster " +
-                                             std::to_string(flags[1]) + " (scaling)");
-    }
-    return SPAND_OK;
-  };
-  std::memset(h->stats.step_phase_seconds, 0, sizeof(h->stats.step_phase_seconds));
-  std::memset(h->stats.step_m_F, 0, sizeof(h->stats.step_m_F));
-
-  EventPool evpool;  // per-launch timing of the CPQR
+// One problem of a factorization run: its handle and what the run keeps for it
+// across the steps.  A run factors one problem, or several in lockstep (step t of
+// every problem together), with the work of all of them in shared launches.
+struct Prob {
+  spand_ctx* h = nullptr;
+  const double* values = nullptr;
+  int32_t L = 0;
+  bool live = true;             // false once it failed (its handle holds the error)
+  int32_t* flags = nullptr;     // [0] elimination failure id, [1] scaling failure id, [2] non-finite input
+  DevBuf arena, arena_prev;     // trailing panels of the remaining clusters, this and the last step
+  Layout lay, lay_prev;
+  ApplyPlan pending;            // apply descriptors of the last step, built while this one runs
+  std::vector<TDesc> t_pending; // compact-WY factors of the last step's interfaces
   int64_t m_F = 0;
-  double elim_flops = 0.0, elim_ms = 0.0;
-  double cpqr_flops = 0.0, cpqr_ms = 0.0;
-  int64_t cpqr_launches = 0;
+  double elim_flops = 0.0, cpqr_flops = 0.0;
   int64_t cpqr_ifaces[4] = {0, 0, 0, 0};  // single, wide, multi (32 x 2), multi (20 x 3)
   int32_t s_top = 0;
+  // this step
+  bool on = false, sparsify = false;
+  int64_t cbase = 0;            // first entry of this problem's clusters in the run's size and rank arrays
+  std::vector<int64_t> c_off, ed_off, sc_off, sd_off, v_off, tau_off, t_off, xch_off, ncols;
+  std::vector<int32_t> nN, nref, slabS, tg, nseg, rlay;
+  std::vector<char> wide;
+  DevBuf cbuf;
+};
 
-  DevBuf arena_prev;
-  Layout lay_prev;
-  // apply descriptors of the previous step, built while the current step runs
-  // (lay_prev is that step's layout until the end of the current one)
-  ApplyPlan pending;
-  // Compact-WY factors T_p of the interfaces sparsified in the last step: launched
-  // after the next step's sparsification (or at the end) so that their planning is
-  // off the path between a rank read-back and the next step's first kernels.
-  std::vector<TDesc> t_pending;
-  auto flush_t = [&]() -> spand_status {
-    if (t_pending.empty()) return SPAND_OK;
-    const std::vector<TDesc> tds = std::move(t_pending);
-    t_pending.clear();
-    spand_status st = SPAND_OK;
-    // S = V^T V into the T blocks (MFMA, upper tiles), then the T recurrence
-    GemmSeq vtv;
-    for (const TDesc& td : tds) {
-      GemmDesc q{};
-      q.A = td.V; q.lda = td.m;
-      q.B = td.V; q.ldb = td.m;
-      q.C = td.T; q.ldc = td.r;
-      q.M = td.r; q.N = td.r; q.K = td.m;
-      q.flags = G_TA;
-      q.alpha = 1.0; q.beta = 0.0;
-      vtv.add(q, 2);
+// Compact-WY factors T_p (Q = I - V T V^T) of interfaces of any problems of the run:
+// S = V^T V (MFMA, upper tiles), the 64-wide diagonal blocks of T in LDS, then
+// T[:J0, J] = -T[:J0, :J0] (S[:J0, J] T_JJ) by block columns.
+spand_status build_t_factors(spand_ctx* h, const std::vector<TDesc>& tds) {
+  if (tds.empty()) return SPAND_OK;
+  spand_status st = SPAND_OK;
+  GemmSeq vtv;
+  for (const TDesc& td : tds) {
+    GemmDesc q{};
+    q.A = td.V; q.lda = td.m;
+    q.B = td.V; q.ldb = td.m;
+    q.C = td.T; q.ldc = td.r;
+    q.M = td.r; q.N = td.r; q.K = td.m;
+    q.flags = G_TA;
+    q.alpha = 1.0; q.beta = 0.0;
+    vtv.add(q, 2);
+  }
+  vtv.end_launch(0);
+  if ((st = vtv.upload_all(h)) != SPAND_OK) return st;
+  vtv.launch(h, 0);
+  HIPCHK(hipGetLastError());
+  std::vector<TBlock> tbs;
+  int32_t rmax = 0;
+  int64_t x_total = 0;
+  std::vector<int64_t> x_off(tds.size(), -1);
+  for (size_t q = 0; q < tds.size(); ++q) {
+    const TDesc& td = tds[q];
+    for (int32_t j0 = 0; j0 < td.r; j0 += 64) tbs.push_back(TBlock{td.T, td.tau, td.r, j0});
+    rmax = std::max(rmax, td.r);
+    if (td.r > 64) {
+      x_off[q] = x_total;
+      x_total += int64_t(td.r) * 64;
     }
-    vtv.end_launch(0);
-    if ((st = vtv.upload_all(h)) != SPAND_OK) return st;
-    vtv.launch(h, 0);
+  }
+  DevBuf dtb, xb;
+  if ((st = upload(h, dtb, tbs)) != SPAND_OK) return st;
+  launch_build_t_diag(dtb.as<TBlock>(), int32_t(tbs.size()), h->stream);
+  HIPCHK(hipGetLastError());
+  if (rmax > 64) {
+    if ((st = dalloc(h, xb, size_t(x_total) * sizeof(double))) != SPAND_OK) return st;
+    GemmSeq tg2;
+    for (int32_t j0 = 64; j0 < rmax; j0 += 64) {
+      for (size_t q = 0; q < tds.size(); ++q) {
+        const TDesc& td = tds[q];
+        if (td.r <= j0) continue;
+        const int32_t w = std::min(64, td.r - j0);
+        GemmDesc g{};  // X = S[:j0, J] T_JJ
+        g.A = td.T + int64_t(j0) * td.r; g.lda = td.r;
+        g.B = td.T + j0 + int64_t(j0) * td.r; g.ldb = td.r;
+        g.C = xb.as<double>() + x_off[q]; g.ldc = td.r;
+        g.M = j0; g.N = w; g.K = w;
+        g.alpha = 1.0; g.beta = 0.0;
+        tg2.add(g, 0);
+      }
+      tg2.end_launch(0);
+      for (size_t q = 0; q < tds.size(); ++q) {
+        const TDesc& td = tds[q];
+        if (td.r <= j0) continue;
+        const int32_t w = std::min(64, td.r - j0);
+        GemmDesc g{};  // T[:j0, J] = -T[:j0, :j0] X
+        g.A = td.T; g.lda = td.r;
+        g.B = xb.as<double>() + x_off[q]; g.ldb = td.r;
+        g.C = td.T + int64_t(j0) * td.r; g.ldc = td.r;
+        g.M = j0; g.N = w; g.K = j0;
+        g.alpha = -1.0; g.beta = 0.0;
+        tg2.add(g, 0);
+      }
+      tg2.end_launch(0);
+    }
+    if ((st = tg2.upload_all(h)) != SPAND_OK) return st;
+    for (size_t q = 0; q < tg2.cut.size(); ++q) tg2.launch(h, q);
     HIPCHK(hipGetLastError());
-    // T by 64-wide block columns: the diagonal blocks, then for J = 1, 2, ...
-    // X = S[:J0, J] T_JJ and T[:J0, J] = -T[:J0, :J0] X (GEMMs across interfaces)
-    std::vector<TBlock> tbs;
-    int32_t rmax = 0;
-    int64_t x_total = 0;
-    std::vector<int64_t> x_off(tds.size(), -1);
-    for (size_t q = 0; q < tds.size(); ++q) {
-      const TDesc& td = tds[q];
-      for (int32_t j0 = 0; j0 < td.r; j0 += 64) tbs.push_back(TBlock{td.T, td.tau, td.r, j0});
-      rmax = std::max(rmax, td.r);
-      if (td.r > 64) {
-        x_off[q] = x_total;
-        x_total += int64_t(td.r) * 64;
+  }
+  return SPAND_OK;
+}
+
+// Sizes and slots of step t of one problem, from the ranks kept at step t-1.
+void step_sizes(const SymStep& sy, int32_t t, std::vector<StepNum>& num) {
+  StepNum& sn = num[t - 1];
+  const int32_t nc = sy.nc;
+  sn.size.assign(nc, 0);
+  sn.slot_ptr.assign(nc + 1, 0);
+  if (t == 1) {
+    for (int32_t c = 0; c < nc; ++c) sn.size[c] = int32_t(sy.child_ptr[c + 1] - sy.child_ptr[c]);
+    sn.slot.assign(sy.child.begin(), sy.child.end());
+    for (int32_t c = 0; c < nc; ++c) sn.slot_ptr[c + 1] = sy.child_ptr[c + 1];
+    return;
+  }
+  const StepNum& pv = num[t - 2];
+  for (int32_t c = 0; c < nc; ++c) {
+    int32_t s = 0;
+    for (int64_t e = sy.child_ptr[c]; e < sy.child_ptr[c + 1]; ++e) s += pv.rank[sy.child[e]];
+    sn.size[c] = s;
+    sn.slot_ptr[c + 1] = sn.slot_ptr[c] + s;
+  }
+  sn.slot.resize(sn.slot_ptr[nc]);
+  for (int32_t c = 0; c < nc; ++c) {
+    int64_t o = sn.slot_ptr[c];
+    for (int64_t e = sy.child_ptr[c]; e < sy.child_ptr[c + 1]; ++e) {
+      const int32_t ch = sy.child[e];
+      const int32_t r = pv.rank[ch];
+      std::copy(pv.slot.begin() + pv.slot_ptr[ch], pv.slot.begin() + pv.slot_ptr[ch] + r, sn.slot.begin() + o);
+      o += r;
+    }
+  }
+}
+
+// Merge copies of step t (> 1) of one problem: parent blocks are the concatenation
+// of the children's kept blocks (Sec. 2.7).  Large steps are planned by several host
+// threads over contiguous ranges of block pairs; the list is the same as one thread's.
+void plan_merge(const SymStep& sy, const StepNum& pv, const Layout& lay, const Layout& lay_prev, double* E, double* A,
+                const double* arena_prev, std::vector<CopyDesc>& out) {
+  auto plan_copies = [&](size_t q0, size_t q1, std::vector<CopyDesc>& dst) {
+    for (size_t q = q0; q < q1; ++q) {
+      const uint64_t pr = sy.before[q];
+      const int32_t I = pair_i(pr), J = pair_j(pr);
+      double* dbase = lay.panel(J, E, A) + lay.find(I, J);
+      int64_t ro = 0;
+      for (int64_t a = sy.child_ptr[I]; a < sy.child_ptr[I + 1]; ++a) {
+        const int32_t i = sy.child[a];
+        const int32_t ri = pv.rank[i];
+        int64_t co = 0;
+        for (int64_t b = sy.child_ptr[J]; b < sy.child_ptr[J + 1]; ++b) {
+          const int32_t j = sy.child[b];
+          const int32_t rj = pv.rank[j];
+          if (ri > 0 && rj > 0) {
+            const int32_t hi = std::max(i, j), lo = std::min(i, j);
+            const int64_t so = lay_prev.find(hi, lo);
+            if (so >= 0) {
+              CopyDesc cd;
+              cd.src = arena_prev + lay_prev.base[lo] + so;
+              cd.lds = int32_t(lay_prev.H[lo]);
+              cd.trans = (i < j) ? 1 : 0;
+              cd.rows = ri;
+              cd.dst = dbase + ro + co * lay.H[J];
+              cd.ldd = int32_t(lay.H[J]);
+              const int32_t step = std::max(1, COPY_CHUNK / ri);  // column ranges of at most COPY_CHUNK entries
+              for (int32_t c0 = 0; c0 < rj; c0 += step) {
+                cd.c0 = c0;
+                cd.c1 = std::min(rj, c0 + step);
+                dst.push_back(cd);
+              }
+            }
+          }
+          co += rj;
+        }
+        ro += ri;
       }
     }
-    DevBuf dtb, xb;
-    if ((st = upload(h, dtb, tbs)) != SPAND_OK) return st;
-    launch_build_t_diag(dtb.as<TBlock>(), int32_t(tbs.size()), h->stream);
-    HIPCHK(hipGetLastError());
-    if (rmax > 64) {
-      if ((st = dalloc(h, xb, size_t(x_total) * sizeof(double))) != SPAND_OK) return st;
-      GemmSeq tg2;
-      for (int32_t j0 = 64; j0 < rmax; j0 += 64) {
-        for (size_t q = 0; q < tds.size(); ++q) {
-          const TDesc& td = tds[q];
-          if (td.r <= j0) continue;
-          const int32_t w = std::min(64, td.r - j0);
-          GemmDesc g{};  // X = S[:j0, J] T_JJ
-          g.A = td.T + int64_t(j0) * td.r; g.lda = td.r;
-          g.B = td.T + j0 + int64_t(j0) * td.r; g.ldb = td.r;
-          g.C = xb.as<double>() + x_off[q]; g.ldc = td.r;
-          g.M = j0; g.N = w; g.K = w;
-          g.alpha = 1.0; g.beta = 0.0;
-          tg2.add(g, 0);
-        }
-        tg2.end_launch(0);
-        for (size_t q = 0; q < tds.size(); ++q) {
-          const TDesc& td = tds[q];
-          if (td.r <= j0) continue;
-          const int32_t w = std::min(64, td.r - j0);
-          GemmDesc g{};  // T[:j0, J] = -T[:j0, :j0] X
-          g.A = td.T; g.lda = td.r;
-          g.B = xb.as<double>() + x_off[q]; g.ldb = td.r;
-          g.C = td.T + int64_t(j0) * td.r; g.ldc = td.r;
-          g.M = j0; g.N = w; g.K = j0;
-          g.alpha = -1.0; g.beta = 0.0;
-          tg2.add(g, 0);
-        }
-        tg2.end_launch(0);
-      }
-      if ((st = tg2.upload_all(h)) != SPAND_OK) return st;
-      for (size_t q = 0; q < tg2.cut.size(); ++q) tg2.launch(h, q);
-      HIPCHK(hipGetLastError());
+  };
+  const size_t npair = sy.before.size();
+  const size_t nth = std::min<size_t>(8, std::max<size_t>(1, npair / 4096));
+  if (nth == 1) {
+    plan_copies(0, npair, out);
+    return;
+  }
+  std::vector<std::vector<CopyDesc>> part(nth);
+  {
+    std::vector<std::thread> pool;
+    for (size_t k = 1; k < nth; ++k)
+      pool.emplace_back(plan_copies, npair * k / nth, npair * (k + 1) / nth, std::ref(part[k]));
+    plan_copies(0, npair / nth, part[0]);
+    for (std::thread& th : pool) th.join();
+  }
+  size_t total = out.size();
+  for (auto& pp : part) total += pp.size();
+  out.reserve(total);
+  for (auto& pp : part) out.insert(out.end(), pp.begin(), pp.end());
+}
+
+// Host-to-device copy of a descriptor list through pinned staging, with the pinned
+// copy done by several threads when the list is large.
+template <typename T>
+spand_status upload_big(spand_ctx* h, DevBuf& b, const std::vector<T>& v) {
+  const size_t bytes = v.size() * sizeof(T);
+  spand_status st = dalloc(h, b, bytes);
+  if (st != SPAND_OK || bytes == 0) return st;
+  char* hp = h->stage.get(bytes);
+  if (!hp) return set_err(h, SPAND_E_NOMEM, "pinned staging of " + std::to_string(bytes) + " bytes failed");
+  const size_t nth = std::min<size_t>(8, std::max<size_t>(1, bytes >> 22));
+  if (nth == 1) {
+    std::memcpy(hp, v.data(), bytes);
+  } else {
+    std::vector<std::thread> pool;
+    auto put = [&](size_t k) {
+      const size_t a = v.size() * k / nth, e = v.size() * (k + 1) / nth;
+      std::memcpy(hp + a * sizeof(T), v.data() + a, (e - a) * sizeof(T));
+    };
+    for (size_t k = 1; k < nth; ++k) pool.emplace_back(put, k);
+    put(0);
+    for (std::thread& th : pool) th.join();
+  }
+  HIPCHK(hipMemcpyAsync(b.p, hp, bytes, hipMemcpyHostToDevice, h->stream));
+  return SPAND_OK;
+}
+
+// Problem index and cluster of a failure id of a run (ids carry the problem in
+// their high bits so that one flag word may serve several problems).
+constexpr int32_t FAIL_NONE = 0x7fffffff;
+
+spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_prec prec) {
+  spand_ctx* h = P[0].h;  // the run's stream, staging and scratch; errors of shared work
+  const int gemm_prec = (prec == SPAND_FP64) ? 0 : (prec == SPAND_FP32 ? 1 : 2);
+  const int32_t NP = int32_t(P.size());
+  int32_t Lmax = 0;
+  spand_status st;
+  for (Prob& pb : P) {
+    pb.L = pb.h->an.levels;
+    Lmax = std::max(Lmax, pb.L);
+    pb.h->stage.reset();
+    pb.h->num.clear();
+    pb.h->num.resize(pb.L);
+    pb.h->max_tmp = 0;
+    pb.h->max_gather = 0;
+    std::memset(pb.h->stats.step_phase_seconds, 0, sizeof(pb.h->stats.step_phase_seconds));
+    std::memset(pb.h->stats.step_m_F, 0, sizeof(pb.h->stats.step_m_F));
+  }
+  // failure and input flags of every problem, read back at one sync per step
+  DevBuf dflag;
+  {
+    std::vector<int32_t> init(size_t(4) * NP);
+    for (int32_t q = 0; q < NP; ++q) {
+      init[4 * q] = init[4 * q + 1] = FAIL_NONE;
+      init[4 * q + 2] = init[4 * q + 3] = 0;
     }
-    return SPAND_OK;
+    if ((st = upload(h, dflag, init)) != SPAND_OK) return st;
+    for (int32_t q = 0; q < NP; ++q) P[q].flags = dflag.as<int32_t>() + 4 * q;
+  }
+  std::vector<int32_t> hflags(size_t(4) * NP);
+  auto fail_problem = [&](Prob& pb, spand_status s2, const std::string& msg) {
+    set_err(pb.h, s2, msg);
+    pb.live = false;
   };
 
-  auto flush_apply = [&]() -> spand_status {
-    if (pending.t == 0) return SPAND_OK;
-    const int32_t pt = pending.t;
-    pending.t = 0;
-    return build_apply(h, an.steps[pt - 1], h->num[pt - 1], lay_prev, pending);
-  };
+  EventPool phev;   // 5 phase boundaries per step, read after the last sync
+  EventPool evpool; // every CPQR launch
+  std::vector<char> elim_ran(size_t(Lmax) + 1, 0);
+  double cpqr_ms = 0.0;
+  int64_t cpqr_launches = 0;
 
-  for (int32_t t = 1; t <= Lv; ++t) {
-    const SymStep& sy = an.steps[t - 1];
-    StepNum& sn = h->num[t - 1];
-    const int32_t nc = sy.nc, ne = sy.ne;
-    const bool sparsify = (t > skip) && (sy.level > 1);
-    bool flags_read = false;  // this step's flags were checked at its rank read-back
+  for (int32_t t = 1; t <= Lmax; ++t) {
+    std::vector<Prob*> act;
+    for (Prob& pb : P) {
+      pb.on = pb.live && t <= pb.L;
+      if (pb.on) act.push_back(&pb);
+    }
+    if (act.empty()) break;
     hipEvent_t ph[5];
     for (int q = 0; q < 5; ++q) HIPCHK(phev.get(5 * size_t(t - 1) + q, &ph[q]));
 
-    // ---- sizes and slots of this step's clusters
-    sn.size.assign(nc, 0);
-    sn.slot_ptr.assign(nc + 1, 0);
-    if (t == 1) {
-      for (int32_t c = 0; c < nc; ++c) sn.size[c] = int32_t(sy.child_ptr[c + 1] - sy.child_ptr[c]);
-      sn.slot.assign(sy.child.begin(), sy.child.end());
-      for (int32_t c = 0; c < nc; ++c) sn.slot_ptr[c + 1] = sy.child_ptr[c + 1];
-    } else {
-      const StepNum& pv = h->num[t - 2];
-      for (int32_t c = 0; c < nc; ++c) {
-        int32_t s = 0;
-        for (int64_t e = sy.child_ptr[c]; e < sy.child_ptr[c + 1]; ++e) s += pv.rank[sy.child[e]];
-        sn.size[c] = s;
-        sn.slot_ptr[c + 1] = sn.slot_ptr[c] + s;
-      }
-      sn.slot.resize(sn.slot_ptr[nc]);
-      for (int32_t c = 0; c < nc; ++c) {
-        int64_t o = sn.slot_ptr[c];
-        for (int64_t e = sy.child_ptr[c]; e < sy.child_ptr[c + 1]; ++e) {
-          const int32_t ch = sy.child[e];
-          const int32_t r = pv.rank[ch];
-          std::copy(pv.slot.begin() + pv.slot_ptr[ch], pv.slot.begin() + pv.slot_ptr[ch] + r, sn.slot.begin() + o);
-          o += r;
-        }
-      }
-    }
-    if (sy.level == 1)
-      for (int32_t s = 0; s < ne; ++s) s_top += sn.size[s];
-
-    // ---- layout and assembly
+    // ---- sizes, slots, layout and assembly of every problem
     HIPCHK(hipEventRecord(ph[0], h->stream));
-    Layout lay;
-    build_layout(sy, sn.size, lay);
-    DevBuf arena;
-    if ((st = dalloc(h, sn.elim, size_t(lay.total_elim) * sizeof(double))) != SPAND_OK) return st;
-    if ((st = dalloc(h, arena, size_t(lay.total_arena) * sizeof(double))) != SPAND_OK) return st;
-    double* E = sn.elim.as<double>();
-    double* A = arena.as<double>();
-    if (lay.total_elim) HIPCHK(hipMemsetAsync(E, 0, size_t(lay.total_elim) * sizeof(double), h->stream));
-    if (lay.total_arena) HIPCHK(hipMemsetAsync(A, 0, size_t(lay.total_arena) * sizeof(double), h->stream));
-    DevBuf d_copy;
     std::vector<CopyDesc> copies;
-    if (t == 1 && h->d_dst1.p) {
-      // the step-1 layout depends on the pattern only: reuse the map of an earlier factor
-      launch_scatter_values(values, h->d_dst1.as<int64_t>(), int64_t(an.colind.size()), A, E, d_nonfinite, h->stream);
-      HIPCHK(hipGetLastError());
-    } else if (t == 1) {
-      // destination of every CSR entry inside the step-1 panels: >= 0 arena offset,
-      // <= -2 elimination-buffer offset -(d+2), -1 skipped (upper triangle)
-      std::vector<int32_t> cl(an.n), pos(an.n);
-      for (int32_t c = 0; c < nc; ++c)
-        for (int64_t e = sy.child_ptr[c]; e < sy.child_ptr[c + 1]; ++e) {
-          cl[sy.child[e]] = c;
-          pos[sy.child[e]] = int32_t(e - sy.child_ptr[c]);
-        }
-      std::vector<int64_t> dst(an.colind.size(), -1);
-      for (int64_t v = 0; v < an.n; ++v)
-        for (int64_t e = an.rowptr[v]; e < an.rowptr[v + 1]; ++e) {
-          const int32_t u = an.colind[e];
-          const int32_t i = cl[v], j = cl[u];
-          if (i < j) continue;
-          const int64_t off = lay.base[j] + lay.find(i, j) + pos[v] + int64_t(pos[u]) * lay.H[j];
-          dst[e] = (j < ne) ? -(off + 2) : off;
-        }
-      if ((st = upload(h, h->d_dst1, dst)) != SPAND_OK) return st;
-      launch_scatter_values(values, h->d_dst1.as<int64_t>(), int64_t(dst.size()), A, E, d_nonfinite, h->stream);
-      HIPCHK(hipGetLastError());
-    } else {
-      const StepNum& pv = h->num[t - 2];
-      // the copies of the pairs [q0, q1) of `before`, in order
-      auto plan_copies = [&](size_t q0, size_t q1, std::vector<CopyDesc>& out) {
-        for (size_t q = q0; q < q1; ++q) {
-          const uint64_t pr = sy.before[q];
-          const int32_t I = pair_i(pr), J = pair_j(pr);
-          double* dbase = lay.panel(J, E, A) + lay.find(I, J);
-          int64_t ro = 0;
-          for (int64_t a = sy.child_ptr[I]; a < sy.child_ptr[I + 1]; ++a) {
-            const int32_t i = sy.child[a];
-            const int32_t ri = pv.rank[i];
-            int64_t co = 0;
-            for (int64_t b = sy.child_ptr[J]; b < sy.child_ptr[J + 1]; ++b) {
-              const int32_t j = sy.child[b];
-              const int32_t rj = pv.rank[j];
-              if (ri > 0 && rj > 0) {
-                const int32_t hi = std::max(i, j), lo = std::min(i, j);
-                const int64_t so = lay_prev.find(hi, lo);
-                if (so >= 0) {
-                  CopyDesc cd;
-                  cd.src = arena_prev.as<double>() + lay_prev.base[lo] + so;
-                  cd.lds = int32_t(lay_prev.H[lo]);
-                  cd.trans = (i < j) ? 1 : 0;
-                  cd.rows = ri;
-                  cd.dst = dbase + ro + co * lay.H[J];
-                  cd.ldd = int32_t(lay.H[J]);
-                  const int32_t step = std::max(1, COPY_CHUNK / ri);  // column ranges of at most COPY_CHUNK entries
-                  for (int32_t c0 = 0; c0 < rj; c0 += step) {
-                    cd.c0 = c0;
-                    cd.c1 = std::min(rj, c0 + step);
-                    out.push_back(cd);
-                  }
-                }
-              }
-              co += rj;
+    for (Prob* pp : act) {
+      Prob& pb = *pp;
+      spand_ctx* hq = pb.h;
+      const SymStep& sy = hq->an.steps[t - 1];
+      step_sizes(sy, t, hq->num);
+      StepNum& sn = hq->num[t - 1];
+      const int32_t nc = sy.nc, ne = sy.ne;
+      pb.sparsify = (t > skip) && (sy.level > 1);
+      if (sy.level == 1)
+        for (int32_t s = 0; s < ne; ++s) pb.s_top += sn.size[s];
+      pb.lay = Layout();
+      build_layout(sy, sn.size, pb.lay);
+      const Layout& lay = pb.lay;
+      if ((st = dalloc(hq, sn.elim, size_t(lay.total_elim) * sizeof(double))) != SPAND_OK) return st;
+      if ((st = dalloc(hq, pb.arena, size_t(lay.total_arena) * sizeof(double))) != SPAND_OK) return st;
+      double* E = sn.elim.as<double>();
+      double* A = pb.arena.as<double>();
+      if (lay.total_elim) HIPCHK(hipMemsetAsync(E, 0, size_t(lay.total_elim) * sizeof(double), h->stream));
+      if (lay.total_arena) HIPCHK(hipMemsetAsync(A, 0, size_t(lay.total_arena) * sizeof(double), h->stream));
+      if (t == 1) {
+        if (!hq->d_dst1.p) {
+          // destination of every CSR entry inside the step-1 panels (it depends on the
+          // pattern only, so later factors reuse it): >= 0 arena offset, <= -2
+          // elimination-buffer offset -(d+2), -1 skipped (upper triangle)
+          const Analysis& an = hq->an;
+          std::vector<int32_t> cl(an.n), pos(an.n);
+          for (int32_t c = 0; c < nc; ++c)
+            for (int64_t e = sy.child_ptr[c]; e < sy.child_ptr[c + 1]; ++e) {
+              cl[sy.child[e]] = c;
+              pos[sy.child[e]] = int32_t(e - sy.child_ptr[c]);
             }
-            ro += ri;
-          }
+          std::vector<int64_t> dst(an.colind.size(), -1);
+          for (int64_t v = 0; v < an.n; ++v)
+            for (int64_t e = an.rowptr[v]; e < an.rowptr[v + 1]; ++e) {
+              const int32_t u = an.colind[e];
+              const int32_t i = cl[v], j = cl[u];
+              if (i < j) continue;
+              const int64_t off = lay.base[j] + lay.find(i, j) + pos[v] + int64_t(pos[u]) * lay.H[j];
+              dst[e] = (j < ne) ? -(off + 2) : off;
+            }
+          if ((st = upload(hq, hq->d_dst1, dst)) != SPAND_OK) return st;
         }
-      };
-      // large steps are planned by several host threads over contiguous ranges of
-      // pairs (they only read); each thread then writes its part into the pinned
-      // staging buffer at its offset, so the list is the same as one thread's
-      const size_t npair = sy.before.size();
-      const size_t nth = std::min<size_t>(8, std::max<size_t>(1, npair / 4096));
-      if (nth == 1) {
-        plan_copies(0, npair, copies);
-        if ((st = upload(h, d_copy, copies)) != SPAND_OK) return st;
-        launch_copy(d_copy.as<CopyDesc>(), int64_t(copies.size()), h->stream);
+        launch_scatter_values(pb.values, hq->d_dst1.as<int64_t>(), int64_t(hq->an.colind.size()), A, E, pb.flags + 2,
+                              h->stream);
+        HIPCHK(hipGetLastError());
       } else {
-        std::vector<std::vector<CopyDesc>> part(nth);
-        {
-          std::vector<std::thread> pool;
-          for (size_t k = 1; k < nth; ++k)
-            pool.emplace_back(plan_copies, npair * k / nth, npair * (k + 1) / nth, std::ref(part[k]));
-          plan_copies(0, npair / nth, part[0]);
-          for (std::thread& th : pool) th.join();
-        }
-        std::vector<size_t> off(nth + 1, 0);
-        for (size_t k = 0; k < nth; ++k) off[k + 1] = off[k] + part[k].size();
-        const size_t bytes = off[nth] * sizeof(CopyDesc);
-        if ((st = dalloc(h, d_copy, bytes)) != SPAND_OK) return st;
-        char* hp = h->stage.get(bytes);
-        if (bytes > 0 && !hp) return set_err(h, SPAND_E_NOMEM, "pinned staging of " + std::to_string(bytes) + " bytes failed");
-        {
-          auto put = [&](size_t k) {
-            if (!part[k].empty()) std::memcpy(hp + off[k] * sizeof(CopyDesc), part[k].data(), part[k].size() * sizeof(CopyDesc));
-          };
-          std::vector<std::thread> pool;
-          for (size_t k = 1; k < nth; ++k) pool.emplace_back(put, k);
-          put(0);
-          for (std::thread& th : pool) th.join();
-        }
-        if (bytes > 0) {
-          HIPCHK(hipMemcpyAsync(d_copy.p, hp, bytes, hipMemcpyHostToDevice, h->stream));
-          launch_copy(d_copy.as<CopyDesc>(), int64_t(off[nth]), h->stream);
-        }
+        plan_merge(sy, hq->num[t - 2], lay, pb.lay_prev, E, A, pb.arena_prev.as<double>(), copies);
       }
+    }
+    if (!copies.empty()) {
+      DevBuf d_copy;
+      if ((st = upload_big(h, d_copy, copies)) != SPAND_OK) return st;
+      launch_copy(d_copy.as<CopyDesc>(), int64_t(copies.size()), h->stream);
       HIPCHK(hipGetLastError());
     }
 
-    // ---- elimination (Sec. 2.4)
+    // ---- elimination (Sec. 2.4) of every problem's level-l clusters, in shared launches
     HIPCHK(hipEventRecord(ph[1], h->stream));
     HIPCHK(hipEventRecord(ph[2], h->stream));  // recorded again after the reduction
-    std::vector<int64_t> c_off(ne), ed_off(ne);
-    std::vector<int32_t> nN(ne);
-    int64_t cbuf_total = 0, ed_total = 0;
-    for (int32_t s = 0; s < ne; ++s) {
-      nN[s] = int32_t(lay.H[s] - sn.size[s]);
-      c_off[s] = cbuf_total;
-      cbuf_total += int64_t(nN[s]) * nN[s];
-      ed_off[s] = ed_total;
-      ed_total += dinv_size(sn.size[s]);
-      const double ns = sn.size[s], nn = nN[s];
-      elim_flops += nn * ns * ns + nn * (nn + 1.0) * ns;
-      m_F += int64_t(sn.size[s]) * (sn.size[s] + 1) / 2 + int64_t(sn.size[s]) * nN[s];
-    }
-    if ((st = dalloc(h, sn.edinv, size_t(ed_total) * sizeof(double))) != SPAND_OK) return st;
-    DevBuf cbuf;
-    if ((st = dalloc(h, cbuf, size_t(cbuf_total) * sizeof(double))) != SPAND_OK) return st;
     {
       std::vector<Front> fr;
-      for (int32_t s = 0; s < ne; ++s)
-        if (sn.size[s] > 0)
-          fr.push_back(Front{E + lay.base[s], sn.edinv.as<double>() + ed_off[s], int32_t(lay.H[s]), sn.size[s],
-                             int32_t(lay.H[s]), s});
-      if ((st = blocked_cholesky(h, fr, d_fail_elim, gemm_prec)) != SPAND_OK) return st;
       GemmSeq syrk;
-      for (int32_t s = 0; s < ne; ++s) {
-        const int32_t ns = sn.size[s], nn = nN[s];
-        GemmDesc y{};
-        y.A = E + lay.base[s] + ns; y.lda = int32_t(lay.H[s]);
-        y.B = y.A; y.ldb = y.lda;
-        y.C = cbuf.as<double>() + c_off[s]; y.ldc = nn;
-        y.M = nn; y.N = nn; y.K = ns;
-        y.flags = G_TB | G_LOWERC;
-        y.alpha = 1.0; y.beta = 0.0;
-        syrk.add(y, 1);
+      struct Item { int32_t prob; uint64_t tgt; int32_t s; int64_t coff; };
+      std::vector<ReduceDesc> rds;
+      std::vector<ContribDesc> cds2;
+      for (Prob* pp : act) {
+        Prob& pb = *pp;
+        spand_ctx* hq = pb.h;
+        const SymStep& sy = hq->an.steps[t - 1];
+        StepNum& sn = hq->num[t - 1];
+        const Layout& lay = pb.lay;
+        const int32_t ne = sy.ne;
+        double* E = sn.elim.as<double>();
+        double* A = pb.arena.as<double>();
+        pb.c_off.assign(ne, 0);
+        pb.ed_off.assign(ne, 0);
+        pb.nN.assign(ne, 0);
+        int64_t cbuf_total = 0, ed_total = 0;
+        for (int32_t s = 0; s < ne; ++s) {
+          pb.nN[s] = int32_t(lay.H[s] - sn.size[s]);
+          pb.c_off[s] = cbuf_total;
+          cbuf_total += int64_t(pb.nN[s]) * pb.nN[s];
+          pb.ed_off[s] = ed_total;
+          ed_total += dinv_size(sn.size[s]);
+          const double ns = sn.size[s], nn = pb.nN[s];
+          pb.elim_flops += nn * ns * ns + nn * (nn + 1.0) * ns;
+          pb.m_F += int64_t(sn.size[s]) * (sn.size[s] + 1) / 2 + int64_t(sn.size[s]) * pb.nN[s];
+        }
+        if ((st = dalloc(hq, sn.edinv, size_t(ed_total) * sizeof(double))) != SPAND_OK) return st;
+        if ((st = dalloc(hq, pb.cbuf, size_t(cbuf_total) * sizeof(double))) != SPAND_OK) return st;
+        const int32_t qid = int32_t(pp - P.data());
+        for (int32_t s = 0; s < ne; ++s)
+          if (sn.size[s] > 0)
+            fr.push_back(Front{E + lay.base[s], sn.edinv.as<double>() + pb.ed_off[s], int32_t(lay.H[s]), sn.size[s],
+                               int32_t(lay.H[s]), s, P[qid].flags + 0});
+        for (int32_t s = 0; s < ne; ++s) {
+          const int32_t ns = sn.size[s], nn = pb.nN[s];
+          GemmDesc y{};
+          y.A = E + lay.base[s] + ns; y.lda = int32_t(lay.H[s]);
+          y.B = y.A; y.ldb = y.lda;
+          y.C = pb.cbuf.as<double>() + pb.c_off[s]; y.ldc = nn;
+          y.M = nn; y.N = nn; y.K = ns;
+          y.flags = G_TB | G_LOWERC;
+          y.alpha = 1.0; y.beta = 0.0;
+          syrk.add(y, 1);
+        }
+        // deterministic reduction of C_s into the targets: contributions to one target
+        // block in ascending s
+        std::vector<Item> items;
+        for (int32_t s = 0; s < ne; ++s) {
+          const int64_t b = sy.enb_ptr[s], e = sy.enb_ptr[s + 1];
+          int64_t oa = 0;
+          for (int64_t a = b; a < e; ++a) {
+            const int32_t na = sy.enb[a];
+            int64_t ob = 0;
+            for (int64_t q = b; q <= a; ++q) {
+              const int32_t nb = sy.enb[q];
+              if (sn.size[na] > 0 && sn.size[nb] > 0 && sn.size[s] > 0)
+                items.push_back(Item{qid, pair_pack(na, nb), s, pb.c_off[s] + oa + ob * pb.nN[s]});
+              ob += sn.size[nb];
+            }
+            oa += sn.size[na];
+          }
+        }
+        std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.tgt < y.tgt; });
+        for (size_t q = 0; q < items.size();) {
+          size_t r = q;
+          const int32_t ia = pair_i(items[q].tgt), ib = pair_j(items[q].tgt);
+          ReduceDesc rd{};
+          rd.T = A + lay.base[ib] + lay.find(ia, ib);
+          rd.ldT = int32_t(lay.H[ib]);
+          rd.rows = sn.size[ia];
+          rd.cols = sn.size[ib];
+          rd.diag = (ia == ib);
+          rd.c_begin = int32_t(cds2.size());
+          while (r < items.size() && items[r].tgt == items[q].tgt) {
+            cds2.push_back(ContribDesc{pb.cbuf.as<double>() + items[r].coff, pb.nN[items[r].s], 0});
+            ++r;
+          }
+          rd.c_end = int32_t(cds2.size());
+          // large blocks are split into ranges of entries, one workgroup each
+          const int64_t cnt = int64_t(rd.rows) * rd.cols;
+          for (int64_t e0 = 0; e0 < cnt; e0 += REDUCE_CHUNK) {
+            rd.e0 = int32_t(e0);
+            rd.e1 = int32_t(std::min<int64_t>(cnt, e0 + REDUCE_CHUNK));
+            rds.push_back(rd);
+          }
+          q = r;
+        }
       }
+      if ((st = blocked_cholesky(h, fr, gemm_prec)) != SPAND_OK) return st;
       syrk.end_launch(gemm_prec);
       if ((st = syrk.upload_all(h)) != SPAND_OK) return st;
       syrk.launch(h, 0);
       HIPCHK(hipGetLastError());
-      // deterministic reduction of C_s into the targets
-      struct Item { uint64_t tgt; int32_t s; int64_t coff; };
-      std::vector<Item> items;
-      for (int32_t s = 0; s < ne; ++s) {
-        const int64_t b = sy.enb_ptr[s], e = sy.enb_ptr[s + 1];
-        int64_t oa = 0;
-        for (int64_t a = b; a < e; ++a) {
-          const int32_t na = sy.enb[a];
-          int64_t ob = 0;
-          for (int64_t q = b; q <= a; ++q) {
-            const int32_t nb = sy.enb[q];
-            if (sn.size[na] > 0 && sn.size[nb] > 0 && sn.size[s] > 0)
-              items.push_back(Item{pair_pack(na, nb), s, c_off[s] + oa + ob * nN[s]});
-            ob += sn.size[nb];
-          }
-          oa += sn.size[na];
-        }
-      }
-      std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.tgt < y.tgt; });
-      std::vector<ReduceDesc> rds;
-      std::vector<ContribDesc> cds2;
-      for (size_t q = 0; q < items.size();) {
-        size_t r = q;
-        const int32_t ia = pair_i(items[q].tgt), ib = pair_j(items[q].tgt);
-        ReduceDesc rd{};
-        rd.T = A + lay.base[ib] + lay.find(ia, ib);
-        rd.ldT = int32_t(lay.H[ib]);
-        rd.rows = sn.size[ia];
-        rd.cols = sn.size[ib];
-        rd.diag = (ia == ib);
-        rd.c_begin = int32_t(cds2.size());
-        while (r < items.size() && items[r].tgt == items[q].tgt) {
-          cds2.push_back(ContribDesc{cbuf.as<double>() + items[r].coff, nN[items[r].s], 0});
-          ++r;
-        }
-        rd.c_end = int32_t(cds2.size());
-        // large blocks are split into ranges of entries, one workgroup each
-        const int64_t cnt = int64_t(rd.rows) * rd.cols;
-        for (int64_t e0 = 0; e0 < cnt; e0 += REDUCE_CHUNK) {
-          rd.e0 = int32_t(e0);
-          rd.e1 = int32_t(std::min<int64_t>(cnt, e0 + REDUCE_CHUNK));
-          rds.push_back(rd);
-        }
-        q = r;
-      }
       DevBuf drd, dcd;
-      if ((st = upload(h, drd, rds)) != SPAND_OK) return st;
-      if ((st = upload(h, dcd, cds2)) != SPAND_OK) return st;
+      if ((st = upload_big(h, drd, rds)) != SPAND_OK) return st;
+      if ((st = upload_big(h, dcd, cds2)) != SPAND_OK) return st;
       launch_reduce(drd.as<ReduceDesc>(), int32_t(rds.size()), dcd.as<ContribDesc>(), h->stream);
       HIPCHK(hipGetLastError());
       HIPCHK(hipEventRecord(ph[2], h->stream));
       elim_ran[t] = 1;
+      for (Prob* pp : act) pp->cbuf.release();
     }
-    cbuf.release();
 
-    // ---- scaling (Sec. 2.5) and sparsification (Sec. 2.6.1)
-    sn.rank.assign(nc, -1);
-    for (int32_t c = ne; c < nc; ++c) sn.rank[c] = sn.size[c];
-    std::vector<int64_t> sc_off(nc, -1), sd_off(nc, -1), v_off(nc, -1), tau_off(nc, -1), t_off(nc, -1);
-    std::vector<int32_t> nref(nc, 0);
+    // ---- scaling (Sec. 2.5) of every sparsified problem's interfaces
     HIPCHK(hipEventRecord(ph[3], h->stream));
     HIPCHK(hipEventRecord(ph[4], h->stream));
-    if (sparsify && nc > ne) {
-      int64_t sc_total = 0, sd_total = 0;
-      for (int32_t p = ne; p < nc; ++p) {
-        if (sn.size[p] == 0) continue;
-        sc_off[p] = sc_total;
-        sc_total += int64_t(sn.size[p]) * sn.size[p];
-        sd_off[p] = sd_total;
-        sd_total += dinv_size(sn.size[p]);
-        m_F += int64_t(sn.size[p]) * (sn.size[p] + 1) / 2;
-      }
-      if ((st = dalloc(h, sn.scale, size_t(sc_total) * sizeof(double))) != SPAND_OK) return st;
-      if ((st = dalloc(h, sn.sdinv, size_t(sd_total) * sizeof(double))) != SPAND_OK) return st;
-      double* SC = sn.scale.as<double>();
-      double* SD = sn.sdinv.as<double>();
+    bool any_sparsify = false;
+    {
       std::vector<Front> fr;
-      for (int32_t p = ne; p < nc; ++p)
-        if (sn.size[p] > 0)
-          fr.push_back(Front{A + lay.base[p], SD + sd_off[p], int32_t(lay.H[p]), sn.size[p], int32_t(lay.H[p]), p});
-      if ((st = blocked_cholesky(h, fr, d_fail_scale, 0)) != SPAND_OK) return st;
-      // L_p^{-1} for the apply (the identity solved against L_p), and L_i^{-1} from the
-      // left on every block (i, p), in one blocked left solve
       std::vector<LeftBlock> lb;
-      std::vector<IdentDesc> ids;
-      for (int32_t p = ne; p < nc; ++p) {
-        if (sn.size[p] == 0) continue;
-        add_identity(ids, SC + sc_off[p], sn.size[p], sn.size[p]);
-        lb.push_back(LeftBlock{SC + sc_off[p], A + lay.base[p], SD + sd_off[p], sn.size[p], int32_t(lay.H[p]),
-                               sn.size[p], sn.size[p]});
-        for (int64_t e = lay.pan_ptr[p] + 1; e < lay.pan_ptr[p + 1]; ++e) {
-          const int32_t i = lay.prow[e];
-          if (sn.size[i] == 0) continue;
-          lb.push_back(LeftBlock{A + lay.base[p] + lay.proff[e], A + lay.base[i], SD + sd_off[i], int32_t(lay.H[p]),
-                                 int32_t(lay.H[i]), sn.size[i], sn.size[p]});
+      std::vector<IdentDesc> ids, did;
+      for (Prob* pp : act) {
+        Prob& pb = *pp;
+        spand_ctx* hq = pb.h;
+        const SymStep& sy = hq->an.steps[t - 1];
+        StepNum& sn = hq->num[t - 1];
+        const int32_t nc = sy.nc, ne = sy.ne;
+        sn.rank.assign(nc, -1);
+        for (int32_t c = ne; c < nc; ++c) sn.rank[c] = sn.size[c];
+        pb.sc_off.assign(nc, -1);
+        pb.sd_off.assign(nc, -1);
+        pb.v_off.assign(nc, -1);
+        pb.tau_off.assign(nc, -1);
+        pb.t_off.assign(nc, -1);
+        pb.nref.assign(nc, 0);
+        if (!(pb.sparsify && nc > ne)) continue;
+        any_sparsify = true;
+        const Layout& lay = pb.lay;
+        double* A = pb.arena.as<double>();
+        int64_t sc_total = 0, sd_total = 0;
+        for (int32_t p = ne; p < nc; ++p) {
+          if (sn.size[p] == 0) continue;
+          pb.sc_off[p] = sc_total;
+          sc_total += int64_t(sn.size[p]) * sn.size[p];
+          pb.sd_off[p] = sd_total;
+          sd_total += dinv_size(sn.size[p]);
+          pb.m_F += int64_t(sn.size[p]) * (sn.size[p] + 1) / 2;
         }
+        if ((st = dalloc(hq, sn.scale, size_t(sc_total) * sizeof(double))) != SPAND_OK) return st;
+        if ((st = dalloc(hq, sn.sdinv, size_t(sd_total) * sizeof(double))) != SPAND_OK) return st;
+        double* SC = sn.scale.as<double>();
+        double* SD = sn.sdinv.as<double>();
+        for (int32_t p = ne; p < nc; ++p)
+          if (sn.size[p] > 0)
+            fr.push_back(Front{A + lay.base[p], SD + pb.sd_off[p], int32_t(lay.H[p]), sn.size[p], int32_t(lay.H[p]), p,
+                               pb.flags + 1});
+        // L_p^{-1} for the apply (the identity solved against L_p), and L_i^{-1} from the
+        // left on every block (i, p), in one blocked left solve
+        for (int32_t p = ne; p < nc; ++p) {
+          if (sn.size[p] == 0) continue;
+          add_identity(ids, SC + pb.sc_off[p], sn.size[p], sn.size[p]);
+          lb.push_back(LeftBlock{SC + pb.sc_off[p], A + lay.base[p], SD + pb.sd_off[p], sn.size[p], int32_t(lay.H[p]),
+                                 sn.size[p], sn.size[p]});
+          for (int64_t e = lay.pan_ptr[p] + 1; e < lay.pan_ptr[p + 1]; ++e) {
+            const int32_t i = lay.prow[e];
+            if (sn.size[i] == 0) continue;
+            lb.push_back(LeftBlock{A + lay.base[p] + lay.proff[e], A + lay.base[i], SD + pb.sd_off[i],
+                                   int32_t(lay.H[p]), int32_t(lay.H[i]), sn.size[i], sn.size[p]});
+          }
+        }
+        for (int32_t p = ne; p < nc; ++p)
+          if (sn.size[p] > 0) add_identity(did, A + lay.base[p], sn.size[p], int32_t(lay.H[p]));
       }
-      {
-        DevBuf d1;
+      if (any_sparsify) {
+        if ((st = blocked_cholesky(h, fr, 0)) != SPAND_OK) return st;
+        DevBuf d1, d2;
         if ((st = upload(h, d1, ids)) != SPAND_OK) return st;
         launch_set_identity(d1.as<IdentDesc>(), int32_t(ids.size()), h->stream);
         HIPCHK(hipGetLastError());
         if ((st = left_trsm(h, lb)) != SPAND_OK) return st;
+        if ((st = upload(h, d2, did)) != SPAND_OK) return st;
+        launch_set_identity(d2.as<IdentDesc>(), int32_t(did.size()), h->stream);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipEventRecord(ph[3], h->stream));
       }
-      std::vector<IdentDesc> did;
-      for (int32_t p = ne; p < nc; ++p)
-        if (sn.size[p] > 0) add_identity(did, A + lay.base[p], sn.size[p], int32_t(lay.H[p]));
-      DevBuf d1;
-      if ((st = upload(h, d1, did)) != SPAND_OK) return st;
-      launch_set_identity(d1.as<IdentDesc>(), int32_t(did.size()), h->stream);
-      HIPCHK(hipGetLastError());
-      HIPCHK(hipEventRecord(ph[3], h->stream));
+    }
 
-      // sparsification, colour by colour.  A_pn of interface p lives in the registers
-      // of slabS[p] workgroups with tg[p] lanes per column.  Interfaces of one slab go
-      // in one plain launch per team size; interfaces of several slabs go in one
-      // cooperative launch per colour, as rounds of at most the co-resident number of
-      // workgroups.
-      std::vector<int64_t> ncols(nc, 0);
+    // ---- sparsification (Sec. 2.6.1), one colour class of every problem at a time.
+    // A_pn of interface p lives in the registers of slabS[p] workgroups with tg[p]
+    // lanes per column.  Interfaces of one slab go in one plain launch per team size;
+    // interfaces of several slabs go in one cooperative launch per colour.
+    size_t nlaunch = 0;
+    DevBuf curb, nrefb, errb, xchb;
+    int64_t ncl = 0;  // clusters of the sparsified problems in the run's size and rank arrays
+    if (any_sparsify) {
       int32_t ncolour = 0;
-      int64_t house_total = 0, xch_total = 0;
-      std::vector<int64_t> xch_off(nc, -1);
-      std::vector<int32_t> slabS(nc, 0), tg(nc, 0), nseg(nc, 0);
-      std::vector<char> wide(nc, 0);  // single slab of the wide layout (teams of 2)
-      std::vector<int32_t> rlay(nc, 0);  // register layout of a multi-slab interface
-      for (int32_t p = ne; p < nc; ++p) {
-        for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e)
-          if (sn.size[sy.nb[e]] > 0) {
-            ncols[p] += sn.size[sy.nb[e]];
-            nseg[p]++;
-          }
-        if (sn.size[p] == 0 || ncols[p] == 0) continue;
-        ncolour = std::max(ncolour, sy.colour[p] + 1);
-        const int64_t m = sn.size[p];
-        const int32_t G = cpqr_team(sn.size[p]);
-        if (G < 0)
-          return set_err(h, SPAND_E_INVALID, "interface of " + std::to_string(m) +
-                                                 " dofs exceeds the largest CPQR team (2048 rows)");
-        tg[p] = G;
-        const int64_t cap = cpqr_capacity(G);
-        slabS[p] = int32_t((ncols[p] + cap - 1) / cap);
-        if (slabS[p] > 1 && G == 2 && m <= cpqr_wide_rows() && ncols[p] <= cpqr_wide_capacity()) {
-          wide[p] = 1;  // fits one workgroup of the wide layout: no exchange between slabs
-          slabS[p] = 1;
-        }
-        if (slabS[p] > 1) {  // layout 1 when it needs fewer slabs (and still more than one)
-          const int32_t G1 = cpqr_team(sn.size[p], 1);
-          if (G1 > 0) {
-            const int64_t cap1 = cpqr_capacity(G1, 1);
-            const int32_t S1 = int32_t((ncols[p] + cap1 - 1) / cap1);
-            if (S1 > 1 && S1 < slabS[p]) {
-              rlay[p] = 1;
-              tg[p] = G1;
-              slabS[p] = S1;
+      int64_t xch_total = 0;
+      std::vector<int32_t> cur_h;
+      for (Prob* pp : act) {
+        Prob& pb = *pp;
+        spand_ctx* hq = pb.h;
+        const SymStep& sy = hq->an.steps[t - 1];
+        StepNum& sn = hq->num[t - 1];
+        const int32_t nc = sy.nc, ne = sy.ne;
+        if (!(pb.sparsify && nc > ne)) continue;
+        pb.cbase = ncl;
+        ncl += nc;
+        cur_h.insert(cur_h.end(), sn.size.begin(), sn.size.end());
+        pb.ncols.assign(nc, 0);
+        pb.xch_off.assign(nc, -1);
+        pb.slabS.assign(nc, 0);
+        pb.tg.assign(nc, 0);
+        pb.nseg.assign(nc, 0);
+        pb.wide.assign(nc, 0);
+        pb.rlay.assign(nc, 0);
+        int64_t house_total = 0;
+        for (int32_t p = ne; p < nc; ++p) {
+          for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e)
+            if (sn.size[sy.nb[e]] > 0) {
+              pb.ncols[p] += sn.size[sy.nb[e]];
+              pb.nseg[p]++;
             }
+          if (sn.size[p] == 0 || pb.ncols[p] == 0) continue;
+          ncolour = std::max(ncolour, sy.colour[p] + 1);
+          const int64_t m = sn.size[p];
+          const int32_t G = cpqr_team(sn.size[p]);
+          if (G < 0)
+            return set_err(h, SPAND_E_INVALID, "interface of " + std::to_string(m) +
+                                                   " dofs exceeds the largest CPQR team (2048 rows)");
+          pb.tg[p] = G;
+          const int64_t cap = cpqr_capacity(G);
+          pb.slabS[p] = int32_t((pb.ncols[p] + cap - 1) / cap);
+          if (pb.slabS[p] > 1 && G == 2 && m <= cpqr_wide_rows() && pb.ncols[p] <= cpqr_wide_capacity()) {
+            pb.wide[p] = 1;  // fits one workgroup of the wide layout: no exchange between slabs
+            pb.slabS[p] = 1;
           }
-          xch_off[p] = xch_total;
-          xch_total += 3 * int64_t(slabS[p]) * cpqr_record(tg[p], rlay[p]);  // three exchange buffers
+          if (pb.slabS[p] > 1) {  // layout 1 when it needs fewer slabs (and still more than one)
+            const int32_t G1 = cpqr_team(sn.size[p], 1);
+            if (G1 > 0) {
+              const int64_t cap1 = cpqr_capacity(G1, 1);
+              const int32_t S1 = int32_t((pb.ncols[p] + cap1 - 1) / cap1);
+              if (S1 > 1 && S1 < pb.slabS[p]) {
+                pb.rlay[p] = 1;
+                pb.tg[p] = G1;
+                pb.slabS[p] = S1;
+              }
+            }
+            pb.xch_off[p] = xch_total;
+            xch_total += 3 * int64_t(pb.slabS[p]) * cpqr_record(pb.tg[p], pb.rlay[p]);  // three exchange buffers
+          }
+          const int64_t kmax = std::min<int64_t>(sn.size[p], pb.ncols[p]);
+          pb.v_off[p] = house_total;
+          house_total += int64_t(sn.size[p]) * kmax;
+          pb.tau_off[p] = house_total;
+          house_total += kmax;
+          pb.t_off[p] = house_total;  // compact WY factor T (r x r, r <= kmax)
+          house_total += kmax * kmax;
         }
-        const int64_t kmax = std::min<int64_t>(sn.size[p], ncols[p]);
-        v_off[p] = house_total;
-        house_total += int64_t(sn.size[p]) * kmax;
-        tau_off[p] = house_total;
-        house_total += kmax;
-        t_off[p] = house_total;  // compact WY factor T (r x r, r <= kmax)
-        house_total += kmax * kmax;
+        if ((st = dalloc(hq, sn.house, size_t(house_total) * sizeof(double))) != SPAND_OK) return st;
+        for (int32_t p = ne; p < nc; ++p)
+          if (pb.v_off[p] >= 0) ++pb.cpqr_ifaces[pb.slabS[p] > 1 ? 2 + pb.rlay[p] : (pb.wide[p] ? 1 : 0)];
       }
-      if ((st = dalloc(h, sn.house, size_t(house_total) * sizeof(double))) != SPAND_OK) return st;
-      DevBuf xchb, curb, nrefb, errb;
       if ((st = dalloc(h, xchb, size_t(xch_total) * sizeof(double))) != SPAND_OK) return st;
       // the exchange headers start with tag 0; the first exchange of a buffer uses tag 1
       if (xch_total > 0) HIPCHK(hipMemsetAsync(xchb.p, 0, size_t(xch_total) * sizeof(double), h->stream));
       if ((st = dalloc(h, errb, sizeof(int32_t))) != SPAND_OK) return st;
       HIPCHK(hipMemsetAsync(errb.p, 0, sizeof(int32_t), h->stream));
       // current sizes: interfaces shrink to their rank as their colour class finishes
-      if ((st = upload(h, curb, sn.size)) != SPAND_OK) return st;
-      if ((st = upload(h, nrefb, std::vector<int32_t>(nc, 0))) != SPAND_OK) return st;
-      for (int32_t p = ne; p < nc; ++p)
-        if (v_off[p] >= 0) ++cpqr_ifaces[slabS[p] > 1 ? 2 + rlay[p] : (wide[p] ? 1 : 0)];
-      std::vector<std::vector<int32_t>> by_colour(ncolour);
-      for (int32_t p = ne; p < nc; ++p)
-        if (v_off[p] >= 0) by_colour[sy.colour[p]].push_back(p);
+      if ((st = upload(h, curb, cur_h)) != SPAND_OK) return st;
+      if ((st = upload(h, nrefb, std::vector<int32_t>(size_t(ncl), 0))) != SPAND_OK) return st;
+      struct Ref { Prob* pb; int32_t p; };
+      std::vector<std::vector<Ref>> by_colour(ncolour);
+      for (Prob* pp : act) {
+        if (!(pp->sparsify && pp->h->an.steps[t - 1].nc > pp->h->an.steps[t - 1].ne)) continue;
+        const SymStep& sy = pp->h->an.steps[t - 1];
+        for (int32_t p = sy.ne; p < sy.nc; ++p)
+          if (pp->v_off[p] >= 0) by_colour[sy.colour[p]].push_back(Ref{pp, p});
+      }
       struct CpqrLaunch {
         bool multi;
         int32_t G, nslab, nround;
@@ -1027,7 +1106,6 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
       std::vector<SparsDesc> all_sds;
       std::vector<SegDesc> all_segs;
       std::vector<SlabRef> all_slabs;
-      size_t nlaunch = 0;
       // launch groups of one colour: single-slab interfaces per team size G
       // (group G), the wide single-slab ones (group 128), then every multi-slab
       // interface of the colour together (group 256)
@@ -1035,19 +1113,25 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
         if (by_colour[c].empty()) continue;
         for (int32_t grp = 1; grp <= 256; grp <<= 1) {
           const bool multi = grp == 256, wgrp = grp == 128;
-          std::vector<int32_t> plist;
-          for (int32_t p : by_colour[c])
-            if (multi ? slabS[p] > 1 : wgrp ? wide[p] != 0 : (slabS[p] == 1 && !wide[p] && tg[p] == grp))
-              plist.push_back(p);
+          std::vector<Ref> plist;
+          for (const Ref& f : by_colour[c]) {
+            const Prob& pb = *f.pb;
+            const int32_t p = f.p;
+            if (multi ? pb.slabS[p] > 1
+                      : wgrp ? pb.wide[p] != 0 : (pb.slabS[p] == 1 && !pb.wide[p] && pb.tg[p] == grp))
+              plist.push_back(f);
+          }
           if (plist.empty()) continue;
+          auto msize = [&](const Ref& f) { return f.pb->h->num[t - 1].size[f.p]; };
           // largest first: interfaces of similar step counts share a launch
-          std::stable_sort(plist.begin(), plist.end(), [&](int32_t x, int32_t y) {
-            if (multi) return sn.size[x] > sn.size[y];
-            return int64_t(sn.size[x]) * ncols[x] > int64_t(sn.size[y]) * ncols[y];
+          std::stable_sort(plist.begin(), plist.end(), [&](const Ref& x, const Ref& y) {
+            if (multi) return msize(x) > msize(y);
+            return int64_t(msize(x)) * x.pb->ncols[x.p] > int64_t(msize(y)) * y.pb->ncols[y.p];
           });
           size_t lds = 0;
-          for (int32_t p : plist)
-            lds = std::max(lds, wgrp ? cpqr_wide_lds_bytes(nseg[p]) : cpqr_lds_bytes(tg[p], rlay[p], nseg[p]));
+          for (const Ref& f : plist)
+            lds = std::max(lds, wgrp ? cpqr_wide_lds_bytes(f.pb->nseg[f.p])
+                                     : cpqr_lds_bytes(f.pb->tg[f.p], f.pb->rlay[f.p], f.pb->nseg[f.p]));
           int cap = INT_MAX;
           if (multi) {
             cap = cpqr_max_coresident(lds);
@@ -1055,31 +1139,36 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
           }
           // The chunks of at most cap co-resident slabs: one plain launch each for the
           // single-slab interfaces; for the multi-slab ones, the rounds of one launch.
-          CpqrLaunch L{};
-          L.multi = multi;
-          L.G = multi ? 0 : grp;  // 128: the wide layout
-          L.lds = lds;
-          L.d0 = all_sds.size();
+          CpqrLaunch Lc{};
+          Lc.multi = multi;
+          Lc.G = multi ? 0 : grp;  // 128: the wide layout
+          Lc.lds = lds;
+          Lc.d0 = all_sds.size();
           std::vector<std::vector<SlabRef>> rounds;
           size_t pos = 0;
           while (pos < plist.size()) {
             std::vector<SlabRef> rd;
             while (pos < plist.size()) {
-              const int32_t p = plist[pos];
-              if (multi && slabS[p] > cap)
+              const Prob& pb = *plist[pos].pb;
+              const int32_t p = plist[pos].p;
+              const StepNum& sn = pb.h->num[t - 1];
+              const SymStep& sy = pb.h->an.steps[t - 1];
+              const Layout& lay = pb.lay;
+              double* A = pb.arena.as<double>();
+              if (multi && pb.slabS[p] > cap)
                 return set_err(h, SPAND_E_INVALID, "interface needs more co-resident workgroups than the GPU holds");
-              if (multi && !rd.empty() && int64_t(rd.size()) + slabS[p] > cap) break;
+              if (multi && !rd.empty() && int64_t(rd.size()) + pb.slabS[p] > cap) break;
               SparsDesc d{};
-              d.V = sn.house.as<double>() + v_off[p];
-              d.tau = sn.house.as<double>() + tau_off[p];
+              d.V = sn.house.as<double>() + pb.v_off[p];
+              d.tau = sn.house.as<double>() + pb.tau_off[p];
               d.diag = A + lay.base[p];
               d.ldd = int32_t(lay.H[p]);
               d.m = sn.size[p];
-              d.id = p;
-              d.S = slabS[p];
-              d.G = tg[p];
-              d.lay = rlay[p];
-              if (multi) d.xch = xchb.as<double>() + xch_off[p];
+              d.id = int32_t(pb.cbase + p);
+              d.S = pb.slabS[p];
+              d.G = pb.tg[p];
+              d.lay = pb.rlay[p];
+              if (multi) d.xch = xchb.as<double>() + pb.xch_off[p];
               d.seg_begin = int32_t(all_segs.size());
               for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e) {
                 const int32_t q = sy.nb[e];
@@ -1094,11 +1183,11 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
                   g.ld = int32_t(lay.H[p]);
                   g.trans = 1;
                 }
-                g.q = q;
+                g.q = int32_t(pb.cbase + q);
                 all_segs.push_back(g);
               }
               d.seg_end = int32_t(all_segs.size());
-              for (int32_t w = 0; w < slabS[p]; ++w) rd.push_back(SlabRef{int32_t(all_sds.size() - L.d0), w});
+              for (int32_t w = 0; w < pb.slabS[p]; ++w) rd.push_back(SlabRef{int32_t(all_sds.size() - Lc.d0), w});
               all_sds.push_back(d);
               ++pos;
             }
@@ -1106,12 +1195,12 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
           }
           if (!multi) {
             for (const auto& rd : rounds) {
-              CpqrLaunch P = L;
-              P.s0 = all_slabs.size();
-              P.nslab = int32_t(rd.size());
-              P.nround = 1;
+              CpqrLaunch Pl = Lc;
+              Pl.s0 = all_slabs.size();
+              Pl.nslab = int32_t(rd.size());
+              Pl.nround = 1;
               all_slabs.insert(all_slabs.end(), rd.begin(), rd.end());
-              launches.push_back(P);
+              launches.push_back(Pl);
             }
           } else {
             // List scheduling over the co-resident workgroups: each interface, in
@@ -1127,7 +1216,8 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
                 ifs.emplace_back(&rd[k], int32_t(e - k));
                 k = e;
               }
-            if (ifs.size() != plist.size()) return set_err(h, SPAND_E_INVALID, "sparsification schedule: interfaces and slabs disagree");
+            if (ifs.size() != plist.size())
+              return set_err(h, SPAND_E_INVALID, "sparsification schedule: interfaces and slabs disagree");
             size_t total = 0;
             for (const auto& f : ifs) total += size_t(f.second);
             const size_t grid = std::min(total, size_t(cap));
@@ -1139,116 +1229,178 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
             std::make_heap(heap.begin(), heap.end(), std::greater<Slot>());
             std::vector<int32_t> wg;
             for (size_t q = 0; q < ifs.size(); ++q) {
-              const int32_t p = plist[q];
+              const Ref& f = plist[q];
               const int32_t S = ifs[q].second;
               wg.clear();
-              int64_t t = 0;
+              int64_t tt = 0;
               for (int32_t k = 0; k < S; ++k) {
                 std::pop_heap(heap.begin(), heap.end(), std::greater<Slot>());
-                t = std::max(t, heap.back().first);
+                tt = std::max(tt, heap.back().first);
                 wg.push_back(heap.back().second);
                 heap.pop_back();
               }
-              t += std::min<int64_t>(sn.size[p], ncols[p]);
+              tt += std::min<int64_t>(msize(f), f.pb->ncols[f.p]);
               for (int32_t k = 0; k < S; ++k) {
                 lists[wg[k]].push_back(ifs[q].first[k]);
-                heap.push_back(Slot{t, wg[k]});
+                heap.push_back(Slot{tt, wg[k]});
                 std::push_heap(heap.begin(), heap.end(), std::greater<Slot>());
               }
             }
             size_t nround = 0;
             for (const auto& l : lists) nround = std::max(nround, l.size());
-            L.s0 = all_slabs.size();
-            L.nslab = int32_t(grid);
-            L.nround = int32_t(nround);
+            Lc.s0 = all_slabs.size();
+            Lc.nslab = int32_t(grid);
+            Lc.nround = int32_t(nround);
             for (size_t k = 0; k < nround; ++k)
               for (size_t b = 0; b < grid; ++b) all_slabs.push_back(k < lists[b].size() ? lists[b][k] : SlabRef{-1, 0});
-            launches.push_back(L);
+            launches.push_back(Lc);
           }
         }
       }
       // every launch of the step is planned: one upload, then the launches back to back
       DevBuf a, b, sl;
-      if ((st = upload(h, a, all_sds)) != SPAND_OK) return st;
-      if ((st = upload(h, b, all_segs)) != SPAND_OK) return st;
-      if ((st = upload(h, sl, all_slabs)) != SPAND_OK) return st;
-      for (const CpqrLaunch& L : launches) {
+      if ((st = upload_big(h, a, all_sds)) != SPAND_OK) return st;
+      if ((st = upload_big(h, b, all_segs)) != SPAND_OK) return st;
+      if ((st = upload_big(h, sl, all_slabs)) != SPAND_OK) return st;
+      for (const CpqrLaunch& Lc : launches) {
         hipEvent_t e0, e1;
         HIPCHK(evpool.get(2 * nlaunch, &e0));
         HIPCHK(evpool.get(2 * nlaunch + 1, &e1));
         HIPCHK(hipEventRecord(e0, h->stream));
-        const SparsDesc* dd = a.as<SparsDesc>() + L.d0;
-        const SlabRef* ss = sl.as<SlabRef>() + L.s0;
-        hipError_t le = L.multi ? launch_cpqr_multi(dd, ss, L.nslab, L.nround, b.as<SegDesc>(), tol,
-                                                    curb.as<int32_t>(), nrefb.as<int32_t>(), errb.as<int32_t>(),
-                                                    L.lds, h->stream)
-                    : L.G == 128 ? launch_cpqr_one_wide(dd, ss, L.nslab, b.as<SegDesc>(), tol, curb.as<int32_t>(),
-                                                        nrefb.as<int32_t>(), errb.as<int32_t>(), L.lds, h->stream)
-                                 : launch_cpqr_one(L.G, dd, ss, L.nslab, b.as<SegDesc>(), tol, curb.as<int32_t>(),
-                                                   nrefb.as<int32_t>(), errb.as<int32_t>(), L.lds, h->stream);
+        const SparsDesc* dd = a.as<SparsDesc>() + Lc.d0;
+        const SlabRef* ss = sl.as<SlabRef>() + Lc.s0;
+        hipError_t le = Lc.multi ? launch_cpqr_multi(dd, ss, Lc.nslab, Lc.nround, b.as<SegDesc>(), tol,
+                                                     curb.as<int32_t>(), nrefb.as<int32_t>(), errb.as<int32_t>(),
+                                                     Lc.lds, h->stream)
+                     : Lc.G == 128 ? launch_cpqr_one_wide(dd, ss, Lc.nslab, b.as<SegDesc>(), tol, curb.as<int32_t>(),
+                                                          nrefb.as<int32_t>(), errb.as<int32_t>(), Lc.lds, h->stream)
+                                   : launch_cpqr_one(Lc.G, dd, ss, Lc.nslab, b.as<SegDesc>(), tol, curb.as<int32_t>(),
+                                                     nrefb.as<int32_t>(), errb.as<int32_t>(), Lc.lds, h->stream);
         if (le != hipSuccess)
           return set_err(h, SPAND_E_HIP, std::string("sparsification launch: ") + hipGetErrorString(le));
         HIPCHK(hipEventRecord(e1, h->stream));
         ++nlaunch;
       }
-      std::vector<int32_t> rk(nc, -1);
       HIPCHK(hipEventRecord(ph[4], h->stream));
-      if ((st = flush_t()) != SPAND_OK) return st;      // the previous step's, while this one runs
-      if ((st = flush_apply()) != SPAND_OK) return st;
-      if ((st = check_flags(t)) != SPAND_OK) return st;
-      flags_read = true;
-      HIPCHK(hipMemcpyAsync(rk.data(), curb.p, size_t(nc) * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
-      HIPCHK(hipMemcpyAsync(nref.data(), nrefb.p, size_t(nc) * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
-      int32_t serr = 0;
-      HIPCHK(hipMemcpyAsync(&serr, errb.p, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
-      HIPCHK(hipStreamSynchronize(h->stream));
-      if (serr) return set_err(h, SPAND_E_HIP, "sparsification slab exchange timed out");
-      for (size_t q = 0; q < nlaunch; ++q) {
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, evpool.ev[2 * q], evpool.ev[2 * q + 1]));
-        cpqr_ms += ms;
-      }
-      cpqr_launches += int64_t(nlaunch);
+    }
+
+    // ---- while the step's last kernels run: the previous step's T factors and apply
+    // descriptors; then one sync for the flags of every problem and the ranks
+    {
       std::vector<TDesc> tds;
-      for (int32_t p = ne; p < nc; ++p)
-        if (v_off[p] >= 0) {
-          sn.rank[p] = rk[p];
-          const int64_t r = nref[p];
-          {
-            // sum over steps j < r of 2 (m-j)(n-j) + 4 (m-j)(n-j-1) + 3 (m-j)
-            // = 6 (m-j)(n-j) - (m-j), in closed form (exact in 64-bit integers)
-            const int64_t m = sn.size[p], nq = ncols[p];
-            const int64_t s1 = r * (r - 1) / 2, s2 = (r - 1) * r * (2 * r - 1) / 6;
-            const int64_t f = 6 * (r * m * nq - (m + nq) * s1 + s2) - (r * m - s1);
-            cpqr_flops += double(f);
-            if (r < std::min<int64_t>(m, nq)) cpqr_flops += 2.0 * double(m - r) * double(nq - r);
+      for (Prob& pb : P) {
+        tds.insert(tds.end(), pb.t_pending.begin(), pb.t_pending.end());
+        pb.t_pending.clear();
+      }
+      if ((st = build_t_factors(h, tds)) != SPAND_OK) return st;
+    }
+    for (Prob& pb : P) {
+      if (pb.pending.t == 0) continue;
+      const int32_t pt = pb.pending.t;
+      pb.pending.t = 0;
+      if (!pb.live) continue;
+      if ((st = build_apply(pb.h, pb.h->an.steps[pt - 1], pb.h->num[pt - 1], pb.lay_prev, pb.pending)) != SPAND_OK)
+        return st;
+    }
+    std::vector<int32_t> rk(size_t(ncl), -1), nrefh(size_t(ncl), 0);
+    int32_t serr = 0;
+    HIPCHK(hipMemcpyAsync(hflags.data(), dflag.p, hflags.size() * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    if (any_sparsify) {
+      HIPCHK(hipMemcpyAsync(rk.data(), curb.p, size_t(ncl) * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(hipMemcpyAsync(nrefh.data(), nrefb.p, size_t(ncl) * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(hipMemcpyAsync(&serr, errb.p, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    }
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (serr) return set_err(h, SPAND_E_HIP, "sparsification slab exchange timed out");
+    for (size_t q = 0; q < nlaunch; ++q) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, evpool.ev[2 * q], evpool.ev[2 * q + 1]));
+      cpqr_ms += ms;
+    }
+    cpqr_launches += int64_t(nlaunch);
+    // Kernels that ran after a failure in the same step only saw bad values, never bad
+    // indices; the failed problem stops here, the others go on.
+    for (Prob* pp : act) {
+      Prob& pb = *pp;
+      const int32_t q = int32_t(pp - P.data());
+      const int32_t* fl = hflags.data() + 4 * q;
+      spand_ctx* hq = pb.h;
+      if (fl[2]) {
+        fail_problem(pb, SPAND_E_INVALID, "matrix values contain NaN or Inf");
+      } else if (fl[0] != FAIL_NONE) {
+        hq->stats.fail_step = t;
+        hq->stats.fail_cluster = fl[0];
+        hq->stats.fail_phase = 0;
+        fail_problem(pb, SPAND_E_NOT_SPD, "pivot block not SPD at step " + std::to_string(t) + ", cluster " +
+                                              std::to_string(fl[0]) + " (elimination)");
+      } else if (fl[1] != FAIL_NONE) {
+        hq->stats.fail_step = t;
+        hq->stats.fail_cluster = fl[1];
+        hq->stats.fail_phase = 1;
+        fail_problem(pb, SPAND_E_NOT_SPD, "interface block not SPD at step " + std::to_string(t) + ", cluster " +
+                                              std::to_string(fl[1]) + " (scaling)");
+      }
+      if (!pb.live) {
+        pb.t_pending.clear();
+        pb.arena.release();
+        pb.arena_prev.release();
+        hq->num.clear();
+        continue;
+      }
+      const SymStep& sy = hq->an.steps[t - 1];
+      StepNum& sn = hq->num[t - 1];
+      const int32_t nc = sy.nc, ne = sy.ne;
+      if (pb.sparsify && nc > ne) {
+        std::vector<TDesc> tds;
+        for (int32_t p = ne; p < nc; ++p)
+          if (pb.v_off[p] >= 0) {
+            sn.rank[p] = rk[pb.cbase + p];
+            const int64_t r = nrefh[pb.cbase + p];
+            pb.nref[p] = int32_t(r);
+            {
+              // sum over steps j < r of 2 (m-j)(n-j) + 4 (m-j)(n-j-1) + 3 (m-j)
+              // = 6 (m-j)(n-j) - (m-j), in closed form (exact in 64-bit integers)
+              const int64_t m = sn.size[p], nq = pb.ncols[p];
+              const int64_t s1 = r * (r - 1) / 2, s2 = (r - 1) * r * (2 * r - 1) / 6;
+              const int64_t f = 6 * (r * m * nq - (m + nq) * s1 + s2) - (r * m - s1);
+              pb.cpqr_flops += double(f);
+              if (r < std::min<int64_t>(m, nq)) pb.cpqr_flops += 2.0 * double(m - r) * double(nq - r);
+            }
+            pb.m_F += (2 * int64_t(sn.size[p]) - r + 1) * r / 2 + r;
+            if (r > 0)
+              tds.push_back(TDesc{sn.house.as<double>() + pb.v_off[p], sn.house.as<double>() + pb.tau_off[p],
+                                  sn.house.as<double>() + pb.t_off[p], sn.size[p], int32_t(r)});
           }
-          m_F += (2 * int64_t(sn.size[p]) - r + 1) * r / 2 + r;
-          if (r > 0)
-            tds.push_back(TDesc{sn.house.as<double>() + v_off[p], sn.house.as<double>() + tau_off[p],
-                                sn.house.as<double>() + t_off[p], sn.size[p], int32_t(r)});
-        }
-      // the compact-WY factors are only read by the apply: they are built while the
-      // next step runs (flush_t)
-      t_pending = std::move(tds);
+        // the compact-WY factors are only read by the apply: they are built while the
+        // next step runs
+        pb.t_pending = std::move(tds);
+      }
+      if (t <= 32) hq->stats.step_m_F[t - 1] = pb.m_F;
+      pb.pending = ApplyPlan{t, std::move(pb.ed_off), std::move(pb.sc_off), std::move(pb.v_off), std::move(pb.t_off),
+                             std::move(pb.nN), std::move(pb.nref)};
+      pb.arena_prev = std::move(pb.arena);
+      pb.lay_prev = std::move(pb.lay);
     }
-    if (t <= 32) h->stats.step_m_F[t - 1] = m_F;
-
-    if (!flags_read) {
-      if ((st = flush_t()) != SPAND_OK) return st;
-      if ((st = flush_apply()) != SPAND_OK) return st;
-      if ((st = check_flags(t)) != SPAND_OK) return st;
-    }
-    pending = ApplyPlan{t, std::move(ed_off), std::move(sc_off), std::move(v_off), std::move(t_off), std::move(nN),
-                        std::move(nref)};
-
-    arena_prev = std::move(arena);
-    lay_prev = std::move(lay);
   }
-  if ((st = flush_t()) != SPAND_OK) return st;
-  if ((st = flush_apply()) != SPAND_OK) return st;
+  {
+    std::vector<TDesc> tds;
+    for (Prob& pb : P) {
+      tds.insert(tds.end(), pb.t_pending.begin(), pb.t_pending.end());
+      pb.t_pending.clear();
+    }
+    if ((st = build_t_factors(h, tds)) != SPAND_OK) return st;
+  }
+  for (Prob& pb : P) {
+    if (pb.pending.t == 0 || !pb.live) continue;
+    const int32_t pt = pb.pending.t;
+    pb.pending.t = 0;
+    if ((st = build_apply(pb.h, pb.h->an.steps[pt - 1], pb.h->num[pt - 1], pb.lay_prev, pb.pending)) != SPAND_OK)
+      return st;
+  }
   HIPCHK(hipStreamSynchronize(h->stream));
-  for (int32_t t = 1; t <= Lv; ++t) {  // phase times from the events of every step
+  double elim_ms = 0.0;
+  double phase_s[32][4] = {};
+  for (int32_t t = 1; t <= Lmax && 5 * size_t(t) <= phev.ev.size(); ++t) {  // phase times from the events of every step
     hipEvent_t ph[5];
     for (int q = 0; q < 5; ++q) ph[q] = phev.ev[5 * size_t(t - 1) + q];
     float ms[4] = {0.f, 0.f, 0.f, 0.f};
@@ -1257,25 +1409,65 @@ spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int3
     HIPCHK(hipEventElapsedTime(&ms[2], ph[2], ph[3]));
     HIPCHK(hipEventElapsedTime(&ms[3], ph[3], ph[4]));
     if (t <= 32)
-      for (int q = 0; q < 4; ++q) h->stats.step_phase_seconds[t - 1][q] = 1e-3 * ms[q];
+      for (int q = 0; q < 4; ++q) phase_s[t - 1][q] = 1e-3 * ms[q];
     if (elim_ran[t]) elim_ms += ms[1];
   }
-  arena_prev.release();
-  h->stats.m_F = m_F;
-  h->stats.s_top = s_top;
-  h->stats.schur_flops = elim_flops;
-  h->stats.schur_seconds = elim_ms * 1e-3;
-  h->stats.cpqr_flops = cpqr_flops;
-  h->stats.cpqr_seconds = cpqr_ms * 1e-3;
-  h->stats.cpqr_launches = cpqr_launches;
-  for (int q = 0; q < 4; ++q) h->stats.cpqr_interfaces[q] = cpqr_ifaces[q];
-  for (int q = 0; q < 3; ++q) h->stats.apply_interfaces[q] = 0;
-  for (const StepNum& sn : h->num) {
-    h->stats.apply_interfaces[0] += sn.n_iface1;
-    h->stats.apply_interfaces[1] += sn.n_iface2;
-    h->stats.apply_interfaces[2] += sn.n_scale;
+  for (Prob& pb : P) {
+    pb.arena_prev.release();
+    if (!pb.live) continue;
+    spand_stats& s = pb.h->stats;
+    std::memcpy(s.step_phase_seconds, phase_s, sizeof(phase_s));
+    s.m_F = pb.m_F;
+    s.s_top = pb.s_top;
+    s.schur_flops = pb.elim_flops;
+    s.schur_seconds = elim_ms * 1e-3;
+    s.cpqr_flops = pb.cpqr_flops;
+    s.cpqr_seconds = cpqr_ms * 1e-3;
+    s.cpqr_launches = cpqr_launches;
+    for (int q = 0; q < 4; ++q) s.cpqr_interfaces[q] = pb.cpqr_ifaces[q];
+    for (int q = 0; q < 3; ++q) s.apply_interfaces[q] = 0;
+    for (const StepNum& sn : pb.h->num) {
+      s.apply_interfaces[0] += sn.n_iface1;
+      s.apply_interfaces[1] += sn.n_iface2;
+      s.apply_interfaces[2] += sn.n_scale;
+    }
   }
   return SPAND_OK;
+}
+
+}  // namespace
+
+spand_status factor_numeric(spand_ctx* h, const double* values, double tol, int32_t skip, spand_prec prec) {
+  std::vector<Prob> P(1);
+  P[0].h = h;
+  P[0].values = values;
+  spand_status st = factor_run(P, tol, skip, prec);
+  if (st == SPAND_OK && !P[0].live) {
+    // the problem's own failure: its status is in the error text's class
+    st = h->stats.fail_step >= 0 ? SPAND_E_NOT_SPD : SPAND_E_INVALID;
+  }
+  return st;
+}
+
+spand_status factor_numeric_batch(spand_ctx* const* hs, const double* const* values, int32_t np, double tol,
+                                  int32_t skip, spand_prec prec, spand_status* per) {
+  std::vector<Prob> P(np);
+  for (int32_t q = 0; q < np; ++q) {
+    P[q].h = hs[q];
+    P[q].values = values[q];
+  }
+  spand_status st = factor_run(P, tol, skip, prec);
+  for (int32_t q = 0; q < np; ++q) {
+    if (st != SPAND_OK) {
+      per[q] = st;
+      if (q > 0) set_err(hs[q], st, "batched factor: " + hs[0]->err);
+    } else if (!P[q].live) {
+      per[q] = hs[q]->stats.fail_step >= 0 ? SPAND_E_NOT_SPD : SPAND_E_INVALID;
+    } else {
+      per[q] = SPAND_OK;
+    }
+  }
+  return st;
 }
 
 }  // namespace spand

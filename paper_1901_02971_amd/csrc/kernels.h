@@ -12,6 +12,7 @@ constexpr int CHOL_NB = 64;
 struct PotrfDesc {
   double* P;     // diagonal block start (column-major, ld)
   double* Dinv;  // w x w output: inverse of the diagonal block's factor, ld w
+  int32_t* fail; // on a non-positive pivot: atomicMin(fail, id) (the problem's flag word)
   int32_t ld, w, id, pad;
 };
 struct PanelDesc {
@@ -24,7 +25,7 @@ struct LeftDesc {
   const double* Dinv;  // w x w
   int32_t ldx, w, c0, c1;  // columns [c0, c1) are solved
 };
-void launch_potrf_diag(const PotrfDesc* d, int32_t count, int32_t* fail, hipStream_t s);
+void launch_potrf_diag(const PotrfDesc* d, int32_t count, hipStream_t s);
 void launch_panel_trsm(const PanelDesc* d, int32_t count, hipStream_t s);
 void launch_left_trsm_diag(const LeftDesc* d, int32_t count, hipStream_t s);
 

@@ -54,7 +54,7 @@ __device__ inline void stage_inverse(const double* __restrict__ D, int w, double
 // updates column j = t % 64 of rows t / 64, t / 64 + 4, ... (no index division);
 // then lane c of wave 0 forms column c of L^{-1} by forward substitution, entirely
 // in registers (the rows of L are broadcast from LDS).
-__global__ void __launch_bounds__(PW, 3) k_potrf_diag(const PotrfDesc* __restrict__ descs, int32_t* fail) {
+__global__ void __launch_bounds__(PW, 3) k_potrf_diag(const PotrfDesc* __restrict__ descs) {
   const PotrfDesc d = descs[blockIdx.x];
   const int w = d.w;
   __shared__ double D[CHOL_NB][CHOL_NB + 1];
@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(PW, 3) k_potrf_diag(const PotrfDesc* __restric
     const int r = i0 + 4 * s;
     if (r < w && jc < w && r >= jc) gstc(d.P + r + (int64_t)jc * d.ld, r == jc ? diag[jc] : D[r][jc]);
   }
-  if (bad && tid == 0) atomicMin(fail, d.id);
+  if (bad && tid == 0) atomicMin(d.fail, d.id);
 }
 
 // rows [r0, r1) of the panel below the diagonal block: x <- x L_kk^{-T}, computed as
@@ -223,9 +223,9 @@ __global__ void __launch_bounds__(PW) k_left_trsm_diag(const LeftDesc* __restric
   }
 }
 
-void launch_potrf_diag(const PotrfDesc* d, int32_t count, int32_t* fail, hipStream_t s) {
+void launch_potrf_diag(const PotrfDesc* d, int32_t count, hipStream_t s) {
   if (count == 0) return;
-  hipLaunchKernelGGL(k_potrf_diag, dim3(count), dim3(PW), 0, s, d, fail);
+  hipLaunchKernelGGL(k_potrf_diag, dim3(count), dim3(PW), 0, s, d);
 }
 void launch_panel_trsm(const PanelDesc* d, int32_t count, hipStream_t s) {
   if (count == 0) return;

@@ -3,9 +3,10 @@
 Problems shaped like the batched workload (variable coefficients 10^U(-2,2) on
 grids of uneven edge lengths, depth from the grid size, 16 right-hand sides), at
 sizes the oracle finishes in seconds.  Bars: every problem's result equals that of
-the same handle driven alone (bit for bit: the batch only runs handles
-concurrently on their own streams); kept ranks equal the oracle's; PCG iterations
-within +-1 of the oracle's and true relative residual <= 1e-12.
+the same handle driven alone (bit for bit: the batch shares launches between the
+problems, but no problem's arithmetic depends on another's); kept ranks equal the
+oracle's; PCG iterations within +-1 of the oracle's and true relative residual
+<= 1e-12.
 """
 import numpy as np
 import pytest
