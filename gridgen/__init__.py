@@ -159,6 +159,45 @@ def high_contrast(shape, rng: np.random.Generator, rho: float) -> GridProblem:
     return _assemble(shape, _harmonic_faces(high_contrast_field(shape, rng, rho)))
 
 
+def knn_graph_laplacian(n: int, k: int, rng: np.random.Generator, shift: float = 0.1) -> GridProblem:
+    """An irregular SPD matrix without usable geometry: the graph Laplacian of the
+    symmetric k-nearest-neighbour graph of n random points in the unit cube, plus
+    shift * I.  The points only build the edges; the returned coords are all zero,
+    so an analysis must use the graph."""
+    from scipy.spatial import cKDTree
+    pts = rng.random((n, 3))
+    _, nb = cKDTree(pts).query(pts, k + 1)
+    rows = np.repeat(np.arange(n), k)
+    cols = nb[:, 1:].ravel()
+    a = np.concatenate([rows, cols])
+    b = np.concatenate([cols, rows])
+    pairs = np.unique(np.stack([a, b], axis=1), axis=0)
+    deg = np.bincount(pairs[:, 0], minlength=n).astype(np.float64)
+    r = np.concatenate([pairs[:, 0], np.arange(n)])
+    c = np.concatenate([pairs[:, 1], np.arange(n)])
+    v = np.concatenate([-np.ones(len(pairs)), deg + shift])
+    order = np.lexsort((c, r))
+    r, c, v = r[order], c[order], v[order]
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rowptr, r + 1, 1)
+    rowptr = np.cumsum(rowptr)
+    return GridProblem(n=n, rowptr=rowptr, colind=c.astype(np.int32), values=v, coords=np.zeros((n, 3)), dim=3,
+                       shape=(n,))
+
+
+def permuted(p: GridProblem, rng: np.random.Generator) -> GridProblem:
+    """The same operator with its vertices renumbered by a random permutation (P A P^T),
+    coordinates permuted along."""
+    perm = rng.permutation(p.n)           # new vertex i is old vertex perm[i]
+    inv = np.empty(p.n, dtype=np.int64)
+    inv[perm] = np.arange(p.n)
+    A = p.scipy().tocsr()[perm][:, perm].tocsr()
+    A.sort_indices()
+    return GridProblem(n=p.n, rowptr=A.indptr.astype(np.int64), colind=A.indices.astype(np.int32),
+                       values=A.data.astype(np.float64), coords=np.ascontiguousarray(p.coords[perm]), dim=p.dim,
+                       shape=p.shape)
+
+
 def rhs(rng: np.random.Generator, n: int, nrhs: int) -> np.ndarray:
     """Right-hand sides b ~ N(0,1), returned column-major as an (n, nrhs) Fortran array."""
     return np.asfortranarray(rng.standard_normal((nrhs, n)).T)

@@ -120,12 +120,17 @@ typedef struct {
   int32_t reserved[5];
 } spand_tuning;
 
-/* Ordering, clustering and symbolic factorization (Algorithm 2 with a geometric
- * vertex separator, Sec. 2.3; cluster hierarchy, Sec. 2.7; fill pattern, Sec. 2.4).
+/* Ordering, clustering and symbolic factorization (Algorithm 2, Sec. 2.3, with a
+ * geometric vertex separator, or a graph one when no coordinates are given;
+ * cluster hierarchy, Sec. 2.7; fill pattern, Sec. 2.4).
  *   n        matrix dimension (>= 1)
  *   rowptr   host, n+1 entries, rowptr[0] = 0
  *   colind   host, rowptr[n] entries, sorted per row, pattern symmetric, diagonal present
- *   dim      2 or 3; coords host, n*dim doubles, row-major (x, y[, z]) per vertex
+ *   dim      2 or 3: coords host, n*dim doubles, row-major (x, y[, z]) per vertex, and
+ *            the separator cuts the widest coordinate axis at its lower median;
+ *            0: coords must be NULL, and the separator is a breadth-first level
+ *            structure of the graph from a pseudo-peripheral root (George-Liu), cut at
+ *            the lower median level
  *   levels   ND tree depth L >= 1 (2^(L-1) leaves)
  *   out      receives the new handle (NULL on failure)
  * Host-only: touches no GPU.  Errors: SPAND_E_INVALID, SPAND_E_NOMEM. */

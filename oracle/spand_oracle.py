@@ -10,7 +10,9 @@ blocking, fusion or reordering beyond what the paper's algorithms state.
 
 Contents, each following the cited passage:
   * ``nd_order``      Algorithm 2 (modified ND ordering and clustering, Sec. 2.3)
-                      with the geometric vertex separator of Sec. 2.3 / 4.1.1.
+                      with the geometric vertex separator of Sec. 2.3 / 4.1.1, or a
+                      breadth-first level-structure separator for graphs without
+                      coordinates.
   * ``symbolic``      the cluster hierarchy of each separator (Sec. 2.3, 2.7) and the
                       block pattern of the trailing matrix with the fill of Sec. 2.4.
   * ``factor``        Algorithm 3 (OrthS): elimination (Sec. 2.4), block scaling
@@ -115,13 +117,92 @@ def rcb_separator(U, coords, rowptr, colind, n):
     return F[~touches], F[touches], U[~first]
 
 
+def _bfs_levels(root, inU, rowptr, colind):
+    """Breadth-first distances from root inside the vertex set inU (a boolean mask):
+    dict vertex -> level."""
+    lev = {int(root): 0}
+    frontier = [int(root)]
+    d = 0
+    while frontier:
+        d += 1
+        nxt = []
+        for v in frontier:
+            for u in colind[rowptr[v]:rowptr[v + 1]]:
+                u = int(u)
+                if inU[u] and u not in lev:
+                    lev[u] = d
+                    nxt.append(u)
+        frontier = nxt
+    return lev
+
+
+def graph_separator(U, rowptr, colind, n):
+    """Vertex separator of U from the graph alone, for inputs without coordinates
+    (the paper's Algorithm 2 takes any separator; Sec. 2.3 names a graph partitioner
+    as the alternative to the geometric one).  A level structure replaces the
+    coordinate of the geometric separator:
+
+    * the components of the graph restricted to U are taken in the order of their
+      smallest vertex id; in each, a pseudo-peripheral root is found by the
+      George-Liu iteration (start at the smallest id; move to the vertex of the
+      last breadth-first level with the smallest degree inside U, ties to the
+      smallest id, while that increases the eccentricity), and its breadth-first
+      levels, shifted past the levels of the earlier components, are the
+      vertices' keys;
+    * the split is the threshold split of the geometric separator on these keys:
+      m = the key at sorted position floor((|U|-1)/2), first part {key <= m} (or
+      {key < m} if that is all of U), separator = first-part vertices with an edge
+      inside U to the second part.  Returns (left, middle, right).
+    """
+    U = np.asarray(U, dtype=np.int64)
+    inU = np.zeros(n, dtype=bool)
+    inU[U] = True
+    deg = {}
+    for v in U.tolist():
+        nb = colind[rowptr[v]:rowptr[v + 1]]
+        deg[v] = int(np.sum(inU[nb] & (nb != v)))
+    key = {}
+    offset = 0
+    for start in sorted(U.tolist()):
+        if start in key:
+            continue
+        root = start
+        lev = _bfs_levels(root, inU, rowptr, colind)
+        ecc = max(lev.values())
+        while True:
+            last = [v for v, d in lev.items() if d == ecc]
+            x = min(last, key=lambda v: (deg[v], v))
+            lx = _bfs_levels(x, inU, rowptr, colind)
+            ex = max(lx.values())
+            if ex > ecc:
+                root, lev, ecc = x, lx, ex
+            else:
+                break
+        for v, d in lev.items():
+            key[v] = offset + d
+        offset += ecc + 1
+    c = np.array([key[v] for v in U.tolist()], dtype=np.int64)
+    h = (len(U) - 1) // 2
+    m = np.sort(c, kind="stable")[h]
+    first = c <= m
+    if first.all():
+        first = c < m
+    in_second = np.zeros(n, dtype=bool)
+    in_second[U[~first]] = True
+    F = U[first]
+    touches = np.array([bool(np.any(in_second[colind[rowptr[v]:rowptr[v + 1]]])) for v in F.tolist()], dtype=bool)
+    return F[~touches], F[touches], U[~first]
+
+
 def nd_order(n, rowptr, colind, coords, levels):
     """Algorithm 2: per-vertex (S, L, R) separator ids for an ND tree of depth ``levels``.
 
     The root is level 1 and leaves are level ``levels``; levels-1 dissections are
     made.  Boxes of one level are processed in increasing k (their updates never
     touch the same field of a vertex, so the order does not change the result).
-    Vertices of the middle set that lie on the boundary keep their pointers.
+    Vertices of the middle set that lie on the boundary keep their pointers.  With
+    coords None the separator is the graph one (``graph_separator``), else the
+    geometric one (``rcb_separator``).
     """
     rowptr = np.asarray(rowptr, dtype=np.int64)
     colind = np.asarray(colind, dtype=np.int64)
@@ -136,7 +217,10 @@ def nd_order(n, rowptr, colind, coords, levels):
             U = np.union1d(I, B)
             if len(U) == 0:
                 continue
-            left, mid, right = rcb_separator(U, coords, rowptr, colind, n)
+            if coords is None:
+                left, mid, right = graph_separator(U, rowptr, colind, n)
+            else:
+                left, mid, right = rcb_separator(U, coords, rowptr, colind, n)
             inI = np.zeros(n, dtype=bool)
             inI[I] = True
             a, b = pack(l + 1, 2 * k - 1), pack(l + 1, 2 * k)
@@ -392,7 +476,7 @@ class Analysis:
         self.n = n
         self.rowptr = np.asarray(rowptr, dtype=np.int64)
         self.colind = np.asarray(colind, dtype=np.int64)
-        self.coords = np.asarray(coords, dtype=np.float64).reshape(n, -1)
+        self.coords = None if coords is None else np.asarray(coords, dtype=np.float64).reshape(n, -1)
         self.levels = levels
         self.skip = skip
         self.S, self.L, self.R = nd_order(n, self.rowptr, self.colind, self.coords, levels)

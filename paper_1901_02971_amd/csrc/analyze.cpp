@@ -1,10 +1,12 @@
 // Host-side analysis: Algorithm 2 (modified nested dissection ordering and
-// clustering, Sec. 2.3) with a recursive-coordinate-bisection vertex separator,
+// clustering, Sec. 2.3) with a recursive-coordinate-bisection vertex separator (or,
+// without coordinates, a breadth-first level-structure separator),
 // the cluster hierarchy of every separator (Sec. 2.3, 2.7) and the structural
 // block pattern of the trailing matrix with the fill of block elimination
 // (Sec. 2.4).  Integer work only; never touches the GPU.
 #include <algorithm>
 #include <cmath>
+#include <memory>
 #include <numeric>
 
 #include "spand_internal.h"
@@ -63,6 +65,121 @@ void rcb_split(const Analysis& an, const std::vector<int32_t>& U, std::vector<in
   }
 }
 
+// Per-vertex scratch of the graph separator, stamped so that nothing is cleared
+// between calls.
+struct GraphScratch {
+  std::vector<int32_t> in_u;   // == u_stamp: v is in the current U
+  std::vector<int32_t> seen;   // == seen_stamp: v reached by the current breadth-first search
+  std::vector<int32_t> dist;   // its level in that search
+  std::vector<int64_t> key;    // final level key of v in U
+  std::vector<int32_t> deg;    // degree of v inside U
+  int32_t u_stamp = 0, seen_stamp = 0;
+  explicit GraphScratch(int64_t n) : in_u(n, -1), seen(n, -1), dist(n, 0), key(n, -1), deg(n, 0) {}
+};
+
+// Breadth-first search from root inside U; `order` receives the vertices reached in
+// search order (so by level), dist their levels.  Returns the eccentricity.
+int32_t bfs_in_u(const Analysis& an, GraphScratch& g, int32_t root, std::vector<int32_t>& order) {
+  ++g.seen_stamp;
+  order.clear();
+  order.push_back(root);
+  g.seen[root] = g.seen_stamp;
+  g.dist[root] = 0;
+  int32_t ecc = 0;
+  for (size_t h = 0; h < order.size(); ++h) {
+    const int32_t v = order[h];
+    for (int64_t e = an.rowptr[v]; e < an.rowptr[v + 1]; ++e) {
+      const int32_t u = an.colind[e];
+      if (g.in_u[u] != g.u_stamp || g.seen[u] == g.seen_stamp) continue;
+      g.seen[u] = g.seen_stamp;
+      g.dist[u] = g.dist[v] + 1;
+      ecc = std::max(ecc, g.dist[u]);
+      order.push_back(u);
+    }
+  }
+  return ecc;
+}
+
+// Vertex separator of U from the graph alone, for inputs without coordinates: a
+// breadth-first level structure gives every vertex a key, and the threshold split of
+// the geometric separator is taken on the keys.  The components of the graph inside
+// U are taken in the order of their smallest vertex id; each gets a pseudo-peripheral
+// root by the George-Liu iteration (start at the smallest id; go to the last-level
+// vertex of smallest degree inside U, ties to the smallest id, while that raises the
+// eccentricity), and its levels from that root, shifted past the keys of the earlier
+// components.  Then m = the key at sorted position floor((|U|-1)/2), first part
+// {key <= m} (or {key < m} when that is all of U), middle = first-part vertices
+// adjacent (inside U) to the second part.  side[q] as in rcb_split.
+void graph_split(const Analysis& an, const std::vector<int32_t>& U, std::vector<int32_t>& mark, int32_t stamp,
+                 std::vector<uint8_t>& side, GraphScratch& g) {
+  ++g.u_stamp;
+  for (int32_t v : U) g.in_u[v] = g.u_stamp;
+  for (int32_t v : U) {
+    int32_t d = 0;
+    for (int64_t e = an.rowptr[v]; e < an.rowptr[v + 1]; ++e) {
+      const int32_t u = an.colind[e];
+      if (u != v && g.in_u[u] == g.u_stamp) ++d;
+    }
+    g.deg[v] = d;
+    g.key[v] = -1;
+  }
+  std::vector<int32_t> byid(U);
+  std::sort(byid.begin(), byid.end());
+  std::vector<int32_t> order, trial;
+  int64_t offset = 0;
+  for (int32_t start : byid) {
+    if (g.key[start] >= 0) continue;
+    int32_t ecc = bfs_in_u(an, g, start, order);
+    for (;;) {
+      int32_t x = -1;
+      for (size_t h = order.size(); h-- > 0;) {  // the last level is at the end of the search order
+        const int32_t v = order[h];
+        if (g.dist[v] != ecc) break;
+        if (x < 0 || g.deg[v] < g.deg[x] || (g.deg[v] == g.deg[x] && v < x)) x = v;
+      }
+      const int32_t ex = bfs_in_u(an, g, x, trial);
+      if (ex > ecc) {
+        ecc = ex;
+        order.swap(trial);
+      } else {
+        // the accepted search is `order`, whose levels were overwritten by the trial:
+        // search again from its root (order[0]) to restore them
+        const int32_t root = order[0];
+        ecc = bfs_in_u(an, g, root, order);
+        break;
+      }
+    }
+    for (int32_t v : order) g.key[v] = offset + g.dist[v];
+    offset += int64_t(ecc) + 1;
+  }
+  std::vector<int64_t> c(U.size());
+  for (size_t q = 0; q < U.size(); ++q) c[q] = g.key[U[q]];
+  std::vector<int64_t> tmp(c);
+  const size_t h = (U.size() - 1) / 2;
+  std::nth_element(tmp.begin(), tmp.begin() + h, tmp.end());
+  const int64_t m = tmp[h];
+  bool all_first = true;
+  for (int64_t x : c)
+    if (!(x <= m)) {
+      all_first = false;
+      break;
+    }
+  for (size_t q = 0; q < U.size(); ++q) {
+    const bool first = all_first ? (c[q] < m) : (c[q] <= m);
+    side[q] = first ? 0 : 2;
+    if (!first) mark[U[q]] = stamp;
+  }
+  for (size_t q = 0; q < U.size(); ++q) {
+    if (side[q] != 0) continue;
+    const int32_t v = U[q];
+    for (int64_t e = an.rowptr[v]; e < an.rowptr[v + 1]; ++e)
+      if (mark[an.colind[e]] == stamp) {
+        side[q] = 1;
+        break;
+      }
+  }
+}
+
 // Algorithm 2: fills S, L, R.
 void order_and_cluster(Analysis& an) {
   const int64_t n = an.n;
@@ -71,6 +188,8 @@ void order_and_cluster(Analysis& an) {
   an.R.assign(n, 0);
   std::vector<int32_t> mark(n, -1);
   int32_t stamp = 0;
+  std::unique_ptr<GraphScratch> gs;
+  if (an.dim == 0) gs.reset(new GraphScratch(n));
   for (int32_t l = 1; l < an.levels; ++l) {
     const int64_t nbox = int64_t(1) << (l - 1);
     // Bucket interiors (S at level l) and boundaries (L or R at level l) by box.
@@ -105,7 +224,10 @@ void order_and_cluster(Analysis& an) {
       U.assign(ilist.begin() + iptr[k], ilist.begin() + iptr[k + 1]);
       U.insert(U.end(), blist.begin() + bptr[k], blist.begin() + bptr[k + 1]);
       side.assign(U.size(), 0);
-      rcb_split(an, U, mark, stamp++, side);
+      if (gs)
+        graph_split(an, U, mark, stamp++, side, *gs);
+      else
+        rcb_split(an, U, mark, stamp++, side);
       const int64_t a = sep_pack(l + 1, 2 * k - 1), b = sep_pack(l + 1, 2 * k);
       for (size_t q = 0; q < U.size(); ++q) {
         const int32_t v = U[q];

@@ -158,8 +158,10 @@ spand_status spand_analyze(int64_t n, const int64_t* rowptr, const int32_t* coli
   if (!out) return fail_null(SPAND_E_INVALID, "out is NULL");
   *out = nullptr;
   if (n < 1 || n > INT32_MAX - 1) return fail_null(SPAND_E_INVALID, "n must be in [1, 2^31-2]");
-  if (!rowptr || !colind || !coords) return fail_null(SPAND_E_INVALID, "NULL input array");
-  if (dim != 2 && dim != 3) return fail_null(SPAND_E_INVALID, "dim must be 2 or 3");
+  if (!rowptr || !colind) return fail_null(SPAND_E_INVALID, "NULL input array");
+  if (dim == 0 && coords) return fail_null(SPAND_E_INVALID, "dim = 0 (graph separator) takes no coordinates");
+  if (dim != 0 && dim != 2 && dim != 3) return fail_null(SPAND_E_INVALID, "dim must be 0, 2 or 3");
+  if (dim != 0 && !coords) return fail_null(SPAND_E_INVALID, "coords is NULL");
   if (levels < 1 || levels > 30) return fail_null(SPAND_E_INVALID, "levels must be in [1, 30]");
   const double t0 = now();
   std::string msg = check_pattern(n, rowptr, colind);
@@ -174,7 +176,7 @@ spand_status spand_analyze(int64_t n, const int64_t* rowptr, const int32_t* coli
     h->an.dim = dim;
     h->an.rowptr.assign(rowptr, rowptr + n + 1);
     h->an.colind.assign(colind, colind + rowptr[n]);
-    h->an.coords.assign(coords, coords + n * dim);
+    if (dim) h->an.coords.assign(coords, coords + n * dim);
     msg = spand::analyze_pattern(h->an);
   } catch (const std::bad_alloc&) {
     delete h;

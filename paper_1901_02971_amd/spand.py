@@ -163,8 +163,11 @@ class Solver:
         self._lib = lib
         rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
         colind = np.ascontiguousarray(colind, dtype=np.int32)
-        coords = np.ascontiguousarray(coords, dtype=np.float64)
-        dim = coords.shape[1] if coords.ndim == 2 else 1
+        if coords is None:   # graph separator: no geometry
+            dim = 0
+        else:
+            coords = np.ascontiguousarray(coords, dtype=np.float64)
+            dim = coords.shape[1] if coords.ndim == 2 else 1
         self.n = int(n)
         self.levels = int(levels)
         h = C.c_void_p()
@@ -181,8 +184,9 @@ class Solver:
         self.close()
 
     @classmethod
-    def from_problem(cls, problem, levels):
-        return cls(problem.n, problem.rowptr, problem.colind, problem.coords, levels)
+    def from_problem(cls, problem, levels, geometry=True):
+        """geometry=False analyzes the graph alone (level-structure separator)."""
+        return cls(problem.n, problem.rowptr, problem.colind, problem.coords if geometry else None, levels)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -26,9 +26,9 @@ def from_dev(t):
     return t.cpu().numpy().T.copy()
 
 
-def gpu_factor(p, levels, tol, skip=0, prec=0):
+def gpu_factor(p, levels, tol, skip=0, prec=0, geometry=True):
     import torch
-    s = Solver.from_problem(p, levels)
+    s = Solver.from_problem(p, levels, geometry)
     vals = torch.from_numpy(p.values).to("cuda:0")
     s.factor(vals, tol, skip, prec)
     return s
@@ -50,8 +50,8 @@ def gpu_apply(s, r):
     return from_dev(zt)
 
 
-def oracle_run(p, levels, tol, skip=0):
-    an = O.Analysis(p.n, p.rowptr, p.colind, p.coords, levels, skip)
+def oracle_run(p, levels, tol, skip=0, geometry=True):
+    an = O.Analysis(p.n, p.rowptr, p.colind, p.coords if geometry else None, levels, skip)
     fac = O.factor(an, p.values, tol)
     return an, fac
 

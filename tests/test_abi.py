@@ -54,6 +54,34 @@ def test_stats_struct_matches_header(tmp_path, cname, mirror):
         assert getattr(M, f).offset == off, f
 
 
+def _graph_problems():
+    return [("grid2d", gridgen.laplacian((33, 20)), 6),
+            ("grid3d", gridgen.laplacian((12, 10, 9)), 6),
+            ("permuted3d", gridgen.permuted(gridgen.laplacian((10, 11, 12)), np.random.default_rng(5)), 6),
+            ("knn", gridgen.knn_graph_laplacian(2000, 7, np.random.default_rng(6)), 7)]
+
+
+@pytest.mark.parametrize("name,p,levels", _graph_problems(), ids=[c[0] for c in _graph_problems()])
+def test_graph_separator_analyze_bit_exact_vs_oracle(name, p, levels):
+    """Without coordinates (dim = 0) the library's level-structure separator, cluster
+    keys, block patterns and colouring equal the oracle's bit for bit."""
+    lib = S.Solver.from_problem(p, levels, geometry=False)
+    an = O.Analysis(p.n, p.rowptr, p.colind, None, levels)
+    Sg, Lg, Rg = lib.ordering()
+    assert np.array_equal(Sg, an.S) and np.array_equal(Lg, an.L) and np.array_equal(Rg, an.R)
+    for t, st in enumerate(an.steps, start=1):
+        g = lib.step_structure(t)
+        assert np.array_equal(g["keys"], st.keys)
+        assert np.array_equal(g["colour"], st.colour)
+        assert [tuple(x) for x in g["after"]] == [tuple(x) for x in st.after]
+
+
+def test_graph_separator_argument_checks():
+    p = gridgen.laplacian((5, 5))
+    with pytest.raises(S.SpandError):
+        S.Solver(p.n, p.rowptr, p.colind, np.zeros((p.n, 0)), 3)   # dim 0 array is not NULL
+
+
 CASES = [((7, 7), 3), ((6, 4), 2), ((16, 16), 5), ((64, 64), 6), ((9, 7, 6), 4), ((8, 8, 8), 5),
          ((24, 31, 40), 7), ((32, 32, 32), 9), ((5, 5, 5), 1), ((3, 2), 4)]
 

@@ -267,6 +267,32 @@ def test_cholesky_group_tuning_keeps_parity(group):
     assert np.abs(z - zr).max() <= 1e-10 * np.abs(zr).max()
 
 
+GRAPH = [
+    ("permuted_grid_16x14x12", lambda: gridgen.permuted(gridgen.laplacian((16, 14, 12)), np.random.default_rng(7)), 6),
+    ("knn_graph_2500", lambda: gridgen.knn_graph_laplacian(2500, 6, np.random.default_rng(8)), 6),
+    ("var3d_16x15x14", lambda: gridgen.variable_coefficient((16, 15, 14), np.random.default_rng(9), -3, 3), 6),
+]
+
+
+@pytest.mark.parametrize("name,make,levels", GRAPH, ids=[c[0] for c in GRAPH])
+def test_graph_separator_parity(name, make, levels):
+    """Matrices analyzed from the graph alone (no coordinates): ranks identical to the
+    oracle's, the apply within 1e-10 of it, iterations within +-1, relres <= 1e-12."""
+    p = make()
+    b = gridgen.rhs(np.random.default_rng(50), p.n, 3)
+    an, fac = oracle_run(p, levels, 1e-2, geometry=False)
+    s = gpu_factor(p, levels, 1e-2, geometry=False)
+    assert rank_mismatches(s, an, fac) == 0
+    assert s.stats()["s_top"] == fac.stats["s_top"] and s.stats()["m_F"] == fac.stats["m_F"]
+    z = gpu_apply(s, b)
+    zr = O.apply(fac, b)
+    assert np.abs(z - zr).max() <= 1e-10 * np.abs(zr).max()
+    x, it, rr, _ = gpu_solve(s, b)
+    _, it_ref, _ = O.pcg(p.scipy(), b, lambda r: O.apply(fac, r))
+    note(f"{name}: iters {it} oracle {it_ref}")
+    assert np.all(np.abs(it - it_ref) <= 1) and np.all(rr <= 1e-12)
+
+
 # ------------------------------------------------------------------ Schur-product precisions
 @pytest.mark.parametrize("prec,bound", [(1, 1e-5), (2, 1e-4)], ids=["fp32", "bf16x3"])
 def test_exact_factorization_reduced_precision(prec, bound):

@@ -66,6 +66,60 @@ def test_alg2_hand_stepped_3d(fname, shape, levels):
             assert (S[v], L[v], R[v]) == (_code(s), _code(l), _code(r)), (x, y, z)
 
 
+def test_alg2_graph_separator_hand_stepped():
+    """Algorithm 2 with the breadth-first level-structure separator (no coordinates)
+    on the 4x4 grid at 3 levels against a hand-stepped run."""
+    rows = [ln.split(":")[1].split() for ln in open(os.path.join(GOLDEN, "nd_graph_4x4_L3.txt"))
+            if ln.startswith("y")]
+    p = gridgen.laplacian((4, 4))
+    S, L, R = O.nd_order(p.n, p.rowptr, p.colind, None, 3)
+    for y, row in enumerate(rows):
+        for x, ent in enumerate(row):
+            s, l, r = ent.split("/")
+            v = x + 4 * y
+            assert (S[v], L[v], R[v]) == (_code(s), _code(l), _code(r)), (x, y)
+
+
+def _graph_cases():
+    two = gridgen.laplacian((5, 4))
+    # two disconnected copies of a small grid (block diagonal)
+    import scipy.sparse as sp
+    A = sp.block_diag([two.scipy(), 2.0 * two.scipy()]).tocsr()
+    A.sort_indices()
+    disc = gridgen.GridProblem(n=A.shape[0], rowptr=A.indptr.astype(np.int64), colind=A.indices.astype(np.int32),
+                               values=A.data, coords=np.zeros((A.shape[0], 2)), dim=2, shape=(A.shape[0],))
+    return [("grid2d", gridgen.laplacian((16, 16)), 5),
+            ("grid3d", gridgen.laplacian((9, 7, 6)), 4),
+            ("permuted3d", gridgen.permuted(gridgen.laplacian((8, 9, 10)), np.random.default_rng(3)), 5),
+            ("knn", gridgen.knn_graph_laplacian(600, 6, np.random.default_rng(4)), 5),
+            ("disconnected", disc, 4)]
+
+
+@pytest.mark.parametrize("name,p,levels", _graph_cases(), ids=[c[0] for c in _graph_cases()])
+def test_graph_separator_invariants(name, p, levels):
+    """Without coordinates: every edge joins equal S or an ancestor/descendant pair
+    (the middle set separates), each separator is one cluster at its step, and the
+    factorization stays exact at eps = 0."""
+    S, L, R = O.nd_order(p.n, p.rowptr, p.colind, None, levels)
+    rows = np.repeat(np.arange(p.n), np.diff(p.rowptr))
+    a, b = S[rows], S[p.colind]
+    la, lb = O.lev_of(a), O.lev_of(b)
+    deep = np.where(la >= lb, a, b)
+    shallow = np.where(la >= lb, b, a)
+    assert np.all(O.truncate(deep, np.minimum(la, lb)) == shallow)
+    an = O.Analysis(p.n, p.rowptr, p.colind, None, levels)
+    for st in an.steps:
+        ids = st.keys[: st.n_elim, 0]
+        assert len(np.unique(ids)) == st.n_elim
+    if p.n <= 700:
+        A = p.scipy().toarray()
+        bb = np.random.default_rng(1).standard_normal((p.n, 2))
+        fac = O.factor(an, p.values, 0.0)
+        z = O.apply(fac, bb)
+        x_ref = sla.cho_solve(sla.cho_factor(A), bb)
+        assert np.abs(z - x_ref).max() <= 1e-10 * np.abs(x_ref).max()
+
+
 @pytest.mark.parametrize("shape,levels", [((7, 7), 3), ((16, 16), 5), ((9, 7, 6), 4), ((8, 8, 8), 5)])
 def test_alg2_invariants(shape, levels):
     """ND invariants: an edge never joins two different separators unless one is an
