@@ -101,6 +101,10 @@ typedef struct {
   /* Residual replacements in the last solve: columns whose recursive residual met
    * rtol while the true residual did not, and which went on from the true one. */
   int64_t pcg_replacements;
+  /* Interfaces of the last factor whose CPQR ran in the global-memory kernel for
+   * interfaces beyond the register layouts (more than 2048 rows, more columns than
+   * the co-resident slabs hold, or at least tuning.cpqr_big_min rows). */
+  int64_t cpqr_big_interfaces;
 } spand_stats;
 
 /* Kernel-shape and path parameters of a handle.  None of them changes what is
@@ -112,12 +116,16 @@ typedef struct {
  *                 dofs when a step has at least this many of them (default 256;
  *                 0 = always, -1 = never)
  *   gemm_variant  output tile of the batched matrix-core GEMM (see spand_autotune)
+ *   cpqr_big_min  interfaces of at least this many dofs take the global-memory CPQR
+ *                 kernel, which is otherwise kept for interfaces beyond the register
+ *                 layouts (0 = only those; default 0)
  */
 typedef struct {
   int32_t chol_group;
   int32_t fuse128_min;
   int32_t gemm_variant;
-  int32_t reserved[5];
+  int32_t cpqr_big_min;
+  int32_t reserved[4];
 } spand_tuning;
 
 /* Ordering, clustering and symbolic factorization (Algorithm 2, Sec. 2.3, with a

@@ -510,7 +510,8 @@ struct Prob {
   int64_t cbase = 0;            // first entry of this problem's clusters in the run's size and rank arrays
   std::vector<int64_t> c_off, ed_off, sc_off, sd_off, v_off, tau_off, t_off, xch_off, ncols;
   std::vector<int32_t> nN, nref, slabS, tg, nseg, rlay;
-  std::vector<char> wide;
+  std::vector<char> wide, big;
+  int64_t cpqr_big = 0;         // interfaces of the global-memory CPQR kernel
   DevBuf cbuf;
 };
 
@@ -1034,6 +1035,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
         pb.nseg.assign(nc, 0);
         pb.wide.assign(nc, 0);
         pb.rlay.assign(nc, 0);
+        pb.big.assign(nc, 0);
         int64_t house_total = 0;
         for (int32_t p = ne; p < nc; ++p) {
           for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e)
@@ -1045,9 +1047,24 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
           ncolour = std::max(ncolour, sy.colour[p] + 1);
           const int64_t m = sn.size[p];
           const int32_t G = cpqr_team(sn.size[p]);
-          if (G < 0)
-            return set_err(h, SPAND_E_INVALID, "interface of " + std::to_string(m) +
-                                                   " dofs exceeds the largest CPQR team (2048 rows)");
+          // beyond the register layouts (or asked for by the tuning): the global-memory
+          // kernel, one cooperative launch per interface
+          bool big = G < 0 || (h->tune.cpqr_big_min > 0 && m >= h->tune.cpqr_big_min);
+          if (!big) {
+            const int64_t cap = cpqr_capacity(G);
+            const int64_t S0 = (pb.ncols[p] + cap - 1) / cap;
+            if (S0 > 1 && S0 > cpqr_max_coresident(cpqr_lds_bytes(G, 0, pb.nseg[p]))) {
+              const int32_t G1 = cpqr_team(sn.size[p], 1);
+              const int64_t S1 = G1 > 0 ? (pb.ncols[p] + cpqr_capacity(G1, 1) - 1) / cpqr_capacity(G1, 1) : S0;
+              if (S1 > cpqr_max_coresident(cpqr_lds_bytes(G1 > 0 ? G1 : G, G1 > 0 ? 1 : 0, pb.nseg[p]))) big = true;
+            }
+          }
+          if (big) {
+            if (m > cpqr_big_max_rows())
+              return set_err(h, SPAND_E_INVALID, "interface of " + std::to_string(m) + " dofs exceeds the CPQR limit (" +
+                                                     std::to_string(cpqr_big_max_rows()) + " rows)");
+            pb.big[p] = 1;
+          } else {
           pb.tg[p] = G;
           const int64_t cap = cpqr_capacity(G);
           pb.slabS[p] = int32_t((pb.ncols[p] + cap - 1) / cap);
@@ -1069,6 +1086,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
             pb.xch_off[p] = xch_total;
             xch_total += 3 * int64_t(pb.slabS[p]) * cpqr_record(pb.tg[p], pb.rlay[p]);  // three exchange buffers
           }
+          }
           const int64_t kmax = std::min<int64_t>(sn.size[p], pb.ncols[p]);
           pb.v_off[p] = house_total;
           house_total += int64_t(sn.size[p]) * kmax;
@@ -1079,7 +1097,10 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
         }
         if ((st = dalloc(hq, sn.house, size_t(house_total) * sizeof(double))) != SPAND_OK) return st;
         for (int32_t p = ne; p < nc; ++p)
-          if (pb.v_off[p] >= 0) ++pb.cpqr_ifaces[pb.slabS[p] > 1 ? 2 + pb.rlay[p] : (pb.wide[p] ? 1 : 0)];
+          if (pb.v_off[p] >= 0 && !pb.big[p])
+            ++pb.cpqr_ifaces[pb.slabS[p] > 1 ? 2 + pb.rlay[p] : (pb.wide[p] ? 1 : 0)];
+          else if (pb.v_off[p] >= 0)
+            ++pb.cpqr_big;
       }
       if ((st = dalloc(h, xchb, size_t(xch_total) * sizeof(double))) != SPAND_OK) return st;
       // the exchange headers start with tag 0; the first exchange of a buffer uses tag 1
@@ -1101,8 +1122,10 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
         bool multi;
         int32_t G, nslab, nround;
         size_t lds, d0, s0;
+        int32_t big_nseg = -1;  // >= 0: one global-memory launch of descriptor d0 with nslab workgroups
       };
       std::vector<CpqrLaunch> launches;
+      int64_t big_m = 0, big_mn = 0, big_nc = 0;
       std::vector<SparsDesc> all_sds;
       std::vector<SegDesc> all_segs;
       std::vector<SlabRef> all_slabs;
@@ -1117,6 +1140,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
           for (const Ref& f : by_colour[c]) {
             const Prob& pb = *f.pb;
             const int32_t p = f.p;
+            if (pb.big[p]) continue;
             if (multi ? pb.slabS[p] > 1
                       : wgrp ? pb.wide[p] != 0 : (pb.slabS[p] == 1 && !pb.wide[p] && pb.tg[p] == grp))
               plist.push_back(f);
@@ -1256,6 +1280,65 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
             launches.push_back(Lc);
           }
         }
+        // the interfaces of this colour beyond the register layouts, one launch each
+        for (const Ref& f : by_colour[c]) {
+          const Prob& pb = *f.pb;
+          const int32_t p = f.p;
+          if (!pb.big[p]) continue;
+          const StepNum& sn = pb.h->num[t - 1];
+          const SymStep& sy = pb.h->an.steps[t - 1];
+          const Layout& lay = pb.lay;
+          double* A = pb.arena.as<double>();
+          SparsDesc d{};
+          d.V = sn.house.as<double>() + pb.v_off[p];
+          d.tau = sn.house.as<double>() + pb.tau_off[p];
+          d.diag = A + lay.base[p];
+          d.ldd = int32_t(lay.H[p]);
+          d.m = sn.size[p];
+          d.id = int32_t(pb.cbase + p);
+          d.S = 1;
+          d.seg_begin = int32_t(all_segs.size());
+          for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e) {
+            const int32_t q = sy.nb[e];
+            if (sn.size[q] == 0) continue;
+            SegDesc g{};
+            if (q < p) {
+              g.blk = A + lay.base[q] + lay.find(p, q);
+              g.ld = int32_t(lay.H[q]);
+              g.trans = 0;
+            } else {
+              g.blk = A + lay.base[p] + lay.find(q, p);
+              g.ld = int32_t(lay.H[p]);
+              g.trans = 1;
+            }
+            g.q = int32_t(pb.cbase + q);
+            all_segs.push_back(g);
+          }
+          d.seg_end = int32_t(all_segs.size());
+          const int capb = cpqr_big_max_coresident(pb.nseg[p]);
+          if (capb <= 0) return set_err(h, SPAND_E_HIP, "occupancy query for the large-interface CPQR failed");
+          CpqrLaunch Lb{};
+          Lb.multi = false;
+          Lb.big_nseg = pb.nseg[p];
+          Lb.d0 = all_sds.size();
+          Lb.nslab = int32_t(std::max<int64_t>(1, std::min<int64_t>(capb, (pb.ncols[p] + 15) / 16)));
+          all_sds.push_back(d);
+          launches.push_back(Lb);
+          big_m = std::max<int64_t>(big_m, sn.size[p]);
+          big_mn = std::max<int64_t>(big_mn, int64_t(sn.size[p]) * pb.ncols[p]);
+          big_nc = std::max<int64_t>(big_nc, pb.ncols[p]);
+        }
+      }
+      // scratch of the large-interface launches (they run one after another on the stream)
+      DevBuf bwk, bnrm, bpst, brb, bpost, bpcd, bbar;
+      if (big_m > 0) {
+        if ((st = dalloc(h, bwk, size_t(big_mn) * sizeof(double))) != SPAND_OK) return st;
+        if ((st = dalloc(h, bnrm, size_t(big_nc) * sizeof(double))) != SPAND_OK) return st;
+        if ((st = dalloc(h, bpst, size_t(big_nc) * sizeof(int32_t))) != SPAND_OK) return st;
+        if ((st = dalloc(h, brb, size_t(std::min(big_m, big_nc)) * sizeof(double))) != SPAND_OK) return st;
+        if ((st = dalloc(h, bpost, 1024 * sizeof(double))) != SPAND_OK) return st;
+        if ((st = dalloc(h, bpcd, 1024 * sizeof(int32_t))) != SPAND_OK) return st;
+        if ((st = dalloc(h, bbar, 256)) != SPAND_OK) return st;
       }
       // every launch of the step is planned: one upload, then the launches back to back
       DevBuf a, b, sl;
@@ -1269,6 +1352,18 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
         HIPCHK(hipEventRecord(e0, h->stream));
         const SparsDesc* dd = a.as<SparsDesc>() + Lc.d0;
         const SlabRef* ss = sl.as<SlabRef>() + Lc.s0;
+        if (Lc.big_nseg >= 0) {
+          HIPCHK(hipMemsetAsync(bbar.p, 0, 256, h->stream));
+          hipError_t le = launch_cpqr_big(all_sds[Lc.d0], Lc.big_nseg, b.as<SegDesc>(), tol, curb.as<int32_t>(),
+                                          nrefb.as<int32_t>(), errb.as<int32_t>(), Lc.nslab, bwk.as<double>(),
+                                          bnrm.as<double>(), bpst.as<int32_t>(), brb.as<double>(), bpost.as<double>(),
+                                          bpcd.as<int32_t>(), bbar.as<uint32_t>(), h->stream);
+          if (le != hipSuccess)
+            return set_err(h, SPAND_E_HIP, std::string("large-interface sparsification launch: ") + hipGetErrorString(le));
+          HIPCHK(hipEventRecord(e1, h->stream));
+          ++nlaunch;
+          continue;
+        }
         hipError_t le = Lc.multi ? launch_cpqr_multi(dd, ss, Lc.nslab, Lc.nround, b.as<SegDesc>(), tol,
                                                      curb.as<int32_t>(), nrefb.as<int32_t>(), errb.as<int32_t>(),
                                                      Lc.lds, h->stream)
@@ -1425,6 +1520,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
     s.cpqr_seconds = cpqr_ms * 1e-3;
     s.cpqr_launches = cpqr_launches;
     for (int q = 0; q < 4; ++q) s.cpqr_interfaces[q] = pb.cpqr_ifaces[q];
+    s.cpqr_big_interfaces = pb.cpqr_big;
     for (int q = 0; q < 3; ++q) s.apply_interfaces[q] = 0;
     for (const StepNum& sn : pb.h->num) {
       s.apply_interfaces[0] += sn.n_iface1;

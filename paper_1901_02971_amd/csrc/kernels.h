@@ -148,6 +148,16 @@ hipError_t launch_cpqr_one(int32_t G, const SparsDesc* d, const SlabRef* slabs, 
 hipError_t launch_cpqr_multi(const SparsDesc* d, const SlabRef* slabs, int32_t nslab, int32_t nround,
                              const SegDesc* seg, double eps, int32_t* cursize, int32_t* nref, int32_t* err,
                              size_t lds_bytes, hipStream_t s);
+// Interfaces beyond the register layouts (kernels_cpqr.hip k_cpqr_big): one
+// cooperative launch of nb workgroups per interface, A_pn in a global work copy.
+// Rows at most cpqr_big_max_rows(); the scratch holds wk (m * ncols doubles), nrm
+// (ncols), pst (ncols ints), rb (min(m, ncols)), post_mx (nb), post_cd (nb ints) and
+// the barrier counter bar, which must be zero at launch.
+int32_t cpqr_big_max_rows();
+int cpqr_big_max_coresident(int32_t nseg);
+hipError_t launch_cpqr_big(const SparsDesc& d, int32_t nseg, const SegDesc* seg, double eps, int32_t* cursize,
+                           int32_t* nref, int32_t* err, int32_t nb, double* wk, double* nrm, int32_t* pst, double* rb,
+                           double* post_mx, int32_t* post_cd, uint32_t* bar, hipStream_t s);
 struct TDesc {
   const double* V;    // m x r, ld m
   const double* tau;  // r

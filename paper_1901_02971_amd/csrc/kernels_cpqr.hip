@@ -863,6 +863,285 @@ hipError_t launch_cpqr_one_wide(const SparsDesc* d, const SlabRef* slabs, int32_
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Interfaces beyond the register layouts (more than 2048 rows, or more columns than
+// the co-resident slabs hold): one cooperative launch per interface.  The NB
+// workgroups of the launch own the columns c = b, b + NB, ... of A_pn, kept in a
+// global work copy Wk (m x nc, ld m); the same Householder QR with column pivoting
+// as the slab kernels (exact trailing norms recomputed every step, the pivot is the
+// smallest column index whose norm is within TIE_RTOL of the largest, the dlarfg
+// reflector convention, the ratio stop rule), with two grid-wide barriers per step:
+//   after the update, each workgroup posts the largest norm of its remaining
+//   columns; barrier; every workgroup combines them and posts its smallest column
+//   index inside the window; barrier; every workgroup combines those, reads the
+//   pivot column, forms the reflector in LDS with identical arithmetic, and
+//   updates its own columns.
+// Wk, the posts and the barrier counter are written and read with agent-scope
+// atomic accesses (coherent across the XCD caches); a workgroup waits for its stores
+// to complete before it arrives at a barrier.  Waits are bounded: on time-out bit 2
+// of err is set and every workgroup leaves.
+#define CB_NT 256
+#define CB_MAXM 7680  // rows of the reflector kept in LDS
+struct BigScratch {
+  double* wk;      // m x nc, ld m
+  double* nrm;     // nc: squared norm of rows j..m-1 of each column
+  int32_t* pst;    // nc: step at which the column was the pivot, -1 remaining
+  double* rb;      // R_jj of every step
+  double* post_mx; // NB
+  int32_t* post_cd;// NB
+  uint32_t* bar;   // barrier counter, zero at launch
+};
+
+__device__ inline double big_wave_sum(double v) {
+  v += dpp_d<DPP_X1>(v);
+  v += dpp_d<DPP_X2>(v);
+  v += dpp_d<DPP_HMIR>(v);
+  v += dpp_d<DPP_MIR>(v);
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
+__device__ inline int big_pst(const BigScratch& bs, int c) {
+  return __hip_atomic_load(bs.pst + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid barrier number k (1, 2, ...) of the launch; false on time-out.
+__device__ inline bool big_barrier(uint32_t* bar, uint32_t k, int32_t* err) {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __syncthreads();
+  __shared__ int ok;
+  if (threadIdx.x == 0) {
+    ok = 1;
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t target = k * gridDim.x;
+    for (long spins = 0;; ++spins) {
+      if (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+      if (spins > SPIN_LIMIT || ((spins & 1023) == 1023 && timed_out(err))) {
+        atomicOr(err, 4);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+__global__ void __launch_bounds__(CB_NT) k_cpqr_big(SparsDesc d, const SegDesc* __restrict__ segs, double eps,
+                                                   int32_t* cursize, int32_t* nref, int32_t* err, BigScratch bs) {
+  __shared__ double vv[CB_MAXM];
+  __shared__ double red[CB_NT / 64];
+  __shared__ int redi[CB_NT / 64];
+  __shared__ int segoff_s[65];
+  extern __shared__ int segoff_dyn[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NWV = CB_NT / 64;
+  const int NB = gridDim.x, b = blockIdx.x;
+  const int nseg = d.seg_end - d.seg_begin;
+  const SegDesc* sg = segs + d.seg_begin;
+  int* segoff = nseg < 64 ? segoff_s : segoff_dyn;
+  if (tid == 0) {
+    int off = 0;
+    for (int s = 0; s < nseg; ++s) {
+      segoff[s] = off;
+      off += cursize[sg[s].q];
+    }
+    segoff[nseg] = off;
+  }
+  __syncthreads();
+  const int m = d.m, nc = segoff[nseg];
+  if (nc == 0) {
+    if (b == 0 && tid == 0) nref[d.id] = 0;
+    return;
+  }
+  double* wk = bs.wk;
+  auto W = [&](int i, int c) -> double* { return wk + (int64_t)c * m + i; };
+  // load the owned columns and their norms
+  for (int c = b + NB * wave; c < nc; c += NB * NWV) {
+    double* base;
+    int64_t stride;
+    column_ptr(sg, segoff, c, base, stride);
+    double s2 = 0.0;
+    for (int i = lane; i < m; i += 64) {
+      const double v = base[(int64_t)i * stride];
+      shared_store(W(i, c), v);
+      s2 = fma(v, v, s2);
+    }
+    s2 = big_wave_sum(s2);
+    if (lane == 0) {
+      shared_store(bs.nrm + c, s2);
+      __hip_atomic_store(bs.pst + c, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  uint32_t nbar = 0;
+  const int kmax = min(m, nc);
+  int r = kmax;
+  double r00 = 0.0;
+  bool alive = true;
+  for (int j = 0; j < kmax && alive; ++j) {
+    // largest remaining norm of this workgroup
+    __syncthreads();  // the owner-written norms of this workgroup are visible to its threads
+    double lmx = -1.0;
+    for (int c = b + NB * tid; c < nc; c += NB * CB_NT)
+      if (big_pst(bs, c) == -1) lmx = fmax(lmx, sqrt(shared_load(bs.nrm + c)));
+    lmx = wave_max(lmx);
+    if (lane == 0) red[wave] = lmx;
+    __syncthreads();
+    if (tid == 0) {
+      double x = red[0];
+      for (int q = 1; q < NWV; ++q) x = fmax(x, red[q]);
+      shared_store(bs.post_mx + b, x);
+    }
+    if (!big_barrier(bs.bar, ++nbar, err)) { alive = false; break; }
+    double gmx = -1.0;
+    for (int q = 0; q < NB; ++q) gmx = fmax(gmx, shared_load(bs.post_mx + q));
+    const double thr = gmx * (1.0 - TIE_RTOL);
+    int lcd = INT_MAX;
+    for (int c = b + NB * tid; c < nc; c += NB * CB_NT)
+      if (big_pst(bs, c) == -1 && sqrt(shared_load(bs.nrm + c)) >= thr) lcd = min(lcd, c);
+    lcd = wave_min(lcd);
+    if (lane == 0) redi[wave] = lcd;
+    __syncthreads();
+    if (tid == 0) {
+      int x = redi[0];
+      for (int q = 1; q < NWV; ++q) x = min(x, redi[q]);
+      __hip_atomic_store(bs.post_cd + b, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (!big_barrier(bs.bar, ++nbar, err)) { alive = false; break; }
+    int piv = INT_MAX;
+    for (int q = 0; q < NB; ++q)
+      piv = min(piv, __hip_atomic_load(bs.post_cd + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (piv == INT_MAX) {  // only non-finite norms left
+      r = j;
+      break;
+    }
+    // the pivot column: its norm (rows j..), alpha and the squared norm below j, by
+    // every workgroup with the same arithmetic
+    double s_all = 0.0, s_low = 0.0;
+    for (int i = j + tid; i < m; i += CB_NT) {
+      const double x = shared_load(W(i, piv));
+      vv[i] = x;
+      s_all = fma(x, x, s_all);
+      if (i > j) s_low = fma(x, x, s_low);
+    }
+    s_all = big_wave_sum(s_all);
+    s_low = big_wave_sum(s_low);
+    __shared__ double red2[2][CB_NT / 64];
+    if (lane == 0) {
+      red2[0][wave] = s_all;
+      red2[1][wave] = s_low;
+    }
+    __syncthreads();
+    double pn2 = 0.0, x2 = 0.0;
+    for (int q = 0; q < NWV; ++q) {
+      pn2 += red2[0][q];
+      x2 += red2[1][q];
+    }
+    const double pn = sqrt(pn2);
+    if (j == 0) {
+      r00 = pn;
+      if (r00 == 0.0) {
+        r = 0;
+        break;
+      }
+    }
+    if (pn < eps * r00) {
+      r = j;
+      break;
+    }
+    const double alpha = vv[j];
+    double tau = 0.0, scale = 0.0, beta = alpha;
+    if (x2 != 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + x2), alpha);
+      tau = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    __syncthreads();  // every thread has read alpha
+    for (int i = j + tid; i < m; i += CB_NT) vv[i] = (i == j) ? 1.0 : vv[i] * scale;
+    __syncthreads();
+    if (b == 0) {
+      for (int i = tid; i < m; i += CB_NT) d.V[(int64_t)j * m + i] = (i >= j) ? vv[i] : 0.0;
+      if (tid == 0) {
+        d.tau[j] = tau;
+        shared_store(bs.rb + j, beta);
+      }
+    }
+    if (piv % NB == b && tid == 0) __hip_atomic_store(bs.pst + piv, j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    // apply H_j to the owned remaining columns and form their new trailing norms
+    for (int c = b + NB * wave; c < nc; c += NB * NWV) {
+      if (big_pst(bs, c) != -1) continue;
+      double dt = 0.0;
+      for (int i = j + lane; i < m; i += 64) dt = fma(vv[i], shared_load(W(i, c)), dt);
+      dt = big_wave_sum(dt);
+      const double wv = tau * dt;
+      double s2 = 0.0;
+      for (int i = j + lane; i < m; i += 64) {
+        const double x = fma(-wv, vv[i], shared_load(W(i, c)));
+        shared_store(W(i, c), x);
+        if (i > j) s2 = fma(x, x, s2);
+      }
+      s2 = big_wave_sum(s2);
+      if (lane == 0) shared_store(bs.nrm + c, s2);
+    }
+  }
+  // every R_jj (posted by workgroup 0) is visible past one more barrier
+  if (alive && !big_barrier(bs.bar, ++nbar, err)) alive = false;
+  if (!alive) return;
+  // W_cn = R[:r, :] into the blocks of p; a pivot column of step s holds R_is for
+  // i < s, R_ss = rb[s] and zeros below
+  for (int c = b + NB * wave; c < nc; c += NB * NWV) {
+    if (r == 0) break;
+    double* base;
+    int64_t stride;
+    column_ptr(sg, segoff, c, base, stride);
+    const int ps = big_pst(bs, c);
+    for (int i = lane; i < r; i += 64) {
+      double v;
+      if (ps >= 0 && i >= ps)
+        v = (i == ps) ? shared_load(bs.rb + ps) : 0.0;
+      else
+        v = shared_load(W(i, c));
+      base[(int64_t)i * stride] = v;
+    }
+  }
+  if (b == 0) {
+    for (int64_t e = tid; e < (int64_t)r * r; e += CB_NT) {
+      const int x = (int)(e % r), y = (int)(e / r);
+      d.diag[x + (int64_t)y * d.ldd] = (x == y) ? 1.0 : 0.0;
+    }
+    if (tid == 0) {
+      cursize[d.id] = r;
+      nref[d.id] = r;
+    }
+  }
+}
+
+int32_t cpqr_big_max_rows() { return CB_MAXM; }
+
+int cpqr_big_max_coresident(int32_t nseg) {
+  int per_cu = 0;
+  const size_t lds = nseg < 64 ? 0 : (size_t(nseg) + 1) * sizeof(int);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cpqr_big, CB_NT, lds) != hipSuccess) return 0;
+  int dev = 0, cus = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  return per_cu * cus;
+}
+
+hipError_t launch_cpqr_big(const SparsDesc& d, int32_t nseg, const SegDesc* seg, double eps, int32_t* cursize,
+                           int32_t* nref, int32_t* err, int32_t nb, double* wk, double* nrm, int32_t* pst, double* rb,
+                           double* post_mx, int32_t* post_cd, uint32_t* bar, hipStream_t s) {
+  BigScratch bs{wk, nrm, pst, rb, post_mx, post_cd, bar};
+  SparsDesc dd = d;
+  const size_t lds = nseg < 64 ? 0 : (size_t(nseg) + 1) * sizeof(int);
+  void* args[] = {(void*)&dd, (void*)&seg, (void*)&eps, (void*)&cursize, (void*)&nref, (void*)&err, (void*)&bs};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_cpqr_big), dim3(nb), dim3(CB_NT), args,
+                                    (unsigned int)lds, s);
+}
+
 int cpqr_max_coresident(size_t lds) {
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cpqr_multi, CQ_NT, lds) != hipSuccess) return 0;

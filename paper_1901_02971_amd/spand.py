@@ -33,10 +33,11 @@ class SpandError(RuntimeError):
 
 class Tuning(C.Structure):
     _fields_ = [("chol_group", C.c_int32), ("fuse128_min", C.c_int32), ("gemm_variant", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("cpqr_big_min", C.c_int32), ("reserved", C.c_int32 * 4)]
+    KEYS = ("chol_group", "fuse128_min", "gemm_variant", "cpqr_big_min")
 
     def as_dict(self):
-        return {"chol_group": self.chol_group, "fuse128_min": self.fuse128_min, "gemm_variant": self.gemm_variant}
+        return {k: getattr(self, k) for k in self.KEYS}
 
 
 class Stats(C.Structure):
@@ -49,7 +50,8 @@ class Stats(C.Structure):
                 ("cpqr_flops", C.c_double), ("cpqr_seconds", C.c_double), ("cpqr_launches", C.c_int64),
                 ("apply_bytes", C.c_double), ("apply_seconds", C.c_double), ("apply_calls", C.c_int64),
                 ("apply_graph", C.c_int32), ("reserved2", C.c_int32), ("cpqr_interfaces", C.c_int64 * 4),
-                ("apply_interfaces", C.c_int64 * 3), ("pcg_replacements", C.c_int64)]
+                ("apply_interfaces", C.c_int64 * 3), ("pcg_replacements", C.c_int64),
+                ("cpqr_big_interfaces", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_
@@ -248,7 +250,7 @@ class Solver:
         t = Tuning()
         self._check(self._lib.spand_get_tuning(self._h, C.byref(t)))
         for k, v in kw.items():
-            if k not in ("chol_group", "fuse128_min", "gemm_variant"):
+            if k not in Tuning.KEYS:
                 raise KeyError(k)
             setattr(t, k, int(v))
         self._check(self._lib.spand_set_tuning(self._h, C.byref(t)))

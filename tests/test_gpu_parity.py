@@ -267,6 +267,36 @@ def test_cholesky_group_tuning_keeps_parity(group):
     assert np.abs(z - zr).max() <= 1e-10 * np.abs(zr).max()
 
 
+@pytest.mark.parametrize("big_min,shape,levels", [(1, (24, 24, 24), 5), (60, (26, 23, 21), 6)],
+                         ids=["all_big", "mixed"])
+def test_large_interface_cpqr_matches_oracle(big_min, shape, levels):
+    """The global-memory CPQR kernel (one cooperative launch per interface, the path
+    of interfaces beyond the register layouts) forced on every interface of at
+    least big_min dofs: ranks identical to the oracle's, the apply within 1e-10."""
+    p = gridgen.variable_coefficient(shape, np.random.default_rng(61), -2, 2)
+    b = gridgen.rhs(np.random.default_rng(62), p.n, 3)
+    an, fac = oracle_run(p, levels, 1e-2)
+    from paper_1901_02971_amd import Solver
+    s = Solver.from_problem(p, levels)
+    s.set_tuning(cpqr_big_min=big_min)
+    s.factor(torch.from_numpy(p.values).to("cuda:0"), 1e-2)
+    st = s.stats()
+    note(f"big CPQR interfaces {st['cpqr_big_interfaces']}, register layouts {st['cpqr_interfaces']}")
+    assert st["cpqr_big_interfaces"] > 0
+    if big_min == 1:
+        assert sum(st["cpqr_interfaces"]) == 0
+    else:
+        assert sum(st["cpqr_interfaces"]) > 0
+    assert rank_mismatches(s, an, fac) == 0
+    assert st["s_top"] == fac.stats["s_top"] and st["m_F"] == fac.stats["m_F"]
+    z = gpu_apply(s, b)
+    zr = O.apply(fac, b)
+    assert np.abs(z - zr).max() <= 1e-10 * np.abs(zr).max()
+    x, it, rr, _ = gpu_solve(s, b)
+    _, it_ref, _ = O.pcg(p.scipy(), b, lambda r: O.apply(fac, r))
+    assert np.all(np.abs(it - it_ref) <= 1) and np.all(rr <= 1e-12)
+
+
 GRAPH = [
     ("permuted_grid_16x14x12", lambda: gridgen.permuted(gridgen.laplacian((16, 14, 12)), np.random.default_rng(7)), 6),
     ("knn_graph_2500", lambda: gridgen.knn_graph_laplacian(2500, 6, np.random.default_rng(8)), 6),
