@@ -282,6 +282,60 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_sweep(args):
+    """The 3D size sweep of Sec. 4.2: n^3 grids with the quantized high-contrast field
+    (rho = 1: the Laplacian; rho = 100), 7-point stencil, depth 1 + ceil(log2(n^3/512)),
+    eps in {1e-1, 1e-3, 1e-5}, one RHS, PCG to 1e-12: s_top (the top separator right
+    before its elimination), PCG iterations, t_F, t_S and m_F per point, one JSON line
+    each, then a skip sweep (Sec. 4.4) at one size.  Points that do not fit the GPU's
+    memory are reported as such."""
+    import gridgen
+    import torch
+    from paper_1901_02971_amd import Solver, SpandError
+    dev = torch.device("cuda:0")
+    sizes = [int(x) for x in args.sweep_sizes.split(",")]
+    tols = [float(x) for x in args.sweep_tols.split(",")]
+    rhos = [float(x) for x in args.sweep_rhos.split(",")]
+    rows = []
+
+    def run(n, rho, tols, skips):
+        name = f"x4_{n}_rho{rho:g}"
+        print(json.dumps({"sweep_generating": name}), flush=True)
+        t0 = time.perf_counter()
+        p, b, L = gridgen.config_problem(name)
+        t_gen = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        s = Solver.from_problem(p, L)   # one analysis per grid, refactored for every point
+        t_P = time.perf_counter() - t0
+        vals = torch.from_numpy(p.values).to(dev)
+        bt = torch.from_numpy(np.ascontiguousarray(b.T)).to(dev)
+        xt = torch.empty_like(bt)
+        for tol, skip in [(t, 0) for t in tols] + [(1e-3, k) for k in skips]:
+            rec = {"n": n, "N": int(p.n), "rho": rho, "tol": tol, "skip": skip, "levels": int(L),
+                   "t_gen": round(t_gen, 1), "t_P": round(t_P, 3)}
+            try:
+                s.factor(vals, tol, skip, 0)
+                f = s.stats()
+                it, rr, st = s.solve(bt, xt, 1e-12, 500, check=False)
+                g = s.stats()
+                rec.update({"status": int(st), "s_top": int(f["s_top"]), "pcg_iters": int(it[0]),
+                            "relres": float(rr[0]), "t_F": round(f["t_factor"], 4), "t_S": round(g["t_solve"], 4),
+                            "m_F": int(f["m_F"]), "cpqr_big_interfaces": int(f["cpqr_big_interfaces"])})
+            except SpandError as e:
+                rec.update({"status": e.status, "error": str(e)[:200]})
+            print(json.dumps({"sweep_point": rec}), flush=True)
+            rows.append(rec)
+        s.close()
+        del vals, bt, xt
+        torch.cuda.empty_cache()
+
+    skip_n = int(args.skip_sweep) if args.skip_sweep else -1
+    for n in sizes:
+        for rho in rhos:
+            run(n, rho, tols, list(range(1, 5)) if (n == skip_n and rho == 1.0) else [])
+    print(json.dumps({"sweep": "x4", "points": len(rows)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -293,6 +347,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the FP32 / BF16x3 lines after the FP64 step")
     ap.add_argument("--problems", type=int, default=256, help="problems of the batched workload (--config c5)")
+    ap.add_argument("--sweep-sizes", default="32,48,64,96,128", help="grid edges of --config sweep")
+    ap.add_argument("--sweep-tols", default="1e-1,1e-3,1e-5")
+    ap.add_argument("--sweep-rhos", default="1,100")
+    ap.add_argument("--skip-sweep", default="", help="grid edge of the skip sweep (skip 0..4, eps 1e-3)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration for the traffic figure)")
     args = ap.parse_args()
@@ -306,6 +364,9 @@ def main():
         return
     if args.config == "c5":
         bench_batch(args)
+        return
+    if args.config == "sweep":
+        bench_sweep(args)
         return
     import torch
     from paper_1901_02971_amd import Solver

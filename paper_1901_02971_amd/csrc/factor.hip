@@ -1321,7 +1321,8 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
           Lb.multi = false;
           Lb.big_nseg = pb.nseg[p];
           Lb.d0 = all_sds.size();
-          Lb.nslab = int32_t(std::max<int64_t>(1, std::min<int64_t>(capb, (pb.ncols[p] + 15) / 16)));
+          // at most 1024 workgroups: the size of the launch's post arrays
+          Lb.nslab = int32_t(std::max<int64_t>(1, std::min<int64_t>(std::min(capb, 1024), (pb.ncols[p] + 15) / 16)));
           all_sds.push_back(d);
           launches.push_back(Lb);
           big_m = std::max<int64_t>(big_m, sn.size[p]);
