@@ -115,7 +115,13 @@ typedef struct {
  *   fuse128_min   the apply's fused one-wave kernel also takes interfaces of 65..128
  *                 dofs when a step has at least this many of them (default 256;
  *                 0 = always, -1 = never)
- *   gemm_variant  output tile of the batched matrix-core GEMM (see spand_autotune)
+ *   gemm_syrk     output tile of the batched matrix-core GEMM of the Schur SYRK
+ *   gemm_chol     ... of the trailing updates of the blocked Cholesky (pivot blocks and
+ *                 the rows below them)
+ *   gemm_scale    ... of the left scaling and the compact-WY T factors
+ *                 (0: 64 x 64, 1: 128 x 128, 2: 32 x 32 output tiles; every tile adds the
+ *                 products of an entry in one order, so results agree bit for bit; the
+ *                 BF16x3 products always use 64 x 64)
  *   cpqr_big_min  interfaces of at least this many dofs take the global-memory CPQR
  *                 kernel, which is otherwise kept for interfaces beyond the register
  *                 layouts (0 = only those; default 0)
@@ -123,9 +129,11 @@ typedef struct {
 typedef struct {
   int32_t chol_group;
   int32_t fuse128_min;
-  int32_t gemm_variant;
+  int32_t gemm_syrk;
   int32_t cpqr_big_min;
-  int32_t reserved[4];
+  int32_t gemm_chol;
+  int32_t gemm_scale;
+  int32_t reserved[2];
 } spand_tuning;
 
 /* Ordering, clustering and symbolic factorization (Algorithm 2, Sec. 2.3, with a
@@ -192,6 +200,23 @@ spand_status spand_set_apply_graph(spand_t h, int32_t enable);
  * next factor on.  Errors: SPAND_E_INVALID for a value out of range. */
 spand_status spand_set_tuning(spand_t h, const spand_tuning* t);
 spand_status spand_get_tuning(spand_t h, spand_tuning* t);
+
+/* Autotuner of the kernel shapes (spand_tuning) for this matrix and these settings.
+ * Coordinate descent over the parameters in turn (the GEMM tile of the Cholesky
+ * updates, the Cholesky grouping, the SYRK tile, the scaling tile, the apply's fusion
+ * threshold), each candidate timed on this handle's own factorization (the device
+ * time of the factor phases the parameter acts on, best of reps runs) or, for the
+ * fusion threshold, on its apply with nrhs columns; a candidate replaces the current
+ * choice only if it is at least 2% faster.  The handle ends factored (values, tol,
+ * skip, prec as in spand_factor) with the chosen tuning, which *out receives (may be
+ * NULL).  When the environment variable SPAND_TUNE_CACHE names a file, a choice
+ * stored there for the same matrix size, pattern size, levels, tol, skip, prec, nrhs
+ * and GPU architecture is taken without measuring, and a new choice is appended.
+ * The search factors the matrix about 16 x reps times.  Errors as spand_factor and
+ * spand_apply; SPAND_E_NOMEM if the timing vectors (2 n nrhs doubles) cannot be
+ * allocated. */
+spand_status spand_autotune(spand_t h, const double* values, double tol, int32_t skip, spand_prec prec, int32_t nrhs,
+                            int32_t reps, spand_tuning* out);
 
 /* Copy the statistics of the last analyze/factor/solve into *s. */
 spand_status spand_get_stats(spand_t h, spand_stats* s);

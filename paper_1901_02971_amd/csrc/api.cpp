@@ -263,8 +263,8 @@ spand_status spand_set_tuning(spand_t h, const spand_tuning* t) {
   if (t->chol_group < 1 || t->chol_group > 4) return set_err(h, SPAND_E_INVALID, "chol_group must be in [1, 4]");
   if (t->fuse128_min < -1) return set_err(h, SPAND_E_INVALID, "fuse128_min must be >= -1");
   if (t->cpqr_big_min < 0) return set_err(h, SPAND_E_INVALID, "cpqr_big_min must be >= 0");
-  if (t->gemm_variant < 0 || t->gemm_variant >= spand::gemm_variant_count())
-    return set_err(h, SPAND_E_INVALID, "unknown gemm_variant");
+  for (int32_t v : {t->gemm_syrk, t->gemm_chol, t->gemm_scale})
+    if (v < 0 || v >= spand::gemm_variant_count()) return set_err(h, SPAND_E_INVALID, "unknown GEMM variant");
   h->tune = *t;
   return SPAND_OK;
 }

@@ -131,8 +131,12 @@ void build_layout(const SymStep& st, const std::vector<int32_t>& size, Layout& L
 // A sequence of batched-GEMM launches.  The host uploads the products only; a
 // device kernel expands them into the tile -> product map the launches read.
 // part: 0 every tile, 1 tiles on or below the diagonal, 2 tiles on or above it.
+// The products of a launch are numbered at end_launch, once its arithmetic (and so
+// its output tile: the sequence's variant, or 64 for BF16x3) is known.
 struct GemmSeq {
-  std::vector<GemmDesc> d;
+  explicit GemmSeq(int variant_ = 0) : variant(variant_) {}
+  int variant;
+  std::vector<GemmDesc> d, cur;
   std::vector<int64_t> cut;  // tile range end of every launch
   std::vector<int> prec;
   int64_t ntiles = 0;
@@ -140,11 +144,17 @@ struct GemmSeq {
   void add(GemmDesc g, int part) {
     if (g.M <= 0 || g.N <= 0 || g.K <= 0) return;
     g.part = part;
-    g.t0 = ntiles;
-    ntiles += gemm_tiles(g.M, g.N, part);
-    d.push_back(g);
+    cur.push_back(g);
   }
   void end_launch(int p) {
+    const int ts = p == 2 ? 64 : gemm_variant_tile(variant);
+    for (GemmDesc& g : cur) {
+      g.ts = ts;
+      g.t0 = ntiles;
+      ntiles += gemm_tiles(g.M, g.N, g.part, ts);
+      d.push_back(g);
+    }
+    cur.clear();
     cut.push_back(ntiles);
     prec.push_back(p);
   }
@@ -157,7 +167,7 @@ struct GemmSeq {
   }
   void launch(spand_ctx* h, size_t q) const {
     const int64_t b = q ? cut[q - 1] : 0;
-    if (cut[q] > b) launch_gemm(dd.as<GemmDesc>(), dmap.as<int32_t>(), b, cut[q] - b, prec[q], h->stream);
+    if (cut[q] > b) launch_gemm(dd.as<GemmDesc>(), dmap.as<int32_t>(), b, cut[q] - b, prec[q], variant, h->stream);
   }
 };
 
@@ -188,7 +198,7 @@ spand_status blocked_cholesky(spand_ctx* h, const std::vector<Front>& F, int pre
   std::vector<PotrfDesc> pd;
   std::vector<PanelDesc> td;
   std::vector<int64_t> pcut, tcut;
-  GemmSeq g;
+  GemmSeq g(h->tune.gemm_chol);
   for (int32_t kb = 0; kb < nmax; kb += CHOL_NB) {
     for (const Front& f : F) {
       if (f.n <= kb) continue;
@@ -277,7 +287,7 @@ spand_status left_trsm(spand_ctx* h, const std::vector<LeftBlock>& B) {
   for (const LeftBlock& b : B) nmax = std::max(nmax, b.nrows);
   std::vector<LeftDesc> ld;
   std::vector<int64_t> lcut;
-  GemmSeq g;
+  GemmSeq g(h->tune.gemm_scale);
   for (int32_t kb = 0; kb < nmax; kb += CHOL_NB) {
     // grouped as in blocked_cholesky: inside a group only the next block row is
     // updated, at the group's end every row below, at depth CHOL_GROUP NB
@@ -521,7 +531,7 @@ struct Prob {
 spand_status build_t_factors(spand_ctx* h, const std::vector<TDesc>& tds) {
   if (tds.empty()) return SPAND_OK;
   spand_status st = SPAND_OK;
-  GemmSeq vtv;
+  GemmSeq vtv(h->tune.gemm_scale);
   for (const TDesc& td : tds) {
     GemmDesc q{};
     q.A = td.V; q.lda = td.m;
@@ -555,7 +565,7 @@ spand_status build_t_factors(spand_ctx* h, const std::vector<TDesc>& tds) {
   HIPCHK(hipGetLastError());
   if (rmax > 64) {
     if ((st = dalloc(h, xb, size_t(x_total) * sizeof(double))) != SPAND_OK) return st;
-    GemmSeq tg2;
+    GemmSeq tg2(h->tune.gemm_scale);
     for (int32_t j0 = 64; j0 < rmax; j0 += 64) {
       for (size_t q = 0; q < tds.size(); ++q) {
         const TDesc& td = tds[q];
@@ -829,7 +839,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
     HIPCHK(hipEventRecord(ph[2], h->stream));  // recorded again after the reduction
     {
       std::vector<Front> fr;
-      GemmSeq syrk;
+      GemmSeq syrk(h->tune.gemm_syrk);
       struct Item { int32_t prob; uint64_t tgt; int32_t s; int64_t coff; };
       std::vector<ReduceDesc> rds;
       std::vector<ContribDesc> cds2;

@@ -47,10 +47,12 @@ struct GemmDesc {
   int32_t part;  // 64x64 output tiles produced: 0 all, 1 on or below the diagonal, 2 on or above (M == N)
   double alpha, beta;
   int64_t t0;    // first tile of this product in the numbering of its launch sequence
+  int32_t ts;    // output tile edge of the launch (64, 128 or 32)
+  int32_t pad;
 };
-// Output tiles of one product (part != 0 requires M == N).
-__host__ __device__ inline int64_t gemm_tiles(int32_t M, int32_t N, int32_t part) {
-  const int64_t tm = (M + 63) / 64, tn = (N + 63) / 64;
+// Output tiles of edge ts of one product (part != 0 requires M == N).
+__host__ __device__ inline int64_t gemm_tiles(int32_t M, int32_t N, int32_t part, int32_t ts = 64) {
+  const int64_t tm = (M + ts - 1) / ts, tn = (N + ts - 1) / ts;
   return part == 0 ? tm * tn : tm * (tm + 1) / 2;
 }
 
@@ -110,9 +112,13 @@ void launch_scatter_values(const double* vals, const int64_t* dst, int64_t nnz, 
 // tile_desc[t] = product of tile t, for the tiles of nd products numbered by their t0.
 void launch_expand_tiles(const GemmDesc* d, int32_t nd, int32_t* tile_desc, hipStream_t s);
 // Tiles [tile0, tile0 + ntiles) of a sequence, one workgroup each.
-void launch_gemm(const GemmDesc* d, const int32_t* tile_desc, int64_t tile0, int64_t ntiles, int prec, hipStream_t s);
-// Number of output-tile variants of the batched GEMM (spand_tuning.gemm_variant).
+// variant: output tile 64 (0), 128 (1) or 32 (2) of the FP64 / FP32 kernels (BF16x3: 64);
+// every variant adds an entry's products in the same order, so results agree bit for bit.
+void launch_gemm(const GemmDesc* d, const int32_t* tile_desc, int64_t tile0, int64_t ntiles, int prec, int variant,
+                 hipStream_t s);
+// Number of output-tile variants of the batched GEMM, and the tile edge of each.
 int gemm_variant_count();
+int gemm_variant_tile(int variant);
 void launch_reduce(const ReduceDesc* d, int32_t count, const ContribDesc* c, hipStream_t s);
 void launch_copy(const CopyDesc* d, int64_t count, hipStream_t s);
 void launch_set_identity(const IdentDesc* d, int32_t count, hipStream_t s);

@@ -62,7 +62,9 @@ inline spand_tuning default_tuning() {
   spand_tuning t{};
   t.chol_group = 3;
   t.fuse128_min = 256;
-  t.gemm_variant = 0;
+  t.gemm_syrk = 0;
+  t.gemm_chol = 0;
+  t.gemm_scale = 0;
   return t;
 }
 

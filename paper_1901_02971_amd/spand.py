@@ -32,9 +32,10 @@ class SpandError(RuntimeError):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("chol_group", C.c_int32), ("fuse128_min", C.c_int32), ("gemm_variant", C.c_int32),
-                ("cpqr_big_min", C.c_int32), ("reserved", C.c_int32 * 4)]
-    KEYS = ("chol_group", "fuse128_min", "gemm_variant", "cpqr_big_min")
+    _fields_ = [("chol_group", C.c_int32), ("fuse128_min", C.c_int32), ("gemm_syrk", C.c_int32),
+                ("cpqr_big_min", C.c_int32), ("gemm_chol", C.c_int32), ("gemm_scale", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
+    KEYS = ("chol_group", "fuse128_min", "gemm_syrk", "cpqr_big_min", "gemm_chol", "gemm_scale")
 
     def as_dict(self):
         return {k: getattr(self, k) for k in self.KEYS}
@@ -90,6 +91,7 @@ def load_library():
         "spand_get_stats": (i32, [P, C.POINTER(Stats)]),
         "spand_set_tuning": (i32, [P, C.POINTER(Tuning)]),
         "spand_get_tuning": (i32, [P, C.POINTER(Tuning)]),
+        "spand_autotune": (i32, [P, P, f64, i32, i32, i32, i32, C.POINTER(Tuning)]),
         "spand_get_ordering": (i32, [P, P, P, P]),
         "spand_step_counts": (i32, [P, i32, P]),
         "spand_step_structure": (i32, [P, i32, P, P, P, P, P]),
@@ -254,6 +256,18 @@ class Solver:
                 raise KeyError(k)
             setattr(t, k, int(v))
         self._check(self._lib.spand_set_tuning(self._h, C.byref(t)))
+
+    def autotune(self, values, tol, skip=0, prec=SPAND_FP64, nrhs=1, reps=2):
+        """spand_autotune: choose the kernel shapes on this matrix; the handle ends
+        factored with them.  Returns the chosen tuning."""
+        import torch
+        if not (isinstance(values, torch.Tensor) and values.is_cuda and values.dtype == torch.float64
+                and values.is_contiguous()):
+            raise TypeError("values must be a contiguous float64 GPU tensor")
+        t = Tuning()
+        self._check(self._lib.spand_autotune(self._h, _ptr(values), float(tol), int(skip), int(prec), int(nrhs),
+                                             int(reps), C.byref(t)))
+        return t.as_dict()
 
     def stats(self):
         s = Stats()

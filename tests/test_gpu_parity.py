@@ -297,6 +297,51 @@ def test_large_interface_cpqr_matches_oracle(big_min, shape, levels):
     assert np.all(np.abs(it - it_ref) <= 1) and np.all(rr <= 1e-12)
 
 
+def test_gemm_tile_variants_agree_bit_for_bit():
+    """Every output tile of the FP64 GEMM adds an entry's products in one order: the
+    factorization, and so the apply, is the same bits whichever tile each GEMM class
+    uses (the autotuner only reorders work)."""
+    p = gridgen.variable_coefficient((22, 21, 20), np.random.default_rng(71), -2, 2)
+    b = gridgen.rhs(np.random.default_rng(72), p.n, 2)
+    from paper_1901_02971_amd import Solver
+    vals = torch.from_numpy(p.values).to("cuda:0")
+    zs = []
+    for v in (0, 1, 2):
+        s = Solver.from_problem(p, 6)
+        s.set_tuning(gemm_syrk=v, gemm_chol=v, gemm_scale=v)
+        s.factor(vals, 1e-2)
+        zs.append(gpu_apply(s, b))
+        s.close()
+    assert np.array_equal(zs[0], zs[1]) and np.array_equal(zs[0], zs[2])
+
+
+def test_autotune_and_cache(tmp_path, monkeypatch):
+    """spand_autotune picks a tuning, leaves the handle factored with it (parity with
+    the oracle unchanged), and stores the choice in SPAND_TUNE_CACHE, from which a
+    second handle takes it without measuring."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("SPAND_TUNE_CACHE", str(cache))
+    p = gridgen.variable_coefficient((20, 19, 18), np.random.default_rng(73), -2, 2)
+    b = gridgen.rhs(np.random.default_rng(74), p.n, 2)
+    an, fac = oracle_run(p, 6, 1e-2)
+    from paper_1901_02971_amd import Solver
+    vals = torch.from_numpy(p.values).to("cuda:0")
+    s = Solver.from_problem(p, 6)
+    t1 = s.autotune(vals, 1e-2, nrhs=2, reps=1)
+    note(f"autotune chose {t1}")
+    assert s.tuning() == t1
+    assert rank_mismatches(s, an, fac) == 0
+    z = gpu_apply(s, b)
+    zr = O.apply(fac, b)
+    assert np.abs(z - zr).max() <= 1e-10 * np.abs(zr).max()
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and " | " in lines[0]
+    s2 = Solver.from_problem(p, 6)
+    t2 = s2.autotune(vals, 1e-2, nrhs=2, reps=1)
+    assert t2 == t1 and len(cache.read_text().splitlines()) == 1
+    assert np.array_equal(gpu_apply(s2, b), z)
+
+
 GRAPH = [
     ("permuted_grid_16x14x12", lambda: gridgen.permuted(gridgen.laplacian((16, 14, 12)), np.random.default_rng(7)), 6),
     ("knn_graph_2500", lambda: gridgen.knn_graph_laplacian(2500, 6, np.random.default_rng(8)), 6),
