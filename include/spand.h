@@ -105,6 +105,9 @@ typedef struct {
    * interfaces beyond the register layouts (more than 2048 rows, more columns than
    * the co-resident slabs hold, or at least tuning.cpqr_big_min rows). */
   int64_t cpqr_big_interfaces;
+  /* Doubles of apply scratch per right-hand side that the last factorization needs
+   * (spand_apply_noalloc holds 8 Mi doubles in all). */
+  int64_t apply_scratch_per_rhs;
 } spand_stats;
 
 /* Kernel-shape and path parameters of a handle.  None of them changes what is
@@ -184,6 +187,21 @@ spand_status spand_solve(spand_t h, int32_t nrhs, const double* b, double* x, do
 /* Preconditioner apply z = M M^T r (Sec. 2.8) for nrhs columns; r, z device n x nrhs
  * column-major (may not alias).  Errors: SPAND_E_STATE, SPAND_E_HIP. */
 spand_status spand_apply(spand_t h, int32_t nrhs, const double* r, double* z);
+
+/* spand_apply for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same apply
+ * z = M M^T r, with the apply's scratch in a fixed 64 MiB array of the library (8 Mi
+ * doubles per GPU, held until the process ends) instead of the handle's workspace.
+ * It calls no allocator and does not synchronize: the kernels are enqueued on the
+ * handle's stream and z is ready when that stream reaches them.  All calls on one
+ * GPU share the array, so calls that overlap on one GPU (other streams, other
+ * handles, other threads) race; the array is fully written before it is read, so
+ * nothing carries over from one call to the next.  It needs
+ * spand_stats.apply_scratch_per_rhs * nrhs doubles of scratch (a property of the
+ * factorization); a call needing more than the array holds returns
+ * SPAND_E_INVALID, with the size needed in spand_error_string, and runs nothing.  Other errors:
+ * SPAND_E_STATE, SPAND_E_HIP. */
+spand_status spand_apply_noalloc(spand_t h, int32_t nrhs, const double* r, double* z);
 
 /* Use this HIP stream (hipStream_t passed as void*) for all later device work of
  * the handle; NULL selects the default stream. */

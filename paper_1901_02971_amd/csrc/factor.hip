@@ -1532,6 +1532,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
     s.cpqr_launches = cpqr_launches;
     for (int q = 0; q < 4; ++q) s.cpqr_interfaces[q] = pb.cpqr_ifaces[q];
     s.cpqr_big_interfaces = pb.cpqr_big;
+    s.apply_scratch_per_rhs = std::max<int64_t>(pb.h->max_tmp, 1) + std::max<int64_t>(pb.h->max_gather, 1);
     for (int q = 0; q < 3; ++q) s.apply_interfaces[q] = 0;
     for (const StepNum& sn : pb.h->num) {
       s.apply_interfaces[0] += sn.n_iface1;

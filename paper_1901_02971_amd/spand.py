@@ -52,7 +52,7 @@ class Stats(C.Structure):
                 ("apply_bytes", C.c_double), ("apply_seconds", C.c_double), ("apply_calls", C.c_int64),
                 ("apply_graph", C.c_int32), ("reserved2", C.c_int32), ("cpqr_interfaces", C.c_int64 * 4),
                 ("apply_interfaces", C.c_int64 * 3), ("pcg_replacements", C.c_int64),
-                ("cpqr_big_interfaces", C.c_int64)]
+                ("cpqr_big_interfaces", C.c_int64), ("apply_scratch_per_rhs", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_

@@ -12,6 +12,7 @@ from paper_1901_02971_amd import spand as S
 
 DECLARED = ["spand_analyze", "spand_factor", "spand_solve", "spand_apply", "spand_set_stream",
             "spand_set_apply_graph", "spand_get_stats", "spand_set_tuning", "spand_get_tuning", "spand_autotune",
+            "spand_apply_noalloc",
             "spand_get_ordering", "spand_step_counts", "spand_step_structure", "spand_step_ranks",
             "spand_factor_batch", "spand_solve_batch", "spand_error_string", "spand_destroy"]
 
