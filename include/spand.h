@@ -243,6 +243,12 @@ spand_status spand_get_stats(spand_t h, spand_stats* s);
  * ("none" = 0); host arrays of n entries each. */
 spand_status spand_get_ordering(spand_t h, int64_t* S, int64_t* L, int64_t* R);
 
+/* The nested-dissection elimination order of the vertices (Algorithm 2's output
+ * order): perm[k] = the k-th vertex eliminated, sorted by the step of its separator
+ * (leaves first), then by the cluster of that step it belongs to (canonical cluster
+ * order), then by vertex id.  host array of n entries. */
+spand_status spand_get_permutation(spand_t h, int64_t* perm);
+
 /* Symbolic structure of elimination step `step` (1-based; level = levels - step + 1).
  * counts (host, 6 entries) receives: number of clusters nc, number eliminated ne,
  * number of blocks before elimination nb, number of blocks among remaining clusters

@@ -483,6 +483,22 @@ class Analysis:
         self.steps = symbolic(n, self.rowptr, self.colind, self.S, self.L, self.R, levels, skip)
 
 
+def nd_permutation(an: Analysis):
+    """The elimination order of the vertices under Algorithm 2 + the cluster tree: a
+    vertex goes at the step that eliminates its separator's level, inside the
+    cluster its step-1 cluster has merged into by then; ties by vertex id."""
+    cl = np.empty(an.n, dtype=np.int64)
+    for c, ch in enumerate(an.steps[0].children):
+        cl[ch] = c
+    up = [np.arange(len(an.steps[0].keys))]
+    for st in an.steps[:-1]:
+        prev = up[-1]
+        up.append(np.where(prev >= 0, st.parent[np.maximum(prev, 0)], -1))
+    t = an.levels - lev_of(an.S)   # 0-based step of each vertex
+    c = np.array([up[t[v]][cl[v]] for v in range(an.n)], dtype=np.int64)
+    return np.lexsort((np.arange(an.n), c, t))
+
+
 def _get(blocks, i, j):
     if i >= j:
         return blocks[(i, j)]

@@ -290,6 +290,39 @@ spand_status spand_get_ordering(spand_t h, int64_t* S, int64_t* L, int64_t* R) {
   return SPAND_OK;
 }
 
+spand_status spand_get_permutation(spand_t h, int64_t* perm) {
+  if (!h || !perm) return fail_null(SPAND_E_INVALID, "NULL argument");
+  // vertex v is eliminated at the step of its separator, t = L - level(S) + 1, inside
+  // the cluster its step-1 cluster has merged into by then
+  const spand::Analysis& an = h->an;
+  const int64_t n = an.n;
+  std::vector<int32_t> cl(n), ptr(n);
+  const spand::SymStep& s1 = an.steps[0];
+  for (int32_t c = 0; c < s1.nc; ++c)
+    for (int64_t e = s1.child_ptr[c]; e < s1.child_ptr[c + 1]; ++e) cl[s1.child[e]] = c;
+  struct Key { int32_t t, c; int64_t v; };
+  std::vector<Key> keys(n);
+  std::vector<std::vector<int32_t>> up(an.levels);  // cluster of step t holding each step-1 cluster
+  up[0].resize(s1.nc);
+  for (int32_t c = 0; c < s1.nc; ++c) up[0][c] = c;
+  for (int32_t t = 1; t < an.levels; ++t) {
+    up[t].resize(s1.nc);
+    const spand::SymStep& pv = an.steps[t - 1];
+    for (int32_t c = 0; c < s1.nc; ++c) up[t][c] = up[t - 1][c] >= 0 ? pv.parent[up[t - 1][c]] : -1;
+  }
+  for (int64_t v = 0; v < n; ++v) {
+    const int32_t t = an.levels - int32_t(spand::sep_level(an.S[v]));  // 0-based step
+    keys[v] = Key{t, up[t][cl[v]], v};
+  }
+  std::sort(keys.begin(), keys.end(), [](const Key& a, const Key& b) {
+    if (a.t != b.t) return a.t < b.t;
+    if (a.c != b.c) return a.c < b.c;
+    return a.v < b.v;
+  });
+  for (int64_t q = 0; q < n; ++q) perm[q] = keys[q].v;
+  return SPAND_OK;
+}
+
 spand_status spand_step_counts(spand_t h, int32_t step, int64_t* counts) {
   if (!h || !counts) return fail_null(SPAND_E_INVALID, "NULL argument");
   if (step < 1 || step > h->an.levels) return set_err(h, SPAND_E_INVALID, "step out of range");

@@ -93,6 +93,7 @@ def load_library():
         "spand_get_tuning": (i32, [P, C.POINTER(Tuning)]),
         "spand_autotune": (i32, [P, P, f64, i32, i32, i32, i32, C.POINTER(Tuning)]),
         "spand_get_ordering": (i32, [P, P, P, P]),
+        "spand_get_permutation": (i32, [P, P]),
         "spand_step_counts": (i32, [P, i32, P]),
         "spand_step_structure": (i32, [P, i32, P, P, P, P, P]),
         "spand_step_ranks": (i32, [P, i32, P, P]),
@@ -280,6 +281,11 @@ class Solver:
         R = np.zeros(self.n, np.int64)
         self._check(self._lib.spand_get_ordering(self._h, _ptr(S), _ptr(L), _ptr(R)))
         return S, L, R
+
+    def permutation(self):
+        perm = np.zeros(self.n, np.int64)
+        self._check(self._lib.spand_get_permutation(self._h, _ptr(perm)))
+        return perm
 
     def step_counts(self, step):
         c = np.zeros(6, np.int64)
