@@ -40,22 +40,34 @@ CPQR_SRC = os.path.join(ROOT, "paper_1901_02971_amd", "csrc", "kernels_cpqr.hip"
 TRAFFIC_MD = os.path.join(ROOT, "profiles", "k_cpqr_lap128_tol1e-2_traffic.md")
 
 
-def cpqr_traffic():
-    """HBM bytes per CPQR launch measured with rocprofv3 --pmc (FETCH_SIZE + WRITE_SIZE,
-    scaled by a plain-copy calibration), from the committed summary.  None unless the
-    summary was taken on the kernel source as it is now."""
+APPLY_SRC = os.path.join(ROOT, "paper_1901_02971_amd", "csrc", "kernels_apply.hip")
+APPLY_TRAFFIC_MD = os.path.join(ROOT, "profiles", "apply_lap128_tol1e-2_traffic.md")
+
+
+def measured_traffic(src, md, label):
+    """HBM bytes per launch (or per apply) measured with rocprofv3 --pmc (FETCH_SIZE +
+    WRITE_SIZE, scaled by a plain-copy calibration), from a committed summary.  None
+    unless the summary was taken on the kernel source as it is now."""
     try:
-        with open(CPQR_SRC, "rb") as f:
+        with open(src, "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
-        with open(TRAFFIC_MD) as f:
+        with open(md) as f:
             txt = f.read()
     except OSError:
         return None
     m_sha = re.search(r"kernel source sha256: `([0-9a-f]{64})`", txt)
-    m_val = re.search(r"HBM bytes per launch: `([0-9.eE+]+)`", txt)
+    m_val = re.search(label + r": `([0-9.eE+]+)`", txt)
     if not m_sha or not m_val or m_sha.group(1) != sha:
         return None
     return float(m_val.group(1))
+
+
+def cpqr_traffic():
+    return measured_traffic(CPQR_SRC, TRAFFIC_MD, "HBM bytes per launch")
+
+
+def apply_traffic():
+    return measured_traffic(APPLY_SRC, APPLY_TRAFFIC_MD, "HBM bytes per apply")
 
 
 def copy_calibration(mib=1024, reps=3):
@@ -438,7 +450,8 @@ def main():
                   "hip_graph": bool(ss[-1]["apply_graph"]),
                   "calls_per_step": int(ss[-1]["apply_calls"]), "ms_per_apply": round(apply_s * 1e3, 3),
                   "bytes_per_apply": ss[-1]["apply_bytes"], "achieved": round(apply_gbs, 1), "peak": HBM_GBS,
-                  "unit": "GB/s", "frac": round(apply_gbs / HBM_GBS, 4)},
+                  "unit": "GB/s", "frac": round(apply_gbs / HBM_GBS, 4),
+                  "traffic": apply_traffic() if args.config == "c4" and args.tol == 1e-2 and nrhs == 8 else None},
         "schur": {"kernel": "elimination phase: blocked Cholesky + MFMA TRSM/SYRK + ordered reduce (Sec. 2.4)",
                   "bound": "mfma", "ms_total": round(schur_s * 1e3, 2), "flops": schur_flops,
                   "achieved": round(schur_tf, 3), "peak": round(PEAK_TFLOPS[args.prec], 1), "unit": "TFLOP/s",
@@ -447,7 +460,9 @@ def main():
     share = {"cpqr": cpqr_s, "apply": apply_s * ss[-1]["apply_calls"], "schur": schur_s}
     dom = max(share, key=share.get)
     k = kernels[dom]
-    traffic = cpqr_traffic() if dom == "cpqr" else None
+    traffic = None
+    if args.config == "c4" and args.tol == 1e-2:
+        traffic = cpqr_traffic() if dom == "cpqr" else (apply_traffic() if dom == "apply" else None)
     roof = {"bound": k["bound"], "kernel": k["kernel"], "achieved": k["achieved"], "peak": k["peak"],
             "unit": k["unit"], "frac": k["frac"], "traffic": traffic,
             "seconds_per_step": round(share[dom], 4)}
