@@ -94,8 +94,22 @@ struct ApplyArgs {
 void apply_step_forward(const StepDev& s, const ApplyArgs& a, hipStream_t st);
 void apply_step_backward(const StepDev& s, const ApplyArgs& a, hipStream_t st);
 
+// y = A x; x and y have leading dimension ld (n when ld <= 0).
 void launch_spmv(const int64_t* rowptr, const int32_t* colind, const double* val, int64_t n, int nrhs,
-                 const double* x, double* y, hipStream_t s);
+                 const double* x, double* y, hipStream_t s, int64_t ld = 0);
+
+// Batched PCG over problems stacked in one vector (leading dimension ld): the blocks
+// of the segmented dot products (problem q: nblk[q] blocks of its n_q rows at off).
+struct SegBlk {
+  int64_t off, n;
+  int32_t local, nblk;
+};
+void launch_seg_dot(const double* a, const double* b, int64_t ld, int nrhs, const SegBlk* blks, int64_t nb_tot,
+                    const int64_t* pbase, const int32_t* nblk, int32_t P, double* partial, double* out, hipStream_t s);
+void launch_seg_update_xr(int64_t ntot, int nrhs, const int32_t* pid, const double* rz, const double* pq,
+                          const int32_t* active, const double* p, const double* q, double* x, double* r, hipStream_t s);
+void launch_seg_update_p(int64_t ntot, int nrhs, const int32_t* pid, const double* rz_new, const double* rz,
+                         const int32_t* active, const double* z, double* p, hipStream_t s);
 void launch_dot(const double* a, const double* b, int64_t n, int nrhs, double* partial, int nblk, double* out,
                 hipStream_t s);
 void launch_update_xr(int64_t n, int nrhs, const double* rz, const double* pq, const int32_t* active,

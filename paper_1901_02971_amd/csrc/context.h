@@ -207,6 +207,7 @@ struct StepNum {
   std::vector<HouseTile> h_hr, h_hv;
   std::vector<ScaleTile> h_stile;
   std::vector<int32_t> h_sgather;
+  std::vector<int32_t> h_nslot;  // neighbour slots of the eliminated clusters (vertex ids)
   std::vector<IfaceAp> h_iface;
 };
 

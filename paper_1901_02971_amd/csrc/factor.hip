@@ -482,6 +482,7 @@ spand_status build_apply(spand_ctx* h, const SymStep& sy, StepNum& sn, const Lay
   sn.n_hv = int32_t(sn.h_hv.size());
   if ((st = upload(h, sn.d_slot, sn.slot)) != SPAND_OK) return st;
   if ((st = upload(h, sn.d_nslot, nslot)) != SPAND_OK) return st;
+  sn.h_nslot = std::move(nslot);
   if ((st = upload(h, sn.d_elim, sn.h_elim)) != SPAND_OK) return st;
   if ((st = upload(h, sn.d_target, sn.h_target)) != SPAND_OK) return st;
   if ((st = upload(h, sn.d_contrib, sn.h_contrib)) != SPAND_OK) return st;

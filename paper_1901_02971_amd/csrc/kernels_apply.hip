@@ -760,13 +760,13 @@ void apply_step_backward(const StepDev& s, const ApplyArgs& a, hipStream_t st) {
 // read once per block of right-hand sides.
 __global__ void __launch_bounds__(256) k_spmv(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
                                               const double* __restrict__ val, int64_t n, int nrhs,
-                                              const double* __restrict__ x, double* __restrict__ y) {
+                                              const double* __restrict__ x, double* __restrict__ y, int64_t ld) {
   const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (v >= n) return;
   const int64_t b = rowptr[v], e = rowptr[v + 1];
   for (int c0 = 0; c0 < nrhs; c0 += RB) {
     const int nr = min(RB, nrhs - c0);
-    const double* xc = x + (int64_t)c0 * n;
+    const double* xc = x + (int64_t)c0 * ld;
     double s[RB];
 #pragma unroll
     for (int c = 0; c < RB; ++c) s[c] = 0.0;
@@ -775,11 +775,11 @@ __global__ void __launch_bounds__(256) k_spmv(const int64_t* __restrict__ rowptr
       const int64_t col = colind[q];
 #pragma unroll
       for (int c = 0; c < RB; ++c)
-        if (c < nr) s[c] = fma(a, xc[col + (int64_t)c * n], s[c]);
+        if (c < nr) s[c] = fma(a, xc[col + (int64_t)c * ld], s[c]);
     }
 #pragma unroll
     for (int c = 0; c < RB; ++c)
-      if (c < nr) y[v + (int64_t)(c0 + c) * n] = s[c];
+      if (c < nr) y[v + (int64_t)(c0 + c) * ld] = s[c];
   }
 }
 
@@ -852,8 +852,91 @@ __global__ void k_residual(int64_t len, const double* __restrict__ b, double* __
 }
 
 void launch_spmv(const int64_t* rowptr, const int32_t* colind, const double* val, int64_t n, int nrhs,
-                 const double* x, double* y, hipStream_t s) {
-  hipLaunchKernelGGL(k_spmv, dim3((n + 255) / 256), dim3(256), 0, s, rowptr, colind, val, n, nrhs, x, y);
+                 const double* x, double* y, hipStream_t s, int64_t ld) {
+  hipLaunchKernelGGL(k_spmv, dim3((n + 255) / 256), dim3(256), 0, s, rowptr, colind, val, n, nrhs, x, y,
+                     ld > 0 ? ld : n);
+}
+
+// ---------------------------------------------------------------- batched PCG kernels
+// Several problems stacked in one vector of leading dimension ld (problem q in rows
+// [off[q], off[q] + n_q)); scalars per (problem, column) at q * nrhs + c.  The dot
+// products keep the single-problem reduction order: problem q has nblk[q] blocks
+// (its own count), each summing its rows with the same stride and tree.
+__global__ void __launch_bounds__(256) k_seg_dot_partial(const double* __restrict__ a, const double* __restrict__ b,
+                                                         int64_t ld, const SegBlk* __restrict__ blks, int64_t nb_tot,
+                                                         double* __restrict__ partial) {
+  const int c = blockIdx.y;
+  const SegBlk sb = blks[blockIdx.x];
+  const double* ac = a + sb.off + (int64_t)c * ld;
+  const double* bc = b + sb.off + (int64_t)c * ld;
+  double s = 0.0;
+  for (int64_t i = int64_t(sb.local) * 256 + threadIdx.x; i < sb.n; i += int64_t(sb.nblk) * 256) s += ac[i] * bc[i];
+  __shared__ double red[4];
+  s = wsum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x + (int64_t)c * nb_tot] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void __launch_bounds__(256) k_seg_dot_final(const double* __restrict__ partial, const int64_t* __restrict__ pbase,
+                                                       const int32_t* __restrict__ nblk, int64_t nb_tot, int nrhs,
+                                                       double* __restrict__ out) {
+  const int q = blockIdx.x, c = blockIdx.y;
+  const double* pp = partial + pbase[q] + (int64_t)c * nb_tot;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nblk[q]; i += 256) s += pp[i];
+  __shared__ double red[4];
+  s = wsum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[(int64_t)q * nrhs + c] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void k_seg_update_xr(int64_t ntot, int nrhs, const int32_t* __restrict__ pid, const double* __restrict__ rz,
+                                const double* __restrict__ pq, const int32_t* __restrict__ active,
+                                const double* __restrict__ p, const double* __restrict__ q, double* __restrict__ x,
+                                double* __restrict__ r) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= ntot) return;
+  const int64_t k = (int64_t)pid[i] * nrhs;
+  for (int c = 0; c < nrhs; ++c) {
+    if (!active[k + c]) continue;
+    const double alpha = rz[k + c] / pq[k + c];
+    const int64_t o = i + (int64_t)c * ntot;
+    x[o] += alpha * p[o];
+    r[o] -= alpha * q[o];
+  }
+}
+
+__global__ void k_seg_update_p(int64_t ntot, int nrhs, const int32_t* __restrict__ pid, const double* __restrict__ rz_new,
+                               const double* __restrict__ rz, const int32_t* __restrict__ active,
+                               const double* __restrict__ z, double* __restrict__ p) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= ntot) return;
+  const int64_t k = (int64_t)pid[i] * nrhs;
+  for (int c = 0; c < nrhs; ++c) {
+    if (!active[k + c]) continue;
+    const double beta = rz_new[k + c] / rz[k + c];
+    const int64_t o = i + (int64_t)c * ntot;
+    p[o] = z[o] + beta * p[o];
+  }
+}
+
+void launch_seg_dot(const double* a, const double* b, int64_t ld, int nrhs, const SegBlk* blks, int64_t nb_tot,
+                    const int64_t* pbase, const int32_t* nblk, int32_t P, double* partial, double* out,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_seg_dot_partial, dim3(nb_tot, nrhs), dim3(256), 0, s, a, b, ld, blks, nb_tot, partial);
+  hipLaunchKernelGGL(k_seg_dot_final, dim3(P, nrhs), dim3(256), 0, s, partial, pbase, nblk, nb_tot, nrhs, out);
+}
+void launch_seg_update_xr(int64_t ntot, int nrhs, const int32_t* pid, const double* rz, const double* pq,
+                          const int32_t* active, const double* p, const double* q, double* x, double* r, hipStream_t s) {
+  hipLaunchKernelGGL(k_seg_update_xr, dim3((ntot + 255) / 256), dim3(256), 0, s, ntot, nrhs, pid, rz, pq, active, p, q,
+                     x, r);
+}
+void launch_seg_update_p(int64_t ntot, int nrhs, const int32_t* pid, const double* rz_new, const double* rz,
+                         const int32_t* active, const double* z, double* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_seg_update_p, dim3((ntot + 255) / 256), dim3(256), 0, s, ntot, nrhs, pid, rz_new, rz, active,
+                     z, p);
 }
 void launch_dot(const double* a, const double* b, int64_t n, int nrhs, double* partial, int nblk, double* out,
                 hipStream_t s) {

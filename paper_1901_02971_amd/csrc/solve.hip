@@ -294,23 +294,6 @@ namespace spand {
 
 namespace {
 
-// Vectors and scalars of one problem of a batched solve, inside its handle's
-// workspace; the residual norms, true-residual norms, |b| and the active flags of
-// every problem live in shared arrays so that one copy moves them all.
-struct PcgVecs {
-  spand_ctx* h = nullptr;
-  const double* b = nullptr;
-  double* x = nullptr;
-  int64_t n = 0;
-  size_t vec = 0;
-  int nblk = 0;
-  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *partial = nullptr;
-  double *rz = nullptr, *rz_new = nullptr, *pq = nullptr, *scratch = nullptr;
-  double *rr = nullptr, *tt = nullptr, *bb = nullptr;  // in the shared arrays
-  int32_t* act = nullptr;                              // in the shared array
-  bool live = true;
-};
-
 // Capture fn(stream) on a private stream into an executable graph; false if the
 // runtime refuses.
 template <class F>
@@ -339,163 +322,347 @@ struct GraphExec {
   }
 };
 
+// Device memory of one batched solve, from the first handle's pool.
+spand_status pool_alloc(spand_ctx* h, DevBuf& b, size_t bytes) {
+  b.release();
+  if (bytes == 0) return SPAND_OK;
+  void* p = nullptr;
+  size_t cap = 0;
+  if (h->pool.get(bytes, &p, &cap) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_err(h, SPAND_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes for the batched solve failed");
+  }
+  b.p = p;
+  b.bytes = bytes;
+  b.cap = cap;
+  b.pool = &h->pool;
+  return SPAND_OK;
+}
+
+template <typename T>
+spand_status pool_upload(spand_ctx* h, DevBuf& b, const std::vector<T>& v) {
+  spand_status st = pool_alloc(h, b, v.size() * sizeof(T));
+  if (st != SPAND_OK || v.empty()) return st;
+  HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
+  return SPAND_OK;
+}
+
+// The apply of all problems of a batch as one: their vectors stacked (problem q in
+// rows off[q] ..), and the descriptors of step t of every problem concatenated, with
+// slot and neighbour-slot values shifted by the problem's row offset, offsets into
+// the slot arrays, the scratch and the descriptor arrays shifted by the sizes of the
+// earlier problems' parts.  Every descriptor still computes what it computes alone.
+struct MergedStep {
+  StepDev d{};
+  DevBuf slot, nslot, elim, target, contrib, scale, house, etile, stile, sgather, hr, hv, iface;
+};
+
+spand_status build_merged(spand_ctx* const* hs, int32_t P, const std::vector<int64_t>& off,
+                          std::vector<MergedStep>& out, int64_t& ldt, int64_t& ldg) {
+  spand_ctx* h = hs[0];
+  int32_t Lmax = 0;
+  for (int32_t q = 0; q < P; ++q) Lmax = std::max<int32_t>(Lmax, int32_t(hs[q]->num.size()));
+  out.clear();
+  out.resize(Lmax);
+  ldt = 1;
+  ldg = 1;
+  spand_status st = SPAND_OK;
+  for (int32_t t = 0; t < Lmax; ++t) {
+    std::vector<int32_t> slot, nslot, sgather;
+    std::vector<ElimAp> elim;
+    std::vector<TargetAp> target;
+    std::vector<TargetContrib> contrib;
+    std::vector<ScaleAp> scale;
+    std::vector<HouseAp> house;
+    std::vector<ElimTile> etile;
+    std::vector<ScaleTile> stile;
+    std::vector<HouseTile> hr, hv;
+    std::vector<IfaceAp> if1, if2;
+    int64_t te = 0, ts = 0;  // scratch rows of the elimination and of the scaling phase so far
+    for (int32_t q = 0; q < P; ++q) {
+      if (t >= int32_t(hs[q]->num.size())) continue;
+      const StepNum& sn = hs[q]->num[t];
+      const int64_t so = int64_t(slot.size()), no = int64_t(nslot.size());
+      const int32_t eo = int32_t(elim.size()), co = int32_t(contrib.size());
+      const int32_t sco = int32_t(scale.size()), ho = int32_t(house.size());
+      const int32_t v0 = int32_t(off[q]);
+      for (int32_t v : sn.slot) slot.push_back(v + v0);
+      for (ElimAp e : sn.h_elim) {
+        e.slot_s += so;
+        e.slot_N += no;
+        e.tmp += te;
+        elim.push_back(e);
+      }
+      for (TargetAp a : sn.h_target) {
+        a.cbeg += co;
+        a.cend += co;
+        a.slot_n += so;
+        target.push_back(a);
+      }
+      for (TargetContrib c : sn.h_contrib) {
+        c.tmp_s += te;
+        contrib.push_back(c);
+      }
+      for (ScaleAp a : sn.h_scale) {
+        a.slot_p += so;
+        a.tmp += ts;
+        scale.push_back(a);
+      }
+      for (HouseAp a : sn.h_house) {
+        a.slot_p += so;
+        a.tmp += ts;
+        house.push_back(a);
+      }
+      for (ElimTile e : sn.h_etile) {
+        e.s += eo;
+        etile.push_back(e);
+      }
+      for (ScaleTile s2 : sn.h_stile) {
+        s2.p += sco;
+        stile.push_back(s2);
+      }
+      for (HouseTile s2 : sn.h_hr) {
+        s2.p += ho;
+        hr.push_back(s2);
+      }
+      for (HouseTile s2 : sn.h_hv) {
+        s2.p += ho;
+        hv.push_back(s2);
+      }
+      for (int32_t k = 0; k < int32_t(sn.h_iface.size()); ++k) {
+        IfaceAp a = sn.h_iface[k];
+        a.slot_p += so;
+        (k < sn.n_iface1 ? if1 : if2).push_back(a);
+      }
+      // scratch rows of the scaled interfaces (gathered by row): this problem's rows at
+      // ts.., padded with row 0 of the stacked vector up to its scaling-phase scratch
+      sgather.resize(size_t(ts), v0);
+      for (int32_t v : sn.h_sgather) sgather.push_back(v + v0);
+      sgather.resize(size_t(ts + sn.tmp_scale), v0);
+      te += sn.tmp_elim;
+      ts += sn.tmp_scale;
+      // the neighbour slots of the step's eliminated clusters (gathered rows of gbuf)
+      nslot.insert(nslot.end(), sn.h_nslot.begin(), sn.h_nslot.end());
+      for (int64_t k = no; k < int64_t(nslot.size()); ++k) nslot[k] += v0;
+    }
+    ldt = std::max(ldt, std::max(te, ts));
+    ldg = std::max<int64_t>(ldg, int64_t(nslot.size()));
+    MergedStep& m = out[t];
+    if ((st = pool_upload(h, m.slot, slot)) != SPAND_OK) return st;
+    if ((st = pool_upload(h, m.nslot, nslot)) != SPAND_OK) return st;
+    if ((st = pool_upload(h, m.elim, elim)) != SPAND_OK) return st;
+    if ((st = pool_upload(h, m.target, target)) != SPAND_OK) return st;
+    if ((st = pool_upload(h, m.contrib, contrib)) != SPAND_OK) return st;
+    if ((st = pool_upload(h, m.scale, scale)) != SPAND_OK) return st;
+    if ((st = pool_upload(h, m.house, house)) != SPAND_OK) return st;
+    if ((st = pool_upload(h, m.etile, etile)) != SPAND_OK) return st;
+    if ((st = pool_upload(h, m.stile, stile)) != SPAND_OK) return st;
+    if ((st = pool_upload(h, m.sgather, sgather)) != SPAND_OK) return st;
+    if ((st = pool_upload(h, m.hr, hr)) != SPAND_OK) return st;
+    if ((st = pool_upload(h, m.hv, hv)) != SPAND_OK) return st;
+    std::vector<IfaceAp> ifs(if1);
+    ifs.insert(ifs.end(), if2.begin(), if2.end());
+    if ((st = pool_upload(h, m.iface, ifs)) != SPAND_OK) return st;
+    StepDev& d = m.d;
+    d.elim = m.elim.as<ElimAp>();
+    d.target = m.target.as<TargetAp>();
+    d.contrib = m.contrib.as<TargetContrib>();
+    d.scale = m.scale.as<ScaleAp>();
+    d.house = m.house.as<HouseAp>();
+    d.etile = m.etile.as<ElimTile>();
+    d.n_etile = int32_t(etile.size());
+    d.stile = m.stile.as<ScaleTile>();
+    d.n_stile = int32_t(stile.size());
+    d.sgather = m.sgather.as<int32_t>();
+    d.sgather_len = int64_t(sgather.size());
+    d.hr = m.hr.as<HouseTile>();
+    d.hv = m.hv.as<HouseTile>();
+    d.n_hr = int32_t(hr.size());
+    d.n_hv = int32_t(hv.size());
+    d.iface = m.iface.as<IfaceAp>();
+    d.n_iface1 = int32_t(if1.size());
+    d.n_iface2 = int32_t(if2.size());
+    d.slot = m.slot.as<int32_t>();
+    d.nslot = m.nslot.as<int32_t>();
+    d.nslot_len = int64_t(nslot.size());
+    d.n_elim = int32_t(elim.size());
+    d.n_target = int32_t(target.size());
+    d.n_scale = int32_t(scale.size());
+    d.n_house = int32_t(house.size());
+  }
+  return SPAND_OK;
+}
+
 }  // namespace
 
-// PCG on P problems in lockstep on the stream of hs[0] (every handle's stream is
-// that one): each half of an iteration, for every problem, is one captured graph
-// (the first: SpMV, p.q, x and r updates, r.r; the second: the preconditioner apply,
-// r.z, p update), replayed each iteration; the host reads every residual norm with
-// one copy per iteration and retires converged columns through device-side flags.
+// PCG on P problems as one block-diagonal system on the stream of hs[0] (every
+// handle's stream is that one): the vectors of all problems stacked, one SpMV per
+// problem, every other vector kernel and every apply kernel one launch for the batch
+// (scalars per problem and column).  Each half of an iteration is one captured graph
+// replayed every iteration; one copy per iteration brings every residual norm to the
+// host, which retires converged columns through device-side flags.  The arithmetic
+// of every problem (dot-product order included) is that of its own solve.
 spand_status pcg_solve_batch(spand_ctx* const* hs, int32_t P, int32_t nrhs, const double* const* b,
                              double* const* x, double rtol, int32_t maxit, int32_t* iters, double* relres,
                              spand_status* per) {
   spand_ctx* h = hs[0];
   const hipStream_t s = h->stream;
   const size_t scal = size_t(nrhs);
+  const size_t ps = size_t(P) * scal;
   spand_status st = SPAND_OK;
-  // shared arrays: rr, tt, bb (doubles) and act (ints), P * nrhs each
-  DevBuf shared;
-  {
-    void* p = nullptr;
-    size_t cap = 0;
-    const size_t bytes = 3 * size_t(P) * scal * sizeof(double) + size_t(P) * scal * sizeof(int32_t);
-    if (h->pool.get(bytes, &p, &cap) != hipSuccess) {
-      (void)hipGetLastError();
-      return set_err(h, SPAND_E_NOMEM, "device allocation of the batched solve's shared scalars failed");
-    }
-    shared.p = p;
-    shared.bytes = bytes;
-    shared.cap = cap;
-    shared.pool = &h->pool;
+  std::vector<int64_t> off(P + 1, 0), n(P);
+  for (int32_t q = 0; q < P; ++q) {
+    n[q] = hs[q]->an.n;
+    off[q + 1] = off[q] + n[q];
+    per[q] = SPAND_OK;
   }
-  double* rr_all = shared.as<double>();
-  double* tt_all = rr_all + size_t(P) * scal;
-  double* bb_all = tt_all + size_t(P) * scal;
-  int32_t* act_all = reinterpret_cast<int32_t*>(bb_all + size_t(P) * scal);
-  std::vector<PcgVecs> V(P);
-  for (int32_t k = 0; k < P; ++k) {
-    PcgVecs& v = V[k];
-    spand_ctx* hq = hs[k];
-    v.h = hq;
-    v.b = b[k];
-    v.x = x[k];
-    v.n = hq->an.n;
-    v.vec = size_t(v.n) * scal;
-    v.nblk = int(std::min<int64_t>((v.n + 255) / 256, 1024));
-    const size_t doubles = 4 * v.vec + size_t(v.nblk) * scal + 4 * scal + apply_scratch_doubles(hq, nrhs) + 16;
-    if ((st = ensure_work(hq, doubles * sizeof(double))) != SPAND_OK) {
-      per[k] = st;
-      return st;
-    }
-    double* w = hq->work.as<double>();
-    v.r = w;
-    v.z = v.r + v.vec;
-    v.p = v.z + v.vec;
-    v.q = v.p + v.vec;
-    v.partial = v.q + v.vec;
-    v.rz = v.partial + size_t(v.nblk) * scal;
-    v.rz_new = v.rz + scal;
-    v.pq = v.rz_new + scal;
-    v.scratch = v.pq + 2 * scal;
-    v.rr = rr_all + size_t(k) * scal;
-    v.tt = tt_all + size_t(k) * scal;
-    v.bb = bb_all + size_t(k) * scal;
-    v.act = act_all + size_t(k) * scal;
+  const int64_t ntot = off[P];
+  if (ntot > INT32_MAX) return set_err(h, SPAND_E_INVALID, "the batch has more than 2^31 unknowns in all");
+  const size_t vec = size_t(ntot) * scal;
+  // segmented dot products: problem q keeps its own block count
+  std::vector<SegBlk> blks;
+  std::vector<int64_t> pbase(P);
+  std::vector<int32_t> nblk(P), pid(ntot);
+  for (int32_t q = 0; q < P; ++q) {
+    nblk[q] = int32_t(std::min<int64_t>((n[q] + 255) / 256, 1024));
+    pbase[q] = int64_t(blks.size());
+    for (int32_t k = 0; k < nblk[q]; ++k) blks.push_back(SegBlk{off[q], n[q], k, nblk[q]});
+    std::fill(pid.begin() + off[q], pid.begin() + off[q + 1], q);
   }
-  std::vector<double> hr(size_t(P) * scal), ht(size_t(P) * scal), hb(size_t(P) * scal);
-  std::vector<int32_t> act(size_t(P) * scal, 0);
-  std::vector<char> broke(P, 0);
+  const int64_t nb_tot = int64_t(blks.size());
+  std::vector<MergedStep> steps;
+  int64_t ldt = 1, ldg = 1;
+  if ((st = build_merged(hs, P, off, steps, ldt, ldg)) != SPAND_OK) return st;
+  DevBuf vecs, scalars, dblks, dpbase, dnblk, dpid, dact;
+  const size_t nvec = 6;  // r, z, p, q, x, b
+  if ((st = pool_alloc(h, vecs, (nvec * vec + size_t(ldt + ldg) * scal) * sizeof(double))) != SPAND_OK) return st;
+  if ((st = pool_alloc(h, scalars, (size_t(nb_tot) * scal + 7 * ps) * sizeof(double))) != SPAND_OK) return st;
+  if ((st = pool_upload(h, dblks, blks)) != SPAND_OK) return st;
+  if ((st = pool_upload(h, dpbase, pbase)) != SPAND_OK) return st;
+  if ((st = pool_upload(h, dnblk, nblk)) != SPAND_OK) return st;
+  if ((st = pool_upload(h, dpid, pid)) != SPAND_OK) return st;
+  if ((st = pool_alloc(h, dact, ps * sizeof(int32_t))) != SPAND_OK) return st;
+  double* R = vecs.as<double>();
+  double* Z = R + vec;
+  double* Pv = Z + vec;
+  double* Q = Pv + vec;
+  double* X = Q + vec;
+  double* B = X + vec;
+  double* TMP = B + vec;
+  double* GB = TMP + size_t(ldt) * scal;
+  double* partial = scalars.as<double>();
+  double* bb = partial + size_t(nb_tot) * scal;
+  double* rz = bb + ps;
+  double* rz_new = rz + ps;
+  double* pq = rz_new + ps;
+  double* rr = pq + ps;
+  double* tt = rr + ps;
+  int32_t* act_d = dact.as<int32_t>();
+  const SegBlk* SB = dblks.as<SegBlk>();
+  const int64_t* PB = dpbase.as<int64_t>();
+  const int32_t* NB = dnblk.as<int32_t>();
+  const int32_t* PID = dpid.as<int32_t>();
+  for (int32_t q = 0; q < P; ++q)
+    for (int c = 0; c < nrhs; ++c)
+      HIPCHK(hipMemcpyAsync(B + off[q] + size_t(c) * ntot, b[q] + size_t(c) * n[q], size_t(n[q]) * sizeof(double),
+                            hipMemcpyDeviceToDevice, s));
+  auto dot = [&](const double* u, const double* v, double* outp, hipStream_t cs) {
+    launch_seg_dot(u, v, ntot, nrhs, SB, nb_tot, PB, NB, P, partial, outp, cs);
+  };
+  auto spmv_all = [&](const double* xin, double* yout, hipStream_t cs) {
+    for (int32_t q = 0; q < P; ++q) {
+      spand_ctx* hq = hs[q];
+      launch_spmv(hq->d_rowptr.as<int64_t>(), hq->d_colind.as<int32_t>(), hq->d_values.as<double>(), n[q], nrhs,
+                  xin + off[q], yout + off[q], cs, ntot);
+    }
+  };
+  // z = M M^T r for the stacked vector: the merged steps forward, then backward
+  auto apply_all = [&](hipStream_t cs) {
+    launch_copy_vec(R, Z, int64_t(vec), cs);
+    ApplyArgs a{};
+    a.x = Z;
+    a.ldx = ntot;
+    a.nrhs = nrhs;
+    a.tmp = TMP;
+    a.ldt = ldt;
+    a.gbuf = GB;
+    a.ldg = ldg;
+    for (size_t t = 0; t < steps.size(); ++t) {
+      a.slot = steps[t].d.slot;
+      apply_step_forward(steps[t].d, a, cs);
+    }
+    for (size_t t = steps.size(); t-- > 0;) {
+      a.slot = steps[t].d.slot;
+      apply_step_backward(steps[t].d, a, cs);
+    }
+  };
+  std::vector<double> hr(ps), ht(ps), hb(ps);
+  std::vector<int32_t> act(ps, 0);
+  std::vector<char> broke(P, 0), live(P, 1);
   std::vector<int64_t> replaced(P, 0);
-  for (int32_t k = 0; k < P; ++k) {
-    const PcgVecs& v = V[k];
-    launch_dot(v.b, v.b, v.n, nrhs, v.partial, v.nblk, v.bb, s);
-  }
+  dot(B, B, bb, s);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipMemcpyAsync(hb.data(), bb_all, hb.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hb.data(), bb, ps * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  for (int32_t k = 0; k < P; ++k) {
-    per[k] = SPAND_OK;
+  for (int32_t q = 0; q < P; ++q) {
     for (int c = 0; c < nrhs; ++c) {
-      const size_t o = size_t(k) * scal + c;
+      const size_t o = size_t(q) * scal + c;
       iters[o] = 0;
-      if (!std::isfinite(hb[o])) {
-        per[k] = set_err(hs[k], SPAND_E_INVALID, "right-hand side contains NaN or Inf");
-        V[k].live = false;
+      if (!std::isfinite(hb[o]) && live[q]) {
+        per[q] = set_err(hs[q], SPAND_E_INVALID, "right-hand side contains NaN or Inf");
+        live[q] = 0;
       }
       hb[o] = std::sqrt(hb[o]);
     }
     for (int c = 0; c < nrhs; ++c) {
-      const size_t o = size_t(k) * scal + c;
-      act[o] = (V[k].live && hb[o] > 0.0) ? 1 : 0;
+      const size_t o = size_t(q) * scal + c;
+      act[o] = (live[q] && hb[o] > 0.0) ? 1 : 0;
     }
   }
-  for (int32_t k = 0; k < P; ++k) {
-    const PcgVecs& v = V[k];
-    HIPCHK(hipMemsetAsync(v.x, 0, v.vec * sizeof(double), s));
-    launch_copy_vec(v.b, v.r, int64_t(v.vec), s);
-  }
-  HIPCHK(hipMemcpyAsync(act_all, act.data(), act.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  HIPCHK(hipGetLastError());
-  // the two halves of an iteration, for every live problem
+  HIPCHK(hipMemsetAsync(X, 0, vec * sizeof(double), s));
+  launch_copy_vec(B, R, int64_t(vec), s);
+  HIPCHK(hipMemcpyAsync(act_d, act.data(), ps * sizeof(int32_t), hipMemcpyHostToDevice, s));
   auto half1 = [&](hipStream_t cs) {
-    for (const PcgVecs& v : V) {
-      if (!v.live) continue;
-      launch_spmv(v.h->d_rowptr.as<int64_t>(), v.h->d_colind.as<int32_t>(), v.h->d_values.as<double>(), v.n, nrhs,
-                  v.p, v.q, cs);
-      launch_dot(v.p, v.q, v.n, nrhs, v.partial, v.nblk, v.pq, cs);
-      launch_update_xr(v.n, nrhs, v.rz, v.pq, v.act, v.p, v.q, v.x, v.r, cs);
-      launch_dot(v.r, v.r, v.n, nrhs, v.partial, v.nblk, v.rr, cs);
-    }
+    spmv_all(Pv, Q, cs);
+    dot(Pv, Q, pq, cs);
+    launch_seg_update_xr(ntot, nrhs, PID, rz, pq, act_d, Pv, Q, X, R, cs);
+    dot(R, R, rr, cs);
     return hipGetLastError() == hipSuccess;
   };
-  auto applies = [&](hipStream_t cs) {
-    for (const PcgVecs& v : V)
-      if (v.live && apply_precond(v.h, nrhs, v.r, v.z, v.scratch, cs) != SPAND_OK) return false;
-    return true;
-  };
   auto half2 = [&](hipStream_t cs) {
-    if (!applies(cs)) return false;
-    for (const PcgVecs& v : V) {
-      if (!v.live) continue;
-      launch_dot(v.r, v.z, v.n, nrhs, v.partial, v.nblk, v.rz_new, cs);
-      launch_update_p(v.n, nrhs, v.rz_new, v.rz, v.act, v.z, v.p, cs);
-      launch_copy_vec(v.rz_new, v.rz, int64_t(nrhs), cs);
-    }
+    apply_all(cs);
+    dot(R, Z, rz_new, cs);
+    launch_seg_update_p(ntot, nrhs, PID, rz_new, rz, act_d, Z, Pv, cs);
+    launch_copy_vec(rz_new, rz, int64_t(ps), cs);
     return hipGetLastError() == hipSuccess;
   };
   GraphExec g1, g2;
   const bool graphs = h->apply_graph && capture(half1, &g1.g) && capture(half2, &g2.g);
   EventPool evpool;
-  size_t nhalf2 = 0;
-  auto run_half2 = [&]() -> spand_status {
+  size_t napply = 0;
+  auto run_apply = [&](bool with_rest) -> spand_status {
     hipEvent_t e0, e1;
-    HIPCHK(evpool.get(2 * nhalf2, &e0));
-    HIPCHK(evpool.get(2 * nhalf2 + 1, &e1));
+    HIPCHK(evpool.get(2 * napply, &e0));
+    HIPCHK(evpool.get(2 * napply + 1, &e1));
     HIPCHK(hipEventRecord(e0, s));
-    if (graphs) {
-      HIPCHK(hipGraphLaunch(g2.g, s));
-    } else if (!half2(s)) {
-      return set_err(h, SPAND_E_HIP, "batched PCG: apply launch failed");
+    if (with_rest) {
+      if (graphs) {
+        HIPCHK(hipGraphLaunch(g2.g, s));
+      } else if (!half2(s)) {
+        return set_err(h, SPAND_E_HIP, "batched PCG: launch failed");
+      }
+    } else {
+      apply_all(s);
     }
     HIPCHK(hipEventRecord(e1, s));
-    ++nhalf2;
+    ++napply;
     return SPAND_OK;
   };
   bool any = std::any_of(act.begin(), act.end(), [](int32_t a) { return a != 0; });
-  if (any) {
-    // z = M M^T r, p = z, rz = r.z
-    hipEvent_t e0, e1;
-    HIPCHK(evpool.get(2 * nhalf2, &e0));
-    HIPCHK(evpool.get(2 * nhalf2 + 1, &e1));
-    HIPCHK(hipEventRecord(e0, s));
-    if (!applies(s)) return set_err(h, SPAND_E_HIP, "batched PCG: apply launch failed");
-    HIPCHK(hipEventRecord(e1, s));
-    ++nhalf2;
-    for (const PcgVecs& v : V) {
-      if (!v.live) continue;
-      launch_copy_vec(v.z, v.p, int64_t(v.vec), s);
-      launch_dot(v.r, v.z, v.n, nrhs, v.partial, v.nblk, v.rz, s);
-    }
+  if (any) {  // z = M M^T r, p = z, rz = r.z
+    if ((st = run_apply(false)) != SPAND_OK) return st;
+    launch_copy_vec(Z, Pv, int64_t(vec), s);
+    dot(R, Z, rz, s);
     HIPCHK(hipGetLastError());
   }
   int32_t it = 0;
@@ -505,93 +672,84 @@ spand_status pcg_solve_batch(spand_ctx* const* hs, int32_t P, int32_t nrhs, cons
     } else if (!half1(s)) {
       return set_err(h, SPAND_E_HIP, "batched PCG: launch failed");
     }
-    HIPCHK(hipMemcpyAsync(hr.data(), rr_all, hr.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hr.data(), rr, ps * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     ++it;
-    std::vector<int32_t> check;
-    for (int32_t k = 0; k < P; ++k) {
-      bool need = false;
+    bool check = false;
+    for (int32_t q = 0; q < P; ++q)
       for (int c = 0; c < nrhs; ++c) {
-        const size_t o = size_t(k) * scal + c;
+        const size_t o = size_t(q) * scal + c;
         if (!act[o]) continue;
         iters[o] = it;
         if (!std::isfinite(hr[o])) {
           act[o] = 0;
-          broke[k] = 1;
+          broke[q] = 1;
         } else if (std::sqrt(hr[o]) <= rtol * hb[o]) {
-          need = true;
+          check = true;
         }
       }
-      if (need) check.push_back(k);
-    }
-    if (!check.empty()) {  // true residuals of the problems with a column whose recursive residual passed
-      for (int32_t k : check) {
-        const PcgVecs& v = V[k];
-        launch_spmv(v.h->d_rowptr.as<int64_t>(), v.h->d_colind.as<int32_t>(), v.h->d_values.as<double>(), v.n, nrhs,
-                    v.x, v.q, s);
-        launch_residual(int64_t(v.vec), v.b, v.q, s);
-        launch_dot(v.q, v.q, v.n, nrhs, v.partial, v.nblk, v.tt, s);
-      }
+    if (check) {  // true residuals (every problem: one SpMV launch per problem is cheap here)
+      spmv_all(X, Q, s);
+      launch_residual(int64_t(vec), B, Q, s);
+      dot(Q, Q, tt, s);
       HIPCHK(hipGetLastError());
-      HIPCHK(hipMemcpyAsync(ht.data(), tt_all, ht.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(ht.data(), tt, ps * sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      for (int32_t k : check) {
-        const PcgVecs& v = V[k];
+      for (int32_t q = 0; q < P; ++q)
         for (int c = 0; c < nrhs; ++c) {
-          const size_t o = size_t(k) * scal + c;
+          const size_t o = size_t(q) * scal + c;
           if (!act[o] || !std::isfinite(hr[o]) || std::sqrt(hr[o]) > rtol * hb[o]) continue;
           if (std::sqrt(ht[o]) <= rtol * hb[o]) {
             act[o] = 0;
           } else {  // the recursive residual drifted: continue from the true one
-            HIPCHK(hipMemcpyAsync(v.r + size_t(c) * v.n, v.q + size_t(c) * v.n, size_t(v.n) * sizeof(double),
-                                  hipMemcpyDeviceToDevice, s));
-            ++replaced[k];
+            HIPCHK(hipMemcpyAsync(R + off[q] + size_t(c) * ntot, Q + off[q] + size_t(c) * ntot,
+                                  size_t(n[q]) * sizeof(double), hipMemcpyDeviceToDevice, s));
+            ++replaced[q];
           }
         }
-      }
     }
     any = std::any_of(act.begin(), act.end(), [](int32_t a) { return a != 0; });
     if (!any || it >= maxit) break;
-    HIPCHK(hipMemcpyAsync(act_all, act.data(), act.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    if ((st = run_half2()) != SPAND_OK) return st;
+    HIPCHK(hipMemcpyAsync(act_d, act.data(), ps * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if ((st = run_apply(true)) != SPAND_OK) return st;
   }
-  // true residuals
-  for (const PcgVecs& v : V) {
-    if (!v.live) continue;
-    launch_spmv(v.h->d_rowptr.as<int64_t>(), v.h->d_colind.as<int32_t>(), v.h->d_values.as<double>(), v.n, nrhs,
-                v.x, v.q, s);
-    launch_residual(int64_t(v.vec), v.b, v.q, s);
-    launch_dot(v.q, v.q, v.n, nrhs, v.partial, v.nblk, v.tt, s);
-  }
+  // true residuals and the solutions back to the callers' arrays
+  spmv_all(X, Q, s);
+  launch_residual(int64_t(vec), B, Q, s);
+  dot(Q, Q, tt, s);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipMemcpyAsync(ht.data(), tt_all, ht.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  for (int32_t q = 0; q < P; ++q)
+    for (int c = 0; c < nrhs; ++c)
+      HIPCHK(hipMemcpyAsync(x[q] + size_t(c) * n[q], X + off[q] + size_t(c) * ntot, size_t(n[q]) * sizeof(double),
+                            hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(ht.data(), tt, ps * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   double apply_ms = 0.0;
-  for (size_t q = 0; q < nhalf2; ++q) {
+  for (size_t q = 0; q < napply; ++q) {
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, evpool.ev[2 * q], evpool.ev[2 * q + 1]));
     apply_ms += ms;
   }
-  for (int32_t k = 0; k < P; ++k) {
-    spand_ctx* hq = hs[k];
+  for (int32_t q = 0; q < P; ++q) {
+    spand_ctx* hq = hs[q];
     bool noconv = false;
     hq->stats.last_iters = 0;
     for (int c = 0; c < nrhs; ++c) {
-      const size_t o = size_t(k) * scal + c;
-      relres[o] = (V[k].live && hb[o] > 0.0) ? std::sqrt(ht[o]) / hb[o] : 0.0;
+      const size_t o = size_t(q) * scal + c;
+      relres[o] = (live[q] && hb[o] > 0.0) ? std::sqrt(ht[o]) / hb[o] : 0.0;
       if (act[o]) noconv = true;
       hq->stats.last_iters = std::max(hq->stats.last_iters, iters[o]);
     }
-    hq->stats.apply_seconds = apply_ms * 1e-3;  // the shared second halves (applies of every problem)
-    hq->stats.apply_calls = int64_t(nhalf2);
+    hq->stats.apply_seconds = apply_ms * 1e-3;  // the shared applies (with the second half of each iteration)
+    hq->stats.apply_calls = int64_t(napply);
     hq->stats.apply_graph = graphs ? 1 : 0;
     hq->stats.apply_bytes = 16.0 * double(hq->stats.m_F) + 4.0 * 8.0 * double(hq->an.n) * nrhs;
-    hq->stats.pcg_replacements = replaced[k];
-    if (per[k] != SPAND_OK) continue;
-    if (broke[k])
-      per[k] = set_err(hq, SPAND_E_BREAKDOWN, "PCG breakdown: non-finite residual");
+    hq->stats.pcg_replacements = replaced[q];
+    if (per[q] != SPAND_OK) continue;
+    if (broke[q])
+      per[q] = set_err(hq, SPAND_E_BREAKDOWN, "PCG breakdown: non-finite residual");
     else if (noconv)
-      per[k] = set_err(hq, SPAND_E_NOCONV, "PCG reached maxit = " + std::to_string(maxit));
+      per[q] = set_err(hq, SPAND_E_NOCONV, "PCG reached maxit = " + std::to_string(maxit));
   }
   return SPAND_OK;
 }
