@@ -104,6 +104,24 @@ struct SegBlk {
   int64_t off, n;
   int32_t local, nblk;
 };
+// One problem of a stacked system: its CSR (local indices) and its first row.
+struct SpmvProb {
+  const int64_t* rowptr;
+  const int32_t* colind;
+  const double* val;
+  int64_t n, off;
+};
+// One problem's own vector block (leading dimension n) and its first stacked row.
+struct StackProb {
+  const double* own_in;
+  double* own_out;
+  int64_t n, off;
+};
+// blk[k] = (problem, 256-row block) of workgroup k.
+void launch_spmv_batch(const SpmvProb* probs, const int2* blk, int64_t nblk, int nrhs, int64_t ld, const double* x,
+                       double* y, hipStream_t s);
+void launch_stack(const StackProb* probs, const int2* blk, int64_t nblk, int nrhs, int64_t ld, double* stacked,
+                  bool to_stack, hipStream_t s);
 void launch_seg_dot(const double* a, const double* b, int64_t ld, int nrhs, const SegBlk* blks, int64_t nb_tot,
                     const int64_t* pbase, const int32_t* nblk, int32_t P, double* partial, double* out, hipStream_t s);
 void launch_seg_update_xr(int64_t ntot, int nrhs, const int32_t* pid, const double* rz, const double* pq,

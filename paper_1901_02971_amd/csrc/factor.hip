@@ -779,6 +779,11 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
     // ---- sizes, slots, layout and assembly of every problem
     HIPCHK(hipEventRecord(ph[0], h->stream));
     std::vector<CopyDesc> copies;
+    std::vector<ZeroDesc> zeros;  // the new step buffers of every problem, zeroed in one launch
+    std::vector<Prob*> scatters;  // step 1: the CSR values go in after the fill
+    auto add_zero = [&](double* p0, int64_t len) {
+      for (int64_t o = 0; o < len; o += ZERO_CHUNK) zeros.push_back(ZeroDesc{p0 + o, std::min<int64_t>(ZERO_CHUNK, len - o)});
+    };
     for (Prob* pp : act) {
       Prob& pb = *pp;
       spand_ctx* hq = pb.h;
@@ -796,8 +801,8 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
       if ((st = dalloc(hq, pb.arena, size_t(lay.total_arena) * sizeof(double))) != SPAND_OK) return st;
       double* E = sn.elim.as<double>();
       double* A = pb.arena.as<double>();
-      if (lay.total_elim) HIPCHK(hipMemsetAsync(E, 0, size_t(lay.total_elim) * sizeof(double), h->stream));
-      if (lay.total_arena) HIPCHK(hipMemsetAsync(A, 0, size_t(lay.total_arena) * sizeof(double), h->stream));
+      add_zero(E, lay.total_elim);
+      add_zero(A, lay.total_arena);
       if (t == 1) {
         if (!hq->d_dst1.p) {
           // destination of every CSR entry inside the step-1 panels (it depends on the
@@ -821,12 +826,22 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
             }
           if ((st = upload(hq, hq->d_dst1, dst)) != SPAND_OK) return st;
         }
-        launch_scatter_values(pb.values, hq->d_dst1.as<int64_t>(), int64_t(hq->an.colind.size()), A, E, pb.flags + 2,
-                              h->stream);
-        HIPCHK(hipGetLastError());
+        scatters.push_back(pp);
       } else {
         plan_merge(sy, hq->num[t - 2], lay, pb.lay_prev, E, A, pb.arena_prev.as<double>(), copies);
       }
+    }
+    if (!zeros.empty()) {
+      DevBuf dz;
+      if ((st = upload_big(h, dz, zeros)) != SPAND_OK) return st;
+      launch_zero(dz.as<ZeroDesc>(), int64_t(zeros.size()), h->stream);
+      HIPCHK(hipGetLastError());
+    }
+    for (Prob* pp : scatters) {
+      spand_ctx* hq = pp->h;
+      launch_scatter_values(pp->values, hq->d_dst1.as<int64_t>(), int64_t(hq->an.colind.size()), pp->arena.as<double>(),
+                            hq->num[0].elim.as<double>(), pp->flags + 2, h->stream);
+      HIPCHK(hipGetLastError());
     }
     if (!copies.empty()) {
       DevBuf d_copy;

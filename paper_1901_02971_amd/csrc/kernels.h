@@ -81,6 +81,12 @@ struct IdentDesc {
   int32_t n, ld, c0, c1;
 };
 #define COPY_CHUNK 16384  // entries per workgroup of the copies and identity fills
+struct ZeroDesc {  // len (<= ZERO_CHUNK) doubles at p set to zero
+  double* p;
+  int64_t len;
+};
+#define ZERO_CHUNK 65536
+void launch_zero(const ZeroDesc* d, int64_t count, hipStream_t s);
 
 // Sparsification of one interface p (Sec. 2.6.1).  A_pn is held in the registers of
 // S workgroups (slabs) of CAP = cpqr_capacity(G) columns each.  The width of A_pn is

@@ -922,6 +922,66 @@ __global__ void k_seg_update_p(int64_t ntot, int nrhs, const int32_t* __restrict
   }
 }
 
+// y = A x for every problem of a stacked vector (leading dimension ld): one thread per
+// row, 256-row blocks of one problem each; the same per-row arithmetic as k_spmv.
+__global__ void __launch_bounds__(256) k_spmv_batch(const SpmvProb* __restrict__ probs, const int2* __restrict__ blk,
+                                                    int nrhs, int64_t ld, const double* __restrict__ x,
+                                                    double* __restrict__ y) {
+  const int2 bq = blk[blockIdx.x];
+  const SpmvProb pr = probs[bq.x];
+  const int64_t v = int64_t(bq.y) * 256 + threadIdx.x;
+  if (v >= pr.n) return;
+  const int64_t b = pr.rowptr[v], e = pr.rowptr[v + 1];
+  const double* xo = x + pr.off;
+  for (int c0 = 0; c0 < nrhs; c0 += RB) {
+    const int nr = min(RB, nrhs - c0);
+    const double* xc = xo + (int64_t)c0 * ld;
+    double s[RB];
+#pragma unroll
+    for (int c = 0; c < RB; ++c) s[c] = 0.0;
+    for (int64_t q = b; q < e; ++q) {
+      const double a = pr.val[q];
+      const int64_t col = pr.colind[q];
+#pragma unroll
+      for (int c = 0; c < RB; ++c)
+        if (c < nr) s[c] = fma(a, xc[col + (int64_t)c * ld], s[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < RB; ++c)
+      if (c < nr) y[pr.off + v + (int64_t)(c0 + c) * ld] = s[c];
+  }
+}
+
+// Copies between each problem's own n x nrhs block (leading dimension n) and its rows
+// of the stacked vector (leading dimension ld); TO_STACK selects the direction.
+template <bool TO_STACK>
+__global__ void k_stack(const StackProb* __restrict__ probs, const int2* __restrict__ blk, int nrhs, int64_t ld,
+                        double* __restrict__ stacked) {
+  const int2 bq = blk[blockIdx.x];
+  const StackProb pr = probs[bq.x];
+  const int64_t v = int64_t(bq.y) * 256 + threadIdx.x;
+  if (v >= pr.n) return;
+  for (int c = 0; c < nrhs; ++c) {
+    if (TO_STACK)
+      stacked[pr.off + v + (int64_t)c * ld] = pr.own_in[v + (int64_t)c * pr.n];
+    else
+      pr.own_out[v + (int64_t)c * pr.n] = stacked[pr.off + v + (int64_t)c * ld];
+  }
+}
+
+void launch_spmv_batch(const SpmvProb* probs, const int2* blk, int64_t nblk, int nrhs, int64_t ld, const double* x,
+                       double* y, hipStream_t s) {
+  if (nblk > 0) hipLaunchKernelGGL(k_spmv_batch, dim3(nblk), dim3(256), 0, s, probs, blk, nrhs, ld, x, y);
+}
+void launch_stack(const StackProb* probs, const int2* blk, int64_t nblk, int nrhs, int64_t ld, double* stacked,
+                  bool to_stack, hipStream_t s) {
+  if (nblk == 0) return;
+  if (to_stack)
+    hipLaunchKernelGGL(k_stack<true>, dim3(nblk), dim3(256), 0, s, probs, blk, nrhs, ld, stacked);
+  else
+    hipLaunchKernelGGL(k_stack<false>, dim3(nblk), dim3(256), 0, s, probs, blk, nrhs, ld, stacked);
+}
+
 void launch_seg_dot(const double* a, const double* b, int64_t ld, int nrhs, const SegBlk* blks, int64_t nb_tot,
                     const int64_t* pbase, const int32_t* nblk, int32_t P, double* partial, double* out,
                     hipStream_t s) {

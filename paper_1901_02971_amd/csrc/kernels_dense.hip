@@ -183,4 +183,16 @@ void launch_set_identity(const IdentDesc* d, int32_t count, hipStream_t s) {
   hipLaunchKernelGGL(k_set_identity, dim3(count), dim3(WG), 0, s, d);
 }
 
+// Zero fill of ranges of at most ZERO_CHUNK doubles, one workgroup each (the step
+// buffers of every problem of a factorization run in one launch).
+__global__ void __launch_bounds__(WG) k_zero(const ZeroDesc* __restrict__ descs) {
+  const ZeroDesc d = descs[blockIdx.x];
+  for (int64_t i = threadIdx.x; i < d.len; i += WG) d.p[i] = 0.0;
+}
+
+void launch_zero(const ZeroDesc* d, int64_t count, hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_zero, dim3(count), dim3(WG), 0, s, d);
+}
+
 }  // namespace spand

@@ -496,9 +496,9 @@ spand_status build_merged(spand_ctx* const* hs, int32_t P, const std::vector<int
 }  // namespace
 
 // PCG on P problems as one block-diagonal system on the stream of hs[0] (every
-// handle's stream is that one): the vectors of all problems stacked, one SpMV per
-// problem, every other vector kernel and every apply kernel one launch for the batch
-// (scalars per problem and column).  Each half of an iteration is one captured graph
+// handle's stream is that one): the vectors of all problems stacked, and every
+// vector, SpMV and apply kernel one launch for the batch (scalars per problem and
+// column).  Each half of an iteration is one captured graph
 // replayed every iteration; one copy per iteration brings every residual norm to the
 // host, which retires converged columns through device-side flags.  The arithmetic
 // of every problem (dot-product order included) is that of its own solve.
@@ -523,6 +523,17 @@ spand_status pcg_solve_batch(spand_ctx* const* hs, int32_t P, int32_t nrhs, cons
   std::vector<SegBlk> blks;
   std::vector<int64_t> pbase(P);
   std::vector<int32_t> nblk(P), pid(ntot);
+  // the batched SpMV and the stacking copies: 256-row blocks of every problem
+  std::vector<SpmvProb> sprobs(P);
+  std::vector<StackProb> bprobs(P), xprobs(P);
+  std::vector<int2> rblk;
+  for (int32_t q = 0; q < P; ++q) {
+    sprobs[q] = SpmvProb{hs[q]->d_rowptr.as<int64_t>(), hs[q]->d_colind.as<int32_t>(), hs[q]->d_values.as<double>(),
+                         n[q], off[q]};
+    bprobs[q] = StackProb{b[q], nullptr, n[q], off[q]};
+    xprobs[q] = StackProb{nullptr, x[q], n[q], off[q]};
+    for (int64_t k = 0; k * 256 < n[q]; ++k) rblk.push_back(make_int2(q, int(k)));
+  }
   for (int32_t q = 0; q < P; ++q) {
     nblk[q] = int32_t(std::min<int64_t>((n[q] + 255) / 256, 1024));
     pbase[q] = int64_t(blks.size());
@@ -533,7 +544,12 @@ spand_status pcg_solve_batch(spand_ctx* const* hs, int32_t P, int32_t nrhs, cons
   std::vector<MergedStep> steps;
   int64_t ldt = 1, ldg = 1;
   if ((st = build_merged(hs, P, off, steps, ldt, ldg)) != SPAND_OK) return st;
-  DevBuf vecs, scalars, dblks, dpbase, dnblk, dpid, dact;
+  DevBuf vecs, scalars, dblks, dpbase, dnblk, dpid, dact, dsp, dbp, dxp, drb;
+  if ((st = pool_upload(h, dsp, sprobs)) != SPAND_OK) return st;
+  if ((st = pool_upload(h, dbp, bprobs)) != SPAND_OK) return st;
+  if ((st = pool_upload(h, dxp, xprobs)) != SPAND_OK) return st;
+  if ((st = pool_upload(h, drb, rblk)) != SPAND_OK) return st;
+  const int64_t nrb = int64_t(rblk.size());
   const size_t nvec = 6;  // r, z, p, q, x, b
   if ((st = pool_alloc(h, vecs, (nvec * vec + size_t(ldt + ldg) * scal) * sizeof(double))) != SPAND_OK) return st;
   if ((st = pool_alloc(h, scalars, (size_t(nb_tot) * scal + 7 * ps) * sizeof(double))) != SPAND_OK) return st;
@@ -562,19 +578,12 @@ spand_status pcg_solve_batch(spand_ctx* const* hs, int32_t P, int32_t nrhs, cons
   const int64_t* PB = dpbase.as<int64_t>();
   const int32_t* NB = dnblk.as<int32_t>();
   const int32_t* PID = dpid.as<int32_t>();
-  for (int32_t q = 0; q < P; ++q)
-    for (int c = 0; c < nrhs; ++c)
-      HIPCHK(hipMemcpyAsync(B + off[q] + size_t(c) * ntot, b[q] + size_t(c) * n[q], size_t(n[q]) * sizeof(double),
-                            hipMemcpyDeviceToDevice, s));
+  launch_stack(dbp.as<StackProb>(), drb.as<int2>(), nrb, nrhs, ntot, B, true, s);
   auto dot = [&](const double* u, const double* v, double* outp, hipStream_t cs) {
     launch_seg_dot(u, v, ntot, nrhs, SB, nb_tot, PB, NB, P, partial, outp, cs);
   };
   auto spmv_all = [&](const double* xin, double* yout, hipStream_t cs) {
-    for (int32_t q = 0; q < P; ++q) {
-      spand_ctx* hq = hs[q];
-      launch_spmv(hq->d_rowptr.as<int64_t>(), hq->d_colind.as<int32_t>(), hq->d_values.as<double>(), n[q], nrhs,
-                  xin + off[q], yout + off[q], cs, ntot);
-    }
+    launch_spmv_batch(dsp.as<SpmvProb>(), drb.as<int2>(), nrb, nrhs, ntot, xin, yout, cs);
   };
   // z = M M^T r for the stacked vector: the merged steps forward, then backward
   auto apply_all = [&](hipStream_t cs) {
@@ -718,10 +727,8 @@ spand_status pcg_solve_batch(spand_ctx* const* hs, int32_t P, int32_t nrhs, cons
   launch_residual(int64_t(vec), B, Q, s);
   dot(Q, Q, tt, s);
   HIPCHK(hipGetLastError());
-  for (int32_t q = 0; q < P; ++q)
-    for (int c = 0; c < nrhs; ++c)
-      HIPCHK(hipMemcpyAsync(x[q] + size_t(c) * n[q], X + off[q] + size_t(c) * ntot, size_t(n[q]) * sizeof(double),
-                            hipMemcpyDeviceToDevice, s));
+  launch_stack(dxp.as<StackProb>(), drb.as<int2>(), nrb, nrhs, ntot, X, false, s);
+  HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(ht.data(), tt, ps * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   double apply_ms = 0.0;
