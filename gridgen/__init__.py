@@ -230,7 +230,20 @@ def config_problem(name: str):
         return batched_problem(int(name[3:]))
     if name.startswith("x4_"):
         return sweep_problem(name)
+    if name.startswith("x1_"):
+        return contrast2d_problem(name)
     raise KeyError(name)
+
+
+def contrast2d_problem(name: str):
+    """A point of the 2D variant comparison of Sec. 4.1.1: "x1_<n>_rho<rho>" is the
+    n x n 5-point operator with the high-contrast field of contrast rho (rho = 1: the
+    Laplacian), seed 1000 + n, one RHS from seed 7, depth 1 + ceil(log2(n^2 / 512))."""
+    body = name[3:]
+    n_s, rho_s = body.split("_rho")
+    n, rho = int(n_s), float(rho_s)
+    p = high_contrast((n, n), np.random.default_rng(1000 + n), rho)
+    return p, rhs(np.random.default_rng(7), p.n, 1), levels_for(p.n)
 
 
 def sweep_problem(name: str):

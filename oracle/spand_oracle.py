@@ -1,4 +1,4 @@
-"""Plain FP64 CPU oracle for sparsified nested dissection (spaND, OrthS variant).
+"""Plain FP64 CPU oracle for sparsified nested dissection (spaND: OrthS, In, InS).
 
 TEST INFRASTRUCTURE ONLY.  Nothing in the product library imports, links or runs
 this module; only the tests, the smoke check and the CPU-baseline leg of the
@@ -17,7 +17,9 @@ Contents, each following the cited passage:
                       block pattern of the trailing matrix with the fill of Sec. 2.4.
   * ``factor``        Algorithm 3 (OrthS): elimination (Sec. 2.4), block scaling
                       (Sec. 2.5), orthogonal sparsification (Sec. 2.6.1) with the
-                      truncation rule of Sec. 4 (intro), merge (Sec. 2.7).
+                      truncation rule of Sec. 4 (intro), merge (Sec. 2.7); and the
+                      interpolative variants In (no scaling) and InS (scaling) of
+                      Sec. 2.6.2 / Sec. 3.1.
   * ``apply``         z = M M^T r with M from Sec. 2.8 (operator order of the
                       caption of the spaND illustration figure).
   * ``pcg``           CG preconditioned by M M^T, stopped at ||b-Ax||/||b|| <= rtol (Sec. 4).
@@ -41,6 +43,10 @@ from scipy.linalg import solve_triangular
 # geqp3, whose idamax takes the first maximum).
 TIE_RTOL = 1e-10
 TIE_RULES = ("original", "position")
+
+# Sparsification variants compared in Sec. 3.1 / Sec. 4.1: orthogonal with block
+# scaling (the method), interpolative without and with block scaling.
+VARIANTS = ("OrthS", "In", "InS")
 
 
 class NotSPD(Exception):
@@ -458,6 +464,7 @@ class StepFactor:
     E: list = field(default_factory=list)   # (slots_s, L_s, [(slots_n, G_ns)])
     S: list = field(default_factory=list)   # (slots_p, L_p)
     Q: list = field(default_factory=list)   # (slots_p, V, tau)
+    I: list = field(default_factory=list)   # (slots_p, perm, r, T_cf, L_f, G_cf): interpolative
     ranks: dict = field(default_factory=dict)   # cluster id -> kept size after sparsification
     sizes: list = field(default_factory=list)   # cluster sizes before elimination
 
@@ -505,7 +512,7 @@ def _get(blocks, i, j):
     return blocks[(j, i)].T
 
 
-def factor(an: Analysis, values, tol, tie="original", on_sparsify=None):
+def factor(an: Analysis, values, tol, tie="original", on_sparsify=None, variant="OrthS"):
     """Algorithm 3: returns a Factor, or raises NotSPD(step, cluster, phase).
 
     ``tie`` selects the CPQR tie rule (see ``cpqr``).  ``on_sparsify``, when given,
@@ -514,7 +521,15 @@ def factor(an: Analysis, values, tol, tie="original", on_sparsify=None):
     live trailing matrix (scaled, so A_pp = I), ``Apn`` the gathered row block and
     ``result`` the tuple returned by ``cpqr``.  It lets tests inspect the step in
     context; it must not modify anything.
+
+    ``variant`` is one of VARIANTS.  "In" skips the block scaling and sparsifies by
+    the interpolative transformation of Sec. 2.6.2; "InS" scales first, then does
+    the same.  For those the hook receives A_np (not A_pn), the ``cpqr`` result of
+    A_np, and a keyword ``interp`` = dict(c, f, T, Cff, Ccf) of the congruence.
+    The phase of a failed Cholesky of C_ff is "sparsify".
     """
+    if variant not in VARIANTS:
+        raise ValueError(f"variant must be one of {VARIANTS}")
     n = an.n
     steps = an.steps
     values = np.asarray(values, dtype=np.float64)
@@ -566,7 +581,13 @@ def factor(an: Analysis, values, tol, tie="original", on_sparsify=None):
             del blocks[(s, s)]
         nc = len(st.keys)
         rem = range(st.n_elim, nc)
-        if st.sparsify:
+        if st.sparsify and variant != "OrthS":
+            if variant == "InS":
+                _scale(t, rem, st, blocks, sizes, slots, sf)
+            m_F += sum(sizes[p] * (sizes[p] + 1) // 2 for p in rem) if variant == "InS" else 0
+            for p in sorted(rem, key=lambda p: (st.colour[p], p)):
+                m_F += _interpolative(t, p, st, blocks, sizes, slots, sf, tol, tie, on_sparsify)
+        elif st.sparsify:
             # -- block scaling of every interface (Sec. 2.5) --
             Lp = {}
             for p in rem:
@@ -639,6 +660,83 @@ def factor(an: Analysis, values, tol, tie="original", on_sparsify=None):
     return Factor(n=n, steps=out, stats=stats)
 
 
+def _scale(t, rem, st, blocks, sizes, slots, sf):
+    """Block scaling of the interfaces ``rem`` (Sec. 2.5): A_pp = L_p L_p^T,
+    A_pq <- L_p^-1 A_pq L_q^-T, A_pp <- I."""
+    Lp = {}
+    for p in rem:
+        try:
+            Lp[p] = np.linalg.cholesky(blocks[(p, p)])
+        except np.linalg.LinAlgError:
+            raise NotSPD(t, p, "scale")
+        sf.S.append((slots[p].copy(), Lp[p]))
+    for (i, j) in st.after:
+        if i != j:
+            X = solve_triangular(Lp[i], blocks[(i, j)], lower=True)
+            blocks[(i, j)] = solve_triangular(Lp[j], X.T, lower=True).T
+    for p in rem:
+        blocks[(p, p)] = np.eye(sizes[p])
+
+
+def _interpolative(t, p, st, blocks, sizes, slots, sf, tol, tie, on_sparsify):
+    """Interpolative sparsification of interface p (Sec. 2.6.2); returns the entries
+    it stores.
+
+    The truncated CPQR of A_np (pivoting over the dofs of p) splits p into the
+    coarse dofs c (the r pivot columns, in pivot order) and the fine dofs f (the
+    rest), and gives T_cf = R_11^-1 R_12, so that A_nf ~ A_nc T_cf.  The congruence
+    with T_p = [I_f 0; -T_cf I_c] leaves
+
+        C_ff = A_ff - A_fc T_cf - T_cf^T A_cf + T_cf^T A_cc T_cf,
+        C_cf = A_cf - A_cc T_cf,
+
+    and an f-n coupling A_nf - A_nc T_cf that is dropped.  f, now coupled to c
+    only, is eliminated (Sec. 2.4 on the pair f, c): C_ff = L_f L_f^T,
+    G_cf = C_cf L_f^-T, A_cc <- A_cc - G_cf G_cf^T.  p keeps the dofs c, whose rows
+    of A_pn are A_cn unchanged.  Nothing is done when p has no coupled dofs or no
+    fine dof (r = |p|).
+    """
+    nb = st.nbrs[p]
+    if sizes[p] == 0 or sum(sizes[q] for q in nb) == 0:
+        sf.ranks[p] = sizes[p]
+        return 0
+    Anp = np.vstack([_get(blocks, q, p) for q in nb])
+    res = cpqr(Anp, tol, tie)
+    r, _, _, W, perm = res
+    if r == sizes[p]:
+        if on_sparsify is not None:
+            on_sparsify(t, p, nb, list(sizes), blocks, Anp, res, interp=None)
+        sf.ranks[p] = r
+        return 0
+    c, f = perm[:r], perm[r:]
+    R = W[:, perm]                                         # R_11 | R_12, pivot order
+    T = solve_triangular(R[:, :r], R[:, r:], lower=False)  # T_cf
+    App = blocks[(p, p)]
+    Acc, Acf, Aff = App[np.ix_(c, c)], App[np.ix_(c, f)], App[np.ix_(f, f)]
+    Cff = Aff - Acf.T @ T - T.T @ Acf + T.T @ Acc @ T
+    Ccf = Acf - Acc @ T
+    if on_sparsify is not None:
+        on_sparsify(t, p, nb, list(sizes), blocks, Anp, res,
+                    interp=dict(c=c.copy(), f=f.copy(), T=T, Cff=Cff, Ccf=Ccf))
+    try:
+        Lf = np.linalg.cholesky(Cff)
+    except np.linalg.LinAlgError:
+        raise NotSPD(t, p, "sparsify")
+    G = solve_triangular(Lf, Ccf.T, lower=True).T          # C_cf L_f^-T
+    blocks[(p, p)] = Acc - G @ G.T
+    for q in nb:
+        if p >= q:
+            blocks[(p, q)] = blocks[(p, q)][c, :]
+        else:
+            blocks[(q, p)] = blocks[(q, p)][:, c]
+    sf.I.append((slots[p].copy(), perm.copy(), r, T, Lf, G))
+    nf = sizes[p] - r
+    sizes[p] = r
+    slots[p] = slots[p][c].copy()
+    sf.ranks[p] = r
+    return r * nf + nf * (nf + 1) // 2 + r * nf
+
+
 def apply(fac: Factor, r):
     """z = M M^T r = F^T F r with F = M^T (Sec. 2.8): forward sweep over the steps
     applying E_s, S_p, Q_p^T; the trailing diagonal is the identity; backward sweep
@@ -656,7 +754,21 @@ def apply(fac: Factor, r):
             x[sp] = solve_triangular(Lp, x[sp], lower=True)
         for (sp, V, tau) in sf.Q:
             x[sp] = apply_qt(V, tau, x[sp])
+        for (sp, perm, k, T, Lf, G) in sf.I:
+            # T_p^T, then the elimination of f: y_f = L_f^-1 (x_f - T^T x_c),
+            # y_c = x_c - G y_f
+            sc, sfn = sp[perm[:k]], sp[perm[k:]]
+            yf = solve_triangular(Lf, x[sfn] - T.T @ x[sc], lower=True)
+            x[sc] = x[sc] - G @ yf
+            x[sfn] = yf
     for sf in reversed(fac.steps):
+        for (sp, perm, k, T, Lf, G) in sf.I:
+            # the elimination of f backward, then T_p: y_f = L_f^-T (y_f - G^T y_c),
+            # x_c = y_c - T y_f
+            sc, sfn = sp[perm[:k]], sp[perm[k:]]
+            yf = solve_triangular(Lf.T, x[sfn] - G.T @ x[sc], lower=False)
+            x[sc] = x[sc] - T @ yf
+            x[sfn] = yf
         for (sp, V, tau) in sf.Q:
             x[sp] = apply_q(V, tau, x[sp])
         for (sp, Lp) in sf.S:
@@ -729,10 +841,10 @@ def pcg(A, b, precond, rtol=1e-12, maxit=500):
     return X, iters, relres
 
 
-def solve(problem, b, levels, tol, skip=0, rtol=1e-12, maxit=500):
+def solve(problem, b, levels, tol, skip=0, rtol=1e-12, maxit=500, variant="OrthS"):
     """Convenience: analyze + factor + PCG on a gridgen problem."""
     an = Analysis(problem.n, problem.rowptr, problem.colind, problem.coords, levels, skip)
-    fac = factor(an, problem.values, tol)
+    fac = factor(an, problem.values, tol, variant=variant)
     A = problem.scipy()
     x, it, rr = pcg(A, b, lambda r: apply(fac, r), rtol, maxit)
     return an, fac, x, it, rr

@@ -561,3 +561,127 @@ def test_generator_operator():
     q = gridgen.variable_coefficient((4, 3, 5), np.random.default_rng(0), -3, 3)
     B = q.scipy().toarray()
     assert np.allclose(B, B.T) and np.linalg.eigvalsh(B).min() > 0
+
+
+# ---------------------------------------------------------------------------
+# Interpolative variants In / InS (Sec. 2.6.2, Sec. 3.1, Sec. 4.1.1)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("variant", ["In", "InS"])
+def test_interpolative_congruence_in_context(variant):
+    """The interpolative step on the live trailing matrix of a small 2D grid, against
+    an explicit dense congruence: with T_p = [I_f 0; -T_cf I_c] (written out as a
+    matrix over p's dofs), T_p^T B T_p has f-f block C_ff and c-f block C_cf as the
+    step computes them, leaves the c-c and c-n blocks of B unchanged, and its f-n
+    block A_nf - A_nc T_cf = Q_2 R_22 has every column below eps times the largest
+    column of A_np (the CPQR stop rule).  With scaling (InS) A_pp = I, so
+    C_ff = I + T_cf^T T_cf and C_cf = -T_cf (Sec. 3.1)."""
+    tol = 1e-2
+    p = gridgen.variable_coefficient((24, 20), np.random.default_rng(3), -1, 1)
+    an = O.Analysis(p.n, p.rowptr, p.colind, p.coords, 5)
+    seen = {"n": 0}
+
+    def hook(t, q, nb, sizes, blocks, Anp, res, interp=None):
+        if interp is None:
+            return
+        r, _, _, _, perm = res
+        c, f, T = interp["c"], interp["f"], interp["T"]
+        assert np.array_equal(np.sort(np.concatenate([c, f])), np.arange(sizes[q]))
+        ids = [q] + list(nb)
+        B, off = _dense_trailing(blocks, sizes, ids)
+        k = sizes[q]
+        assert np.array_equal(B[k:, :k], Anp)
+        Tp = np.eye(B.shape[0])
+        Tp[np.ix_(c, f)] = -T
+        C = Tp.T @ B @ Tp
+        scale = max(1.0, np.abs(B).max())
+        assert np.abs(C[np.ix_(f, f)] - interp["Cff"]).max() <= 1e-12 * scale * (1 + np.abs(T).max()) ** 2
+        assert np.abs(C[np.ix_(c, f)] - interp["Ccf"]).max() <= 1e-12 * scale * (1 + np.abs(T).max())
+        assert np.array_equal(C[np.ix_(c, c)], B[np.ix_(c, c)])
+        assert np.array_equal(C[c, k:], B[c, k:])
+        Ynf = C[k:, f]
+        cmax = np.sqrt((Anp ** 2).sum(axis=0)).max()
+        assert np.sqrt((Ynf ** 2).sum(axis=0)).max() < tol * cmax * (1 + 1e-9)
+        if variant == "InS":
+            assert np.abs(B[:k, :k] - np.eye(k)).max() < 1e-13
+            assert np.abs(interp["Cff"] - (np.eye(len(f)) + T.T @ T)).max() <= 1e-13 * (1 + np.abs(T).max()) ** 2
+            assert np.abs(interp["Ccf"] + T).max() <= 1e-13 * (1 + np.abs(T).max())
+        seen["n"] += 1
+
+    O.factor(an, p.values, tol, on_sparsify=hook, variant=variant)
+    assert seen["n"] >= 5
+
+
+@pytest.mark.parametrize("variant", ["In", "InS"])
+def test_interpolative_error_follows_eps(variant):
+    """z = M M^T b against an exact dense solve: the interpolative preconditioner is
+    exact up to the dropped f-n coupling, so the error falls with eps (Sec. 3.1:
+    ||E_nn|| = O(eps^2) ||C_ff^-1||), down to rounding once nothing is dropped."""
+    p = gridgen.variable_coefficient((24, 20), np.random.default_rng(3), -1, 1)
+    an = O.Analysis(p.n, p.rowptr, p.colind, p.coords, 5)
+    A = p.scipy().toarray()
+    b = np.random.default_rng(1).standard_normal((p.n, 2))
+    x = np.linalg.solve(A, b)
+    for tol in (1e-4, 1e-6, 1e-8):
+        fac = O.factor(an, p.values, tol, variant=variant)
+        assert sum(len(sf.I) for sf in fac.steps) >= 1          # something was dropped
+        assert not any(sf.Q for sf in fac.steps)
+        assert bool(any(sf.S for sf in fac.steps)) == (variant == "InS")
+        err = np.abs(O.apply(fac, b) - x).max() / np.abs(x).max()
+        assert err <= 100 * tol
+    fac = O.factor(an, p.values, 1e-12, variant=variant)
+    assert not any(sf.I for sf in fac.steps)
+    assert np.abs(O.apply(fac, b) - x).max() / np.abs(x).max() < 1e-12
+
+
+def test_interpolative_stored_factors_and_slots():
+    """The stored pieces of an interpolative step are consistent: L_f is the lower
+    Cholesky factor of C_ff, G_cf L_f^T = C_cf, perm is a permutation of p whose first
+    r entries name the kept (coarse) dofs and the rest the fine ones, in the order
+    the step handed them out; the apply is symmetric (M M^T)."""
+    p = gridgen.variable_coefficient((24, 20), np.random.default_rng(3), -1, 1)
+    an = O.Analysis(p.n, p.rowptr, p.colind, p.coords, 5)
+    got = {}
+
+    def hook(t, q, nb, sizes, blocks, Anp, res, interp=None):
+        if interp is not None:
+            got.setdefault(t, []).append(interp)   # in the order the step stores them
+
+    fac = O.factor(an, p.values, 1e-2, on_sparsify=hook, variant="In")
+    assert got
+    for t, sf in enumerate(fac.steps, start=1):
+        assert len(sf.I) == len(got.get(t, []))
+        for (sp, perm, k, T, Lf, G), it in zip(sf.I, got.get(t, [])):
+            assert np.array_equal(np.sort(perm), np.arange(len(sp)))
+            assert np.array_equal(perm[:k], it["c"]) and np.array_equal(perm[k:], it["f"])
+            assert np.allclose(Lf @ Lf.T, it["Cff"], rtol=0, atol=1e-12 * np.abs(it["Cff"]).max())
+            assert np.all(np.triu(Lf, 1) == 0)
+            assert np.allclose(G @ Lf.T, it["Ccf"], rtol=0, atol=1e-12 * max(1, np.abs(it["Ccf"]).max()))
+    Z = O.apply(fac, np.eye(p.n)[:, :40])
+    ZT = O.apply(fac, np.eye(p.n))[:40, :].T
+    assert np.abs(Z - ZT).max() <= 1e-12 * np.abs(Z).max()
+
+
+def test_interpolative_breaks_down_where_orths_does_not():
+    """Sec. 3.2 / Sec. 4.1.1: on a 2D high-contrast field (rho = 100, 64 x 64, five
+    levels) the interpolative factorization loses positive definiteness, without
+    scaling at eps = 1e-2 and with scaling at eps = 1e-1, while OrthS factors and
+    PCG converges at both."""
+    prob = gridgen.high_contrast((64, 64), np.random.default_rng(1064), 100.0)
+    an = O.Analysis(prob.n, prob.rowptr, prob.colind, prob.coords, 5)
+    A = prob.scipy()
+    b = gridgen.rhs(np.random.default_rng(7), prob.n, 1)
+    with pytest.raises(O.NotSPD):
+        O.factor(an, prob.values, 1e-2, variant="In")
+    with pytest.raises(O.NotSPD):
+        O.factor(an, prob.values, 1e-1, variant="InS")
+    for tol in (1e-1, 1e-2):
+        fac = O.factor(an, prob.values, tol)
+        _, it, rr = O.pcg(A, b, lambda r: O.apply(fac, r), 1e-10, 100)
+        assert rr[0] <= 1e-10 and it[0] < 100
+
+
+def test_variant_argument_checked():
+    p = gridgen.laplacian((6, 6))
+    an = O.Analysis(p.n, p.rowptr, p.colind, p.coords, 2)
+    with pytest.raises(ValueError):
+        O.factor(an, p.values, 1e-2, variant="Orth")
