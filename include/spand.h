@@ -48,6 +48,12 @@ typedef enum {
  * and PCG are FP64 in every mode. */
 typedef enum { SPAND_FP64 = 0, SPAND_FP32 = 1, SPAND_BF16X3 = 2 } spand_prec;
 
+/* Sparsification variant (Sec. 2.6, compared in Sec. 3.1 and Sec. 4.1):
+ *   SPAND_ORTHS  block scaling (Sec. 2.5), then orthogonal sparsification (Sec. 2.6.1): the method
+ *   SPAND_IN     interpolative sparsification (Sec. 2.6.2) without block scaling
+ *   SPAND_INS    block scaling, then interpolative sparsification */
+typedef enum { SPAND_ORTHS = 0, SPAND_IN = 1, SPAND_INS = 2 } spand_variant;
+
 /* Per-run statistics (the paper's metrics of Sec. 4: t_P, t_F, t_S, n_CG,
  * size_Top, mem_F). Times in seconds measured with host clocks around the calls,
  * after device synchronisation. */
@@ -67,7 +73,8 @@ typedef struct {
                             holds the pivot-block Cholesky and the ordered Schur reduction */
   int32_t fail_step;     /* on SPAND_E_NOT_SPD: elimination step (1-based) */
   int32_t fail_cluster;  /* ... cluster id within that step */
-  int32_t fail_phase;    /* ... 0 = elimination, 1 = scaling */
+  int32_t fail_phase;    /* ... 0 = elimination, 1 = scaling, 2 = interpolative sparsification
+                            (the Cholesky of C_ff, Sec. 2.6.2) */
   int32_t reserved;
   /* Per-step profile of the last factor (the paper's time/memory per level,
    * Sec. 4.4): device seconds (HIP events) of each phase of step t (t = 1..32):
@@ -218,6 +225,20 @@ spand_status spand_set_apply_graph(spand_t h, int32_t enable);
  * next factor on.  Errors: SPAND_E_INVALID for a value out of range. */
 spand_status spand_set_tuning(spand_t h, const spand_tuning* t);
 spand_status spand_get_tuning(spand_t h, spand_tuning* t);
+
+/* Select the sparsification variant (spand_variant) of the later factors of h; the
+ * default is SPAND_ORTHS.  For SPAND_IN and SPAND_INS each interface p is split by the
+ * truncated CPQR of A_np (pivoting over the dofs of p, the rule of spand_factor's tol)
+ * into coarse dofs c (the pivots) and fine dofs f; T_cf = R_11^{-1} R_12 interpolates
+ * A_nf ~ A_nc T_cf; the congruence with T_p = [I 0; -T_cf I] forms C_ff and C_cf, the
+ * f-n coupling is dropped and f is eliminated against c (Sec. 2.6.2).  The
+ * factorization may then lose positive definiteness: SPAND_E_NOT_SPD, with fail_phase
+ * 2 when the Cholesky of C_ff fails.  Limits of these variants: interfaces of at most
+ * 4096 dofs and A_np of at most 7680 rows (SPAND_E_INVALID beyond); the batched
+ * calls accept SPAND_ORTHS handles only.  Errors: SPAND_E_INVALID for an unknown
+ * variant. */
+spand_status spand_set_variant(spand_t h, spand_variant v);
+spand_status spand_get_variant(spand_t h, spand_variant* v);
 
 /* Autotuner of the kernel shapes (spand_tuning) for this matrix and these settings.
  * Coordinate descent over the parameters in turn (the GEMM tile of the Cholesky

@@ -275,6 +275,20 @@ spand_status spand_get_tuning(spand_t h, spand_tuning* t) {
   return SPAND_OK;
 }
 
+spand_status spand_set_variant(spand_t h, spand_variant v) {
+  if (!h) return fail_null(SPAND_E_INVALID, "handle is NULL");
+  if (v != SPAND_ORTHS && v != SPAND_IN && v != SPAND_INS)
+    return set_err(h, SPAND_E_INVALID, "unknown sparsification variant");
+  h->variant = v;
+  return SPAND_OK;
+}
+
+spand_status spand_get_variant(spand_t h, spand_variant* v) {
+  if (!h || !v) return fail_null(SPAND_E_INVALID, "NULL argument");
+  *v = h->variant;
+  return SPAND_OK;
+}
+
 spand_status spand_get_stats(spand_t h, spand_stats* s) {
   if (!h || !s) return fail_null(SPAND_E_INVALID, "NULL argument");
   *s = h->stats;
@@ -379,8 +393,12 @@ spand_status spand_factor_batch(int32_t P, spand_t* hs, const double* const* val
   if (!bs.ok()) return fail_null(SPAND_E_INVALID, bs.err);
   const std::string msg = check_factor_args(tol, skip, prec);
   if (!msg.empty()) return fail_null(SPAND_E_INVALID, msg);
-  for (int32_t q = 0; q < P; ++q)
+  for (int32_t q = 0; q < P; ++q) {
     if (!values[q]) return fail_null(SPAND_E_INVALID, "values[" + std::to_string(q) + "] is NULL");
+    if (hs[q]->variant != SPAND_ORTHS)
+      return fail_null(SPAND_E_INVALID, "the batched factor supports the OrthS variant only (handle " +
+                                            std::to_string(q) + ")");
+  }
   const double t0 = now();
   std::vector<spand_status> per(P, SPAND_OK);
   std::vector<const double*> dv(P);
@@ -433,6 +451,10 @@ spand_status spand_solve_batch(int32_t P, spand_t* hs, int32_t nrhs, const doubl
       return SPAND_E_STATE;
     }
     if (!b[q] || !x[q] || b[q] == x[q]) return fail_null(SPAND_E_INVALID, "bad b/x of batch problem " + std::to_string(q));
+    for (const spand::StepNum& sn : hs[q]->num)
+      if (sn.n_interp > 0)
+        return fail_null(SPAND_E_INVALID, "the batched solve supports OrthS factorizations only (problem " +
+                                              std::to_string(q) + ")");
   }
   const double t0 = now();
   std::vector<spand_status> per(P, SPAND_OK);

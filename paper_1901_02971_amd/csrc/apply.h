@@ -58,6 +58,18 @@ struct IfaceAp {
 struct HouseTile {    // 64 reflectors [j0, j0 + 64) or 64 rows [j0, j0 + 64) of interface p
   int32_t p, j0;
 };
+// An interface sparsified by the interpolative transformation (Sec. 2.6.2): its
+// coarse dofs c = perm[0..r) and fine dofs f = perm[r..np) (indices into its slots
+// at the step), T_cf, and X = [L_f; G_cf] (np x nf, ld np: L_f the nf x nf lower
+// Cholesky factor of C_ff on top, G_cf = C_cf L_f^{-T} below).  The forward sweep
+// leaves y_c in the first r slots and y_f in the others.
+struct InterpAp {
+  const int32_t* perm;
+  const double* T;    // r x nf, ld r
+  const double* X;    // ld np
+  int32_t np, r;
+  int64_t slot_p;
+};
 
 // Device-side view of one step for the apply.
 struct StepDev {
@@ -74,6 +86,8 @@ struct StepDev {
   const HouseTile* hv;   // row tiles of every Q_p
   const IfaceAp* iface;  // small interfaces: np <= 64 first (n_iface1), then np <= 128 (n_iface2)
   int32_t n_iface1, n_iface2;
+  const InterpAp* interp;  // interpolative interfaces (after the scaling of the step)
+  int32_t n_interp, pad_interp;
   const int32_t* slot;
   const int32_t* nslot;
   int64_t nslot_len;
@@ -91,6 +105,8 @@ struct ApplyArgs {
   const int32_t* slot;   // step slot array
 };
 
+// Interpolative interfaces of a step (kernels_interp.hip): dir > 0 forward, < 0 backward.
+void launch_interp_apply(const InterpAp* d, int32_t count, const ApplyArgs& a, int dir, hipStream_t s);
 void apply_step_forward(const StepDev& s, const ApplyArgs& a, hipStream_t st);
 void apply_step_backward(const StepDev& s, const ApplyArgs& a, hipStream_t st);
 

@@ -209,6 +209,12 @@ struct StepNum {
   std::vector<int32_t> h_sgather;
   std::vector<int32_t> h_nslot;  // neighbour slots of the eliminated clusters (vertex ids)
   std::vector<IfaceAp> h_iface;
+  // interpolative interfaces (Sec. 2.6.2): their apply descriptors and the buffers
+  // holding perm, T_cf and [L_f; G_cf]
+  std::vector<InterpAp> h_interp;
+  DevBuf d_interp;
+  int32_t n_interp = 0;
+  std::vector<DevBuf> interp_store;
 };
 
 }  // namespace spand
@@ -216,6 +222,7 @@ struct StepNum {
 struct spand_ctx {
   spand::Analysis an;
   spand_tuning tune = spand::default_tuning();
+  spand_variant variant = SPAND_ORTHS;  // sparsification variant of the next factor
   std::string err;
   hipStream_t stream = nullptr;
   spand_stats stats{};

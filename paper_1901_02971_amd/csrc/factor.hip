@@ -494,6 +494,8 @@ spand_status build_apply(spand_ctx* h, const SymStep& sy, StepNum& sn, const Lay
   if ((st = upload(h, sn.d_hr, sn.h_hr)) != SPAND_OK) return st;
   if ((st = upload(h, sn.d_hv, sn.h_hv)) != SPAND_OK) return st;
   if ((st = upload(h, sn.d_iface, sn.h_iface)) != SPAND_OK) return st;
+  sn.n_interp = int32_t(sn.h_interp.size());
+  if ((st = upload(h, sn.d_interp, sn.h_interp)) != SPAND_OK) return st;
   return SPAND_OK;
 }
 
@@ -507,7 +509,8 @@ struct Prob {
   const double* values = nullptr;
   int32_t L = 0;
   bool live = true;             // false once it failed (its handle holds the error)
-  int32_t* flags = nullptr;     // [0] elimination failure id, [1] scaling failure id, [2] non-finite input
+  int32_t* flags = nullptr;     // [0] elimination failure id, [1] scaling failure id, [2] non-finite input,
+                                // [3] interpolative sparsification failure id
   DevBuf arena, arena_prev;     // trailing panels of the remaining clusters, this and the last step
   Layout lay, lay_prev;
   ApplyPlan pending;            // apply descriptors of the last step, built while this one runs
@@ -722,6 +725,369 @@ spand_status upload_big(spand_ctx* h, DevBuf& b, const std::vector<T>& v) {
   return SPAND_OK;
 }
 
+// Interpolative sparsification (Sec. 2.6.2) of the interfaces of step t of one
+// problem (after the scaling for InS), one colour class at a time: an interface's
+// A_np takes the final sizes of the neighbours sparsified before it, and the launches
+// after its CPQR need its rank on the host.  Per class: A_np of every interface
+// gathered twice (the CPQR's work copy and a copy kept for the new rows), the
+// truncated CPQR of every A_np with its pivots, one sync for the ranks, then for the
+// interfaces that drop dofs, in shared launches: perm, T_cf, X = A_pp in (f, c)
+// order, the congruence C_cf = A_cf - A_cc T, C_ff = A_ff - A_fc T - T^T C_cf, the
+// blocked Cholesky of [C_ff; C_cf] (L_f and G_cf = C_cf L_f^{-T} in place), A_cc -=
+// G G^T, and the write-back of A_cc and of the rows c of every A_pq, c first in
+// pivot order (the apply moves the values of the interface the same way).
+spand_status sparsify_interp(Prob& pb, int32_t t, double tol, double& cpqr_ms, int64_t& cpqr_launches) {
+  spand_ctx* h = pb.h;
+  const SymStep& sy = h->an.steps[t - 1];
+  StepNum& sn = h->num[t - 1];
+  const Layout& lay = pb.lay;
+  double* A = pb.arena.as<double>();
+  const int32_t nc = sy.nc, ne = sy.ne;
+  std::vector<int32_t> cur(sn.size.begin(), sn.size.end());
+  int32_t ncolour = 0;
+  for (int32_t p = ne; p < nc; ++p) ncolour = std::max(ncolour, sy.colour[p] + 1);
+  EventPool ev;
+  spand_status st;
+  for (int32_t colr = 0; colr < ncolour; ++colr) {
+    struct It {
+      int32_t p, m, np, G, r;
+      bool big;
+      int64_t ow, ov, otau, ox, opiv, ot;
+    };
+    std::vector<It> its;
+    int64_t tw = 0, tv = 0, ttau = 0, tx = 0, tpiv = 0, bigmax = 0, bign = 0;
+    for (int32_t p = ne; p < nc; ++p) {
+      if (sy.colour[p] != colr || cur[p] == 0) continue;
+      int64_t m = 0;
+      for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e) m += cur[sy.nb[e]];
+      if (m == 0) continue;  // no coupled dofs: p is left as it is
+      const int32_t np = cur[p];
+      if (np > INTERP_MAX_NP)
+        return set_err(h, SPAND_E_INVALID, "interface of " + std::to_string(np) +
+                                               " dofs exceeds the interpolative limit (" +
+                                               std::to_string(INTERP_MAX_NP) + ")");
+      if (m > cpqr_big_max_rows())
+        return set_err(h, SPAND_E_INVALID, "A_np of " + std::to_string(m) + " rows exceeds the CPQR limit (" +
+                                               std::to_string(cpqr_big_max_rows()) + " rows)");
+      It it{};
+      it.p = p;
+      it.m = int32_t(m);
+      it.np = np;
+      it.G = cpqr_team(it.m);
+      it.big = it.G < 0 || np > cpqr_capacity(it.G) || (h->tune.cpqr_big_min > 0 && m >= h->tune.cpqr_big_min);
+      const int64_t k = std::min<int64_t>(m, np);
+      it.ow = tw;
+      tw += m * np;
+      it.ov = tv;
+      tv += m * k;
+      it.otau = ttau;
+      ttau += k;
+      it.ox = tx;
+      tx += int64_t(np) * np;
+      it.opiv = tpiv;
+      tpiv += 2 * int64_t(np);  // the pivots, then perm
+      if (it.big) {
+        bigmax = std::max(bigmax, m * np);
+        bign = std::max<int64_t>(bign, np);
+      }
+      its.push_back(it);
+    }
+    if (its.empty()) continue;
+    const int32_t K = int32_t(its.size());
+    DevBuf work, keep, vbuf, taub, xbuf, pbuf, curb, nrefb, errb;
+    if ((st = dalloc(h, work, size_t(tw) * sizeof(double))) != SPAND_OK) return st;
+    if ((st = dalloc(h, keep, size_t(tw) * sizeof(double))) != SPAND_OK) return st;
+    if ((st = dalloc(h, vbuf, size_t(tv) * sizeof(double))) != SPAND_OK) return st;
+    if ((st = dalloc(h, taub, size_t(ttau) * sizeof(double))) != SPAND_OK) return st;
+    if ((st = dalloc(h, xbuf, size_t(tx) * sizeof(double))) != SPAND_OK) return st;
+    if ((st = dalloc(h, pbuf, size_t(tpiv) * sizeof(int32_t))) != SPAND_OK) return st;
+    if ((st = dalloc(h, errb, sizeof(int32_t))) != SPAND_OK) return st;
+    // pivots and perm start at 0: every index they hand out stays inside the interface
+    HIPCHK(hipMemsetAsync(pbuf.p, 0, size_t(tpiv) * sizeof(int32_t), h->stream));
+    HIPCHK(hipMemsetAsync(errb.p, 0, sizeof(int32_t), h->stream));
+    // sizes the CPQR kernels read and write: [2k] the width of A_np (np), [2k + 1] the rank
+    std::vector<int32_t> c2(size_t(2) * K);
+    for (int32_t k = 0; k < K; ++k) c2[2 * k] = c2[2 * k + 1] = its[k].np;
+    if ((st = upload(h, curb, c2)) != SPAND_OK) return st;
+    if ((st = upload(h, nrefb, std::vector<int32_t>(size_t(2) * K, 0))) != SPAND_OK) return st;
+    // A_np = [A_qp] over the neighbours q (m x np, ld m), into both copies
+    std::vector<CopyDesc> cps;
+    for (const It& it : its) {
+      const int32_t p = it.p;
+      int64_t off = 0;
+      for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e) {
+        const int32_t q = sy.nb[e], nq = cur[q];
+        if (nq == 0) continue;
+        const double* src;
+        int32_t lds, trans;
+        if (q > p) {  // block (q, p) in panel p: A_qp itself
+          src = A + lay.base[p] + lay.find(q, p);
+          lds = int32_t(lay.H[p]);
+          trans = 0;
+        } else {      // block (p, q) in panel q: A_pq, transposed
+          src = A + lay.base[q] + lay.find(p, q);
+          lds = int32_t(lay.H[q]);
+          trans = 1;
+        }
+        const int32_t step = std::max(1, COPY_CHUNK / nq);
+        for (double* dst : {work.as<double>() + it.ow + off, keep.as<double>() + it.ow + off})
+          for (int32_t c0 = 0; c0 < it.np; c0 += step)
+            cps.push_back(CopyDesc{src, dst, lds, it.m, nq, c0, std::min(it.np, c0 + step), trans});
+        off += nq;
+      }
+    }
+    DevBuf dcp;
+    if ((st = upload_big(h, dcp, cps)) != SPAND_OK) return st;
+    launch_copy(dcp.as<CopyDesc>(), int64_t(cps.size()), h->stream);
+    HIPCHK(hipGetLastError());
+    // the truncated CPQR of every A_np, with its pivots
+    std::vector<SparsDesc> sds(K);
+    std::vector<SegDesc> segs(K);
+    for (int32_t k = 0; k < K; ++k) {
+      const It& it = its[k];
+      SparsDesc d{};
+      d.V = vbuf.as<double>() + it.ov;
+      d.tau = taub.as<double>() + it.otau;
+      d.diag = xbuf.as<double>() + it.ox;  // I_r lands in X, which is rewritten later
+      d.ldd = it.np;
+      d.m = it.m;
+      d.seg_begin = k;
+      d.seg_end = k + 1;
+      d.id = 2 * k + 1;
+      d.S = 1;
+      d.G = it.big ? 0 : it.G;
+      d.piv = pbuf.as<int32_t>() + it.opiv;
+      sds[k] = d;
+      SegDesc g{};
+      g.blk = work.as<double>() + it.ow;
+      g.ld = it.m;
+      g.trans = 0;
+      g.q = 2 * k;
+      segs[k] = g;
+    }
+    std::vector<SlabRef> slabs;
+    std::vector<std::pair<int32_t, size_t>> one;  // (team size, first slab) of each plain launch
+    for (int32_t G = 1; G <= 64; G <<= 1) {
+      const size_t s0 = slabs.size();
+      for (int32_t k = 0; k < K; ++k)
+        if (!its[k].big && its[k].G == G) slabs.push_back(SlabRef{k, 0});
+      if (slabs.size() > s0) one.emplace_back(G, s0);
+    }
+    DevBuf dsd, dsg, dsl;
+    if ((st = upload(h, dsd, sds)) != SPAND_OK) return st;
+    if ((st = upload(h, dsg, segs)) != SPAND_OK) return st;
+    if ((st = upload(h, dsl, slabs)) != SPAND_OK) return st;
+    DevBuf bwk, bnrm, bpst, brb, bpost, bpcd, bbar;
+    if (bigmax > 0) {
+      if ((st = dalloc(h, bwk, size_t(bigmax) * sizeof(double))) != SPAND_OK) return st;
+      if ((st = dalloc(h, bnrm, size_t(bign) * sizeof(double))) != SPAND_OK) return st;
+      if ((st = dalloc(h, bpst, size_t(bign) * sizeof(int32_t))) != SPAND_OK) return st;
+      if ((st = dalloc(h, brb, size_t(bign) * sizeof(double))) != SPAND_OK) return st;
+      if ((st = dalloc(h, bpost, 1024 * sizeof(double))) != SPAND_OK) return st;
+      if ((st = dalloc(h, bpcd, 1024 * sizeof(int32_t))) != SPAND_OK) return st;
+      if ((st = dalloc(h, bbar, 256)) != SPAND_OK) return st;
+    }
+    hipEvent_t e0, e1;
+    HIPCHK(ev.get(0, &e0));
+    HIPCHK(ev.get(1, &e1));
+    HIPCHK(hipEventRecord(e0, h->stream));
+    int64_t nl = 0;
+    for (size_t q = 0; q < one.size(); ++q) {
+      const size_t s1 = q + 1 < one.size() ? one[q + 1].second : slabs.size();
+      const int32_t G = one[q].first;
+      hipError_t le = launch_cpqr_one(G, dsd.as<SparsDesc>(), dsl.as<SlabRef>() + one[q].second,
+                                      int32_t(s1 - one[q].second), dsg.as<SegDesc>(), tol, curb.as<int32_t>(),
+                                      nrefb.as<int32_t>(), errb.as<int32_t>(), cpqr_lds_bytes(G, 0, 1), h->stream);
+      if (le != hipSuccess) return set_err(h, SPAND_E_HIP, std::string("sparsification launch: ") + hipGetErrorString(le));
+      ++nl;
+      pb.cpqr_ifaces[0] += int64_t(s1 - one[q].second);
+    }
+    for (int32_t k = 0; k < K; ++k) {
+      if (!its[k].big) continue;
+      const int capb = cpqr_big_max_coresident(1);
+      if (capb <= 0) return set_err(h, SPAND_E_HIP, "occupancy query for the large-interface CPQR failed");
+      const int32_t nb = int32_t(std::max<int64_t>(1, std::min<int64_t>(std::min(capb, 1024), (its[k].np + 15) / 16)));
+      HIPCHK(hipMemsetAsync(bbar.p, 0, 256, h->stream));
+      hipError_t le = launch_cpqr_big(sds[k], 1, dsg.as<SegDesc>(), tol, curb.as<int32_t>(), nrefb.as<int32_t>(),
+                                      errb.as<int32_t>(), nb, bwk.as<double>(), bnrm.as<double>(), bpst.as<int32_t>(),
+                                      brb.as<double>(), bpost.as<double>(), bpcd.as<int32_t>(), bbar.as<uint32_t>(),
+                                      h->stream);
+      if (le != hipSuccess)
+        return set_err(h, SPAND_E_HIP, std::string("large-interface sparsification launch: ") + hipGetErrorString(le));
+      ++nl;
+      ++pb.cpqr_big;
+    }
+    HIPCHK(hipEventRecord(e1, h->stream));
+    int32_t serr = 0;
+    HIPCHK(hipMemcpyAsync(c2.data(), curb.p, c2.size() * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(&serr, errb.p, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (serr) return set_err(h, SPAND_E_HIP, "sparsification barrier timed out");
+    {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      cpqr_ms += ms;
+      cpqr_launches += nl;
+    }
+    // the interfaces that drop dofs
+    std::vector<InterpPermDesc> pds;
+    std::vector<InterpTDesc> tds;
+    std::vector<InterpCol> tcols;
+    std::vector<InterpXDesc> xds;
+    std::vector<InterpRowDesc> rws;
+    std::vector<CopyDesc> back;
+    std::vector<Front> fr;
+    GemmSeq cong(h->tune.gemm_chol), syrk(h->tune.gemm_syrk);
+    int64_t ttot = 0, dtot = 0;
+    int32_t rmax = 0;
+    for (It& it : its) {
+      it.r = std::min(std::max(c2[2 * (&it - its.data()) + 1], 0), it.np);
+      const int64_t r = it.r, m = it.m, np = it.np;
+      {
+        // CPQR flops as in the orthogonal path: 6 (m-j)(np-j) - (m-j) per step
+        const int64_t s1 = r * (r - 1) / 2, s2 = (r - 1) * r * (2 * r - 1) / 6;
+        pb.cpqr_flops += double(6 * (r * m * np - (m + np) * s1 + s2) - (r * m - s1));
+      }
+      if (it.r == it.np) continue;
+      it.ot = ttot;
+      ttot += r * (np - r);
+      dtot += dinv_size(int32_t(np - r));
+      rmax = std::max(rmax, it.r);
+    }
+    DevBuf tbuf, dinvb;
+    if ((st = dalloc(h, tbuf, size_t(std::max<int64_t>(ttot, 1)) * sizeof(double))) != SPAND_OK) return st;
+    if ((st = dalloc(h, dinvb, size_t(std::max<int64_t>(dtot, 1)) * sizeof(double))) != SPAND_OK) return st;
+    int64_t doff = 0;
+    for (const It& it : its) {
+      if (it.r == it.np) continue;
+      const int32_t p = it.p, np = it.np, r = it.r, nf = np - r;
+      int32_t* piv = pbuf.as<int32_t>() + it.opiv;
+      int32_t* perm = piv + np;
+      double* X = xbuf.as<double>() + it.ox;
+      double* T = tbuf.as<double>() + it.ot;
+      pds.push_back(InterpPermDesc{piv, perm, np, r});
+      if (r > 0) {
+        const int32_t td = int32_t(tds.size());
+        tds.push_back(InterpTDesc{work.as<double>() + it.ow, perm, T, it.m, r});
+        for (int32_t j = 0; j < nf; ++j) tcols.push_back(InterpCol{td, j});
+      }
+      const int64_t ne2 = int64_t(np) * np;
+      for (int64_t e0 = 0; e0 < ne2; e0 += INTERP_CHUNK)
+        xds.push_back(InterpXDesc{A + lay.base[p], perm, X, int32_t(lay.H[p]), np, r, 0, e0,
+                                  std::min<int64_t>(ne2, e0 + INTERP_CHUNK)});
+      // X = [X_ff X_fc; X_cf X_cc] (ld np): rows and columns 0..nf are f, nf..np are c
+      GemmDesc g{};
+      g.A = X + nf + int64_t(nf) * np; g.lda = np;  // X_cc
+      g.B = T; g.ldb = r;
+      g.C = X + nf; g.ldc = np;                     // X_cf <- C_cf = A_cf - A_cc T
+      g.M = r; g.N = nf; g.K = r;
+      g.flags = 0; g.alpha = -1.0; g.beta = 1.0;
+      cong.add(g, 0);
+      GemmDesc f1{};
+      f1.A = X + int64_t(nf) * np; f1.lda = np;     // X_fc = A_fc
+      f1.B = T; f1.ldb = r;
+      f1.C = X; f1.ldc = np;                        // X_ff -= A_fc T
+      f1.M = nf; f1.N = nf; f1.K = r;
+      f1.flags = G_LOWERC; f1.alpha = -1.0; f1.beta = 1.0;
+      cong.add(f1, 1);
+      fr.push_back(Front{X, dinvb.as<double>() + doff, np, nf, np, p, pb.flags + 3});
+      doff += dinv_size(nf);
+      GemmDesc s{};
+      s.A = X + nf; s.lda = np;                     // G_cf
+      s.B = X + nf; s.ldb = np;
+      s.C = X + nf + int64_t(nf) * np; s.ldc = np;  // X_cc -= G G^T
+      s.M = r; s.N = r; s.K = nf;
+      s.flags = G_TB | G_LOWERC; s.alpha = -1.0; s.beta = 1.0;
+      syrk.add(s, 1);
+      // A_cc back into the diagonal block of p; the rows c of every A_pq
+      if (r > 0) {
+        const int32_t step = std::max(1, COPY_CHUNK / r);
+        for (int32_t c0 = 0; c0 < r; c0 += step)
+          back.push_back(CopyDesc{X + nf + int64_t(nf) * np, A + lay.base[p], np, int32_t(lay.H[p]), r, c0,
+                                  std::min(r, c0 + step), 0});
+        int32_t row0 = 0;
+        for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e) {
+          const int32_t q = sy.nb[e], nq = cur[q];
+          if (nq == 0) continue;
+          InterpRowDesc rd{};
+          rd.keep = keep.as<double>() + it.ow;
+          rd.perm = perm;
+          rd.ldk = it.m;
+          rd.row0 = row0;
+          rd.nq = nq;
+          rd.r = r;
+          if (q < p) {  // block (p, q) in panel q, rows over p
+            rd.blk = A + lay.base[q] + lay.find(p, q);
+            rd.ld = int32_t(lay.H[q]);
+            rd.trans = 0;
+          } else {      // block (q, p) in panel p, columns over p
+            rd.blk = A + lay.base[p] + lay.find(q, p);
+            rd.ld = int32_t(lay.H[p]);
+            rd.trans = 1;
+          }
+          const int64_t cnt = int64_t(r) * nq;
+          for (int64_t e0 = 0; e0 < cnt; e0 += INTERP_CHUNK) {
+            rd.e0 = e0;
+            rd.e1 = std::min<int64_t>(cnt, e0 + INTERP_CHUNK);
+            rws.push_back(rd);
+          }
+          row0 += nq;
+        }
+      }
+      sn.h_interp.push_back(InterpAp{perm, T, X, np, r, sn.slot_ptr[p]});
+      pb.m_F += 2 * int64_t(r) * nf + int64_t(nf) * (nf + 1) / 2;
+    }
+    if (!pds.empty()) {
+      cong.end_launch(0);
+      GemmDesc g2{};
+      for (const It& it : its) {  // X_ff -= T^T C_cf, once C_cf is formed
+        if (it.r == it.np || it.r == 0) continue;
+        const int32_t np = it.np, r = it.r, nf = np - r;
+        double* X = xbuf.as<double>() + it.ox;
+        g2.A = tbuf.as<double>() + it.ot; g2.lda = r;
+        g2.B = X + nf; g2.ldb = np;
+        g2.C = X; g2.ldc = np;
+        g2.M = nf; g2.N = nf; g2.K = r;
+        g2.flags = G_TA | G_LOWERC; g2.alpha = -1.0; g2.beta = 1.0;
+        cong.add(g2, 1);
+      }
+      cong.end_launch(0);
+      syrk.end_launch(0);
+      DevBuf dpd, dtd, dtc, dxd, drw, dbk;
+      if ((st = upload(h, dpd, pds)) != SPAND_OK) return st;
+      if ((st = upload(h, dtd, tds)) != SPAND_OK) return st;
+      if ((st = upload_big(h, dtc, tcols)) != SPAND_OK) return st;
+      if ((st = upload_big(h, dxd, xds)) != SPAND_OK) return st;
+      if ((st = upload_big(h, drw, rws)) != SPAND_OK) return st;
+      if ((st = upload_big(h, dbk, back)) != SPAND_OK) return st;
+      if ((st = cong.upload_all(h)) != SPAND_OK) return st;
+      if ((st = syrk.upload_all(h)) != SPAND_OK) return st;
+      launch_interp_perm(dpd.as<InterpPermDesc>(), int32_t(pds.size()), h->stream);
+      launch_interp_t(dtd.as<InterpTDesc>(), dtc.as<InterpCol>(), int64_t(tcols.size()), rmax, h->stream);
+      launch_interp_x(dxd.as<InterpXDesc>(), int64_t(xds.size()), h->stream);
+      HIPCHK(hipGetLastError());
+      cong.launch(h, 0);
+      cong.launch(h, 1);
+      HIPCHK(hipGetLastError());
+      if ((st = blocked_cholesky(h, fr, 0)) != SPAND_OK) return st;
+      syrk.launch(h, 0);
+      launch_copy(dbk.as<CopyDesc>(), int64_t(back.size()), h->stream);
+      launch_interp_rows(drw.as<InterpRowDesc>(), int64_t(rws.size()), h->stream);
+      HIPCHK(hipGetLastError());
+      sn.interp_store.push_back(std::move(xbuf));
+      sn.interp_store.push_back(std::move(pbuf));
+      sn.interp_store.push_back(std::move(tbuf));
+      // the descriptor and scratch buffers of this class go back to the pool; later
+      // allocations that reuse them are ordered after these launches on the stream
+    }
+    for (const It& it : its) {
+      cur[it.p] = it.r;
+      sn.rank[it.p] = it.r;
+    }
+  }
+  return SPAND_OK;
+}
+
 // Problem index and cluster of a failure id of a run (ids carry the problem in
 // their high bits so that one flag word may serve several problems).
 constexpr int32_t FAIL_NONE = 0x7fffffff;
@@ -748,8 +1114,8 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
   {
     std::vector<int32_t> init(size_t(4) * NP);
     for (int32_t q = 0; q < NP; ++q) {
-      init[4 * q] = init[4 * q + 1] = FAIL_NONE;
-      init[4 * q + 2] = init[4 * q + 3] = 0;
+      init[4 * q] = init[4 * q + 1] = init[4 * q + 3] = FAIL_NONE;
+      init[4 * q + 2] = 0;
     }
     if ((st = upload(h, dflag, init)) != SPAND_OK) return st;
     for (int32_t q = 0; q < NP; ++q) P[q].flags = dflag.as<int32_t>() + 4 * q;
@@ -981,7 +1347,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
         pb.tau_off.assign(nc, -1);
         pb.t_off.assign(nc, -1);
         pb.nref.assign(nc, 0);
-        if (!(pb.sparsify && nc > ne)) continue;
+        if (!(pb.sparsify && nc > ne) || hq->variant == SPAND_IN) continue;
         any_sparsify = true;
         const Layout& lay = pb.lay;
         double* A = pb.arena.as<double>();
@@ -1040,7 +1406,13 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
     size_t nlaunch = 0;
     DevBuf curb, nrefb, errb, xchb;
     int64_t ncl = 0;  // clusters of the sparsified problems in the run's size and rank arrays
-    if (any_sparsify) {
+    auto orth = [&](const Prob& pb) {
+      const SymStep& sy = pb.h->an.steps[t - 1];
+      return pb.sparsify && sy.nc > sy.ne && pb.h->variant == SPAND_ORTHS;
+    };
+    bool any_orth = false;
+    for (Prob* pp : act) any_orth = any_orth || orth(*pp);
+    if (any_orth) {
       int32_t ncolour = 0;
       int64_t xch_total = 0;
       std::vector<int32_t> cur_h;
@@ -1050,7 +1422,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
         const SymStep& sy = hq->an.steps[t - 1];
         StepNum& sn = hq->num[t - 1];
         const int32_t nc = sy.nc, ne = sy.ne;
-        if (!(pb.sparsify && nc > ne)) continue;
+        if (!orth(pb)) continue;
         pb.cbase = ncl;
         ncl += nc;
         cur_h.insert(cur_h.end(), sn.size.begin(), sn.size.end());
@@ -1139,7 +1511,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
       struct Ref { Prob* pb; int32_t p; };
       std::vector<std::vector<Ref>> by_colour(ncolour);
       for (Prob* pp : act) {
-        if (!(pp->sparsify && pp->h->an.steps[t - 1].nc > pp->h->an.steps[t - 1].ne)) continue;
+        if (!orth(*pp)) continue;
         const SymStep& sy = pp->h->an.steps[t - 1];
         for (int32_t p = sy.ne; p < sy.nc; ++p)
           if (pp->v_off[p] >= 0) by_colour[sy.colour[p]].push_back(Ref{pp, p});
@@ -1405,6 +1777,13 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
       }
       HIPCHK(hipEventRecord(ph[4], h->stream));
     }
+    // ---- interpolative sparsification (Sec. 2.6.2) of the problems that ask for it
+    for (Prob* pp : act) {
+      const SymStep& sy = pp->h->an.steps[t - 1];
+      if (!(pp->sparsify && sy.nc > sy.ne && pp->h->variant != SPAND_ORTHS)) continue;
+      if ((st = sparsify_interp(*pp, t, tol, cpqr_ms, cpqr_launches)) != SPAND_OK) return st;
+      HIPCHK(hipEventRecord(ph[4], h->stream));
+    }
 
     // ---- while the step's last kernels run: the previous step's T factors and apply
     // descriptors; then one sync for the flags of every problem and the ranks
@@ -1427,7 +1806,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
     std::vector<int32_t> rk(size_t(ncl), -1), nrefh(size_t(ncl), 0);
     int32_t serr = 0;
     HIPCHK(hipMemcpyAsync(hflags.data(), dflag.p, hflags.size() * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
-    if (any_sparsify) {
+    if (any_orth) {
       HIPCHK(hipMemcpyAsync(rk.data(), curb.p, size_t(ncl) * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
       HIPCHK(hipMemcpyAsync(nrefh.data(), nrefb.p, size_t(ncl) * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
       HIPCHK(hipMemcpyAsync(&serr, errb.p, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
@@ -1461,6 +1840,12 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
         hq->stats.fail_phase = 1;
         fail_problem(pb, SPAND_E_NOT_SPD, "interface block not SPD at step " + std::to_string(t) + ", cluster " +
                                               std::to_string(fl[1]) + " (scaling)");
+      } else if (fl[3] != FAIL_NONE) {
+        hq->stats.fail_step = t;
+        hq->stats.fail_cluster = fl[3];
+        hq->stats.fail_phase = 2;
+        fail_problem(pb, SPAND_E_NOT_SPD, "C_ff not SPD at step " + std::to_string(t) + ", cluster " +
+                                              std::to_string(fl[3]) + " (interpolative sparsification)");
       }
       if (!pb.live) {
         pb.t_pending.clear();
@@ -1472,7 +1857,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
       const SymStep& sy = hq->an.steps[t - 1];
       StepNum& sn = hq->num[t - 1];
       const int32_t nc = sy.nc, ne = sy.ne;
-      if (pb.sparsify && nc > ne) {
+      if (orth(pb)) {
         std::vector<TDesc> tds;
         for (int32_t p = ne; p < nc; ++p)
           if (pb.v_off[p] >= 0) {

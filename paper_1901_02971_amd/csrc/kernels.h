@@ -98,6 +98,7 @@ struct SparsDesc {
   double* diag;    // diagonal block of p (ld ldd), set to I_r on exit
   double* xch;     // slab exchange (S > 1): 3 buffers x S records of cpqr_record(G) doubles, zeroed
                    // before the launch
+  int32_t* piv;    // when not null: piv[j] = column (index in A_pn) chosen at step j < r
   int32_t m, ldd, seg_begin, seg_end, id, S, G, lay;  // G: lanes per column (team size);
                                                       // lay: register layout (multi-slab kernel)
 };
@@ -186,5 +187,43 @@ struct TBlock {
 void launch_build_t_diag(const TBlock* blocks, int32_t count, hipStream_t s);
 
 constexpr int GEMM_TILE = 64;
+
+// Interpolative sparsification (Sec. 2.6.2, kernels_interp.hip).  For one interface
+// p of np dofs, the truncated CPQR of A_np (m x np, ld m, in W) has chosen r pivot
+// columns piv[0..r); nf = np - r.
+struct InterpPermDesc {  // perm = the pivots in pivot order, then the other columns ascending
+  const int32_t* piv;
+  int32_t* perm;
+  int32_t np, r;
+};
+struct InterpTDesc {     // T_cf = R_11^-1 R_12 (r x nf, ld r); R = W[0..r, perm]
+  const double* W;
+  const int32_t* perm;
+  double* T;
+  int32_t ldw, r;
+};
+struct InterpCol {       // column j of T of interface desc
+  int32_t desc, j;
+};
+struct InterpXDesc {     // entries [e0, e1) of X = A_pp[s, s], s = (perm[r..np), perm[0..r)), ld np;
+  const double* App;     // A_pp read from its lower triangle (ld lda)
+  const int32_t* perm;
+  double* X;
+  int32_t lda, np, r, pad;
+  int64_t e0, e1;
+};
+struct InterpRowDesc {   // entries [e0, e1) of the r x nq block A_cq (c = perm[0..r)) from a copy of A_np
+  const double* keep;    // A_np, ld ldk; neighbour q occupies rows [row0, row0 + nq)
+  const int32_t* perm;
+  double* blk;           // trans = 0: A_cq[i][k] at blk[i + k ld]; 1: at blk[k + i ld]
+  int32_t ldk, row0, nq, r, ld, trans;
+  int64_t e0, e1;
+};
+#define INTERP_CHUNK 16384   // entries per workgroup of the gathers
+#define INTERP_MAX_NP 4096   // interface dofs an interpolative step handles
+void launch_interp_perm(const InterpPermDesc* d, int32_t count, hipStream_t s);
+void launch_interp_t(const InterpTDesc* d, const InterpCol* cols, int64_t ncols, int32_t rmax, hipStream_t s);
+void launch_interp_x(const InterpXDesc* d, int64_t count, hipStream_t s);
+void launch_interp_rows(const InterpRowDesc* d, int64_t count, hipStream_t s);
 
 }  // namespace spand

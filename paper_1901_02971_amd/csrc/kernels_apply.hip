@@ -12,7 +12,9 @@
 //   k_iface<1>    x_p <- Q_p^T L_p^{-1} x_p      (interfaces of at most 128 dofs, one wave each)
 //   k_scale<1>    x_p <- L_p^{-1} x_p                (larger interfaces: explicit inverse, 64-row tiles)
 //   k_house_*     x_p <- Q_p^T x_p                (compact WY form, three tile launches)
+//   k_interp_apply<1>  interpolative interfaces (Sec. 2.6.2, kernels_interp.hip)
 // Backward sweep (levels 1 -> L), the transposes in reverse order:
+//   k_interp_apply<-1>
 //   k_iface<-1>   x_p <- L_p^{-T} Q_p x_p
 //   k_house_*     x_p <- Q_p x_p
 //   k_scale<-1>   x_p <- L_p^{-T} x_p
@@ -732,9 +734,11 @@ void apply_step_forward(const StepDev& s, const ApplyArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_house_t<1>, dim3(s.n_hr), dim3(AW), 0, st, s.house, s.hr, a);
     hipLaunchKernelGGL(k_house_v, dim3(s.n_hv), dim3(AW), 0, st, s.house, s.hv, a);
   }
+  if (s.n_interp) launch_interp_apply(s.interp, s.n_interp, a, 1, st);
 }
 
 void apply_step_backward(const StepDev& s, const ApplyArgs& a, hipStream_t st) {
+  if (s.n_interp) launch_interp_apply(s.interp, s.n_interp, a, -1, st);
   if (s.n_iface1) hipLaunchKernelGGL((k_iface<-1, 1>), dim3(s.n_iface1), dim3(64), 0, st, s.iface, a);
   if (s.n_iface2) hipLaunchKernelGGL((k_iface<-1, 2>), dim3(s.n_iface2), dim3(64), 0, st, s.iface + s.n_iface1, a);
   if (s.n_hr) {

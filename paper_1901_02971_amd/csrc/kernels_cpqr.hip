@@ -719,6 +719,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
     column_ptr(sg, segoff, col[k], base, stride);
     const int ps = pst[k];
     const double rss = (ps >= 0) ? rb[ps] : 0.0;
+    if (d.piv && ps >= 0 && g == 0) d.piv[ps] = col[k];
 #pragma unroll
     for (int q = 0; q < MR; ++q) {
       const int i = q * G + g;
@@ -1098,6 +1099,7 @@ __global__ void __launch_bounds__(CB_NT) k_cpqr_big(SparsDesc d, const SegDesc* 
     int64_t stride;
     column_ptr(sg, segoff, c, base, stride);
     const int ps = big_pst(bs, c);
+    if (d.piv && ps >= 0 && lane == 0) d.piv[ps] = c;
     for (int i = lane; i < r; i += 64) {
       double v;
       if (ps >= 0 && i >= ps)

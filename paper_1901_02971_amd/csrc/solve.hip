@@ -45,6 +45,8 @@ StepDev step_dev(const StepNum& s) {
   d.iface = s.d_iface.as<IfaceAp>();
   d.n_iface1 = s.n_iface1;
   d.n_iface2 = s.n_iface2;
+  d.interp = s.d_interp.as<InterpAp>();
+  d.n_interp = s.n_interp;
   d.slot = s.d_slot.as<int32_t>();
   d.nslot = s.d_nslot.as<int32_t>();
   d.nslot_len = s.nslot_len;

@@ -20,6 +20,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
 SPAND_FP64, SPAND_FP32, SPAND_BF16X3 = 0, 1, 2
+SPAND_ORTHS, SPAND_IN, SPAND_INS = 0, 1, 2
+VARIANTS = {"OrthS": SPAND_ORTHS, "In": SPAND_IN, "InS": SPAND_INS}
 STATUS = {0: "SPAND_OK", 1: "SPAND_E_INVALID", 2: "SPAND_E_NOT_SPD", 3: "SPAND_E_NOCONV",
           4: "SPAND_E_NOMEM", 5: "SPAND_E_HIP", 6: "SPAND_E_STATE", 7: "SPAND_E_BREAKDOWN"}
 
@@ -91,6 +93,8 @@ def load_library():
         "spand_get_stats": (i32, [P, C.POINTER(Stats)]),
         "spand_set_tuning": (i32, [P, C.POINTER(Tuning)]),
         "spand_get_tuning": (i32, [P, C.POINTER(Tuning)]),
+        "spand_set_variant": (i32, [P, i32]),
+        "spand_get_variant": (i32, [P, C.POINTER(i32)]),
         "spand_autotune": (i32, [P, P, f64, i32, i32, i32, i32, C.POINTER(Tuning)]),
         "spand_get_ordering": (i32, [P, P, P, P]),
         "spand_get_permutation": (i32, [P, P]),
@@ -257,6 +261,15 @@ class Solver:
                 raise KeyError(k)
             setattr(t, k, int(v))
         self._check(self._lib.spand_set_tuning(self._h, C.byref(t)))
+
+    def set_variant(self, variant):
+        """spand_set_variant: "OrthS" (default), "In" or "InS" for the later factors."""
+        self._check(self._lib.spand_set_variant(self._h, VARIANTS[variant] if isinstance(variant, str) else int(variant)))
+
+    def variant(self):
+        v = C.c_int32()
+        self._check(self._lib.spand_get_variant(self._h, C.byref(v)))
+        return {num: name for name, num in VARIANTS.items()}[v.value]
 
     def autotune(self, values, tol, skip=0, prec=SPAND_FP64, nrhs=1, reps=2):
         """spand_autotune: choose the kernel shapes on this matrix; the handle ends

@@ -12,6 +12,7 @@ from paper_1901_02971_amd import spand as S
 
 DECLARED = ["spand_analyze", "spand_factor", "spand_solve", "spand_apply", "spand_set_stream",
             "spand_set_apply_graph", "spand_get_stats", "spand_set_tuning", "spand_get_tuning", "spand_autotune",
+            "spand_set_variant", "spand_get_variant",
             "spand_apply_noalloc", "spand_get_permutation",
             "spand_get_ordering", "spand_step_counts", "spand_step_structure", "spand_step_ranks",
             "spand_factor_batch", "spand_solve_batch", "spand_error_string", "spand_destroy"]
@@ -183,3 +184,19 @@ def test_batch_rejects_bad_handle_lists():
     it = np.zeros(2, np.int32)
     rr = np.zeros(2)
     assert lib.spand_solve_batch(2, hs, 1, vals, vals, 1e-12, 10, it.ctypes.data, rr.ctypes.data) == 1
+
+
+def test_variant_selection_host_only():
+    """spand_set_variant / spand_get_variant touch no GPU: the default is OrthS, the
+    three variants round-trip, an unknown value is refused and leaves the choice."""
+    p = gridgen.laplacian((6, 5))
+    s = S.Solver.from_problem(p, 2)
+    assert s.variant() == "OrthS"
+    for v in ("In", "InS", "OrthS", "In"):
+        s.set_variant(v)
+        assert s.variant() == v
+    lib = S.load_library()
+    assert S.STATUS[lib.spand_set_variant(s._h, 3)] == "SPAND_E_INVALID"
+    assert S.STATUS[lib.spand_set_variant(None, 0)] == "SPAND_E_INVALID"
+    assert s.variant() == "In"
+    s.close()
