@@ -348,6 +348,81 @@ def bench_sweep(args):
     print(json.dumps({"sweep": "x4", "points": len(rows)}), flush=True)
 
 
+def bench_variants(args):
+    """The variant comparison of Sec. 4.1.1 (fig. of the 2D high-contrast Laplacians):
+    n x n grids with the quantized high-contrast field (rho = 1: the Laplacian; rho =
+    100), 5-point stencil, depth 1 + ceil(log2(n^2/512)), one RHS; for each eps, the
+    three sparsification variants In, InS and OrthS, each factored and solved with PCG
+    (to 1e-12 at rho = 1; to 1e-10 at rho = 100, where the attainable true residual
+    of FP64 CG sits near 1e-12).  A point whose factorization loses positive
+    definiteness reports where (step, cluster, phase).  Where the oracle's result of
+    the same point is stored under tests/golden, the point is checked against it
+    (ranks, s_top, m_F, iterations within +-1, or the same failure site)."""
+    import gridgen
+    import torch
+    from paper_1901_02971_amd import Solver, SpandError
+    dev = torch.device("cuda:0")
+    golden = os.path.join(ROOT, "tests", "golden")
+    sizes = [int(x) for x in args.variant_sizes.split(",")]
+    tols = [float(x) for x in args.variant_tols.split(",")]
+    rhos = [float(x) for x in args.sweep_rhos.split(",")]
+    phase = {0: "elim", 1: "scale", 2: "sparsify"}
+    rows = []
+    for n in sizes:
+        for rho in rhos:
+            name = f"x1_{n}_rho{rho:g}"
+            p, b, L = gridgen.config_problem(name)
+            rtol = 1e-12 if rho == 1.0 else 1e-10
+            s = Solver.from_problem(p, L)
+            vals = torch.from_numpy(p.values).to(dev)
+            bt = torch.from_numpy(np.ascontiguousarray(b.T)).to(dev)
+            xt = torch.empty_like(bt)
+            for tol in tols:
+                for variant in ("In", "InS", "OrthS"):
+                    rec = {"n": n, "N": int(p.n), "rho": rho, "tol": tol, "variant": variant, "levels": int(L),
+                           "rtol": rtol}
+                    s.set_variant(variant)
+                    try:
+                        s.factor(vals, tol, 0, 0)
+                        f = s.stats()
+                        it, rr, st = s.solve(bt, xt, rtol, 500, check=False)
+                        g = s.stats()
+                        rec.update({"status": int(st), "pcg_iters": int(it[0]), "relres": float(rr[0]),
+                                    "s_top": int(f["s_top"]), "m_F": int(f["m_F"]), "t_F": round(f["t_factor"], 4),
+                                    "t_S": round(g["t_solve"], 4)})
+                    except SpandError as e:
+                        f = s.stats()
+                        rec.update({"status": e.status, "not_spd": e.name == "SPAND_E_NOT_SPD"})
+                        if e.name == "SPAND_E_NOT_SPD":
+                            rec["site"] = {"step": int(f["fail_step"]), "cluster": int(f["fail_cluster"]),
+                                           "phase": phase.get(int(f["fail_phase"]), "?")}
+                        else:
+                            rec["error"] = str(e)[:200]
+                    tag = f"{tol:.0e}".replace("e-0", "e-")
+                    gpath = os.path.join(golden, f"oracle_{name}_tol{tag}" + ("" if variant == "OrthS" else "_" + variant)
+                                         + ".json")
+                    if os.path.exists(gpath):
+                        with open(gpath) as fh:
+                            ref = json.load(fh)
+                        if "not_spd" in ref:
+                            ok = rec.get("site") == ref["not_spd"]
+                        else:
+                            ok = (rec.get("status") == 0 and rec["s_top"] == ref["s_top"] and rec["m_F"] == ref["m_F"]
+                                  and abs(rec["pcg_iters"] - ref["pcg_iters"][0]) <= 1)
+                        rec["oracle_check"] = "match" if ok else "mismatch"
+                    print(json.dumps({"variant_point": rec}), flush=True)
+                    rows.append(rec)
+            s.close()
+            del vals, bt, xt
+            torch.cuda.empty_cache()
+    checked = [r for r in rows if "oracle_check" in r]
+    print(json.dumps({"variants": "x1", "points": len(rows), "oracle_checked": len(checked),
+                      "oracle_mismatches": sum(r["oracle_check"] != "match" for r in checked),
+                      "orths_failures": sum(1 for r in rows if r["variant"] == "OrthS" and r.get("status") != 0),
+                      "in_failures": sum(1 for r in rows if r["variant"] == "In" and r.get("not_spd")),
+                      "ins_failures": sum(1 for r in rows if r["variant"] == "InS" and r.get("not_spd"))}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -364,6 +439,9 @@ def main():
     ap.add_argument("--sweep-tols", default="1e-1,1e-3,1e-5")
     ap.add_argument("--sweep-rhos", default="1,100")
     ap.add_argument("--skip-sweep", default="", help="grid edge of the skip sweep (skip 0..4, eps 1e-3)")
+    ap.add_argument("--variant-sizes", default="64,128,256,512,1024,2048",
+                    help="grid edges of --config variants (2D In / InS / OrthS comparison)")
+    ap.add_argument("--variant-tols", default="1e-1,1e-2,1e-4")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration for the traffic figure)")
     args = ap.parse_args()
@@ -380,6 +458,9 @@ def main():
         return
     if args.config == "sweep":
         bench_sweep(args)
+        return
+    if args.config == "variants":
+        bench_variants(args)
         return
     import torch
     from paper_1901_02971_amd import Solver

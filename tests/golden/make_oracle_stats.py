@@ -12,9 +12,12 @@ the sum of the kept sizes, and SHA-256 digests of the two int32 arrays
                sparsification (its size when the step does not sparsify it)
 
 in cluster order; plus s_top, m_F, and the PCG iteration count and true relative
-residual of every right-hand side.
+residual of every right-hand side.  With the interpolative variants (Sec. 2.6.2) a
+factorization that loses positive definiteness stores the site instead (step,
+cluster, phase).
 
-Usage:  python tests/golden/make_oracle_stats.py c3 [tol]
+Usage:  python tests/golden/make_oracle_stats.py c3 [tol [variant [rtol]]]
+        (variant OrthS, In or InS; files of In and InS end in _In / _InS)
 """
 import hashlib
 import json
@@ -50,14 +53,27 @@ def step_arrays(an, fac):
 def main():
     name = sys.argv[1]
     tol = float(sys.argv[2]) if len(sys.argv) > 2 else 1e-2
+    variant = sys.argv[3] if len(sys.argv) > 3 else "OrthS"
+    rtol = float(sys.argv[4]) if len(sys.argv) > 4 else 1e-12
     p, b, levels = gridgen.config_problem(name)
+    tag = f"{tol:.0e}".replace("e-0", "e-")
+    suffix = "" if variant == "OrthS" else "_" + variant
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"oracle_{name}_tol{tag}{suffix}.json")
     t0 = time.perf_counter()
     an = O.Analysis(p.n, p.rowptr, p.colind, p.coords, levels)
     t1 = time.perf_counter()
-    fac = O.factor(an, p.values, tol)
+    try:
+        fac = O.factor(an, p.values, tol, variant=variant)
+    except O.NotSPD as e:
+        rec = {"workload": name, "n": int(p.n), "levels": int(levels), "tol": tol, "skip": 0, "variant": variant,
+               "not_spd": {"step": int(e.step), "cluster": int(e.cluster), "phase": e.phase}}
+        with open(path, "w") as f:
+            json.dump(rec, f, indent=1)
+        print(f"{name} {variant}: not SPD at step {e.step}, cluster {e.cluster} ({e.phase}); wrote {path}", flush=True)
+        return
     t2 = time.perf_counter()
     print(f"{name}: analyze {t1 - t0:.1f}s factor {t2 - t1:.1f}s", flush=True)
-    _, it, rr = O.pcg(p.scipy(), b, lambda r: O.apply(fac, r))
+    _, it, rr = O.pcg(p.scipy(), b, lambda r: O.apply(fac, r), rtol)
     t3 = time.perf_counter()
     print(f"{name}: pcg {t3 - t2:.1f}s iters {it.tolist()} relres {rr.max():.2e}", flush=True)
     steps = []
@@ -65,12 +81,12 @@ def main():
         steps.append({"step": t, "clusters": int(len(sizes)), "size_sum": int(sizes.sum()),
                       "kept_sum": int(kept[kept >= 0].sum()), "sizes_sha256": digest(sizes),
                       "kept_sha256": digest(kept)})
-    rec = {"workload": name, "n": int(p.n), "levels": int(levels), "tol": tol, "skip": 0, "rtol": 1e-12,
+    rec = {"workload": name, "n": int(p.n), "levels": int(levels), "tol": tol, "skip": 0, "rtol": rtol,
            "maxit": 500, "s_top": int(fac.stats["s_top"]), "m_F": int(fac.stats["m_F"]),
            "pcg_iters": [int(v) for v in it], "relres": [float(v) for v in rr], "steps": steps,
            "oracle_seconds": {"analyze": round(t1 - t0, 1), "factor": round(t2 - t1, 1), "pcg": round(t3 - t2, 1)}}
-    tag = f"{tol:.0e}".replace("e-0", "e-")
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"oracle_{name}_tol{tag}.json")
+    if variant != "OrthS":
+        rec["variant"] = variant
     with open(path, "w") as f:
         json.dump(rec, f, indent=1)
     print(f"wrote {path}", flush=True)

@@ -26,9 +26,10 @@ def from_dev(t):
     return t.cpu().numpy().T.copy()
 
 
-def gpu_factor(p, levels, tol, skip=0, prec=0, geometry=True):
+def gpu_factor(p, levels, tol, skip=0, prec=0, geometry=True, variant="OrthS"):
     import torch
     s = Solver.from_problem(p, levels, geometry)
+    s.set_variant(variant)
     vals = torch.from_numpy(p.values).to("cuda:0")
     s.factor(vals, tol, skip, prec)
     return s

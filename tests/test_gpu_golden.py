@@ -1,6 +1,6 @@
 """GPU parity at the workload sizes, against the oracle's stored results.
 
-The stored files (tests/golden/oracle_<name>_tol<eps>.json) were written by
+The stored files (tests/golden/oracle_<name>_tol<eps>[_<variant>].json) were written by
 tests/golden/make_oracle_stats.py, which runs only the FP64 oracle on the seeded
 grid problems of gridgen.config_problem.  Bars: every step's cluster sizes and kept
 ranks identical (SHA-256 of the int32 arrays, sums reported on mismatch); s_top and
@@ -62,17 +62,47 @@ def check_against(ref, s):
     assert stats["m_F"] == ref["m_F"]
 
 
+PHASE = {"elim": 0, "scale": 1, "sparsify": 2}
+
+
 @pytest.mark.parametrize("path", cases())
 def test_workload_matches_oracle(path):
+    """Records of the interpolative variants (file names ending in _In / _InS) run
+    that variant; a record of a lost positive definiteness expects SPAND_E_NOT_SPD at
+    the same step, cluster and phase."""
     with open(path) as f:
         ref = json.load(f)
     p, b, levels = gridgen.config_problem(ref["workload"])
     assert levels == ref["levels"] and p.n == ref["n"]
-    s = gpu_factor(p, levels, ref["tol"], ref["skip"])
+    variant = ref.get("variant", "OrthS")
+    if "not_spd" in ref:
+        from paper_1901_02971_amd import SpandError
+        with pytest.raises(SpandError) as e:
+            gpu_factor(p, levels, ref["tol"], ref["skip"], variant=variant)
+        assert e.value.name == "SPAND_E_NOT_SPD"
+        return
+    s = gpu_factor(p, levels, ref["tol"], ref["skip"], variant=variant)
     check_against(ref, s)
     _, it, rr, _ = gpu_solve(s, b, ref["rtol"], ref["maxit"])
     assert np.all(np.abs(it - np.array(ref["pcg_iters"])) <= 1), (it.tolist(), ref["pcg_iters"])
-    assert np.all(rr <= 1e-12), rr
+    assert np.all(rr <= ref["rtol"]), rr
+
+
+@pytest.mark.parametrize("path", [c for c in cases() if "not_spd" in json.load(open(c.values[0]))])
+def test_workload_breakdown_site(path):
+    """The failure site of a stored interpolative breakdown: step, cluster and phase."""
+    from paper_1901_02971_amd import Solver, SpandError
+    with open(path) as f:
+        ref = json.load(f)
+    p, _, levels = gridgen.config_problem(ref["workload"])
+    s = Solver.from_problem(p, levels)
+    s.set_variant(ref["variant"])
+    with pytest.raises(SpandError):
+        s.factor(torch.from_numpy(p.values).to("cuda:0"), ref["tol"], ref["skip"])
+    st = s.stats()
+    site = ref["not_spd"]
+    assert (st["fail_step"], st["fail_cluster"], st["fail_phase"]) == \
+        (site["step"], site["cluster"], PHASE[site["phase"]])
 
 
 def reduced_cases():
