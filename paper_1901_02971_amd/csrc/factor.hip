@@ -82,7 +82,9 @@ struct Layout {
   std::vector<int64_t> pan_ptr;  // nc+1
   std::vector<int32_t> prow;     // row cluster of each panel entry (diagonal first)
   std::vector<int64_t> proff;    // row offset of each entry inside its panel
-  std::vector<int64_t> H;        // panel heights
+  std::vector<int64_t> H;        // leading dimension of each panel: its height rounded up to 16
+                                 // entries, so every column starts on a 128-byte line
+  std::vector<int64_t> Hr;       // panel heights (rows in use)
   std::vector<int64_t> base;     // panel start (elements) inside its buffer
   int64_t total_elim = 0, total_arena = 0;
   int64_t find(int32_t i, int32_t j) const {
@@ -111,6 +113,7 @@ void build_layout(const SymStep& st, const std::vector<int32_t>& size, Layout& L
   // `before` (j < ne) and `after` (j >= ne) touch disjoint panels, each in ascending i
   each([&](uint64_t p) { L.prow[fill[pair_j(p)]++] = pair_i(p); });
   L.H.assign(nc, 0);
+  L.Hr.assign(nc, 0);
   L.base.assign(nc, 0);
   int64_t te = 0, ta = 0;
   for (int32_t j = 0; j < nc; ++j) {
@@ -119,7 +122,9 @@ void build_layout(const SymStep& st, const std::vector<int32_t>& size, Layout& L
       L.proff[e] = h;
       h += size[L.prow[e]];
     }
-    L.H[j] = h;
+    L.Hr[j] = h;
+    L.H[j] = (h + 15) / 16 * 16;
+    h = L.H[j];
     int64_t& tot = (j < ne) ? te : ta;
     L.base[j] = tot;
     tot += h * size[j];
@@ -1239,7 +1244,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
         pb.nN.assign(ne, 0);
         int64_t cbuf_total = 0, ed_total = 0;
         for (int32_t s = 0; s < ne; ++s) {
-          pb.nN[s] = int32_t(lay.H[s] - sn.size[s]);
+          pb.nN[s] = int32_t(lay.Hr[s] - sn.size[s]);
           pb.c_off[s] = cbuf_total;
           cbuf_total += int64_t(pb.nN[s]) * pb.nN[s];
           pb.ed_off[s] = ed_total;
@@ -1254,7 +1259,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
         for (int32_t s = 0; s < ne; ++s)
           if (sn.size[s] > 0)
             fr.push_back(Front{E + lay.base[s], sn.edinv.as<double>() + pb.ed_off[s], int32_t(lay.H[s]), sn.size[s],
-                               int32_t(lay.H[s]), s, P[qid].flags + 0});
+                               int32_t(lay.Hr[s]), s, P[qid].flags + 0});
         for (int32_t s = 0; s < ne; ++s) {
           const int32_t ns = sn.size[s], nn = pb.nN[s];
           GemmDesc y{};
@@ -1366,7 +1371,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
         double* SD = sn.sdinv.as<double>();
         for (int32_t p = ne; p < nc; ++p)
           if (sn.size[p] > 0)
-            fr.push_back(Front{A + lay.base[p], SD + pb.sd_off[p], int32_t(lay.H[p]), sn.size[p], int32_t(lay.H[p]), p,
+            fr.push_back(Front{A + lay.base[p], SD + pb.sd_off[p], int32_t(lay.H[p]), sn.size[p], int32_t(lay.Hr[p]), p,
                                pb.flags + 1});
         // L_p^{-1} for the apply (the identity solved against L_p), and L_i^{-1} from the
         // left on every block (i, p), in one blocked left solve
