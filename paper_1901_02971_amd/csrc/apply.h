@@ -16,6 +16,10 @@ struct ElimAp {
   int64_t slot_s;      // offset of s's slots in the step slot array
   int64_t slot_N;      // offset of s's neighbour slots in the step neighbour-slot array
   int64_t tmp;         // offset of s's rows in the apply scratch: t, then nchunk > 1 partial sums
+  int64_t ytmp;        // offset of the nN rows of y = G L_s^{-1} x_s (forward sweep) in the scratch
+};
+struct FwdTile {      // panel rows [r0, r0 + 64) of eliminated cluster s (r0 a multiple of 64), those of G
+  int32_t s, r0;
 };
 struct ElimTile {     // columns [k0, min(k0 + 64, ns)) of eliminated cluster s, rows of G in chunk c
   int32_t s, k0, c, pad;
@@ -26,9 +30,7 @@ struct TargetAp {     // rows [r0, min(r0 + 64, nn)) of receiving cluster n
   int64_t slot_n;
 };
 struct TargetContrib {
-  const double* G;  // rows of n inside G_s, ld ldG
-  int32_t ldG, ns;
-  int64_t tmp_s;    // where L_s^{-1} x_s lives in the apply scratch
+  int64_t y;        // where the rows of n of y_s = G_s L_s^{-1} x_s live in the apply scratch
 };
 struct ScaleAp {
   const double* Linv;  // np x np lower-triangular L_p^{-1}, ld np
@@ -79,6 +81,8 @@ struct StepDev {
   const ScaleAp* scale;
   const HouseAp* house;
   const ElimTile* etile;
+  const FwdTile* ftile;    // 64-row tiles of every G_s for the forward products
+  int32_t n_ftile, pad_ftile;
   const ScaleTile* stile;  // row tiles of every L_p^{-1}
   const int32_t* sgather;  // slot of every scratch row of the scaled interfaces
   int64_t sgather_len;

@@ -192,9 +192,10 @@ struct StepNum {
                                 // (scale holds L_p^{-1} itself)
   DevBuf d_slot, d_nslot;       // slot arrays on the device
   // apply descriptors
-  DevBuf d_elim, d_target, d_contrib, d_scale, d_house, d_etile, d_hr, d_hv, d_stile, d_sgather, d_iface;
+  DevBuf d_elim, d_target, d_contrib, d_scale, d_house, d_etile, d_ftile, d_hr, d_hv, d_stile, d_sgather, d_iface;
   int32_t n_iface1 = 0, n_iface2 = 0;  // small interfaces with np <= 64, then np <= 128
   int32_t n_elim_ap = 0, n_target = 0, n_scale = 0, n_house = 0, n_etile = 0, n_hr = 0, n_hv = 0, n_stile = 0;
+  int32_t n_ftile = 0;
   int64_t sgather_len = 0;
   int64_t nslot_len = 0;
   int64_t tmp_elim = 0, tmp_scale = 0;  // doubles per RHS of temp needed
@@ -204,6 +205,7 @@ struct StepNum {
   std::vector<ScaleAp> h_scale;
   std::vector<HouseAp> h_house;
   std::vector<ElimTile> h_etile;
+  std::vector<FwdTile> h_ftile;
   std::vector<HouseTile> h_hr, h_hv;
   std::vector<ScaleTile> h_stile;
   std::vector<int32_t> h_sgather;

@@ -372,9 +372,19 @@ spand_status build_apply(spand_ctx* h, const SymStep& sy, StepNum& sn, const Lay
     e.nchunk = std::max(1, (e.nN + ELIM_RC - 1) / ELIM_RC);
     e.tmp = tmp;
     tmp += int64_t(std::max(e.ns, 1)) * (e.nchunk > 1 ? 1 + e.nchunk : 1);
+    e.ytmp = tmp;
+    tmp += e.nN;
     sn.h_elim.push_back(e);
   }
   sn.tmp_elim = tmp;
+  // forward products y_s = G_s (L_s^{-1} x_s): 64-row tiles at multiples of 64 panel
+  // rows covering the rows of G (ns .. ns + nN)
+  sn.h_ftile.clear();
+  for (int32_t s = 0; s < ne; ++s) {
+    const ElimAp& e = sn.h_elim[s];
+    if (e.ns == 0 || e.nN == 0) continue;
+    for (int32_t r0 = e.ns / 64 * 64; r0 < e.ns + e.nN; r0 += 64) sn.h_ftile.push_back(FwdTile{s, r0});
+  }
   sn.h_etile.clear();
   for (int32_t s = 0; s < ne; ++s)
     for (int32_t c = 0; c < sn.h_elim[s].nchunk; ++c)
@@ -401,7 +411,7 @@ spand_status build_apply(spand_ctx* h, const SymStep& sy, StepNum& sn, const Lay
     ta.cbeg = int32_t(sn.h_contrib.size());
     while (r < tis.size() && tis[r].n == tis[q].n) {
       const int32_t s = tis[r].s;
-      sn.h_contrib.push_back(TargetContrib{sn.h_elim[s].G + tis[r].row, sn.h_elim[s].ld, sn.size[s], sn.h_elim[s].tmp});
+      sn.h_contrib.push_back(TargetContrib{sn.h_elim[s].ytmp + tis[r].row});
       ++r;
     }
     ta.cend = int32_t(sn.h_contrib.size());
@@ -481,6 +491,7 @@ spand_status build_apply(spand_ctx* h, const SymStep& sy, StepNum& sn, const Lay
   sn.n_scale = int32_t(sn.h_scale.size());
   sn.n_house = int32_t(sn.h_house.size());
   sn.n_etile = int32_t(sn.h_etile.size());
+  sn.n_ftile = int32_t(sn.h_ftile.size());
   sn.n_stile = int32_t(sn.h_stile.size());
   sn.sgather_len = int64_t(sn.h_sgather.size());
   sn.n_hr = int32_t(sn.h_hr.size());
@@ -494,6 +505,7 @@ spand_status build_apply(spand_ctx* h, const SymStep& sy, StepNum& sn, const Lay
   if ((st = upload(h, sn.d_scale, sn.h_scale)) != SPAND_OK) return st;
   if ((st = upload(h, sn.d_house, sn.h_house)) != SPAND_OK) return st;
   if ((st = upload(h, sn.d_etile, sn.h_etile)) != SPAND_OK) return st;
+  if ((st = upload(h, sn.d_ftile, sn.h_ftile)) != SPAND_OK) return st;
   if ((st = upload(h, sn.d_stile, sn.h_stile)) != SPAND_OK) return st;
   if ((st = upload(h, sn.d_sgather, sn.h_sgather)) != SPAND_OK) return st;
   if ((st = upload(h, sn.d_hr, sn.h_hr)) != SPAND_OK) return st;

@@ -6,9 +6,9 @@
 //   k_elim_fwd    x_s <- L_s^{-1} x_s            (one workgroup per eliminated s;
 //                                                  blocked substitution with the
 //                                                  inverses of the diagonal blocks)
-//   k_target_fwd  x_n <- x_n - sum_s G_ns x_s     (one workgroup per 64-row tile of a
-//                                                  receiving n, contributions in
-//                                                  ascending s)
+//   k_fwd_gemv    y_s <- G_{N_s s} x_s            (one workgroup per 64 panel rows of
+//                                                  s, on the panel's 128-byte lines)
+//   k_target_sum  x_n <- x_n - sum_s y_s (rows of n) (contributions in ascending s)
 //   k_iface<1>    x_p <- Q_p^T L_p^{-1} x_p      (interfaces of at most 128 dofs, one wave each)
 //   k_scale<1>    x_p <- L_p^{-1} x_p                (larger interfaces: explicit inverse, 64-row tiles)
 //   k_house_*     x_p <- Q_p^T x_p                (compact WY form, three tile launches)
@@ -120,10 +120,10 @@ __device__ inline void mfma_out(const dbl4& c, TileShared& sh, double acc[2]) {
 // that consecutive calls keep alternating the two x buffers.
 __device__ void mfma_n_acc(const double* __restrict__ A, int ld, int r0, int nrows, int ncols,
                            const double* __restrict__ x, int64_t ldx, int nr, TileShared& sh, dbl4& c, int& tpar,
-                           const int32_t* __restrict__ xsl = nullptr) {
+                           const int32_t* __restrict__ xsl = nullptr, int rlo = 0) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, i = lane & 15, kq = lane >> 4;
   const int row = r0 + 16 * w + i;
-  const bool rok = row < nrows;
+  const bool rok = row >= rlo && row < nrows;
   const int nt = (ncols + 63) >> 6;
   const __amdgpu_buffer_rsrc_t ar = block_rsrc(A, ncols > 0 ? (int64_t)(ncols - 1) * ld + nrows : 0);
   double a0[16], a1[16], x0[2], x1[2];
@@ -155,13 +155,13 @@ __device__ void mfma_n_acc(const double* __restrict__ A, int ld, int r0, int nro
   tpar += nt;
 }
 
-// acc += A[(r0 + rr) + k*ld] x[k], k < ncols (rows beyond nrows read as zero)
+// acc += A[(r0 + rr) + k*ld] x[k], k < ncols (rows below rlo or from nrows on read as zero)
 __device__ void tile_gemv_n(const double* __restrict__ A, int ld, int r0, int nrows, int ncols,
                             const double* __restrict__ x, int64_t ldx, int nr, TileShared& sh, double acc[2],
-                            const int32_t* __restrict__ xsl = nullptr) {
+                            const int32_t* __restrict__ xsl = nullptr, int rlo = 0) {
   dbl4 c = {0.0, 0.0, 0.0, 0.0};
   int tpar = 0;
-  mfma_n_acc(A, ld, r0, nrows, ncols, x, ldx, nr, sh, c, tpar, xsl);
+  mfma_n_acc(A, ld, r0, nrows, ncols, x, ldx, nr, sh, c, tpar, xsl, rlo);
   __syncthreads();  // the last x tile has been read
   mfma_out(c, sh, acc);
 }
@@ -358,32 +358,42 @@ __global__ void __launch_bounds__(AW, 2) k_elim_fwd(const ElimAp* __restrict__ d
   scatter_seg(sl, e.ns, a, e.tmp);
 }
 
-// x_n -= sum_s G_ns y_s over the contributions of n in ascending s
-__global__ void __launch_bounds__(AW) k_target_fwd(const TargetAp* __restrict__ ts, const TargetContrib* __restrict__ cs,
-                                                   ApplyArgs a) {
+// y_s = G_s L_s^{-1} x_s for the panel rows [r0, r0 + 64) of s (those of G: rows ns
+// to ns + nN): the tiles follow the panel's 128-byte lines, so every G entry is read
+// once, in whole lines; L_s^{-1} x_s comes from the scratch where k_elim_fwd left it.
+__global__ void __launch_bounds__(AW) k_fwd_gemv(const ElimAp* __restrict__ ds, const FwdTile* __restrict__ ft,
+                                                 ApplyArgs a) {
   __shared__ TileShared sh;
-  const TargetAp t = ts[blockIdx.x];
-  const int32_t* sl = a.slot + t.slot_n;
+  const FwdTile f = ft[blockIdx.x];
+  const ElimAp e = ds[f.s];
   const int rr = threadIdx.x & 63, g = threadIdx.x >> 6;
-  const int r0 = t.r0;
+  const int row = f.r0 + rr;
+  const bool rok = row >= e.ns && row < e.ns + e.nN;
   for (int c0 = 0; c0 < a.nrhs; c0 += RB) {
     const int nr = min(RB, a.nrhs - c0);
-    dbl4 c = {0.0, 0.0, 0.0, 0.0};
-    int tpar = 0;
-    for (int q = t.cbeg; q < t.cend; ++q) {
-      const TargetContrib tc = cs[q];
-      mfma_n_acc(tc.G, tc.ldG, r0, t.nn, tc.ns, a.tmp + tc.tmp_s + (int64_t)c0 * a.ldt, a.ldt, nr, sh, c, tpar);
-    }
-    __syncthreads();  // the last x tile has been read
     double acc[2] = {0.0, 0.0};
-    mfma_out(c, sh, acc);
-    if (r0 + rr < t.nn) {
-      double* xp = a.x + sl[r0 + rr] + (int64_t)c0 * a.ldx;
-      const double x0 = g < nr ? xp[(int64_t)g * a.ldx] : 0.0;
-      const double x1 = g + 4 < nr ? xp[(int64_t)(g + 4) * a.ldx] : 0.0;
-      if (g < nr) xp[(int64_t)g * a.ldx] = x0 - acc[0];
-      if (g + 4 < nr) xp[(int64_t)(g + 4) * a.ldx] = x1 - acc[1];
+    tile_gemv_n(e.L, e.ld, f.r0, e.ns + e.nN, e.ns, a.tmp + e.tmp + (int64_t)c0 * a.ldt, a.ldt, nr, sh, acc,
+                nullptr, e.ns);
+    if (rok) {
+      double* yp = a.tmp + e.ytmp + (row - e.ns) + (int64_t)c0 * a.ldt;
+      if (g < nr) yp[(int64_t)g * a.ldt] = acc[0];
+      if (g + 4 < nr) yp[(int64_t)(g + 4) * a.ldt] = acc[1];
     }
+  }
+}
+
+// x_n -= sum_s y_s (the rows of n), the contributions of n in ascending s
+__global__ void __launch_bounds__(AW) k_target_sum(const TargetAp* __restrict__ ts, const TargetContrib* __restrict__ cs,
+                                                   ApplyArgs a) {
+  const TargetAp t = ts[blockIdx.x];
+  const int rr = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int r = t.r0 + rr;
+  if (r >= t.nn) return;
+  const int64_t xo = a.slot[t.slot_n + r];
+  for (int c = g; c < a.nrhs; c += 4) {
+    double acc = 0.0;
+    for (int q = t.cbeg; q < t.cend; ++q) acc += a.tmp[cs[q].y + r + (int64_t)c * a.ldt];
+    a.x[xo + (int64_t)c * a.ldx] -= acc;
   }
 }
 
@@ -721,7 +731,8 @@ __global__ void __launch_bounds__(AW) k_elim_bwd(const ElimAp* __restrict__ ds, 
 
 void apply_step_forward(const StepDev& s, const ApplyArgs& a, hipStream_t st) {
   if (s.n_elim) hipLaunchKernelGGL(k_elim_fwd, dim3(s.n_elim), dim3(AW), 0, st, s.elim, a);
-  if (s.n_target) hipLaunchKernelGGL(k_target_fwd, dim3(s.n_target), dim3(AW), 0, st, s.target, s.contrib, a);
+  if (s.n_ftile) hipLaunchKernelGGL(k_fwd_gemv, dim3(s.n_ftile), dim3(AW), 0, st, s.elim, s.ftile, a);
+  if (s.n_target) hipLaunchKernelGGL(k_target_sum, dim3(s.n_target), dim3(AW), 0, st, s.target, s.contrib, a);
   if (s.n_iface1) hipLaunchKernelGGL((k_iface<1, 1>), dim3(s.n_iface1), dim3(64), 0, st, s.iface, a);
   if (s.n_iface2) hipLaunchKernelGGL((k_iface<1, 2>), dim3(s.n_iface2), dim3(64), 0, st, s.iface + s.n_iface1, a);
   if (s.n_stile) {

@@ -34,6 +34,8 @@ StepDev step_dev(const StepNum& s) {
   d.house = s.d_house.as<HouseAp>();
   d.etile = s.d_etile.as<ElimTile>();
   d.n_etile = s.n_etile;
+  d.ftile = s.d_ftile.as<FwdTile>();
+  d.n_ftile = s.n_ftile;
   d.stile = s.d_stile.as<ScaleTile>();
   d.n_stile = s.n_stile;
   d.sgather = s.d_sgather.as<int32_t>();
@@ -356,7 +358,7 @@ spand_status pool_upload(spand_ctx* h, DevBuf& b, const std::vector<T>& v) {
 // earlier problems' parts.  Every descriptor still computes what it computes alone.
 struct MergedStep {
   StepDev d{};
-  DevBuf slot, nslot, elim, target, contrib, scale, house, etile, stile, sgather, hr, hv, iface;
+  DevBuf slot, nslot, elim, target, contrib, scale, house, etile, ftile, stile, sgather, hr, hv, iface;
 };
 
 spand_status build_merged(spand_ctx* const* hs, int32_t P, const std::vector<int64_t>& off,
@@ -377,6 +379,7 @@ spand_status build_merged(spand_ctx* const* hs, int32_t P, const std::vector<int
     std::vector<ScaleAp> scale;
     std::vector<HouseAp> house;
     std::vector<ElimTile> etile;
+    std::vector<FwdTile> ftile;
     std::vector<ScaleTile> stile;
     std::vector<HouseTile> hr, hv;
     std::vector<IfaceAp> if1, if2;
@@ -393,6 +396,7 @@ spand_status build_merged(spand_ctx* const* hs, int32_t P, const std::vector<int
         e.slot_s += so;
         e.slot_N += no;
         e.tmp += te;
+        e.ytmp += te;
         elim.push_back(e);
       }
       for (TargetAp a : sn.h_target) {
@@ -402,7 +406,7 @@ spand_status build_merged(spand_ctx* const* hs, int32_t P, const std::vector<int
         target.push_back(a);
       }
       for (TargetContrib c : sn.h_contrib) {
-        c.tmp_s += te;
+        c.y += te;
         contrib.push_back(c);
       }
       for (ScaleAp a : sn.h_scale) {
@@ -418,6 +422,10 @@ spand_status build_merged(spand_ctx* const* hs, int32_t P, const std::vector<int
       for (ElimTile e : sn.h_etile) {
         e.s += eo;
         etile.push_back(e);
+      }
+      for (FwdTile f : sn.h_ftile) {
+        f.s += eo;
+        ftile.push_back(f);
       }
       for (ScaleTile s2 : sn.h_stile) {
         s2.p += sco;
@@ -458,6 +466,7 @@ spand_status build_merged(spand_ctx* const* hs, int32_t P, const std::vector<int
     if ((st = pool_upload(h, m.scale, scale)) != SPAND_OK) return st;
     if ((st = pool_upload(h, m.house, house)) != SPAND_OK) return st;
     if ((st = pool_upload(h, m.etile, etile)) != SPAND_OK) return st;
+    if ((st = pool_upload(h, m.ftile, ftile)) != SPAND_OK) return st;
     if ((st = pool_upload(h, m.stile, stile)) != SPAND_OK) return st;
     if ((st = pool_upload(h, m.sgather, sgather)) != SPAND_OK) return st;
     if ((st = pool_upload(h, m.hr, hr)) != SPAND_OK) return st;
@@ -473,6 +482,8 @@ spand_status build_merged(spand_ctx* const* hs, int32_t P, const std::vector<int
     d.house = m.house.as<HouseAp>();
     d.etile = m.etile.as<ElimTile>();
     d.n_etile = int32_t(etile.size());
+    d.ftile = m.ftile.as<FwdTile>();
+    d.n_ftile = int32_t(ftile.size());
     d.stile = m.stile.as<ScaleTile>();
     d.n_stile = int32_t(stile.size());
     d.sgather = m.sgather.as<int32_t>();
