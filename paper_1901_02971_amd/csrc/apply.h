@@ -156,5 +156,8 @@ void launch_update_p(int64_t n, int nrhs, const double* rz_new, const double* rz
                      const double* z, double* p, hipStream_t s);
 void launch_residual(int64_t len, const double* b, double* y, hipStream_t s);
 void launch_copy_vec(const double* r, double* z, int64_t len, hipStream_t s);
+// dst[i + c ld] = src[idx[i] + c ld] for i < n and the nrhs columns
+void launch_permute(const double* src, double* dst, const int32_t* idx, int64_t n, int nrhs, int64_t ld,
+                    hipStream_t s);
 
 }  // namespace spand

@@ -238,6 +238,10 @@ struct spand_ctx {
   spand::DevBuf d_dst1;                         // step-1 destination of every CSR entry (pattern-only)
   int64_t max_tmp = 0;                          // doubles per RHS for apply scratch
   int64_t max_gather = 0;                       // doubles per RHS for gathered neighbours
+  // The apply works on its vector in the order in which the factorization freezes the
+  // dofs (every cluster's slots are then a few contiguous runs); the device slot arrays
+  // hold positions in that order.  d_pos[v] = position of vertex v, d_inv its inverse.
+  spand::DevBuf d_pos, d_inv;
   // PCG / apply scratch, grown on demand
   spand::DevBuf work;
   size_t work_bytes = 0;

@@ -536,6 +536,7 @@ struct Prob {
   double elim_flops = 0.0, cpqr_flops = 0.0;
   int64_t cpqr_ifaces[4] = {0, 0, 0, 0};  // single, wide, multi (32 x 2), multi (20 x 3)
   int32_t s_top = 0;
+  std::vector<int32_t> frozen;  // vertices in the order the steps freeze them (freeze_order)
   // this step
   bool on = false, sparsify = false;
   int64_t cbase = 0;            // first entry of this problem's clusters in the run's size and rank arrays
@@ -1105,6 +1106,53 @@ spand_status sparsify_interp(Prob& pb, int32_t t, double tol, double& cpqr_ms, i
   return SPAND_OK;
 }
 
+// The order in which the factorization freezes the dofs: step by step, the slots of
+// every eliminated cluster, then those an interface drops at its sparsification (the
+// slots from its rank on), each in slot-list order.  In this order every cluster's
+// slot list at every step is a few contiguous runs (its dropped part, and the kept
+// parts of its children inside the parents they are frozen with), so the apply's
+// gathers and scatters through the slots read whole lines.  The order grows step by
+// step on the host (frozen_at); at the end the device slot arrays of every step are
+// rewritten with positions in this order by one kernel.  The host keeps the vertex
+// ids (the batched solve works in vertex order).
+void frozen_at(const SymStep& sy, const StepNum& sn, std::vector<int32_t>& inv) {
+  for (int32_t c = 0; c < sy.nc; ++c) {
+    const int64_t b = sn.slot_ptr[c];
+    const int32_t size = sn.size[c];
+    const int32_t from = c < sy.ne ? 0 : std::max(0, std::min(size, sn.rank[c]));
+    inv.insert(inv.end(), sn.slot.begin() + b + from, sn.slot.begin() + b + size);
+  }
+}
+
+spand_status freeze_order(spand_ctx* h, std::vector<int32_t>& inv) {
+  const int64_t n = h->an.n;
+  if (int64_t(inv.size()) != n) return set_err(h, SPAND_E_INVALID, "freeze order does not cover every dof");
+  std::vector<int32_t> pos(static_cast<size_t>(n), -1);
+  for (int64_t k = 0; k < n; ++k) {
+    const int32_t v = inv[k];
+    if (v < 0 || v >= n || pos[v] >= 0) return set_err(h, SPAND_E_INVALID, "freeze order is not a permutation");
+    pos[v] = int32_t(k);
+  }
+  spand_status st;
+  if ((st = upload(h, h->d_pos, pos)) != SPAND_OK) return st;
+  if ((st = upload(h, h->d_inv, inv)) != SPAND_OK) return st;
+  std::vector<RemapSeg> segs;
+  auto add = [&](DevBuf& b, int64_t len) {
+    for (int64_t o = 0; o < len; o += REMAP_CHUNK)
+      segs.push_back(RemapSeg{b.as<int32_t>() + o, std::min<int64_t>(REMAP_CHUNK, len - o)});
+  };
+  for (StepNum& sn : h->num) {
+    add(sn.d_slot, int64_t(sn.slot.size()));
+    add(sn.d_nslot, int64_t(sn.h_nslot.size()));
+    add(sn.d_sgather, int64_t(sn.h_sgather.size()));
+  }
+  DevBuf dsg;
+  if ((st = upload_big(h, dsg, segs)) != SPAND_OK) return st;
+  launch_remap(dsg.as<RemapSeg>(), int64_t(segs.size()), h->d_pos.as<int32_t>(), h->stream);
+  HIPCHK(hipGetLastError());
+  return SPAND_OK;
+}
+
 // Problem index and cluster of a failure id of a run (ids carry the problem in
 // their high bits so that one flag word may serve several problems).
 constexpr int32_t FAIL_NONE = 0x7fffffff;
@@ -1123,6 +1171,10 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
     pb.h->num.resize(pb.L);
     pb.h->max_tmp = 0;
     pb.h->max_gather = 0;
+    pb.h->d_pos.release();
+    pb.h->d_inv.release();
+    pb.frozen.clear();
+    pb.frozen.reserve(size_t(pb.h->an.n));
     std::memset(pb.h->stats.step_phase_seconds, 0, sizeof(pb.h->stats.step_phase_seconds));
     std::memset(pb.h->stats.step_m_F, 0, sizeof(pb.h->stats.step_m_F));
   }
@@ -1899,6 +1951,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
         // next step runs
         pb.t_pending = std::move(tds);
       }
+      frozen_at(sy, sn, pb.frozen);
       if (t <= 32) hq->stats.step_m_F[t - 1] = pb.m_F;
       pb.pending = ApplyPlan{t, std::move(pb.ed_off), std::move(pb.sc_off), std::move(pb.v_off), std::move(pb.t_off),
                              std::move(pb.nN), std::move(pb.nref)};
@@ -1921,6 +1974,8 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
     if ((st = build_apply(pb.h, pb.h->an.steps[pt - 1], pb.h->num[pt - 1], pb.lay_prev, pb.pending)) != SPAND_OK)
       return st;
   }
+  for (Prob& pb : P)
+    if (pb.live && (st = freeze_order(pb.h, pb.frozen)) != SPAND_OK) return st;
   HIPCHK(hipStreamSynchronize(h->stream));
   double elim_ms = 0.0;
   double phase_s[32][4] = {};
@@ -1950,7 +2005,8 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
     s.cpqr_launches = cpqr_launches;
     for (int q = 0; q < 4; ++q) s.cpqr_interfaces[q] = pb.cpqr_ifaces[q];
     s.cpqr_big_interfaces = pb.cpqr_big;
-    s.apply_scratch_per_rhs = std::max<int64_t>(pb.h->max_tmp, 1) + std::max<int64_t>(pb.h->max_gather, 1);
+    s.apply_scratch_per_rhs = std::max<int64_t>(pb.h->max_tmp, 1) + std::max<int64_t>(pb.h->max_gather, 1) +
+                              (pb.h->d_inv.p ? pb.h->an.n : 0);
     for (int q = 0; q < 3; ++q) s.apply_interfaces[q] = 0;
     for (const StepNum& sn : pb.h->num) {
       s.apply_interfaces[0] += sn.n_iface1;

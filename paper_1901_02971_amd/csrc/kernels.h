@@ -87,6 +87,12 @@ struct ZeroDesc {  // len (<= ZERO_CHUNK) doubles at p set to zero
 };
 #define ZERO_CHUNK 65536
 void launch_zero(const ZeroDesc* d, int64_t count, hipStream_t s);
+struct RemapSeg {  // p[k] <- pos[p[k]] for k < len (<= REMAP_CHUNK)
+  int32_t* p;
+  int64_t len;
+};
+#define REMAP_CHUNK 65536
+void launch_remap(const RemapSeg* d, int64_t count, const int32_t* pos, hipStream_t s);
 
 // Sparsification of one interface p (Sec. 2.6.1).  A_pn is held in the registers of
 // S workgroups (slabs) of CAP = cpqr_capacity(G) columns each.  The width of A_pn is

@@ -855,6 +855,19 @@ __global__ void k_update_p(int64_t n, int nrhs, const double* __restrict__ rz_ne
 }
 
 // z = r (plain copy; a kernel so that the apply can be captured into a graph)
+__global__ void k_permute(const double* __restrict__ src, double* __restrict__ dst, const int32_t* __restrict__ idx,
+                          int64_t n, int nrhs, int64_t ld) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t from = idx[i];
+  for (int c = 0; c < nrhs; ++c) dst[i + (int64_t)c * ld] = src[from + (int64_t)c * ld];
+}
+
+void launch_permute(const double* src, double* dst, const int32_t* idx, int64_t n, int nrhs, int64_t ld,
+                    hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_permute, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, src, dst, idx, n, nrhs, ld);
+}
+
 __global__ void k_copy_vec(const double* __restrict__ r, double* __restrict__ z, int64_t len) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < len) z[i] = r[i];

@@ -195,4 +195,13 @@ void launch_zero(const ZeroDesc* d, int64_t count, hipStream_t s) {
   hipLaunchKernelGGL(k_zero, dim3(count), dim3(WG), 0, s, d);
 }
 
+__global__ void __launch_bounds__(WG) k_remap(const RemapSeg* __restrict__ d, const int32_t* __restrict__ pos) {
+  const RemapSeg g = d[blockIdx.x];
+  for (int64_t k = threadIdx.x; k < g.len; k += WG) g.p[k] = pos[g.p[k]];
+}
+
+void launch_remap(const RemapSeg* d, int64_t count, const int32_t* pos, hipStream_t s) {
+  if (count > 0) hipLaunchKernelGGL(k_remap, dim3(unsigned(count)), dim3(WG), 0, s, d, pos);
+}
+
 }  // namespace spand

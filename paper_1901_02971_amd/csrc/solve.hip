@@ -74,20 +74,26 @@ spand_status ensure_work(spand_ctx* h, size_t bytes) {
 
 }  // namespace
 
-// z = M M^T r on stream st; scratch holds (max_tmp + max_gather) * nrhs doubles.
+// z = M M^T r on stream st; scratch holds apply_scratch_doubles(h, nrhs) doubles.
 // Only kernels are launched (no memset or memcpy nodes), so the sequence can be
-// captured into a graph.
+// captured into a graph.  The sweeps run on a copy of r in the factorization's
+// freeze order (h->d_inv), which comes back to the vertex order at the end.
 spand_status apply_precond(spand_ctx* h, int32_t nrhs, const double* r, double* z, double* scratch, hipStream_t st) {
   const int64_t n = h->an.n;
-  if (z != r) launch_copy_vec(r, z, n * nrhs, st);
   ApplyArgs a{};
-  a.x = z;
-  a.ldx = n;
   a.nrhs = nrhs;
   a.tmp = scratch;
   a.ldt = std::max<int64_t>(h->max_tmp, 1);
   a.gbuf = scratch + a.ldt * nrhs;
   a.ldg = std::max<int64_t>(h->max_gather, 1);
+  a.ldx = n;
+  if (h->d_inv.p) {
+    a.x = a.gbuf + a.ldg * nrhs;
+    launch_permute(r, a.x, h->d_inv.as<int32_t>(), n, nrhs, n, st);
+  } else {
+    a.x = z;
+    if (z != r) launch_copy_vec(r, z, n * nrhs, st);
+  }
   for (size_t t = 0; t < h->num.size(); ++t) {
     const StepDev d = step_dev(h->num[t]);
     a.slot = d.slot;
@@ -98,6 +104,7 @@ spand_status apply_precond(spand_ctx* h, int32_t nrhs, const double* r, double* 
     a.slot = d.slot;
     apply_step_backward(d, a, st);
   }
+  if (h->d_inv.p) launch_permute(a.x, z, h->d_pos.as<int32_t>(), n, nrhs, n, st);
   HIPCHK(hipGetLastError());
   return SPAND_OK;
 }
@@ -130,7 +137,8 @@ bool capture_apply(spand_ctx* h, int32_t nrhs, const double* r, double* z, doubl
 }  // namespace
 
 size_t apply_scratch_doubles(const spand_ctx* h, int32_t nrhs) {
-  return size_t(std::max<int64_t>(h->max_tmp, 1) + std::max<int64_t>(h->max_gather, 1)) * size_t(nrhs);
+  const int64_t perm = h->d_inv.p ? h->an.n : 0;
+  return size_t(std::max<int64_t>(h->max_tmp, 1) + std::max<int64_t>(h->max_gather, 1) + perm) * size_t(nrhs);
 }
 
 spand_status apply_public(spand_ctx* h, int32_t nrhs, const double* r, double* z) {
