@@ -1197,6 +1197,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
 
   EventPool phev;   // 5 phase boundaries per step, read after the last sync
   EventPool evpool; // every CPQR launch
+  EventPool rbev;   // the rank read-back of every step
   std::vector<char> elim_ran(size_t(Lmax) + 1, 0);
   double cpqr_ms = 0.0;
   int64_t cpqr_launches = 0;
@@ -1854,8 +1855,25 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
       HIPCHK(hipEventRecord(ph[4], h->stream));
     }
 
-    // ---- while the step's last kernels run: the previous step's T factors and apply
-    // descriptors; then one sync for the flags of every problem and the ranks
+    // ---- the flags of every problem and the ranks go to pinned host memory right
+    // behind the step's kernels; the previous step's T factors and apply descriptors
+    // are enqueued after those copies, and the host waits for the copies only, so the
+    // GPU builds those factors while the host plans the next step
+    int32_t* pin = reinterpret_cast<int32_t*>(h->stage.get((hflags.size() + 2 * size_t(ncl) + 1) * sizeof(int32_t)));
+    if (!pin) return set_err(h, SPAND_E_NOMEM, "pinned staging for the rank read-back failed");
+    int32_t* pin_rk = pin + hflags.size();
+    int32_t* pin_nref = pin_rk + ncl;
+    int32_t* pin_err = pin_nref + ncl;
+    *pin_err = 0;
+    HIPCHK(hipMemcpyAsync(pin, dflag.p, hflags.size() * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    if (any_orth) {
+      HIPCHK(hipMemcpyAsync(pin_rk, curb.p, size_t(ncl) * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(hipMemcpyAsync(pin_nref, nrefb.p, size_t(ncl) * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(hipMemcpyAsync(pin_err, errb.p, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    }
+    hipEvent_t readback;
+    HIPCHK(rbev.get(size_t(t - 1), &readback));
+    HIPCHK(hipEventRecord(readback, h->stream));
     {
       std::vector<TDesc> tds;
       for (Prob& pb : P) {
@@ -1872,15 +1890,10 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
       if ((st = build_apply(pb.h, pb.h->an.steps[pt - 1], pb.h->num[pt - 1], pb.lay_prev, pb.pending)) != SPAND_OK)
         return st;
     }
-    std::vector<int32_t> rk(size_t(ncl), -1), nrefh(size_t(ncl), 0);
-    int32_t serr = 0;
-    HIPCHK(hipMemcpyAsync(hflags.data(), dflag.p, hflags.size() * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
-    if (any_orth) {
-      HIPCHK(hipMemcpyAsync(rk.data(), curb.p, size_t(ncl) * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
-      HIPCHK(hipMemcpyAsync(nrefh.data(), nrefb.p, size_t(ncl) * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
-      HIPCHK(hipMemcpyAsync(&serr, errb.p, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
-    }
-    HIPCHK(hipStreamSynchronize(h->stream));
+    HIPCHK(hipEventSynchronize(readback));
+    std::copy(pin, pin + hflags.size(), hflags.begin());
+    std::vector<int32_t> rk(pin_rk, pin_rk + ncl), nrefh(pin_nref, pin_nref + ncl);
+    const int32_t serr = *pin_err;
     if (serr) return set_err(h, SPAND_E_HIP, "sparsification slab exchange timed out");
     for (size_t q = 0; q < nlaunch; ++q) {
       float ms = 0.f;
