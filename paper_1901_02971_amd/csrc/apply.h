@@ -33,8 +33,8 @@ struct TargetContrib {
   int64_t y;        // where the rows of n of y_s = G_s L_s^{-1} x_s live in the apply scratch
 };
 struct ScaleAp {
-  const double* Linv;  // np x np lower-triangular L_p^{-1}, ld np
-  int32_t np, pad;
+  const double* Linv;  // np x np lower-triangular L_p^{-1}, ld ldl (np rounded up to 16)
+  int32_t np, ldl;
   int64_t slot_p;
   int64_t tmp;         // np rows of scratch: x_p gathered
 };
@@ -42,19 +42,19 @@ struct ScaleTile {    // rows [r0, r0 + 64) of the product with L_p^{-1} (or its
   int32_t p, r0;
 };
 struct HouseAp {
-  const double* V;    // np x r reflectors, ld np (unit diagonal, zeros above)
-  const double* T;    // r x r upper-triangular factor of Q = I - V T V^T, ld r
-  int32_t np, r;
+  const double* V;    // np x r reflectors, ld ldv (unit diagonal, zeros above)
+  const double* T;    // r x r upper-triangular factor of Q = I - V T V^T, ld ldt
+  int32_t np, r, ldv, ldt;
   int64_t slot_p;
   int64_t tmp;        // 2*r rows of scratch: V^T x, then the T-product
 };
 // A small interface p (np <= 128) whose scaling and Householder product are
 // applied together by one wave (k_iface).
 struct IfaceAp {
-  const double* Linv;  // np x np lower-triangular L_p^{-1}, ld np
-  const double* V;     // np x r reflectors, ld np (unused when r == 0)
-  const double* T;     // r x r upper-triangular T, ld r
-  int32_t np, r;
+  const double* Linv;  // np x np lower-triangular L_p^{-1}, ld ldl
+  const double* V;     // np x r reflectors, ld ldv (unused when r == 0)
+  const double* T;     // r x r upper-triangular T, ld ldt
+  int32_t np, r, ldl, ldv, ldt, pad;
   int64_t slot_p;
 };
 struct HouseTile {    // 64 reflectors [j0, j0 + 64) or 64 rows [j0, j0 + 64) of interface p

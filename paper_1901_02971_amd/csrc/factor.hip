@@ -441,11 +441,14 @@ spand_status build_apply(spand_ctx* h, const SymStep& sy, StepNum& sn, const Lay
       IfaceAp f{};
       f.Linv = sn.scale.as<double>() + sc_off[p];
       f.np = sn.size[p];
+      f.ldl = pad16(f.np);
+      f.ldv = pad16(f.np);
       f.slot_p = sn.slot_ptr[p];
       if (v_off[p] >= 0 && nref[p] > 0) {
         f.V = sn.house.as<double>() + v_off[p];
         f.T = sn.house.as<double>() + t_off[p];
         f.r = nref[p];
+        f.ldt = pad16(f.r);
       }
       (f.np <= 64 ? if1 : if2).push_back(f);
       continue;
@@ -454,6 +457,7 @@ spand_status build_apply(spand_ctx* h, const SymStep& sy, StepNum& sn, const Lay
       ScaleAp a{};
       a.Linv = sn.scale.as<double>() + sc_off[p];
       a.np = sn.size[p];
+      a.ldl = pad16(a.np);
       a.slot_p = sn.slot_ptr[p];
       a.tmp = tmp2;
       tmp2 += sn.size[p];
@@ -469,6 +473,8 @@ spand_status build_apply(spand_ctx* h, const SymStep& sy, StepNum& sn, const Lay
       hp.T = sn.house.as<double>() + t_off[p];
       hp.np = sn.size[p];
       hp.r = nref[p];
+      hp.ldv = pad16(hp.np);
+      hp.ldt = pad16(hp.r);
       hp.slot_p = sn.slot_ptr[p];
       hp.tmp = tmp3;
       tmp3 += 2 * int64_t(nref[p]);
@@ -556,9 +562,9 @@ spand_status build_t_factors(spand_ctx* h, const std::vector<TDesc>& tds) {
   GemmSeq vtv(h->tune.gemm_scale);
   for (const TDesc& td : tds) {
     GemmDesc q{};
-    q.A = td.V; q.lda = td.m;
-    q.B = td.V; q.ldb = td.m;
-    q.C = td.T; q.ldc = td.r;
+    q.A = td.V; q.lda = td.ldv;
+    q.B = td.V; q.ldb = td.ldv;
+    q.C = td.T; q.ldc = td.ldt;
     q.M = td.r; q.N = td.r; q.K = td.m;
     q.flags = G_TA;
     q.alpha = 1.0; q.beta = 0.0;
@@ -574,7 +580,7 @@ spand_status build_t_factors(spand_ctx* h, const std::vector<TDesc>& tds) {
   std::vector<int64_t> x_off(tds.size(), -1);
   for (size_t q = 0; q < tds.size(); ++q) {
     const TDesc& td = tds[q];
-    for (int32_t j0 = 0; j0 < td.r; j0 += 64) tbs.push_back(TBlock{td.T, td.tau, td.r, j0});
+    for (int32_t j0 = 0; j0 < td.r; j0 += 64) tbs.push_back(TBlock{td.T, td.tau, td.r, j0, td.ldt, 0});
     rmax = std::max(rmax, td.r);
     if (td.r > 64) {
       x_off[q] = x_total;
@@ -594,8 +600,8 @@ spand_status build_t_factors(spand_ctx* h, const std::vector<TDesc>& tds) {
         if (td.r <= j0) continue;
         const int32_t w = std::min(64, td.r - j0);
         GemmDesc g{};  // X = S[:j0, J] T_JJ
-        g.A = td.T + int64_t(j0) * td.r; g.lda = td.r;
-        g.B = td.T + j0 + int64_t(j0) * td.r; g.ldb = td.r;
+        g.A = td.T + int64_t(j0) * td.ldt; g.lda = td.ldt;
+        g.B = td.T + j0 + int64_t(j0) * td.ldt; g.ldb = td.ldt;
         g.C = xb.as<double>() + x_off[q]; g.ldc = td.r;
         g.M = j0; g.N = w; g.K = w;
         g.alpha = 1.0; g.beta = 0.0;
@@ -607,9 +613,9 @@ spand_status build_t_factors(spand_ctx* h, const std::vector<TDesc>& tds) {
         if (td.r <= j0) continue;
         const int32_t w = std::min(64, td.r - j0);
         GemmDesc g{};  // T[:j0, J] = -T[:j0, :j0] X
-        g.A = td.T; g.lda = td.r;
+        g.A = td.T; g.lda = td.ldt;
         g.B = xb.as<double>() + x_off[q]; g.ldb = td.r;
-        g.C = td.T + int64_t(j0) * td.r; g.ldc = td.r;
+        g.C = td.T + int64_t(j0) * td.ldt; g.ldc = td.ldt;
         g.M = j0; g.N = w; g.K = j0;
         g.alpha = -1.0; g.beta = 0.0;
         tg2.add(g, 0);
@@ -865,6 +871,7 @@ spand_status sparsify_interp(Prob& pb, int32_t t, double tol, double& cpqr_ms, i
       const It& it = its[k];
       SparsDesc d{};
       d.V = vbuf.as<double>() + it.ov;
+      d.ldv = it.m;
       d.tau = taub.as<double>() + it.otau;
       d.diag = xbuf.as<double>() + it.ox;  // I_r lands in X, which is rewritten later
       d.ldd = it.np;
@@ -1425,7 +1432,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
         for (int32_t p = ne; p < nc; ++p) {
           if (sn.size[p] == 0) continue;
           pb.sc_off[p] = sc_total;
-          sc_total += int64_t(sn.size[p]) * sn.size[p];
+          sc_total += int64_t(pad16(sn.size[p])) * sn.size[p];
           pb.sd_off[p] = sd_total;
           sd_total += dinv_size(sn.size[p]);
           pb.m_F += int64_t(sn.size[p]) * (sn.size[p] + 1) / 2;
@@ -1442,8 +1449,8 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
         // left on every block (i, p), in one blocked left solve
         for (int32_t p = ne; p < nc; ++p) {
           if (sn.size[p] == 0) continue;
-          add_identity(ids, SC + pb.sc_off[p], sn.size[p], sn.size[p]);
-          lb.push_back(LeftBlock{SC + pb.sc_off[p], A + lay.base[p], SD + pb.sd_off[p], sn.size[p], int32_t(lay.H[p]),
+          add_identity(ids, SC + pb.sc_off[p], sn.size[p], pad16(sn.size[p]));
+          lb.push_back(LeftBlock{SC + pb.sc_off[p], A + lay.base[p], SD + pb.sd_off[p], pad16(sn.size[p]), int32_t(lay.H[p]),
                                  sn.size[p], sn.size[p]});
           for (int64_t e = lay.pan_ptr[p] + 1; e < lay.pan_ptr[p + 1]; ++e) {
             const int32_t i = lay.prow[e];
@@ -1557,11 +1564,11 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
           }
           const int64_t kmax = std::min<int64_t>(sn.size[p], pb.ncols[p]);
           pb.v_off[p] = house_total;
-          house_total += int64_t(sn.size[p]) * kmax;
+          house_total += int64_t(pad16(sn.size[p])) * kmax;
           pb.tau_off[p] = house_total;
-          house_total += kmax;
-          pb.t_off[p] = house_total;  // compact WY factor T (r x r, r <= kmax)
-          house_total += kmax * kmax;
+          house_total += (kmax + 15) / 16 * 16;
+          pb.t_off[p] = house_total;  // compact WY factor T (r x r, r <= kmax, ld pad16(r))
+          house_total += (kmax + 15) / 16 * 16 * kmax;
         }
         if ((st = dalloc(hq, sn.house, size_t(house_total) * sizeof(double))) != SPAND_OK) return st;
         for (int32_t p = ne; p < nc; ++p)
@@ -1652,6 +1659,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
               if (multi && !rd.empty() && int64_t(rd.size()) + pb.slabS[p] > cap) break;
               SparsDesc d{};
               d.V = sn.house.as<double>() + pb.v_off[p];
+              d.ldv = pad16(sn.size[p]);
               d.tau = sn.house.as<double>() + pb.tau_off[p];
               d.diag = A + lay.base[p];
               d.ldd = int32_t(lay.H[p]);
@@ -1759,6 +1767,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
           double* A = pb.arena.as<double>();
           SparsDesc d{};
           d.V = sn.house.as<double>() + pb.v_off[p];
+          d.ldv = pad16(sn.size[p]);
           d.tau = sn.house.as<double>() + pb.tau_off[p];
           d.diag = A + lay.base[p];
           d.ldd = int32_t(lay.H[p]);
@@ -1958,7 +1967,8 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
             pb.m_F += (2 * int64_t(sn.size[p]) - r + 1) * r / 2 + r;
             if (r > 0)
               tds.push_back(TDesc{sn.house.as<double>() + pb.v_off[p], sn.house.as<double>() + pb.tau_off[p],
-                                  sn.house.as<double>() + pb.t_off[p], sn.size[p], int32_t(r)});
+                                  sn.house.as<double>() + pb.t_off[p], sn.size[p], int32_t(r), pad16(sn.size[p]),
+                                  pad16(int32_t(r))});
           }
         // the compact-WY factors are only read by the apply: they are built while the
         // next step runs

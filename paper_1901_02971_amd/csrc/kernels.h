@@ -9,6 +9,9 @@ namespace spand {
 
 // Blocked Cholesky (kernels_chol.hip).  Diagonal blocks are CHOL_NB wide.
 constexpr int CHOL_NB = 64;
+// Leading dimension of the factor matrices of the interfaces (L_p^{-1}, V, T): the
+// row count rounded up to 16 entries, so that every column starts on a 128-byte line.
+__host__ __device__ inline int32_t pad16(int32_t n) { return (n + 15) / 16 * 16; }
 struct PotrfDesc {
   double* P;     // diagonal block start (column-major, ld)
   double* Dinv;  // w x w output: inverse of the diagonal block's factor, ld w
@@ -107,6 +110,7 @@ struct SparsDesc {
   int32_t* piv;    // when not null: piv[j] = column (index in A_pn) chosen at step j < r
   int32_t m, ldd, seg_begin, seg_end, id, S, G, lay;  // G: lanes per column (team size);
                                                       // lay: register layout (multi-slab kernel)
+  int32_t ldv, pad;                                   // leading dimension of V (>= m)
 };
 struct SegDesc {
   double* blk;  // block holding A_pq: trans=0 -> A_pq[r][c] = blk[r + c*ld]; trans=1 -> blk[c + r*ld]
@@ -178,17 +182,17 @@ hipError_t launch_cpqr_big(const SparsDesc& d, int32_t nseg, const SegDesc* seg,
                            int32_t* nref, int32_t* err, int32_t nb, double* wk, double* nrm, int32_t* pst, double* rb,
                            double* post_mx, int32_t* post_cd, uint32_t* bar, hipStream_t s);
 struct TDesc {
-  const double* V;    // m x r, ld m
+  const double* V;    // m x r, ld ldv
   const double* tau;  // r
-  double* T;          // r x r output, ld r
-  int32_t m, r;
+  double* T;          // r x r output, ld ldt
+  int32_t m, r, ldv, ldt;
 };
 // Diagonal 64-wide block j0 of the compact-WY factor T (r x r, ld r) of one
 // interface; on entry the upper triangle of T holds V^T V.
 struct TBlock {
-  double* T;
+  double* T;          // ld ld
   const double* tau;
-  int32_t r, j0;
+  int32_t r, j0, ld, pad;
 };
 void launch_build_t_diag(const TBlock* blocks, int32_t count, hipStream_t s);
 

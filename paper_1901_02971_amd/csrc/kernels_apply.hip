@@ -429,9 +429,9 @@ __global__ void __launch_bounds__(AW) k_scale(const ScaleAp* __restrict__ ds, co
     const int64_t co = (int64_t)c0 * a.ldt;
     double acc[2] = {0.0, 0.0};
     if (DIR > 0)  // rows r0.. of L^{-1} x: columns up to the diagonal tile
-      tile_gemv_n(e.Linv, np, r0, np, min(np, r0 + 64), xs + co, a.ldt, nr, sh, acc);
+      tile_gemv_n(e.Linv, e.ldl, r0, np, min(np, r0 + 64), xs + co, a.ldt, nr, sh, acc);
     else          // rows r0.. of L^{-T} x: rows r0.. of L^{-1}
-      tile_gemv_t(e.Linv + r0, np, r0, np, np - r0, xs + co + r0, a.ldt, nr, sh, acc);
+      tile_gemv_t(e.Linv + r0, e.ldl, r0, np, np - r0, xs + co + r0, a.ldt, nr, sh, acc);
     if (r0 + rr < np) {
       double* xp = a.x + sl[r0 + rr] + (int64_t)c0 * a.ldx;
       if (g < nr) xp[(int64_t)g * a.ldx] = acc[0];
@@ -458,7 +458,7 @@ __global__ void __launch_bounds__(AW) k_house_w(const HouseAp* __restrict__ ds, 
   for (int c0 = 0; c0 < a.nrhs; c0 += RB) {
     const int nr = min(RB, a.nrhs - c0);
     double acc[2] = {0.0, 0.0};
-    tile_gemv_t(e.V, np, j0, r, np, a.x + (int64_t)c0 * a.ldx, a.ldx, nr, sh, acc, sl);
+    tile_gemv_t(e.V, e.ldv, j0, r, np, a.x + (int64_t)c0 * a.ldx, a.ldx, nr, sh, acc, sl);
     if (j0 + cc < r) {
       if (g < nr) ws[j0 + cc + (int64_t)(c0 + g) * a.ldt] = acc[0];
       if (g + 4 < nr) ws[j0 + cc + (int64_t)(c0 + g + 4) * a.ldt] = acc[1];
@@ -481,9 +481,9 @@ __global__ void __launch_bounds__(AW) k_house_t(const HouseAp* __restrict__ ds, 
     const int64_t co = (int64_t)c0 * a.ldt;
     double acc[2] = {0.0, 0.0};
     if (DIR > 0)
-      tile_gemv_t(e.T, r, j0, r, r, ws + co, a.ldt, nr, sh, acc);
+      tile_gemv_t(e.T, e.ldt, j0, r, r, ws + co, a.ldt, nr, sh, acc);
     else
-      tile_gemv_n(e.T, r, j0, r, r, ws + co, a.ldt, nr, sh, acc);
+      tile_gemv_n(e.T, e.ldt, j0, r, r, ws + co, a.ldt, nr, sh, acc);
     if (j0 + cc < r) {
       if (g < nr) us[co + j0 + cc + (int64_t)g * a.ldt] = acc[0];
       if (g + 4 < nr) us[co + j0 + cc + (int64_t)(g + 4) * a.ldt] = acc[1];
@@ -503,7 +503,7 @@ __global__ void __launch_bounds__(AW) k_house_v(const HouseAp* __restrict__ ds, 
   for (int c0 = 0; c0 < a.nrhs; c0 += RB) {
     const int nr = min(RB, a.nrhs - c0);
     double acc[2] = {0.0, 0.0};
-    tile_gemv_n(e.V, np, r0, np, r, us + (int64_t)c0 * a.ldt, a.ldt, nr, sh, acc);
+    tile_gemv_n(e.V, e.ldv, r0, np, r, us + (int64_t)c0 * a.ldt, a.ldt, nr, sh, acc);
     if (r0 + rr < np) {
       double* xp = a.x + sl[r0 + rr] + (int64_t)c0 * a.ldx;
       const double x0 = g < nr ? xp[(int64_t)g * a.ldx] : 0.0;
@@ -605,7 +605,7 @@ __global__ void __launch_bounds__(64) k_iface(const IfaceAp* __restrict__ ds, Ap
     }
     if (DIR > 0) {
       iface_put<RPL>(xb, x);
-      iface_product<RPL, false>(e.Linv, np, np, np, 2, xb, y);  // y = L^{-1} x (lower: i >= k)
+      iface_product<RPL, false>(e.Linv, e.ldl, np, np, 2, xb, y);  // y = L^{-1} x (lower: i >= k)
     } else {
 #pragma unroll
       for (int q = 0; q < RPL; ++q)
@@ -616,16 +616,16 @@ __global__ void __launch_bounds__(64) k_iface(const IfaceAp* __restrict__ ds, Ap
       double w[RPL][RB], u[RPL][RB];
       __syncthreads();
       iface_put<RPL>(xb, y);
-      iface_product<RPL, true>(e.V, np, np, r, 0, xb, w);  // w = V^T y
+      iface_product<RPL, true>(e.V, e.ldv, np, r, 0, xb, w);  // w = V^T y
       iface_put<RPL>(wb, w);
       if (DIR > 0)
-        iface_product<RPL, true>(e.T, r, r, r, 1, wb, u);  // u = T^T w (upper: k <= j)
+        iface_product<RPL, true>(e.T, e.ldt, r, r, 1, wb, u);  // u = T^T w (upper: k <= j)
       else
-        iface_product<RPL, false>(e.T, r, r, r, 1, wb, u);  // u = T w (upper: i <= k)
+        iface_product<RPL, false>(e.T, e.ldt, r, r, 1, wb, u);  // u = T w (upper: i <= k)
       __syncthreads();
       iface_put<RPL>(wb, u);
       double vu[RPL][RB];
-      iface_product<RPL, false>(e.V, np, np, r, 0, wb, vu);  // V u
+      iface_product<RPL, false>(e.V, e.ldv, np, r, 0, wb, vu);  // V u
 #pragma unroll
       for (int q = 0; q < RPL; ++q)
 #pragma unroll
@@ -634,7 +634,7 @@ __global__ void __launch_bounds__(64) k_iface(const IfaceAp* __restrict__ ds, Ap
     if (DIR < 0) {
       __syncthreads();
       iface_put<RPL>(xb, y);
-      iface_product<RPL, true>(e.Linv, np, np, np, 2, xb, y);  // y = L^{-T} y (column j of L^{-1}, rows i >= j)
+      iface_product<RPL, true>(e.Linv, e.ldl, np, np, 2, xb, y);  // y = L^{-T} y (column j of L^{-1}, rows i >= j)
     }
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {

@@ -633,7 +633,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
         if (i < ROWS) {
           const double v = (i > j) ? xs[u] * scale : ((i == j) ? 1.0 : 0.0);
           vv[i] = v;
-          if (w == 0 && i < m) d.V[(int64_t)j * m + i] = v;
+          if (w == 0 && i < m) d.V[(int64_t)j * d.ldv + i] = v;
         }
       }
     }
@@ -805,15 +805,16 @@ __global__ void __launch_bounds__(CQ_NT) k_cpqr_multi(const SparsDesc* __restric
 __global__ void __launch_bounds__(CW) k_build_t_diag(const TBlock* __restrict__ blocks) {
   const TBlock b = blocks[blockIdx.x];
   const int r = b.r, j0 = b.j0, w = min(64, r - j0);
+  const int64_t ld = b.ld;
   __shared__ double tl[64 * 65];
   const int below = r - j0;
   for (int q = threadIdx.x; q < below * w; q += CW) {  // zeros under the diagonal of this block column
     const int i = j0 + q % below, j = j0 + q / below;
-    if (i > j) b.T[i + (int64_t)j * r] = 0.0;
+    if (i > j) b.T[i + j * ld] = 0.0;
   }
   for (int q = threadIdx.x; q < w * w; q += CW) {
     const int i = q % w, j = q / w;
-    tl[i + j * 65] = (i < j) ? b.T[(j0 + i) + (int64_t)(j0 + j) * r] : 0.0;
+    tl[i + j * 65] = (i < j) ? b.T[(j0 + i) + (j0 + j) * ld] : 0.0;
   }
   __syncthreads();
   const int i = threadIdx.x;
@@ -828,7 +829,7 @@ __global__ void __launch_bounds__(CW) k_build_t_diag(const TBlock* __restrict__ 
   }
   for (int q = threadIdx.x; q < w * w; q += CW) {
     const int ii = q % w, jj = q / w;
-    if (ii <= jj) b.T[(j0 + ii) + (int64_t)(j0 + jj) * r] = tl[ii + jj * 65];
+    if (ii <= jj) b.T[(j0 + ii) + (j0 + jj) * ld] = tl[ii + jj * 65];
   }
 }
 
@@ -1063,7 +1064,7 @@ __global__ void __launch_bounds__(CB_NT) k_cpqr_big(SparsDesc d, const SegDesc* 
     for (int i = j + tid; i < m; i += CB_NT) vv[i] = (i == j) ? 1.0 : vv[i] * scale;
     __syncthreads();
     if (b == 0) {
-      for (int i = tid; i < m; i += CB_NT) d.V[(int64_t)j * m + i] = (i >= j) ? vv[i] : 0.0;
+      for (int i = tid; i < m; i += CB_NT) d.V[(int64_t)j * d.ldv + i] = (i >= j) ? vv[i] : 0.0;
       if (tid == 0) {
         d.tau[j] = tau;
         shared_store(bs.rb + j, beta);
