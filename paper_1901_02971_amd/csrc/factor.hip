@@ -1181,7 +1181,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
     pb.h->d_pos.release();
     pb.h->d_inv.release();
     pb.frozen.clear();
-    pb.frozen.reserve(size_t(pb.h->an.n));
+    if (P.size() == 1) pb.frozen.reserve(size_t(pb.h->an.n));
     std::memset(pb.h->stats.step_phase_seconds, 0, sizeof(pb.h->stats.step_phase_seconds));
     std::memset(pb.h->stats.step_m_F, 0, sizeof(pb.h->stats.step_m_F));
   }
@@ -1974,7 +1974,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
         // next step runs
         pb.t_pending = std::move(tds);
       }
-      frozen_at(sy, sn, pb.frozen);
+      if (NP == 1) frozen_at(sy, sn, pb.frozen);
       if (t <= 32) hq->stats.step_m_F[t - 1] = pb.m_F;
       pb.pending = ApplyPlan{t, std::move(pb.ed_off), std::move(pb.sc_off), std::move(pb.v_off), std::move(pb.t_off),
                              std::move(pb.nN), std::move(pb.nref)};
@@ -1997,8 +1997,8 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
     if ((st = build_apply(pb.h, pb.h->an.steps[pt - 1], pb.h->num[pt - 1], pb.lay_prev, pb.pending)) != SPAND_OK)
       return st;
   }
-  for (Prob& pb : P)
-    if (pb.live && (st = freeze_order(pb.h, pb.frozen)) != SPAND_OK) return st;
+  // (a batch solves in vertex order, through the host's slot lists: no freeze order)
+  if (NP == 1 && P[0].live && (st = freeze_order(P[0].h, P[0].frozen)) != SPAND_OK) return st;
   HIPCHK(hipStreamSynchronize(h->stream));
   double elim_ms = 0.0;
   double phase_s[32][4] = {};
