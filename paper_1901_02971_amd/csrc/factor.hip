@@ -1343,6 +1343,22 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
           y.alpha = 1.0; y.beta = 0.0;
           syrk.add(y, 1);
         }
+      }
+      // the Cholesky and the SYRK go first; the reduction plan is built while they run
+      if ((st = blocked_cholesky(h, fr, gemm_prec)) != SPAND_OK) return st;
+      syrk.end_launch(gemm_prec);
+      if ((st = syrk.upload_all(h)) != SPAND_OK) return st;
+      syrk.launch(h, 0);
+      HIPCHK(hipGetLastError());
+      for (Prob* pp : act) {
+        Prob& pb = *pp;
+        spand_ctx* hq = pb.h;
+        const SymStep& sy = hq->an.steps[t - 1];
+        StepNum& sn = hq->num[t - 1];
+        const Layout& lay = pb.lay;
+        const int32_t ne = sy.ne;
+        double* A = pb.arena.as<double>();
+        const int32_t qid = int32_t(pp - P.data());
         // deterministic reduction of C_s into the targets: contributions to one target
         // block in ascending s
         std::vector<Item> items;
@@ -1387,11 +1403,6 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
           q = r;
         }
       }
-      if ((st = blocked_cholesky(h, fr, gemm_prec)) != SPAND_OK) return st;
-      syrk.end_launch(gemm_prec);
-      if ((st = syrk.upload_all(h)) != SPAND_OK) return st;
-      syrk.launch(h, 0);
-      HIPCHK(hipGetLastError());
       DevBuf drd, dcd;
       if ((st = upload_big(h, drd, rds)) != SPAND_OK) return st;
       if ((st = upload_big(h, dcd, cds2)) != SPAND_OK) return st;
