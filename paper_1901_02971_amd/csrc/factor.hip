@@ -1131,18 +1131,17 @@ void frozen_at(const SymStep& sy, const StepNum& sn, std::vector<int32_t>& inv) 
   }
 }
 
-spand_status freeze_order(spand_ctx* h, std::vector<int32_t>& inv) {
+spand_status freeze_order(spand_ctx* h, const std::vector<int32_t>& inv, DevBuf& bad) {
   const int64_t n = h->an.n;
   if (int64_t(inv.size()) != n) return set_err(h, SPAND_E_INVALID, "freeze order does not cover every dof");
-  std::vector<int32_t> pos(static_cast<size_t>(n), -1);
-  for (int64_t k = 0; k < n; ++k) {
-    const int32_t v = inv[k];
-    if (v < 0 || v >= n || pos[v] >= 0) return set_err(h, SPAND_E_INVALID, "freeze order is not a permutation");
-    pos[v] = int32_t(k);
-  }
   spand_status st;
-  if ((st = upload(h, h->d_pos, pos)) != SPAND_OK) return st;
-  if ((st = upload(h, h->d_inv, inv)) != SPAND_OK) return st;
+  if ((st = upload_big(h, h->d_inv, inv)) != SPAND_OK) return st;
+  // the inverse is formed on the device; bad is read at the end of the factorization
+  if ((st = dalloc(h, h->d_pos, size_t(n) * sizeof(int32_t))) != SPAND_OK) return st;
+  if ((st = dalloc(h, bad, sizeof(int32_t))) != SPAND_OK) return st;
+  HIPCHK(hipMemsetAsync(h->d_pos.p, 0xFF, size_t(n) * sizeof(int32_t), h->stream));
+  HIPCHK(hipMemsetAsync(bad.p, 0, sizeof(int32_t), h->stream));
+  launch_invert_perm(h->d_inv.as<int32_t>(), n, h->d_pos.as<int32_t>(), bad.as<int32_t>(), h->stream);
   std::vector<RemapSeg> segs;
   auto add = [&](DevBuf& b, int64_t len) {
     for (int64_t o = 0; o < len; o += REMAP_CHUNK)
@@ -1610,16 +1609,39 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
         size_t lds, d0, s0;
         int32_t big_nseg = -1;  // >= 0: one global-memory launch of descriptor d0 with nslab workgroups
       };
-      std::vector<CpqrLaunch> launches;
+      // scratch of the large-interface launches (they run one after another on the stream)
       int64_t big_m = 0, big_mn = 0, big_nc = 0;
-      std::vector<SparsDesc> all_sds;
-      std::vector<SegDesc> all_segs;
-      std::vector<SlabRef> all_slabs;
+      for (const auto& cl : by_colour)
+        for (const Ref& f : cl)
+          if (f.pb->big[f.p]) {
+            const int64_t m = f.pb->h->num[t - 1].size[f.p], n = f.pb->ncols[f.p];
+            big_m = std::max(big_m, m);
+            big_mn = std::max(big_mn, m * n);
+            big_nc = std::max(big_nc, n);
+          }
+      DevBuf bwk, bnrm, bpst, brb, bpost, bpcd, bbar;
+      if (big_m > 0) {
+        if ((st = dalloc(h, bwk, size_t(big_mn) * sizeof(double))) != SPAND_OK) return st;
+        if ((st = dalloc(h, bnrm, size_t(big_nc) * sizeof(double))) != SPAND_OK) return st;
+        if ((st = dalloc(h, bpst, size_t(big_nc) * sizeof(int32_t))) != SPAND_OK) return st;
+        if ((st = dalloc(h, brb, size_t(std::min(big_m, big_nc)) * sizeof(double))) != SPAND_OK) return st;
+        if ((st = dalloc(h, bpost, 1024 * sizeof(double))) != SPAND_OK) return st;
+        if ((st = dalloc(h, bpcd, 1024 * sizeof(int32_t))) != SPAND_OK) return st;
+        if ((st = dalloc(h, bbar, 256)) != SPAND_OK) return st;
+      }
+      // Each colour class is planned, uploaded and launched before the next one is
+      // planned, so the GPU runs a colour while the host plans the next.  The
+      // descriptor buffers of the colours stay allocated until the step ends.
+      std::vector<DevBuf> colour_bufs;
       // launch groups of one colour: single-slab interfaces per team size G
       // (group G), the wide single-slab ones (group 128), then every multi-slab
       // interface of the colour together (group 256)
       for (int32_t c = 0; c < ncolour; ++c) {
         if (by_colour[c].empty()) continue;
+        std::vector<CpqrLaunch> launches;
+        std::vector<SparsDesc> all_sds;
+        std::vector<SegDesc> all_segs;
+        std::vector<SlabRef> all_slabs;
         for (int32_t grp = 1; grp <= 256; grp <<= 1) {
           const bool multi = grp == 256, wgrp = grp == 128;
           std::vector<Ref> plist;
@@ -1813,57 +1835,46 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
           Lb.nslab = int32_t(std::max<int64_t>(1, std::min<int64_t>(std::min(capb, 1024), (pb.ncols[p] + 15) / 16)));
           all_sds.push_back(d);
           launches.push_back(Lb);
-          big_m = std::max<int64_t>(big_m, sn.size[p]);
-          big_mn = std::max<int64_t>(big_mn, int64_t(sn.size[p]) * pb.ncols[p]);
-          big_nc = std::max<int64_t>(big_nc, pb.ncols[p]);
         }
-      }
-      // scratch of the large-interface launches (they run one after another on the stream)
-      DevBuf bwk, bnrm, bpst, brb, bpost, bpcd, bbar;
-      if (big_m > 0) {
-        if ((st = dalloc(h, bwk, size_t(big_mn) * sizeof(double))) != SPAND_OK) return st;
-        if ((st = dalloc(h, bnrm, size_t(big_nc) * sizeof(double))) != SPAND_OK) return st;
-        if ((st = dalloc(h, bpst, size_t(big_nc) * sizeof(int32_t))) != SPAND_OK) return st;
-        if ((st = dalloc(h, brb, size_t(std::min(big_m, big_nc)) * sizeof(double))) != SPAND_OK) return st;
-        if ((st = dalloc(h, bpost, 1024 * sizeof(double))) != SPAND_OK) return st;
-        if ((st = dalloc(h, bpcd, 1024 * sizeof(int32_t))) != SPAND_OK) return st;
-        if ((st = dalloc(h, bbar, 256)) != SPAND_OK) return st;
-      }
-      // every launch of the step is planned: one upload, then the launches back to back
-      DevBuf a, b, sl;
-      if ((st = upload_big(h, a, all_sds)) != SPAND_OK) return st;
-      if ((st = upload_big(h, b, all_segs)) != SPAND_OK) return st;
-      if ((st = upload_big(h, sl, all_slabs)) != SPAND_OK) return st;
-      for (const CpqrLaunch& Lc : launches) {
-        hipEvent_t e0, e1;
-        HIPCHK(evpool.get(2 * nlaunch, &e0));
-        HIPCHK(evpool.get(2 * nlaunch + 1, &e1));
-        HIPCHK(hipEventRecord(e0, h->stream));
-        const SparsDesc* dd = a.as<SparsDesc>() + Lc.d0;
-        const SlabRef* ss = sl.as<SlabRef>() + Lc.s0;
-        if (Lc.big_nseg >= 0) {
-          HIPCHK(hipMemsetAsync(bbar.p, 0, 256, h->stream));
-          hipError_t le = launch_cpqr_big(all_sds[Lc.d0], Lc.big_nseg, b.as<SegDesc>(), tol, curb.as<int32_t>(),
-                                          nrefb.as<int32_t>(), errb.as<int32_t>(), Lc.nslab, bwk.as<double>(),
-                                          bnrm.as<double>(), bpst.as<int32_t>(), brb.as<double>(), bpost.as<double>(),
-                                          bpcd.as<int32_t>(), bbar.as<uint32_t>(), h->stream);
+        // this colour's launches: one upload of each descriptor list, then the launches
+        DevBuf a, b, sl;
+        if ((st = upload_big(h, a, all_sds)) != SPAND_OK) return st;
+        if ((st = upload_big(h, b, all_segs)) != SPAND_OK) return st;
+        if ((st = upload_big(h, sl, all_slabs)) != SPAND_OK) return st;
+        for (const CpqrLaunch& Lc : launches) {
+          hipEvent_t e0, e1;
+          HIPCHK(evpool.get(2 * nlaunch, &e0));
+          HIPCHK(evpool.get(2 * nlaunch + 1, &e1));
+          HIPCHK(hipEventRecord(e0, h->stream));
+          const SparsDesc* dd = a.as<SparsDesc>() + Lc.d0;
+          const SlabRef* ss = sl.as<SlabRef>() + Lc.s0;
+          if (Lc.big_nseg >= 0) {
+            HIPCHK(hipMemsetAsync(bbar.p, 0, 256, h->stream));
+            hipError_t le = launch_cpqr_big(all_sds[Lc.d0], Lc.big_nseg, b.as<SegDesc>(), tol, curb.as<int32_t>(),
+                                            nrefb.as<int32_t>(), errb.as<int32_t>(), Lc.nslab, bwk.as<double>(),
+                                            bnrm.as<double>(), bpst.as<int32_t>(), brb.as<double>(), bpost.as<double>(),
+                                            bpcd.as<int32_t>(), bbar.as<uint32_t>(), h->stream);
+            if (le != hipSuccess)
+              return set_err(h, SPAND_E_HIP, std::string("large-interface sparsification launch: ") + hipGetErrorString(le));
+            HIPCHK(hipEventRecord(e1, h->stream));
+            ++nlaunch;
+            continue;
+          }
+          hipError_t le = Lc.multi ? launch_cpqr_multi(dd, ss, Lc.nslab, Lc.nround, b.as<SegDesc>(), tol,
+                                                       curb.as<int32_t>(), nrefb.as<int32_t>(), errb.as<int32_t>(),
+                                                       Lc.lds, h->stream)
+                       : Lc.G == 128 ? launch_cpqr_one_wide(dd, ss, Lc.nslab, b.as<SegDesc>(), tol, curb.as<int32_t>(),
+                                                            nrefb.as<int32_t>(), errb.as<int32_t>(), Lc.lds, h->stream)
+                                     : launch_cpqr_one(Lc.G, dd, ss, Lc.nslab, b.as<SegDesc>(), tol, curb.as<int32_t>(),
+                                                       nrefb.as<int32_t>(), errb.as<int32_t>(), Lc.lds, h->stream);
           if (le != hipSuccess)
-            return set_err(h, SPAND_E_HIP, std::string("large-interface sparsification launch: ") + hipGetErrorString(le));
+            return set_err(h, SPAND_E_HIP, std::string("sparsification launch: ") + hipGetErrorString(le));
           HIPCHK(hipEventRecord(e1, h->stream));
           ++nlaunch;
-          continue;
         }
-        hipError_t le = Lc.multi ? launch_cpqr_multi(dd, ss, Lc.nslab, Lc.nround, b.as<SegDesc>(), tol,
-                                                     curb.as<int32_t>(), nrefb.as<int32_t>(), errb.as<int32_t>(),
-                                                     Lc.lds, h->stream)
-                     : Lc.G == 128 ? launch_cpqr_one_wide(dd, ss, Lc.nslab, b.as<SegDesc>(), tol, curb.as<int32_t>(),
-                                                          nrefb.as<int32_t>(), errb.as<int32_t>(), Lc.lds, h->stream)
-                                   : launch_cpqr_one(Lc.G, dd, ss, Lc.nslab, b.as<SegDesc>(), tol, curb.as<int32_t>(),
-                                                     nrefb.as<int32_t>(), errb.as<int32_t>(), Lc.lds, h->stream);
-        if (le != hipSuccess)
-          return set_err(h, SPAND_E_HIP, std::string("sparsification launch: ") + hipGetErrorString(le));
-        HIPCHK(hipEventRecord(e1, h->stream));
-        ++nlaunch;
+        colour_bufs.push_back(std::move(a));
+        colour_bufs.push_back(std::move(b));
+        colour_bufs.push_back(std::move(sl));
       }
       HIPCHK(hipEventRecord(ph[4], h->stream));
     }
@@ -2009,8 +2020,20 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
       return st;
   }
   // (a batch solves in vertex order, through the host's slot lists: no freeze order)
-  if (NP == 1 && P[0].live && (st = freeze_order(P[0].h, P[0].frozen)) != SPAND_OK) return st;
+  DevBuf badperm;
+  int32_t* pin_bad = nullptr;
+  if (NP == 1 && P[0].live) {
+    if ((st = freeze_order(P[0].h, P[0].frozen, badperm)) != SPAND_OK) return st;
+    pin_bad = reinterpret_cast<int32_t*>(h->stage.get(sizeof(int32_t)));
+    if (!pin_bad) return set_err(h, SPAND_E_NOMEM, "pinned staging for the freeze-order check failed");
+    HIPCHK(hipMemcpyAsync(pin_bad, badperm.p, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+  }
   HIPCHK(hipStreamSynchronize(h->stream));
+  if (pin_bad && *pin_bad) {
+    P[0].h->d_pos.release();
+    P[0].h->d_inv.release();
+    return set_err(h, SPAND_E_INVALID, "freeze order is not a permutation");
+  }
   double elim_ms = 0.0;
   double phase_s[32][4] = {};
   for (int32_t t = 1; t <= Lmax && 5 * size_t(t) <= phev.ev.size(); ++t) {  // phase times from the events of every step

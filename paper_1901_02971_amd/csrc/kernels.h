@@ -96,6 +96,7 @@ struct RemapSeg {  // p[k] <- pos[p[k]] for k < len (<= REMAP_CHUNK)
 };
 #define REMAP_CHUNK 65536
 void launch_remap(const RemapSeg* d, int64_t count, const int32_t* pos, hipStream_t s);
+void launch_invert_perm(const int32_t* inv, int64_t n, int32_t* pos, int32_t* bad, hipStream_t s);
 
 // Sparsification of one interface p (Sec. 2.6.1).  A_pn is held in the registers of
 // S workgroups (slabs) of CAP = cpqr_capacity(G) columns each.  The width of A_pn is

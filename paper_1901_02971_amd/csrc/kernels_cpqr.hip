@@ -32,6 +32,9 @@
 
 #include <climits>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "kernels.h"
 
@@ -1124,14 +1127,35 @@ __global__ void __launch_bounds__(CB_NT) k_cpqr_big(SparsDesc d, const SegDesc* 
 
 int32_t cpqr_big_max_rows() { return CB_MAXM; }
 
-int cpqr_big_max_coresident(int32_t nseg) {
-  int per_cu = 0;
-  const size_t lds = nseg < 64 ? 0 : (size_t(nseg) + 1) * sizeof(int);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cpqr_big, CB_NT, lds) != hipSuccess) return 0;
-  int dev = 0, cus = 0;
+namespace {
+
+// Co-resident workgroups of a cooperative CPQR kernel on the current device for a
+// dynamic LDS size: the runtime's occupancy answer, remembered per (device, kernel,
+// LDS bytes), since the host asks once per interface while it plans a step.
+int coresident(const void* kernel, int nt, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, const void*, size_t>, int> known;
+  int dev = 0;
   (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const auto key = std::make_tuple(dev, kernel, lds);
+  {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = known.find(key);
+    if (it != known.end()) return it->second;
+  }
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, lds) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  std::lock_guard<std::mutex> g(mu);
+  known[key] = per_cu * cus;
   return per_cu * cus;
+}
+
+}  // namespace
+
+int cpqr_big_max_coresident(int32_t nseg) {
+  const size_t lds = nseg < 64 ? 0 : (size_t(nseg) + 1) * sizeof(int);
+  return coresident(reinterpret_cast<const void*>(&k_cpqr_big), CB_NT, lds);
 }
 
 hipError_t launch_cpqr_big(const SparsDesc& d, int32_t nseg, const SegDesc* seg, double eps, int32_t* cursize,
@@ -1146,12 +1170,7 @@ hipError_t launch_cpqr_big(const SparsDesc& d, int32_t nseg, const SegDesc* seg,
 }
 
 int cpqr_max_coresident(size_t lds) {
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cpqr_multi, CQ_NT, lds) != hipSuccess) return 0;
-  int dev = 0, cus = 0;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  return per_cu * cus;
+  return coresident(reinterpret_cast<const void*>(&k_cpqr_multi), CQ_NT, lds);
 }
 
 hipError_t launch_cpqr_one(int32_t G, const SparsDesc* d, const SlabRef* slabs, int32_t nslab, const SegDesc* seg,

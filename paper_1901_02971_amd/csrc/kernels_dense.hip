@@ -204,4 +204,22 @@ void launch_remap(const RemapSeg* d, int64_t count, const int32_t* pos, hipStrea
   if (count > 0) hipLaunchKernelGGL(k_remap, dim3(unsigned(count)), dim3(WG), 0, s, d, pos);
 }
 
+// pos[inv[k]] = k on pos filled with -1 beforehand; an entry of inv outside [0, n)
+// or met twice sets bit 0 of *bad (inv is then no permutation).
+__global__ void __launch_bounds__(WG) k_invert_perm(const int32_t* __restrict__ inv, int64_t n, int32_t* pos,
+                                                    int32_t* bad) {
+  const int64_t k = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (k >= n) return;
+  const int32_t v = inv[k];
+  if (v < 0 || v >= n) {
+    atomicOr(bad, 1);
+    return;
+  }
+  if (atomicExch(pos + v, (int32_t)k) != -1) atomicOr(bad, 1);
+}
+
+void launch_invert_perm(const int32_t* inv, int64_t n, int32_t* pos, int32_t* bad, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_invert_perm, dim3(unsigned((n + WG - 1) / WG)), dim3(WG), 0, s, inv, n, pos, bad);
+}
+
 }  // namespace spand

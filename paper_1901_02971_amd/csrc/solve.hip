@@ -181,9 +181,10 @@ spand_status pcg_solve(spand_ctx* h, int32_t nrhs, const double* b, double* x, d
   int broke_col = -1;
   int64_t replaced = 0;
   // the apply of this solve: one captured graph (same vectors every iteration),
-  // replayed on the handle's stream; device time of every apply from a pair of
-  // events around it
-  const bool use_graph = h->apply_graph && capture_apply(h, nrhs, r, z, scratch);
+  // replayed on the handle's stream from the second apply on; the first one is
+  // launched kernel by kernel and the graph is captured while the GPU runs it.
+  // Device time of every apply from a pair of events around it.
+  bool use_graph = false;
   EventPool evpool;
   size_t napply = 0;
   auto timed_apply = [&]() -> spand_status {
@@ -219,6 +220,7 @@ spand_status pcg_solve(spand_ctx* h, int32_t nrhs, const double* b, double* x, d
     HIPCHK(hipMemcpyAsync(p, z, vec * sizeof(double), hipMemcpyDeviceToDevice, s));
     launch_dot(r, z, n, nrhs, partial, nblk, rz, s);
   }
+  use_graph = any && h->apply_graph && capture_apply(h, nrhs, r, z, scratch);
   int32_t it = 0;
   while (any && it < maxit) {
     launch_spmv(h->d_rowptr.as<int64_t>(), h->d_colind.as<int32_t>(), h->d_values.as<double>(), n, nrhs, p, q, s);
