@@ -227,6 +227,9 @@ struct spand_ctx {
   spand_variant variant = SPAND_ORTHS;  // sparsification variant of the next factor
   std::string err;
   hipStream_t stream = nullptr;
+  // second stream of the factorization: the multi-slab CPQR launch of a colour class
+  // runs on it beside that class's single-slab launches (created on first use)
+  hipStream_t stream2 = nullptr;
   spand_stats stats{};
   bool factored = false;
   int device = -1;
@@ -251,6 +254,7 @@ struct spand_ctx {
   hipGraphExec_t graph_exec = nullptr;
   ~spand_ctx() {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (stream2) (void)hipStreamDestroy(stream2);
   }
 };
 

@@ -290,7 +290,15 @@ spand_status left_trsm(spand_ctx* h, const std::vector<LeftBlock>& B) {
   const int32_t CHOL_GROUP = std::max(1, h->tune.chol_group);
   int32_t nmax = 0;
   for (const LeftBlock& b : B) nmax = std::max(nmax, b.nrows);
+  // the blocks that share a triangular factor (hence its diagonal-block inverses)
+  // fill the workgroups of the diagonal solves together, 256 columns each
+  std::vector<int32_t> order(B.size());
+  for (size_t q = 0; q < B.size(); ++q) order[q] = int32_t(q);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    return std::less<const double*>()(B[x].dinv, B[y].dinv);
+  });
   std::vector<LeftDesc> ld;
+  std::vector<LeftSeg> ls;
   std::vector<int64_t> lcut;
   GemmSeq g(h->tune.gemm_scale);
   for (int32_t kb = 0; kb < nmax; kb += CHOL_NB) {
@@ -299,12 +307,25 @@ spand_status left_trsm(spand_ctx* h, const std::vector<LeftBlock>& B) {
     const int32_t kblk = kb / CHOL_NB;
     const bool pair = (kblk % CHOL_GROUP) == CHOL_GROUP - 1;
     const int32_t kg = (kblk / CHOL_GROUP) * CHOL_GROUP * CHOL_NB;
-    for (const LeftBlock& b : B) {
+    const double* cur = nullptr;  // Dinv of the open workgroup
+    int32_t fill = 0;             // its columns so far
+    for (int32_t ob : order) {
+      const LeftBlock& b = B[ob];
       if (b.nrows <= kb) continue;
       const int32_t w = std::min(CHOL_NB, b.nrows - kb);
       const double* Dk = b.dinv + int64_t(kb / CHOL_NB) * CHOL_NB * CHOL_NB;
-      for (int32_t c0 = 0; c0 < b.ncols; c0 += 256)
-        ld.push_back(LeftDesc{b.X + kb, Dk, b.ldx, w, c0, std::min(b.ncols, c0 + 256)});
+      for (int32_t c0 = 0; c0 < b.ncols;) {
+        if (Dk != cur || fill == 256) {
+          ld.push_back(LeftDesc{Dk, w, int32_t(ls.size()), 0, 0});
+          cur = Dk;
+          fill = 0;
+        }
+        const int32_t take = std::min(b.ncols - c0, 256 - fill);
+        ls.push_back(LeftSeg{b.X + kb + int64_t(c0) * b.ldx, b.ldx, take, fill, 0});
+        ++ld.back().nseg;
+        fill += take;
+        c0 += take;
+      }
       const int32_t ks = kg, r0 = kb + w;
       const int32_t r1 = pair ? b.nrows : std::min(b.nrows, r0 + CHOL_NB);
       GemmDesc q{};
@@ -318,13 +339,14 @@ spand_status left_trsm(spand_ctx* h, const std::vector<LeftBlock>& B) {
     lcut.push_back(int64_t(ld.size()));
     g.end_launch(0);
   }
-  DevBuf dl;
+  DevBuf dl, dsg;
   spand_status st;
   if ((st = upload(h, dl, ld)) != SPAND_OK) return st;
+  if ((st = upload(h, dsg, ls)) != SPAND_OK) return st;
   if ((st = g.upload_all(h)) != SPAND_OK) return st;
   for (size_t q = 0; q < lcut.size(); ++q) {
     const int64_t b = q ? lcut[q - 1] : 0;
-    launch_left_trsm_diag(dl.as<LeftDesc>() + b, int32_t(lcut[q] - b), h->stream);
+    launch_left_trsm_diag(dl.as<LeftDesc>() + b, dsg.as<LeftSeg>(), int32_t(lcut[q] - b), h->stream);
     g.launch(h, q);
   }
   HIPCHK(hipGetLastError());
@@ -1203,6 +1225,12 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
 
   EventPool phev;   // 5 phase boundaries per step, read after the last sync
   EventPool evpool; // every CPQR launch
+  EventPool joinev; // the joins of the two streams of the sparsification
+  size_t njoin = 0;
+  struct ColourSpan {
+    size_t ev, l0, l1;  // start event in joinev, CPQR launches [l0, l1) of evpool
+  };
+  std::vector<ColourSpan> colour_span;  // colour classes of the current step
   EventPool rbev;   // the rank read-back of every step
   std::vector<char> elim_ran(size_t(Lmax) + 1, 0);
   double cpqr_ms = 0.0;
@@ -1633,6 +1661,8 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
       // planned, so the GPU runs a colour while the host plans the next.  The
       // descriptor buffers of the colours stay allocated until the step ends.
       std::vector<DevBuf> colour_bufs;
+      hipEvent_t b_done = nullptr;  // the last multi-slab launch on the second stream
+      bool b_pending = false;       // ... not yet waited for on the handle's stream
       // launch groups of one colour: single-slab interfaces per team size G
       // (group G), the wide single-slab ones (group 128), then every multi-slab
       // interface of the colour together (group 256)
@@ -1836,46 +1866,81 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
           all_sds.push_back(d);
           launches.push_back(Lb);
         }
-        // this colour's launches: one upload of each descriptor list, then the launches
+        // this colour's launches: one upload of each descriptor list, then the launches.
+        // The multi-slab launch runs on the second stream beside the single-slab ones
+        // (independent interfaces of one colour; the single-slab workgroups never
+        // wait, so the multi-slab ones always get their CUs); the large-interface
+        // launches, which hold grid barriers, run after it.
         DevBuf a, b, sl;
         if ((st = upload_big(h, a, all_sds)) != SPAND_OK) return st;
         if ((st = upload_big(h, b, all_segs)) != SPAND_OK) return st;
         if ((st = upload_big(h, sl, all_slabs)) != SPAND_OK) return st;
-        for (const CpqrLaunch& Lc : launches) {
+        if (b_pending) {  // the previous colour's multi-slab launch
+          HIPCHK(hipStreamWaitEvent(h->stream, b_done, 0));
+          b_pending = false;
+        }
+        // start of the colour on the handle's stream: after everything before it,
+        // this colour's uploads included; the CPQR time of the colour runs from here
+        // to the last end of its launches on either stream
+        hipEvent_t cstart;
+        HIPCHK(joinev.get(njoin, &cstart));
+        HIPCHK(hipEventRecord(cstart, h->stream));
+        colour_span.push_back(ColourSpan{njoin++, nlaunch, 0});
+        auto issue = [&](const CpqrLaunch& Lc, hipStream_t sq) -> spand_status {
           hipEvent_t e0, e1;
           HIPCHK(evpool.get(2 * nlaunch, &e0));
           HIPCHK(evpool.get(2 * nlaunch + 1, &e1));
-          HIPCHK(hipEventRecord(e0, h->stream));
+          HIPCHK(hipEventRecord(e0, sq));
           const SparsDesc* dd = a.as<SparsDesc>() + Lc.d0;
           const SlabRef* ss = sl.as<SlabRef>() + Lc.s0;
+          hipError_t le;
           if (Lc.big_nseg >= 0) {
-            HIPCHK(hipMemsetAsync(bbar.p, 0, 256, h->stream));
-            hipError_t le = launch_cpqr_big(all_sds[Lc.d0], Lc.big_nseg, b.as<SegDesc>(), tol, curb.as<int32_t>(),
-                                            nrefb.as<int32_t>(), errb.as<int32_t>(), Lc.nslab, bwk.as<double>(),
-                                            bnrm.as<double>(), bpst.as<int32_t>(), brb.as<double>(), bpost.as<double>(),
-                                            bpcd.as<int32_t>(), bbar.as<uint32_t>(), h->stream);
-            if (le != hipSuccess)
-              return set_err(h, SPAND_E_HIP, std::string("large-interface sparsification launch: ") + hipGetErrorString(le));
-            HIPCHK(hipEventRecord(e1, h->stream));
-            ++nlaunch;
-            continue;
+            HIPCHK(hipMemsetAsync(bbar.p, 0, 256, sq));
+            le = launch_cpqr_big(all_sds[Lc.d0], Lc.big_nseg, b.as<SegDesc>(), tol, curb.as<int32_t>(),
+                                 nrefb.as<int32_t>(), errb.as<int32_t>(), Lc.nslab, bwk.as<double>(), bnrm.as<double>(),
+                                 bpst.as<int32_t>(), brb.as<double>(), bpost.as<double>(), bpcd.as<int32_t>(),
+                                 bbar.as<uint32_t>(), sq);
+          } else if (Lc.multi) {
+            le = launch_cpqr_multi(dd, ss, Lc.nslab, Lc.nround, b.as<SegDesc>(), tol, curb.as<int32_t>(),
+                                   nrefb.as<int32_t>(), errb.as<int32_t>(), Lc.lds, sq);
+          } else if (Lc.G == 128) {
+            le = launch_cpqr_one_wide(dd, ss, Lc.nslab, b.as<SegDesc>(), tol, curb.as<int32_t>(), nrefb.as<int32_t>(),
+                                      errb.as<int32_t>(), Lc.lds, sq);
+          } else {
+            le = launch_cpqr_one(Lc.G, dd, ss, Lc.nslab, b.as<SegDesc>(), tol, curb.as<int32_t>(), nrefb.as<int32_t>(),
+                                 errb.as<int32_t>(), Lc.lds, sq);
           }
-          hipError_t le = Lc.multi ? launch_cpqr_multi(dd, ss, Lc.nslab, Lc.nround, b.as<SegDesc>(), tol,
-                                                       curb.as<int32_t>(), nrefb.as<int32_t>(), errb.as<int32_t>(),
-                                                       Lc.lds, h->stream)
-                       : Lc.G == 128 ? launch_cpqr_one_wide(dd, ss, Lc.nslab, b.as<SegDesc>(), tol, curb.as<int32_t>(),
-                                                            nrefb.as<int32_t>(), errb.as<int32_t>(), Lc.lds, h->stream)
-                                     : launch_cpqr_one(Lc.G, dd, ss, Lc.nslab, b.as<SegDesc>(), tol, curb.as<int32_t>(),
-                                                       nrefb.as<int32_t>(), errb.as<int32_t>(), Lc.lds, h->stream);
           if (le != hipSuccess)
             return set_err(h, SPAND_E_HIP, std::string("sparsification launch: ") + hipGetErrorString(le));
-          HIPCHK(hipEventRecord(e1, h->stream));
+          HIPCHK(hipEventRecord(e1, sq));
           ++nlaunch;
+          return SPAND_OK;
+        };
+        for (const CpqrLaunch& Lc : launches) {
+          if (!Lc.multi) continue;
+          if (!h->stream2) HIPCHK(hipStreamCreateWithFlags(&h->stream2, hipStreamNonBlocking));
+          HIPCHK(hipStreamWaitEvent(h->stream2, cstart, 0));
+          if ((st = issue(Lc, h->stream2)) != SPAND_OK) return st;
+          HIPCHK(joinev.get(njoin++, &b_done));
+          HIPCHK(hipEventRecord(b_done, h->stream2));
+          b_pending = true;
         }
+        for (const CpqrLaunch& Lc : launches)
+          if (!Lc.multi && Lc.big_nseg < 0 && (st = issue(Lc, h->stream)) != SPAND_OK) return st;
+        for (const CpqrLaunch& Lc : launches) {
+          if (Lc.big_nseg < 0) continue;
+          if (b_pending) {
+            HIPCHK(hipStreamWaitEvent(h->stream, b_done, 0));
+            b_pending = false;
+          }
+          if ((st = issue(Lc, h->stream)) != SPAND_OK) return st;
+        }
+        colour_span.back().l1 = nlaunch;
         colour_bufs.push_back(std::move(a));
         colour_bufs.push_back(std::move(b));
         colour_bufs.push_back(std::move(sl));
       }
+      if (b_pending) HIPCHK(hipStreamWaitEvent(h->stream, b_done, 0));
       HIPCHK(hipEventRecord(ph[4], h->stream));
     }
     // ---- interpolative sparsification (Sec. 2.6.2) of the problems that ask for it
@@ -1926,11 +1991,16 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
     std::vector<int32_t> rk(pin_rk, pin_rk + ncl), nrefh(pin_nref, pin_nref + ncl);
     const int32_t serr = *pin_err;
     if (serr) return set_err(h, SPAND_E_HIP, "sparsification slab exchange timed out");
-    for (size_t q = 0; q < nlaunch; ++q) {
-      float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, evpool.ev[2 * q], evpool.ev[2 * q + 1]));
-      cpqr_ms += ms;
+    for (const ColourSpan& cs : colour_span) {  // the launches of a colour overlap
+      float span = 0.f;
+      for (size_t q = cs.l0; q < cs.l1; ++q) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, joinev.ev[cs.ev], evpool.ev[2 * q + 1]));
+        span = std::max(span, ms);
+      }
+      cpqr_ms += span;
     }
+    colour_span.clear();
     cpqr_launches += int64_t(nlaunch);
     // Kernels that ran after a failure in the same step only saw bad values, never bad
     // indices; the failed problem stops here, the others go on.

@@ -200,16 +200,23 @@ __global__ void __launch_bounds__(PW) k_panel_trsm(const PanelDesc* __restrict__
     }
 }
 
-// columns [c0, c1) of X (rows kb..kb+w): x <- L_kk^{-1} x
-__global__ void __launch_bounds__(PW) k_left_trsm_diag(const LeftDesc* __restrict__ descs) {
+// One column per thread (rows kb..kb+w): x <- L_kk^{-1} x; the workgroup's columns
+// come from the segments of its descriptor, which all share L_kk.
+__global__ void __launch_bounds__(PW) k_left_trsm_diag(const LeftDesc* __restrict__ descs,
+                                                       const LeftSeg* __restrict__ segs) {
   const LeftDesc d = descs[blockIdx.x];
   const int w = d.w;
   __shared__ double Xi[CHOL_NB][CHOL_NB + 1];
   stage_inverse(d.Dinv, w, Xi);
   __syncthreads();
-  const int c = d.c0 + threadIdx.x;
-  if (c >= d.c1) return;
-  double* col = d.X + (int64_t)c * d.ldx;
+  const int t = threadIdx.x;
+  int sg = d.seg0;
+  const int se = d.seg0 + d.nseg;
+  while (sg + 1 < se && segs[sg + 1].t0 <= t) ++sg;
+  const LeftSeg g = segs[sg];
+  const int c = t - g.t0;
+  if (c < 0 || c >= g.ncols) return;
+  double* col = g.X + (int64_t)c * g.ldx;
   double x[CHOL_NB];  // x[k] for k >= w is read from row w - 1 and only enters outputs i >= w
 #pragma unroll
   for (int k = 0; k < CHOL_NB; ++k) x[k] = gldc(col + (k < w ? k : w - 1));
@@ -231,9 +238,9 @@ void launch_panel_trsm(const PanelDesc* d, int32_t count, hipStream_t s) {
   if (count == 0) return;
   hipLaunchKernelGGL(k_panel_trsm, dim3(count), dim3(PW), 0, s, d);
 }
-void launch_left_trsm_diag(const LeftDesc* d, int32_t count, hipStream_t s) {
+void launch_left_trsm_diag(const LeftDesc* d, const LeftSeg* segs, int32_t count, hipStream_t s) {
   if (count == 0) return;
-  hipLaunchKernelGGL(k_left_trsm_diag, dim3(count), dim3(PW), 0, s, d);
+  hipLaunchKernelGGL(k_left_trsm_diag, dim3(count), dim3(PW), 0, s, d, segs);
 }
 
 }  // namespace spand
