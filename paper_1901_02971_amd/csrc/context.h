@@ -188,6 +188,7 @@ struct StepNum {
   std::vector<int64_t> slot_ptr;
   std::vector<int32_t> slot;    // current dofs of every cluster (vertex ids)
   DevBuf elim, scale, house;    // factor pieces: [L_s; G_s] panels, L_p, reflectors
+  DevBuf iso;                   // L_s^{-1} of eliminated clusters without neighbours (the top separator)
   DevBuf edinv, sdinv;          // inverses of the CHOL_NB-wide diagonal blocks of L_s, L_p
                                 // (scale holds L_p^{-1} itself)
   DevBuf d_slot, d_nslot;       // slot arrays on the device
@@ -196,6 +197,7 @@ struct StepNum {
   int32_t n_iface1 = 0, n_iface2 = 0;  // small interfaces with np <= 64, then np <= 128
   int32_t n_elim_ap = 0, n_target = 0, n_scale = 0, n_house = 0, n_etile = 0, n_hr = 0, n_hv = 0, n_stile = 0;
   int32_t n_ftile = 0;
+  int32_t n_iso = 0;  // entries of h_scale that are eliminated clusters (their L_s^{-1})
   int64_t sgather_len = 0;
   int64_t nslot_len = 0;
   int64_t tmp_elim = 0, tmp_scale = 0;  // doubles per RHS of temp needed

@@ -362,6 +362,7 @@ struct ApplyPlan {
   int32_t t = 0;
   std::vector<int64_t> ed_off, sc_off, v_off, t_off;
   std::vector<int32_t> nN, nref;
+  std::vector<int64_t> iso_off;  // offset of L_s^{-1} in the step's iso buffer, -1 if none
 };
 
 spand_status build_apply(spand_ctx* h, const SymStep& sy, StepNum& sn, const Layout& lay, const ApplyPlan& pl) {
@@ -377,13 +378,18 @@ spand_status build_apply(spand_ctx* h, const SymStep& sy, StepNum& sn, const Lay
   std::vector<int32_t> nslot;
   int64_t tmp = 0;
   sn.h_elim.clear();
+  const std::vector<int64_t>& iso_off = pl.iso_off;
+  auto isolated = [&](int32_t s) { return s < int32_t(iso_off.size()) && iso_off[s] >= 0; };
   for (int32_t s = 0; s < ne; ++s) {
     ElimAp e{};
     e.L = E + lay.base[s];
     e.G = E + lay.base[s] + sn.size[s];
     e.Dinv = sn.edinv.as<double>() + ed_off[s];
     e.ld = int32_t(lay.H[s]);
-    e.ns = sn.size[s];
+    // a cluster with no neighbours and an explicit inverse goes through the scaling
+    // kernels below (x_s <- L_s^{-1} x_s, and its transpose backward), not through
+    // the blocked substitution
+    e.ns = isolated(s) ? 0 : sn.size[s];
     e.nN = nN[s];
     e.slot_s = sn.slot_ptr[s];
     e.slot_N = int64_t(nslot.size());
@@ -506,6 +512,23 @@ spand_status build_apply(spand_ctx* h, const SymStep& sy, StepNum& sn, const Lay
       sn.h_house.push_back(hp);
     }
   }
+  sn.n_iso = 0;
+  for (int32_t s = 0; s < ne; ++s) {
+    if (!isolated(s) || sn.size[s] == 0) continue;
+    ++sn.n_iso;
+    ScaleAp a{};
+    a.Linv = sn.iso.as<double>() + iso_off[s];
+    a.np = sn.size[s];
+    a.ldl = pad16(a.np);
+    a.slot_p = sn.slot_ptr[s];
+    a.tmp = tmp2;
+    tmp2 += sn.size[s];
+    const int32_t sid = int32_t(sn.h_scale.size());
+    for (int32_t r0 = 0; r0 < a.np; r0 += 64) sn.h_stile.push_back(ScaleTile{sid, r0});
+    sn.h_sgather.insert(sn.h_sgather.end(), sn.slot.begin() + sn.slot_ptr[s],
+                        sn.slot.begin() + sn.slot_ptr[s] + sn.size[s]);
+    sn.h_scale.push_back(a);
+  }
   sn.n_iface1 = int32_t(if1.size());
   sn.n_iface2 = int32_t(if2.size());
   sn.h_iface = std::move(if1);
@@ -568,7 +591,7 @@ struct Prob {
   // this step
   bool on = false, sparsify = false;
   int64_t cbase = 0;            // first entry of this problem's clusters in the run's size and rank arrays
-  std::vector<int64_t> c_off, ed_off, sc_off, sd_off, v_off, tau_off, t_off, xch_off, ncols;
+  std::vector<int64_t> c_off, ed_off, sc_off, sd_off, v_off, tau_off, t_off, xch_off, ncols, iso_off;
   std::vector<int32_t> nN, nref, slabS, tg, nseg, rlay;
   std::vector<char> wide, big;
   int64_t cpqr_big = 0;         // interfaces of the global-memory CPQR kernel
@@ -1377,6 +1400,49 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
       if ((st = syrk.upload_all(h)) != SPAND_OK) return st;
       syrk.launch(h, 0);
       HIPCHK(hipGetLastError());
+      {
+        // Clusters without neighbours (the top separator): L_s^{-1} itself (the
+        // identity solved against L_s), so that the apply multiplies by it over
+        // 64-row tiles in parallel instead of a substitution chained over its
+        // 64-row blocks in one workgroup.
+        std::vector<LeftBlock> lb;
+        std::vector<IdentDesc> ids;
+        for (Prob* pp : act) {
+          Prob& pb = *pp;
+          spand_ctx* hq = pb.h;
+          const SymStep& sy = hq->an.steps[t - 1];
+          StepNum& sn = hq->num[t - 1];
+          const Layout& lay = pb.lay;
+          const int32_t ne = sy.ne;
+          pb.iso_off.assign(ne, -1);
+          int64_t iso_total = 0;
+          for (int32_t s = 0; s < ne; ++s)
+            if (sn.size[s] > 0 && pb.nN[s] == 0) {
+              pb.iso_off[s] = iso_total;
+              iso_total += int64_t(pad16(sn.size[s])) * sn.size[s];
+            }
+          if (iso_total == 0) {
+            sn.iso.release();
+            continue;
+          }
+          if ((st = dalloc(hq, sn.iso, size_t(iso_total) * sizeof(double))) != SPAND_OK) return st;
+          double* E = sn.elim.as<double>();
+          double* ISO = sn.iso.as<double>();
+          for (int32_t s = 0; s < ne; ++s) {
+            if (pb.iso_off[s] < 0) continue;
+            add_identity(ids, ISO + pb.iso_off[s], sn.size[s], pad16(sn.size[s]));
+            lb.push_back(LeftBlock{ISO + pb.iso_off[s], E + lay.base[s], sn.edinv.as<double>() + pb.ed_off[s],
+                                   pad16(sn.size[s]), int32_t(lay.H[s]), sn.size[s], sn.size[s]});
+          }
+        }
+        if (!lb.empty()) {
+          DevBuf di;
+          if ((st = upload(h, di, ids)) != SPAND_OK) return st;
+          launch_set_identity(di.as<IdentDesc>(), int32_t(ids.size()), h->stream);
+          HIPCHK(hipGetLastError());
+          if ((st = left_trsm(h, lb)) != SPAND_OK) return st;
+        }
+      }
       for (Prob* pp : act) {
         Prob& pb = *pp;
         spand_ctx* hq = pb.h;
@@ -2069,7 +2135,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
       if (NP == 1) frozen_at(sy, sn, pb.frozen);
       if (t <= 32) hq->stats.step_m_F[t - 1] = pb.m_F;
       pb.pending = ApplyPlan{t, std::move(pb.ed_off), std::move(pb.sc_off), std::move(pb.v_off), std::move(pb.t_off),
-                             std::move(pb.nN), std::move(pb.nref)};
+                             std::move(pb.nN), std::move(pb.nref), std::move(pb.iso_off)};
       pb.arena_prev = std::move(pb.arena);
       pb.lay_prev = std::move(pb.lay);
     }
@@ -2138,7 +2204,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
     for (const StepNum& sn : pb.h->num) {
       s.apply_interfaces[0] += sn.n_iface1;
       s.apply_interfaces[1] += sn.n_iface2;
-      s.apply_interfaces[2] += sn.n_scale;
+      s.apply_interfaces[2] += sn.n_scale - sn.n_iso;
     }
   }
   return SPAND_OK;
