@@ -227,6 +227,11 @@ struct spand_ctx {
   spand::Analysis an;
   spand_tuning tune = spand::default_tuning();
   spand_variant variant = SPAND_ORTHS;  // sparsification variant of the next factor
+  // Kept ranks of the last completed factorization (per step and cluster) and its
+  // tolerance.  A refactorization at the same tolerance takes them as the step
+  // counts of its CPQR list schedule; the schedule never changes what is computed.
+  std::vector<std::vector<int32_t>> last_rank;
+  double last_rank_tol = -1.0;
   std::string err;
   hipStream_t stream = nullptr;
   // second stream of the factorization: the multi-slab CPQR launch of a colour class

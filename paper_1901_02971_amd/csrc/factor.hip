@@ -1751,9 +1751,24 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
           }
           if (plist.empty()) continue;
           auto msize = [&](const Ref& f) { return f.pb->h->num[t - 1].size[f.p]; };
-          // largest first: interfaces of similar step counts share a launch
+          // Householder steps of an interface, for the schedule: min(m, ncols) bounds
+          // the rank; a refactorization at the same tolerance takes the rank that the
+          // interface kept the last time, plus the step that stops
+          auto steps_est = [&](const Ref& f) -> int64_t {
+            const spand_ctx* hq = f.pb->h;
+            const int64_t ub = std::min<int64_t>(msize(f), f.pb->ncols[f.p]);
+            if (hq->last_rank_tol == tol && int64_t(hq->last_rank.size()) >= t) {
+              const std::vector<int32_t>& lr = hq->last_rank[t - 1];
+              if (f.p < int32_t(lr.size()) && lr[f.p] >= 0) return std::min<int64_t>(ub, int64_t(lr[f.p]) + 1);
+            }
+            return ub;
+          };
+          // longest first: interfaces of similar step counts share a launch
           std::stable_sort(plist.begin(), plist.end(), [&](const Ref& x, const Ref& y) {
-            if (multi) return msize(x) > msize(y);
+            if (multi) {
+              const int64_t ex = steps_est(x), ey = steps_est(y);
+              return ex != ey ? ex > ey : msize(x) > msize(y);
+            }
             return int64_t(msize(x)) * x.pb->ncols[x.p] > int64_t(msize(y)) * y.pb->ncols[y.p];
           });
           size_t lds = 0;
@@ -1868,7 +1883,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
                 wg.push_back(heap.back().second);
                 heap.pop_back();
               }
-              tt += std::min<int64_t>(msize(f), f.pb->ncols[f.p]);
+              tt += steps_est(f);
               for (int32_t k = 0; k < S; ++k) {
                 lists[wg[k]].push_back(ifs[q].first[k]);
                 heap.push_back(Slot{tt, wg[k]});
@@ -2187,6 +2202,9 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
   for (Prob& pb : P) {
     pb.arena_prev.release();
     if (!pb.live) continue;
+    pb.h->last_rank.resize(pb.h->num.size());
+    for (size_t q = 0; q < pb.h->num.size(); ++q) pb.h->last_rank[q] = pb.h->num[q].rank;
+    pb.h->last_rank_tol = tol;
     spand_stats& s = pb.h->stats;
     std::memcpy(s.step_phase_seconds, phase_s, sizeof(phase_s));
     s.m_F = pb.m_F;
