@@ -141,6 +141,29 @@ def test_deterministic_fp64():
     assert np.array_equal(xs[0], xs[1])
 
 
+def test_refactor_schedule_is_bit_identical():
+    """A refactorization at the same tolerance lists the multi-slab CPQR work by the
+    ranks of the previous factorization, and the colour classes' multi-slab launches run
+    on a second stream beside the single-slab ones: neither changes a bit of the
+    factors.  The 24^3 Laplacian at 5 levels takes every CPQR layout; the apply after
+    the second factorization equals the first bit for bit, with the same ranks."""
+    p = gridgen.laplacian((24, 24, 24))
+    b = gridgen.rhs(np.random.default_rng(13), p.n, 3)
+    from paper_1901_02971_amd import Solver
+    vals = torch.from_numpy(p.values).to("cuda:0")
+    s = Solver.from_problem(p, 5)
+    s.factor(vals, 1e-2)
+    st1 = s.stats()
+    assert all(k > 0 for k in st1["cpqr_interfaces"]), st1["cpqr_interfaces"]
+    z1 = gpu_apply(s, b)
+    s.factor(vals, 1e-2)
+    st2 = s.stats()
+    z2 = gpu_apply(s, b)
+    assert np.array_equal(z1, z2)
+    assert (st1["s_top"], st1["m_F"]) == (st2["s_top"], st2["m_F"])
+    s.close()
+
+
 def test_refactor_same_handle():
     """A handle is refactored with new values and a new tolerance."""
     import torch as T
