@@ -284,6 +284,7 @@ struct LeftBlock {
   const double* L;
   const double* dinv;
   int32_t ldx, ldl, nrows, ncols;
+  int32_t key;  // blocks with one key share L (and dinv); keys are small and >= 0
 };
 
 spand_status left_trsm(spand_ctx* h, const std::vector<LeftBlock>& B) {
@@ -291,15 +292,19 @@ spand_status left_trsm(spand_ctx* h, const std::vector<LeftBlock>& B) {
   int32_t nmax = 0;
   for (const LeftBlock& b : B) nmax = std::max(nmax, b.nrows);
   // the blocks that share a triangular factor (hence its diagonal-block inverses)
-  // fill the workgroups of the diagonal solves together, 256 columns each
-  std::vector<int32_t> order(B.size());
-  for (size_t q = 0; q < B.size(); ++q) order[q] = int32_t(q);
-  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-    return std::less<const double*>()(B[x].dinv, B[y].dinv);
-  });
+  // fill the workgroups of the diagonal solves together, 256 columns each: the blocks
+  // in key order (a counting sort, stable)
+  int32_t kmax = -1;
+  for (const LeftBlock& b : B) kmax = std::max(kmax, b.key);
+  std::vector<int32_t> kstart(size_t(kmax) + 2, 0);
+  for (const LeftBlock& b : B) ++kstart[size_t(b.key) + 1];
+  for (size_t k = 1; k < kstart.size(); ++k) kstart[k] += kstart[k - 1];
+  std::vector<LeftBlock> Bs(B.size());
+  for (const LeftBlock& b : B) Bs[size_t(kstart[size_t(b.key)]++)] = b;
   std::vector<LeftDesc> ld;
   std::vector<LeftSeg> ls;
   std::vector<int64_t> lcut;
+  ls.reserve(Bs.size() * size_t((nmax + CHOL_NB - 1) / CHOL_NB));
   GemmSeq g(h->tune.gemm_scale);
   for (int32_t kb = 0; kb < nmax; kb += CHOL_NB) {
     // grouped as in blocked_cholesky: inside a group only the next block row is
@@ -309,8 +314,7 @@ spand_status left_trsm(spand_ctx* h, const std::vector<LeftBlock>& B) {
     const int32_t kg = (kblk / CHOL_GROUP) * CHOL_GROUP * CHOL_NB;
     const double* cur = nullptr;  // Dinv of the open workgroup
     int32_t fill = 0;             // its columns so far
-    for (int32_t ob : order) {
-      const LeftBlock& b = B[ob];
+    for (const LeftBlock& b : Bs) {
       if (b.nrows <= kb) continue;
       const int32_t w = std::min(CHOL_NB, b.nrows - kb);
       const double* Dk = b.dinv + int64_t(kb / CHOL_NB) * CHOL_NB * CHOL_NB;
@@ -1432,7 +1436,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
             if (pb.iso_off[s] < 0) continue;
             add_identity(ids, ISO + pb.iso_off[s], sn.size[s], pad16(sn.size[s]));
             lb.push_back(LeftBlock{ISO + pb.iso_off[s], E + lay.base[s], sn.edinv.as<double>() + pb.ed_off[s],
-                                   pad16(sn.size[s]), int32_t(lay.H[s]), sn.size[s], sn.size[s]});
+                                   pad16(sn.size[s]), int32_t(lay.H[s]), sn.size[s], sn.size[s], int32_t(lb.size())});
           }
         }
         if (!lb.empty()) {
@@ -1514,6 +1518,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
       std::vector<Front> fr;
       std::vector<LeftBlock> lb;
       std::vector<IdentDesc> ids, did;
+      int32_t kbase = 0;  // left-solve keys: kbase + cluster of the factor, per problem
       for (Prob* pp : act) {
         Prob& pb = *pp;
         spand_ctx* hq = pb.h;
@@ -1555,14 +1560,15 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
           if (sn.size[p] == 0) continue;
           add_identity(ids, SC + pb.sc_off[p], sn.size[p], pad16(sn.size[p]));
           lb.push_back(LeftBlock{SC + pb.sc_off[p], A + lay.base[p], SD + pb.sd_off[p], pad16(sn.size[p]), int32_t(lay.H[p]),
-                                 sn.size[p], sn.size[p]});
+                                 sn.size[p], sn.size[p], kbase + p});
           for (int64_t e = lay.pan_ptr[p] + 1; e < lay.pan_ptr[p + 1]; ++e) {
             const int32_t i = lay.prow[e];
             if (sn.size[i] == 0) continue;
             lb.push_back(LeftBlock{A + lay.base[p] + lay.proff[e], A + lay.base[i], SD + pb.sd_off[i],
-                                   int32_t(lay.H[p]), int32_t(lay.H[i]), sn.size[i], sn.size[p]});
+                                   int32_t(lay.H[p]), int32_t(lay.H[i]), sn.size[i], sn.size[p], kbase + i});
           }
         }
+        kbase += nc;
         for (int32_t p = ne; p < nc; ++p)
           if (sn.size[p] > 0) add_identity(did, A + lay.base[p], sn.size[p], int32_t(lay.H[p]));
       }
