@@ -592,6 +592,7 @@ struct Prob {
   int64_t cpqr_ifaces[4] = {0, 0, 0, 0};  // single, wide, multi (32 x 2), multi (20 x 3)
   int32_t s_top = 0;
   std::vector<int32_t> frozen;  // vertices in the order the steps freeze them (freeze_order)
+  size_t frozen_up = 0;         // entries of frozen already copied to the device (d_inv)
   // this step
   bool on = false, sparsify = false;
   int64_t cbase = 0;            // first entry of this problem's clusters in the run's size and rank arrays
@@ -1180,11 +1181,16 @@ void frozen_at(const SymStep& sy, const StepNum& sn, std::vector<int32_t>& inv) 
   }
 }
 
-spand_status freeze_order(spand_ctx* h, const std::vector<int32_t>& inv, DevBuf& bad) {
+spand_status freeze_order(spand_ctx* h, const std::vector<int32_t>& inv, size_t uploaded, DevBuf& bad) {
   const int64_t n = h->an.n;
   if (int64_t(inv.size()) != n) return set_err(h, SPAND_E_INVALID, "freeze order does not cover every dof");
+  if (h->d_inv.bytes < size_t(n) * sizeof(int32_t) || uploaded > inv.size())
+    return set_err(h, SPAND_E_INVALID, "freeze order buffer missing");
   spand_status st;
-  if ((st = upload_big(h, h->d_inv, inv)) != SPAND_OK) return st;
+  // entries [0, uploaded) went to the device during the steps; the rest goes now
+  if ((st = stage_copy(h, h->d_inv.as<int32_t>() + uploaded, inv.data() + uploaded,
+                       (inv.size() - uploaded) * sizeof(int32_t))) != SPAND_OK)
+    return st;
   // the inverse is formed on the device; bad is read at the end of the factorization
   if ((st = dalloc(h, h->d_pos, size_t(n) * sizeof(int32_t))) != SPAND_OK) return st;
   if ((st = dalloc(h, bad, sizeof(int32_t))) != SPAND_OK) return st;
@@ -1229,7 +1235,12 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
     pb.h->d_pos.release();
     pb.h->d_inv.release();
     pb.frozen.clear();
-    if (P.size() == 1) pb.frozen.reserve(size_t(pb.h->an.n));
+    pb.frozen_up = 0;
+    if (P.size() == 1) {
+      pb.frozen.reserve(size_t(pb.h->an.n));
+      // the freeze order is copied to the device step by step, while later steps run
+      if ((st = dalloc(pb.h, pb.h->d_inv, size_t(pb.h->an.n) * sizeof(int32_t))) != SPAND_OK) return st;
+    }
     std::memset(pb.h->stats.step_phase_seconds, 0, sizeof(pb.h->stats.step_phase_seconds));
     std::memset(pb.h->stats.step_m_F, 0, sizeof(pb.h->stats.step_m_F));
   }
@@ -2072,6 +2083,12 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
       if (!pb.live) continue;
       if ((st = build_apply(pb.h, pb.h->an.steps[pt - 1], pb.h->num[pt - 1], pb.lay_prev, pb.pending)) != SPAND_OK)
         return st;
+      if (NP == 1 && pb.frozen.size() > pb.frozen_up) {  // the dofs frozen so far
+        if ((st = stage_copy(pb.h, pb.h->d_inv.as<int32_t>() + pb.frozen_up, pb.frozen.data() + pb.frozen_up,
+                             (pb.frozen.size() - pb.frozen_up) * sizeof(int32_t))) != SPAND_OK)
+          return st;
+        pb.frozen_up = pb.frozen.size();
+      }
     }
     HIPCHK(hipEventSynchronize(readback));
     std::copy(pin, pin + hflags.size(), hflags.begin());
@@ -2180,7 +2197,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
   DevBuf badperm;
   int32_t* pin_bad = nullptr;
   if (NP == 1 && P[0].live) {
-    if ((st = freeze_order(P[0].h, P[0].frozen, badperm)) != SPAND_OK) return st;
+    if ((st = freeze_order(P[0].h, P[0].frozen, P[0].frozen_up, badperm)) != SPAND_OK) return st;
     pin_bad = reinterpret_cast<int32_t*>(h->stage.get(sizeof(int32_t)));
     if (!pin_bad) return set_err(h, SPAND_E_NOMEM, "pinned staging for the freeze-order check failed");
     HIPCHK(hipMemcpyAsync(pin_bad, badperm.p, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
