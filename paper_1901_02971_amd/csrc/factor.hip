@@ -713,37 +713,50 @@ void step_sizes(const SymStep& sy, int32_t t, std::vector<StepNum>& num) {
 // Merge copies of step t (> 1) of one problem: parent blocks are the concatenation
 // of the children's kept blocks (Sec. 2.7).  Large steps are planned by several host
 // threads over contiguous ranges of block pairs; the list is the same as one thread's.
-void plan_merge(const SymStep& sy, const StepNum& pv, const Layout& lay, const Layout& lay_prev, double* E, double* A,
-                const double* arena_prev, std::vector<CopyDesc>& out) {
-  auto plan_copies = [&](size_t q0, size_t q1, std::vector<CopyDesc>& dst) {
+// The merge of one problem into step t: copy descriptors of the blocks of the previous
+// step's kept dofs into the new panels, by cluster pairs of the new step.
+struct MergeJob {
+  const SymStep* sy;
+  const StepNum* pv;
+  const Layout* lay;
+  const Layout* lay_prev;
+  double *E, *A;
+  const double* arena_prev;
+  // the descriptors of pairs [q0, q1) (count only when dst is null); returns how many
+  size_t plan(size_t q0, size_t q1, CopyDesc* dst) const {
+    size_t n = 0;
     for (size_t q = q0; q < q1; ++q) {
-      const uint64_t pr = sy.before[q];
+      const uint64_t pr = sy->before[q];
       const int32_t I = pair_i(pr), J = pair_j(pr);
-      double* dbase = lay.panel(J, E, A) + lay.find(I, J);
+      double* dbase = dst ? lay->panel(J, E, A) + lay->find(I, J) : nullptr;
       int64_t ro = 0;
-      for (int64_t a = sy.child_ptr[I]; a < sy.child_ptr[I + 1]; ++a) {
-        const int32_t i = sy.child[a];
-        const int32_t ri = pv.rank[i];
+      for (int64_t a = sy->child_ptr[I]; a < sy->child_ptr[I + 1]; ++a) {
+        const int32_t i = sy->child[a];
+        const int32_t ri = pv->rank[i];
         int64_t co = 0;
-        for (int64_t b = sy.child_ptr[J]; b < sy.child_ptr[J + 1]; ++b) {
-          const int32_t j = sy.child[b];
-          const int32_t rj = pv.rank[j];
+        for (int64_t b = sy->child_ptr[J]; b < sy->child_ptr[J + 1]; ++b) {
+          const int32_t j = sy->child[b];
+          const int32_t rj = pv->rank[j];
           if (ri > 0 && rj > 0) {
             const int32_t hi = std::max(i, j), lo = std::min(i, j);
-            const int64_t so = lay_prev.find(hi, lo);
+            const int64_t so = lay_prev->find(hi, lo);
             if (so >= 0) {
-              CopyDesc cd;
-              cd.src = arena_prev + lay_prev.base[lo] + so;
-              cd.lds = int32_t(lay_prev.H[lo]);
-              cd.trans = (i < j) ? 1 : 0;
-              cd.rows = ri;
-              cd.dst = dbase + ro + co * lay.H[J];
-              cd.ldd = int32_t(lay.H[J]);
               const int32_t step = std::max(1, COPY_CHUNK / ri);  // column ranges of at most COPY_CHUNK entries
-              for (int32_t c0 = 0; c0 < rj; c0 += step) {
-                cd.c0 = c0;
-                cd.c1 = std::min(rj, c0 + step);
-                dst.push_back(cd);
+              if (!dst) {
+                n += size_t((rj + step - 1) / step);
+              } else {
+                CopyDesc cd;
+                cd.src = arena_prev + lay_prev->base[lo] + so;
+                cd.lds = int32_t(lay_prev->H[lo]);
+                cd.trans = (i < j) ? 1 : 0;
+                cd.rows = ri;
+                cd.dst = dbase + ro + co * lay->H[J];
+                cd.ldd = int32_t(lay->H[J]);
+                for (int32_t c0 = 0; c0 < rj; c0 += step) {
+                  cd.c0 = c0;
+                  cd.c1 = std::min(rj, c0 + step);
+                  dst[n++] = cd;
+                }
               }
             }
           }
@@ -752,25 +765,53 @@ void plan_merge(const SymStep& sy, const StepNum& pv, const Layout& lay, const L
         ro += ri;
       }
     }
+    return n;
+  }
+};
+
+// The copy descriptors of every merge job, counted and then written straight into
+// the pinned staging (in job and pair order, the same list one thread would build) by
+// up to 8 threads over ranges of cluster pairs; one upload.  Returns the count.
+spand_status plan_merges(spand_ctx* h, const std::vector<MergeJob>& jobs, DevBuf& out, int64_t& count) {
+  struct Range {
+    size_t job, q0, q1, off, n;
   };
-  const size_t npair = sy.before.size();
-  const size_t nth = std::min<size_t>(8, std::max<size_t>(1, npair / 4096));
-  if (nth == 1) {
-    plan_copies(0, npair, out);
-    return;
+  std::vector<Range> rs;
+  for (size_t k = 0; k < jobs.size(); ++k) {
+    const size_t npair = jobs[k].sy->before.size();
+    const size_t nr = std::min<size_t>(32, std::max<size_t>(1, npair / 2048));
+    for (size_t c = 0; c < nr; ++c) rs.push_back(Range{k, npair * c / nr, npair * (c + 1) / nr, 0, 0});
   }
-  std::vector<std::vector<CopyDesc>> part(nth);
-  {
+  const size_t nth = std::min<size_t>(8, rs.size());
+  auto run = [&](auto&& fn) {
+    if (nth <= 1) {
+      for (size_t r = 0; r < rs.size(); ++r) fn(r);
+      return;
+    }
     std::vector<std::thread> pool;
-    for (size_t k = 1; k < nth; ++k)
-      pool.emplace_back(plan_copies, npair * k / nth, npair * (k + 1) / nth, std::ref(part[k]));
-    plan_copies(0, npair / nth, part[0]);
+    auto worker = [&](size_t w) {
+      for (size_t r = w; r < rs.size(); r += nth) fn(r);
+    };
+    for (size_t w = 1; w < nth; ++w) pool.emplace_back(worker, w);
+    worker(0);
     for (std::thread& th : pool) th.join();
+  };
+  run([&](size_t r) { rs[r].n = jobs[rs[r].job].plan(rs[r].q0, rs[r].q1, nullptr); });
+  size_t total = 0;
+  for (Range& r : rs) {
+    r.off = total;
+    total += r.n;
   }
-  size_t total = out.size();
-  for (auto& pp : part) total += pp.size();
-  out.reserve(total);
-  for (auto& pp : part) out.insert(out.end(), pp.begin(), pp.end());
+  count = int64_t(total);
+  if (total == 0) return SPAND_OK;
+  const size_t bytes = total * sizeof(CopyDesc);
+  spand_status st = dalloc(h, out, bytes);
+  if (st != SPAND_OK) return st;
+  CopyDesc* hp = reinterpret_cast<CopyDesc*>(h->stage.get(bytes));
+  if (!hp) return set_err(h, SPAND_E_NOMEM, "pinned staging of " + std::to_string(bytes) + " bytes failed");
+  run([&](size_t r) { (void)jobs[rs[r].job].plan(rs[r].q0, rs[r].q1, hp + rs[r].off); });
+  HIPCHK(hipMemcpyAsync(out.p, hp, bytes, hipMemcpyHostToDevice, h->stream));
+  return SPAND_OK;
 }
 
 // Host-to-device copy of a descriptor list through pinned staging, with the pinned
@@ -1286,7 +1327,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
 
     // ---- sizes, slots, layout and assembly of every problem
     HIPCHK(hipEventRecord(ph[0], h->stream));
-    std::vector<CopyDesc> copies;
+    std::vector<MergeJob> merges;
     std::vector<ZeroDesc> zeros;  // the new step buffers of every problem, zeroed in one launch
     std::vector<Prob*> scatters;  // step 1: the CSR values go in after the fill
     auto add_zero = [&](double* p0, int64_t len) {
@@ -1336,7 +1377,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
         }
         scatters.push_back(pp);
       } else {
-        plan_merge(sy, hq->num[t - 2], lay, pb.lay_prev, E, A, pb.arena_prev.as<double>(), copies);
+        merges.push_back(MergeJob{&sy, &hq->num[t - 2], &pb.lay, &pb.lay_prev, E, A, pb.arena_prev.as<double>()});
       }
     }
     if (!zeros.empty()) {
@@ -1351,10 +1392,11 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
                             hq->num[0].elim.as<double>(), pp->flags + 2, h->stream);
       HIPCHK(hipGetLastError());
     }
-    if (!copies.empty()) {
+    if (!merges.empty()) {
       DevBuf d_copy;
-      if ((st = upload_big(h, d_copy, copies)) != SPAND_OK) return st;
-      launch_copy(d_copy.as<CopyDesc>(), int64_t(copies.size()), h->stream);
+      int64_t ncopy = 0;
+      if ((st = plan_merges(h, merges, d_copy, ncopy)) != SPAND_OK) return st;
+      launch_copy(d_copy.as<CopyDesc>(), ncopy, h->stream);
       HIPCHK(hipGetLastError());
     }
 
