@@ -284,52 +284,34 @@ struct LeftBlock {
   const double* L;
   const double* dinv;
   int32_t ldx, ldl, nrows, ncols;
-  int32_t key;  // blocks with one key share L (and dinv); keys are small and >= 0
 };
 
 spand_status left_trsm(spand_ctx* h, const std::vector<LeftBlock>& B) {
   const int32_t CHOL_GROUP = std::max(1, h->tune.chol_group);
   int32_t nmax = 0;
   for (const LeftBlock& b : B) nmax = std::max(nmax, b.nrows);
-  // the blocks that share a triangular factor (hence its diagonal-block inverses)
-  // fill the workgroups of the diagonal solves together, 256 columns each: the blocks
-  // in key order (a counting sort, stable)
-  int32_t kmax = -1;
-  for (const LeftBlock& b : B) kmax = std::max(kmax, b.key);
-  std::vector<int32_t> kstart(size_t(kmax) + 2, 0);
-  for (const LeftBlock& b : B) ++kstart[size_t(b.key) + 1];
-  for (size_t k = 1; k < kstart.size(); ++k) kstart[k] += kstart[k - 1];
-  std::vector<LeftBlock> Bs(B.size());
-  for (const LeftBlock& b : B) Bs[size_t(kstart[size_t(b.key)]++)] = b;
-  std::vector<LeftDesc> ld;
-  std::vector<LeftSeg> ls;
-  std::vector<int64_t> lcut;
-  ls.reserve(Bs.size() * size_t((nmax + CHOL_NB - 1) / CHOL_NB));
-  GemmSeq g(h->tune.gemm_scale);
+  // X[kb:kb+w, :] <- L_kk^{-1} X[kb:kb+w, :] is a product with the lower-triangular
+  // inverse, done in place by the batched GEMM: with w <= 64 rows one 64 x 64 output
+  // tile holds every row of its columns, so the workgroup that writes them has read
+  // them all (the 64-wide tile, whatever the tuned tile of the updates).  The
+  // products of an entry are added in k order, as the substitution adds them.
+  GemmSeq gd(0), g(h->tune.gemm_scale);
   for (int32_t kb = 0; kb < nmax; kb += CHOL_NB) {
     // grouped as in blocked_cholesky: inside a group only the next block row is
     // updated, at the group's end every row below, at depth CHOL_GROUP NB
     const int32_t kblk = kb / CHOL_NB;
     const bool pair = (kblk % CHOL_GROUP) == CHOL_GROUP - 1;
     const int32_t kg = (kblk / CHOL_GROUP) * CHOL_GROUP * CHOL_NB;
-    const double* cur = nullptr;  // Dinv of the open workgroup
-    int32_t fill = 0;             // its columns so far
-    for (const LeftBlock& b : Bs) {
+    for (const LeftBlock& b : B) {
       if (b.nrows <= kb) continue;
       const int32_t w = std::min(CHOL_NB, b.nrows - kb);
-      const double* Dk = b.dinv + int64_t(kb / CHOL_NB) * CHOL_NB * CHOL_NB;
-      for (int32_t c0 = 0; c0 < b.ncols;) {
-        if (Dk != cur || fill == 256) {
-          ld.push_back(LeftDesc{Dk, w, int32_t(ls.size()), 0, 0});
-          cur = Dk;
-          fill = 0;
-        }
-        const int32_t take = std::min(b.ncols - c0, 256 - fill);
-        ls.push_back(LeftSeg{b.X + kb + int64_t(c0) * b.ldx, b.ldx, take, fill, 0});
-        ++ld.back().nseg;
-        fill += take;
-        c0 += take;
-      }
+      GemmDesc s{};
+      s.A = b.dinv + int64_t(kb / CHOL_NB) * CHOL_NB * CHOL_NB; s.lda = w;
+      s.B = b.X + kb; s.ldb = b.ldx;
+      s.C = b.X + kb; s.ldc = b.ldx;
+      s.M = w; s.N = b.ncols; s.K = w;
+      s.flags = G_TRIA; s.alpha = 1.0; s.beta = 0.0;
+      gd.add(s, 0);
       const int32_t ks = kg, r0 = kb + w;
       const int32_t r1 = pair ? b.nrows : std::min(b.nrows, r0 + CHOL_NB);
       GemmDesc q{};
@@ -340,17 +322,14 @@ spand_status left_trsm(spand_ctx* h, const std::vector<LeftBlock>& B) {
       q.flags = 0; q.alpha = -1.0; q.beta = 1.0;
       g.add(q, 0);
     }
-    lcut.push_back(int64_t(ld.size()));
+    gd.end_launch(0);
     g.end_launch(0);
   }
-  DevBuf dl, dsg;
   spand_status st;
-  if ((st = upload(h, dl, ld)) != SPAND_OK) return st;
-  if ((st = upload(h, dsg, ls)) != SPAND_OK) return st;
+  if ((st = gd.upload_all(h)) != SPAND_OK) return st;
   if ((st = g.upload_all(h)) != SPAND_OK) return st;
-  for (size_t q = 0; q < lcut.size(); ++q) {
-    const int64_t b = q ? lcut[q - 1] : 0;
-    launch_left_trsm_diag(dl.as<LeftDesc>() + b, dsg.as<LeftSeg>(), int32_t(lcut[q] - b), h->stream);
+  for (size_t q = 0; q < g.cut.size(); ++q) {
+    gd.launch(h, q);
     g.launch(h, q);
   }
   HIPCHK(hipGetLastError());
@@ -1489,7 +1468,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
             if (pb.iso_off[s] < 0) continue;
             add_identity(ids, ISO + pb.iso_off[s], sn.size[s], pad16(sn.size[s]));
             lb.push_back(LeftBlock{ISO + pb.iso_off[s], E + lay.base[s], sn.edinv.as<double>() + pb.ed_off[s],
-                                   pad16(sn.size[s]), int32_t(lay.H[s]), sn.size[s], sn.size[s], int32_t(lb.size())});
+                                   pad16(sn.size[s]), int32_t(lay.H[s]), sn.size[s], sn.size[s]});
           }
         }
         if (!lb.empty()) {
@@ -1571,7 +1550,6 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
       std::vector<Front> fr;
       std::vector<LeftBlock> lb;
       std::vector<IdentDesc> ids, did;
-      int32_t kbase = 0;  // left-solve keys: kbase + cluster of the factor, per problem
       for (Prob* pp : act) {
         Prob& pb = *pp;
         spand_ctx* hq = pb.h;
@@ -1613,15 +1591,14 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
           if (sn.size[p] == 0) continue;
           add_identity(ids, SC + pb.sc_off[p], sn.size[p], pad16(sn.size[p]));
           lb.push_back(LeftBlock{SC + pb.sc_off[p], A + lay.base[p], SD + pb.sd_off[p], pad16(sn.size[p]), int32_t(lay.H[p]),
-                                 sn.size[p], sn.size[p], kbase + p});
+                                 sn.size[p], sn.size[p]});
           for (int64_t e = lay.pan_ptr[p] + 1; e < lay.pan_ptr[p + 1]; ++e) {
             const int32_t i = lay.prow[e];
             if (sn.size[i] == 0) continue;
             lb.push_back(LeftBlock{A + lay.base[p] + lay.proff[e], A + lay.base[i], SD + pb.sd_off[i],
-                                   int32_t(lay.H[p]), int32_t(lay.H[i]), sn.size[i], sn.size[p], kbase + i});
+                                   int32_t(lay.H[p]), int32_t(lay.H[i]), sn.size[i], sn.size[p]});
           }
         }
-        kbase += nc;
         for (int32_t p = ne; p < nc; ++p)
           if (sn.size[p] > 0) add_identity(did, A + lay.base[p], sn.size[p], int32_t(lay.H[p]));
       }

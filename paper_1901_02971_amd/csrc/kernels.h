@@ -23,19 +23,8 @@ struct PanelDesc {
   const double* Dinv;  // w x w
   int32_t ld, w, r0, r1;  // rows [r0, r1) are solved
 };
-// One workgroup of the left block solve: up to 256 columns, drawn from every block
-// that shares the diagonal block (hence Dinv), as the segments [seg0, seg0 + nseg).
-struct LeftDesc {
-  const double* Dinv;  // w x w
-  int32_t w, seg0, nseg, pad;
-};
-struct LeftSeg {  // columns 0..ncols of X (row kb of a block, ld ldx) at threads t0..t0+ncols
-  double* X;
-  int32_t ldx, ncols, t0, pad;
-};
 void launch_potrf_diag(const PotrfDesc* d, int32_t count, hipStream_t s);
 void launch_panel_trsm(const PanelDesc* d, int32_t count, hipStream_t s);
-void launch_left_trsm_diag(const LeftDesc* d, const LeftSeg* segs, int32_t count, hipStream_t s);
 
 // One product C = alpha * op(A) op(B) + beta * C on column-major operands.
 enum : int32_t {

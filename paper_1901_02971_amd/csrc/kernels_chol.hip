@@ -11,7 +11,7 @@
 // factor and G of the elimination; applied to an interface panel it leaves L_p on
 // top and the right-scaled blocks below.  The left scaling by L_i^{-1} of block
 // (i, p) is the same recurrence from the left:
-//     k_left_trsm_diag  X[kb:kb+w, :] <- L_kk^{-1} X[kb:kb+w, :]
+//     GEMM (in place, lower-triangular L_kk^{-1})  X[kb:kb+w, :] <- L_kk^{-1} X[kb:kb+w, :]
 //     GEMM              X[kb+w:, :] -= L[kb+w:, kb:kb+w] X[kb:kb+w, :]
 #include <hip/hip_runtime.h>
 
@@ -200,36 +200,6 @@ __global__ void __launch_bounds__(PW) k_panel_trsm(const PanelDesc* __restrict__
     }
 }
 
-// One column per thread (rows kb..kb+w): x <- L_kk^{-1} x; the workgroup's columns
-// come from the segments of its descriptor, which all share L_kk.
-__global__ void __launch_bounds__(PW) k_left_trsm_diag(const LeftDesc* __restrict__ descs,
-                                                       const LeftSeg* __restrict__ segs) {
-  const LeftDesc d = descs[blockIdx.x];
-  const int w = d.w;
-  __shared__ double Xi[CHOL_NB][CHOL_NB + 1];
-  stage_inverse(d.Dinv, w, Xi);
-  __syncthreads();
-  const int t = threadIdx.x;
-  int sg = d.seg0;
-  const int se = d.seg0 + d.nseg;
-  while (sg + 1 < se && segs[sg + 1].t0 <= t) ++sg;
-  const LeftSeg g = segs[sg];
-  const int c = t - g.t0;
-  if (c < 0 || c >= g.ncols) return;
-  double* col = g.X + (int64_t)c * g.ldx;
-  double x[CHOL_NB];  // x[k] for k >= w is read from row w - 1 and only enters outputs i >= w
-#pragma unroll
-  for (int k = 0; k < CHOL_NB; ++k) x[k] = gldc(col + (k < w ? k : w - 1));
-  // out[i] = sum_{k <= i} Xi[i][k] x[k]
-#pragma unroll
-  for (int i = 0; i < CHOL_NB; ++i) {
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k <= i; ++k) s = fma(Xi[i][k], x[k], s);
-    if (i < w) gstc(col + i, s);
-  }
-}
-
 void launch_potrf_diag(const PotrfDesc* d, int32_t count, hipStream_t s) {
   if (count == 0) return;
   hipLaunchKernelGGL(k_potrf_diag, dim3(count), dim3(PW), 0, s, d);
@@ -237,10 +207,6 @@ void launch_potrf_diag(const PotrfDesc* d, int32_t count, hipStream_t s) {
 void launch_panel_trsm(const PanelDesc* d, int32_t count, hipStream_t s) {
   if (count == 0) return;
   hipLaunchKernelGGL(k_panel_trsm, dim3(count), dim3(PW), 0, s, d);
-}
-void launch_left_trsm_diag(const LeftDesc* d, const LeftSeg* segs, int32_t count, hipStream_t s) {
-  if (count == 0) return;
-  hipLaunchKernelGGL(k_left_trsm_diag, dim3(count), dim3(PW), 0, s, d, segs);
 }
 
 }  // namespace spand
