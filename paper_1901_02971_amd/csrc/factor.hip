@@ -1621,7 +1621,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
     // lanes per column.  Interfaces of one slab go in one plain launch per team size;
     // interfaces of several slabs go in one cooperative launch per colour.
     size_t nlaunch = 0;
-    DevBuf curb, nrefb, errb, xchb;
+    DevBuf curb, nrefb, errb, xchb, doneb;
     int64_t ncl = 0;  // clusters of the sparsified problems in the run's size and rank arrays
     auto orth = [&](const Prob& pb) {
       const SymStep& sy = pb.h->an.steps[t - 1];
@@ -1717,11 +1717,71 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
           else if (pb.v_off[p] >= 0)
             ++pb.cpqr_big;
       }
+      // Householder steps of an interface, for the schedules: min(m, ncols) bounds the
+      // rank; a refactorization at the same tolerance takes the rank that the interface
+      // kept the last time, plus the step that stops
+      auto est_steps = [&](const Prob& pb, int32_t p) -> int64_t {
+        const spand_ctx* hq = pb.h;
+        const int64_t ub = std::min<int64_t>(hq->num[t - 1].size[p], pb.ncols[p]);
+        if (hq->last_rank_tol == tol && int64_t(hq->last_rank.size()) >= t) {
+          const std::vector<int32_t>& lr = hq->last_rank[t - 1];
+          if (p < int32_t(lr.size()) && lr[p] >= 0) return std::min<int64_t>(ub, int64_t(lr[p]) + 1);
+        }
+        return ub;
+      };
+      // A step whose work lies mostly in multi-slab interfaces runs all its colour
+      // classes in one cooperative launch, where an interface waits on the device for
+      // its neighbours of earlier classes only, not for the whole previous class.  Its
+      // single-slab interfaces then run in that launch as teams of one slab (an
+      // exchange with itself at every step).  A step with an interface beyond the
+      // register layouts keeps the launches per class.
+      bool unified = false;
+      {
+        int64_t w1 = 0, wm = 0;
+        bool anybig = false;
+        for (Prob* pp : act) {
+          if (!orth(*pp)) continue;
+          const SymStep& sy = pp->h->an.steps[t - 1];
+          for (int32_t p = sy.ne; p < sy.nc; ++p) {
+            if (pp->v_off[p] < 0) continue;
+            if (pp->big[p]) {
+              anybig = true;
+              continue;
+            }
+            const int64_t e = est_steps(*pp, p);
+            if (pp->slabS[p] > 1)
+              wm += e * pp->slabS[p];
+            else
+              w1 += e;
+          }
+        }
+        unified = !anybig && wm > 0 && 10 * w1 <= wm;
+      }
+      if (unified)
+        for (Prob* pp : act) {
+          if (!orth(*pp)) continue;
+          Prob& pb = *pp;
+          const SymStep& sy = pb.h->an.steps[t - 1];
+          for (int32_t p = sy.ne; p < sy.nc; ++p) {
+            if (pb.v_off[p] < 0 || pb.slabS[p] > 1) continue;
+            if (pb.wide[p]) {  // the standard layout of teams of 2 instead
+              --pb.cpqr_ifaces[1];
+              pb.wide[p] = 0;
+              pb.slabS[p] = int32_t((pb.ncols[p] + cpqr_capacity(2) - 1) / cpqr_capacity(2));
+              ++pb.cpqr_ifaces[pb.slabS[p] > 1 ? 2 : 0];
+            }
+            pb.xch_off[p] = xch_total;
+            xch_total += 3 * int64_t(pb.slabS[p]) * cpqr_record(pb.tg[p], pb.rlay[p]);
+          }
+        }
       if ((st = dalloc(h, xchb, size_t(xch_total) * sizeof(double))) != SPAND_OK) return st;
       // the exchange headers start with tag 0; the first exchange of a buffer uses tag 1
       if (xch_total > 0) HIPCHK(hipMemsetAsync(xchb.p, 0, size_t(xch_total) * sizeof(double), h->stream));
       if ((st = dalloc(h, errb, sizeof(int32_t))) != SPAND_OK) return st;
       HIPCHK(hipMemsetAsync(errb.p, 0, sizeof(int32_t), h->stream));
+      // finished slabs of every interface (the multi-slab kernel counts them)
+      if ((st = dalloc(h, doneb, size_t(std::max<int64_t>(ncl, 1)) * sizeof(int32_t))) != SPAND_OK) return st;
+      HIPCHK(hipMemsetAsync(doneb.p, 0, size_t(std::max<int64_t>(ncl, 1)) * sizeof(int32_t), h->stream));
       // current sizes: interfaces shrink to their rank as their colour class finishes
       if ((st = upload(h, curb, cur_h)) != SPAND_OK) return st;
       if ((st = upload(h, nrefb, std::vector<int32_t>(size_t(ncl), 0))) != SPAND_OK) return st;
@@ -1768,7 +1828,133 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
       // launch groups of one colour: single-slab interfaces per team size G
       // (group G), the wide single-slab ones (group 128), then every multi-slab
       // interface of the colour together (group 256)
-      for (int32_t c = 0; c < ncolour; ++c) {
+      if (unified) {
+        // every interface, class by class, each class longest first: the order of the
+        // workgroups' lists, in which the neighbours an interface waits for come first
+        std::vector<Ref> plist;
+        for (int32_t c = 0; c < ncolour; ++c) {
+          std::vector<Ref> cl = by_colour[c];
+          std::stable_sort(cl.begin(), cl.end(), [&](const Ref& x, const Ref& y) {
+            const int64_t ex = est_steps(*x.pb, x.p), ey = est_steps(*y.pb, y.p);
+            return ex != ey ? ex > ey : x.pb->h->num[t - 1].size[x.p] > y.pb->h->num[t - 1].size[y.p];
+          });
+          plist.insert(plist.end(), cl.begin(), cl.end());
+        }
+        size_t lds = 0, total = 0;
+        for (const Ref& f : plist) {
+          lds = std::max(lds, cpqr_lds_bytes(f.pb->tg[f.p], f.pb->rlay[f.p], f.pb->nseg[f.p]));
+          total += size_t(f.pb->slabS[f.p]);
+        }
+        const int cap = cpqr_max_coresident(lds);
+        if (cap <= 0) return set_err(h, SPAND_E_HIP, "occupancy query for the CPQR kernel failed");
+        std::vector<SparsDesc> sds;
+        std::vector<SegDesc> segs;
+        std::vector<int2> deps;
+        // List scheduling over the co-resident workgroups as for one class, with an
+        // interface's start no earlier than the estimated end of the neighbours it
+        // waits for
+        const size_t grid = std::min(total, size_t(cap));
+        std::vector<std::vector<SlabRef>> lists(grid);
+        using Slot = std::pair<int64_t, int32_t>;  // (time the workgroup frees up, workgroup)
+        std::vector<Slot> heap(grid);
+        for (size_t b = 0; b < grid; ++b) heap[b] = Slot{0, int32_t(b)};
+        std::make_heap(heap.begin(), heap.end(), std::greater<Slot>());
+        std::vector<int64_t> fin(size_t(ncl), 0);  // estimated end of every interface
+        std::vector<int32_t> wg;
+        for (const Ref& f : plist) {
+          Prob& pb = *f.pb;
+          const int32_t p = f.p;
+          const StepNum& sn = pb.h->num[t - 1];
+          const SymStep& sy = pb.h->an.steps[t - 1];
+          const Layout& lay = pb.lay;
+          double* A = pb.arena.as<double>();
+          const int32_t S = pb.slabS[p];
+          if (S > cap) return set_err(h, SPAND_E_INVALID, "interface needs more co-resident workgroups than the GPU holds");
+          SparsDesc d{};
+          d.V = sn.house.as<double>() + pb.v_off[p];
+          d.ldv = pad16(sn.size[p]);
+          d.tau = sn.house.as<double>() + pb.tau_off[p];
+          d.diag = A + lay.base[p];
+          d.ldd = int32_t(lay.H[p]);
+          d.m = sn.size[p];
+          d.id = int32_t(pb.cbase + p);
+          d.S = S;
+          d.G = pb.tg[p];
+          d.lay = pb.rlay[p];
+          d.xch = xchb.as<double>() + pb.xch_off[p];
+          d.seg_begin = int32_t(segs.size());
+          d.dep_begin = int32_t(deps.size());
+          int64_t ready = 0;
+          for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e) {
+            const int32_t q = sy.nb[e];
+            if (sn.size[q] == 0) continue;
+            SegDesc g{};
+            if (q < p) {  // block (p, q) in panel q
+              g.blk = A + lay.base[q] + lay.find(p, q);
+              g.ld = int32_t(lay.H[q]);
+              g.trans = 0;
+            } else {      // block (q, p) in panel p holds A_pq^T
+              g.blk = A + lay.base[p] + lay.find(q, p);
+              g.ld = int32_t(lay.H[p]);
+              g.trans = 1;
+            }
+            g.q = int32_t(pb.cbase + q);
+            segs.push_back(g);
+            if (pb.v_off[q] >= 0 && sy.colour[q] < sy.colour[p]) {
+              deps.push_back(make_int2(int32_t(pb.cbase + q), pb.slabS[q]));
+              ready = std::max(ready, fin[size_t(pb.cbase + q)]);
+            }
+          }
+          d.seg_end = int32_t(segs.size());
+          d.dep_end = int32_t(deps.size());
+          wg.clear();
+          int64_t tt = ready;
+          for (int32_t k = 0; k < S; ++k) {
+            std::pop_heap(heap.begin(), heap.end(), std::greater<Slot>());
+            tt = std::max(tt, heap.back().first);
+            wg.push_back(heap.back().second);
+            heap.pop_back();
+          }
+          tt += est_steps(pb, p);
+          fin[size_t(pb.cbase + p)] = tt;
+          for (int32_t k = 0; k < S; ++k) {
+            lists[size_t(wg[k])].push_back(SlabRef{int32_t(sds.size()), k});
+            heap.push_back(Slot{tt, wg[k]});
+            std::push_heap(heap.begin(), heap.end(), std::greater<Slot>());
+          }
+          sds.push_back(d);
+        }
+        size_t nround = 0;
+        for (const auto& l : lists) nround = std::max(nround, l.size());
+        std::vector<SlabRef> slabs;
+        slabs.reserve(nround * grid);
+        for (size_t k = 0; k < nround; ++k)
+          for (size_t b = 0; b < grid; ++b) slabs.push_back(k < lists[b].size() ? lists[b][k] : SlabRef{-1, 0});
+        DevBuf a, b, sl, dp;
+        if ((st = upload_big(h, a, sds)) != SPAND_OK) return st;
+        if ((st = upload_big(h, b, segs)) != SPAND_OK) return st;
+        if ((st = upload_big(h, sl, slabs)) != SPAND_OK) return st;
+        if (deps.empty()) deps.push_back(make_int2(0, 0));
+        if ((st = upload_big(h, dp, deps)) != SPAND_OK) return st;
+        hipEvent_t cstart, e1;
+        HIPCHK(joinev.get(njoin, &cstart));
+        HIPCHK(hipEventRecord(cstart, h->stream));
+        colour_span.push_back(ColourSpan{njoin++, nlaunch, nlaunch + 1});
+        HIPCHK(evpool.get(2 * nlaunch, &e1));  // the start event of the launch is not read
+        HIPCHK(evpool.get(2 * nlaunch + 1, &e1));
+        const hipError_t le =
+            launch_cpqr_multi(a.as<SparsDesc>(), sl.as<SlabRef>(), int32_t(grid), int32_t(nround), b.as<SegDesc>(),
+                              tol, curb.as<int32_t>(), nrefb.as<int32_t>(), errb.as<int32_t>(), dp.as<int2>(),
+                              doneb.as<int32_t>(), lds, h->stream);
+        if (le != hipSuccess) return set_err(h, SPAND_E_HIP, std::string("sparsification launch: ") + hipGetErrorString(le));
+        HIPCHK(hipEventRecord(e1, h->stream));
+        ++nlaunch;
+        colour_bufs.push_back(std::move(a));
+        colour_bufs.push_back(std::move(b));
+        colour_bufs.push_back(std::move(sl));
+        colour_bufs.push_back(std::move(dp));
+      }
+      for (int32_t c = 0; c < ncolour && !unified; ++c) {
         if (by_colour[c].empty()) continue;
         std::vector<CpqrLaunch> launches;
         std::vector<SparsDesc> all_sds;
@@ -1787,18 +1973,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
           }
           if (plist.empty()) continue;
           auto msize = [&](const Ref& f) { return f.pb->h->num[t - 1].size[f.p]; };
-          // Householder steps of an interface, for the schedule: min(m, ncols) bounds
-          // the rank; a refactorization at the same tolerance takes the rank that the
-          // interface kept the last time, plus the step that stops
-          auto steps_est = [&](const Ref& f) -> int64_t {
-            const spand_ctx* hq = f.pb->h;
-            const int64_t ub = std::min<int64_t>(msize(f), f.pb->ncols[f.p]);
-            if (hq->last_rank_tol == tol && int64_t(hq->last_rank.size()) >= t) {
-              const std::vector<int32_t>& lr = hq->last_rank[t - 1];
-              if (f.p < int32_t(lr.size()) && lr[f.p] >= 0) return std::min<int64_t>(ub, int64_t(lr[f.p]) + 1);
-            }
-            return ub;
-          };
+          auto steps_est = [&](const Ref& f) { return est_steps(*f.pb, f.p); };
           // longest first: interfaces of similar step counts share a launch
           std::stable_sort(plist.begin(), plist.end(), [&](const Ref& x, const Ref& y) {
             if (multi) {
@@ -2019,7 +2194,8 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
                                  bbar.as<uint32_t>(), sq);
           } else if (Lc.multi) {
             le = launch_cpqr_multi(dd, ss, Lc.nslab, Lc.nround, b.as<SegDesc>(), tol, curb.as<int32_t>(),
-                                   nrefb.as<int32_t>(), errb.as<int32_t>(), Lc.lds, sq);
+                                   nrefb.as<int32_t>(), errb.as<int32_t>(), nullptr, doneb.as<int32_t>(), Lc.lds,
+                                   sq);
           } else if (Lc.G == 128) {
             le = launch_cpqr_one_wide(dd, ss, Lc.nslab, b.as<SegDesc>(), tol, curb.as<int32_t>(), nrefb.as<int32_t>(),
                                       errb.as<int32_t>(), Lc.lds, sq);

@@ -105,7 +105,8 @@ struct SparsDesc {
   int32_t* piv;    // when not null: piv[j] = column (index in A_pn) chosen at step j < r
   int32_t m, ldd, seg_begin, seg_end, id, S, G, lay;  // G: lanes per column (team size);
                                                       // lay: register layout (multi-slab kernel)
-  int32_t ldv, pad;                                   // leading dimension of V (>= m)
+  int32_t ldv;                                        // leading dimension of V (>= m)
+  int32_t dep_begin, dep_end, pad;                    // multi-slab launch: neighbours to wait for
 };
 struct SegDesc {
   double* blk;  // block holding A_pq: trans=0 -> A_pq[r][c] = blk[r + c*ld]; trans=1 -> blk[c + r*ld]
@@ -163,9 +164,12 @@ hipError_t launch_cpqr_one(int32_t G, const SparsDesc* d, const SlabRef* slabs, 
                            double eps, int32_t* cursize, int32_t* nref, int32_t* err, size_t lds_bytes, hipStream_t s);
 // The multi-slab launch gives workgroup b the places slabs[k * nslab + b], k < nround,
 // in turn; the interfaces must appear in one order in every workgroup's places.
+// Interface d waits until done[deps[e].x] >= deps[e].y for e in [dep_begin, dep_end)
+// (neighbours earlier in that order); every slab adds 1 to done[id] when it ends.
+// done starts at zero.
 hipError_t launch_cpqr_multi(const SparsDesc* d, const SlabRef* slabs, int32_t nslab, int32_t nround,
                              const SegDesc* seg, double eps, int32_t* cursize, int32_t* nref, int32_t* err,
-                             size_t lds_bytes, hipStream_t s);
+                             const int2* deps, int32_t* done, size_t lds_bytes, hipStream_t s);
 // Interfaces beyond the register layouts (kernels_cpqr.hip k_cpqr_big): one
 // cooperative launch of nb workgroups per interface, A_pn in a global work copy.
 // Rows at most cpqr_big_max_rows(); the scratch holds wk (m * ncols doubles), nrm

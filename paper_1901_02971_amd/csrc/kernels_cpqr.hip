@@ -243,7 +243,7 @@ __device__ __forceinline__ void cpqr_update_group(double (&a)[CPL][MR], int gi, 
 // of CPL columns.
 template <int G, bool MULTI, int MR = CQ_MR, int CPL = CQ_CPL>
 __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const SegDesc* __restrict__ segs, double eps,
-                                          int32_t* cursize, int32_t* nref, int32_t* err) {
+                                          int32_t* cursize, int32_t* nref, int32_t* err, int32_t* done = nullptr) {
   constexpr int NT = CQ_NT;
   constexpr int NTEAM = NT / G;
   constexpr int CAP = CPL * NTEAM;
@@ -282,7 +282,10 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
     int off = 0;
     for (int s = 0; s < nseg; ++s) {
       segoff[s] = off;
-      off += cursize[sg[s].q];
+      // a neighbour sparsified earlier in the same launch published its rank with a
+      // device-scope store
+      off += MULTI ? __hip_atomic_load(cursize + sg[s].q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                   : cursize[sg[s].q];
     }
     segoff[nseg] = off;
   }
@@ -290,6 +293,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
   const int nc = segoff[nseg];
   if (nc == 0) {  // no coupled dofs left: p keeps its size, no reflectors
     if (w == 0 && tid == 0) nref[d.id] = 0;
+    if (MULTI && tid == 0 && done) __hip_atomic_fetch_add(done + d.id, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return;
   }
 
@@ -315,7 +319,10 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
 #pragma unroll
     for (int q = 0; q < MR; ++q) {
       const int i = q * G + g;
-      a[k][q] = base[(i < rows ? i : 0) * (int)stride];
+      // device-scope loads in the multi-slab kernel: a neighbour sparsified earlier
+      // in the same launch wrote these blocks (from another XCD, perhaps)
+      const gdouble* e = base + (i < rows ? i : 0) * (int)stride;
+      a[k][q] = MULTI ? __hip_atomic_load(e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *e;
     }
     // keep the loads ahead of their uses: scheduled among them the loads would
     // be issued one at a time
@@ -726,7 +733,13 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
 #pragma unroll
     for (int q = 0; q < MR; ++q) {
       const int i = q * G + g;
-      if (i < r) base[(int64_t)i * stride] = (ps >= 0 && i >= ps) ? ((i == ps) ? rss : 0.0) : a[k][q];
+      if (i < r) {
+        const double v = (ps >= 0 && i >= ps) ? ((i == ps) ? rss : 0.0) : a[k][q];
+        if constexpr (MULTI)
+          shared_store(base + (int64_t)i * stride, v);  // read by later neighbours of the launch
+        else
+          base[(int64_t)i * stride] = v;
+      }
     }
   }
   if (w == 0) {
@@ -735,9 +748,19 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
       d.diag[x + (int64_t)y * d.ldd] = (x == y) ? 1.0 : 0.0;
     }
     if (tid == 0) {
-      cursize[d.id] = r;
+      if constexpr (MULTI)
+        __hip_atomic_store(cursize + d.id, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      else
+        cursize[d.id] = r;
       nref[d.id] = r;
     }
+  }
+  if constexpr (MULTI) {
+    // this slab is done once its stores have completed: the neighbours that wait for
+    // p count the slabs of p (k_cpqr_multi)
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0 && done) __hip_atomic_fetch_add(done + d.id, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -766,20 +789,47 @@ __global__ void __launch_bounds__(CQ_NT) k_cpqr_one_w2(const SparsDesc* __restri
 // workgroup takes the code path of its interface's G.  Workgroup b runs the slabs
 // slabs[k * gridDim.x + b], k = 0 .. nround - 1, in turn (a negative descriptor
 // index is an unused place).  The host numbers the interfaces and every workgroup's
-// slabs come in that order, so the lowest-numbered unfinished interface has each of
-// its slabs at the head of its workgroup's remaining list (all workgroups are
-// resident): it completes, and by induction every later one.
+// slabs come in that order.  An interface may depend on neighbours numbered before
+// it (a launch that holds several colour classes): deps[dep_begin, dep_end) lists
+// (neighbour id, its slab count), and its slabs wait until done[neighbour] has
+// counted every slab of the neighbour; the neighbour's blocks, rank and current
+// size are then read with device-scope loads.  The lowest-numbered unfinished
+// interface therefore has every neighbour it waits for finished and each of its
+// slabs at the head of its workgroup's remaining list (all workgroups are
+// resident): it completes, and by induction every later one.  The waits are
+// bounded like the exchange polls.
 __global__ void __launch_bounds__(CQ_NT) k_cpqr_multi(const SparsDesc* __restrict__ descs,
                                                       const SlabRef* __restrict__ slabs, int32_t nround,
                                                       const SegDesc* __restrict__ segs, double eps,
-                                                      int32_t* cursize, int32_t* nref, int32_t* err) {
+                                                      int32_t* cursize, int32_t* nref, int32_t* err,
+                                                      const int2* __restrict__ deps, int32_t* done) {
   for (int32_t rd = 0; rd < nround; ++rd) {
     const SlabRef sr = slabs[(size_t)rd * gridDim.x + blockIdx.x];
     if (sr.desc < 0) continue;
     const SparsDesc d = descs[sr.desc];
+    if (d.dep_end > d.dep_begin) {
+      if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        for (long spins = 0;; ++spins) {
+          int ok = 1;
+          for (int e = d.dep_begin + lane; e < d.dep_end; e += 64) {
+            const int2 q = deps[e];
+            ok &= __hip_atomic_load(done + q.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= q.y;
+          }
+          if (__all(ok)) break;
+          if (spins > SPIN_LIMIT) {
+            if (lane == 0) atomicOr(err, 4);
+            break;
+          }
+          if ((spins & 1023) == 1023 && timed_out(err)) break;
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
+      __syncthreads();
+    }
 #define CQ_CASE(GG)                                                                   \
-  case GG: cpqr_slab<GG, true>(d, sr.w, segs, eps, cursize, nref, err); break;       \
-  case GG | 256: cpqr_slab<GG, true, CQ_MR_1, CQ_CPL_1>(d, sr.w, segs, eps, cursize, nref, err); break;
+  case GG: cpqr_slab<GG, true>(d, sr.w, segs, eps, cursize, nref, err, done); break; \
+  case GG | 256: cpqr_slab<GG, true, CQ_MR_1, CQ_CPL_1>(d, sr.w, segs, eps, cursize, nref, err, done); break;
     switch (d.G | (d.lay << 8)) {
       CQ_CASE(1)
       CQ_CASE(2)
@@ -1188,10 +1238,10 @@ hipError_t launch_cpqr_one(int32_t G, const SparsDesc* d, const SlabRef* slabs, 
 
 hipError_t launch_cpqr_multi(const SparsDesc* d, const SlabRef* slabs, int32_t nslab, int32_t nround,
                              const SegDesc* seg, double eps, int32_t* cursize, int32_t* nref, int32_t* err,
-                             size_t lds, hipStream_t s) {
+                             const int2* deps, int32_t* done, size_t lds, hipStream_t s) {
   if (nslab == 0 || nround == 0) return hipSuccess;
-  void* args[] = {(void*)&d,   (void*)&slabs,   (void*)&nround, (void*)&seg,
-                  (void*)&eps, (void*)&cursize, (void*)&nref,   (void*)&err};
+  void* args[] = {(void*)&d,   (void*)&slabs,   (void*)&nround, (void*)&seg,  (void*)&eps,
+                  (void*)&cursize, (void*)&nref, (void*)&err,   (void*)&deps, (void*)&done};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_cpqr_multi), dim3(nslab), dim3(CQ_NT), args,
                                     (unsigned int)lds, s);
 }
