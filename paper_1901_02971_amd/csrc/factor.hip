@@ -1829,17 +1829,31 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
       // (group G), the wide single-slab ones (group 128), then every multi-slab
       // interface of the colour together (group 256)
       if (unified) {
-        // every interface, class by class, each class longest first: the order of the
-        // workgroups' lists, in which the neighbours an interface waits for come first
+        // Every interface by its estimated path to the end of the step: its own steps
+        // plus the longest such path among the neighbours of later classes that wait for
+        // it.  A neighbour an interface waits for has a longer path, so this order
+        // (that of the workgroups' lists) puts it first; the longest chains start first.
+        std::vector<int64_t> bl(size_t(ncl), 0);
+        for (int32_t c = ncolour - 1; c >= 0; --c)
+          for (const Ref& f : by_colour[c]) {
+            const Prob& pb = *f.pb;
+            const SymStep& sy = pb.h->an.steps[t - 1];
+            int64_t below = 0;
+            for (int64_t e = sy.nb_ptr[f.p]; e < sy.nb_ptr[f.p + 1]; ++e) {
+              const int32_t q = sy.nb[e];
+              if (pb.v_off[q] >= 0 && sy.colour[q] > c) below = std::max(below, bl[size_t(pb.cbase + q)]);
+            }
+            bl[size_t(pb.cbase + f.p)] = est_steps(pb, f.p) + below;
+          }
         std::vector<Ref> plist;
-        for (int32_t c = 0; c < ncolour; ++c) {
-          std::vector<Ref> cl = by_colour[c];
-          std::stable_sort(cl.begin(), cl.end(), [&](const Ref& x, const Ref& y) {
-            const int64_t ex = est_steps(*x.pb, x.p), ey = est_steps(*y.pb, y.p);
-            return ex != ey ? ex > ey : x.pb->h->num[t - 1].size[x.p] > y.pb->h->num[t - 1].size[y.p];
-          });
-          plist.insert(plist.end(), cl.begin(), cl.end());
-        }
+        for (int32_t c = 0; c < ncolour; ++c) plist.insert(plist.end(), by_colour[c].begin(), by_colour[c].end());
+        auto colour_of = [&](const Ref& f) { return f.pb->h->an.steps[t - 1].colour[f.p]; };
+        std::stable_sort(plist.begin(), plist.end(), [&](const Ref& x, const Ref& y) {
+          const int64_t bx = bl[size_t(x.pb->cbase + x.p)], by = bl[size_t(y.pb->cbase + y.p)];
+          if (bx != by) return bx > by;
+          if (colour_of(x) != colour_of(y)) return colour_of(x) < colour_of(y);
+          return x.pb->h->num[t - 1].size[x.p] > y.pb->h->num[t - 1].size[y.p];
+        });
         size_t lds = 0, total = 0;
         for (const Ref& f : plist) {
           lds = std::max(lds, cpqr_lds_bytes(f.pb->tg[f.p], f.pb->rlay[f.p], f.pb->nseg[f.p]));
