@@ -75,7 +75,9 @@ typedef struct {
   int32_t fail_cluster;  /* ... cluster id within that step */
   int32_t fail_phase;    /* ... 0 = elimination, 1 = scaling, 2 = interpolative sparsification
                             (the Cholesky of C_ff, Sec. 2.6.2) */
-  int32_t reserved;
+  int32_t cpqr_one_launch_steps; /* steps of the last factor whose CPQRs (Sec. 2.6.1) ran in
+                                    one launch, each interface waiting for its neighbours of
+                                    earlier colour classes only */
   /* Per-step profile of the last factor (the paper's time/memory per level,
    * Sec. 4.4): device seconds (HIP events) of each phase of step t (t = 1..32):
    * [t-1][0] assembly/merge, [1] elimination, [2] scaling, [3] sparsification;

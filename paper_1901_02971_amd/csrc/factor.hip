@@ -579,6 +579,7 @@ struct Prob {
   std::vector<int32_t> nN, nref, slabS, tg, nseg, rlay;
   std::vector<char> wide, big;
   int64_t cpqr_big = 0;         // interfaces of the global-memory CPQR kernel
+  int32_t cpqr_one_launch = 0;  // steps whose CPQRs ran in one launch
   DevBuf cbuf;
 };
 
@@ -1761,6 +1762,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
         for (Prob* pp : act) {
           if (!orth(*pp)) continue;
           Prob& pb = *pp;
+          ++pb.cpqr_one_launch;
           const SymStep& sy = pb.h->an.steps[t - 1];
           for (int32_t p = sy.ne; p < sy.nc; ++p) {
             if (pb.v_off[p] < 0 || pb.slabS[p] > 1) continue;
@@ -2448,6 +2450,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
     s.cpqr_launches = cpqr_launches;
     for (int q = 0; q < 4; ++q) s.cpqr_interfaces[q] = pb.cpqr_ifaces[q];
     s.cpqr_big_interfaces = pb.cpqr_big;
+    s.cpqr_one_launch_steps = pb.cpqr_one_launch;
     s.apply_scratch_per_rhs = std::max<int64_t>(pb.h->max_tmp, 1) + std::max<int64_t>(pb.h->max_gather, 1) +
                               (pb.h->d_inv.p ? pb.h->an.n : 0);
     for (int q = 0; q < 3; ++q) s.apply_interfaces[q] = 0;

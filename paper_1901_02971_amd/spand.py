@@ -48,7 +48,7 @@ class Stats(C.Structure):
                 ("n", C.c_int64), ("levels", C.c_int32), ("n_steps", C.c_int32), ("last_iters", C.c_int32),
                 ("s_top", C.c_int32), ("m_F", C.c_int64), ("schur_flops", C.c_double),
                 ("schur_seconds", C.c_double), ("fail_step", C.c_int32), ("fail_cluster", C.c_int32),
-                ("fail_phase", C.c_int32), ("reserved", C.c_int32),
+                ("fail_phase", C.c_int32), ("cpqr_one_launch_steps", C.c_int32),
                 ("step_phase_seconds", (C.c_double * 4) * 32), ("step_m_F", C.c_int64 * 32),
                 ("cpqr_flops", C.c_double), ("cpqr_seconds", C.c_double), ("cpqr_launches", C.c_int64),
                 ("apply_bytes", C.c_double), ("apply_seconds", C.c_double), ("apply_calls", C.c_int64),
@@ -58,7 +58,7 @@ class Stats(C.Structure):
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_
-             if k not in ("reserved", "reserved2", "step_phase_seconds", "step_m_F", "cpqr_interfaces",
+             if k not in ("reserved2", "step_phase_seconds", "step_m_F", "cpqr_interfaces",
                           "apply_interfaces")}
         d["cpqr_interfaces"] = [int(v) for v in self.cpqr_interfaces]
         d["apply_interfaces"] = [int(v) for v in self.apply_interfaces]

@@ -164,6 +164,32 @@ def test_refactor_schedule_is_bit_identical():
     s.close()
 
 
+@pytest.mark.parametrize("shape,levels", [((24, 24, 24), 5), ((32, 32, 32), 9)])
+def test_one_launch_cpqr_steps_match_oracle(shape, levels):
+    """Steps whose CPQR work lies mostly in multi-slab interfaces run all colour classes
+    in one cooperative launch, each interface waiting on device counters for its
+    neighbours of earlier classes (and reading their write-back and ranks with
+    device-scope loads).  At least one step takes that path here; ranks per cluster and
+    step equal the oracle's and the apply, which reads every reflector, T factor and W
+    block these launches wrote, equals the oracle's within 1e-10.  A refactorization
+    estimates the interfaces' steps from the previous ranks, which may move a step to or
+    from that path; the factors come out the same bits either way."""
+    p = gridgen.laplacian(shape)
+    b = gridgen.rhs(np.random.default_rng(17), p.n, 3)
+    an, fac = oracle_run(p, levels, 1e-2)
+    s = gpu_factor(p, levels, 1e-2)
+    st = s.stats()
+    assert st["cpqr_one_launch_steps"] > 0, st
+    assert rank_mismatches(s, an, fac) == 0
+    z = gpu_apply(s, b)
+    zr = O.apply(fac, b)
+    assert np.abs(z - zr).max() <= 1e-10 * np.abs(zr).max()
+    assert (st["s_top"], st["m_F"]) == (fac.stats["s_top"], fac.stats["m_F"])
+    s.factor(torch.from_numpy(p.values).to("cuda:0"), 1e-2)
+    assert np.array_equal(gpu_apply(s, b), z)
+    s.close()
+
+
 def test_refactor_same_handle():
     """A handle is refactored with new values and a new tolerance."""
     import torch as T
