@@ -75,6 +75,32 @@ spand_status upload(spand_ctx* h, DevBuf& b, const std::vector<T>& v) {
   return stage_copy(h, b.p, v.data(), v.size() * sizeof(T));
 }
 
+// Host-to-device copy of a descriptor list through pinned staging, with the pinned
+// copy done by several threads when the list is large.
+template <typename T>
+spand_status upload_big(spand_ctx* h, DevBuf& b, const std::vector<T>& v) {
+  const size_t bytes = v.size() * sizeof(T);
+  spand_status st = dalloc(h, b, bytes);
+  if (st != SPAND_OK || bytes == 0) return st;
+  char* hp = h->stage.get(bytes);
+  if (!hp) return set_err(h, SPAND_E_NOMEM, "pinned staging of " + std::to_string(bytes) + " bytes failed");
+  const size_t nth = std::min<size_t>(8, std::max<size_t>(1, bytes >> 22));
+  if (nth == 1) {
+    std::memcpy(hp, v.data(), bytes);
+  } else {
+    std::vector<std::thread> pool;
+    auto put = [&](size_t k) {
+      const size_t a = v.size() * k / nth, e = v.size() * (k + 1) / nth;
+      std::memcpy(hp + a * sizeof(T), v.data() + a, (e - a) * sizeof(T));
+    };
+    for (size_t k = 1; k < nth; ++k) pool.emplace_back(put, k);
+    put(0);
+    for (std::thread& th : pool) th.join();
+  }
+  HIPCHK(hipMemcpyAsync(b.p, hp, bytes, hipMemcpyHostToDevice, h->stream));
+  return SPAND_OK;
+}
+
 // Column-panel layout of one step.  Panels of eliminated clusters (j < ne) are
 // placed in the persistent elimination buffer, the others in the step arena.
 struct Layout {
@@ -139,32 +165,39 @@ void build_layout(const SymStep& st, const std::vector<int32_t>& size, Layout& L
 // The products of a launch are numbered at end_launch, once its arithmetic (and so
 // its output tile: the sequence's variant, or 64 for BF16x3) is known.
 struct GemmSeq {
-  explicit GemmSeq(int variant_ = 0) : variant(variant_) {}
-  int variant;
-  std::vector<GemmDesc> d, cur;
+  explicit GemmSeq(int variant_ = 0) : variant(variant_), ts0(gemm_variant_tile(variant_)) {}
+  int variant, ts0;
+  std::vector<GemmDesc> d;
   std::vector<int64_t> cut;  // tile range end of every launch
   std::vector<int> prec;
   int64_t ntiles = 0;
+  size_t open = 0;  // first product of the launch being filled
   DevBuf dd, dmap;
+  // Products go straight into the list with their first tile number for the tuned
+  // tile; a launch of BF16x3 products (64-wide tiles only) renumbers its own.
   void add(GemmDesc g, int part) {
     if (g.M <= 0 || g.N <= 0 || g.K <= 0) return;
     g.part = part;
-    cur.push_back(g);
+    g.ts = ts0;
+    g.t0 = ntiles;
+    ntiles += gemm_tiles(g.M, g.N, part, ts0);
+    d.push_back(g);
   }
   void end_launch(int p) {
-    const int ts = p == 2 ? 64 : gemm_variant_tile(variant);
-    for (GemmDesc& g : cur) {
-      g.ts = ts;
-      g.t0 = ntiles;
-      ntiles += gemm_tiles(g.M, g.N, g.part, ts);
-      d.push_back(g);
+    if (p == 2 && ts0 != 64) {
+      ntiles = cut.empty() ? 0 : cut.back();
+      for (size_t k = open; k < d.size(); ++k) {
+        d[k].ts = 64;
+        d[k].t0 = ntiles;
+        ntiles += gemm_tiles(d[k].M, d[k].N, d[k].part, 64);
+      }
     }
-    cur.clear();
+    open = d.size();
     cut.push_back(ntiles);
     prec.push_back(p);
   }
   spand_status upload_all(spand_ctx* h) {
-    spand_status st = upload(h, dd, d);
+    spand_status st = upload_big(h, dd, d);
     if (st != SPAND_OK) return st;
     if ((st = dalloc(h, dmap, size_t(ntiles) * sizeof(int32_t))) != SPAND_OK) return st;
     launch_expand_tiles(dd.as<GemmDesc>(), int32_t(d.size()), dmap.as<int32_t>(), h->stream);
@@ -296,6 +329,10 @@ spand_status left_trsm(spand_ctx* h, const std::vector<LeftBlock>& B) {
   // them all (the 64-wide tile, whatever the tuned tile of the updates).  The
   // products of an entry are added in k order, as the substitution adds them.
   GemmSeq gd(0), g(h->tune.gemm_scale);
+  size_t nprod = 0;
+  for (const LeftBlock& b : B) nprod += size_t((b.nrows + CHOL_NB - 1) / CHOL_NB);
+  gd.d.reserve(nprod);
+  g.d.reserve(nprod);
   for (int32_t kb = 0; kb < nmax; kb += CHOL_NB) {
     // grouped as in blocked_cholesky: inside a group only the next block row is
     // updated, at the group's end every row below, at depth CHOL_GROUP NB
@@ -794,31 +831,6 @@ spand_status plan_merges(spand_ctx* h, const std::vector<MergeJob>& jobs, DevBuf
   return SPAND_OK;
 }
 
-// Host-to-device copy of a descriptor list through pinned staging, with the pinned
-// copy done by several threads when the list is large.
-template <typename T>
-spand_status upload_big(spand_ctx* h, DevBuf& b, const std::vector<T>& v) {
-  const size_t bytes = v.size() * sizeof(T);
-  spand_status st = dalloc(h, b, bytes);
-  if (st != SPAND_OK || bytes == 0) return st;
-  char* hp = h->stage.get(bytes);
-  if (!hp) return set_err(h, SPAND_E_NOMEM, "pinned staging of " + std::to_string(bytes) + " bytes failed");
-  const size_t nth = std::min<size_t>(8, std::max<size_t>(1, bytes >> 22));
-  if (nth == 1) {
-    std::memcpy(hp, v.data(), bytes);
-  } else {
-    std::vector<std::thread> pool;
-    auto put = [&](size_t k) {
-      const size_t a = v.size() * k / nth, e = v.size() * (k + 1) / nth;
-      std::memcpy(hp + a * sizeof(T), v.data() + a, (e - a) * sizeof(T));
-    };
-    for (size_t k = 1; k < nth; ++k) pool.emplace_back(put, k);
-    put(0);
-    for (std::thread& th : pool) th.join();
-  }
-  HIPCHK(hipMemcpyAsync(b.p, hp, bytes, hipMemcpyHostToDevice, h->stream));
-  return SPAND_OK;
-}
 
 // Interpolative sparsification (Sec. 2.6.2) of the interfaces of step t of one
 // problem (after the scaling for InS), one colour class at a time: an interface's
@@ -1866,6 +1878,11 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
         std::vector<SparsDesc> sds;
         std::vector<SegDesc> segs;
         std::vector<int2> deps;
+        size_t nsegs = 0;
+        for (const Ref& f : plist) nsegs += size_t(f.pb->nseg[f.p]);
+        sds.reserve(plist.size());
+        segs.reserve(nsegs);
+        deps.reserve(nsegs);
         // List scheduling over the co-resident workgroups as for one class, with an
         // interface's start no earlier than the estimated end of the neighbours it
         // waits for
