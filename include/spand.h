@@ -98,7 +98,8 @@ typedef struct {
   double apply_seconds;   /* summed device time of the applies (HIP events) */
   int64_t apply_calls;
   int32_t apply_graph;    /* 1 if the last solve replayed its apply from a captured graph */
-  int32_t reserved2;
+  int32_t cpqr_lds_slot_interfaces; /* interfaces of the last factor whose CPQR teams kept a
+                                       column in LDS beside their register columns */
   /* Interfaces of the last factor by the register layout of their CPQR: one workgroup
    * (32 rows x 2 columns per lane), one workgroup of the wide layout (teams of 2
    * lanes, 28 rows x 3 columns), several workgroups with 32 x 2, several with 20 x 3. */

@@ -613,10 +613,11 @@ struct Prob {
   bool on = false, sparsify = false;
   int64_t cbase = 0;            // first entry of this problem's clusters in the run's size and rank arrays
   std::vector<int64_t> c_off, ed_off, sc_off, sd_off, v_off, tau_off, t_off, xch_off, ncols, iso_off;
-  std::vector<int32_t> nN, nref, slabS, tg, nseg, rlay;
+  std::vector<int32_t> nN, nref, slabS, tg, nseg, rlay, kslots;
   std::vector<char> wide, big;
   int64_t cpqr_big = 0;         // interfaces of the global-memory CPQR kernel
   int32_t cpqr_one_launch = 0;  // steps whose CPQRs ran in one launch
+  int32_t cpqr_slot = 0;        // interfaces whose CPQR teams used the LDS column slot
   DevBuf cbuf;
 };
 
@@ -964,6 +965,7 @@ spand_status sparsify_interp(Prob& pb, int32_t t, double tol, double& cpqr_ms, i
       d.id = 2 * k + 1;
       d.S = 1;
       d.G = it.big ? 0 : it.G;
+      d.kslots = it.big ? 0 : cpqr_kslots(it.G, 0, true);  // the capacity that admitted it
       d.piv = pbuf.as<int32_t>() + it.opiv;
       sds[k] = d;
       SegDesc g{};
@@ -1646,6 +1648,28 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
       int32_t ncolour = 0;
       int64_t xch_total = 0;
       std::vector<int32_t> cur_h;
+      // The LDS slot of the register layouts (a third, or fourth, column per team)
+      // serves a single-slab interface that it spares an exchange, and the multi-slab
+      // interfaces of a step with many of them (fewer slab steps in all); at a step of
+      // few multi-slab interfaces, whose time is the chain of its longest ones, those
+      // keep to the register slots (more slabs, less work per step).
+      bool slot_multi = false;
+      {
+        int64_t nmulti = 0;
+        for (Prob* pp : act) {
+          if (!orth(*pp)) continue;
+          const SymStep& sy = pp->h->an.steps[t - 1];
+          const StepNum& sn = pp->h->num[t - 1];
+          for (int32_t p = sy.ne; p < sy.nc; ++p) {
+            const int32_t G = cpqr_team(sn.size[p]);
+            if (sn.size[p] == 0 || G < 0) continue;
+            int64_t ncols = 0;
+            for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e) ncols += sn.size[sy.nb[e]];
+            if (ncols > cpqr_capacity(G, 0, true)) ++nmulti;
+          }
+        }
+        slot_multi = nmulti >= 100;
+      }
       for (Prob* pp : act) {
         Prob& pb = *pp;
         spand_ctx* hq = pb.h;
@@ -1664,6 +1688,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
         pb.wide.assign(nc, 0);
         pb.rlay.assign(nc, 0);
         pb.big.assign(nc, 0);
+        pb.kslots.assign(nc, 0);
         int64_t house_total = 0;
         for (int32_t p = ne; p < nc; ++p) {
           for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e)
@@ -1679,11 +1704,12 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
           // kernel, one cooperative launch per interface
           bool big = G < 0 || (h->tune.cpqr_big_min > 0 && m >= h->tune.cpqr_big_min);
           if (!big) {
-            const int64_t cap = cpqr_capacity(G);
+            const int64_t cap = cpqr_capacity(G, 0, slot_multi);
             const int64_t S0 = (pb.ncols[p] + cap - 1) / cap;
             if (S0 > 1 && S0 > cpqr_max_coresident(cpqr_lds_bytes(G, 0, pb.nseg[p]))) {
               const int32_t G1 = cpqr_team(sn.size[p], 1);
-              const int64_t S1 = G1 > 0 ? (pb.ncols[p] + cpqr_capacity(G1, 1) - 1) / cpqr_capacity(G1, 1) : S0;
+              const int64_t cap1 = G1 > 0 ? cpqr_capacity(G1, 1, slot_multi) : cap;
+              const int64_t S1 = G1 > 0 ? (pb.ncols[p] + cap1 - 1) / cap1 : S0;
               if (S1 > cpqr_max_coresident(cpqr_lds_bytes(G1 > 0 ? G1 : G, G1 > 0 ? 1 : 0, pb.nseg[p]))) big = true;
             }
           }
@@ -1694,21 +1720,27 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
             pb.big[p] = 1;
           } else {
           pb.tg[p] = G;
-          const int64_t cap = cpqr_capacity(G);
-          pb.slabS[p] = int32_t((pb.ncols[p] + cap - 1) / cap);
-          if (pb.slabS[p] > 1 && G == 2 && m <= cpqr_wide_rows() && pb.ncols[p] <= cpqr_wide_capacity()) {
-            pb.wide[p] = 1;  // fits one workgroup of the wide layout: no exchange between slabs
+          const int64_t cap_r = cpqr_capacity(G, 0, false), cap_s = cpqr_capacity(G, 0, true);
+          if (pb.ncols[p] <= cap_s) {  // one slab; the LDS slot only when the registers are short
             pb.slabS[p] = 1;
+            pb.kslots[p] = cpqr_kslots(G, 0, pb.ncols[p] > cap_r);
+            if (pb.ncols[p] > cap_r && G == 2 && m <= cpqr_wide_rows() && pb.ncols[p] <= cpqr_wide_capacity())
+              pb.wide[p] = 1;  // the wide layout holds it in registers alone
+          } else {
+            const int64_t cap = cpqr_capacity(G, 0, slot_multi);
+            pb.slabS[p] = int32_t((pb.ncols[p] + cap - 1) / cap);
+            pb.kslots[p] = cpqr_kslots(G, 0, slot_multi);
           }
           if (pb.slabS[p] > 1) {  // layout 1 when it needs fewer slabs (and still more than one)
             const int32_t G1 = cpqr_team(sn.size[p], 1);
             if (G1 > 0) {
-              const int64_t cap1 = cpqr_capacity(G1, 1);
+              const int64_t cap1 = cpqr_capacity(G1, 1, slot_multi);
               const int32_t S1 = int32_t((pb.ncols[p] + cap1 - 1) / cap1);
               if (S1 > 1 && S1 < pb.slabS[p]) {
                 pb.rlay[p] = 1;
                 pb.tg[p] = G1;
                 pb.slabS[p] = S1;
+                pb.kslots[p] = cpqr_kslots(G1, 1, slot_multi);
               }
             }
             pb.xch_off[p] = xch_total;
@@ -1725,8 +1757,10 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
         }
         if ((st = dalloc(hq, sn.house, size_t(house_total) * sizeof(double))) != SPAND_OK) return st;
         for (int32_t p = ne; p < nc; ++p)
-          if (pb.v_off[p] >= 0 && !pb.big[p])
+          if (pb.v_off[p] >= 0 && !pb.big[p]) {
             ++pb.cpqr_ifaces[pb.slabS[p] > 1 ? 2 + pb.rlay[p] : (pb.wide[p] ? 1 : 0)];
+            if (!pb.wide[p] && pb.kslots[p] > cpqr_kslots(pb.tg[p], pb.rlay[p], false)) ++pb.cpqr_slot;
+          }
           else if (pb.v_off[p] >= 0)
             ++pb.cpqr_big;
       }
@@ -1781,7 +1815,8 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
             if (pb.wide[p]) {  // the standard layout of teams of 2 instead
               --pb.cpqr_ifaces[1];
               pb.wide[p] = 0;
-              pb.slabS[p] = int32_t((pb.ncols[p] + cpqr_capacity(2) - 1) / cpqr_capacity(2));
+              pb.slabS[p] = int32_t((pb.ncols[p] + cpqr_capacity(2, 0, true) - 1) / cpqr_capacity(2, 0, true));
+              pb.kslots[p] = cpqr_kslots(2, 0, true);
               ++pb.cpqr_ifaces[pb.slabS[p] > 1 ? 2 : 0];
             }
             pb.xch_off[p] = xch_total;
@@ -1914,6 +1949,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
           d.S = S;
           d.G = pb.tg[p];
           d.lay = pb.rlay[p];
+          d.kslots = pb.kslots[p];
           d.xch = xchb.as<double>() + pb.xch_off[p];
           d.seg_begin = int32_t(segs.size());
           d.dep_begin = int32_t(deps.size());
@@ -2056,6 +2092,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
               d.S = pb.slabS[p];
               d.G = pb.tg[p];
               d.lay = pb.rlay[p];
+              d.kslots = pb.kslots[p];
               if (multi) d.xch = xchb.as<double>() + pb.xch_off[p];
               d.seg_begin = int32_t(all_segs.size());
               for (int64_t e = sy.nb_ptr[p]; e < sy.nb_ptr[p + 1]; ++e) {
@@ -2468,6 +2505,7 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
     for (int q = 0; q < 4; ++q) s.cpqr_interfaces[q] = pb.cpqr_ifaces[q];
     s.cpqr_big_interfaces = pb.cpqr_big;
     s.cpqr_one_launch_steps = pb.cpqr_one_launch;
+    s.cpqr_lds_slot_interfaces = pb.cpqr_slot;
     s.apply_scratch_per_rhs = std::max<int64_t>(pb.h->max_tmp, 1) + std::max<int64_t>(pb.h->max_gather, 1) +
                               (pb.h->d_inv.p ? pb.h->an.n : 0);
     for (int q = 0; q < 3; ++q) s.apply_interfaces[q] = 0;

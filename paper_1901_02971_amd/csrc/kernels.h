@@ -106,7 +106,9 @@ struct SparsDesc {
   int32_t m, ldd, seg_begin, seg_end, id, S, G, lay;  // G: lanes per column (team size);
                                                       // lay: register layout (multi-slab kernel)
   int32_t ldv;                                        // leading dimension of V (>= m)
-  int32_t dep_begin, dep_end, pad;                    // multi-slab launch: neighbours to wait for
+  int32_t dep_begin, dep_end;                         // multi-slab launch: neighbours to wait for
+  int32_t kslots;  // column slots per team in use: the register slots, plus the LDS slot when
+                   // cpqr_capacity(G, lay, true) sized the slabs
 };
 struct SegDesc {
   double* blk;  // block holding A_pq: trans=0 -> A_pq[r][c] = blk[r + c*ld]; trans=1 -> blk[c + r*ld]
@@ -144,7 +146,10 @@ void launch_set_identity(const IdentDesc* d, int32_t count, hipStream_t s);
 // kernel), lay 1 20 rows of 3 columns (multi-slab kernel only).
 // Team size G (lanes per column, a power of two) for m rows; -1 if m is too large.
 int32_t cpqr_team(int32_t m, int32_t lay = 0);
-int32_t cpqr_capacity(int32_t G, int32_t lay = 0);
+// Columns of one slab: the register slots only, or with the LDS slot where the layout
+// has one (SparsDesc::kslots tells the kernel which).
+int32_t cpqr_capacity(int32_t G, int32_t lay = 0, bool lds_slot = true);
+int32_t cpqr_kslots(int32_t G, int32_t lay, bool lds_slot);
 // Doubles of one slab's exchange record (S > 1): the header + the rows of a team.
 int32_t cpqr_record(int32_t G, int32_t lay = 0);
 size_t cpqr_lds_bytes(int32_t G, int32_t lay, int32_t nseg);

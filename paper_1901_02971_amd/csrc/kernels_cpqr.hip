@@ -48,6 +48,16 @@ namespace spand {
 #define CQ_MR_1 20  // layout 1 of the multi-slab kernel: fewer rows, more columns per lane
 #define CQ_CPL_1 3
 #define CQ_XH 16  // doubles of an exchange record's header: a 128-byte line of its own
+// Column slots a team keeps in LDS next to its CQ_CPL (or CQ_CPL_1) register slots:
+// one when the LDS of a workgroup holds it (MR rows of every thread) beside the
+// reflector, pivot-column and R_jj buffers (3 G MR doubles), with 16 KB left for the
+// segment offsets and the static LDS; none otherwise (teams of 32 and 64 with 32 rows).
+// A thread keeps its MR rows of the slot together (MR + 1 doubles apart from the next
+// thread's, so the lanes of a wave spread over the banks): one address and immediate
+// offsets reach them all.
+__host__ __device__ constexpr int cq_lds_slots(int G, int MR) {
+  return (3 * G * MR + (MR + 1) * CQ_NT) * 8 + 16 * 1024 <= 160 * 1024 ? 1 : 0;
+}
 #define CW 256  // threads of k_build_t
 #define TIE_RTOL 1e-10
 #define SPIN_LIMIT (1L << 22)
@@ -241,12 +251,16 @@ __device__ __forceinline__ void cpqr_update_group(double (&a)[CPL][MR], int gi, 
 
 // Slab w of interface d (w = 0, S = 1 when MULTI is false); a lane keeps MR rows
 // of CPL columns.
-template <int G, bool MULTI, int MR = CQ_MR, int CPL = CQ_CPL>
+template <int G, bool MULTI, int MR = CQ_MR, int CPL = CQ_CPL, int CPL2 = 0>
 __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const SegDesc* __restrict__ segs, double eps,
                                           int32_t* cursize, int32_t* nref, int32_t* err, int32_t* done = nullptr) {
   constexpr int NT = CQ_NT;
   constexpr int NTEAM = NT / G;
-  constexpr int CAP = CPL * NTEAM;
+  constexpr int KS = CPL + CPL2;  // column slots of a team: CPL in registers, CPL2 (0 or 1) in LDS
+  // slots in use for this interface (the host leaves the LDS slot empty where more
+  // slabs with less work per step serve better), and the columns of a slab
+  const int KU = (CPL2 > 0 && d.kslots > CPL) ? KS : CPL;
+  const int CAP = KU * NTEAM;
   constexpr int NW = NT / 64;
   constexpr int ROWS = G * MR;    // rows a team can hold (>= m)
   constexpr int NGRP = MR / 4;    // row groups: group u is rows [4uG, 4uG + 4G), registers 4u..4u+3
@@ -272,7 +286,9 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
   double* vv = lds;
   double* cv = lds + ROWS;
   double* rb = lds + 2 * ROWS;
-  int* segoff = reinterpret_cast<int*>(lds + 3 * ROWS);  // nseg + 1
+  // the LDS column slot of this thread: its rows q * G + g at lcs[q]
+  double* lcs = lds + 3 * ROWS + tid * (MR + 1);
+  int* segoff = reinterpret_cast<int*>(lds + 3 * ROWS + CPL2 * (MR + 1) * NT);  // nseg + 1
   // exchange record of slab q in buffer b: header [max, cand norm, cand xn2, cand index + 1,
   // unused up to CQ_XH], then ROWS column rows
   auto xrec = [&](int b, int q) { return d.xch + ((size_t)b * S + q) * (size_t)(ROWS + CQ_XH); };
@@ -298,9 +314,43 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
   }
 
   double a[CPL][MR];
-  double nrm[CPL];  // squared norm of rows j..m-1 (identical in the lanes of a team)
-  int col[CPL];     // column index in A_pn, -1 if the slot is empty
-  int pst[CPL];     // -1 remaining, >= 0 step at which the column was the pivot, -2 empty
+  double nrm[KS];  // squared norm of rows j..m-1 (identical in the lanes of a team)
+  int col[KS];     // column index in A_pn, -1 if the slot is empty
+  int pst[KS];     // -1 remaining, >= 0 step at which the column was the pivot, -2 empty
+  // row q * G + g of slot k of this team: registers for k < CPL, LDS for k = CPL
+  auto val = [&](int k, int q) -> double { return k < CPL ? a[k < CPL ? k : 0][q] : lcs[q]; };
+  if constexpr (CPL2 > 0) {  // the LDS slot (k = CPL), four rows at a time
+    const int c = KU > CPL ? w * CAP + CPL * NTEAM + team : nc;
+    col[CPL] = c < nc ? c : -1;
+    pst[CPL] = c < nc ? -1 : -2;
+    const gdouble* base = (const gdouble*)&g_cq_zero;
+    int64_t stride = 0;
+    if (c < nc) {
+      double* b;
+      column_ptr(sg, segoff, c, b, stride);
+      base = (const gdouble*)b;
+    }
+    const int rows = (c < nc) ? m : 0;
+    double sq = 0.0;
+#pragma unroll
+    for (int q0 = 0; q0 < MR; q0 += 4) {
+      double t4[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = (q0 + u) * G + g;
+        const gdouble* e = base + (i < rows ? i : 0) * (int)stride;
+        t4[u] = MULTI ? __hip_atomic_load(e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *e;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double v = ((q0 + u) * G + g < rows) ? t4[u] : 0.0;
+        lcs[q0 + u] = v;
+        sq = fma(v, v, sq);
+      }
+      __builtin_amdgcn_sched_barrier(0);  // four rows in registers at a time
+    }
+    nrm[CPL] = team_sum<G>(sq);
+  }
 #pragma unroll
   for (int k = 0; k < CPL; ++k) {
     const int c = w * CAP + k * NTEAM + team;
@@ -346,10 +396,10 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
     const int jg = j - g;  // row q * G + g of this lane lies below row j iff q * G > jg
     // ---- pivot of this slab: the largest remaining norm M, then the smallest column
     // index whose norm is >= M (1 - TIE_RTOL); two exact reductions
-    double nv[CPL];
+    double nv[KS];
     double lmx = -1.0;
 #pragma unroll
-    for (int k = 0; k < CPL; ++k) {
+    for (int k = 0; k < KS; ++k) {
       nv[k] = (pst[k] == -1) ? sqrt(nrm[k]) : -1.0;
       lmx = fmax(lmx, nv[k]);
     }
@@ -364,7 +414,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
       const double thr = smx * (1.0 - TIE_RTOL);
       int c = INT_MAX;
 #pragma unroll
-      for (int k = 0; k < CPL; ++k)
+      for (int k = 0; k < KS; ++k)
         if (pst[k] == -1 && nv[k] >= thr) c = min(c, col[k]);
       c = wave_min(c);
       if (lane == 0) pcd[j & 1][wave] = c;
@@ -389,7 +439,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
       // the owner team publishes its column and the squared norm of its rows below j
       if (own) {
 #pragma unroll
-        for (int k = 0; k < CPL; ++k)
+        for (int k = 0; k < KS; ++k)
           if (k == pk) {
             double s2 = 0.0;
 #pragma unroll
@@ -398,8 +448,9 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                   const int q = 4 * gi + u;
-                  cv[q * G + g] = a[k][q];
-                  s2 = (gi > ujp || q * G > jg) ? fma(a[k][q], a[k][q], s2) : s2;
+                  const double x = val(k, q);
+                  cv[q * G + g] = x;
+                  s2 = (gi > ujp || q * G > jg) ? fma(x, x, s2) : s2;
                 }
               }
             }
@@ -423,7 +474,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
         double* rw = xrec(j & 1, w);
         if (own) {
 #pragma unroll
-          for (int k = 0; k < CPL; ++k)
+          for (int k = 0; k < KS; ++k)
             if (k == pk) {
               double* rl = rw + CQ_XH + g * MR;
               double s2 = 0.0;
@@ -433,8 +484,9 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
 #pragma unroll
                   for (int u = 0; u < 4; ++u) {
                     const int q = 4 * gi + u;
-                    shared_store(rl + q, a[k][q]);
-                    s2 = (gi > ujp || q * G > jg) ? fma(a[k][q], a[k][q], s2) : s2;
+                    const double x = val(k, q);
+                    shared_store(rl + q, x);
+                    s2 = (gi > ujp || q * G > jg) ? fma(x, x, s2) : s2;
                   }
                 }
               }
@@ -522,7 +574,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
         const double thr = xg_mx * (1.0 - TIE_RTOL);
         int c2 = INT_MAX;
 #pragma unroll
-        for (int k = 0; k < CPL; ++k)
+        for (int k = 0; k < KS; ++k)
           if (pst[k] == -1 && nv[k] >= thr) c2 = min(c2, col[k]);
         c2 = wave_min(c2);
         if (lane == 0) pcd[j & 1][wave] = c2;  // free: every wave has read pcd[j & 1]
@@ -535,14 +587,15 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
         if (best != INT_MAX && team == lc2 % NTEAM) {
           const int pk2 = lc2 / NTEAM;
 #pragma unroll
-          for (int k = 0; k < CPL; ++k)
+          for (int k = 0; k < KS; ++k)
             if (k == pk2) {
               double* rl = rw + CQ_XH + g * MR;
               double s2 = 0.0;
 #pragma unroll
               for (int q = 0; q < MR; ++q) {
-                shared_store(rl + q, a[k][q]);
-                s2 = (q * G > jg) ? fma(a[k][q], a[k][q], s2) : s2;
+                const double x = val(k, q);
+                shared_store(rl + q, x);
+                s2 = (q * G > jg) ? fma(x, x, s2) : s2;
               }
               s2 = team_sum<G>(s2);
               if (g == 0) {
@@ -655,7 +708,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
       const int plc = piv - w * CAP;
       if (plc >= 0 && plc < CAP && team == plc % NTEAM) {
 #pragma unroll
-        for (int k = 0; k < CPL; ++k)
+        for (int k = 0; k < KS; ++k)
           if (k == plc / NTEAM) pst[k] = j;
       }
     }
@@ -672,6 +725,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
     double dot[CPL];
 #pragma unroll
     for (int k = 0; k < CPL; ++k) dot[k] = 0.0;
+
     if (uj & 1) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) vb[u] = vl[(4 * uj + u) * G];
@@ -697,6 +751,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
       wv[k] = (pst[k] == -1) ? tau * dot[k] : 0.0;
       sq[k] = 0.0;
     }
+
     if (uj & 1) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) vb[u] = vl[(4 * uj + u) * G];
@@ -717,12 +772,39 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
     }
 #pragma unroll
     for (int k = 0; k < CPL; ++k) nrm[k] = team_sum<G>(sq[k]);
+    if (CPL2 > 0 && pst[CPL] == -1) {
+      // the LDS slot, after the register slots (fewer values live at once): the same
+      // two passes, a <- a - tau (v . a) v and its squared norm below j (a team whose
+      // slot is empty or holds a pivot column skips them)
+      double dot2 = 0.0;
+#pragma unroll
+      for (int gi = 0; gi < NGRP; ++gi)
+        if (gi >= uj && gi < uend) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) dot2 = fma(vl[(4 * gi + u) * G], lcs[4 * gi + u], dot2);
+        }
+      dot2 = team_sum<G>(dot2);
+      const double wv2 = tau * dot2;
+      double sq2 = 0.0;
+#pragma unroll
+      for (int gi = 0; gi < NGRP; ++gi)
+        if (gi >= uj && gi < uend) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int q = 4 * gi + u;
+            const double x = fma(-wv2, vl[q * G], lcs[q]);
+            lcs[q] = x;
+            sq2 = (gi > uj || q * G > jg) ? fma(x, x, sq2) : sq2;
+          }
+        }
+      nrm[CPL] = team_sum<G>(sq2);
+    }
   }
   __syncthreads();  // rb complete
   // ---- W_cn = R[:r, :] (column order of A_pn) into the blocks of p.  A pivot
   // column of step s holds R_ij for i < s; its row s is R_ss and the rows below are 0.
 #pragma unroll
-  for (int k = 0; k < CPL; ++k) {
+  for (int k = 0; k < KS; ++k) {
     if (col[k] < 0 || r == 0) continue;
     double* base;
     int64_t stride;
@@ -734,7 +816,7 @@ __device__ __forceinline__ void cpqr_slab(const SparsDesc& d, int wslab, const S
     for (int q = 0; q < MR; ++q) {
       const int i = q * G + g;
       if (i < r) {
-        const double v = (ps >= 0 && i >= ps) ? ((i == ps) ? rss : 0.0) : a[k][q];
+        const double v = (ps >= 0 && i >= ps) ? ((i == ps) ? rss : 0.0) : val(k, q);
         if constexpr (MULTI)
           shared_store(base + (int64_t)i * stride, v);  // read by later neighbours of the launch
         else
@@ -771,7 +853,7 @@ __global__ void __launch_bounds__(CQ_NT) k_cpqr_one(const SparsDesc* __restrict_
                                                     const SegDesc* __restrict__ segs, double eps, int32_t* cursize,
                                                     int32_t* nref, int32_t* err) {
   const SlabRef sr = slabs[blockIdx.x];
-  cpqr_slab<G, false>(descs[sr.desc], 0, segs, eps, cursize, nref, err);
+  cpqr_slab<G, false, CQ_MR, CQ_CPL, cq_lds_slots(G, CQ_MR)>(descs[sr.desc], 0, segs, eps, cursize, nref, err);
 }
 
 // Single-slab interfaces of at most 2 * CQ_MR_W rows whose width needs more than
@@ -828,8 +910,11 @@ __global__ void __launch_bounds__(CQ_NT) k_cpqr_multi(const SparsDesc* __restric
       __syncthreads();
     }
 #define CQ_CASE(GG)                                                                   \
-  case GG: cpqr_slab<GG, true>(d, sr.w, segs, eps, cursize, nref, err, done); break; \
-  case GG | 256: cpqr_slab<GG, true, CQ_MR_1, CQ_CPL_1>(d, sr.w, segs, eps, cursize, nref, err, done); break;
+  case GG: cpqr_slab<GG, true, CQ_MR, CQ_CPL, cq_lds_slots(GG, CQ_MR)>(d, sr.w, segs, eps, cursize, nref, err, done); \
+    break;                                                                                                          \
+  case GG | 256:                                                                                                    \
+    cpqr_slab<GG, true, CQ_MR_1, CQ_CPL_1, cq_lds_slots(GG, CQ_MR_1)>(d, sr.w, segs, eps, cursize, nref, err, done); \
+    break;
     switch (d.G | (d.lay << 8)) {
       CQ_CASE(1)
       CQ_CASE(2)
@@ -897,10 +982,15 @@ int32_t cpqr_team(int32_t m, int32_t lay) {
   return G <= 64 ? G : -1;
 }
 
-int32_t cpqr_capacity(int32_t G, int32_t lay) { return (lay == 1 ? CQ_CPL_1 : CQ_CPL) * CQ_NT / G; }
+int32_t cpqr_kslots(int32_t G, int32_t lay, bool lds_slot) {
+  return (lay == 1 ? CQ_CPL_1 : CQ_CPL) + (lds_slot ? cq_lds_slots(G, layout_rows(lay)) : 0);
+}
+int32_t cpqr_capacity(int32_t G, int32_t lay, bool lds_slot) { return cpqr_kslots(G, lay, lds_slot) * CQ_NT / G; }
 
 size_t cpqr_lds_bytes(int32_t G, int32_t lay, int32_t nseg) {
-  return 3 * size_t(G) * layout_rows(lay) * sizeof(double) + (size_t(nseg) + 1) * sizeof(int32_t) + 16;
+  const size_t mr = size_t(layout_rows(lay));
+  return (3 * size_t(G) * mr + size_t(cq_lds_slots(G, int(mr))) * (mr + 1) * CQ_NT) * sizeof(double) +
+         (size_t(nseg) + 1) * sizeof(int32_t) + 16;
 }
 
 int32_t cpqr_record(int32_t G, int32_t lay) { return G * layout_rows(lay) + CQ_XH; }

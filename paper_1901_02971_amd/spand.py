@@ -52,13 +52,13 @@ class Stats(C.Structure):
                 ("step_phase_seconds", (C.c_double * 4) * 32), ("step_m_F", C.c_int64 * 32),
                 ("cpqr_flops", C.c_double), ("cpqr_seconds", C.c_double), ("cpqr_launches", C.c_int64),
                 ("apply_bytes", C.c_double), ("apply_seconds", C.c_double), ("apply_calls", C.c_int64),
-                ("apply_graph", C.c_int32), ("reserved2", C.c_int32), ("cpqr_interfaces", C.c_int64 * 4),
+                ("apply_graph", C.c_int32), ("cpqr_lds_slot_interfaces", C.c_int32), ("cpqr_interfaces", C.c_int64 * 4),
                 ("apply_interfaces", C.c_int64 * 3), ("pcg_replacements", C.c_int64),
                 ("cpqr_big_interfaces", C.c_int64), ("apply_scratch_per_rhs", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_
-             if k not in ("reserved2", "step_phase_seconds", "step_m_F", "cpqr_interfaces",
+             if k not in ("step_phase_seconds", "step_m_F", "cpqr_interfaces",
                           "apply_interfaces")}
         d["cpqr_interfaces"] = [int(v) for v in self.cpqr_interfaces]
         d["apply_interfaces"] = [int(v) for v in self.apply_interfaces]

@@ -104,8 +104,9 @@ def test_apply_many_rhs_matches_oracle():
     the tiled apply products, on a 24^3 Laplacian at 5 levels whose upper clusters span
     several 64-wide tiles with a ragged last tile.  Its interfaces take every CPQR
     register layout: one workgroup, the wide single workgroup, and several workgroups
-    in each of the two multi-slab layouts; the ranks and the apply (which reads the
-    reflectors, T factors and W blocks they wrote) are checked against the oracle."""
+    in each of the two multi-slab layouts, some with a column per team in LDS beside
+    the register columns; the ranks and the apply (which reads the reflectors, T
+    factors and W blocks they wrote) are checked against the oracle."""
     p = gridgen.laplacian((24, 24, 24))
     b = gridgen.rhs(np.random.default_rng(12), p.n, 11)
     an, fac = oracle_run(p, 5, 1e-2)
@@ -114,6 +115,7 @@ def test_apply_many_rhs_matches_oracle():
     st = s.stats()
     assert st["s_top"] > 64
     assert all(k > 0 for k in st["cpqr_interfaces"]), st["cpqr_interfaces"]
+    assert st["cpqr_lds_slot_interfaces"] > 0, st
     z = gpu_apply(s, b)
     zr = O.apply(fac, b)
     assert np.abs(z - zr).max() <= 1e-10 * np.abs(zr).max()
@@ -164,7 +166,7 @@ def test_refactor_schedule_is_bit_identical():
     s.close()
 
 
-@pytest.mark.parametrize("shape,levels", [((24, 24, 24), 5), ((32, 32, 32), 9)])
+@pytest.mark.parametrize("shape,levels", [((32, 32, 32), 9), ((40, 40, 40), 8)])
 def test_one_launch_cpqr_steps_match_oracle(shape, levels):
     """Steps whose CPQR work lies mostly in multi-slab interfaces run all colour classes
     in one cooperative launch, each interface waiting on device counters for its
