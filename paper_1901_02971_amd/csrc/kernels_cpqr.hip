@@ -3,11 +3,12 @@
 //
 // Interface p couples its m dofs to nc neighbour dofs through A_pn (m x nc).  A
 // workgroup of NT = 512 threads (two waves per SIMD, so the whole register file of
-// a CU) holds a slab of CAP = CQ_CPL * NT / G columns: a team of G consecutive
-// lanes (G a power of two, G * CQ_MR >= m) owns CQ_CPL columns, and lane g of the
-// team keeps rows i = q * G + g (q < CQ_MR) of each of them in registers.  Column c
-// of A_pn lives in slab c / CAP, team (c % CAP) % (NT / G), register slot
-// (c % CAP) / (NT / G).  Interface p uses S = ceil(nc / CAP) slabs.
+// a CU) holds a slab of CAP = K * NT / G columns: a team of G consecutive lanes (G a
+// power of two, G * CQ_MR >= m) owns K column slots, and lane g of the team keeps
+// rows i = q * G + g (q < CQ_MR) of each of them: CQ_CPL slots in registers, and,
+// where the LDS holds it and the host asks for it, one more slot in LDS (K =
+// CQ_CPL + 1).  Column c of A_pn lives in slab c / CAP, team (c % CAP) % (NT / G),
+// slot (c % CAP) / (NT / G).  Interface p uses S = ceil(nc / CAP) slabs.
 //
 // Step j of Householder QR with column pivoting:
 //   1. every column knows the exact norm of its rows j..m-1 (recomputed from the
@@ -26,8 +27,9 @@
 //   4. every remaining column is updated in registers, a <- a - tau v (v^T a), and
 //      its new trailing norm formed (team sums by lane shuffles).
 // Columns are never moved: a column pivoted at step j keeps R_0j..R_j-1,j in its
-// rows 0..j-1 and R_jj is set at the end.  At the end every slab writes W_cn = R[:r, :] P^T straight into the blocks of
-// p, and slab 0 stores the reflectors, sets A_cc = I and publishes the rank.
+// rows 0..j-1 and R_jj is set at the end.  At the end every slab writes
+// W_cn = R[:r, :] P^T straight into the blocks of p, and slab 0 stores the
+// reflectors, sets A_cc = I and publishes the rank.
 #include <hip/hip_runtime.h>
 
 #include <climits>
