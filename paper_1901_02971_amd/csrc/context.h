@@ -237,6 +237,7 @@ struct spand_ctx {
   // second stream of the factorization: the multi-slab CPQR launch of a colour class
   // runs on it beside that class's single-slab launches (created on first use)
   hipStream_t stream2 = nullptr;
+  hipStream_t stream3 = nullptr;  // every other single-slab CPQR launch of a colour class
   spand_stats stats{};
   bool factored = false;
   int device = -1;
@@ -262,6 +263,7 @@ struct spand_ctx {
   ~spand_ctx() {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (stream2) (void)hipStreamDestroy(stream2);
+    if (stream3) (void)hipStreamDestroy(stream3);
   }
 };
 

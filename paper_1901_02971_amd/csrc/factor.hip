@@ -2288,8 +2288,25 @@ spand_status factor_run(std::vector<Prob>& P, double tol, int32_t skip, spand_pr
           HIPCHK(hipEventRecord(b_done, h->stream2));
           b_pending = true;
         }
-        for (const CpqrLaunch& Lc : launches)
-          if (!Lc.multi && Lc.big_nseg < 0 && (st = issue(Lc, h->stream)) != SPAND_OK) return st;
+        // the single-slab launches (independent interfaces) alternate between the
+        // handle's stream and a third one, so that one launch's last workgroups run
+        // beside the next one's first
+        {
+          int nsingle = 0;
+          for (const CpqrLaunch& Lc : launches) nsingle += (!Lc.multi && Lc.big_nseg < 0) ? 1 : 0;
+          if (nsingle > 1 && !h->stream3) HIPCHK(hipStreamCreateWithFlags(&h->stream3, hipStreamNonBlocking));
+          if (nsingle > 1) HIPCHK(hipStreamWaitEvent(h->stream3, cstart, 0));
+          int k = 0;
+          for (const CpqrLaunch& Lc : launches)
+            if (!Lc.multi && Lc.big_nseg < 0 && (st = issue(Lc, (k++ & 1) ? h->stream3 : h->stream)) != SPAND_OK)
+              return st;
+          if (nsingle > 1) {
+            hipEvent_t s3;
+            HIPCHK(joinev.get(njoin++, &s3));
+            HIPCHK(hipEventRecord(s3, h->stream3));
+            HIPCHK(hipStreamWaitEvent(h->stream, s3, 0));
+          }
+        }
         for (const CpqrLaunch& Lc : launches) {
           if (Lc.big_nseg < 0) continue;
           if (b_pending) {
