@@ -785,12 +785,29 @@ __global__ void __launch_bounds__(256) k_spmv(const int64_t* __restrict__ rowptr
     double s[RB];
 #pragma unroll
     for (int c = 0; c < RB; ++c) s[c] = 0.0;
-    for (int64_t q = b; q < e; ++q) {
-      const double a = val[q];
-      const int64_t col = colind[q];
+    // eight entries of the row at a time: their values and columns, then every x
+    // entry they need, are requested together (the sum keeps the entries' order)
+    for (int64_t q0 = b; q0 < e; q0 += 8) {
+      double a[8];
+      int64_t col[8];
 #pragma unroll
-      for (int c = 0; c < RB; ++c)
-        if (c < nr) s[c] = fma(a, xc[col + (int64_t)c * ld], s[c]);
+      for (int u = 0; u < 8; ++u) {
+        const bool ok = q0 + u < e;
+        a[u] = ok ? val[q0 + u] : 0.0;
+        col[u] = ok ? (int64_t)colind[q0 + u] : v;
+      }
+      double xv[8][RB];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int c = 0; c < RB; ++c) xv[u][c] = c < nr ? xc[col[u] + (int64_t)c * ld] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (q0 + u < e) {
+#pragma unroll
+          for (int c = 0; c < RB; ++c)
+            if (c < nr) s[c] = fma(a[u], xv[u][c], s[c]);
+        }
     }
 #pragma unroll
     for (int c = 0; c < RB; ++c)
